@@ -1,0 +1,215 @@
+/*
+ * redo.h — C ABI of the REDO propagator library for AMD Instinct MI355X (gfx950).
+ *
+ * REDO (Rapid Exponentiation using Discrete Operators, Bhole & Mahesh,
+ * arXiv 1707.02162) evaluates long sequences of piecewise-constant
+ * propagators U_n = exp[-i dt (H0 + H_n)] without a matrix exponential per
+ * step: every control amplitude is coarse-grained into base-b digits
+ * (Sec. II, Eq. cgrain), every single-operator exponential becomes a product
+ * of precomputed discrete operators (Sec. II, processes 1 and 2, Eqs.
+ * redoform and exp2prod), and the drift is split off per step
+ * (Sec. III, Eqs. vn and vnd).
+ *
+ * Conventions shared by every entry point
+ *   - Every data pointer is a DEVICE pointer (HIP, the caller's allocation)
+ *     unless marked "host".  The library never keeps a caller pointer past
+ *     the call that received it.
+ *   - Matrices are dense, row-major, contiguous.  Complex numbers are
+ *     interleaved (re, im): "c64" = 2 x float, "c128" = 2 x double
+ *     (the layouts of torch.complex64 / torch.complex128).
+ *   - `stream` is a hipStream_t (NULL = the null stream).  All work is
+ *     enqueued on it; calls return before the GPU finishes, except those
+ *     documented as synchronising.  Device-side conditions (non-finite or
+ *     clamped amplitudes) are latched in the table handle and read with
+ *     redo_get_device_status.
+ *   - Errors are status codes; no exception or abort crosses the ABI.
+ *     Arguments are validated on the host before anything is launched; on
+ *     error nothing is written and redo_last_error() (thread-local) says why.
+ *   - A table handle may be used from several streams after it is built,
+ *     except for redo_cache_levels / redo_get_device_status, which must not
+ *     overlap other calls on the same handle.
+ *
+ * Data layouts of the per-call arrays (B instances, N_max steps, K channels):
+ *   u        float [B][N_max][K]     signed amplitudes (table built with phased = 0)
+ *            float [B][N_max][K][2]  Cartesian pairs (u_x, u_y) (phased = 1)
+ *            in rad/s; the stride between instances is N_max*K (x2) floats.
+ *   n_steps  int32 [B] per-instance lengths (1..N_max), or NULL for all N_max;
+ *            steps n >= n_steps[b] are ignored.
+ */
+#ifndef REDO_H
+#define REDO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct redo_table_s* redo_table;
+
+typedef enum {
+    REDO_OK = 0,
+    REDO_ERR_ARG = 1,            /* invalid argument (size, NULL, range) */
+    REDO_ERR_ALLOC = 2,          /* device allocation failed */
+    REDO_ERR_HIP = 3,            /* a HIP runtime call failed */
+    REDO_ERR_NOT_HERMITIAN = 4,  /* a generator or drift is not Hermitian */
+    REDO_ERR_NONFINITE = 5,      /* a non-finite amplitude was seen on the device */
+    REDO_ERR_UNSUPPORTED = 6,    /* valid, but not provided by this build */
+    REDO_ERR_WORKSPACE = 7,      /* workspace smaller than redo_workspace_bytes */
+    REDO_WARN_CLAMPED = 100      /* some amplitude exceeded (b^P - 1) eps and was clamped */
+} redo_status;
+
+typedef enum {
+    REDO_PREC_F32 = 0,     /* FP32 complex products, four real products per complex one */
+    REDO_PREC_F32_3M = 1,  /* FP32, three real products (Gauss) per complex one; d >= 128 */
+    REDO_PREC_BF16X3 = 2   /* split BF16: hi*hi + hi*lo + lo*hi, FP32 accumulate; d >= 128 */
+} redo_precision;
+
+typedef enum {
+    REDO_OP_COMPOSE = 0,
+    REDO_OP_CHAIN = 1,
+    REDO_OP_GRAPE = 2,
+    REDO_OP_EXPM_CHAIN = 3,
+    REDO_OP_EXPM_GRAPE = 4
+} redo_op;
+
+/* Problem description of one table (Sec. II coarse graining; Sec. III model). */
+typedef struct {
+    int32_t d;             /* Hilbert-space dimension: a power of two 2..64, or a multiple of 64 >= 128 */
+    int32_t K;             /* control channels, 1..16 */
+    int32_t base;          /* b >= 2 */
+    int32_t digits;        /* P >= 1, with b^P - 1 <= 2^31 - 1 */
+    double dt;             /* segment length Delta t (s), > 0 */
+    double eps;            /* amplitude quantum (rad/s), > 0: the paper's b^l */
+    int32_t phased;        /* 1: channel k takes a Cartesian pair and its x-generator S_k is rotated by the
+                                 diagonal phase generator g_k, H_kn = Z_n (Omega_kn S_k) Z_n^dag (Sec. III, Eq. vn);
+                              0: channel k takes a signed amplitude, H_kn = u_kn S_k */
+    int32_t drift_is_diag; /* 1: H0 is real diagonal, double [n_drift][d]; 0: c128 [n_drift][d][d] */
+    int32_t n_drift;       /* number of drift Hamiltonians (>= 1); instance b uses drift b % n_drift */
+    int32_t reserved;      /* must be 0 */
+} redo_table_desc;
+
+/*
+ * Process 1 of Sec. II (Eq. redoform, read as exp(-i c b^j eps dt S_k), digit
+ * j = 0..P-1, coefficient c = 1..b-1): builds the table of discrete operators
+ *     T_k[j][c] = exp(-i c b^j eps dt S_k)
+ * in FP64 on the GPU (scaling-and-squaring Taylor for c = 1, then powers),
+ * rounded once to FP32 for storage, plus the drift propagators
+ * V = exp(-i dt H0) (Sec. III: the drift is split off each step).
+ *   H0  double [n_drift][d] (diagonal) or c128 [n_drift][d][d]; Hermitian
+ *   S   c128 [K][d][d]      Hermitian control generators (x-generators when phased)
+ *   g   double [K][d]       diagonal phase generators (phased), else NULL
+ * Inputs are read during the call only.  Synchronises `stream`.
+ * Errors: REDO_ERR_ARG, REDO_ERR_NOT_HERMITIAN (relative anti-Hermitian part
+ * > 1e-10), REDO_ERR_ALLOC, REDO_ERR_HIP.  On success *out owns the table
+ * (device memory: K*P*(b-1)*d*d*8 bytes + drifts) until redo_table_destroy.
+ */
+redo_status redo_build_table(const redo_table_desc* desc, const double* H0, const double* S,
+                             const double* g, void* stream, redo_table* out);
+
+/* Frees the table and everything it owns.  NULL is accepted.  Synchronises the device. */
+redo_status redo_table_destroy(redo_table table);
+
+/* Host copy of the descriptor and the table's device footprint in bytes. */
+redo_status redo_table_query(redo_table table, redo_table_desc* desc, size_t* device_bytes);
+
+/* Bytes of workspace that `op` needs for B instances of up to N_max steps
+ * (0 on invalid arguments).  Workspace is caller-owned device memory. */
+size_t redo_workspace_bytes(redo_table table, int32_t op, int32_t B, int32_t N_max);
+
+/*
+ * Coarse graining alone (Sec. II, Eq. cgrain): for every (b, n, k) with
+ * n < N_max, the code q = min(floor(Omega/eps + 1/2), b^P - 1) with
+ * Omega = |u| (signed tables) or sqrt(u_x^2 + u_y^2) (phased), evaluated in
+ * FP64 from the FP32 inputs with IEEE rounding.
+ *   codes  int32 [B][N_max][K]: q, negated for a negative signed amplitude
+ *   phi    double [B][N_max][K]: atan2(u_y, u_x) (phased), or NULL
+ * Non-finite amplitudes give q = 0 and latch REDO_ERR_NONFINITE; clamps are counted.
+ */
+redo_status redo_quantise(redo_table table, const float* u, int32_t B, int32_t N_max,
+                          int32_t* codes, double* phi, void* stream);
+
+/*
+ * Process 2 of Sec. II (Eq. exp2prod) with the drift split of Sec. III:
+ * every step propagator
+ *     U_n = Z_n [prod_k R_k(q_kn)] Z_n^dag V,    R_k = T_k[0][c_0] T_k[1][c_1] ... (c_j = 0 skipped)
+ * (channel 1 rightmost; Z_n = diag exp(-i sum_k phi_kn g_k) when phased; for
+ * a negative signed amplitude R_k is replaced by its adjoint).
+ *   U_out  c64 [B][N][d][d]
+ * Workspace: redo_workspace_bytes(table, REDO_OP_COMPOSE, B, N).
+ */
+redo_status redo_compose_steps(redo_table table, int32_t precision, const float* u, int32_t B,
+                               int32_t N, float* U_out, void* workspace, size_t workspace_bytes,
+                               void* stream);
+
+/*
+ * The chain U = U_N ... U_1 (Sec. III, Eq. propUn) of REDO steps, per instance:
+ *     X_0 = X0[b] (identity when X0 is NULL),  X_n = U_n X_{n-1},  n = 1 .. n_steps[b].
+ *   X0        c64 [B][d][d] or NULL
+ *   U_total   c64 [B][d][d]  receives X_{n_steps[b]} (may equal X0)
+ *   X_prefix  c64 [B][N_max][d][d] receives X_1 .. X_N, or NULL (d <= 64 only)
+ *   reproject_every  R > 0: after every step whose global index
+ *             (step_offset + n) is a multiple of R, replace X by its
+ *             Newton-Schulz polar step X (3I - X^dag X) / 2; 0 = never
+ *   obs_cols, obs_vals, obs_width  an optional Hermitian observable M in
+ *             row-list form: int32 [d][w] column indices and c64 [d][w] values
+ *             of row a (pad with value 0); NULL/0 for none
+ *   obs_out   double [B][N_max]: Tr(X_n M X_n^dag M) / Tr(M M) after step n
+ *             (Sec. IV: <M>(t) for rho(0) = M), or NULL
+ * Workspace: redo_workspace_bytes(table, REDO_OP_CHAIN, B, N_max).
+ */
+redo_status redo_chain_propagator(redo_table table, int32_t precision, const float* u,
+                                  const int32_t* n_steps, int32_t B, int32_t N_max,
+                                  int32_t step_offset, int32_t reproject_every, const float* X0,
+                                  float* U_total, float* X_prefix, const int32_t* obs_cols,
+                                  const float* obs_vals, int32_t obs_width, double* obs_out,
+                                  void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Unitary fidelity (Sec. III): g_b = Tr(U_f^dag U) / Tr(U_f^dag U_f),
+ * F_b = |g_b|^2, accumulated in FP64.
+ *   U_target, U  c64 [B][d][d];  overlap c128 [B] or NULL;  fidelity double [B] or NULL
+ */
+redo_status redo_unitary_fidelity(int32_t d, int32_t B, const float* U_target, const float* U,
+                                  double* overlap, double* fidelity, void* stream);
+
+/*
+ * GRAPE objective and gradient through REDO (Sec. III; the table stays
+ * outside the iteration loop): F_b = |Tr(U_f^dag X_N) / Tr(U_f^dag U_f)|^2
+ * and dF_b/du at the quantised amplitudes, by a forward chain with
+ * checkpoints every `checkpoint_every` steps (0: ceil(sqrt(N_b))), a
+ * recomputation of each segment and a backward scan
+ *     L_N = U_f^dag,  L_{n-1} = L_n U_n,  Y_n = X_n L_n,
+ *     dg/dOmega_kn = -i dt Tr(Z S_k Z^dag Y_n) / Tr(U_f^dag U_f),
+ *     dg/dphi_kn   = -i (Tr(G_k Y_n) - Tr(G_k Y_{n-1})) / Tr(U_f^dag U_f),
+ * then dF = 2 Re(conj(g) dg) and the Cartesian chain rule.  The quantised
+ * step is differentiated as the continuous split step at the quantised
+ * point (straight-through).  Needs channels whose generators commute with
+ * each other and whose phase generators commute with the drift and with the
+ * other channels (REDO_ERR_UNSUPPORTED otherwise).
+ *   U_target  c64 [B][d][d];  fidelity double [B];  overlap c128 [B] or NULL
+ *   grad      float, same layout as u (entries of steps >= n_steps[b] are set to 0)
+ * Workspace: redo_workspace_bytes(table, REDO_OP_GRAPE, B, N_max).
+ */
+redo_status redo_grape_fidelity_grad(redo_table table, int32_t precision, const float* u,
+                                     const int32_t* n_steps, int32_t B, int32_t N_max,
+                                     const float* U_target, int32_t checkpoint_every,
+                                     double* fidelity, double* overlap, float* grad,
+                                     void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Waits for `stream`, then reports and clears the conditions latched by the
+ * device since the last call: REDO_ERR_NONFINITE if a non-finite amplitude
+ * was seen, else REDO_WARN_CLAMPED if any amplitude was clamped, else REDO_OK.
+ * *n_clamped (host, nullable) receives the number of clamped amplitudes.
+ */
+redo_status redo_get_device_status(redo_table table, void* stream, int64_t* n_clamped);
+
+const char* redo_status_string(redo_status status);
+const char* redo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* REDO_H */

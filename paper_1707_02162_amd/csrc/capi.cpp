@@ -1,0 +1,501 @@
+// Host side of the C ABI declared in include/redo.h: argument validation,
+// the one-time FP64 table build (Sec. II, process 1), workspace sizing and
+// dispatch to the small-d fused kernels or the large-d MFMA path.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "large_path.h"
+#include "redo_internal.h"
+
+namespace redo {
+
+static thread_local std::string g_last_error;
+
+redo_status fail(redo_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+redo_status hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? REDO_ERR_ALLOC : REDO_ERR_HIP;
+}
+
+namespace {
+
+bool small_dim(int d) { return d == 2 || d == 4 || d == 8 || d == 16 || d == 32 || d == 64; }
+bool large_dim(int d) { return d >= 128 && d % 64 == 0 && d <= 16384; }
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    template <class T>
+    T* as() const {
+        return static_cast<T*>(p);
+    }
+};
+
+hipError_t dev_alloc(DevBuf& b, size_t bytes) { return hipMalloc(&b.p, std::max<size_t>(bytes, 16)); }
+
+// relative anti-Hermitian part of an interleaved complex d x d matrix
+double antiherm_rel(const double* m, int d) {
+    double num = 0.0, den = 0.0;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            const double ar = m[2 * ((size_t)i * d + j)], ai = m[2 * ((size_t)i * d + j) + 1];
+            const double br = m[2 * ((size_t)j * d + i)], bi = -m[2 * ((size_t)j * d + i) + 1];
+            num += (ar - br) * (ar - br) + (ai - bi) * (ai - bi);
+            den += ar * ar + ai * ai;
+        }
+    return den > 0 ? std::sqrt(num / den) : 0.0;
+}
+
+double norm1(const double* m, int d) {
+    double best = 0.0;
+    for (int j = 0; j < d; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < d; ++i) s += std::hypot(m[2 * ((size_t)i * d + j)], m[2 * ((size_t)i * d + j) + 1]);
+        best = std::max(best, s);
+    }
+    return best;
+}
+
+// exp(-i theta H) in FP64 on the GPU by scaling and squaring of a degree-16
+// Taylor polynomial (Horner form): P <- I + (A_s / i) P, A_s = -i theta H / 2^s,
+// then P <- P^2 s times; s makes ||A_s||_1 <= 1/2, where the truncation
+// error is below 1e-19.  H, out: c128 d x d device; scratch: 1 matrix.
+redo_status expm_fp64(int d, const double2* H, double theta, double h_norm1, double2* out, double2* scratch,
+                      hipStream_t st) {
+    const double a = std::fabs(theta) * h_norm1;
+    int s = 0;
+    while (a / std::ldexp(1.0, s) > 0.5) ++s;
+    const int m = 16;
+    REDO_HIP(fill_identity_z(d, 1, out, 0, st));
+    double2* cur = out;
+    double2* nxt = scratch;
+    for (int i = m; i >= 1; --i) {
+        const double2 alpha = make_double2(0.0, -theta / (std::ldexp(1.0, s) * i));
+        REDO_HIP(zgemm_batched(d, 1, H, 0, cur, 0, nxt, 0, alpha, 1.0, st));
+        std::swap(cur, nxt);
+    }
+    for (int r = 0; r < s; ++r) {
+        REDO_HIP(zgemm_batched(d, 1, cur, 0, cur, 0, nxt, 0, make_double2(1.0, 0.0), 0.0, st));
+        std::swap(cur, nxt);
+    }
+    if (cur != out) REDO_HIP(hipMemcpyAsync(out, cur, sizeof(double2) * d * d, hipMemcpyDeviceToDevice, st));
+    return REDO_OK;
+}
+
+redo_status check_desc(const redo_table_desc* d) {
+    if (!d) return fail(REDO_ERR_ARG, "desc is NULL");
+    if (!small_dim(d->d) && !large_dim(d->d))
+        return fail(REDO_ERR_ARG, "d must be a power of two in [2, 64] or a multiple of 64 in [128, 16384]");
+    if (d->K < 1 || d->K > 16) return fail(REDO_ERR_ARG, "K must be in [1, 16]");
+    if (d->base < 2) return fail(REDO_ERR_ARG, "base must be >= 2");
+    if (d->digits < 1) return fail(REDO_ERR_ARG, "digits must be >= 1");
+    double levels = 1.0;
+    for (int j = 0; j < d->digits; ++j) levels *= d->base;
+    if (levels - 1.0 > 2147483647.0) return fail(REDO_ERR_ARG, "base^digits - 1 exceeds 2^31 - 1");
+    if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(REDO_ERR_ARG, "dt must be finite and > 0");
+    if (!(d->eps > 0.0) || !std::isfinite(d->eps)) return fail(REDO_ERR_ARG, "eps must be finite and > 0");
+    if (d->phased != 0 && d->phased != 1) return fail(REDO_ERR_ARG, "phased must be 0 or 1");
+    if (d->drift_is_diag != 0 && d->drift_is_diag != 1) return fail(REDO_ERR_ARG, "drift_is_diag must be 0 or 1");
+    if (d->n_drift < 1) return fail(REDO_ERR_ARG, "n_drift must be >= 1");
+    if (d->reserved != 0) return fail(REDO_ERR_ARG, "reserved must be 0");
+    return REDO_OK;
+}
+
+long long ceil_sqrt(long long n) {
+    long long c = (long long)std::ceil(std::sqrt((double)n));
+    while (c * c < n) ++c;
+    while (c > 1 && (c - 1) * (c - 1) >= n) --c;
+    return std::max(1LL, c);
+}
+
+}  // namespace
+}  // namespace redo
+
+using namespace redo;
+
+extern "C" {
+
+const char* redo_last_error(void) { return g_last_error.c_str(); }
+
+const char* redo_status_string(redo_status s) {
+    switch (s) {
+        case REDO_OK: return "ok";
+        case REDO_ERR_ARG: return "invalid argument";
+        case REDO_ERR_ALLOC: return "device allocation failed";
+        case REDO_ERR_HIP: return "HIP runtime error";
+        case REDO_ERR_NOT_HERMITIAN: return "operator is not Hermitian";
+        case REDO_ERR_NONFINITE: return "non-finite amplitude";
+        case REDO_ERR_UNSUPPORTED: return "unsupported";
+        case REDO_ERR_WORKSPACE: return "workspace too small";
+        case REDO_WARN_CLAMPED: return "amplitudes clamped";
+        default: return "unknown status";
+    }
+}
+
+redo_status redo_build_table(const redo_table_desc* desc, const double* H0, const double* S, const double* g,
+                             void* stream, redo_table* out) {
+    g_last_error.clear();
+    if (!out) return fail(REDO_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    redo_status st = check_desc(desc);
+    if (st != REDO_OK) return st;
+    if (!H0 || !S) return fail(REDO_ERR_ARG, "H0 and S must not be NULL");
+    if (desc->phased && !g) return fail(REDO_ERR_ARG, "g must be given for phased channels");
+    const int d = desc->d, K = desc->K, P = desc->digits, b = desc->base, R = desc->n_drift;
+    const size_t nn = (size_t)d * d;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+
+    // ---- host copies for validation
+    std::vector<double> hS(2 * nn * K), hH, hg;
+    REDO_HIP(hipMemcpyAsync(hS.data(), S, sizeof(double) * hS.size(), hipMemcpyDeviceToHost, hs));
+    if (desc->drift_is_diag)
+        hH.resize((size_t)R * d);
+    else
+        hH.resize(2 * nn * R);
+    REDO_HIP(hipMemcpyAsync(hH.data(), H0, sizeof(double) * hH.size(), hipMemcpyDeviceToHost, hs));
+    if (desc->phased) {
+        hg.resize((size_t)K * d);
+        REDO_HIP(hipMemcpyAsync(hg.data(), g, sizeof(double) * hg.size(), hipMemcpyDeviceToHost, hs));
+    }
+    REDO_HIP(hipStreamSynchronize(hs));
+    for (double v : hS)
+        if (!std::isfinite(v)) return fail(REDO_ERR_ARG, "S has non-finite entries");
+    for (double v : hH)
+        if (!std::isfinite(v)) return fail(REDO_ERR_ARG, "H0 has non-finite entries");
+    for (double v : hg)
+        if (!std::isfinite(v)) return fail(REDO_ERR_ARG, "g has non-finite entries");
+    std::vector<double> s_norm(K);
+    for (int k = 0; k < K; ++k) {
+        const double* m = hS.data() + 2 * nn * k;
+        if (antiherm_rel(m, d) > 1e-10) return fail(REDO_ERR_NOT_HERMITIAN, "S_" + std::to_string(k) + " is not Hermitian");
+        s_norm[k] = norm1(m, d);
+    }
+    std::vector<double> h_norm(R, 0.0);
+    if (!desc->drift_is_diag)
+        for (int r = 0; r < R; ++r) {
+            const double* m = hH.data() + 2 * nn * r;
+            if (antiherm_rel(m, d) > 1e-10) return fail(REDO_ERR_NOT_HERMITIAN, "H0 is not Hermitian");
+            h_norm[r] = norm1(m, d);
+        }
+
+    auto t = std::make_unique<redo_table_s>();
+    t->desc = *desc;
+    double levels = 1.0;
+    for (int j = 0; j < P; ++j) levels *= b;
+    t->qmax = levels - 1.0;
+    t->entry_elems = (long long)nn;
+
+    // ---- conditions of the adjoint formulas
+    {
+        bool ok = true;
+        std::string why;
+        const double tol = 1e-9;
+        if (desc->phased) {
+            for (int k = 0; k < K && ok; ++k) {
+                const double* gk = hg.data() + (size_t)k * d;
+                for (int kk = 0; kk < K && ok; ++kk) {
+                    if (kk == k) continue;
+                    const double* m = hS.data() + 2 * nn * kk;
+                    for (size_t e = 0; e < nn && ok; ++e) {
+                        const size_t i = e / d, j = e % d;
+                        if (std::fabs(gk[i] - gk[j]) * std::hypot(m[2 * e], m[2 * e + 1]) > tol * (1 + s_norm[kk])) {
+                            ok = false;
+                            why = "phase generator g_" + std::to_string(k) + " does not commute with S_" + std::to_string(kk);
+                        }
+                    }
+                }
+                if (!desc->drift_is_diag)
+                    for (int r = 0; r < R && ok; ++r) {
+                        const double* m = hH.data() + 2 * nn * r;
+                        for (size_t e = 0; e < nn && ok; ++e) {
+                            const size_t i = e / d, j = e % d;
+                            if (std::fabs(gk[i] - gk[j]) * std::hypot(m[2 * e], m[2 * e + 1]) > tol * (1 + h_norm[r])) {
+                                ok = false;
+                                why = "phase generator g_" + std::to_string(k) + " does not commute with the drift";
+                            }
+                        }
+                    }
+            }
+        }
+        if (ok && K > 1) {
+            // [S_k, S_kk] = 0 for every pair, from FP64 products on the GPU
+            DevBuf w;
+            REDO_HIP(dev_alloc(w, sizeof(double2) * nn * 2));
+            std::vector<double> c1(2 * nn), c2(2 * nn);
+            const double2* Sd = reinterpret_cast<const double2*>(S);
+            for (int k = 0; k < K && ok; ++k)
+                for (int kk = k + 1; kk < K && ok; ++kk) {
+                    REDO_HIP(zgemm_batched(d, 1, Sd + nn * k, 0, Sd + nn * kk, 0, w.as<double2>(), 0,
+                                           make_double2(1.0, 0.0), 0.0, hs));
+                    REDO_HIP(zgemm_batched(d, 1, Sd + nn * kk, 0, Sd + nn * k, 0, w.as<double2>() + nn, 0,
+                                           make_double2(1.0, 0.0), 0.0, hs));
+                    REDO_HIP(hipMemcpyAsync(c1.data(), w.p, sizeof(double2) * nn, hipMemcpyDeviceToHost, hs));
+                    REDO_HIP(hipMemcpyAsync(c2.data(), w.as<double2>() + nn, sizeof(double2) * nn,
+                                            hipMemcpyDeviceToHost, hs));
+                    REDO_HIP(hipStreamSynchronize(hs));
+                    double diff = 0.0;
+                    for (size_t e = 0; e < 2 * nn; ++e) diff = std::max(diff, std::fabs(c1[e] - c2[e]));
+                    if (diff > tol * (1 + s_norm[k] * s_norm[kk])) {
+                        ok = false;
+                        why = "S_" + std::to_string(k) + " and S_" + std::to_string(kk) + " do not commute";
+                    }
+                }
+        }
+        t->grad_ok = ok;
+        t->grad_why = why;
+    }
+
+    // ---- device allocations owned by the table
+    auto alloc = [&](void** p, size_t bytes) -> hipError_t {
+        t->bytes += bytes;
+        return hipMalloc(p, std::max<size_t>(bytes, 16));
+    };
+    struct Guard {
+        redo_table_s* t;
+        bool armed = true;
+        ~Guard() {
+            if (armed && t) redo_table_destroy(t);
+        }
+    } guard{t.get()};
+    REDO_HIP(alloc((void**)&t->T32, sizeof(float2) * nn * (size_t)K * P * (b - 1)));
+    REDO_HIP(alloc((void**)&t->S32, sizeof(float2) * nn * K));
+    REDO_HIP(alloc((void**)&t->flags, sizeof(DeviceFlags)));
+    REDO_HIP(hipMemsetAsync(t->flags, 0, sizeof(DeviceFlags), hs));
+    if (desc->drift_is_diag) {
+        REDO_HIP(alloc((void**)&t->h64, sizeof(double) * d * R));
+        REDO_HIP(alloc((void**)&t->V32, sizeof(float2) * d * R));
+    } else {
+        REDO_HIP(alloc((void**)&t->V32, sizeof(float2) * nn * R));
+    }
+    if (desc->phased) REDO_HIP(alloc((void**)&t->g64, sizeof(double) * d * K));
+
+    // ---- FP64 build: E_kj = exp(-i b^j eps dt S_k), T_kj[c] = E_kj^c
+    {
+        const int KP = K * P;
+        DevBuf E, Pw, Pn, scratch;
+        REDO_HIP(dev_alloc(E, sizeof(double2) * nn * KP));
+        REDO_HIP(dev_alloc(Pw, sizeof(double2) * nn * KP));
+        REDO_HIP(dev_alloc(Pn, sizeof(double2) * nn * KP));
+        REDO_HIP(dev_alloc(scratch, sizeof(double2) * nn));
+        const double2* Sd = reinterpret_cast<const double2*>(S);
+        for (int k = 0; k < K; ++k)
+            for (int j = 0; j < P; ++j) {
+                const double theta = std::pow((double)b, j) * desc->eps * desc->dt;
+                st = expm_fp64(d, Sd + nn * k, theta, s_norm[k], E.as<double2>() + nn * (k * P + j),
+                               scratch.as<double2>(), hs);
+                if (st != REDO_OK) return st;
+            }
+        const long long entry_stride = (long long)nn * (b - 1);  // between (k, j) blocks of T32
+        REDO_HIP(round_table_entries(d, KP, E.as<double2>(), t->T32, entry_stride, hs));
+        REDO_HIP(hipMemcpyAsync(Pw.p, E.p, sizeof(double2) * nn * KP, hipMemcpyDeviceToDevice, hs));
+        for (int c = 2; c <= b - 1; ++c) {
+            REDO_HIP(zgemm_batched(d, KP, Pw.as<double2>(), nn, E.as<double2>(), nn, Pn.as<double2>(), nn,
+                                   make_double2(1.0, 0.0), 0.0, hs));
+            std::swap(Pw.p, Pn.p);
+            REDO_HIP(round_table_entries(d, KP, Pw.as<double2>(), t->T32 + (long long)nn * (c - 1), entry_stride, hs));
+        }
+        // drift propagators V = exp(-i dt H0)
+        if (desc->drift_is_diag) {
+            REDO_HIP(hipMemcpyAsync(t->h64, H0, sizeof(double) * d * R, hipMemcpyDeviceToDevice, hs));
+            REDO_HIP(drift_diag_phases(d, R, t->h64, desc->dt, t->V32, hs));
+        } else {
+            const double2* Hd = reinterpret_cast<const double2*>(H0);
+            for (int r = 0; r < R; ++r) {
+                st = expm_fp64(d, Hd + nn * r, desc->dt, h_norm[r], E.as<double2>(), scratch.as<double2>(), hs);
+                if (st != REDO_OK) return st;
+                REDO_HIP(round_z_to_c((long long)nn, E.as<double2>(), t->V32 + nn * r, hs));
+            }
+        }
+        REDO_HIP(round_z_to_c((long long)nn * K, Sd, t->S32, hs));
+        if (desc->phased) REDO_HIP(hipMemcpyAsync(t->g64, g, sizeof(double) * d * K, hipMemcpyDeviceToDevice, hs));
+        REDO_HIP(hipStreamSynchronize(hs));
+    }
+    guard.armed = false;
+    *out = t.release();
+    return REDO_OK;
+}
+
+redo_status redo_table_destroy(redo_table t) {
+    if (!t) return REDO_OK;
+    (void)hipDeviceSynchronize();
+    void* bufs[] = {t->T32, t->h64, t->V32, t->g64, t->S32, t->flags, t->T16hi, t->T16lo, t->cache};
+    for (void* p : bufs)
+        if (p) (void)hipFree(p);
+    delete t;
+    return REDO_OK;
+}
+
+redo_status redo_table_query(redo_table t, redo_table_desc* desc, size_t* bytes) {
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    if (desc) *desc = t->desc;
+    if (bytes) *bytes = t->bytes;
+    return REDO_OK;
+}
+
+size_t redo_workspace_bytes(redo_table t, int32_t op, int32_t B, int32_t N_max) {
+    if (!t || B < 1 || N_max < 1) return 0;
+    const int d = t->desc.d;
+    const size_t mat = sizeof(float2) * (size_t)d * d;
+    if (small_dim(d)) {
+        switch (op) {
+            case REDO_OP_COMPOSE:
+            case REDO_OP_CHAIN: return 0;
+            case REDO_OP_GRAPE: {
+                const long long C = ceil_sqrt(N_max);
+                const long long nck = (N_max + C - 1) / C;
+                return mat * (size_t)B * (size_t)(nck + C);
+            }
+            default: return 0;
+        }
+    }
+    return large_workspace_bytes(t, op, B, N_max);
+}
+
+redo_status redo_quantise(redo_table t, const float* u, int32_t B, int32_t N_max, int32_t* codes, double* phi,
+                          void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    if (B < 1 || N_max < 1) return fail(REDO_ERR_ARG, "B and N_max must be >= 1");
+    if (!u || !codes) return fail(REDO_ERR_ARG, "u and codes must not be NULL");
+    if (t->desc.phased && !phi) return fail(REDO_ERR_ARG, "phi must be given for phased channels");
+    REDO_HIP(quantise_all(t, u, B, N_max, codes, phi, static_cast<hipStream_t>(stream)));
+    return REDO_OK;
+}
+
+redo_status redo_compose_steps(redo_table t, int32_t precision, const float* u, int32_t B, int32_t N, float* U_out,
+                               void* workspace, size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    if (B < 1 || N < 1) return fail(REDO_ERR_ARG, "B and N must be >= 1");
+    if ((long long)B * N > 2147483647LL) return fail(REDO_ERR_ARG, "B*N too large");
+    if (!u || !U_out) return fail(REDO_ERR_ARG, "u and U_out must not be NULL");
+    if (precision < REDO_PREC_F32 || precision > REDO_PREC_BF16X3) return fail(REDO_ERR_ARG, "unknown precision");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (small_dim(t->desc.d)) {
+        if (precision != REDO_PREC_F32) return fail(REDO_ERR_UNSUPPORTED, "d <= 64 runs in FP32 only");
+        SmallChainArgs a{};
+        a.u = u;
+        a.B = B;
+        a.N_max = N;
+        a.compose = 1;
+        a.X_out = reinterpret_cast<float2*>(U_out);
+        REDO_HIP(small_chain(t, a, hs));
+        return REDO_OK;
+    }
+    return large_compose(t, precision, u, B, N, U_out, workspace, workspace_bytes, hs);
+}
+
+redo_status redo_chain_propagator(redo_table t, int32_t precision, const float* u, const int32_t* n_steps, int32_t B,
+                                  int32_t N_max, int32_t step_offset, int32_t reproject_every, const float* X0,
+                                  float* U_total, float* X_prefix, const int32_t* obs_cols, const float* obs_vals,
+                                  int32_t obs_width, double* obs_out, void* workspace, size_t workspace_bytes,
+                                  void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    if (B < 1 || N_max < 1) return fail(REDO_ERR_ARG, "B and N_max must be >= 1");
+    if (!u || !U_total) return fail(REDO_ERR_ARG, "u and U_total must not be NULL");
+    if (step_offset < 0 || reproject_every < 0) return fail(REDO_ERR_ARG, "step_offset, reproject_every must be >= 0");
+    if (precision < REDO_PREC_F32 || precision > REDO_PREC_BF16X3) return fail(REDO_ERR_ARG, "unknown precision");
+    if (obs_out && (!obs_cols || !obs_vals || obs_width < 1))
+        return fail(REDO_ERR_ARG, "obs_out needs obs_cols, obs_vals and obs_width >= 1");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (small_dim(t->desc.d)) {
+        if (precision != REDO_PREC_F32) return fail(REDO_ERR_UNSUPPORTED, "d <= 64 runs in FP32 only");
+        SmallChainArgs a{};
+        a.u = u;
+        a.n_steps = n_steps;
+        a.B = B;
+        a.N_max = N_max;
+        a.compose = 0;
+        a.step_offset = step_offset;
+        a.reproject_every = reproject_every;
+        a.X0 = reinterpret_cast<const float2*>(X0);
+        a.X_out = reinterpret_cast<float2*>(U_total);
+        a.X_prefix = reinterpret_cast<float2*>(X_prefix);
+        a.obs_cols = obs_cols;
+        a.obs_vals = reinterpret_cast<const float2*>(obs_vals);
+        a.obs_width = obs_width;
+        a.obs_out = obs_out;
+        REDO_HIP(small_chain(t, a, hs));
+        return REDO_OK;
+    }
+    if (X_prefix) return fail(REDO_ERR_UNSUPPORTED, "X_prefix is provided for d <= 64 only");
+    return large_chain(t, precision, u, n_steps, B, N_max, step_offset, reproject_every, X0, U_total, obs_cols,
+                       obs_vals, obs_width, obs_out, workspace, workspace_bytes, hs);
+}
+
+redo_status redo_unitary_fidelity(int32_t d, int32_t B, const float* U_target, const float* U, double* overlap,
+                                  double* fidelity, void* stream) {
+    g_last_error.clear();
+    if (d < 1 || B < 1) return fail(REDO_ERR_ARG, "d and B must be >= 1");
+    if (!U_target || !U) return fail(REDO_ERR_ARG, "U_target and U must not be NULL");
+    REDO_HIP(unitary_fidelity(d, B, reinterpret_cast<const float2*>(U_target), reinterpret_cast<const float2*>(U),
+                              reinterpret_cast<double2*>(overlap), fidelity, static_cast<hipStream_t>(stream)));
+    return REDO_OK;
+}
+
+redo_status redo_grape_fidelity_grad(redo_table t, int32_t precision, const float* u, const int32_t* n_steps,
+                                     int32_t B, int32_t N_max, const float* U_target, int32_t checkpoint_every,
+                                     double* fidelity, double* overlap, float* grad, void* workspace,
+                                     size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    if (B < 1 || N_max < 1) return fail(REDO_ERR_ARG, "B and N_max must be >= 1");
+    if (!u || !U_target || !fidelity || !grad) return fail(REDO_ERR_ARG, "u, U_target, fidelity, grad must not be NULL");
+    if (checkpoint_every < 0) return fail(REDO_ERR_ARG, "checkpoint_every must be >= 0");
+    if (precision < REDO_PREC_F32 || precision > REDO_PREC_BF16X3) return fail(REDO_ERR_ARG, "unknown precision");
+    if (!t->grad_ok) return fail(REDO_ERR_UNSUPPORTED, "adjoint needs commuting channels: " + t->grad_why);
+    const long long C = checkpoint_every > 0 ? checkpoint_every : ceil_sqrt(N_max);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (small_dim(t->desc.d)) {
+        if (precision != REDO_PREC_F32) return fail(REDO_ERR_UNSUPPORTED, "d <= 64 runs in FP32 only");
+        const long long nck = (N_max + C - 1) / C;
+        const size_t need = sizeof(float2) * (size_t)t->desc.d * t->desc.d * (size_t)B * (size_t)(nck + C);
+        if (!workspace || workspace_bytes < need)
+            return fail(REDO_ERR_WORKSPACE, "GRAPE workspace needs " + std::to_string(need) + " bytes");
+        SmallGrapeArgs a{};
+        a.u = u;
+        a.n_steps = n_steps;
+        a.B = B;
+        a.N_max = N_max;
+        a.U_target = reinterpret_cast<const float2*>(U_target);
+        a.checkpoint_every = (int)C;
+        a.fidelity = fidelity;
+        a.overlap = reinterpret_cast<double2*>(overlap);
+        a.grad = grad;
+        a.n_ckpt = (int)nck;
+        a.ckpt = static_cast<float2*>(workspace);
+        a.seg = a.ckpt + (size_t)B * nck * t->desc.d * t->desc.d;
+        REDO_HIP(small_grape(t, a, hs));
+        return REDO_OK;
+    }
+    return large_grape(t, precision, u, n_steps, B, N_max, U_target, (int)C, fidelity, overlap, grad, workspace,
+                       workspace_bytes, hs);
+}
+
+redo_status redo_get_device_status(redo_table t, void* stream, int64_t* n_clamped) {
+    g_last_error.clear();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    REDO_HIP(hipStreamSynchronize(hs));
+    DeviceFlags f{};
+    REDO_HIP(hipMemcpy(&f, t->flags, sizeof(f), hipMemcpyDeviceToHost));
+    REDO_HIP(hipMemset(t->flags, 0, sizeof(DeviceFlags)));
+    if (n_clamped) *n_clamped = (int64_t)f.clamped;
+    if (f.nonfinite) return fail(REDO_ERR_NONFINITE, "a non-finite amplitude was seen");
+    if (f.clamped) return REDO_WARN_CLAMPED;
+    return REDO_OK;
+}
+
+}  // extern "C"

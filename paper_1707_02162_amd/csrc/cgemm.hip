@@ -1,0 +1,279 @@
+// Batched complex GEMM on CDNA4 matrix cores for the large-d REDO path.
+//
+// Every product the method performs at d >= 128 is a dense d x d complex
+// contraction: a table factor applied to the chain state (Sec. II, process 2;
+// Sec. III, chain of Eq. propUn), a Newton-Schulz re-projection, or a
+// backward-scan product of the adjoint.  One launch runs a batch of
+// independent products, each described by a GemmDesc:
+//
+//     C = alpha * diag(rs) op(A) diag(ks) op(B) diag(cs) + beta I
+//
+// with op in {N, H}; A = NULL means the identity (a scaled copy), as does
+// B = NULL.  FP32 complex products use v_mfma_f32_32x32x2_f32 either as four
+// real products (4M) or three (Gauss, 3M); FP32 accumulation throughout.
+// Tiles are staged through double-buffered LDS; tiles of one batch entry
+// are mapped to one XCD so its operands are shared in that XCD's L2.
+#include "redo_internal.h"
+
+namespace redo {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int KT = 16;     // complex k per LDS stage
+constexpr int NXCD = 8;    // MI355X: 8 XCDs, workgroups dispatched round-robin
+
+template <int BM, int BN>
+struct GCfg {
+    static constexpr int THREADS = 256;                 // 4 waves, 2 x 2
+    static constexpr int WM = BM / 2, WN = BN / 2;      // wave tile
+    static constexpr int FM = WM / 32, FN = WN / 32;    // 32x32 MFMA blocks per wave
+    static constexpr int LDA = BM + 4, LDB = BN + 4;    // padded LDS rows (complex)
+    static constexpr int AV = BM * KT / 2 / THREADS;    // float4 loads of A per thread per stage
+    static constexpr int BV = BN * KT / 2 / THREADS;
+};
+
+__device__ inline float2 f2(float a, float b) { return make_float2(a, b); }
+
+// global -> registers for one stage
+template <int BM, int BN>
+__device__ inline void load_stage(const GemmDesc& g, int d, int i0, int j0, int k0, float4 (&ra)[GCfg<BM, BN>::AV],
+                                  float4 (&rb)[GCfg<BM, BN>::BV]) {
+    using C = GCfg<BM, BN>;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int m = 0; m < C::AV; ++m) {
+        const int e = t + C::THREADS * m;
+        if (g.opA == 0) {
+            const int row = e / (KT / 2), kq = e % (KT / 2);
+            ra[m] = *reinterpret_cast<const float4*>(g.A + (long long)(i0 + row) * d + k0 + 2 * kq);
+        } else {
+            const int kr = e / (BM / 2), iq = e % (BM / 2);
+            ra[m] = *reinterpret_cast<const float4*>(g.A + (long long)(k0 + kr) * d + i0 + 2 * iq);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < C::BV; ++m) {
+        const int e = t + C::THREADS * m;
+        if (g.opB == 0) {
+            const int kr = e / (BN / 2), jq = e % (BN / 2);
+            rb[m] = *reinterpret_cast<const float4*>(g.B + (long long)(k0 + kr) * d + j0 + 2 * jq);
+        } else {
+            const int row = e / (KT / 2), kq = e % (KT / 2);
+            rb[m] = *reinterpret_cast<const float4*>(g.B + (long long)(j0 + row) * d + k0 + 2 * kq);
+        }
+    }
+}
+
+// registers -> LDS (k-major tiles As[k][i], Bs[k][j]); conjugation, transposition and the k-scaling here
+template <int BM, int BN>
+__device__ inline void store_stage(const GemmDesc& g, int k0, const float4 (&ra)[GCfg<BM, BN>::AV],
+                                   const float4 (&rb)[GCfg<BM, BN>::BV], float2* As, float2* Bs) {
+    using C = GCfg<BM, BN>;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int m = 0; m < C::AV; ++m) {
+        const int e = t + C::THREADS * m;
+        const float4 v = ra[m];
+        if (g.opA == 0) {
+            const int row = e / (KT / 2), kq = e % (KT / 2);
+            As[(2 * kq) * C::LDA + row] = f2(v.x, v.y);
+            As[(2 * kq + 1) * C::LDA + row] = f2(v.z, v.w);
+        } else {
+            const int kr = e / (BM / 2), iq = e % (BM / 2);
+            *reinterpret_cast<float4*>(As + kr * C::LDA + 2 * iq) = make_float4(v.x, -v.y, v.z, -v.w);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < C::BV; ++m) {
+        const int e = t + C::THREADS * m;
+        const float4 v = rb[m];
+        if (g.opB == 0) {
+            const int kr = e / (BN / 2), jq = e % (BN / 2);
+            float2 a = f2(v.x, v.y), b = f2(v.z, v.w);
+            if (g.kscale) {
+                const float2 s = g.kscale[k0 + kr];
+                a = cmul(s, a);
+                b = cmul(s, b);
+            }
+            *reinterpret_cast<float4*>(Bs + kr * C::LDB + 2 * jq) = make_float4(a.x, a.y, b.x, b.y);
+        } else {
+            const int row = e / (KT / 2), kq = e % (KT / 2);
+            float2 a = f2(v.x, -v.y), b = f2(v.z, -v.w);
+            if (g.kscale) {
+                a = cmul(g.kscale[k0 + 2 * kq], a);
+                b = cmul(g.kscale[k0 + 2 * kq + 1], b);
+            }
+            Bs[(2 * kq) * C::LDB + row] = a;
+            Bs[(2 * kq + 1) * C::LDB + row] = b;
+        }
+    }
+}
+
+// MODE 0: 4M, MODE 1: 3M (Gauss)
+template <int BM, int BN, int MODE>
+__global__ __launch_bounds__(256) void cgemm_kernel(int d, int batch, const GemmDesc* __restrict__ descs) {
+    using C = GCfg<BM, BN>;
+    __shared__ float2 As[2][KT * C::LDA];
+    __shared__ float2 Bs[2][KT * C::LDB];
+    const int tiles_n = d / BN;
+    const int ntile = (d / BM) * tiles_n;
+    int bid = blockIdx.x;
+    const int nb = gridDim.x;
+    if (nb % NXCD == 0) bid = (bid % NXCD) * (nb / NXCD) + bid / NXCD;
+    const int be = bid / ntile, tile = bid % ntile;
+    const GemmDesc g = descs[be];
+    if (!g.active || g.A == nullptr || g.B == nullptr) return;  // identity operands: see scaled_copy_kernel
+    const int i0 = (tile / tiles_n) * BM, j0 = (tile % tiles_n) * BN;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wi0 = (wave >> 1) * C::WM, wj0 = (wave & 1) * C::WN;
+    constexpr int NACC = MODE == 0 ? 2 : 3;
+    floatx16 acc[NACC][C::FM][C::FN];
+#pragma unroll
+    for (int a = 0; a < NACC; ++a)
+#pragma unroll
+        for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < C::FN; ++jb)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][ib][jb][r] = 0.f;
+
+    float4 ra[C::AV], rb[C::BV];
+    load_stage<BM, BN>(g, d, i0, j0, 0, ra, rb);
+    store_stage<BM, BN>(g, 0, ra, rb, As[0], Bs[0]);
+    __syncthreads();
+    const int nk = d / KT;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load_stage<BM, BN>(g, d, i0, j0, (kt + 1) * KT, ra, rb);
+        const float2* Ab = As[buf];
+        const float2* Bb = Bs[buf];
+#pragma unroll
+        for (int kk = 0; kk < KT; kk += 2) {
+            const int kr = kk + (lane >> 5);
+            float2 a[C::FM], b[C::FN];
+#pragma unroll
+            for (int ib = 0; ib < C::FM; ++ib) a[ib] = Ab[kr * C::LDA + wi0 + ib * 32 + (lane & 31)];
+#pragma unroll
+            for (int jb = 0; jb < C::FN; ++jb) b[jb] = Bb[kr * C::LDB + wj0 + jb * 32 + (lane & 31)];
+            if constexpr (MODE == 0) {
+#pragma unroll
+                for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+                    for (int jb = 0; jb < C::FN; ++jb)
+                        acc[0][ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ib].x, b[jb].x, acc[0][ib][jb], 0, 0, 0);
+#pragma unroll
+                for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+                    for (int jb = 0; jb < C::FN; ++jb)
+                        acc[1][ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ib].x, b[jb].y, acc[1][ib][jb], 0, 0, 0);
+#pragma unroll
+                for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+                    for (int jb = 0; jb < C::FN; ++jb)
+                        acc[0][ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[ib].y, b[jb].y, acc[0][ib][jb], 0, 0, 0);
+#pragma unroll
+                for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+                    for (int jb = 0; jb < C::FN; ++jb)
+                        acc[1][ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ib].y, b[jb].x, acc[1][ib][jb], 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+                    for (int jb = 0; jb < C::FN; ++jb)
+                        acc[0][ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ib].x, b[jb].x, acc[0][ib][jb], 0, 0, 0);
+#pragma unroll
+                for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+                    for (int jb = 0; jb < C::FN; ++jb)
+                        acc[1][ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ib].y, b[jb].y, acc[1][ib][jb], 0, 0, 0);
+#pragma unroll
+                for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+                    for (int jb = 0; jb < C::FN; ++jb)
+                        acc[2][ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ib].x + a[ib].y, b[jb].x + b[jb].y,
+                                                                              acc[2][ib][jb], 0, 0, 0);
+            }
+        }
+        if (kt + 1 < nk) store_stage<BM, BN>(g, (kt + 1) * KT, ra, rb, As[buf ^ 1], Bs[buf ^ 1]);
+        __syncthreads();
+    }
+    // epilogue: element (i, j) of a 32x32 block lives in lane j + 32 * ((i / 4) % 2), register 4 * (i / 8) + i % 4
+#pragma unroll
+    for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < C::FN; ++jb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = i0 + wi0 + ib * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                const int j = j0 + wj0 + jb * 32 + (lane & 31);
+                float2 v;
+                if constexpr (MODE == 0) {
+                    v = f2(acc[0][ib][jb][r], acc[1][ib][jb][r]);
+                } else {
+                    const float t1 = acc[0][ib][jb][r], t2 = acc[1][ib][jb][r], t3 = acc[2][ib][jb][r];
+                    v = f2(t1 - t2, t3 - t1 - t2);
+                }
+                if (g.rscale) v = cmul(g.rscale[i], v);
+                if (g.cscale) v = cmul(v, g.cscale[j]);
+                v.x *= g.alpha;
+                v.y *= g.alpha;
+                if (i == j) v.x += g.beta_identity;
+                g.C[(long long)i * d + j] = v;
+            }
+}
+
+// Entries with an identity operand: C = alpha * rs o op(X) o (ks or cs) + beta I, no products.
+__global__ __launch_bounds__(256) void scaled_copy_kernel(int d, const GemmDesc* __restrict__ descs) {
+    const GemmDesc g = descs[blockIdx.y];
+    if (!g.active || (g.A != nullptr && g.B != nullptr)) return;
+    const long long nn = (long long)d * d;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / d), j = (int)(e % d);
+        float2 v;
+        if (g.A == nullptr && g.B == nullptr) {
+            v = f2(i == j ? 1.f : 0.f, 0.f);
+            if (g.kscale && i == j) v = g.kscale[i];
+        } else if (g.A == nullptr) {
+            // diag(ks) op(B)
+            v = g.opB == 0 ? g.B[e] : cconj(g.B[(long long)j * d + i]);
+            if (g.kscale) v = cmul(g.kscale[i], v);
+        } else {
+            // op(A) diag(ks)
+            v = g.opA == 0 ? g.A[e] : cconj(g.A[(long long)j * d + i]);
+            if (g.kscale) v = cmul(v, g.kscale[j]);
+        }
+        if (g.rscale) v = cmul(g.rscale[i], v);
+        if (g.cscale) v = cmul(v, g.cscale[j]);
+        v.x *= g.alpha;
+        v.y *= g.alpha;
+        if (i == j) v.x += g.beta_identity;
+        g.C[e] = v;
+    }
+}
+
+template <int BM, int BN, int MODE>
+hipError_t launch(int d, int batch, const GemmDesc* descs, hipStream_t st) {
+    const long long blocks = (long long)(d / BM) * (d / BN) * batch;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((cgemm_kernel<BM, BN, MODE>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// precision: 0 = 4M FP32, 1 = 3M FP32
+hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision, hipStream_t st) {
+    if (d % 64 != 0 || batch < 1) return hipErrorInvalidValue;
+    // identity-operand entries first (they never alias the product entries' outputs in one launch)
+    const int cblocks = (int)std::min<long long>(((long long)d * d + 255) / 256, 1024);
+    hipLaunchKernelGGL(scaled_copy_kernel, dim3(cblocks, batch), dim3(256), 0, st, d, descs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const bool big = d % 128 == 0 && (long long)(d / 128) * (d / 128) * batch >= 512;
+    if (precision == 1) return big ? launch<128, 128, 1>(d, batch, descs, st) : launch<64, 64, 1>(d, batch, descs, st);
+    return big ? launch<128, 128, 0>(d, batch, descs, st) : launch<64, 64, 0>(d, batch, descs, st);
+}
+
+}  // namespace redo

@@ -1,0 +1,479 @@
+// Small kernels around the batched GEMMs of the large-d REDO path: per-step
+// planning (which table entries a step's digits select, Sec. II, processes 2
+// and 3; the drift and phase scalings of the split step, Sec. III), the
+// observable of Sec. IV, and the traces and gradient assembly of the GRAPE
+// adjoint (Sec. III).  All traces accumulate in FP64.
+#include "large_path.h"
+
+namespace redo {
+namespace {
+
+struct PlanArgs {
+    const float2* T;        // table [K][P][b-1][d][d]
+    const float2* V;        // dense drifts [n_drift][d][d] (dense) or null
+    const double* h;        // diagonal drifts [n_drift][d] (diag) or null
+    const double* g;        // phase generators [K][d] or null
+    const int* codes;       // [B][N][K] at the plan's step: codes + n*K per instance
+    const double* phi;      // same layout, or null
+    const int* n_steps;     // [B] or null
+    long long ent;          // d*d
+    long long code_stride;  // elements between instances in codes/phi (N*K)
+    int d, K, P, base, n_drift, phased, dense;
+    int step;               // step index n (for the activity test)
+    int drift_div;          // drift of instance b: ((drift_offset + b) / drift_div) % n_drift
+    long long drift_offset;
+    double dt;
+    float2* X[2];           // ping-pong buffers (per instance stride ent)
+    long long xstride;
+    int in_buf;             // buffer holding the state before this step
+    int compose;            // 1: first slot takes B = identity
+    float2* pre;            // [B][d] scale vectors of this step
+    float2* post;
+    float2* pstar;
+    GemmDesc* descs;        // [S][B]
+    int B;
+};
+
+// one workgroup per instance: scale vectors and the descriptors of every slot
+__global__ __launch_bounds__(256) void plan_step_kernel(PlanArgs a) {
+    const int b = blockIdx.x;
+    const int d = a.d;
+    const bool active = a.n_steps ? a.step < a.n_steps[b] : true;
+    const int* cb = a.codes + (long long)b * a.code_stride;
+    const double* pb = a.phi ? a.phi + (long long)b * a.code_stride : nullptr;
+    const int drift = (int)(((a.drift_offset + b) / a.drift_div) % a.n_drift);
+    for (int r = threadIdx.x; r < d; r += blockDim.x) {
+        double th = 0.0;
+        if (a.phased)
+            for (int k = 0; k < a.K; ++k) th += pb[k] * a.g[(long long)k * d + r];
+        const double2 po = expmi(th);                        // e^{-i theta}
+        a.post[(long long)b * d + r] = make_float2((float)po.x, (float)po.y);
+        a.pstar[(long long)b * d + r] = make_float2((float)po.x, (float)-po.y);
+        if (!a.dense) {
+            const double2 pr = expmi(a.dt * a.h[(long long)drift * d + r] - th);   // v e^{+i theta}
+            a.pre[(long long)b * d + r] = make_float2((float)pr.x, (float)pr.y);
+        }
+    }
+    if (threadIdx.x != 0) return;
+    const int S = (a.dense ? 1 : 0) + a.K * a.P;
+    int buf = a.in_buf;
+    for (int s = 0; s < S; ++s) {
+        GemmDesc g{};
+        g.active = 1;
+        g.alpha = 1.f;
+        g.beta_identity = 0.f;
+        g.B = (a.compose && s == 0) ? nullptr : a.X[buf] + (long long)b * a.xstride;
+        g.C = a.X[buf ^ 1] + (long long)b * a.xstride;
+        if (active) {
+            const bool first_table = s == (a.dense ? 1 : 0);
+            if (a.dense && s == 0) {
+                g.A = a.V + (long long)drift * a.ent;
+                if (a.phased) g.rscale = a.pstar + (long long)b * d;
+            } else {
+                const int slot = s - (a.dense ? 1 : 0);
+                const int k = slot / a.P, j = slot % a.P;
+                const int q = cb[k];
+                const int c = digit_of(q, j, a.base);
+                g.A = c ? a.T + ((long long)(k * a.P + j) * (a.base - 1) + (c - 1)) * a.ent : nullptr;
+                g.opA = q < 0 ? 1 : 0;
+                if (first_table && !a.dense) g.kscale = a.pre + (long long)b * d;
+                if (s == S - 1 && a.phased) g.rscale = a.post + (long long)b * d;
+            }
+        } else {
+            g.A = nullptr;  // inactive step: plain copy
+        }
+        a.descs[(long long)s * a.B + b] = g;
+        buf ^= 1;
+    }
+}
+
+// generic descriptors for a batch: C_b = op(A_b) op(B_b), inactive -> copy of op(B_b) (or skip)
+__global__ void fill_descs_kernel(GemmDesc* descs, int count, const float2* A, long long sA, int opA, const float2* Bm,
+                                  long long sB, int opB, float2* C, long long sC, const int* n_steps, int step,
+                                  int inactive_mode, float alpha, float beta) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    GemmDesc g{};
+    g.active = 1;
+    g.alpha = alpha;
+    g.beta_identity = beta;
+    g.A = A ? A + b * sA : nullptr;
+    g.B = Bm ? Bm + b * sB : nullptr;
+    g.C = C + b * sC;
+    g.opA = opA;
+    g.opB = opB;
+    const bool active = n_steps ? step < n_steps[b] : true;
+    if (!active) {
+        if (inactive_mode == 0) g.active = 0;
+        if (inactive_mode == 2) {
+            g.B = nullptr;
+        } else {
+            g.A = nullptr;
+        }
+        g.alpha = 1.f;
+        g.beta_identity = 0.f;
+    }
+    descs[b] = g;
+}
+
+// observable partial sums: block (rb, b) handles rows [16 rb, 16 rb + 16) of instance b
+constexpr int OBS_ROWS = 16;
+__global__ __launch_bounds__(256) void observable_partial_kernel(int d, const float2* __restrict__ X, long long xstride,
+                                                                 const int* __restrict__ cols,
+                                                                 const float2* __restrict__ vals, int w,
+                                                                 const int* n_steps, int step, double* partial) {
+    const int b = blockIdx.y, rb = blockIdx.x;
+    const float2* Xb = X + (long long)b * xstride;
+    __shared__ double red[256];
+    double acc = 0.0;
+    const bool active = n_steps ? step < n_steps[b] : true;
+    if (active) {
+        for (int r = 0; r < OBS_ROWS; ++r) {
+            const int a = rb * OBS_ROWS + r;
+            for (int col = threadIdx.x; col < d; col += 256) {
+                float2 xm = make_float2(0.f, 0.f), mx = make_float2(0.f, 0.f);
+                for (int t = 0; t < w; ++t) {
+                    cfma(xm, Xb[(long long)a * d + cols[col * w + t]], cconj(vals[col * w + t]));
+                    cfma(mx, vals[a * w + t], Xb[(long long)cols[a * w + t] * d + col]);
+                }
+                acc += (double)xm.x * mx.x + (double)xm.y * mx.y;
+            }
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(long long)b * gridDim.x + rb] = red[0];
+}
+
+__global__ void observable_final_kernel(int nparts, const double* partial, const float2* vals, int nvals,
+                                        const int* n_steps, int step, double* out, long long out_stride) {
+    const int b = blockIdx.x;
+    __shared__ double red[256];
+    double s = 0.0, m2 = 0.0;
+    for (int e = threadIdx.x; e < nparts; e += 256) s += partial[(long long)b * nparts + e];
+    for (int e = threadIdx.x; e < nvals; e += 256) m2 += (double)vals[e].x * vals[e].x + (double)vals[e].y * vals[e].y;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int t = 128; t > 0; t >>= 1) {
+        if ((int)threadIdx.x < t) red[threadIdx.x] += red[threadIdx.x + t];
+        __syncthreads();
+    }
+    const double tot = red[0];
+    __syncthreads();
+    red[threadIdx.x] = m2;
+    __syncthreads();
+    for (int t = 128; t > 0; t >>= 1) {
+        if ((int)threadIdx.x < t) red[threadIdx.x] += red[threadIdx.x + t];
+        __syncthreads();
+    }
+    const bool active = n_steps ? step < n_steps[b] : true;
+    if (threadIdx.x == 0 && active) out[(long long)b * out_stride] = tot / red[0];
+}
+
+// GRAPE traces of Y = X_{s+1} L_{s+1} for every channel k:
+//   T1 = Tr(S^psi Y) with psi = phi (q != 0) or 0 (q == 0), S^psi_ab = e^{-i psi (g_a - g_b)} S_ab
+//   T2 = Tr(S^{pi/2} Y) (phased, q == 0 only), Dg = Tr(G Y)
+// Tile (32 x 32 of (a, b)) partial sums; block (tile, k, b).
+constexpr int TT = 32;
+__global__ __launch_bounds__(256) void trace_partial_kernel(int d, int K, int phased, const float2* __restrict__ Y,
+                                                            long long ystride, const float2* __restrict__ S,
+                                                            const double* __restrict__ g,
+                                                            const int* __restrict__ codes,
+                                                            const double* __restrict__ phi, long long code_stride,
+                                                            const int* n_steps, int step, double* partial) {
+    const int ntile = (d / TT) * (d / TT);
+    const int tile = blockIdx.x, k = blockIdx.y, b = blockIdx.z;
+    const int a0 = (tile / (d / TT)) * TT, b0 = (tile % (d / TT)) * TT;
+    __shared__ float2 Ys[TT][TT + 1];  // Ys[bb][aa] = Y[b0 + bb][a0 + aa]
+    __shared__ double2 pa[TT], pb[TT], qa[TT], qb[TT];
+    __shared__ double red[6][256];
+    const bool active = n_steps ? step < n_steps[b] : true;
+    const float2* Yb = Y + (long long)b * ystride;
+    int q = 0;
+    double ph = 0.0;
+    if (active) {
+        q = codes[(long long)b * code_stride + k];
+        if (phased) ph = phi[(long long)b * code_stride + k];
+    }
+    const bool origin = phased && q == 0;
+    const double psi = phased && !origin ? ph : 0.0;
+    for (int e = threadIdx.x; e < TT * TT; e += 256) {
+        const int bb = e / TT, aa = e % TT;
+        Ys[bb][aa] = active ? Yb[(long long)(b0 + bb) * d + a0 + aa] : make_float2(0.f, 0.f);
+    }
+    if (threadIdx.x < TT) {
+        const int r = threadIdx.x;
+        const double ga = phased ? g[(long long)k * d + a0 + r] : 0.0, gb = phased ? g[(long long)k * d + b0 + r] : 0.0;
+        pa[r] = expmi(psi * ga);                    // e^{-i psi g_a}
+        pb[r] = zconj(expmi(psi * gb));             // e^{+i psi g_b}
+        qa[r] = expmi(1.5707963267948966 * ga);
+        qb[r] = zconj(expmi(1.5707963267948966 * gb));
+    }
+    __syncthreads();
+    double t1r = 0, t1i = 0, t2r = 0, t2i = 0, dr = 0, di = 0;
+    for (int e = threadIdx.x; e < TT * TT; e += 256) {
+        const int aa = e / TT, bb = e % TT;  // S[a][b] coalesced along b
+        const float2 sv = S[(long long)k * d * d + (long long)(a0 + aa) * d + b0 + bb];
+        const float2 y = Ys[bb][aa];
+        const double yr = y.x, yi = y.y;
+        double sr = sv.x, si = sv.y;
+        if (phased) {
+            const double2 p = zmul(pa[aa], pb[bb]);
+            const double r_ = p.x * sr - p.y * si, i_ = p.x * si + p.y * sr;
+            sr = r_;
+            si = i_;
+        }
+        t1r += sr * yr - si * yi;
+        t1i += sr * yi + si * yr;
+        if (origin) {
+            const double2 p = zmul(qa[aa], qb[bb]);
+            const double r_ = p.x * sv.x - p.y * sv.y, i_ = p.x * sv.y + p.y * sv.x;
+            t2r += r_ * yr - i_ * yi;
+            t2i += r_ * yi + i_ * yr;
+        }
+        if (phased && a0 + aa == b0 + bb) {
+            const double ga = g[(long long)k * d + a0 + aa];
+            dr += ga * yr;
+            di += ga * yi;
+        }
+    }
+    double v[6] = {t1r, t1i, t2r, t2i, dr, di};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) red[c][threadIdx.x] = v[c];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) partial[(((long long)b * K + k) * ntile + tile) * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// sums the tile partials: out[b][k][0..5] (T1 re/im, T2 re/im, D re/im)
+__global__ void trace_final_kernel(int ntile, int K, const double* partial, double* out, long long out_bstride) {
+    const int k = blockIdx.y, b = blockIdx.x;
+    __shared__ double red[6][64];
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int t = threadIdx.x; t < ntile; t += 64)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] += partial[(((long long)b * K + k) * ntile + t) * 6 + c];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) red[c][threadIdx.x] = v[c];
+    __syncthreads();
+    for (int s = 32; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) out[(long long)b * out_bstride + k * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// gradient assembly for every (b, s, k):
+//   tr[b][s][k][6]: traces of Y_{s+1}; dm[b][m][k][2]: Tr(G Y_m) for m = 0 .. N (from tr and D_0)
+__global__ void grad_kernel(int B, int N, int K, int phased, double eps, double dt, const int* codes,
+                            const double* phi, const double* tr, const double* d0, const double2* overlap,
+                            const double* nu, const int* n_steps, float* grad) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)B * N * K) return;
+    const int k = (int)(e % K);
+    const int s = (int)((e / K) % N);
+    const int b = (int)(e / ((long long)K * N));
+    const int len = n_steps ? n_steps[b] : N;
+    const int KK = phased ? 2 : 1;
+    float* gp = grad + e * KK;
+    if (s >= len) {
+        gp[0] = 0.f;
+        if (phased) gp[1] = 0.f;
+        return;
+    }
+    const double gr = overlap[b].x, gi = overlap[b].y;
+    const double scale = 2.0 / nu[b];
+    auto im_gc = [&](double zr, double zi) { return gr * zi - gi * zr; };
+    const double* t = tr + e * 6;
+    const int q = codes[e];
+    if (!phased) {
+        gp[0] = (float)(scale * dt * im_gc(t[0], t[1]));
+        return;
+    }
+    if (q == 0) {
+        gp[0] = (float)(scale * dt * im_gc(t[0], t[1]));
+        gp[1] = (float)(scale * dt * im_gc(t[2], t[3]));
+        return;
+    }
+    // D of Y_s: from the traces of step s-1 (its D is of Y_s), or D_0
+    double Dr, Di;
+    if (s == 0) {
+        Dr = d0[((long long)b * K + k) * 2];
+        Di = d0[((long long)b * K + k) * 2 + 1];
+    } else {
+        const double* tp = tr + (e - K) * 6;
+        Dr = tp[4];
+        Di = tp[5];
+    }
+    const double om = q * eps;
+    const double dFo = scale * dt * im_gc(t[0], t[1]);
+    const double dFp = scale * im_gc(t[4] - Dr, t[5] - Di);
+    const double p = phi[e];
+    const double cp = cos(p), sp = sin(p);
+    gp[0] = (float)(cp * dFo - sp * dFp / om);
+    gp[1] = (float)(sp * dFo + cp * dFp / om);
+}
+
+// D_0 = Tr(G_k L_0) per instance and channel, plus nu = Tr(U_f^dag U_f)
+__global__ void d0_kernel(int d, int K, int phased, const float2* L, long long lstride, const double* g, double* d0) {
+    const int b = blockIdx.x, k = blockIdx.y;
+    __shared__ double rr[256], ri[256];
+    double sr = 0, si = 0;
+    if (phased)
+        for (int a = threadIdx.x; a < d; a += 256) {
+            const float2 v = L[(long long)b * lstride + (long long)a * d + a];
+            sr += g[(long long)k * d + a] * v.x;
+            si += g[(long long)k * d + a] * v.y;
+        }
+    rr[threadIdx.x] = sr;
+    ri[threadIdx.x] = si;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            rr[threadIdx.x] += rr[threadIdx.x + s];
+            ri[threadIdx.x] += ri[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d0[((long long)b * K + k) * 2] = rr[0];
+        d0[((long long)b * K + k) * 2 + 1] = ri[0];
+    }
+}
+
+__global__ void norm_kernel(long long nn, const float2* U, double* nu) {
+    const int b = blockIdx.x;
+    __shared__ double r[256];
+    double s = 0;
+    for (long long e = threadIdx.x; e < nn; e += 256) {
+        const float2 v = U[b * nn + e];
+        s += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    r[threadIdx.x] = s;
+    __syncthreads();
+    for (int t = 128; t > 0; t >>= 1) {
+        if ((int)threadIdx.x < t) r[threadIdx.x] += r[threadIdx.x + t];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) nu[b] = r[0];
+}
+
+__global__ void identity_kernel(long long nn, int d, int B, float2* X, long long stride) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nn * B) return;
+    const long long b = e / nn, r = e % nn;
+    X[b * stride + r] = make_float2((r / d) == (r % d) ? 1.f : 0.f, 0.f);
+}
+
+}  // namespace
+
+hipError_t plan_step(const PlanLaunch& p, hipStream_t st) {
+    PlanArgs a;
+    a.T = p.T;
+    a.V = p.V;
+    a.h = p.h;
+    a.g = p.g;
+    a.codes = p.codes;
+    a.phi = p.phi;
+    a.n_steps = p.n_steps;
+    a.ent = p.ent;
+    a.code_stride = p.code_stride;
+    a.d = p.d;
+    a.K = p.K;
+    a.P = p.P;
+    a.base = p.base;
+    a.n_drift = p.n_drift;
+    a.phased = p.phased;
+    a.dense = p.dense;
+    a.step = p.step;
+    a.drift_div = p.drift_div;
+    a.drift_offset = p.drift_offset;
+    a.dt = p.dt;
+    a.X[0] = p.X0;
+    a.X[1] = p.X1;
+    a.xstride = p.xstride;
+    a.in_buf = p.in_buf;
+    a.compose = p.compose;
+    a.pre = p.pre;
+    a.post = p.post;
+    a.pstar = p.pstar;
+    a.descs = p.descs;
+    a.B = p.B;
+    hipLaunchKernelGGL(plan_step_kernel, dim3(p.B), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t fill_descs(GemmDesc* descs, int count, const float2* A, long long sA, int opA, const float2* B, long long sB,
+                      int opB, float2* C, long long sC, const int* n_steps, int step, int inactive_mode, float alpha,
+                      float beta, hipStream_t st) {
+    hipLaunchKernelGGL(fill_descs_kernel, dim3((count + 63) / 64), dim3(64), 0, st, descs, count, A, sA, opA, B, sB,
+                       opB, C, sC, n_steps, step, inactive_mode, alpha, beta);
+    return hipGetLastError();
+}
+
+size_t observable_partial_doubles(int d, int B) { return (size_t)B * (d / OBS_ROWS); }
+
+hipError_t observable(int d, int B, const float2* X, long long xstride, const int* cols, const float2* vals, int w,
+                      const int* n_steps, int step, double* partial, double* out, long long out_stride,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(observable_partial_kernel, dim3(d / OBS_ROWS, B), dim3(256), 0, st, d, X, xstride, cols, vals, w,
+                       n_steps, step, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(observable_final_kernel, dim3(B), dim3(256), 0, st, d / OBS_ROWS, partial, vals, d * w, n_steps,
+                       step, out, out_stride);
+    return hipGetLastError();
+}
+
+size_t trace_partial_doubles(int d, int B, int K) { return (size_t)B * K * (d / TT) * (d / TT) * 6; }
+
+hipError_t traces(int d, int B, int K, int phased, const float2* Y, long long ystride, const float2* S,
+                  const double* g, const int* codes, const double* phi, long long code_stride, const int* n_steps,
+                  int step, double* partial, double* out, long long out_bstride, hipStream_t st) {
+    const int ntile = (d / TT) * (d / TT);
+    hipLaunchKernelGGL(trace_partial_kernel, dim3(ntile, K, B), dim3(256), 0, st, d, K, phased, Y, ystride, S, g, codes,
+                       phi, code_stride, n_steps, step, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(trace_final_kernel, dim3(B, K), dim3(64), 0, st, ntile, K, partial, out, out_bstride);
+    return hipGetLastError();
+}
+
+hipError_t grad_assemble(int B, int N, int K, int phased, double eps, double dt, const int* codes, const double* phi,
+                         const double* tr, const double* d0, const double2* overlap, const double* nu,
+                         const int* n_steps, float* grad, hipStream_t st) {
+    const long long n = (long long)B * N * K;
+    hipLaunchKernelGGL(grad_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, B, N, K, phased, eps, dt, codes,
+                       phi, tr, d0, overlap, nu, n_steps, grad);
+    return hipGetLastError();
+}
+
+hipError_t d0_traces(int d, int B, int K, int phased, const float2* L, long long lstride, const double* g, double* d0,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(d0_kernel, dim3(B, K), dim3(256), 0, st, d, K, phased, L, lstride, g, d0);
+    return hipGetLastError();
+}
+
+hipError_t frob_norms(int d, int B, const float2* U, double* nu, hipStream_t st) {
+    hipLaunchKernelGGL(norm_kernel, dim3(B), dim3(256), 0, st, (long long)d * d, U, nu);
+    return hipGetLastError();
+}
+
+hipError_t fill_identity(int d, int B, float2* X, long long stride, hipStream_t st) {
+    const long long nn = (long long)d * d;
+    hipLaunchKernelGGL(identity_kernel, dim3((unsigned)((nn * B + 255) / 256)), dim3(256), 0, st, nn, d, B, X, stride);
+    return hipGetLastError();
+}
+
+}  // namespace redo

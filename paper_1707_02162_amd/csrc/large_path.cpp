@@ -1,0 +1,352 @@
+// Host orchestration of the large-d REDO path (d >= 128): every product of
+// the method is a batched MFMA complex GEMM over the instances of a call.
+//
+// Chain (Sec. III, Eq. propUn with the split step of Eqs. vn, vnd): per step
+// one planning kernel maps the digits of every instance to table entries
+// (Sec. II, process 2) and then one batched GEMM per factor slot multiplies
+// the states, with the drift and phase scalings fused into the first and last
+// slot.  GRAPE (Sec. III): every step propagator is composed once per call,
+// the forward chain keeps checkpoints, and the backward scan recomputes each
+// segment and runs the products Y = X L and L U_n as one batched launch.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "large_path.h"
+
+namespace redo {
+namespace {
+
+constexpr int REPROJECT_CHUNK = 256;   // instances re-projected per launch (scratch bound)
+constexpr int COMPOSE_CHUNK = 64;      // (instance, step) pairs composed per launch
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// bump allocator over the caller's workspace
+struct Carve {
+    char* base;
+    size_t used = 0;
+    explicit Carve(void* p) : base(static_cast<char*>(p)) {}
+    template <class T>
+    T* take(size_t count) {
+        T* p = reinterpret_cast<T*>(base ? base + used : nullptr);
+        used += align_up(sizeof(T) * count);
+        return p;
+    }
+};
+
+int slots_of(const redo_table_s* t) { return (t->desc.drift_is_diag ? 0 : 1) + t->desc.K * t->desc.digits; }
+
+// layout of every workspace; with base == nullptr it only measures
+struct ChainWS {
+    int* codes;
+    double* phi;
+    float2* W1;
+    float2 *pre, *post, *pstar;
+    GemmDesc* descs;
+    float2* Z;
+    double* obs_partial;
+    size_t bytes;
+    ChainWS(const redo_table_s* t, int B, int N, void* base) {
+        const int d = t->desc.d, K = t->desc.K;
+        const size_t mat = (size_t)d * d;
+        Carve c(base);
+        codes = c.take<int>((size_t)B * N * K);
+        phi = c.take<double>((size_t)B * N * K);
+        W1 = c.take<float2>(mat * B);
+        pre = c.take<float2>((size_t)B * d);
+        post = c.take<float2>((size_t)B * d);
+        pstar = c.take<float2>((size_t)B * d);
+        descs = c.take<GemmDesc>((size_t)std::max(slots_of(t), 2) * B);
+        Z = c.take<float2>(mat * std::min(B, REPROJECT_CHUNK));
+        obs_partial = c.take<double>(observable_partial_doubles(d, B));
+        bytes = c.used;
+    }
+};
+
+struct ComposeWS {
+    int* codes;
+    double* phi;
+    float2* tmp;
+    float2 *pre, *post, *pstar;
+    GemmDesc* descs;
+    size_t bytes;
+    ComposeWS(const redo_table_s* t, long long I, void* base) {
+        const int d = t->desc.d, K = t->desc.K;
+        const size_t mat = (size_t)d * d;
+        const int ch = (int)std::min<long long>(I, COMPOSE_CHUNK);
+        Carve c(base);
+        codes = c.take<int>((size_t)I * K);
+        phi = c.take<double>((size_t)I * K);
+        tmp = c.take<float2>(mat * ch);
+        pre = c.take<float2>((size_t)ch * d);
+        post = c.take<float2>((size_t)ch * d);
+        pstar = c.take<float2>((size_t)ch * d);
+        descs = c.take<GemmDesc>((size_t)slots_of(t) * ch);
+        bytes = c.used;
+    }
+};
+
+struct GrapeWS {
+    ComposeWS* comp = nullptr;
+    void* comp_base;
+    float2* Ustore;
+    float2* ckpt;
+    float2* seg;
+    float2 *Xa, *Xb, *La, *Lb, *Y;
+    double* tr;
+    double* tpart;
+    double* d0;
+    double* nu;
+    double2* ov;
+    GemmDesc* descs;
+    size_t bytes;
+    GrapeWS(const redo_table_s* t, int B, int N, int C, void* base) {
+        const int d = t->desc.d, K = t->desc.K;
+        const size_t mat = (size_t)d * d;
+        const int nck = (N + C - 1) / C;
+        Carve c(base);
+        Ustore = c.take<float2>(mat * B * N);
+        ckpt = c.take<float2>(mat * B * nck);
+        seg = c.take<float2>(mat * B * C);
+        Xa = c.take<float2>(mat * B);
+        Xb = c.take<float2>(mat * B);
+        La = c.take<float2>(mat * B);
+        Lb = c.take<float2>(mat * B);
+        Y = c.take<float2>(mat * B);
+        tr = c.take<double>((size_t)B * N * K * 6);
+        tpart = c.take<double>(trace_partial_doubles(d, B, K));
+        d0 = c.take<double>((size_t)B * K * 2);
+        nu = c.take<double>(B);
+        ov = c.take<double2>(B);
+        descs = c.take<GemmDesc>((size_t)2 * B);
+        comp_base = base ? c.base + c.used : nullptr;
+        ComposeWS cw(t, (long long)B * N, nullptr);
+        c.used += cw.bytes;
+        bytes = c.used;
+    }
+};
+
+long long ceil_sqrt_ll(long long n) {
+    long long c = (long long)std::ceil(std::sqrt((double)n));
+    while (c * c < n) ++c;
+    while (c > 1 && (c - 1) * (c - 1) >= n) --c;
+    return std::max(1LL, c);
+}
+
+int gemm_prec(int precision) { return precision == REDO_PREC_F32_3M ? 1 : 0; }
+
+redo_status check_precision(int precision) {
+    if (precision == REDO_PREC_BF16X3) return fail(REDO_ERR_UNSUPPORTED, "BF16 split precision is not built yet");
+    return REDO_OK;
+}
+
+PlanLaunch plan_base(const redo_table_s* t) {
+    PlanLaunch p{};
+    p.T = t->T32;
+    p.V = t->desc.drift_is_diag ? nullptr : t->V32;
+    p.h = t->h64;
+    p.g = t->g64;
+    p.ent = t->entry_elems;
+    p.d = t->desc.d;
+    p.K = t->desc.K;
+    p.P = t->desc.digits;
+    p.base = t->desc.base;
+    p.n_drift = t->desc.n_drift;
+    p.phased = t->desc.phased;
+    p.dense = t->desc.drift_is_diag ? 0 : 1;
+    p.dt = t->desc.dt;
+    p.xstride = t->entry_elems;
+    p.drift_div = 1;
+    return p;
+}
+
+// compose U_i for I flattened (instance, step) pairs whose codes are already quantised
+redo_status compose_pairs(redo_table_s* t, int precision, long long I, int N, const ComposeWS& w, float2* U_out,
+                          hipStream_t st) {
+    const int S = slots_of(t);
+    const long long mat = t->entry_elems;
+    for (long long i0 = 0; i0 < I; i0 += COMPOSE_CHUNK) {
+        const int ch = (int)std::min<long long>(COMPOSE_CHUNK, I - i0);
+        PlanLaunch p = plan_base(t);
+        p.codes = w.codes + i0 * t->desc.K;
+        p.phi = t->desc.phased ? w.phi + i0 * t->desc.K : nullptr;
+        p.code_stride = t->desc.K;
+        p.step = 0;
+        // instance i of this chunk is pair i0 + i; its drift follows its instance (i0 + i) / N
+        p.drift_div = N;
+        p.drift_offset = i0;
+        p.X0 = U_out + i0 * mat;
+        p.X1 = w.tmp;
+        p.in_buf = S % 2;
+        p.compose = 1;
+        p.pre = w.pre;
+        p.post = w.post;
+        p.pstar = w.pstar;
+        p.descs = w.descs;
+        p.B = ch;
+        REDO_HIP(plan_step(p, st));
+        for (int s = 0; s < S; ++s) REDO_HIP(cgemm_batched(t->desc.d, ch, w.descs + (size_t)s * ch, gemm_prec(precision), st));
+    }
+    return REDO_OK;
+}
+
+}  // namespace
+
+size_t large_workspace_bytes(const redo_table_s* t, int op, int B, int N) {
+    switch (op) {
+        case REDO_OP_COMPOSE: return ComposeWS(t, (long long)B * N, nullptr).bytes;
+        case REDO_OP_CHAIN: return ChainWS(t, B, N, nullptr).bytes;
+        case REDO_OP_GRAPE: return GrapeWS(t, B, N, (int)ceil_sqrt_ll(N), nullptr).bytes;
+        default: return 0;
+    }
+}
+
+redo_status large_compose(redo_table_s* t, int precision, const float* u, int B, int N, float* U_out, void* workspace,
+                          size_t workspace_bytes, hipStream_t st) {
+    redo_status s = check_precision(precision);
+    if (s != REDO_OK) return s;
+    const long long I = (long long)B * N;
+    ComposeWS need(t, I, nullptr);
+    if (!workspace || workspace_bytes < need.bytes)
+        return fail(REDO_ERR_WORKSPACE, "compose workspace needs " + std::to_string(need.bytes) + " bytes");
+    ComposeWS w(t, I, workspace);
+    REDO_HIP(quantise_all(t, u, B, N, w.codes, w.phi, st));
+    return compose_pairs(t, precision, I, N, w, reinterpret_cast<float2*>(U_out), st);
+}
+
+redo_status large_chain(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N,
+                        int step_offset, int reproject_every, const float* X0, float* U_total, const int* obs_cols,
+                        const float* obs_vals, int obs_width, double* obs_out, void* workspace, size_t workspace_bytes,
+                        hipStream_t st) {
+    redo_status s = check_precision(precision);
+    if (s != REDO_OK) return s;
+    ChainWS need(t, B, N, nullptr);
+    if (!workspace || workspace_bytes < need.bytes)
+        return fail(REDO_ERR_WORKSPACE, "chain workspace needs " + std::to_string(need.bytes) + " bytes");
+    ChainWS w(t, B, N, workspace);
+    const int d = t->desc.d;
+    const long long mat = t->entry_elems;
+    float2* X[2] = {reinterpret_cast<float2*>(U_total), w.W1};
+    REDO_HIP(quantise_all(t, u, B, N, w.codes, w.phi, st));
+    if (!X0)
+        REDO_HIP(fill_identity(d, B, X[0], mat, st));
+    else if (X0 != U_total)
+        REDO_HIP(hipMemcpyAsync(X[0], X0, sizeof(float2) * mat * B, hipMemcpyDeviceToDevice, st));
+    const int S = slots_of(t);
+    int cur = 0;
+    const int prec = gemm_prec(precision);
+    for (int n = 0; n < N; ++n) {
+        PlanLaunch p = plan_base(t);
+        p.codes = w.codes + (size_t)n * t->desc.K;
+        p.phi = t->desc.phased ? w.phi + (size_t)n * t->desc.K : nullptr;
+        p.code_stride = (long long)N * t->desc.K;
+        p.n_steps = n_steps;
+        p.step = n;
+        p.X0 = X[0];
+        p.X1 = X[1];
+        p.in_buf = cur;
+        p.pre = w.pre;
+        p.post = w.post;
+        p.pstar = w.pstar;
+        p.descs = w.descs;
+        p.B = B;
+        REDO_HIP(plan_step(p, st));
+        for (int sl = 0; sl < S; ++sl) REDO_HIP(cgemm_batched(d, B, w.descs + (size_t)sl * B, prec, st));
+        cur = (cur + S) & 1;
+        if (reproject_every > 0 && ((long long)step_offset + n + 1) % reproject_every == 0) {
+            // X <- X (3I - X^dag X) / 2 = X Z with Z = -X^dag X / 2 + 3/2 I
+            for (int b0 = 0; b0 < B; b0 += REPROJECT_CHUNK) {
+                const int ch = std::min(REPROJECT_CHUNK, B - b0);
+                const int* ns = n_steps ? n_steps + b0 : nullptr;
+                float2* xin = X[cur] + (size_t)b0 * mat;
+                REDO_HIP(fill_descs(w.descs, ch, xin, mat, 1, xin, mat, 0, w.Z, mat, ns, n, 0, -0.5f, 1.5f, st));
+                REDO_HIP(cgemm_batched(d, ch, w.descs, prec, st));
+                REDO_HIP(fill_descs(w.descs, ch, xin, mat, 0, w.Z, mat, 0, X[cur ^ 1] + (size_t)b0 * mat, mat, ns, n, 2,
+                                    1.f, 0.f, st));
+                REDO_HIP(cgemm_batched(d, ch, w.descs, prec, st));
+            }
+            cur ^= 1;
+        }
+        if (obs_out)
+            REDO_HIP(observable(d, B, X[cur], mat, obs_cols, reinterpret_cast<const float2*>(obs_vals), obs_width,
+                                n_steps, n, w.obs_partial, obs_out + n, N, st));
+    }
+    if (cur != 0) REDO_HIP(hipMemcpyAsync(X[0], X[1], sizeof(float2) * mat * B, hipMemcpyDeviceToDevice, st));
+    return REDO_OK;
+}
+
+redo_status large_grape(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N,
+                        const float* U_target, int C, double* fidelity, double* overlap, float* grad, void* workspace,
+                        size_t workspace_bytes, hipStream_t st) {
+    redo_status s = check_precision(precision);
+    if (s != REDO_OK) return s;
+    GrapeWS need(t, B, N, C, nullptr);
+    if (!workspace || workspace_bytes < need.bytes)
+        return fail(REDO_ERR_WORKSPACE, "GRAPE workspace needs " + std::to_string(need.bytes) + " bytes");
+    GrapeWS w(t, B, N, C, workspace);
+    ComposeWS cw(t, (long long)B * N, w.comp_base);
+    const int d = t->desc.d, K = t->desc.K;
+    const long long mat = t->entry_elems;
+    const int prec = gemm_prec(precision);
+    const float2* Uf = reinterpret_cast<const float2*>(U_target);
+    // every step propagator once
+    REDO_HIP(quantise_all(t, u, B, N, cw.codes, cw.phi, st));
+    s = compose_pairs(t, precision, (long long)B * N, N, cw, w.Ustore, st);
+    if (s != REDO_OK) return s;
+    REDO_HIP(frob_norms(d, B, Uf, w.nu, st));
+    // forward chain with checkpoints
+    REDO_HIP(fill_identity(d, B, w.Xa, mat, st));
+    float2* cur = w.Xa;
+    float2* nxt = w.Xb;
+    const int nck = (N + C - 1) / C;
+    for (int n = 0; n < N; ++n) {
+        if (n % C == 0) {
+            REDO_HIP(fill_descs(w.descs, B, nullptr, 0, 0, cur, mat, 0, w.ckpt + (size_t)(n / C) * mat, mat * nck, n_steps,
+                                n, 0, 1.f, 0.f, st));
+            REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
+        }
+        REDO_HIP(fill_descs(w.descs, B, w.Ustore + (size_t)n * mat, mat * N, 0, cur, mat, 0, nxt, mat, n_steps, n, 1, 1.f,
+                            0.f, st));
+        REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
+        std::swap(cur, nxt);
+    }
+    REDO_HIP(unitary_fidelity(d, B, Uf, cur, w.ov, fidelity, st));
+    if (overlap) REDO_HIP(hipMemcpyAsync(overlap, w.ov, sizeof(double2) * B, hipMemcpyDeviceToDevice, st));
+    // backward: L_N = U_f^dag
+    float2* L = w.La;
+    float2* Ln = w.Lb;
+    REDO_HIP(fill_descs(w.descs, B, nullptr, 0, 0, Uf, mat, 1, L, mat, nullptr, 0, 1, 1.f, 0.f, st));
+    REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
+    const long long code_stride = (long long)N * K;
+    for (int sg = nck - 1; sg >= 0; --sg) {
+        const int s0 = sg * C, s1 = std::min(N, s0 + C);
+        // recompute X_{s0+1} .. X_{s1} into the segment buffer
+        for (int n = s0; n < s1; ++n) {
+            const float2* src = n == s0 ? w.ckpt + (size_t)sg * mat : w.seg + (size_t)(n - s0 - 1) * mat;
+            const long long src_stride = n == s0 ? mat * nck : mat * C;
+            REDO_HIP(fill_descs(w.descs, B, w.Ustore + (size_t)n * mat, mat * N, 0, src, src_stride, 0,
+                                w.seg + (size_t)(n - s0) * mat, mat * C, n_steps, n, 0, 1.f, 0.f, st));
+            REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
+        }
+        for (int sidx = s1 - 1; sidx >= s0; --sidx) {
+            // Y = X_{s+1} L  and  L' = L U_s in one launch
+            REDO_HIP(fill_descs(w.descs, B, w.seg + (size_t)(sidx - s0) * mat, mat * C, 0, L, mat, 0, w.Y, mat, n_steps,
+                                sidx, 0, 1.f, 0.f, st));
+            REDO_HIP(fill_descs(w.descs + B, B, L, mat, 0, w.Ustore + (size_t)sidx * mat, mat * N, 0, Ln, mat, n_steps,
+                                sidx, 2, 1.f, 0.f, st));
+            REDO_HIP(cgemm_batched(d, 2 * B, w.descs, prec, st));
+            REDO_HIP(traces(d, B, K, t->desc.phased, w.Y, mat, t->S32, t->g64, cw.codes + (size_t)sidx * K,
+                            t->desc.phased ? cw.phi + (size_t)sidx * K : nullptr, code_stride, n_steps, sidx, w.tpart,
+                            w.tr + (size_t)sidx * K * 6, code_stride * 6, st));
+            std::swap(L, Ln);
+        }
+    }
+    REDO_HIP(d0_traces(d, B, K, t->desc.phased, L, mat, t->g64, w.d0, st));
+    REDO_HIP(grad_assemble(B, N, K, t->desc.phased, t->desc.eps, t->desc.dt, cw.codes,
+                           t->desc.phased ? cw.phi : nullptr, w.tr, w.d0, w.ov, w.nu, n_steps, grad, st));
+    return REDO_OK;
+}
+
+}  // namespace redo

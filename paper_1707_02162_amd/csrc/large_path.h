@@ -1,0 +1,66 @@
+// Large-dimension REDO path (d >= 128, d % 64 == 0): batched complex GEMMs on MFMA.
+#pragma once
+#include "redo_internal.h"
+
+namespace redo {
+
+size_t large_workspace_bytes(const redo_table_s* t, int op, int B, int N_max);
+
+redo_status large_compose(redo_table_s* t, int precision, const float* u, int B, int N, float* U_out,
+                          void* workspace, size_t workspace_bytes, hipStream_t st);
+
+redo_status large_chain(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N_max,
+                        int step_offset, int reproject_every, const float* X0, float* U_total, const int* obs_cols,
+                        const float* obs_vals, int obs_width, double* obs_out, void* workspace,
+                        size_t workspace_bytes, hipStream_t st);
+
+redo_status large_grape(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N_max,
+                        const float* U_target, int checkpoint_every, double* fidelity, double* overlap, float* grad,
+                        void* workspace, size_t workspace_bytes, hipStream_t st);
+
+// ---- kernels of large_kernels.hip
+struct PlanLaunch {
+    const float2* T;
+    const float2* V;
+    const double* h;
+    const double* g;
+    const int* codes;
+    const double* phi;
+    const int* n_steps;
+    long long ent, code_stride;
+    int d, K, P, base, n_drift, phased, dense, step, drift_div;
+    long long drift_offset;  // instance b of the launch is global index drift_offset + b
+    double dt;
+    float2* X0;
+    float2* X1;
+    long long xstride;
+    int in_buf, compose;
+    float2* pre;
+    float2* post;
+    float2* pstar;
+    GemmDesc* descs;
+    int B;
+};
+hipError_t plan_step(const PlanLaunch& p, hipStream_t st);
+
+// inactive_mode: 0 skip the entry, 1 copy op(B) into C, 2 copy op(A) into C
+hipError_t fill_descs(GemmDesc* descs, int count, const float2* A, long long sA, int opA, const float2* B,
+                      long long sB, int opB, float2* C, long long sC, const int* n_steps, int step,
+                      int inactive_mode, float alpha, float beta, hipStream_t st);
+size_t observable_partial_doubles(int d, int B);
+hipError_t observable(int d, int B, const float2* X, long long xstride, const int* cols, const float2* vals, int w,
+                      const int* n_steps, int step, double* partial, double* out, long long out_stride,
+                      hipStream_t st);
+size_t trace_partial_doubles(int d, int B, int K);
+hipError_t traces(int d, int B, int K, int phased, const float2* Y, long long ystride, const float2* S,
+                  const double* g, const int* codes, const double* phi, long long code_stride, const int* n_steps,
+                  int step, double* partial, double* out, long long out_bstride, hipStream_t st);
+hipError_t grad_assemble(int B, int N, int K, int phased, double eps, double dt, const int* codes, const double* phi,
+                         const double* tr, const double* d0, const double2* overlap, const double* nu,
+                         const int* n_steps, float* grad, hipStream_t st);
+hipError_t d0_traces(int d, int B, int K, int phased, const float2* L, long long lstride, const double* g, double* d0,
+                     hipStream_t st);
+hipError_t frob_norms(int d, int B, const float2* U, double* nu, hipStream_t st);
+hipError_t fill_identity(int d, int B, float2* X, long long stride, hipStream_t st);
+
+}  // namespace redo

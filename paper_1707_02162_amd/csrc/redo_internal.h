@@ -1,0 +1,203 @@
+// Internal declarations of the REDO library (host and device).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/redo.h"
+
+namespace redo {
+
+// ---------------------------------------------------------------------------
+// complex helpers on float2 / double2 (interleaved re, im)
+// ---------------------------------------------------------------------------
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 zmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
+__host__ __device__ inline double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+// a += b * c  (complex)
+__device__ inline void cfma(float2& a, float2 b, float2 c) {
+    a.x = fmaf(b.x, c.x, a.x);
+    a.x = fmaf(-b.y, c.y, a.x);
+    a.y = fmaf(b.x, c.y, a.y);
+    a.y = fmaf(b.y, c.x, a.y);
+}
+// exp(-i x) in FP64
+__device__ inline double2 expmi(double x) {
+    double s, c;
+    sincos(x, &s, &c);
+    return make_double2(c, -s);
+}
+
+// Device-side latched conditions (one per table).
+struct DeviceFlags {
+    unsigned long long clamped;
+    unsigned int nonfinite;
+    unsigned int pad;
+};
+
+// ---------------------------------------------------------------------------
+// Coarse graining (Sec. II, Eq. cgrain): the one place where floating point
+// decides an integer code.  IEEE FP64 from the FP32 inputs: the squares of
+// FP32 values are exact in FP64, so a contracted fma gives the same sum.
+// Returns q (negated for a negative signed amplitude); *phi gets atan2.
+// ---------------------------------------------------------------------------
+__device__ inline int quantise_one(const float* up, int phased, double eps, double qmax,
+                                   double* phi, DeviceFlags* flags) {
+    double om;
+    bool neg = false;
+    if (phased) {
+        const double ux = up[0], uy = up[1];
+        om = sqrt(ux * ux + uy * uy);
+        *phi = atan2(uy, ux);
+    } else {
+        const double x = up[0];
+        om = fabs(x);
+        neg = x < 0.0;
+        *phi = 0.0;
+    }
+    if (!(om <= 1.7976931348623157e308)) {  // NaN or Inf
+        if (flags) atomicOr(&flags->nonfinite, 1u);
+        *phi = 0.0;
+        return 0;
+    }
+    double qf = floor(om / eps + 0.5);
+    if (qf > qmax) {
+        if (flags) atomicAdd(&flags->clamped, 1ull);
+        qf = qmax;
+    }
+    const int q = (int)qf;
+    return neg ? -q : q;
+}
+
+// digit j of code |q| in base b
+__device__ inline int digit_of(int q, int j, int base) {
+    int a = q < 0 ? -q : q;
+    for (int t = 0; t < j; ++t) a /= base;
+    return a % base;
+}
+
+}  // namespace redo
+
+// ---------------------------------------------------------------------------
+// the opaque table
+// ---------------------------------------------------------------------------
+struct redo_table_s {
+    redo_table_desc desc;
+    double qmax;            // b^P - 1
+    int64_t entry_elems;    // d*d
+    // device buffers owned by the table
+    float2* T32 = nullptr;  // [K][P][b-1][d][d]
+    double* h64 = nullptr;  // diagonal drifts [n_drift][d] (drift_is_diag)
+    float2* V32 = nullptr;  // drift propagators: diag [n_drift][d] or dense [n_drift][d][d]
+    double* g64 = nullptr;  // phase generators [K][d] (phased)
+    float2* S32 = nullptr;  // generators rounded to FP32, [K][d][d]
+    redo::DeviceFlags* flags = nullptr;
+    size_t bytes = 0;
+    bool grad_ok = false;   // channels commute with each other, phases with drift
+    std::string grad_why;
+    // BF16 split planes of the table (built on first use): hi and lo, [K][P][b-1][d][d][2] each
+    uint16_t* T16hi = nullptr;
+    uint16_t* T16lo = nullptr;
+    // composed level cache (process 3): R(q) for q in [cache_lo, cache_hi]
+    float2* cache = nullptr;
+    int cache_lo = 0, cache_hi = -1;
+};
+
+namespace redo {
+
+// error reporting (thread-local string)
+redo_status fail(redo_status st, const std::string& msg);
+redo_status hip_fail(hipError_t e, const char* what);
+
+#define REDO_HIP(call)                                          \
+    do {                                                        \
+        hipError_t _e = (call);                                 \
+        if (_e != hipSuccess) return ::redo::hip_fail(_e, #call); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// launchers implemented in the .hip files
+// ---------------------------------------------------------------------------
+// FP64 complex GEMM, batched with strides: C = alpha*A*B + beta*I  (n x n)
+hipError_t zgemm_batched(int n, int batch, const double2* A, long long sA, const double2* B,
+                         long long sB, double2* C, long long sC, double2 alpha, double beta,
+                         hipStream_t st);
+hipError_t fill_identity_z(int n, int batch, double2* C, long long sC, hipStream_t st);
+hipError_t round_table_entries(int n, int batch, const double2* src, float2* dst, long long dst_batch_stride,
+                               hipStream_t st);
+hipError_t drift_diag_phases(int d, int n_drift, const double* h, double dt, float2* V, hipStream_t st);
+hipError_t round_z_to_c(long long count, const double2* src, float2* dst, hipStream_t st);
+hipError_t split_bf16(long long count, const float2* src, uint16_t* hi, uint16_t* lo, hipStream_t st);
+
+hipError_t quantise_all(const redo_table_s* t, const float* u, int B, int N, int* codes, double* phi,
+                        hipStream_t st);
+
+// small-d fused chain / compose (d <= 64)
+struct SmallChainArgs {
+    const float* u;          // amplitudes
+    const int* n_steps;      // [B] or null
+    int B, N_max;            // instance layout of u
+    int compose;             // 1: instance = (b, n), one step from identity, output U_out
+    int step_offset, reproject_every;
+    const float2* X0;        // [B][d][d] or null
+    float2* X_out;           // [B][d][d] (chain) or [B][N][d][d] (compose)
+    float2* X_prefix;        // [B][N_max][d][d] or null
+    const int* obs_cols;
+    const float2* obs_vals;
+    int obs_width;
+    double* obs_out;         // [B][N_max]
+};
+hipError_t small_chain(const redo_table_s* t, const SmallChainArgs& a, hipStream_t st);
+
+struct SmallGrapeArgs {
+    const float* u;
+    const int* n_steps;
+    int B, N_max;
+    const float2* U_target;
+    int checkpoint_every;    // > 0
+    double* fidelity;
+    double2* overlap;
+    float* grad;
+    float2* ckpt;            // workspace [B][n_ckpt][d][d]
+    float2* seg;             // workspace [B][checkpoint_every][d][d]
+    int n_ckpt;
+};
+hipError_t small_grape(const redo_table_s* t, const SmallGrapeArgs& a, hipStream_t st);
+
+// fidelity reduction, FP64
+hipError_t unitary_fidelity(int d, int B, const float2* Uf, const float2* U, double2* overlap,
+                            double* fidelity, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// large-d path (d >= 128, d % 64 == 0): batched complex GEMM on MFMA
+// ---------------------------------------------------------------------------
+struct GemmDesc {
+    const float2* A;     // d x d, or null for A = I
+    const float2* B;     // d x d
+    float2* C;           // d x d (must not alias A or B)
+    const float2* kscale;  // scales row k of B (diag on the right of op(A)), or null
+    const float2* rscale;  // scales row i of C, or null
+    const float2* cscale;  // scales column j of C, or null
+    int opA;             // 0: A, 1: A^H
+    int opB;             // 0: B, 1: B^H
+    int active;          // 0: skip this entry entirely
+    float beta_identity; // C += beta * I after scaling (Newton-Schulz), usually 0
+    float alpha;         // C = alpha * (...)
+    int pad;
+};
+static_assert(sizeof(GemmDesc) % 8 == 0, "desc alignment");
+
+hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision, hipStream_t st);
+
+}  // namespace redo

@@ -1,0 +1,717 @@
+// Small-dimension REDO path (d = 2 .. 64): one fused kernel runs a whole
+// chain per instance.  Each step quantises its amplitudes (Sec. II, Eq.
+// cgrain), multiplies the state by the table factors that the digits select
+// (processes 1 and 2, Eqs. redoform and exp2prod) between the drift and
+// phase scalings of the split step (Sec. III, Eqs. vn and vnd), and chains
+// the result (Sec. III, Eq. propUn).  Products are staged in LDS; every
+// thread owns a 4x4 strided sub-block of one instance's d x d state, so an
+// instance is (d/4)^2 threads and a 256-thread workgroup hosts several.
+// The GRAPE kernel adds a checkpointed backward scan for the gradient.
+#include "redo_internal.h"
+
+namespace redo {
+namespace {
+
+constexpr int KMAX = 16;
+
+struct TView {
+    const float2* T;
+    const float2* V;
+    const double* h;
+    const double* g;
+    const float2* S;
+    DeviceFlags* flags;
+    long long ent;   // d*d
+    int d, K, P, base, phased, diag, n_drift;
+    double eps, qmax, dt;
+};
+
+TView view_of(const redo_table_s* t) {
+    TView v;
+    v.T = t->T32;
+    v.V = t->V32;
+    v.h = t->h64;
+    v.g = t->g64;
+    v.S = t->S32;
+    v.flags = t->flags;
+    v.ent = t->entry_elems;
+    v.d = t->desc.d;
+    v.K = t->desc.K;
+    v.P = t->desc.digits;
+    v.base = t->desc.base;
+    v.phased = t->desc.phased;
+    v.diag = t->desc.drift_is_diag;
+    v.n_drift = t->desc.n_drift;
+    v.eps = t->desc.eps;
+    v.qmax = t->qmax;
+    v.dt = t->desc.dt;
+    return v;
+}
+
+template <int D>
+struct Cfg {
+    static constexpr int TB = D >= 4 ? 4 : D;  // sub-block edge per thread
+    static constexpr int NT = D / TB;          // threads along a row of sub-blocks
+    static constexpr int TPI = NT * NT;        // threads per instance
+    static constexpr int IPB = 256 / TPI;      // instances per workgroup
+};
+
+// ---------------------------------------------------------------- LDS helpers
+// element (r, c) of the thread's sub-block is (ti + NT r, tj + NT c)
+template <int D>
+__device__ inline void store_block(float2* Ms, const float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], int ti, int tj) {
+    constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
+#pragma unroll
+    for (int r = 0; r < TB; ++r)
+#pragma unroll
+        for (int c = 0; c < TB; ++c) Ms[(ti + NT * r) * D + tj + NT * c] = x[r][c];
+}
+
+// Ms <- src (d x d from global), or src^dag when adj
+template <int D>
+__device__ inline void stage(float2* Ms, const float2* __restrict__ src, bool adj, int lt) {
+    constexpr int TPI = Cfg<D>::TPI;
+    for (int e = lt; e < D * D; e += TPI) {
+        const float2 v = src[e];
+        if (adj)
+            Ms[(e % D) * D + e / D] = cconj(v);
+        else
+            Ms[e] = v;
+    }
+}
+
+// x <- Fs * Xs  (rows of the thread's block)
+template <int D>
+__device__ inline void mul_left(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], const float2* Fs, const float2* Xs, int ti,
+                                int tj) {
+    constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
+    float2 acc[TB][TB];
+#pragma unroll
+    for (int r = 0; r < TB; ++r)
+#pragma unroll
+        for (int c = 0; c < TB; ++c) acc[r][c] = make_float2(0.f, 0.f);
+#pragma unroll 4
+    for (int m = 0; m < D; ++m) {
+        float2 f[TB], y[TB];
+#pragma unroll
+        for (int r = 0; r < TB; ++r) f[r] = Fs[(ti + NT * r) * D + m];
+#pragma unroll
+        for (int c = 0; c < TB; ++c) y[c] = Xs[m * D + tj + NT * c];
+#pragma unroll
+        for (int r = 0; r < TB; ++r)
+#pragma unroll
+            for (int c = 0; c < TB; ++c) cfma(acc[r][c], f[r], y[c]);
+    }
+#pragma unroll
+    for (int r = 0; r < TB; ++r)
+#pragma unroll
+        for (int c = 0; c < TB; ++c) x[r][c] = acc[r][c];
+}
+
+// reduce over the TPI threads of one instance (consecutive lanes); all get the sum
+template <int D>
+__device__ inline double inst_sum(double v, double* scratch) {
+    constexpr int TPI = Cfg<D>::TPI;
+    constexpr int W = TPI < 64 ? TPI : 64;
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if constexpr (TPI > 64) {
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+        __syncthreads();
+        v = scratch[0] + scratch[1] + scratch[2] + scratch[3];
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------- one step
+// phase angle theta_a = sum_k phi_k g_k[a] of every row a the thread owns;
+// also returns the number of channels.  Quantises all channels of the step.
+template <int D>
+__device__ inline void step_phases(const TView& tv, const float* us, bool active, int ti, double (&th)[Cfg<D>::TB]) {
+    constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
+#pragma unroll
+    for (int r = 0; r < TB; ++r) th[r] = 0.0;
+    if (!active || !tv.phased) return;
+    for (int k = 0; k < tv.K; ++k) {
+        double phi;
+        quantise_one(us + 2 * k, 1, tv.eps, tv.qmax, &phi, nullptr);
+#pragma unroll
+        for (int r = 0; r < TB; ++r) th[r] += phi * tv.g[(long long)k * D + ti + NT * r];
+    }
+}
+
+// x <- U_n x with U_n = Z [prod_k R_k] Z^dag V
+template <int D>
+__device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float2* Fs,
+                          const float* us, int drift, bool active, bool report, int lt, int ti, int tj) {
+    constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
+    const int KK = tv.phased ? 2 : 1;
+    double th[TB];
+    step_phases<D>(tv, us, active, ti, th);
+    // drift, then Z^dag (diagonal scalings of rows)
+    if (tv.diag) {
+        if (active) {
+#pragma unroll
+            for (int r = 0; r < TB; ++r) {
+                const double2 e = expmi(tv.dt * tv.h[(long long)drift * D + ti + NT * r] - th[r]);
+                const float2 s = make_float2((float)e.x, (float)e.y);
+#pragma unroll
+                for (int c = 0; c < TB; ++c) x[r][c] = cmul(s, x[r][c]);
+            }
+        }
+    } else {
+        __syncthreads();
+        if (active) {
+            stage<D>(Fs, tv.V + (long long)drift * tv.ent, false, lt);
+            store_block<D>(Xs, x, ti, tj);
+        }
+        __syncthreads();
+        if (active) {
+            mul_left<D>(x, Fs, Xs, ti, tj);
+            if (tv.phased) {
+#pragma unroll
+                for (int r = 0; r < TB; ++r) {
+                    const double2 e = expmi(-th[r]);
+                    const float2 s = make_float2((float)e.x, (float)e.y);
+#pragma unroll
+                    for (int c = 0; c < TB; ++c) x[r][c] = cmul(s, x[r][c]);
+                }
+            }
+        }
+    }
+    // table factors: channel 0 first (rightmost), digits ascending
+    for (int k = 0; k < tv.K; ++k) {
+        double phi;
+        const int q = active ? quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, &phi,
+                                            report ? tv.flags : nullptr)
+                             : 0;
+        for (int j = 0; j < tv.P; ++j) {
+            const int c = digit_of(q, j, tv.base);
+            __syncthreads();
+            if (c != 0) {
+                stage<D>(Fs, tv.T + ((long long)(k * tv.P + j) * (tv.base - 1) + (c - 1)) * tv.ent, q < 0, lt);
+                store_block<D>(Xs, x, ti, tj);
+            }
+            __syncthreads();
+            if (c != 0) mul_left<D>(x, Fs, Xs, ti, tj);
+        }
+    }
+    // Z
+    if (active && tv.phased) {
+#pragma unroll
+        for (int r = 0; r < TB; ++r) {
+            const double2 e = expmi(th[r]);
+            const float2 s = make_float2((float)e.x, (float)e.y);
+#pragma unroll
+            for (int c = 0; c < TB; ++c) x[r][c] = cmul(s, x[r][c]);
+        }
+    }
+}
+
+// l <- l U_n  (the backward scan), U_n = Z [prod_k R_k] Z^dag V
+template <int D>
+__device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB], float2* Ls, float2* Fs,
+                           const float* us, int drift, bool active, int lt, int ti, int tj) {
+    constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
+    const int KK = tv.phased ? 2 : 1;
+    // column phases: theta_c for the columns the thread owns
+    double thc[TB];
+    step_phases<D>(tv, us, active, tj, thc);
+    if (active && tv.phased) {
+#pragma unroll
+        for (int c = 0; c < TB; ++c) {
+            const double2 e = expmi(thc[c]);
+            const float2 s = make_float2((float)e.x, (float)e.y);
+#pragma unroll
+            for (int r = 0; r < TB; ++r) l[r][c] = cmul(l[r][c], s);
+        }
+    }
+    for (int k = tv.K - 1; k >= 0; --k) {
+        double phi;
+        const int q = active ? quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, &phi, nullptr) : 0;
+        for (int j = tv.P - 1; j >= 0; --j) {
+            const int c = digit_of(q, j, tv.base);
+            __syncthreads();
+            if (c != 0) {
+                stage<D>(Fs, tv.T + ((long long)(k * tv.P + j) * (tv.base - 1) + (c - 1)) * tv.ent, q < 0, lt);
+                store_block<D>(Ls, l, ti, tj);
+            }
+            __syncthreads();
+            if (c != 0) mul_left<D>(l, Ls, Fs, ti, tj);  // (Ls Fs) restricted to own block
+        }
+    }
+    if (tv.diag) {
+        if (active) {
+#pragma unroll
+            for (int c = 0; c < TB; ++c) {
+                const double2 e = expmi(tv.dt * tv.h[(long long)drift * D + tj + NT * c] - thc[c]);
+                const float2 s = make_float2((float)e.x, (float)e.y);
+#pragma unroll
+                for (int r = 0; r < TB; ++r) l[r][c] = cmul(l[r][c], s);
+            }
+        }
+    } else {
+        if (active && tv.phased) {
+#pragma unroll
+            for (int c = 0; c < TB; ++c) {
+                const double2 e = expmi(-thc[c]);
+                const float2 s = make_float2((float)e.x, (float)e.y);
+#pragma unroll
+                for (int r = 0; r < TB; ++r) l[r][c] = cmul(l[r][c], s);
+            }
+        }
+        __syncthreads();
+        if (active) {
+            stage<D>(Fs, tv.V + (long long)drift * tv.ent, false, lt);
+            store_block<D>(Ls, l, ti, tj);
+        }
+        __syncthreads();
+        if (active) mul_left<D>(l, Ls, Fs, ti, tj);
+    }
+}
+
+// Newton-Schulz polar step x <- x (3I - x^dag x) / 2  (uniform barriers)
+template <int D>
+__device__ void reproject(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float2* Fs, bool active, int ti, int tj) {
+    constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
+    __syncthreads();
+    if (active) store_block<D>(Xs, x, ti, tj);
+    __syncthreads();
+    float2 z[TB][TB];
+    if (active) {
+        // z = x^dag x on the thread's block
+#pragma unroll
+        for (int r = 0; r < TB; ++r)
+#pragma unroll
+            for (int c = 0; c < TB; ++c) z[r][c] = make_float2(0.f, 0.f);
+        for (int m = 0; m < D; ++m) {
+            float2 a[TB], b[TB];
+#pragma unroll
+            for (int r = 0; r < TB; ++r) a[r] = cconj(Xs[m * D + ti + NT * r]);
+#pragma unroll
+            for (int c = 0; c < TB; ++c) b[c] = Xs[m * D + tj + NT * c];
+#pragma unroll
+            for (int r = 0; r < TB; ++r)
+#pragma unroll
+                for (int c = 0; c < TB; ++c) cfma(z[r][c], a[r], b[c]);
+        }
+#pragma unroll
+        for (int r = 0; r < TB; ++r)
+#pragma unroll
+            for (int c = 0; c < TB; ++c) {
+                z[r][c] = make_float2(-0.5f * z[r][c].x, -0.5f * z[r][c].y);
+                if (ti + NT * r == tj + NT * c) z[r][c].x += 1.5f;
+            }
+        store_block<D>(Fs, z, ti, tj);
+    }
+    __syncthreads();
+    if (active) mul_left<D>(x, Xs, Fs, ti, tj);
+}
+
+// ---------------------------------------------------------------- chain kernel
+template <int D>
+__global__ __launch_bounds__(256) void small_chain_kernel(TView tv, SmallChainArgs a, int ninst) {
+    constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT, TPI = Cfg<D>::TPI, IPB = Cfg<D>::IPB;
+    extern __shared__ float2 lds[];
+    __shared__ double red[4];
+    __shared__ int nblk;
+    const int tid = threadIdx.x, slot = tid / TPI, lt = tid % TPI;
+    const int ti = lt / NT, tj = lt % NT;
+    const int inst = blockIdx.x * IPB + slot;
+    const bool valid = inst < ninst;
+    float2* Xs = lds + (long long)slot * 2 * D * D;
+    float2* Fs = Xs + D * D;
+    int b = 0, n0 = 0, len = 0;
+    if (valid) {
+        if (a.compose) {
+            b = inst / a.N_max;
+            n0 = inst % a.N_max;
+            len = 1;
+        } else {
+            b = inst;
+            len = a.n_steps ? a.n_steps[b] : a.N_max;
+        }
+    }
+    if (tid == 0) nblk = 0;
+    __syncthreads();
+    if (lt == 0 && len > 0) atomicMax(&nblk, len);
+    __syncthreads();
+    const int N = nblk;
+    const int drift = b % tv.n_drift;
+    const int KK = tv.phased ? 2 : 1;
+    const float* ub = a.u + ((long long)b * a.N_max + n0) * tv.K * KK;
+
+    float2 x[TB][TB];
+#pragma unroll
+    for (int r = 0; r < TB; ++r)
+#pragma unroll
+        for (int c = 0; c < TB; ++c) {
+            const int row = ti + NT * r, col = tj + NT * c;
+            if (valid && a.X0 && !a.compose)
+                x[r][c] = a.X0[(long long)b * D * D + row * D + col];
+            else
+                x[r][c] = make_float2(row == col ? 1.f : 0.f, 0.f);
+        }
+
+    double obs_norm = 1.0;
+    if (a.obs_out) {
+        // Tr(M M) = sum of |M_ab|^2 over the row lists (M Hermitian)
+        double s = 0.0;
+        for (int e = lt; e < D * a.obs_width; e += TPI) {
+            const float2 v = a.obs_vals[e];
+            s += (double)v.x * v.x + (double)v.y * v.y;
+        }
+        obs_norm = inst_sum<D>(s, red);
+    }
+    for (int n = 0; n < N; ++n) {
+        const bool active = valid && n < len;
+        step_left<D>(tv, x, Xs, Fs, ub + (long long)n * tv.K * KK, drift, active, lt == 0, lt, ti, tj);
+        if (a.reproject_every > 0 && !a.compose && ((a.step_offset + n + 1) % a.reproject_every) == 0)
+            reproject<D>(x, Xs, Fs, active, ti, tj);
+        if (a.X_prefix && active) {
+            float2* dst = a.X_prefix + ((long long)b * a.N_max + n) * D * D;
+#pragma unroll
+            for (int r = 0; r < TB; ++r)
+#pragma unroll
+                for (int c = 0; c < TB; ++c) dst[(ti + NT * r) * D + tj + NT * c] = x[r][c];
+        }
+        if (a.obs_out) {
+            // m_n = sum_ab (X M)_ab conj((M X)_ab) / Tr(M M)
+            __syncthreads();
+            if (active) store_block<D>(Xs, x, ti, tj);
+            __syncthreads();
+            double acc = 0.0;
+            if (active) {
+#pragma unroll
+                for (int r = 0; r < TB; ++r)
+#pragma unroll
+                    for (int c = 0; c < TB; ++c) {
+                        const int ra = ti + NT * r, cb = tj + NT * c;
+                        float2 xm = make_float2(0.f, 0.f), mx = make_float2(0.f, 0.f);
+                        for (int t = 0; t < a.obs_width; ++t) {
+                            const int colb = a.obs_cols[cb * a.obs_width + t];
+                            cfma(xm, Xs[ra * D + colb], cconj(a.obs_vals[cb * a.obs_width + t]));
+                            const int cola = a.obs_cols[ra * a.obs_width + t];
+                            cfma(mx, a.obs_vals[ra * a.obs_width + t], Xs[cola * D + cb]);
+                        }
+                        acc += (double)xm.x * mx.x + (double)xm.y * mx.y;
+                    }
+            }
+            acc = inst_sum<D>(acc, red);
+            if (active && lt == 0) a.obs_out[(long long)b * a.N_max + n] = acc / obs_norm;
+        }
+    }
+    if (valid) {
+        float2* dst = a.X_out + (long long)inst * D * D;
+#pragma unroll
+        for (int r = 0; r < TB; ++r)
+#pragma unroll
+            for (int c = 0; c < TB; ++c) dst[(ti + NT * r) * D + tj + NT * c] = x[r][c];
+    }
+}
+
+// ---------------------------------------------------------------- GRAPE kernel
+// Per instance: forward chain with checkpoints, overlap g, then for every
+// checkpoint segment from the last: recompute its states, and walk it
+// backwards with L_N = U_f^dag, Y_n = X_n L_n, L_{n-1} = L_n U_n.
+template <int D>
+__device__ inline void load_block(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], const float2* src, int ti, int tj) {
+    constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
+#pragma unroll
+    for (int r = 0; r < TB; ++r)
+#pragma unroll
+        for (int c = 0; c < TB; ++c) x[r][c] = src[(ti + NT * r) * D + tj + NT * c];
+}
+template <int D>
+__device__ inline void save_block(const float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* dst, int ti, int tj) {
+    constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
+#pragma unroll
+    for (int r = 0; r < TB; ++r)
+#pragma unroll
+        for (int c = 0; c < TB; ++c) dst[(ti + NT * r) * D + tj + NT * c] = x[r][c];
+}
+
+struct Pending {
+    double tr[KMAX], ti_[KMAX];   // Tr(S^psi Y) (real, imag)
+    double ur[KMAX], ui[KMAX];    // second trace at the origin (phased, q = 0)
+    double dr[KMAX], di[KMAX];    // D = Tr(G Y) of the later state
+};
+
+template <int D>
+__global__ __launch_bounds__(256) void small_grape_kernel(TView tv, SmallGrapeArgs a) {
+    constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT, TPI = Cfg<D>::TPI, IPB = Cfg<D>::IPB;
+    extern __shared__ float2 lds[];
+    __shared__ double red[4];
+    __shared__ int nblk;
+    const int tid = threadIdx.x, slot = tid / TPI, lt = tid % TPI;
+    const int ti = lt / NT, tj = lt % NT;
+    const int b = blockIdx.x * IPB + slot;
+    const bool valid = b < a.B;
+    float2* Xs = lds + (long long)slot * 3 * D * D;
+    float2* Fs = Xs + D * D;
+    float2* Ls = Fs + D * D;
+    const int len = valid ? (a.n_steps ? a.n_steps[b] : a.N_max) : 0;
+    if (tid == 0) nblk = 0;
+    __syncthreads();
+    if (lt == 0 && len > 0) atomicMax(&nblk, len);
+    __syncthreads();
+    const int N = nblk;
+    const int C = a.checkpoint_every;
+    const int drift = valid ? b % tv.n_drift : 0;
+    const int KK = tv.phased ? 2 : 1;
+    const long long ustride = (long long)tv.K * KK;
+    const float* ub = a.u + (long long)b * a.N_max * ustride;
+    float2* ck = a.ckpt + (long long)b * a.n_ckpt * D * D;
+    float2* sg = a.seg + (long long)b * C * D * D;
+
+    // ---- forward with checkpoints X_0, X_C, X_2C, ...
+    float2 x[TB][TB];
+#pragma unroll
+    for (int r = 0; r < TB; ++r)
+#pragma unroll
+        for (int c = 0; c < TB; ++c) x[r][c] = make_float2((ti + NT * r) == (tj + NT * c) ? 1.f : 0.f, 0.f);
+    for (int n = 0; n < N; ++n) {
+        const bool active = valid && n < len;
+        if (active && n % C == 0) save_block<D>(x, ck + (long long)(n / C) * D * D, ti, tj);
+        step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, lt == 0, lt, ti, tj);
+    }
+    // ---- overlap g = Tr(U_f^dag X_N) / Tr(U_f^dag U_f)
+    const float2* Uf = a.U_target + (long long)(valid ? b : 0) * D * D;
+    double gr = 0.0, gi = 0.0, nu = 0.0;
+    if (valid) {
+#pragma unroll
+        for (int r = 0; r < TB; ++r)
+#pragma unroll
+            for (int c = 0; c < TB; ++c) {
+                const float2 f = Uf[(ti + NT * r) * D + tj + NT * c];
+                gr += (double)f.x * x[r][c].x + (double)f.y * x[r][c].y;
+                gi += (double)f.x * x[r][c].y - (double)f.y * x[r][c].x;
+                nu += (double)f.x * f.x + (double)f.y * f.y;
+            }
+    }
+    gr = inst_sum<D>(gr, red);
+    gi = inst_sum<D>(gi, red);
+    nu = inst_sum<D>(nu, red);
+    gr /= nu;
+    gi /= nu;
+    if (valid && lt == 0) {
+        a.fidelity[b] = gr * gr + gi * gi;
+        if (a.overlap) a.overlap[b] = make_double2(gr, gi);
+    }
+    // ---- backward: L_N = U_f^dag
+    float2 l[TB][TB];
+#pragma unroll
+    for (int r = 0; r < TB; ++r)
+#pragma unroll
+        for (int c = 0; c < TB; ++c) l[r][c] = cconj(Uf[(tj + NT * c) * D + ti + NT * r]);
+    Pending pend;
+    bool has_pend = false;
+    int pend_step = -1;
+    const double scale = 2.0 / nu;   // dF = 2 Re(conj(g) dg) with the 1/nu of g folded in
+    float* gb = a.grad + (long long)b * a.N_max * ustride;
+    // zero the gradient of steps past this instance's length
+    if (valid)
+        for (long long e = (long long)len * ustride + lt; e < (long long)a.N_max * ustride; e += TPI) gb[e] = 0.f;
+
+    auto finalize = [&](int s, const double* Dr, const double* Di) {
+        // gradient of step s from pend (its traces) and D of the earlier state
+        const float* us = ub + (long long)s * ustride;
+        for (int k = 0; k < tv.K; ++k) {
+            double phi;
+            const int q = quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, &phi, nullptr);
+            // Im(conj(g) * z)
+            auto im_gc = [&](double zr, double zi) { return gr * zi - gi * zr; };
+            if (!tv.phased) {
+                gb[(long long)s * ustride + k] = (float)(scale * tv.dt * im_gc(pend.tr[k], pend.ti_[k]));
+            } else if (q == 0) {
+                gb[(long long)s * ustride + 2 * k] = (float)(scale * tv.dt * im_gc(pend.tr[k], pend.ti_[k]));
+                gb[(long long)s * ustride + 2 * k + 1] = (float)(scale * tv.dt * im_gc(pend.ur[k], pend.ui[k]));
+            } else {
+                const double om = (double)q * tv.eps;
+                const double dFo = scale * tv.dt * im_gc(pend.tr[k], pend.ti_[k]);
+                const double dFp = scale * im_gc(pend.dr[k] - Dr[k], pend.di[k] - Di[k]);
+                const double cp = cos(phi), sp = sin(phi);
+                gb[(long long)s * ustride + 2 * k] = (float)(cp * dFo - sp * dFp / om);
+                gb[(long long)s * ustride + 2 * k + 1] = (float)(sp * dFo + cp * dFp / om);
+            }
+        }
+    };
+
+    double Dr[KMAX], Di[KMAX];
+    const int nseg = (N + C - 1) / C;
+    for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+        const int s0 = sgi * C, s1 = min(N, s0 + C);
+        // recompute X_{s0+1} .. X_{s1} into the segment buffer
+        const bool seg_active = valid && s0 < len;
+        if (seg_active) load_block<D>(x, ck + (long long)sgi * D * D, ti, tj);
+        for (int n = s0; n < s1; ++n) {
+            const bool active = valid && n < len;
+            step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, false, lt, ti, tj);
+            if (active) save_block<D>(x, sg + (long long)(n - s0) * D * D, ti, tj);
+        }
+        for (int s = s1 - 1; s >= s0; --s) {
+            const bool active = valid && s < len;
+            // Y_{s+1} = X_{s+1} L_{s+1}
+            __syncthreads();
+            if (active) {
+                float2 xs[TB][TB];
+                load_block<D>(xs, sg + (long long)(s - s0) * D * D, ti, tj);
+                store_block<D>(Xs, xs, ti, tj);
+                store_block<D>(Ls, l, ti, tj);
+            }
+            __syncthreads();
+            float2 y[TB][TB];
+            if (active) mul_left<D>(y, Xs, Ls, ti, tj);
+            // traces per channel
+            const float* us = ub + (long long)s * ustride;
+            double st_tr[KMAX], st_ti[KMAX], st_ur[KMAX], st_ui[KMAX];
+            for (int k = 0; k < tv.K; ++k) {
+                double phi = 0.0;
+                const int q = active ? quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, &phi, nullptr) : 0;
+                const bool origin = tv.phased && q == 0;
+                const double psi = tv.phased ? (origin ? 0.0 : phi) : 0.0;
+                double tr = 0.0, tim = 0.0, ur = 0.0, ui = 0.0, dr = 0.0, di = 0.0;
+                if (active) {
+                    const double* gk = tv.phased ? tv.g + (long long)k * D : nullptr;
+                    const float2* Sk = tv.S + (long long)k * D * D;
+#pragma unroll
+                    for (int r = 0; r < TB; ++r)
+#pragma unroll
+                        for (int c = 0; c < TB; ++c) {
+                            // y[r][c] = Y[bb][aa], contributes S^psi[aa][bb] Y[bb][aa]
+                            const int bb = ti + NT * r, aa = tj + NT * c;
+                            const float2 sv = Sk[aa * D + bb];
+                            const double yr = y[r][c].x, yi = y[r][c].y;
+                            double pr = 1.0, pim = 0.0;
+                            if (gk && psi != 0.0) {
+                                const double2 e = expmi(psi * (gk[aa] - gk[bb]));
+                                pr = e.x;
+                                pim = e.y;
+                            }
+                            const double s_r = pr * sv.x - pim * sv.y, s_i = pr * sv.y + pim * sv.x;
+                            tr += s_r * yr - s_i * yi;
+                            tim += s_r * yi + s_i * yr;
+                            if (origin) {
+                                // psi = pi/2: exp(-i pi/2 (g_a - g_b))
+                                const double2 e = expmi(1.5707963267948966 * (gk[aa] - gk[bb]));
+                                const double t_r = e.x * sv.x - e.y * sv.y, t_i = e.x * sv.y + e.y * sv.x;
+                                ur += t_r * yr - t_i * yi;
+                                ui += t_r * yi + t_i * yr;
+                            }
+                            if (gk && aa == bb) {
+                                dr += gk[aa] * yr;
+                                di += gk[aa] * yi;
+                            }
+                        }
+                }
+                tr = inst_sum<D>(tr, red);
+                tim = inst_sum<D>(tim, red);
+                if (tv.phased) {
+                    ur = inst_sum<D>(ur, red);
+                    ui = inst_sum<D>(ui, red);
+                    dr = inst_sum<D>(dr, red);
+                    di = inst_sum<D>(di, red);
+                }
+                Dr[k] = dr;
+                Di[k] = di;
+                st_tr[k] = tr;
+                st_ti[k] = tim;
+                st_ur[k] = ur;
+                st_ui[k] = ui;
+            }
+            if (active && lt == 0 && has_pend) finalize(pend_step, Dr, Di);
+            if (active) {
+                for (int k = 0; k < tv.K; ++k) {
+                    pend.tr[k] = st_tr[k];
+                    pend.ti_[k] = st_ti[k];
+                    pend.ur[k] = st_ur[k];
+                    pend.ui[k] = st_ui[k];
+                    pend.dr[k] = Dr[k];
+                    pend.di[k] = Di[k];
+                }
+                has_pend = true;
+                pend_step = s;
+            }
+            // L_s = L_{s+1} U_s
+            step_right<D>(tv, l, Ls, Fs, us, drift, active, lt, ti, tj);
+        }
+    }
+    // D_0 = Tr(G Y_0), Y_0 = X_0 L_0 = L_0
+    for (int k = 0; k < tv.K; ++k) {
+        double dr = 0.0, di = 0.0;
+        if (valid && tv.phased) {
+            const double* gk = tv.g + (long long)k * D;
+#pragma unroll
+            for (int r = 0; r < TB; ++r)
+#pragma unroll
+                for (int c = 0; c < TB; ++c)
+                    if (ti + NT * r == tj + NT * c) {
+                        dr += gk[ti + NT * r] * l[r][c].x;
+                        di += gk[ti + NT * r] * l[r][c].y;
+                    }
+        }
+        if (tv.phased) {
+            dr = inst_sum<D>(dr, red);
+            di = inst_sum<D>(di, red);
+        }
+        Dr[k] = dr;
+        Di[k] = di;
+    }
+    if (valid && lt == 0 && has_pend) finalize(pend_step, Dr, Di);
+}
+
+template <int D>
+hipError_t launch_chain(const TView& tv, const SmallChainArgs& a, int ninst, hipStream_t st) {
+    constexpr int IPB = Cfg<D>::IPB;
+    const size_t lds = (size_t)IPB * 2 * D * D * sizeof(float2);
+    hipError_t e = hipFuncSetAttribute((const void*)small_chain_kernel<D>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int grid = (ninst + IPB - 1) / IPB;
+    hipLaunchKernelGGL(small_chain_kernel<D>, dim3(grid), dim3(256), lds, st, tv, a, ninst);
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_grape(const TView& tv, const SmallGrapeArgs& a, hipStream_t st) {
+    constexpr int IPB = Cfg<D>::IPB;
+    const size_t lds = (size_t)IPB * 3 * D * D * sizeof(float2);
+    hipError_t e = hipFuncSetAttribute((const void*)small_grape_kernel<D>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int grid = (a.B + IPB - 1) / IPB;
+    hipLaunchKernelGGL(small_grape_kernel<D>, dim3(grid), dim3(256), lds, st, tv, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t small_chain(const redo_table_s* t, const SmallChainArgs& a, hipStream_t st) {
+    const TView tv = view_of(t);
+    const int ninst = a.compose ? a.B * a.N_max : a.B;
+    switch (tv.d) {
+        case 2: return launch_chain<2>(tv, a, ninst, st);
+        case 4: return launch_chain<4>(tv, a, ninst, st);
+        case 8: return launch_chain<8>(tv, a, ninst, st);
+        case 16: return launch_chain<16>(tv, a, ninst, st);
+        case 32: return launch_chain<32>(tv, a, ninst, st);
+        case 64: return launch_chain<64>(tv, a, ninst, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t small_grape(const redo_table_s* t, const SmallGrapeArgs& a, hipStream_t st) {
+    const TView tv = view_of(t);
+    switch (tv.d) {
+        case 2: return launch_grape<2>(tv, a, st);
+        case 4: return launch_grape<4>(tv, a, st);
+        case 8: return launch_grape<8>(tv, a, st);
+        case 16: return launch_grape<16>(tv, a, st);
+        case 32: return launch_grape<32>(tv, a, st);
+        case 64: return launch_grape<64>(tv, a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace redo

@@ -1,0 +1,172 @@
+// Process 1 of REDO (Sec. II, Eq. redoform): the one-time FP64 build of the
+// discrete-operator table and of the drift propagators.  The table is built
+// outside every iteration loop (Sec. III), so these kernels favour plain,
+// bounds-checked code over speed: an LDS-tiled FP64 complex GEMM, identity
+// fills and the single rounding of each FP64 entry to FP32 storage.
+#include "redo_internal.h"
+
+namespace redo {
+namespace {
+
+constexpr int ZT = 64;   // output tile edge
+constexpr int ZK = 16;   // k-slice
+
+// C[b] = alpha * A[b] B[b] + beta * I for n x n row-major c128 matrices.
+// 256 threads, each owns a 4x4 strided sub-block (rows ty + 16 r, cols tx + 16 c).
+__global__ __launch_bounds__(256) void zgemm_kernel(int n, const double2* __restrict__ A, long long sA,
+                                                     const double2* __restrict__ B, long long sB,
+                                                     double2* __restrict__ C, long long sC, double2 alpha,
+                                                     double beta) {
+    __shared__ double2 As[ZK][ZT + 1];
+    __shared__ double2 Bs[ZK][ZT + 1];
+    const int bz = blockIdx.z;
+    A += sA * bz;
+    B += sB * bz;
+    C += sC * bz;
+    const int i0 = blockIdx.y * ZT, j0 = blockIdx.x * ZT;
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    double2 acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = make_double2(0.0, 0.0);
+    for (int k0 = 0; k0 < n; k0 += ZK) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int e = tid + 256 * m;
+            const int ai = e / ZK, ak = e % ZK;
+            const int gi = i0 + ai, gk = k0 + ak;
+            As[ak][ai] = (gi < n && gk < n) ? A[(long long)gi * n + gk] : make_double2(0.0, 0.0);
+            const int bk = e / ZT, bj = e % ZT;
+            const int hk = k0 + bk, hj = j0 + bj;
+            Bs[bk][bj] = (hk < n && hj < n) ? B[(long long)hk * n + hj] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < ZK; ++k) {
+            double2 a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = As[k][ty + 16 * r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = Bs[k][tx + 16 * c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    acc[r][c].x = fma(a[r].x, b[c].x, acc[r][c].x);
+                    acc[r][c].x = fma(-a[r].y, b[c].y, acc[r][c].x);
+                    acc[r][c].y = fma(a[r].x, b[c].y, acc[r][c].y);
+                    acc[r][c].y = fma(a[r].y, b[c].x, acc[r][c].y);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = i0 + ty + 16 * r, j = j0 + tx + 16 * c;
+            if (i < n && j < n) {
+                double2 v = zmul(alpha, acc[r][c]);
+                if (i == j) v.x += beta;
+                C[(long long)i * n + j] = v;
+            }
+        }
+}
+
+__global__ void fill_identity_kernel(int n, double2* C, long long sC, long long total) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const long long nn = (long long)n * n;
+    const long long b = e / nn, r = e % nn;
+    const int i = (int)(r / n), j = (int)(r % n);
+    C[b * sC + r] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+}
+
+// dst + b * dst_batch_stride <- (float) src[b]   (round to nearest even, once)
+__global__ void round_entries_kernel(long long nn, int batch, const double2* __restrict__ src,
+                                     float2* __restrict__ dst, long long dst_batch_stride) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nn * batch) return;
+    const long long b = e / nn, r = e % nn;
+    const double2 v = src[e];
+    dst[b * dst_batch_stride + r] = make_float2((float)v.x, (float)v.y);
+}
+
+__global__ void round_z_kernel(long long count, const double2* __restrict__ src, float2* __restrict__ dst) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) dst[e] = make_float2((float)src[e].x, (float)src[e].y);
+}
+
+// V[r][a] = exp(-i dt h[r][a]) evaluated in FP64, rounded once
+__global__ void drift_diag_kernel(long long count, const double* __restrict__ h, double dt, float2* __restrict__ V) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    const double2 v = expmi(dt * h[e]);
+    V[e] = make_float2((float)v.x, (float)v.y);
+}
+
+// round-to-nearest-even float -> bf16 bits
+__device__ inline uint16_t bf16_rne(float x) {
+    unsigned u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float(((unsigned)h) << 16); }
+
+// hi = RNE(x), lo = RNE(x - hi), per real component
+__global__ void split_bf16_kernel(long long count, const float* __restrict__ src, uint16_t* __restrict__ hi,
+                                  uint16_t* __restrict__ lo) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    const float x = src[e];
+    const uint16_t h = bf16_rne(x);
+    hi[e] = h;
+    lo[e] = bf16_rne(x - bf16_to_f(h));
+}
+
+inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t zgemm_batched(int n, int batch, const double2* A, long long sA, const double2* B, long long sB,
+                         double2* C, long long sC, double2 alpha, double beta, hipStream_t st) {
+    dim3 grid((n + ZT - 1) / ZT, (n + ZT - 1) / ZT, batch);
+    hipLaunchKernelGGL(zgemm_kernel, grid, dim3(256), 0, st, n, A, sA, B, sB, C, sC, alpha, beta);
+    return hipGetLastError();
+}
+
+hipError_t fill_identity_z(int n, int batch, double2* C, long long sC, hipStream_t st) {
+    const long long total = (long long)n * n * batch;
+    hipLaunchKernelGGL(fill_identity_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, st, n, C, sC, total);
+    return hipGetLastError();
+}
+
+hipError_t round_table_entries(int n, int batch, const double2* src, float2* dst, long long dst_batch_stride,
+                               hipStream_t st) {
+    const long long nn = (long long)n * n;
+    hipLaunchKernelGGL(round_entries_kernel, dim3(blocks_for(nn * batch, 256)), dim3(256), 0, st, nn, batch, src,
+                       dst, dst_batch_stride);
+    return hipGetLastError();
+}
+
+hipError_t round_z_to_c(long long count, const double2* src, float2* dst, hipStream_t st) {
+    hipLaunchKernelGGL(round_z_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, st, count, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t drift_diag_phases(int d, int n_drift, const double* h, double dt, float2* V, hipStream_t st) {
+    const long long count = (long long)d * n_drift;
+    hipLaunchKernelGGL(drift_diag_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, st, count, h, dt, V);
+    return hipGetLastError();
+}
+
+hipError_t split_bf16(long long count, const float2* src, uint16_t* hi, uint16_t* lo, hipStream_t st) {
+    const long long reals = 2 * count;
+    hipLaunchKernelGGL(split_bf16_kernel, dim3(blocks_for(reals, 256)), dim3(256), 0, st, reals,
+                       reinterpret_cast<const float*>(src), hi, lo);
+    return hipGetLastError();
+}
+
+}  // namespace redo

@@ -1,0 +1,253 @@
+"""Python binding of libredo.so (argument marshalling only).
+
+Every step of the REDO path runs in the HIP library; this module only moves
+torch device tensors across the C ABI of include/redo.h, on torch's current
+HIP stream.  If the library is missing the import fails: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libredo.so")
+
+PREC_F32, PREC_F32_3M, PREC_BF16X3 = 0, 1, 2
+OP_COMPOSE, OP_CHAIN, OP_GRAPE, OP_EXPM_CHAIN, OP_EXPM_GRAPE = 0, 1, 2, 3, 4
+STATUS = {0: "REDO_OK", 1: "REDO_ERR_ARG", 2: "REDO_ERR_ALLOC", 3: "REDO_ERR_HIP", 4: "REDO_ERR_NOT_HERMITIAN",
+          5: "REDO_ERR_NONFINITE", 6: "REDO_ERR_UNSUPPORTED", 7: "REDO_ERR_WORKSPACE", 100: "REDO_WARN_CLAMPED"}
+
+# name -> (restype, argtypes); mirrors include/redo.h
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_SIG = {
+    "redo_build_table": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
+    "redo_table_destroy": (_I, [_P]),
+    "redo_table_query": (_I, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
+    "redo_workspace_bytes": (ctypes.c_size_t, [_P, _I, _I, _I]),
+    "redo_quantise": (_I, [_P, _P, _I, _I, _P, _P, _P]),
+    "redo_compose_steps": (_I, [_P, _I, _P, _I, _I, _P, _P, ctypes.c_size_t, _P]),
+    "redo_chain_propagator": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _P, _I, _P, _P,
+                                   ctypes.c_size_t, _P]),
+    "redo_unitary_fidelity": (_I, [_I, _I, _P, _P, _P, _P, _P]),
+    "redo_grape_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _I, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "redo_get_device_status": (_I, [_P, _P, ctypes.POINTER(ctypes.c_int64)]),
+    "redo_status_string": (ctypes.c_char_p, [_I]),
+    "redo_last_error": (ctypes.c_char_p, []),
+}
+
+
+def exported_symbols():
+    return list(_SIG)
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("d", _I), ("K", _I), ("base", _I), ("digits", _I), ("dt", ctypes.c_double),
+                ("eps", ctypes.c_double), ("phased", _I), ("drift_is_diag", _I), ("n_drift", _I),
+                ("reserved", _I)]
+
+
+def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1707_02162_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIG.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+class RedoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status: int, allow_warn: bool = False) -> int:
+    if status == 0 or (allow_warn and status == 100):
+        return status
+    raise RedoError(status, lib().redo_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(x, dtype, device) -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device=device, dtype=dtype).contiguous()
+
+
+class RedoTable:
+    """A built table of discrete operators (process 1) plus drift propagators."""
+
+    def __init__(self, d: int, K: int, base: int, digits: int, dt: float, eps: float, phased: bool,
+                 H0, S, g=None, drift_is_diag: bool = True, device: str = "cuda"):
+        self.device = torch.device(device)
+        self.d, self.K, self.base, self.digits = d, K, base, digits
+        self.dt, self.eps, self.phased = float(dt), float(eps), bool(phased)
+        H0t = _dev(H0, torch.float64 if drift_is_diag else torch.complex128, self.device)
+        if H0t.dim() == (1 if drift_is_diag else 2):
+            H0t = H0t.unsqueeze(0)
+        St = _dev(S, torch.complex128, self.device)
+        gt = _dev(g, torch.float64, self.device) if phased else None
+        self.n_drift = H0t.shape[0]
+        desc = _Desc(d, K, base, digits, self.dt, self.eps, int(phased), int(drift_is_diag), self.n_drift, 0)
+        h = ctypes.c_void_p()
+        _check(lib().redo_build_table(ctypes.byref(desc), _ptr(H0t), _ptr(St), _ptr(gt), _stream(),
+                                      ctypes.byref(h)))
+        self._h = h
+        self.kk = 2 if phased else 1
+
+    @classmethod
+    def from_problem(cls, p, device: str = "cuda") -> "RedoTable":
+        return cls(p.d, p.K, p.base, p.digits, p.dt, p.eps, p.phased, p.H0, p.S,
+                   p.g if p.phased else None, p.drift_is_diag, device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().redo_table_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def device_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().redo_table_query(self._h, None, ctypes.byref(n)))
+        return n.value
+
+    def workspace(self, op: int, B: int, N: int) -> torch.Tensor:
+        nbytes = lib().redo_workspace_bytes(self._h, op, B, N)
+        return torch.empty(max(int(nbytes), 16), dtype=torch.uint8, device=self.device)
+
+    def _u(self, u) -> torch.Tensor:
+        t = _dev(u, torch.float32, self.device)
+        want = 4 if self.phased else 3
+        if t.dim() != want or t.shape[2] != self.K or (self.phased and t.shape[3] != 2):
+            raise ValueError(f"u must be [B, N, {self.K}" + (", 2]" if self.phased else "]"))
+        return t
+
+    def quantise(self, u):
+        ut = self._u(u)
+        B, N = ut.shape[:2]
+        codes = torch.empty((B, N, self.K), dtype=torch.int32, device=self.device)
+        phi = torch.empty((B, N, self.K), dtype=torch.float64, device=self.device) if self.phased else None
+        _check(lib().redo_quantise(self._h, _ptr(ut), B, N, _ptr(codes), _ptr(phi), _stream()))
+        return codes, phi
+
+    def compose(self, u, precision: int = PREC_F32) -> torch.Tensor:
+        ut = self._u(u)
+        B, N = ut.shape[:2]
+        out = torch.empty((B, N, self.d, self.d), dtype=torch.complex64, device=self.device)
+        ws = self.workspace(OP_COMPOSE, B, N)
+        _check(lib().redo_compose_steps(self._h, precision, _ptr(ut), B, N, _ptr(out), _ptr(ws), ws.numel(),
+                                        _stream()))
+        return out
+
+    def chain(self, u, n_steps=None, precision: int = PREC_F32, X0=None, reproject_every: int = 0,
+              step_offset: int = 0, prefix: bool = False, observable=None, out: Optional[torch.Tensor] = None):
+        """Chain of REDO steps.  observable: (cols int32 [d, w], vals complex [d, w]) row lists.
+        Returns (U_total, X_prefix or None, obs or None)."""
+        ut = self._u(u)
+        B, N = ut.shape[:2]
+        ns = None if n_steps is None else _dev(n_steps, torch.int32, self.device)
+        X0t = None if X0 is None else _dev(X0, torch.complex64, self.device)
+        U = out if out is not None else torch.empty((B, self.d, self.d), dtype=torch.complex64, device=self.device)
+        Xp = torch.empty((B, N, self.d, self.d), dtype=torch.complex64, device=self.device) if prefix else None
+        cols = vals = obs = None
+        w = 0
+        if observable is not None:
+            cols = _dev(observable[0], torch.int32, self.device)
+            vals = _dev(observable[1], torch.complex64, self.device)
+            w = cols.shape[1]
+            obs = torch.empty((B, N), dtype=torch.float64, device=self.device)
+        ws = self.workspace(OP_CHAIN, B, N)
+        _check(lib().redo_chain_propagator(self._h, precision, _ptr(ut), _ptr(ns), B, N, step_offset,
+                                           reproject_every, _ptr(X0t), _ptr(U), _ptr(Xp), _ptr(cols), _ptr(vals),
+                                           w, _ptr(obs), _ptr(ws), ws.numel(), _stream()))
+        return U, Xp, obs
+
+    def grape(self, u, U_target, n_steps=None, checkpoint_every: int = 0, precision: int = PREC_F32):
+        """Returns (fidelity float64 [B], overlap complex128 [B], grad float32 like u)."""
+        ut = self._u(u)
+        B, N = ut.shape[:2]
+        ns = None if n_steps is None else _dev(n_steps, torch.int32, self.device)
+        Uf = _dev(U_target, torch.complex64, self.device)
+        F = torch.empty(B, dtype=torch.float64, device=self.device)
+        ov = torch.empty(B, dtype=torch.complex128, device=self.device)
+        grad = torch.empty_like(ut)
+        nbytes = lib().redo_workspace_bytes(self._h, OP_GRAPE, B, N)
+        if checkpoint_every > 0 and self.d <= 64:
+            nck = -(-N // checkpoint_every)
+            nbytes = 8 * self.d * self.d * B * (nck + checkpoint_every)
+        ws = torch.empty(max(int(nbytes), 16), dtype=torch.uint8, device=self.device)
+        _check(lib().redo_grape_fidelity_grad(self._h, precision, _ptr(ut), _ptr(ns), B, N, _ptr(Uf),
+                                              checkpoint_every, _ptr(F), _ptr(ov), _ptr(grad), _ptr(ws),
+                                              ws.numel(), _stream()))
+        return F, ov, grad
+
+    def device_status(self):
+        n = ctypes.c_int64()
+        st = lib().redo_get_device_status(self._h, _stream(), ctypes.byref(n))
+        return st, n.value
+
+
+def unitary_fidelity(U_target: torch.Tensor, U: torch.Tensor):
+    """(overlap complex128 [B], fidelity float64 [B]) of batched d x d unitaries."""
+    B, d = U.shape[0], U.shape[-1]
+    Uf = _dev(U_target, torch.complex64, U.device)
+    Ut = _dev(U, torch.complex64, U.device)
+    ov = torch.empty(B, dtype=torch.complex128, device=U.device)
+    F = torch.empty(B, dtype=torch.float64, device=U.device)
+    _check(lib().redo_unitary_fidelity(d, B, _ptr(Uf), _ptr(Ut), _ptr(ov), _ptr(F), _stream()))
+    return ov, F
+
+
+class GrapeFidelity(torch.autograd.Function):
+    """F = |Tr(U_f^dag U(u)) / Tr(U_f^dag U_f)|^2 of the REDO chain, with the
+    gradient from the library's adjoint kernel (straight-through at the
+    quantised amplitudes)."""
+
+    @staticmethod
+    def forward(ctx, u, table: RedoTable, U_target, n_steps=None, checkpoint_every: int = 0,
+                precision: int = PREC_F32):
+        F, _, grad = table.grape(u.detach(), U_target, n_steps, checkpoint_every, precision)
+        ctx.save_for_backward(grad)
+        return F
+
+    @staticmethod
+    def backward(ctx, gF):
+        (grad,) = ctx.saved_tensors
+        shape = (-1,) + (1,) * (grad.dim() - 1)
+        return (gF.to(grad.dtype).reshape(shape) * grad, None, None, None, None, None)
