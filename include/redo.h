@@ -111,12 +111,31 @@ redo_status redo_build_table(const redo_table_desc* desc, const double* H0, cons
 /* Frees the table and everything it owns.  NULL is accepted.  Synchronises the device. */
 redo_status redo_table_destroy(redo_table table);
 
+/*
+ * Process 3 of Sec. II: a repeated coarse-grained value is evaluated once.
+ * Composes, for every channel k and every level q_lo <= q <= q_hi, the REDO
+ * factor R_k(q) = T_k[0][c_0] T_k[1][c_1] ... in FP64 (from the FP64 digit
+ * operators, rebuilt as in redo_build_table) and keeps it, rounded once to
+ * FP32, in the table (K*(q_hi-q_lo+1)*d*d*8 bytes of device memory).  Later
+ * calls on the large-d path (d >= 128) apply one product per channel and step
+ * for every amplitude whose level is cached, instead of one per non-zero
+ * digit; results then agree with the uncached path to FP32 rounding.  Replaces
+ * any earlier cache; q_hi < 0 only frees it.  Synchronises `stream`.  Must not
+ * overlap other calls on the same table.  Errors: REDO_ERR_ARG, REDO_ERR_ALLOC.
+ */
+redo_status redo_cache_levels(redo_table table, int32_t q_lo, int32_t q_hi, void* stream);
+
 /* Host copy of the descriptor and the table's device footprint in bytes. */
 redo_status redo_table_query(redo_table table, redo_table_desc* desc, size_t* device_bytes);
 
 /* Bytes of workspace that `op` needs for B instances of up to N_max steps
- * (0 on invalid arguments).  Workspace is caller-owned device memory. */
+ * (0 on invalid arguments).  Workspace is caller-owned device memory.  For
+ * REDO_OP_GRAPE this assumes the default checkpoint interval ceil(sqrt(N_max)). */
 size_t redo_workspace_bytes(redo_table table, int32_t op, int32_t B, int32_t N_max);
+
+/* Workspace of redo_grape_fidelity_grad for an explicit checkpoint interval
+ * (0 = ceil(sqrt(N_max))). */
+size_t redo_grape_workspace_bytes(redo_table table, int32_t B, int32_t N_max, int32_t checkpoint_every);
 
 /*
  * Coarse graining alone (Sec. II, Eq. cgrain): for every (b, n, k) with
@@ -205,6 +224,16 @@ redo_status redo_grape_fidelity_grad(redo_table table, int32_t precision, const 
  * *n_clamped (host, nullable) receives the number of clamped amplitudes.
  */
 redo_status redo_get_device_status(redo_table table, void* stream, int64_t* n_clamped);
+
+/*
+ * Launch timing (diagnostics, not part of the method).  While enabled, every
+ * batched complex-GEMM launch of the large-d path is bracketed by HIP events
+ * recorded on the stream it runs on.  redo_profile_read waits for those
+ * events and returns the summed duration (ms) and the number of launches
+ * since the last reset.  Process-wide; may be called from any thread.
+ */
+redo_status redo_profile_enable(int32_t enable);
+redo_status redo_profile_read(double* gemm_ms, int64_t* gemm_launches, int32_t reset);
 
 const char* redo_status_string(redo_status status);
 const char* redo_last_error(void);

@@ -270,6 +270,9 @@ redo_status redo_build_table(const redo_table_desc* desc, const double* H0, cons
     } guard{t.get()};
     REDO_HIP(alloc((void**)&t->T32, sizeof(float2) * nn * (size_t)K * P * (b - 1)));
     REDO_HIP(alloc((void**)&t->S32, sizeof(float2) * nn * K));
+    REDO_HIP(alloc((void**)&t->S64, sizeof(double2) * nn * K));
+    REDO_HIP(hipMemcpyAsync(t->S64, S, sizeof(double2) * nn * K, hipMemcpyDeviceToDevice, hs));
+    t->s_norm = s_norm;
     REDO_HIP(alloc((void**)&t->flags, sizeof(DeviceFlags)));
     REDO_HIP(hipMemsetAsync(t->flags, 0, sizeof(DeviceFlags), hs));
     if (desc->drift_is_diag) {
@@ -329,10 +332,95 @@ redo_status redo_build_table(const redo_table_desc* desc, const double* H0, cons
 redo_status redo_table_destroy(redo_table t) {
     if (!t) return REDO_OK;
     (void)hipDeviceSynchronize();
-    void* bufs[] = {t->T32, t->h64, t->V32, t->g64, t->S32, t->flags, t->T16hi, t->T16lo, t->cache};
+    void* bufs[] = {t->T32, t->h64, t->V32, t->g64, t->S32, t->S64, t->flags, t->T16hi, t->T16lo, t->cache};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     delete t;
+    return REDO_OK;
+}
+
+redo_status redo_cache_levels(redo_table t, int32_t q_lo, int32_t q_hi, void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    REDO_HIP(hipStreamSynchronize(hs));
+    if (t->cache) {
+        REDO_HIP(hipFree(t->cache));
+        t->bytes -= sizeof(float2) * (size_t)t->entry_elems * t->desc.K * (size_t)(t->cache_hi - t->cache_lo + 1);
+        t->cache = nullptr;
+        t->cache_lo = 0;
+        t->cache_hi = -1;
+    }
+    if (q_hi < 0) return REDO_OK;  // clear only
+    if (q_lo < 0 || q_lo > q_hi || (double)q_hi > t->qmax) return fail(REDO_ERR_ARG, "need 0 <= q_lo <= q_hi <= b^P - 1");
+    const int d = t->desc.d, K = t->desc.K, P = t->desc.digits, b = t->desc.base;
+    const size_t nn = (size_t)d * d;
+    const long long L = (long long)q_hi - q_lo + 1;
+    void* cache = nullptr;
+    REDO_HIP(hipMalloc(&cache, sizeof(float2) * nn * K * (size_t)L));
+    struct Free {
+        void* p;
+        ~Free() {
+            if (p) (void)hipFree(p);
+        }
+    } guard{cache};
+    // FP64 digit tables T64[j][c] = E_j^c, c = 0 .. b-1, rebuilt exactly as in the table build
+    DevBuf T64, E, tmp, Rh, Rn, scratch;
+    REDO_HIP(dev_alloc(T64, sizeof(double2) * nn * P * b));
+    REDO_HIP(dev_alloc(E, sizeof(double2) * nn));
+    REDO_HIP(dev_alloc(tmp, sizeof(double2) * nn * b));
+    REDO_HIP(dev_alloc(Rh, sizeof(double2) * nn));
+    REDO_HIP(dev_alloc(Rn, sizeof(double2) * nn));
+    REDO_HIP(dev_alloc(scratch, sizeof(double2) * nn));
+    double2* T = T64.as<double2>();
+    for (int k = 0; k < K; ++k) {
+        for (int j = 0; j < P; ++j) {
+            const double theta = std::pow((double)b, j) * t->desc.eps * t->desc.dt;
+            redo_status st = expm_fp64(d, t->S64 + nn * k, theta, t->s_norm[k], E.as<double2>(), scratch.as<double2>(), hs);
+            if (st != REDO_OK) return st;
+            double2* Tj = T + nn * (size_t)j * b;
+            REDO_HIP(fill_identity_z(d, 1, Tj, 0, hs));
+            REDO_HIP(hipMemcpyAsync(Tj + nn, E.p, sizeof(double2) * nn, hipMemcpyDeviceToDevice, hs));
+            for (int c = 2; c < b; ++c)
+                REDO_HIP(zgemm_batched(d, 1, Tj + nn * (c - 1), 0, E.as<double2>(), 0, Tj + nn * c, 0,
+                                       make_double2(1.0, 0.0), 0.0, hs));
+        }
+        // R(q) = T[0][c_0] (T[1][c_1] T[2][c_2] ...), grouped by the high part h = q / b
+        for (long long h = q_lo / b; h <= q_hi / b; ++h) {
+            double2* R = nullptr;  // product of the digits j >= 1 (null = identity)
+            long long rest = h;
+            for (int j = 1; j < P; ++j) {
+                const int c = (int)(rest % b);
+                rest /= b;
+                if (c == 0) continue;
+                const double2* f = T + nn * ((size_t)j * b + c);
+                if (!R) {
+                    REDO_HIP(hipMemcpyAsync(Rh.p, f, sizeof(double2) * nn, hipMemcpyDeviceToDevice, hs));
+                    R = Rh.as<double2>();
+                } else {
+                    REDO_HIP(zgemm_batched(d, 1, R, 0, f, 0, Rn.as<double2>(), 0, make_double2(1.0, 0.0), 0.0, hs));
+                    REDO_HIP(hipMemcpyAsync(Rh.p, Rn.p, sizeof(double2) * nn, hipMemcpyDeviceToDevice, hs));
+                }
+            }
+            const long long c_lo = std::max<long long>(0, q_lo - h * b);
+            const long long c_hi = std::min<long long>(b - 1, q_hi - h * b);
+            const int cnt = (int)(c_hi - c_lo + 1);
+            float2* dst = static_cast<float2*>(cache) + nn * ((size_t)k * L + (size_t)(h * b + c_lo - q_lo));
+            if (R) {
+                REDO_HIP(zgemm_batched(d, cnt, T + nn * (size_t)c_lo, nn, R, 0, tmp.as<double2>(), nn,
+                                       make_double2(1.0, 0.0), 0.0, hs));
+                REDO_HIP(round_table_entries(d, cnt, tmp.as<double2>(), dst, nn, hs));
+            } else {
+                REDO_HIP(round_table_entries(d, cnt, T + nn * (size_t)c_lo, dst, nn, hs));
+            }
+        }
+    }
+    REDO_HIP(hipStreamSynchronize(hs));
+    guard.p = nullptr;
+    t->cache = static_cast<float2*>(cache);
+    t->cache_lo = q_lo;
+    t->cache_hi = q_hi;
+    t->bytes += sizeof(float2) * nn * K * (size_t)L;
     return REDO_OK;
 }
 
@@ -360,6 +448,17 @@ size_t redo_workspace_bytes(redo_table t, int32_t op, int32_t B, int32_t N_max) 
         }
     }
     return large_workspace_bytes(t, op, B, N_max);
+}
+
+size_t redo_grape_workspace_bytes(redo_table t, int32_t B, int32_t N_max, int32_t checkpoint_every) {
+    if (!t || B < 1 || N_max < 1 || checkpoint_every < 0) return 0;
+    const long long C = checkpoint_every > 0 ? checkpoint_every : ceil_sqrt(N_max);
+    const int d = t->desc.d;
+    if (small_dim(d)) {
+        const long long nck = (N_max + C - 1) / C;
+        return sizeof(float2) * (size_t)d * d * (size_t)B * (size_t)(nck + C);
+    }
+    return large_grape_workspace_bytes(t, B, N_max, (int)C);
 }
 
 redo_status redo_quantise(redo_table t, const float* u, int32_t B, int32_t N_max, int32_t* codes, double* phi,

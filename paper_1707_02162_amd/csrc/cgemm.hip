@@ -267,13 +267,22 @@ hipError_t launch(int d, int batch, const GemmDesc* descs, hipStream_t st) {
 hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision, hipStream_t st) {
     if (d % 64 != 0 || batch < 1) return hipErrorInvalidValue;
     // identity-operand entries first (they never alias the product entries' outputs in one launch)
-    const int cblocks = (int)std::min<long long>(((long long)d * d + 255) / 256, 1024);
+    // keep the copy grid under 2^30 threads whatever the batch
+    const int cblocks = (int)std::max<long long>(1, std::min<long long>(((long long)d * d + 255) / 256,
+                                                                        (1LL << 22) / batch));
     hipLaunchKernelGGL(scaled_copy_kernel, dim3(cblocks, batch), dim3(256), 0, st, d, descs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const bool big = d % 128 == 0 && (long long)(d / 128) * (d / 128) * batch >= 512;
-    if (precision == 1) return big ? launch<128, 128, 1>(d, batch, descs, st) : launch<64, 64, 1>(d, batch, descs, st);
-    return big ? launch<128, 128, 0>(d, batch, descs, st) : launch<64, 64, 0>(d, batch, descs, st);
+    void* tok = nullptr;
+    const bool prof = profiling_on();
+    if (prof) profile_begin(st, &tok);
+    if (precision == 1)
+        e = big ? launch<128, 128, 1>(d, batch, descs, st) : launch<64, 64, 1>(d, batch, descs, st);
+    else
+        e = big ? launch<128, 128, 0>(d, batch, descs, st) : launch<64, 64, 0>(d, batch, descs, st);
+    if (prof) profile_end(st, tok);
+    return e;
 }
 
 }  // namespace redo

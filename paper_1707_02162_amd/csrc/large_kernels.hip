@@ -13,28 +13,36 @@ struct PlanArgs {
     const float2* V;        // dense drifts [n_drift][d][d] (dense) or null
     const double* h;        // diagonal drifts [n_drift][d] (diag) or null
     const double* g;        // phase generators [K][d] or null
-    const int* codes;       // [B][N][K] at the plan's step: codes + n*K per instance
+    const float2* cache;    // composed levels [K][levels][d][d] or null
+    const int* codes;       // codes of this step, instance b at codes + b * code_stride
     const double* phi;      // same layout, or null
     const int* n_steps;     // [B] or null
     long long ent;          // d*d
-    long long code_stride;  // elements between instances in codes/phi (N*K)
+    long long code_stride;
     int d, K, P, base, n_drift, phased, dense;
+    int cache_lo, cache_hi, cache_levels;
     int step;               // step index n (for the activity test)
     int drift_div;          // drift of instance b: ((drift_offset + b) / drift_div) % n_drift
     long long drift_offset;
     double dt;
-    float2* X[2];           // ping-pong buffers (per instance stride ent)
+    float2* X[2];           // state buffers (per instance stride xstride)
     long long xstride;
-    int in_buf;             // buffer holding the state before this step
-    int compose;            // 1: first slot takes B = identity
+    int* loc;               // [B]: which buffer holds the state of instance b (updated here)
+    int compose;            // 1: the state starts as the identity (no B operand)
+    int slots;              // launched slots: dense + K (all levels cached) or dense + K * P
+    int all_cached;
     float2* pre;            // [B][d] scale vectors of this step
     float2* post;
     float2* pstar;
-    GemmDesc* descs;        // [S][B]
+    GemmDesc* descs;        // [slots][B]
     int B;
 };
 
-// one workgroup per instance: scale vectors and the descriptors of every slot
+// One workgroup per instance: the step's scale vectors and one descriptor per
+// launched slot.  A slot whose factor is the identity is switched off (no
+// copy); the state's buffer is tracked per instance in loc[b].  The drift and
+// Z^dag scaling rides on the first active factor, Z on the last one; a step
+// with no active factor becomes one scaled copy.
 __global__ __launch_bounds__(256) void plan_step_kernel(PlanArgs a) {
     const int b = blockIdx.x;
     const int d = a.d;
@@ -42,49 +50,119 @@ __global__ __launch_bounds__(256) void plan_step_kernel(PlanArgs a) {
     const int* cb = a.codes + (long long)b * a.code_stride;
     const double* pb = a.phi ? a.phi + (long long)b * a.code_stride : nullptr;
     const int drift = (int)(((a.drift_offset + b) / a.drift_div) % a.n_drift);
-    for (int r = threadIdx.x; r < d; r += blockDim.x) {
-        double th = 0.0;
-        if (a.phased)
-            for (int k = 0; k < a.K; ++k) th += pb[k] * a.g[(long long)k * d + r];
-        const double2 po = expmi(th);                        // e^{-i theta}
-        a.post[(long long)b * d + r] = make_float2((float)po.x, (float)po.y);
-        a.pstar[(long long)b * d + r] = make_float2((float)po.x, (float)-po.y);
-        if (!a.dense) {
-            const double2 pr = expmi(a.dt * a.h[(long long)drift * d + r] - th);   // v e^{+i theta}
-            a.pre[(long long)b * d + r] = make_float2((float)pr.x, (float)pr.y);
+    if (active)
+        for (int r = threadIdx.x; r < d; r += blockDim.x) {
+            double th = 0.0;
+            if (a.phased)
+                for (int k = 0; k < a.K; ++k) th += pb[k] * a.g[(long long)k * d + r];
+            const double2 po = expmi(th);                        // e^{-i theta}
+            a.post[(long long)b * d + r] = make_float2((float)po.x, (float)po.y);
+            a.pstar[(long long)b * d + r] = make_float2((float)po.x, (float)-po.y);
+            if (!a.dense) {
+                const double2 pr = expmi(a.dt * a.h[(long long)drift * d + r] - th);   // v e^{+i theta}
+                a.pre[(long long)b * d + r] = make_float2((float)pr.x, (float)pr.y);
+            }
         }
-    }
     if (threadIdx.x != 0) return;
-    const int S = (a.dense ? 1 : 0) + a.K * a.P;
-    int buf = a.in_buf;
+    const int S = a.slots;
+    int loc = a.loc[b];
+    // factors of every slot (null = identity)
+    const float2* fa[64];
+    int fo[64];
+    int last = -1, first_table = -1;
+    for (int s = 0; s < S; ++s) {
+        fa[s] = nullptr;
+        fo[s] = 0;
+        if (!active) continue;
+        if (a.dense && s == 0) {
+            fa[s] = a.V + (long long)drift * a.ent;
+        } else {
+            const int slot = s - a.dense;
+            const int k = a.all_cached ? slot : slot / a.P;
+            const int j = a.all_cached ? 0 : slot % a.P;
+            const int q = cb[k];
+            const int aq = q < 0 ? -q : q;
+            fo[s] = q < 0 ? 1 : 0;
+            if (a.cache && aq >= a.cache_lo && aq <= a.cache_hi) {
+                if (j == 0 && aq != 0)
+                    fa[s] = a.cache + ((long long)k * a.cache_levels + (aq - a.cache_lo)) * a.ent;
+            } else {
+                const int c = digit_of(q, j, a.base);
+                if (c) fa[s] = a.T + ((long long)(k * a.P + j) * (a.base - 1) + (c - 1)) * a.ent;
+            }
+            if (fa[s] && first_table < 0) first_table = s;
+        }
+        if (fa[s]) last = s;
+    }
+    const bool any_table = first_table >= 0;
+    // a step with no factor at all: one scaled copy on the last slot
+    const int copy_slot = (active && last < 0) ? S - 1 : -1;
+    bool first_op = true;
     for (int s = 0; s < S; ++s) {
         GemmDesc g{};
-        g.active = 1;
         g.alpha = 1.f;
-        g.beta_identity = 0.f;
-        g.B = (a.compose && s == 0) ? nullptr : a.X[buf] + (long long)b * a.xstride;
-        g.C = a.X[buf ^ 1] + (long long)b * a.xstride;
-        if (active) {
-            const bool first_table = s == (a.dense ? 1 : 0);
-            if (a.dense && s == 0) {
-                g.A = a.V + (long long)drift * a.ent;
-                if (a.phased) g.rscale = a.pstar + (long long)b * d;
-            } else {
-                const int slot = s - (a.dense ? 1 : 0);
-                const int k = slot / a.P, j = slot % a.P;
-                const int q = cb[k];
-                const int c = digit_of(q, j, a.base);
-                g.A = c ? a.T + ((long long)(k * a.P + j) * (a.base - 1) + (c - 1)) * a.ent : nullptr;
-                g.opA = q < 0 ? 1 : 0;
-                if (first_table && !a.dense) g.kscale = a.pre + (long long)b * d;
-                if (s == S - 1 && a.phased) g.rscale = a.post + (long long)b * d;
+        const bool use = fa[s] != nullptr || s == copy_slot;
+        g.active = use ? 1 : 0;
+        if (use) {
+            g.A = fa[s];
+            g.opA = fo[s];
+            g.B = (a.compose && first_op) ? nullptr : a.X[loc] + (long long)b * a.xstride;
+            g.C = a.X[loc ^ 1] + (long long)b * a.xstride;
+            if (a.dense) {
+                if (s == 0 && a.phased && any_table) g.rscale = a.pstar + (long long)b * d;
+            } else if (s == first_table || s == copy_slot) {
+                g.kscale = a.pre + (long long)b * d;
             }
-        } else {
-            g.A = nullptr;  // inactive step: plain copy
+            if (a.phased && (s == last || s == copy_slot) && (s != 0 || !a.dense)) g.rscale = a.post + (long long)b * d;
+            loc ^= 1;
+            first_op = false;
         }
         a.descs[(long long)s * a.B + b] = g;
-        buf ^= 1;
     }
+    a.loc[b] = loc;
+}
+
+// re-projection descriptors from the tracked locations:
+// phase 0: Z_b = -X^dag X / 2 + 3/2 I;  phase 1: X'_b = X_b Z_b into the other buffer (and flip loc)
+__global__ void reproject_descs_kernel(GemmDesc* descs, int count, int b0, float2* X0, float2* X1, long long xstride,
+                                       float2* Z, long long zstride, int* loc, const int* n_steps, int step, int phase) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int b = b0 + i;
+    const bool active = n_steps ? step < n_steps[b] : true;
+    GemmDesc g{};
+    g.active = active ? 1 : 0;
+    float2* X[2] = {X0, X1};
+    const int l = loc[b];
+    float2* xb = X[l] + (long long)b * xstride;
+    if (phase == 0) {
+        g.A = xb;
+        g.opA = 1;
+        g.B = xb;
+        g.C = Z + (long long)i * zstride;
+        g.alpha = -0.5f;
+        g.beta_identity = 1.5f;
+    } else {
+        g.A = xb;
+        g.B = Z + (long long)i * zstride;
+        g.C = X[l ^ 1] + (long long)b * xstride;
+        g.alpha = 1.f;
+        if (active) loc[b] = l ^ 1;
+    }
+    descs[i] = g;
+}
+
+// copies the states that ended in buffer 1 back to buffer 0
+__global__ void gather_back_kernel(long long nn, float2* X0, const float2* X1, long long xstride, const int* loc) {
+    const int b = blockIdx.y;
+    if (loc[b] == 0) return;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long long)gridDim.x * blockDim.x)
+        X0[(long long)b * xstride + e] = X1[(long long)b * xstride + e];
+}
+
+__global__ void fill_int_kernel(int* p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // generic descriptors for a batch: C_b = op(A_b) op(B_b), inactive -> copy of op(B_b) (or skip)
@@ -118,12 +196,13 @@ __global__ void fill_descs_kernel(GemmDesc* descs, int count, const float2* A, l
 
 // observable partial sums: block (rb, b) handles rows [16 rb, 16 rb + 16) of instance b
 constexpr int OBS_ROWS = 16;
-__global__ __launch_bounds__(256) void observable_partial_kernel(int d, const float2* __restrict__ X, long long xstride,
-                                                                 const int* __restrict__ cols,
+__global__ __launch_bounds__(256) void observable_partial_kernel(int d, const float2* __restrict__ X0,
+                                                                 const float2* __restrict__ X1, const int* loc,
+                                                                 long long xstride, const int* __restrict__ cols,
                                                                  const float2* __restrict__ vals, int w,
                                                                  const int* n_steps, int step, double* partial) {
     const int b = blockIdx.y, rb = blockIdx.x;
-    const float2* Xb = X + (long long)b * xstride;
+    const float2* Xb = ((loc && loc[b]) ? X1 : X0) + (long long)b * xstride;
     __shared__ double red[256];
     double acc = 0.0;
     const bool active = n_steps ? step < n_steps[b] : true;
@@ -370,10 +449,11 @@ __global__ void norm_kernel(long long nn, const float2* U, double* nu) {
 }
 
 __global__ void identity_kernel(long long nn, int d, int B, float2* X, long long stride) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nn * B) return;
-    const long long b = e / nn, r = e % nn;
-    X[b * stride + r] = make_float2((r / d) == (r % d) ? 1.f : 0.f, 0.f);
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn * B;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long b = e / nn, r = e % nn;
+        X[b * stride + r] = make_float2((r / d) == (r % d) ? 1.f : 0.f, 0.f);
+    }
 }
 
 }  // namespace
@@ -384,6 +464,7 @@ hipError_t plan_step(const PlanLaunch& p, hipStream_t st) {
     a.V = p.V;
     a.h = p.h;
     a.g = p.g;
+    a.cache = p.cache;
     a.codes = p.codes;
     a.phi = p.phi;
     a.n_steps = p.n_steps;
@@ -396,6 +477,9 @@ hipError_t plan_step(const PlanLaunch& p, hipStream_t st) {
     a.n_drift = p.n_drift;
     a.phased = p.phased;
     a.dense = p.dense;
+    a.cache_lo = p.cache_lo;
+    a.cache_hi = p.cache_hi;
+    a.cache_levels = p.cache_hi - p.cache_lo + 1;
     a.step = p.step;
     a.drift_div = p.drift_div;
     a.drift_offset = p.drift_offset;
@@ -403,14 +487,36 @@ hipError_t plan_step(const PlanLaunch& p, hipStream_t st) {
     a.X[0] = p.X0;
     a.X[1] = p.X1;
     a.xstride = p.xstride;
-    a.in_buf = p.in_buf;
+    a.loc = p.loc;
     a.compose = p.compose;
+    a.slots = p.slots;
+    a.all_cached = p.all_cached;
     a.pre = p.pre;
     a.post = p.post;
     a.pstar = p.pstar;
     a.descs = p.descs;
     a.B = p.B;
+    if (a.slots > 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL(plan_step_kernel, dim3(p.B), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t reproject_descs(GemmDesc* descs, int count, int b0, float2* X0, float2* X1, long long xstride, float2* Z,
+                           long long zstride, int* loc, const int* n_steps, int step, int phase, hipStream_t st) {
+    hipLaunchKernelGGL(reproject_descs_kernel, dim3((count + 63) / 64), dim3(64), 0, st, descs, count, b0, X0, X1,
+                       xstride, Z, zstride, loc, n_steps, step, phase);
+    return hipGetLastError();
+}
+
+hipError_t gather_back(int d, int B, float2* X0, const float2* X1, long long xstride, const int* loc, hipStream_t st) {
+    const long long nn = (long long)d * d;
+    const int bx = (int)std::max<long long>(1, std::min<long long>((nn + 255) / 256, (1LL << 22) / B));
+    hipLaunchKernelGGL(gather_back_kernel, dim3(bx, B), dim3(256), 0, st, nn, X0, X1, xstride, loc);
+    return hipGetLastError();
+}
+
+hipError_t fill_int(int* p, int n, int v, hipStream_t st) {
+    hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
     return hipGetLastError();
 }
 
@@ -424,11 +530,11 @@ hipError_t fill_descs(GemmDesc* descs, int count, const float2* A, long long sA,
 
 size_t observable_partial_doubles(int d, int B) { return (size_t)B * (d / OBS_ROWS); }
 
-hipError_t observable(int d, int B, const float2* X, long long xstride, const int* cols, const float2* vals, int w,
-                      const int* n_steps, int step, double* partial, double* out, long long out_stride,
-                      hipStream_t st) {
-    hipLaunchKernelGGL(observable_partial_kernel, dim3(d / OBS_ROWS, B), dim3(256), 0, st, d, X, xstride, cols, vals, w,
-                       n_steps, step, partial);
+hipError_t observable(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
+                      const int* cols, const float2* vals, int w, const int* n_steps, int step, double* partial,
+                      double* out, long long out_stride, hipStream_t st) {
+    hipLaunchKernelGGL(observable_partial_kernel, dim3(d / OBS_ROWS, B), dim3(256), 0, st, d, X0, X1, loc, xstride, cols,
+                       vals, w, n_steps, step, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(observable_final_kernel, dim3(B), dim3(256), 0, st, d / OBS_ROWS, partial, vals, d * w, n_steps,
@@ -472,7 +578,8 @@ hipError_t frob_norms(int d, int B, const float2* U, double* nu, hipStream_t st)
 
 hipError_t fill_identity(int d, int B, float2* X, long long stride, hipStream_t st) {
     const long long nn = (long long)d * d;
-    hipLaunchKernelGGL(identity_kernel, dim3((unsigned)((nn * B + 255) / 256)), dim3(256), 0, st, nn, d, B, X, stride);
+    const long long blocks = std::min<long long>((nn * B + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(identity_kernel, dim3((unsigned)blocks), dim3(256), 0, st, nn, d, B, X, stride);
     return hipGetLastError();
 }
 

@@ -38,6 +38,13 @@ struct Carve {
 
 int slots_of(const redo_table_s* t) { return (t->desc.drift_is_diag ? 0 : 1) + t->desc.K * t->desc.digits; }
 
+// every level 0 .. b^P - 1 is in the composed cache: one factor slot per channel
+bool all_cached(const redo_table_s* t) { return t->cache && t->cache_lo == 0 && (double)t->cache_hi >= t->qmax; }
+
+int launch_slots(const redo_table_s* t) {
+    return (t->desc.drift_is_diag ? 0 : 1) + (all_cached(t) ? t->desc.K : t->desc.K * t->desc.digits);
+}
+
 // layout of every workspace; with base == nullptr it only measures
 struct ChainWS {
     int* codes;
@@ -47,6 +54,7 @@ struct ChainWS {
     GemmDesc* descs;
     float2* Z;
     double* obs_partial;
+    int* loc;
     size_t bytes;
     ChainWS(const redo_table_s* t, int B, int N, void* base) {
         const int d = t->desc.d, K = t->desc.K;
@@ -61,6 +69,7 @@ struct ChainWS {
         descs = c.take<GemmDesc>((size_t)std::max(slots_of(t), 2) * B);
         Z = c.take<float2>(mat * std::min(B, REPROJECT_CHUNK));
         obs_partial = c.take<double>(observable_partial_doubles(d, B));
+        loc = c.take<int>(B);
         bytes = c.used;
     }
 };
@@ -71,6 +80,7 @@ struct ComposeWS {
     float2* tmp;
     float2 *pre, *post, *pstar;
     GemmDesc* descs;
+    int* loc;
     size_t bytes;
     ComposeWS(const redo_table_s* t, long long I, void* base) {
         const int d = t->desc.d, K = t->desc.K;
@@ -84,6 +94,7 @@ struct ComposeWS {
         post = c.take<float2>((size_t)ch * d);
         pstar = c.take<float2>((size_t)ch * d);
         descs = c.take<GemmDesc>((size_t)slots_of(t) * ch);
+        loc = c.take<int>(ch);
         bytes = c.used;
     }
 };
@@ -159,13 +170,18 @@ PlanLaunch plan_base(const redo_table_s* t) {
     p.dt = t->desc.dt;
     p.xstride = t->entry_elems;
     p.drift_div = 1;
+    p.cache = t->cache;
+    p.cache_lo = t->cache_lo;
+    p.cache_hi = t->cache_hi;
+    p.slots = launch_slots(t);
+    p.all_cached = all_cached(t) ? 1 : 0;
     return p;
 }
 
 // compose U_i for I flattened (instance, step) pairs whose codes are already quantised
 redo_status compose_pairs(redo_table_s* t, int precision, long long I, int N, const ComposeWS& w, float2* U_out,
                           hipStream_t st) {
-    const int S = slots_of(t);
+    const int S = launch_slots(t);
     const long long mat = t->entry_elems;
     for (long long i0 = 0; i0 < I; i0 += COMPOSE_CHUNK) {
         const int ch = (int)std::min<long long>(COMPOSE_CHUNK, I - i0);
@@ -174,20 +190,22 @@ redo_status compose_pairs(redo_table_s* t, int precision, long long I, int N, co
         p.phi = t->desc.phased ? w.phi + i0 * t->desc.K : nullptr;
         p.code_stride = t->desc.K;
         p.step = 0;
-        // instance i of this chunk is pair i0 + i; its drift follows its instance (i0 + i) / N
+        // pair i of this chunk is global pair i0 + i, whose drift follows its instance (i0 + i) / N
         p.drift_div = N;
         p.drift_offset = i0;
         p.X0 = U_out + i0 * mat;
         p.X1 = w.tmp;
-        p.in_buf = S % 2;
+        p.loc = w.loc;
         p.compose = 1;
         p.pre = w.pre;
         p.post = w.post;
         p.pstar = w.pstar;
         p.descs = w.descs;
         p.B = ch;
+        REDO_HIP(fill_int(w.loc, ch, 0, st));
         REDO_HIP(plan_step(p, st));
         for (int s = 0; s < S; ++s) REDO_HIP(cgemm_batched(t->desc.d, ch, w.descs + (size_t)s * ch, gemm_prec(precision), st));
+        REDO_HIP(gather_back(t->desc.d, ch, p.X0, w.tmp, mat, w.loc, st));
     }
     return REDO_OK;
 }
@@ -201,6 +219,10 @@ size_t large_workspace_bytes(const redo_table_s* t, int op, int B, int N) {
         case REDO_OP_GRAPE: return GrapeWS(t, B, N, (int)ceil_sqrt_ll(N), nullptr).bytes;
         default: return 0;
     }
+}
+
+size_t large_grape_workspace_bytes(const redo_table_s* t, int B, int N, int C) {
+    return GrapeWS(t, B, N, C, nullptr).bytes;
 }
 
 redo_status large_compose(redo_table_s* t, int precision, const float* u, int B, int N, float* U_out, void* workspace,
@@ -234,8 +256,8 @@ redo_status large_chain(redo_table_s* t, int precision, const float* u, const in
         REDO_HIP(fill_identity(d, B, X[0], mat, st));
     else if (X0 != U_total)
         REDO_HIP(hipMemcpyAsync(X[0], X0, sizeof(float2) * mat * B, hipMemcpyDeviceToDevice, st));
-    const int S = slots_of(t);
-    int cur = 0;
+    REDO_HIP(fill_int(w.loc, B, 0, st));
+    const int S = launch_slots(t);
     const int prec = gemm_prec(precision);
     for (int n = 0; n < N; ++n) {
         PlanLaunch p = plan_base(t);
@@ -246,7 +268,7 @@ redo_status large_chain(redo_table_s* t, int precision, const float* u, const in
         p.step = n;
         p.X0 = X[0];
         p.X1 = X[1];
-        p.in_buf = cur;
+        p.loc = w.loc;
         p.pre = w.pre;
         p.post = w.post;
         p.pstar = w.pstar;
@@ -254,26 +276,21 @@ redo_status large_chain(redo_table_s* t, int precision, const float* u, const in
         p.B = B;
         REDO_HIP(plan_step(p, st));
         for (int sl = 0; sl < S; ++sl) REDO_HIP(cgemm_batched(d, B, w.descs + (size_t)sl * B, prec, st));
-        cur = (cur + S) & 1;
         if (reproject_every > 0 && ((long long)step_offset + n + 1) % reproject_every == 0) {
             // X <- X (3I - X^dag X) / 2 = X Z with Z = -X^dag X / 2 + 3/2 I
             for (int b0 = 0; b0 < B; b0 += REPROJECT_CHUNK) {
                 const int ch = std::min(REPROJECT_CHUNK, B - b0);
-                const int* ns = n_steps ? n_steps + b0 : nullptr;
-                float2* xin = X[cur] + (size_t)b0 * mat;
-                REDO_HIP(fill_descs(w.descs, ch, xin, mat, 1, xin, mat, 0, w.Z, mat, ns, n, 0, -0.5f, 1.5f, st));
+                REDO_HIP(reproject_descs(w.descs, ch, b0, X[0], X[1], mat, w.Z, mat, w.loc, n_steps, n, 0, st));
                 REDO_HIP(cgemm_batched(d, ch, w.descs, prec, st));
-                REDO_HIP(fill_descs(w.descs, ch, xin, mat, 0, w.Z, mat, 0, X[cur ^ 1] + (size_t)b0 * mat, mat, ns, n, 2,
-                                    1.f, 0.f, st));
+                REDO_HIP(reproject_descs(w.descs, ch, b0, X[0], X[1], mat, w.Z, mat, w.loc, n_steps, n, 1, st));
                 REDO_HIP(cgemm_batched(d, ch, w.descs, prec, st));
             }
-            cur ^= 1;
         }
         if (obs_out)
-            REDO_HIP(observable(d, B, X[cur], mat, obs_cols, reinterpret_cast<const float2*>(obs_vals), obs_width,
-                                n_steps, n, w.obs_partial, obs_out + n, N, st));
+            REDO_HIP(observable(d, B, X[0], X[1], w.loc, mat, obs_cols, reinterpret_cast<const float2*>(obs_vals),
+                                obs_width, n_steps, n, w.obs_partial, obs_out + n, N, st));
     }
-    if (cur != 0) REDO_HIP(hipMemcpyAsync(X[0], X[1], sizeof(float2) * mat * B, hipMemcpyDeviceToDevice, st));
+    REDO_HIP(gather_back(d, B, X[0], X[1], mat, w.loc, st));
     return REDO_OK;
 }
 

@@ -5,6 +5,7 @@
 namespace redo {
 
 size_t large_workspace_bytes(const redo_table_s* t, int op, int B, int N_max);
+size_t large_grape_workspace_bytes(const redo_table_s* t, int B, int N_max, int checkpoint_every);
 
 redo_status large_compose(redo_table_s* t, int precision, const float* u, int B, int N, float* U_out,
                           void* workspace, size_t workspace_bytes, hipStream_t st);
@@ -24,17 +25,19 @@ struct PlanLaunch {
     const float2* V;
     const double* h;
     const double* g;
+    const float2* cache;
     const int* codes;
     const double* phi;
     const int* n_steps;
     long long ent, code_stride;
-    int d, K, P, base, n_drift, phased, dense, step, drift_div;
+    int d, K, P, base, n_drift, phased, dense, cache_lo, cache_hi, step, drift_div;
     long long drift_offset;  // instance b of the launch is global index drift_offset + b
     double dt;
     float2* X0;
     float2* X1;
     long long xstride;
-    int in_buf, compose;
+    int* loc;
+    int compose, slots, all_cached;
     float2* pre;
     float2* post;
     float2* pstar;
@@ -48,9 +51,13 @@ hipError_t fill_descs(GemmDesc* descs, int count, const float2* A, long long sA,
                       long long sB, int opB, float2* C, long long sC, const int* n_steps, int step,
                       int inactive_mode, float alpha, float beta, hipStream_t st);
 size_t observable_partial_doubles(int d, int B);
-hipError_t observable(int d, int B, const float2* X, long long xstride, const int* cols, const float2* vals, int w,
-                      const int* n_steps, int step, double* partial, double* out, long long out_stride,
-                      hipStream_t st);
+hipError_t observable(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
+                      const int* cols, const float2* vals, int w, const int* n_steps, int step, double* partial,
+                      double* out, long long out_stride, hipStream_t st);
+hipError_t reproject_descs(GemmDesc* descs, int count, int b0, float2* X0, float2* X1, long long xstride, float2* Z,
+                           long long zstride, int* loc, const int* n_steps, int step, int phase, hipStream_t st);
+hipError_t gather_back(int d, int B, float2* X0, const float2* X1, long long xstride, const int* loc, hipStream_t st);
+hipError_t fill_int(int* p, int n, int v, hipStream_t st);
 size_t trace_partial_doubles(int d, int B, int K);
 hipError_t traces(int d, int B, int K, int phased, const float2* Y, long long ystride, const float2* S,
                   const double* g, const int* codes, const double* phi, long long code_stride, const int* n_steps,

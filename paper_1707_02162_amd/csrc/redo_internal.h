@@ -102,6 +102,8 @@ struct redo_table_s {
     float2* V32 = nullptr;  // drift propagators: diag [n_drift][d] or dense [n_drift][d][d]
     double* g64 = nullptr;  // phase generators [K][d] (phased)
     float2* S32 = nullptr;  // generators rounded to FP32, [K][d][d]
+    double2* S64 = nullptr; // generators as given (FP64), [K][d][d]: source of every FP64 rebuild
+    std::vector<double> s_norm;  // ||S_k||_1
     redo::DeviceFlags* flags = nullptr;
     size_t bytes = 0;
     bool grad_ok = false;   // channels commute with each other, phases with drift
@@ -199,5 +201,10 @@ struct GemmDesc {
 static_assert(sizeof(GemmDesc) % 8 == 0, "desc alignment");
 
 hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision, hipStream_t st);
+
+// launch timing (profile.cpp)
+bool profiling_on();
+void profile_begin(hipStream_t st, void** token);
+void profile_end(hipStream_t st, void* token);
 
 }  // namespace redo

@@ -28,7 +28,9 @@ _SIG = {
     "redo_build_table": (_I, [_P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "redo_table_destroy": (_I, [_P]),
     "redo_table_query": (_I, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
+    "redo_cache_levels": (_I, [_P, _I, _I, _P]),
     "redo_workspace_bytes": (ctypes.c_size_t, [_P, _I, _I, _I]),
+    "redo_grape_workspace_bytes": (ctypes.c_size_t, [_P, _I, _I, _I]),
     "redo_quantise": (_I, [_P, _P, _I, _I, _P, _P, _P]),
     "redo_compose_steps": (_I, [_P, _I, _P, _I, _I, _P, _P, ctypes.c_size_t, _P]),
     "redo_chain_propagator": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _P, _I, _P, _P,
@@ -36,6 +38,8 @@ _SIG = {
     "redo_unitary_fidelity": (_I, [_I, _I, _P, _P, _P, _P, _P]),
     "redo_grape_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _I, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "redo_get_device_status": (_I, [_P, _P, ctypes.POINTER(ctypes.c_int64)]),
+    "redo_profile_enable": (_I, [_I]),
+    "redo_profile_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _I]),
     "redo_status_string": (ctypes.c_char_p, [_I]),
     "redo_last_error": (ctypes.c_char_p, []),
 }
@@ -141,6 +145,15 @@ class RedoTable:
         except Exception:
             pass
 
+    def cache_levels(self, q_lo: int = 0, q_hi: Optional[int] = None) -> None:
+        """Compose and keep R_k(q) for q_lo <= q <= q_hi (default: every level)."""
+        if q_hi is None:
+            q_hi = self.base ** self.digits - 1
+        _check(lib().redo_cache_levels(self._h, q_lo, q_hi, _stream()))
+
+    def clear_cache(self) -> None:
+        _check(lib().redo_cache_levels(self._h, 0, -1, _stream()))
+
     @property
     def device_bytes(self) -> int:
         n = ctypes.c_size_t()
@@ -207,10 +220,7 @@ class RedoTable:
         F = torch.empty(B, dtype=torch.float64, device=self.device)
         ov = torch.empty(B, dtype=torch.complex128, device=self.device)
         grad = torch.empty_like(ut)
-        nbytes = lib().redo_workspace_bytes(self._h, OP_GRAPE, B, N)
-        if checkpoint_every > 0 and self.d <= 64:
-            nck = -(-N // checkpoint_every)
-            nbytes = 8 * self.d * self.d * B * (nck + checkpoint_every)
+        nbytes = lib().redo_grape_workspace_bytes(self._h, B, N, checkpoint_every)
         ws = torch.empty(max(int(nbytes), 16), dtype=torch.uint8, device=self.device)
         _check(lib().redo_grape_fidelity_grad(self._h, precision, _ptr(ut), _ptr(ns), B, N, _ptr(Uf),
                                               checkpoint_every, _ptr(F), _ptr(ov), _ptr(grad), _ptr(ws),
@@ -221,6 +231,18 @@ class RedoTable:
         n = ctypes.c_int64()
         st = lib().redo_get_device_status(self._h, _stream(), ctypes.byref(n))
         return st, n.value
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(lib().redo_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = True):
+    """(summed GEMM-launch milliseconds, launch count) since the last reset."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().redo_profile_read(ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
+    return ms.value, n.value
 
 
 def unitary_fidelity(U_target: torch.Tensor, U: torch.Tensor):

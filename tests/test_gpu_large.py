@@ -1,0 +1,248 @@
+"""GPU parity of the large-d path (d >= 128: batched MFMA complex GEMMs)
+against the FP64 oracle.  Tolerances as for the small path:
+||dU||_F / sqrt(d) <= 1e-5 (FP32), |dF| <= 1e-6, gradient relative L2 <= 1e-4."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1707_02162_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FROB_TOL = 1e-5
+FID_TOL = 1e-6
+GRAD_TOL = 1e-4
+
+
+def R():
+    from paper_1707_02162_amd import redo
+    return redo
+
+
+def nfrob(A, B):
+    return float(np.linalg.norm(np.asarray(A, np.complex128) - B) / math.sqrt(B.shape[-1]))
+
+
+def generic_problem(d, B, N, seed, phased=False, K=1):
+    """Random Hermitian generators and diagonal drift at a dimension that is
+    not a power of two (exercises 64-wide tiles and ragged tile counts)."""
+    rng = np.random.default_rng(seed)
+    S = []
+    for _ in range(K):
+        A = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+        S.append((A + A.conj().T) / (2 * math.sqrt(d)))
+    S = np.stack(S)
+    H0 = rng.uniform(-2e4, 2e4, (1, d))
+    dt = 1e-6
+    scale = 3e4
+    if phased:
+        raise NotImplementedError
+    u = (rng.uniform(-1, 1, (B, N, K)) * scale).astype(np.float32)
+    eps = scale / (32 * 32 - 1)
+    return W.Problem("generic", d, K, False, H0, True, S, None, dt, eps, 32, 2, u, None, None, None, u_scale=scale)
+
+
+def test_compose_d128_vs_oracle():
+    p = W.nmr_chain(7, 2, 12, 2e-6, 32, 2, 201)
+    t = R().RedoTable.from_problem(p)
+    U = t.compose(torch.tensor(p.u).cuda()).cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(p.B):
+        steps = O.compose_all_redo(p, tab, b)
+        for n in range(p.N):
+            assert nfrob(U[b, n], steps[n]) < FROB_TOL
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_chain_d128_ragged_vs_oracle(prec):
+    lens = np.array([40, 17, 33], np.int32)
+    p = W.nmr_chain(7, 3, 40, 2e-6, 32, 2, 202, lengths=lens, n_drift=2)
+    t = R().RedoTable.from_problem(p)
+    U, _, _ = t.chain(torch.tensor(p.u).cuda(), n_steps=torch.tensor(lens), precision=prec)
+    U = U.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(p.B):
+        X = O.chain(O.compose_all_redo(p, tab, b))
+        assert nfrob(U[b], X) < FROB_TOL, (b, nfrob(U[b], X))
+
+
+def test_chain_generic_d192_signed_vs_oracle():
+    p = generic_problem(192, 3, 30, 203)
+    t = R().RedoTable.from_problem(p)
+    U, _, _ = t.chain(torch.tensor(p.u).cuda(), reproject_every=8)
+    U = U.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(p.B):
+        X = O.chain(O.compose_all_redo(p, tab, b))
+        assert nfrob(U[b], X) < FROB_TOL
+
+
+def test_chain_generic_two_channels_dense_drift_vs_oracle():
+    p = generic_problem(128, 2, 20, 204, K=2)
+    rng = np.random.default_rng(5)
+    A = rng.normal(size=(128, 128)) + 1j * rng.normal(size=(128, 128))
+    p.H0 = ((A + A.conj().T) * 1e3)[None]
+    p.drift_is_diag = False
+    t = R().RedoTable.from_problem(p)
+    U, _, _ = t.chain(torch.tensor(p.u).cuda())
+    U = U.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(p.B):
+        assert nfrob(U[b], O.chain(O.compose_all_redo(p, tab, b))) < FROB_TOL
+
+
+def test_ising_d128_observable_vs_oracle():
+    p = W.ising_freezing(n=7, B=3, N=70)
+    t = R().RedoTable.from_problem(p)
+    cols, vals = W.observable_ell(p.M)
+    U, _, m = t.chain(torch.tensor(p.u).cuda(), observable=(cols, vals), reproject_every=64)
+    U, m = U.cpu().numpy(), m.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(p.B):
+        mo, X = O.magnetisation_series(O.compose_all_redo(p, tab, b), p.M)
+        assert nfrob(U[b], X) < FROB_TOL
+        assert np.abs(m[b] - mo).max() < 1e-5
+
+
+def test_chunked_chain_equals_one_call_d128():
+    p = W.ising_freezing(n=7, B=2, N=40)
+    t = R().RedoTable.from_problem(p)
+    u = torch.tensor(p.u).cuda()
+    U_all, _, _ = t.chain(u, reproject_every=8)
+    U_a, _, _ = t.chain(u[:, :24].contiguous(), reproject_every=8)
+    U_b, _, _ = t.chain(u[:, 24:].contiguous(), X0=U_a, reproject_every=8, step_offset=24)
+    assert torch.equal(U_all, U_b)
+
+
+def test_grape_d128_phased_vs_oracle():
+    p = W.nmr_chain(7, 2, 30, 2e-6, 32, 2, 205)
+    t = R().RedoTable.from_problem(p)
+    F, ov, grad = t.grape(torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda())
+    F, ov, grad = F.cpu().numpy(), ov.cpu().numpy(), grad.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(p.B):
+        Fo, go, gro = O.fidelity_and_gradient(p, b, model="redo", table=tab)
+        assert abs(F[b] - Fo) < FID_TOL
+        assert abs(ov[b] - go) < 1e-5
+        assert np.linalg.norm(grad[b] - gro) <= GRAD_TOL * np.linalg.norm(gro)
+
+
+def test_grape_d128_signed_ragged_vs_oracle():
+    p = W.ising_freezing(n=7, B=2, N=25)
+    p.n_steps = np.array([25, 14], np.int32)
+    p.U_target = np.stack([W.haar_unitary(128, W.rng(33, 2, b)) for b in range(2)])
+    t = R().RedoTable.from_problem(p)
+    F, ov, grad = t.grape(torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda(),
+                          n_steps=torch.tensor(p.n_steps), checkpoint_every=4)
+    F, grad = F.cpu().numpy(), grad.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(p.B):
+        Fo, go, gro = O.fidelity_and_gradient(p, b, model="redo", table=tab)
+        nb = int(p.n_steps[b])
+        assert abs(F[b] - Fo) < FID_TOL
+        assert np.linalg.norm(grad[b, :nb] - gro) <= GRAD_TOL * np.linalg.norm(gro)
+        assert np.all(grad[b, nb:] == 0)
+
+
+def test_grape_large_matches_small_path_semantics():
+    """The same 7-qubit problem through the GRAPE call at two checkpoint
+    intervals gives identical results (recomputation is exact)."""
+    p = W.nmr_chain(7, 1, 20, 2e-6, 32, 2, 206)
+    t = R().RedoTable.from_problem(p)
+    u, Uf = torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda()
+    F1, _, g1 = t.grape(u, Uf, checkpoint_every=1)
+    F2, _, g2 = t.grape(u, Uf, checkpoint_every=6)
+    assert torch.equal(F1, F2) and torch.equal(g1, g2)
+
+
+# ---------------------------------------------------------------- full size
+def test_ising_d1024_special_cases_full_dimension():
+    """At d = 1024: without coupling the magnetisation stays 1 for any noisy
+    drive; without drive it follows [2 cos Jt + (n-2) cos^2 Jt]/n."""
+    p = W.ising_freezing(n=10, B=2, N=24, J=0.0)
+    t = R().RedoTable.from_problem(p)
+    cols, vals = W.observable_ell(p.M)
+    _, _, m = t.chain(torch.tensor(p.u).cuda(), observable=(cols, vals))
+    assert np.abs(m.cpu().numpy() - 1.0).max() < 1e-4
+    q = W.ising_freezing(n=10, B=1, N=24)
+    q.u[:] = 0.0
+    t2 = R().RedoTable.from_problem(q)
+    _, _, m2 = t2.chain(torch.tensor(q.u).cuda(), observable=(cols, vals))
+    J = q.meta["J"]
+    tt = np.arange(1, 25) * q.dt
+    want = (2 * np.cos(J * tt) + 8 * np.cos(J * tt) ** 2) / 10
+    assert np.abs(m2.cpu().numpy()[0] - want).max() < 1e-4
+
+
+def test_ising_d1024_full_batch_sampled_vs_oracle():
+    """The benchmark's launch shape (4096 realisations x d = 1024, one call
+    per step window) on its first steps; sampled realisations against the oracle."""
+    n_steps = 3
+    p = W.ising_freezing(n=10, B=4096, N=n_steps)
+    t = R().RedoTable.from_problem(p)
+    cols, vals = W.observable_ell(p.M)
+    U, _, m = t.chain(torch.tensor(p.u).cuda(), observable=(cols, vals))
+    torch.cuda.synchronize()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in (0, 4095):
+        mo, X = O.magnetisation_series(O.compose_all_redo(p, tab, b), p.M)
+        assert nfrob(U[b].cpu().numpy(), X) < FROB_TOL
+        assert np.abs(m[b].cpu().numpy() - mo).max() < 1e-5
+
+
+# ---------------------------------------------------------------- level cache (process 3)
+def test_level_cache_full_range_chain_vs_oracle():
+    lens = np.array([30, 11], np.int32)
+    p = W.ising_freezing(n=7, B=2, N=30)
+    t = R().RedoTable.from_problem(p)
+    t.cache_levels()
+    cols, vals = W.observable_ell(p.M)
+    U, _, m = t.chain(torch.tensor(p.u).cuda(), n_steps=torch.tensor(lens), observable=(cols, vals),
+                      reproject_every=7)
+    U, m = U.cpu().numpy(), m.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(p.B):
+        mo, X = O.magnetisation_series(O.compose_all_redo(p, tab, b, n_steps=int(lens[b])), p.M)
+        assert nfrob(U[b], X) < FROB_TOL
+        assert np.abs(m[b, :lens[b]] - mo).max() < 1e-5
+
+
+def test_level_cache_partial_range_phased_vs_oracle():
+    """Levels inside the cached range use one composed factor, the others the
+    digit products; both mixed within one step batch."""
+    p = W.nmr_chain(7, 3, 25, 2e-6, 32, 2, 207, n_drift=2)
+    t = R().RedoTable.from_problem(p)
+    t.cache_levels(200, 700)
+    U, _, _ = t.chain(torch.tensor(p.u).cuda())
+    Uc = t.compose(torch.tensor(p.u[:, :6]).cuda()).cpu().numpy()
+    U = U.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(p.B):
+        steps = O.compose_all_redo(p, tab, b)
+        assert nfrob(U[b], O.chain(steps)) < FROB_TOL
+        for n in range(6):
+            assert nfrob(Uc[b, n], steps[n]) < 2e-7
+
+
+def test_level_cache_grape_vs_oracle():
+    p = W.nmr_chain(7, 1, 24, 2e-6, 32, 2, 208)
+    t = R().RedoTable.from_problem(p)
+    t.cache_levels()
+    F, ov, grad = t.grape(torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda())
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    Fo, go, gro = O.fidelity_and_gradient(p, 0, model="redo", table=tab)
+    assert abs(F[0].item() - Fo) < FID_TOL
+    g = grad[0].cpu().numpy()
+    assert np.linalg.norm(g - gro) <= GRAD_TOL * np.linalg.norm(gro)
+
+
+def test_level_cache_d1024_special_case_and_sampled():
+    p = W.ising_freezing(n=10, B=64, N=24, J=0.0)
+    t = R().RedoTable.from_problem(p)
+    t.cache_levels()
+    cols, vals = W.observable_ell(p.M)
+    _, _, m = t.chain(torch.tensor(p.u).cuda(), observable=(cols, vals))
+    assert np.abs(m.cpu().numpy() - 1.0).max() < 2e-5
