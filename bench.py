@@ -6,7 +6,8 @@ chain (d = 1024) with 4096 seeded noise realisations batched in one launch.
 One benchmark step advances every realisation by one time segment: coarse
 graining of its amplitude, the table products of its step, the chain product,
 the magnetisation observable, and the Newton-Schulz re-projection whenever the
-global step index reaches a multiple of 64.  value = realisation-steps/s.
+global step index reaches a multiple of 64.  Steps are issued --chunk at a
+time per library call.  value = realisation-steps/s.
 
 Also reported: GRAPE iterations/s (fidelity + adjoint gradient) of a
 10-qubit NMR chain (d = 1024, N = 500), the plain per-step exponential on the
@@ -47,8 +48,10 @@ def count_products(codes: np.ndarray, base: int, digits: int) -> int:
 
 
 def bench_freezing(args, redo, W, torch):
+    """REDO chain (FP32 headline, split BF16) and the plain per-step exponential
+    on the same 4096-realisation workload, one table."""
     B, K, Wm = args.realisations, args.steps, args.warmup
-    N = Wm + K
+    N = Wm + max(K, args.expm_steps)
     log(f"[bench] building the Ising workload: B={B} d=1024 steps={N}")
     p = W.ising_freezing(n=10, B=B, N=N)
     t0 = time.time()
@@ -56,66 +59,93 @@ def bench_freezing(args, redo, W, torch):
     torch.cuda.synchronize()
     t_table = time.time() - t0
     log(f"[bench] table built in {t_table:.2f}s ({table.device_bytes / 2**30:.2f} GiB)")
+    t_cache = 0.0
+    if args.cache:
+        t0 = time.time()
+        table.cache_levels()
+        torch.cuda.synchronize()
+        t_cache = time.time() - t0
+        log(f"[bench] every level composed once in {t_cache:.2f}s (table + cache {table.device_bytes / 2**30:.1f} GiB)")
     u = torch.tensor(p.u, device="cuda")
     cols, vals = W.observable_ell(p.M)
     obs = (torch.tensor(cols, device="cuda"), torch.tensor(vals, device="cuda", dtype=torch.complex64))
     U = torch.empty((B, p.d, p.d), dtype=torch.complex64, device="cuda")
     mag = torch.empty((B, N), dtype=torch.float64, device="cuda")
 
-    def step(n, first=False):
-        Un, _, m = table.chain(u[:, n:n + 1].contiguous(), X0=None if first else U, out=U, step_offset=n,
-                               reproject_every=args.reproject, observable=obs)
-        mag[:, n:n + 1] = m
+    def run(kind, precision, steps):
+        def advance(n0, n1):
+            un = u[:, n0:n1].contiguous()
+            X0 = None if n0 == 0 else U
+            if kind == "redo":
+                _, _, m = table.chain(un, X0=X0, out=U, step_offset=n0, reproject_every=args.reproject,
+                                      observable=obs, precision=precision)
+            else:
+                _, m = table.expm_chain(un, X0=X0, out=U, step_offset=n0, reproject_every=args.reproject,
+                                        observable=obs, precision=precision)
+            mag[:, n0:n1] = m
 
-    for n in range(Wm):
-        step(n, first=(n == 0))
+        for n0 in range(0, Wm, args.chunk):
+            advance(n0, min(Wm, n0 + args.chunk))
         torch.cuda.synchronize()
-        log(f"[bench] warmup step {n + 1}/{Wm}")
-    redo.profile_enable(True)
-    redo.profile_read(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for n in range(Wm, N):
-        step(n, first=(n == 0))
-        if (n - Wm) % 2 == 1:
-            log(f"[bench] timed step {n - Wm + 1}/{K}")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    gemm_ms, launches = redo.profile_read(reset=True)
-    redo.profile_enable(False)
-    codes, _ = table.quantise(u[:, Wm:N].contiguous())
-    products = count_products(codes.cpu().numpy(), p.base, p.digits)
-    flops = 8.0 * p.d ** 3 * products
-    achieved = flops / (gemm_ms * 1e-3) / 1e12
-    m = mag.cpu().numpy()
-    res = dict(value=B * K / elapsed, ms_per_step=1e3 * elapsed / K, table_build_s=t_table,
-               gemm_ms=gemm_ms, gemm_launches=launches, products=products, achieved=achieved,
-               flops_per_launch=flops / max(launches, 1), avg_launch_ms=gemm_ms / max(launches, 1),
-               mag_first=float(m[:, 0].mean()), mag_last=float(m[:, -1].mean()))
+        redo.profile_enable(True)
+        redo.profile_read(reset=True)
+        t0 = time.perf_counter()
+        for n0 in range(Wm, Wm + steps, args.chunk):
+            n1 = min(Wm + steps, n0 + args.chunk)
+            advance(n0, n1)
+            log(f"[bench] {kind} p{precision} timed steps {n1 - Wm}/{steps}")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        gemm_ms, launches = redo.profile_read(reset=True)
+        redo.profile_enable(False)
+        codes, _ = table.quantise(u[:, Wm:Wm + steps].contiguous())
+        cn = codes.cpu().numpy()
+        products = int(np.count_nonzero(cn)) if args.cache else count_products(cn, p.base, p.digits)
+        flops = 8.0 * p.d ** 3 * products
+        m = mag[:, :Wm + steps].cpu().numpy()
+        return dict(value=B * steps / elapsed, ms_per_step=1e3 * elapsed / steps, gemm_ms=gemm_ms,
+                    gemm_launches=launches, products=products,
+                    achieved=(flops / (gemm_ms * 1e-3) / 1e12) if kind == "redo" else None,
+                    step_flops=flops / steps,
+                    flops_per_launch=flops / max(launches, 1), avg_launch_ms=gemm_ms / max(launches, 1),
+                    mag_last=m[:, -1].copy())
+
+    fp32 = run("redo", 0, K)
+    bf = None if args.no_bf16 else run("redo", 2, K)
+    ex = None if args.no_expm else run("expm", 0, args.expm_steps)
+    out = dict(fp32=fp32, bf16x3=bf, expm=ex, table_build_s=t_table, cache_build_s=t_cache)
     del table
-    return res, p
+    return out, p
 
 
 def bench_grape(args, redo, W, torch):
     p = W.c6_grape_1024(B=1, N=500)
     table = redo.RedoTable.from_problem(p)
+    if args.cache:
+        table.cache_levels()
     u = torch.tensor(p.u, device="cuda")
     Uf = torch.tensor(p.U_target, device="cuda")
-    for i in range(1):
-        table.grape(u, Uf)
-    torch.cuda.synchronize()
-    log("[bench] grape warmup done")
-    t0 = time.perf_counter()
-    for i in range(args.grape_iters):
-        F, _, g = table.grape(u, Uf)
-        # projected gradient ascent update (the accepted step of an iteration)
-        u = torch.clamp(u + 1e3 * g, -p.u_scale, p.u_scale)
+    res = {}
+    for kind in ("redo", "expm"):
+        if kind == "expm" and args.no_expm:
+            continue
+        fn = table.grape if kind == "redo" else table.expm_grape
+        uu = u.clone()
+        fn(uu, Uf)
         torch.cuda.synchronize()
-        log(f"[bench] grape iteration {i + 1}/{args.grape_iters}")
-    elapsed = time.perf_counter() - t0
+        log(f"[bench] {kind} grape warmup done")
+        t0 = time.perf_counter()
+        for i in range(args.grape_iters):
+            F, _, g = fn(uu, Uf)
+            # projected gradient ascent update (the accepted step of an iteration)
+            uu = torch.clamp(uu + 1e3 * g, -p.u_scale, p.u_scale)
+            torch.cuda.synchronize()
+            log(f"[bench] {kind} grape iteration {i + 1}/{args.grape_iters}")
+        elapsed = time.perf_counter() - t0
+        res[kind] = dict(iters_per_s=args.grape_iters / elapsed, ms_per_iter=1e3 * elapsed / args.grape_iters,
+                         fidelity=float(F.item()))
     del table
-    return dict(iters_per_s=args.grape_iters / elapsed, ms_per_iter=1e3 * elapsed / args.grape_iters,
-                fidelity=float(F.item()))
+    return res
 
 
 def cpu_baseline(args, W):
@@ -150,7 +180,13 @@ def main():
     ap.add_argument("--grape-iters", type=int, default=3)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-grape", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-expm", action="store_true")
+    ap.add_argument("--expm-steps", type=int, default=4)
+    ap.add_argument("--chunk", type=int, default=4, help="time segments advanced per library call")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cache", dest="cache", action="store_false",
+                    help="apply one product per non-zero digit instead of the composed level of each amplitude")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -168,35 +204,52 @@ def main():
     gr = None if args.no_grape else bench_grape(args, redo, W, torch)
     torch.cuda.empty_cache()
     cpu = None if args.no_cpu else cpu_baseline(args, W)
+    f32, bf, ex = fr["fp32"], fr["bf16x3"], fr["expm"]
+    rg = None if gr is None else gr.get("redo")
+    eg = None if gr is None else gr.get("expm")
     out = {
         "metric": "propagator steps/s + GRAPE iters/s at d=1024, REDO vs plain expm, same GPU",
-        "value": fr["value"],
+        "value": f32["value"],
         "unit": "propagator steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": fr["ms_per_step"],
+        "ms_per_step": f32["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 (fp32 complex, 4 real MFMA products per complex product)",
+        "dtype": "c64 (fp32 complex; 4 real MFMA products per complex product)",
         "data": "synthetic (seeded noise realisations)",
         "config": {"workload": "noisy-drive freezing, 10-qubit Ising chain, d=1024, 4096 realisations, "
-                               "REDO b=100 P=2, one step = one time segment for all realisations, "
+                               "REDO b=100 P=2" + (" with every level composed once (process 3)" if args.cache else "") +
+                               ", one step = one time segment for all realisations, "
                                "magnetisation every step, re-projection every 64 steps",
                    "realisations": args.realisations, "d": 1024, "base": p.base, "digits": p.digits},
-        "grape_iters_per_s": None if gr is None else gr["iters_per_s"],
-        "grape": None if gr is None else {"workload": "10-qubit NMR chain d=1024, N=500, b=32 P=2, "
-                                                      "fidelity + adjoint gradient + update", **gr},
-        "expm_baseline": None,
+        "expm_baseline": None if ex is None else {
+            "value": ex["value"], "unit": "propagator steps/s", "ms_per_step": ex["ms_per_step"],
+            "steps": args.expm_steps, "method": "per-step exp(-i dt H_n), scaling-and-squaring Taylor "
+                                                 "(Paterson-Stockmeyer), same batched FP32 MFMA GEMM"},
+        "speedup_vs_expm": None if ex is None else f32["value"] / ex["value"],
+        "bf16x3": None if bf is None else {"value": bf["value"], "unit": "propagator steps/s",
+                                          "ms_per_step": bf["ms_per_step"],
+                                          "achieved_algorithmic_tflops": bf["achieved"],
+                                          "executed_bf16_tflops": 3 * bf["achieved"],
+                                          "frac_of_bf16_peak": 3 * bf["achieved"] / 2500.0,
+                                          "avg_launch_ms": bf["avg_launch_ms"],
+                                          "max_abs_dm_vs_fp32_last_step": float(np.abs(bf["mag_last"] - f32["mag_last"]).max())},
+        "grape_iters_per_s": None if rg is None else rg["iters_per_s"],
+        "grape": None if rg is None else {"workload": "10-qubit NMR chain d=1024, N=500, b=32 P=2, "
+                                                      "fidelity + adjoint gradient + update", **rg},
+        "grape_expm_iters_per_s": None if eg is None else eg["iters_per_s"],
+        "grape_speedup_vs_expm": None if (rg is None or eg is None) else rg["iters_per_s"] / eg["iters_per_s"],
         "table_build_s": fr["table_build_s"],
-        "roofline": {"bound": "mfma", "kernel": "cgemm_kernel<128,128,4M>",
-                     "achieved": fr["achieved"], "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": fr["achieved"] / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
-                     "flops_per_launch": fr["flops_per_launch"], "avg_launch_ms": fr["avg_launch_ms"],
-                     "launches": fr["gemm_launches"]},
+        "level_cache_build_s": fr["cache_build_s"],
+        "roofline": {"bound": "mfma", "kernel": "cgemm_kernel<128,128,4M> (batched complex GEMM, FP32)",
+                     "achieved": f32["achieved"], "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": f32["achieved"] / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
+                     "flops_per_launch": f32["flops_per_launch"], "avg_launch_ms": f32["avg_launch_ms"],
+                     "launches": f32["gemm_launches"]},
         "cpu_baseline": cpu,
-        "magnetisation_mean": {"first_step": fr["mag_first"], "last_step": fr["mag_last"]},
     }
     print(json.dumps(out), flush=True)
 

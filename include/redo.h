@@ -175,7 +175,8 @@ redo_status redo_compose_steps(redo_table table, int32_t precision, const float*
  *             row-list form: int32 [d][w] column indices and c64 [d][w] values
  *             of row a (pad with value 0); NULL/0 for none
  *   obs_out   double [B][N_max]: Tr(X_n M X_n^dag M) / Tr(M M) after step n
- *             (Sec. IV: <M>(t) for rho(0) = M), or NULL
+ *             (Sec. IV: <M>(t) for rho(0) = M), or NULL; at d >= 128 at most
+ *             16 entries per row (REDO_ERR_UNSUPPORTED otherwise)
  * Workspace: redo_workspace_bytes(table, REDO_OP_CHAIN, B, N_max).
  */
 redo_status redo_chain_propagator(redo_table table, int32_t precision, const float* u,
@@ -216,6 +217,39 @@ redo_status redo_grape_fidelity_grad(redo_table table, int32_t precision, const 
                                      const float* U_target, int32_t checkpoint_every,
                                      double* fidelity, double* overlap, float* grad,
                                      void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * The comparison point of the method (not REDO): the same chain with every
+ * step evaluated directly as U_n = exp[-i dt (H0 + H_n)] (Sec. III, Eq.
+ * propUn; H_n = sum_k u_x S_k + u_y S_k^y for phased channels, with S_k^y the
+ * x-generator rotated by exp(-i pi/2 G_k)), by scaling and squaring of a
+ * Taylor polynomial in Paterson-Stockmeyer form whose degree and squarings
+ * keep the truncation below the FP32 unit roundoff for a bound of
+ * ||dt (H0 + H_n)||_1 over the call (one device-to-host read per call).  Same
+ * arguments, layouts and batched GEMMs as redo_chain_propagator; d >= 128 only,
+ * FP32 (REDO_PREC_F32 or REDO_PREC_F32_3M).  Amplitudes are used unquantised.
+ * Workspace: redo_workspace_bytes(table, REDO_OP_EXPM_CHAIN, B, N_max).
+ */
+redo_status redo_expm_chain(redo_table table, int32_t precision, const float* u, const int32_t* n_steps,
+                            int32_t B, int32_t N_max, int32_t step_offset, int32_t reproject_every,
+                            const float* X0, float* U_total, const int32_t* obs_cols, const float* obs_vals,
+                            int32_t obs_width, double* obs_out, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
+/*
+ * GRAPE with the plain per-step exponential (the comparison point): the
+ * fidelity of the unquantised chain and the usual first-order gradient
+ * dU_n/du ~ -i dt H_k U_n (the GRAPE approximation of Khaneja et al., cited in
+ * Sec. III), through the same checkpointed forward and backward scans as
+ * redo_grape_fidelity_grad.  d >= 128, FP32.
+ * Workspace: redo_workspace_bytes(table, REDO_OP_EXPM_GRAPE, B, N_max)
+ * (default checkpoint interval).
+ */
+redo_status redo_expm_grape_fidelity_grad(redo_table table, int32_t precision, const float* u,
+                                          const int32_t* n_steps, int32_t B, int32_t N_max,
+                                          const float* U_target, int32_t checkpoint_every, double* fidelity,
+                                          double* overlap, float* grad, void* workspace,
+                                          size_t workspace_bytes, void* stream);
 
 /*
  * Waits for `stream`, then reports and clears the conditions latched by the

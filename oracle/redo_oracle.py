@@ -343,7 +343,10 @@ def fidelity_and_gradient(prob, b: int, model: str = "redo", table: Optional[Dis
       (default: the instance's own float amplitudes);
     model "redo": the same derivative at the quantised point (straight
       through), with every step built from REDO table products;
-    model "exact": the unsplit step exp[-i dt (H0 + H_n)].
+    model "exact": the unsplit step exp[-i dt (H0 + H_n)];
+    model "exact_first_order": the unsplit step with the usual first-order
+      GRAPE derivative dU_n/du ~ -i dt H_k U_n (the approximation of the
+      GRAPE paper the method cites in Sec. III).
 
     The derivative of each step comes from Daleckii-Krein Frechet derivatives
     of its exponential factors; it is contracted with the chain as
@@ -362,7 +365,7 @@ def fidelity_and_gradient(prob, b: int, model: str = "redo", table: Optional[Dis
         amp = (prob.u[b, :nb].astype(np.float64) if amps is None else np.asarray(amps, np.float64))
         if model == "split":
             steps = [step_split(S, g, amp[n], prob.dt, V) for n in range(nb)]
-        elif model == "exact":
+        elif model in ("exact", "exact_first_order"):
             steps = [step_exact(H0m, S, g, amp[n], prob.dt) for n in range(nb)]
         else:
             raise ValueError(model)
@@ -381,6 +384,15 @@ def fidelity_and_gradient(prob, b: int, model: str = "redo", table: Optional[Dis
 
 def _step_derivatives(model, S, g, amp_n, dt, V, H0m, K, d):
     """Yield (index, dU_n/dtheta) for every control parameter of one step."""
+    if model == "exact_first_order":
+        U = step_exact(H0m, S, g, amp_n, dt)
+        for k in range(K):
+            if g is not None:
+                yield (k, 0), -1j * dt * S[k] @ U
+                yield (k, 1), -1j * dt * y_generator(S[k], g[k]) @ U
+            else:
+                yield (k,), -1j * dt * S[k] @ U
+        return
     if model == "exact":
         H = np.array(H0m, dtype=np.complex128)
         gens = []

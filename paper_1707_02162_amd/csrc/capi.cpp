@@ -321,6 +321,37 @@ redo_status redo_build_table(const redo_table_desc* desc, const double* H0, cons
             }
         }
         REDO_HIP(round_z_to_c((long long)nn * K, Sd, t->S32, hs));
+        // plain-exponential baseline inputs: y-partners of phased generators, FP32 dense drifts
+        if (desc->phased) {
+            std::vector<float> hy(2 * nn * K);
+            for (int k = 0; k < K; ++k) {
+                const double* gk = hg.data() + (size_t)k * d;
+                for (size_t e = 0; e < nn; ++e) {
+                    const size_t i = e / d, j = e % d;
+                    // exp(-i pi/2 (g_i - g_j)) S_ij
+                    const double ang = -0.5 * M_PI * (gk[i] - gk[j]);
+                    const double c = std::cos(ang), sn = std::sin(ang);
+                    const double sr = hS[2 * (nn * k + e)], si = hS[2 * (nn * k + e) + 1];
+                    hy[2 * (nn * k + e)] = (float)(c * sr - sn * si);
+                    hy[2 * (nn * k + e) + 1] = (float)(c * si + sn * sr);
+                }
+            }
+            REDO_HIP(alloc((void**)&t->Sy32, sizeof(float2) * nn * K));
+            REDO_HIP(hipMemcpyAsync(t->Sy32, hy.data(), sizeof(float2) * nn * K, hipMemcpyHostToDevice, hs));
+            REDO_HIP(hipStreamSynchronize(hs));
+        }
+        if (!desc->drift_is_diag) {
+            REDO_HIP(alloc((void**)&t->H32, sizeof(float2) * nn * R));
+            REDO_HIP(round_z_to_c((long long)nn * R, reinterpret_cast<const double2*>(H0), t->H32, hs));
+        }
+        t->h_norm.assign(R, 0.0);
+        for (int r = 0; r < R; ++r) {
+            if (desc->drift_is_diag) {
+                for (int a = 0; a < d; ++a) t->h_norm[r] = std::max(t->h_norm[r], std::fabs(hH[(size_t)r * d + a]));
+            } else {
+                t->h_norm[r] = h_norm[r];
+            }
+        }
         if (desc->phased) REDO_HIP(hipMemcpyAsync(t->g64, g, sizeof(double) * d * K, hipMemcpyDeviceToDevice, hs));
         REDO_HIP(hipStreamSynchronize(hs));
     }
@@ -332,7 +363,7 @@ redo_status redo_build_table(const redo_table_desc* desc, const double* H0, cons
 redo_status redo_table_destroy(redo_table t) {
     if (!t) return REDO_OK;
     (void)hipDeviceSynchronize();
-    void* bufs[] = {t->T32, t->h64, t->V32, t->g64, t->S32, t->S64, t->flags, t->T16hi, t->T16lo, t->cache};
+    void* bufs[] = {t->T32, t->h64, t->V32, t->g64, t->S32, t->S64, t->Sy32, t->H32, t->flags, t->T16hi, t->T16lo, t->cache};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     delete t;
@@ -530,6 +561,7 @@ redo_status redo_chain_propagator(redo_table t, int32_t precision, const float* 
         return REDO_OK;
     }
     if (X_prefix) return fail(REDO_ERR_UNSUPPORTED, "X_prefix is provided for d <= 64 only");
+    if (obs_out && obs_width > 16) return fail(REDO_ERR_UNSUPPORTED, "observables with more than 16 entries per row");
     return large_chain(t, precision, u, n_steps, B, N_max, step_offset, reproject_every, X0, U_total, obs_cols,
                        obs_vals, obs_width, obs_out, workspace, workspace_bytes, hs);
 }
@@ -580,7 +612,42 @@ redo_status redo_grape_fidelity_grad(redo_table t, int32_t precision, const floa
         return REDO_OK;
     }
     return large_grape(t, precision, u, n_steps, B, N_max, U_target, (int)C, fidelity, overlap, grad, workspace,
-                       workspace_bytes, hs);
+                       workspace_bytes, hs, 0);
+}
+
+redo_status redo_expm_chain(redo_table t, int32_t precision, const float* u, const int32_t* n_steps, int32_t B,
+                            int32_t N_max, int32_t step_offset, int32_t reproject_every, const float* X0,
+                            float* U_total, const int32_t* obs_cols, const float* obs_vals, int32_t obs_width,
+                            double* obs_out, void* workspace, size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    if (B < 1 || N_max < 1) return fail(REDO_ERR_ARG, "B and N_max must be >= 1");
+    if (!u || !U_total) return fail(REDO_ERR_ARG, "u and U_total must not be NULL");
+    if (step_offset < 0 || reproject_every < 0) return fail(REDO_ERR_ARG, "step_offset, reproject_every must be >= 0");
+    if (precision < REDO_PREC_F32 || precision > REDO_PREC_BF16X3) return fail(REDO_ERR_ARG, "unknown precision");
+    if (obs_out && (!obs_cols || !obs_vals || obs_width < 1))
+        return fail(REDO_ERR_ARG, "obs_out needs obs_cols, obs_vals and obs_width >= 1");
+    if (small_dim(t->desc.d)) return fail(REDO_ERR_UNSUPPORTED, "the exponential baseline runs on the d >= 128 path");
+    if (obs_out && obs_width > 16) return fail(REDO_ERR_UNSUPPORTED, "observables with more than 16 entries per row");
+    return expm_chain(t, precision, u, n_steps, B, N_max, step_offset, reproject_every, X0, U_total, obs_cols, obs_vals,
+                      obs_width, obs_out, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+redo_status redo_expm_grape_fidelity_grad(redo_table t, int32_t precision, const float* u, const int32_t* n_steps,
+                                          int32_t B, int32_t N_max, const float* U_target, int32_t checkpoint_every,
+                                          double* fidelity, double* overlap, float* grad, void* workspace,
+                                          size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    if (B < 1 || N_max < 1) return fail(REDO_ERR_ARG, "B and N_max must be >= 1");
+    if (!u || !U_target || !fidelity || !grad) return fail(REDO_ERR_ARG, "u, U_target, fidelity, grad must not be NULL");
+    if (checkpoint_every < 0) return fail(REDO_ERR_ARG, "checkpoint_every must be >= 0");
+    if (precision < REDO_PREC_F32 || precision > REDO_PREC_BF16X3) return fail(REDO_ERR_ARG, "unknown precision");
+    if (small_dim(t->desc.d)) return fail(REDO_ERR_UNSUPPORTED, "the exponential baseline runs on the d >= 128 path");
+    if (precision == REDO_PREC_BF16X3) return fail(REDO_ERR_UNSUPPORTED, "the exponential baseline runs in FP32");
+    const long long C = checkpoint_every > 0 ? checkpoint_every : ceil_sqrt(N_max);
+    return large_grape(t, precision, u, n_steps, B, N_max, U_target, (int)C, fidelity, overlap, grad, workspace,
+                       workspace_bytes, static_cast<hipStream_t>(stream), 1);
 }
 
 redo_status redo_get_device_status(redo_table t, void* stream, int64_t* n_clamped) {

@@ -8,8 +8,8 @@
 //
 //     C = alpha * diag(rs) op(A) diag(ks) op(B) diag(cs) + beta I
 //
-// with op in {N, H}; A = NULL means the identity (a scaled copy), as does
-// B = NULL.  FP32 complex products use v_mfma_f32_32x32x2_f32 either as four
+// with op in {N, H}; A = NULL means the identity, as does B = NULL: such an
+// entry's tiles are scaled copies, done by the same launch.  FP32 complex products use v_mfma_f32_32x32x2_f32 either as four
 // real products (4M) or three (Gauss, 3M); FP32 accumulation throughout.
 // Tiles are staged through double-buffered LDS; tiles of one batch entry
 // are mapped to one XCD so its operands are shared in that XCD's L2.
@@ -110,6 +110,32 @@ __device__ inline void store_stage(const GemmDesc& g, int k0, const float4 (&ra)
     }
 }
 
+// An entry with an identity operand: this tile of C = alpha rs o op(X) o (ks or cs) + beta I, no products.
+__device__ inline void copy_tile(const GemmDesc& g, int d, int i0, int j0, int BM, int BN) {
+    for (int e = threadIdx.x; e < BM * BN; e += blockDim.x) {
+        const int i = i0 + e / BN, j = j0 + e % BN;
+        const long long ij = (long long)i * d + j, ji = (long long)j * d + i;
+        float2 v;
+        if (g.A == nullptr && g.B == nullptr) {
+            v = f2(i == j ? 1.f : 0.f, 0.f);
+            if (g.kscale && i == j) v = g.kscale[i];
+        } else if (g.A == nullptr) {
+            v = g.opB == 0 ? g.B[ij] : cconj(g.B[ji]);   // diag(ks) op(B)
+            if (g.kscale) v = cmul(g.kscale[i], v);
+        } else {
+            v = g.opA == 0 ? g.A[ij] : cconj(g.A[ji]);   // op(A) diag(ks)
+            if (g.kscale) v = cmul(v, g.kscale[j]);
+        }
+        if (g.rscale) v = cmul(g.rscale[i], v);
+        if (g.cscale) v = cmul(v, g.cscale[j]);
+        v.x *= g.alpha;
+        v.y *= g.alpha;
+        if (g.addend) v = cadd(v, g.addend[ij]);
+        if (i == j) v.x += g.beta_identity;
+        g.C[ij] = v;
+    }
+}
+
 // MODE 0: 4M, MODE 1: 3M (Gauss)
 template <int BM, int BN, int MODE>
 __global__ __launch_bounds__(256) void cgemm_kernel(int d, int batch, const GemmDesc* __restrict__ descs) {
@@ -123,8 +149,12 @@ __global__ __launch_bounds__(256) void cgemm_kernel(int d, int batch, const Gemm
     if (nb % NXCD == 0) bid = (bid % NXCD) * (nb / NXCD) + bid / NXCD;
     const int be = bid / ntile, tile = bid % ntile;
     const GemmDesc g = descs[be];
-    if (!g.active || g.A == nullptr || g.B == nullptr) return;  // identity operands: see scaled_copy_kernel
+    if (!g.active) return;
     const int i0 = (tile / tiles_n) * BM, j0 = (tile % tiles_n) * BN;
+    if (g.A == nullptr || g.B == nullptr) {
+        copy_tile(g, d, i0, j0, BM, BN);
+        return;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wi0 = (wave >> 1) * C::WM, wj0 = (wave & 1) * C::WN;
     constexpr int NACC = MODE == 0 ? 2 : 3;
@@ -219,38 +249,279 @@ __global__ __launch_bounds__(256) void cgemm_kernel(int d, int batch, const Gemm
                 if (g.cscale) v = cmul(v, g.cscale[j]);
                 v.x *= g.alpha;
                 v.y *= g.alpha;
+                if (g.addend) v = cadd(v, g.addend[(long long)i * d + j]);
                 if (i == j) v.x += g.beta_identity;
                 g.C[(long long)i * d + j] = v;
             }
 }
 
-// Entries with an identity operand: C = alpha * rs o op(X) o (ks or cs) + beta I, no products.
-__global__ __launch_bounds__(256) void scaled_copy_kernel(int d, const GemmDesc* __restrict__ descs) {
-    const GemmDesc g = descs[blockIdx.y];
-    if (!g.active || (g.A != nullptr && g.B != nullptr)) return;
-    const long long nn = (long long)d * d;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(e / d), j = (int)(e % d);
-        float2 v;
-        if (g.A == nullptr && g.B == nullptr) {
-            v = f2(i == j ? 1.f : 0.f, 0.f);
-            if (g.kscale && i == j) v = g.kscale[i];
-        } else if (g.A == nullptr) {
-            // diag(ks) op(B)
-            v = g.opB == 0 ? g.B[e] : cconj(g.B[(long long)j * d + i]);
-            if (g.kscale) v = cmul(g.kscale[i], v);
+// ---------------------------------------------------------------------------
+// Split-BF16 products: each FP32 operand x is carried as hi = RNE_bf16(x) and
+// lo = RNE_bf16(x - hi); a real product is hi*hi + hi*lo + lo*hi on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation (the lo*lo term, ~2^-16
+// relative, is dropped).  LDS holds four bf16 planes (re hi, re lo, im hi,
+// im lo) per operand, k contiguous, so a lane reads its 8 k-values of one
+// row in one 16-byte access.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline unsigned short bf16_rne_bits(float x) {
+    unsigned u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline void split_bf16(float x, unsigned short& h, unsigned short& l) {
+    h = bf16_rne_bits(x);
+    l = bf16_rne_bits(x - __uint_as_float(((unsigned)h) << 16));
+}
+
+template <int BM, int BN>
+struct BCfg {
+    static constexpr int THREADS = 256;
+    static constexpr int WM = BM / 2, WN = BN / 2;
+    static constexpr int FM = WM / 32, FN = WN / 32;
+    static constexpr int LDK = KT + 8;                  // bf16 per LDS row (16-byte aligned rows)
+    static constexpr int AV = BM * KT / 2 / THREADS;
+    static constexpr int BV = BN * KT / 2 / THREADS;
+    static constexpr int APLANE = BM * LDK, BPLANE = BN * LDK;
+};
+
+// plane p of element e: 0 re hi, 1 re lo, 2 im hi, 3 im lo
+template <int BM, int BN>
+__device__ inline void store_stage_bf(const GemmDesc& g, int k0, const float4 (&ra)[GCfg<BM, BN>::AV],
+                                      const float4 (&rb)[GCfg<BM, BN>::BV], unsigned short* As, unsigned short* Bs) {
+    using C = BCfg<BM, BN>;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int m = 0; m < C::AV; ++m) {
+        const int e = t + C::THREADS * m;
+        const float4 v = ra[m];
+        unsigned short h[4], l[4];
+        if (g.opA == 0) {
+            // elements (row, 2kq) and (row, 2kq + 1): pack pairs along k
+            const int row = e / (KT / 2), kq = e % (KT / 2);
+            split_bf16(v.x, h[0], l[0]);
+            split_bf16(v.y, h[1], l[1]);
+            split_bf16(v.z, h[2], l[2]);
+            split_bf16(v.w, h[3], l[3]);
+            const int o = row * C::LDK + 2 * kq;
+            *reinterpret_cast<unsigned*>(As + 0 * C::APLANE + o) = h[0] | ((unsigned)h[2] << 16);
+            *reinterpret_cast<unsigned*>(As + 1 * C::APLANE + o) = l[0] | ((unsigned)l[2] << 16);
+            *reinterpret_cast<unsigned*>(As + 2 * C::APLANE + o) = h[1] | ((unsigned)h[3] << 16);
+            *reinterpret_cast<unsigned*>(As + 3 * C::APLANE + o) = l[1] | ((unsigned)l[3] << 16);
         } else {
-            // op(A) diag(ks)
-            v = g.opA == 0 ? g.A[e] : cconj(g.A[(long long)j * d + i]);
-            if (g.kscale) v = cmul(v, g.kscale[j]);
+            // A^H: elements (2iq, kr) and (2iq + 1, kr), conjugated
+            const int kr = e / (BM / 2), iq = e % (BM / 2);
+            split_bf16(v.x, h[0], l[0]);
+            split_bf16(-v.y, h[1], l[1]);
+            split_bf16(v.z, h[2], l[2]);
+            split_bf16(-v.w, h[3], l[3]);
+            const int o0 = (2 * iq) * C::LDK + kr, o1 = (2 * iq + 1) * C::LDK + kr;
+            As[0 * C::APLANE + o0] = h[0];
+            As[1 * C::APLANE + o0] = l[0];
+            As[2 * C::APLANE + o0] = h[1];
+            As[3 * C::APLANE + o0] = l[1];
+            As[0 * C::APLANE + o1] = h[2];
+            As[1 * C::APLANE + o1] = l[2];
+            As[2 * C::APLANE + o1] = h[3];
+            As[3 * C::APLANE + o1] = l[3];
         }
-        if (g.rscale) v = cmul(g.rscale[i], v);
-        if (g.cscale) v = cmul(v, g.cscale[j]);
-        v.x *= g.alpha;
-        v.y *= g.alpha;
-        if (i == j) v.x += g.beta_identity;
-        g.C[e] = v;
     }
+#pragma unroll
+    for (int m = 0; m < C::BV; ++m) {
+        const int e = t + C::THREADS * m;
+        const float4 v = rb[m];
+        unsigned short h[4], l[4];
+        if (g.opB == 0) {
+            // elements (k = kr, j = 2jq) and (kr, 2jq + 1), stored at [j][k]
+            const int kr = e / (BN / 2), jq = e % (BN / 2);
+            float2 a = f2(v.x, v.y), b = f2(v.z, v.w);
+            if (g.kscale) {
+                const float2 sc = g.kscale[k0 + kr];
+                a = cmul(sc, a);
+                b = cmul(sc, b);
+            }
+            split_bf16(a.x, h[0], l[0]);
+            split_bf16(a.y, h[1], l[1]);
+            split_bf16(b.x, h[2], l[2]);
+            split_bf16(b.y, h[3], l[3]);
+            const int o0 = (2 * jq) * C::LDK + kr, o1 = (2 * jq + 1) * C::LDK + kr;
+            Bs[0 * C::BPLANE + o0] = h[0];
+            Bs[1 * C::BPLANE + o0] = l[0];
+            Bs[2 * C::BPLANE + o0] = h[1];
+            Bs[3 * C::BPLANE + o0] = l[1];
+            Bs[0 * C::BPLANE + o1] = h[2];
+            Bs[1 * C::BPLANE + o1] = l[2];
+            Bs[2 * C::BPLANE + o1] = h[3];
+            Bs[3 * C::BPLANE + o1] = l[3];
+        } else {
+            // B^H: elements (k = 2kq, j = row) and (2kq + 1, row), conjugated: pack along k
+            const int row = e / (KT / 2), kq = e % (KT / 2);
+            float2 a = f2(v.x, -v.y), b = f2(v.z, -v.w);
+            if (g.kscale) {
+                a = cmul(g.kscale[k0 + 2 * kq], a);
+                b = cmul(g.kscale[k0 + 2 * kq + 1], b);
+            }
+            split_bf16(a.x, h[0], l[0]);
+            split_bf16(a.y, h[1], l[1]);
+            split_bf16(b.x, h[2], l[2]);
+            split_bf16(b.y, h[3], l[3]);
+            const int o = row * C::LDK + 2 * kq;
+            *reinterpret_cast<unsigned*>(Bs + 0 * C::BPLANE + o) = h[0] | ((unsigned)h[2] << 16);
+            *reinterpret_cast<unsigned*>(Bs + 1 * C::BPLANE + o) = l[0] | ((unsigned)l[2] << 16);
+            *reinterpret_cast<unsigned*>(Bs + 2 * C::BPLANE + o) = h[1] | ((unsigned)h[3] << 16);
+            *reinterpret_cast<unsigned*>(Bs + 3 * C::BPLANE + o) = l[1] | ((unsigned)l[3] << 16);
+        }
+    }
+}
+
+__device__ inline bf16x8 neg8(bf16x8 x) {
+    uint4 u = __builtin_bit_cast(uint4, x);
+    u.x ^= 0x80008000u;
+    u.y ^= 0x80008000u;
+    u.z ^= 0x80008000u;
+    u.w ^= 0x80008000u;
+    return __builtin_bit_cast(bf16x8, u);
+}
+
+#define MF16(a, b, c) __builtin_amdgcn_mfma_f32_32x32x16_bf16((a), (b), (c), 0, 0, 0)
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void cgemm_bf16x3_kernel(int d, int batch, const GemmDesc* __restrict__ descs) {
+    using C = BCfg<BM, BN>;
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][4 * C::APLANE];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][4 * C::BPLANE];
+    const int tiles_n = d / BN;
+    const int ntile = (d / BM) * tiles_n;
+    int bid = blockIdx.x;
+    const int nb = gridDim.x;
+    if (nb % NXCD == 0) bid = (bid % NXCD) * (nb / NXCD) + bid / NXCD;
+    const int be = bid / ntile, tile = bid % ntile;
+    const GemmDesc g = descs[be];
+    if (!g.active) return;
+    const int i0 = (tile / tiles_n) * BM, j0 = (tile % tiles_n) * BN;
+    if (g.A == nullptr || g.B == nullptr) {
+        copy_tile(g, d, i0, j0, BM, BN);
+        return;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wi0 = (wave >> 1) * C::WM, wj0 = (wave & 1) * C::WN;
+    floatx16 accR[C::FM][C::FN], accI[C::FM][C::FN];
+#pragma unroll
+    for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < C::FN; ++jb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                accR[ib][jb][r] = 0.f;
+                accI[ib][jb][r] = 0.f;
+            }
+    float4 ra[C::AV], rb[C::BV];
+    load_stage<BM, BN>(g, d, i0, j0, 0, ra, rb);
+    store_stage_bf<BM, BN>(g, 0, ra, rb, As[0], Bs[0]);
+    __syncthreads();
+    const int nk = d / KT;
+    const int koff = 8 * (lane >> 5);
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load_stage<BM, BN>(g, d, i0, j0, (kt + 1) * KT, ra, rb);
+        bf16x8 a[C::FM][4], b[C::FN][4], na[C::FM][2];
+#pragma unroll
+        for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl)
+                a[ib][pl] = *reinterpret_cast<const bf16x8*>(As[buf] + pl * C::APLANE +
+                                                             (wi0 + ib * 32 + (lane & 31)) * C::LDK + koff);
+#pragma unroll
+        for (int jb = 0; jb < C::FN; ++jb)
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl)
+                b[jb][pl] = *reinterpret_cast<const bf16x8*>(Bs[buf] + pl * C::BPLANE +
+                                                             (wj0 + jb * 32 + (lane & 31)) * C::LDK + koff);
+#pragma unroll
+        for (int ib = 0; ib < C::FM; ++ib) {
+            na[ib][0] = neg8(a[ib][2]);
+            na[ib][1] = neg8(a[ib][3]);
+        }
+        // Cr += Ar Br - Ai Bi,  Ci += Ar Bi + Ai Br; each real product hi*hi + hi*lo + lo*hi
+#pragma unroll
+        for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < C::FN; ++jb) accR[ib][jb] = MF16(a[ib][0], b[jb][0], accR[ib][jb]);
+#pragma unroll
+        for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < C::FN; ++jb) accI[ib][jb] = MF16(a[ib][0], b[jb][2], accI[ib][jb]);
+#pragma unroll
+        for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < C::FN; ++jb) accR[ib][jb] = MF16(a[ib][0], b[jb][1], accR[ib][jb]);
+#pragma unroll
+        for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < C::FN; ++jb) accI[ib][jb] = MF16(a[ib][0], b[jb][3], accI[ib][jb]);
+#pragma unroll
+        for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < C::FN; ++jb) accR[ib][jb] = MF16(a[ib][1], b[jb][0], accR[ib][jb]);
+#pragma unroll
+        for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < C::FN; ++jb) accI[ib][jb] = MF16(a[ib][1], b[jb][2], accI[ib][jb]);
+#pragma unroll
+        for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < C::FN; ++jb) accR[ib][jb] = MF16(na[ib][0], b[jb][2], accR[ib][jb]);
+#pragma unroll
+        for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < C::FN; ++jb) accI[ib][jb] = MF16(a[ib][2], b[jb][0], accI[ib][jb]);
+#pragma unroll
+        for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < C::FN; ++jb) accR[ib][jb] = MF16(na[ib][0], b[jb][3], accR[ib][jb]);
+#pragma unroll
+        for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < C::FN; ++jb) accI[ib][jb] = MF16(a[ib][2], b[jb][1], accI[ib][jb]);
+#pragma unroll
+        for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < C::FN; ++jb) accR[ib][jb] = MF16(na[ib][1], b[jb][2], accR[ib][jb]);
+#pragma unroll
+        for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < C::FN; ++jb) accI[ib][jb] = MF16(a[ib][3], b[jb][0], accI[ib][jb]);
+        if (kt + 1 < nk) store_stage_bf<BM, BN>(g, (kt + 1) * KT, ra, rb, As[buf ^ 1], Bs[buf ^ 1]);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int ib = 0; ib < C::FM; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < C::FN; ++jb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = i0 + wi0 + ib * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                const int j = j0 + wj0 + jb * 32 + (lane & 31);
+                float2 v = f2(accR[ib][jb][r], accI[ib][jb][r]);
+                if (g.rscale) v = cmul(g.rscale[i], v);
+                if (g.cscale) v = cmul(v, g.cscale[j]);
+                v.x *= g.alpha;
+                v.y *= g.alpha;
+                if (g.addend) v = cadd(v, g.addend[(long long)i * d + j]);
+                if (i == j) v.x += g.beta_identity;
+                g.C[(long long)i * d + j] = v;
+            }
+}
+#undef MF16
+
+template <int BM, int BN>
+hipError_t launch_bf(int d, int batch, const GemmDesc* descs, hipStream_t st) {
+    const long long blocks = (long long)(d / BM) * (d / BN) * batch;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((cgemm_bf16x3_kernel<BM, BN>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
+    return hipGetLastError();
 }
 
 template <int BM, int BN, int MODE>
@@ -263,21 +534,17 @@ hipError_t launch(int d, int batch, const GemmDesc* descs, hipStream_t st) {
 
 }  // namespace
 
-// precision: 0 = 4M FP32, 1 = 3M FP32
+// precision: 0 = 4M FP32, 1 = 3M FP32, 2 = split BF16 (hi*hi + hi*lo + lo*hi)
 hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision, hipStream_t st) {
     if (d % 64 != 0 || batch < 1) return hipErrorInvalidValue;
-    // identity-operand entries first (they never alias the product entries' outputs in one launch)
-    // keep the copy grid under 2^30 threads whatever the batch
-    const int cblocks = (int)std::max<long long>(1, std::min<long long>(((long long)d * d + 255) / 256,
-                                                                        (1LL << 22) / batch));
-    hipLaunchKernelGGL(scaled_copy_kernel, dim3(cblocks, batch), dim3(256), 0, st, d, descs);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
     const bool big = d % 128 == 0 && (long long)(d / 128) * (d / 128) * batch >= 512;
     void* tok = nullptr;
     const bool prof = profiling_on();
     if (prof) profile_begin(st, &tok);
-    if (precision == 1)
+    if (precision == 2)
+        e = big ? launch_bf<128, 128>(d, batch, descs, st) : launch_bf<64, 64>(d, batch, descs, st);
+    else if (precision == 1)
         e = big ? launch<128, 128, 1>(d, batch, descs, st) : launch<64, 64, 1>(d, batch, descs, st);
     else
         e = big ? launch<128, 128, 0>(d, batch, descs, st) : launch<64, 64, 0>(d, batch, descs, st);

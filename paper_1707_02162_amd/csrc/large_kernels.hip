@@ -3,6 +3,8 @@
 // and 3; the drift and phase scalings of the split step, Sec. III), the
 // observable of Sec. IV, and the traces and gradient assembly of the GRAPE
 // adjoint (Sec. III).  All traces accumulate in FP64.
+#include <algorithm>
+
 #include "large_path.h"
 
 namespace redo {
@@ -194,26 +196,53 @@ __global__ void fill_descs_kernel(GemmDesc* descs, int count, const float2* A, l
     descs[b] = g;
 }
 
-// observable partial sums: block (rb, b) handles rows [16 rb, 16 rb + 16) of instance b
-constexpr int OBS_ROWS = 16;
-__global__ __launch_bounds__(256) void observable_partial_kernel(int d, const float2* __restrict__ X0,
+// observable partial sums: block (rb, b) handles rows [OBS_ROWS rb, OBS_ROWS (rb + 1)) of instance b.
+// The block's rows of X sit in LDS: (X M)_ac = sum_t X_a,cols[c][t] conj(vals[c][t]) gathers inside
+// them; (M X)_ac = sum_t vals[a][t] X_cols[a][t],c reads LDS for rows of the block and coalesced
+// rows from L2 otherwise.  Every thread owns columns c = tid, tid + 256, ...
+constexpr int OBS_ROWS_MAX = 8;
+constexpr int OBS_WMAX = 16;
+// rows per block: LDS holds OBS_ROWS rows of d complex values (<= 128 KiB)
+inline int obs_rows(int d) { return std::max(1, std::min(OBS_ROWS_MAX, 16384 / d)); }
+__global__ __launch_bounds__(256) void observable_partial_kernel(int d, int OBS_ROWS, const float2* __restrict__ X0,
                                                                  const float2* __restrict__ X1, const int* loc,
                                                                  long long xstride, const int* __restrict__ cols,
                                                                  const float2* __restrict__ vals, int w,
                                                                  const int* n_steps, int step, double* partial) {
-    const int b = blockIdx.y, rb = blockIdx.x;
-    const float2* Xb = ((loc && loc[b]) ? X1 : X0) + (long long)b * xstride;
+    extern __shared__ float2 rows[];   // [OBS_ROWS][d]
     __shared__ double red[256];
-    double acc = 0.0;
+    const int b = blockIdx.y, rb = blockIdx.x;
+    const int a0 = rb * OBS_ROWS;
+    const float2* Xb = ((loc && loc[b]) ? X1 : X0) + (long long)b * xstride;
     const bool active = n_steps ? step < n_steps[b] : true;
+    double acc = 0.0;
     if (active) {
-        for (int r = 0; r < OBS_ROWS; ++r) {
-            const int a = rb * OBS_ROWS + r;
-            for (int col = threadIdx.x; col < d; col += 256) {
+        for (int e = threadIdx.x; e < OBS_ROWS * d; e += 256) rows[e] = Xb[(long long)a0 * d + e];
+    }
+    __syncthreads();
+    if (active) {
+        for (int c = threadIdx.x; c < d; c += 256) {
+            int cc[OBS_WMAX];
+            float2 cv[OBS_WMAX];
+#pragma unroll
+            for (int t = 0; t < OBS_WMAX; ++t) {
+                if (t < w) {
+                    cc[t] = cols[c * w + t];
+                    cv[t] = cconj(vals[c * w + t]);
+                }
+            }
+            for (int r = 0; r < OBS_ROWS; ++r) {
+                const int a = a0 + r;
                 float2 xm = make_float2(0.f, 0.f), mx = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int t = 0; t < OBS_WMAX; ++t) {
+                    if (t < w) cfma(xm, rows[r * d + cc[t]], cv[t]);
+                }
                 for (int t = 0; t < w; ++t) {
-                    cfma(xm, Xb[(long long)a * d + cols[col * w + t]], cconj(vals[col * w + t]));
-                    cfma(mx, vals[a * w + t], Xb[(long long)cols[a * w + t] * d + col]);
+                    const int ra = cols[a * w + t];
+                    const float2 xv = (ra >= a0 && ra < a0 + OBS_ROWS) ? rows[(ra - a0) * d + c]
+                                                                       : Xb[(long long)ra * d + c];
+                    cfma(mx, vals[a * w + t], xv);
                 }
                 acc += (double)xm.x * mx.x + (double)xm.y * mx.y;
             }
@@ -221,8 +250,8 @@ __global__ __launch_bounds__(256) void observable_partial_kernel(int d, const fl
     }
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
     if (threadIdx.x == 0) partial[(long long)b * gridDim.x + rb] = red[0];
@@ -263,7 +292,8 @@ __global__ __launch_bounds__(256) void trace_partial_kernel(int d, int K, int ph
                                                             const double* __restrict__ g,
                                                             const int* __restrict__ codes,
                                                             const double* __restrict__ phi, long long code_stride,
-                                                            const int* n_steps, int step, double* partial) {
+                                                            const int* n_steps, int step, double* partial,
+                                                            int cartesian) {
     const int ntile = (d / TT) * (d / TT);
     const int tile = blockIdx.x, k = blockIdx.y, b = blockIdx.z;
     const int a0 = (tile / (d / TT)) * TT, b0 = (tile % (d / TT)) * TT;
@@ -278,7 +308,7 @@ __global__ __launch_bounds__(256) void trace_partial_kernel(int d, int K, int ph
         q = codes[(long long)b * code_stride + k];
         if (phased) ph = phi[(long long)b * code_stride + k];
     }
-    const bool origin = phased && q == 0;
+    const bool origin = phased && (q == 0 || cartesian);
     const double psi = phased && !origin ? ph : 0.0;
     for (int e = threadIdx.x; e < TT * TT; e += 256) {
         const int bb = e / TT, aa = e % TT;
@@ -357,7 +387,7 @@ __global__ void trace_final_kernel(int ntile, int K, const double* partial, doub
 //   tr[b][s][k][6]: traces of Y_{s+1}; dm[b][m][k][2]: Tr(G Y_m) for m = 0 .. N (from tr and D_0)
 __global__ void grad_kernel(int B, int N, int K, int phased, double eps, double dt, const int* codes,
                             const double* phi, const double* tr, const double* d0, const double2* overlap,
-                            const double* nu, const int* n_steps, float* grad) {
+                            const double* nu, const int* n_steps, float* grad, int cartesian) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long long)B * N * K) return;
     const int k = (int)(e % K);
@@ -380,7 +410,7 @@ __global__ void grad_kernel(int B, int N, int K, int phased, double eps, double 
         gp[0] = (float)(scale * dt * im_gc(t[0], t[1]));
         return;
     }
-    if (q == 0) {
+    if (q == 0 || cartesian) {
         gp[0] = (float)(scale * dt * im_gc(t[0], t[1]));
         gp[1] = (float)(scale * dt * im_gc(t[2], t[3]));
         return;
@@ -528,16 +558,22 @@ hipError_t fill_descs(GemmDesc* descs, int count, const float2* A, long long sA,
     return hipGetLastError();
 }
 
-size_t observable_partial_doubles(int d, int B) { return (size_t)B * (d / OBS_ROWS); }
+size_t observable_partial_doubles(int d, int B) { return (size_t)B * (d / obs_rows(d)); }
 
 hipError_t observable(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
                       const int* cols, const float2* vals, int w, const int* n_steps, int step, double* partial,
                       double* out, long long out_stride, hipStream_t st) {
-    hipLaunchKernelGGL(observable_partial_kernel, dim3(d / OBS_ROWS, B), dim3(256), 0, st, d, X0, X1, loc, xstride, cols,
-                       vals, w, n_steps, step, partial);
+    if (w > OBS_WMAX) return hipErrorInvalidValue;
+    const int R = obs_rows(d);
+    const size_t lds = sizeof(float2) * R * (size_t)d;
+    hipError_t e0 = hipFuncSetAttribute((const void*)observable_partial_kernel,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e0 != hipSuccess) return e0;
+    hipLaunchKernelGGL(observable_partial_kernel, dim3(d / R, B), dim3(256), lds, st, d, R, X0, X1, loc, xstride,
+                       cols, vals, w, n_steps, step, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(observable_final_kernel, dim3(B), dim3(256), 0, st, d / OBS_ROWS, partial, vals, d * w, n_steps,
+    hipLaunchKernelGGL(observable_final_kernel, dim3(B), dim3(256), 0, st, d / R, partial, vals, d * w, n_steps,
                        step, out, out_stride);
     return hipGetLastError();
 }
@@ -546,10 +582,10 @@ size_t trace_partial_doubles(int d, int B, int K) { return (size_t)B * K * (d / 
 
 hipError_t traces(int d, int B, int K, int phased, const float2* Y, long long ystride, const float2* S,
                   const double* g, const int* codes, const double* phi, long long code_stride, const int* n_steps,
-                  int step, double* partial, double* out, long long out_bstride, hipStream_t st) {
+                  int step, double* partial, double* out, long long out_bstride, int cartesian, hipStream_t st) {
     const int ntile = (d / TT) * (d / TT);
     hipLaunchKernelGGL(trace_partial_kernel, dim3(ntile, K, B), dim3(256), 0, st, d, K, phased, Y, ystride, S, g, codes,
-                       phi, code_stride, n_steps, step, partial);
+                       phi, code_stride, n_steps, step, partial, cartesian);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(trace_final_kernel, dim3(B, K), dim3(64), 0, st, ntile, K, partial, out, out_bstride);
@@ -558,10 +594,10 @@ hipError_t traces(int d, int B, int K, int phased, const float2* Y, long long ys
 
 hipError_t grad_assemble(int B, int N, int K, int phased, double eps, double dt, const int* codes, const double* phi,
                          const double* tr, const double* d0, const double2* overlap, const double* nu,
-                         const int* n_steps, float* grad, hipStream_t st) {
+                         const int* n_steps, float* grad, int cartesian, hipStream_t st) {
     const long long n = (long long)B * N * K;
     hipLaunchKernelGGL(grad_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, B, N, K, phased, eps, dt, codes,
-                       phi, tr, d0, overlap, nu, n_steps, grad);
+                       phi, tr, d0, overlap, nu, n_steps, grad, cartesian);
     return hipGetLastError();
 }
 

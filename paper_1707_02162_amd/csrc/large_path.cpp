@@ -113,14 +113,14 @@ struct GrapeWS {
     double2* ov;
     GemmDesc* descs;
     size_t bytes;
-    GrapeWS(const redo_table_s* t, int B, int N, int C, void* base) {
+    GrapeWS(const redo_table_s* t, int B, int N, int C, void* base, int expm = 0) {
         const int d = t->desc.d, K = t->desc.K;
         const size_t mat = (size_t)d * d;
         const int nck = (N + C - 1) / C;
         Carve c(base);
         Ustore = c.take<float2>(mat * B * N);
         ckpt = c.take<float2>(mat * B * nck);
-        seg = c.take<float2>(mat * B * C);
+        seg = c.take<float2>(mat * B * C * 2);
         Xa = c.take<float2>(mat * B);
         Xb = c.take<float2>(mat * B);
         La = c.take<float2>(mat * B);
@@ -131,10 +131,13 @@ struct GrapeWS {
         d0 = c.take<double>((size_t)B * K * 2);
         nu = c.take<double>(B);
         ov = c.take<double2>(B);
-        descs = c.take<GemmDesc>((size_t)2 * B);
+        descs = c.take<GemmDesc>((size_t)3 * B);
         comp_base = base ? c.base + c.used : nullptr;
         ComposeWS cw(t, (long long)B * N, nullptr);
-        c.used += cw.bytes;
+        c.used += expm ? std::max(cw.bytes, align_up(sizeof(int) * (size_t)B * N * t->desc.K) +
+                                                align_up(sizeof(double) * (size_t)B * N * t->desc.K) +
+                                                expm_compose_workspace_bytes(t))
+                       : cw.bytes;
         bytes = c.used;
     }
 };
@@ -146,12 +149,9 @@ long long ceil_sqrt_ll(long long n) {
     return std::max(1LL, c);
 }
 
-int gemm_prec(int precision) { return precision == REDO_PREC_F32_3M ? 1 : 0; }
+int gemm_prec(int precision) { return precision == REDO_PREC_F32_3M ? 1 : precision == REDO_PREC_BF16X3 ? 2 : 0; }
 
-redo_status check_precision(int precision) {
-    if (precision == REDO_PREC_BF16X3) return fail(REDO_ERR_UNSUPPORTED, "BF16 split precision is not built yet");
-    return REDO_OK;
-}
+redo_status check_precision(int) { return REDO_OK; }
 
 PlanLaunch plan_base(const redo_table_s* t) {
     PlanLaunch p{};
@@ -217,12 +217,18 @@ size_t large_workspace_bytes(const redo_table_s* t, int op, int B, int N) {
         case REDO_OP_COMPOSE: return ComposeWS(t, (long long)B * N, nullptr).bytes;
         case REDO_OP_CHAIN: return ChainWS(t, B, N, nullptr).bytes;
         case REDO_OP_GRAPE: return GrapeWS(t, B, N, (int)ceil_sqrt_ll(N), nullptr).bytes;
+        case REDO_OP_EXPM_CHAIN: return expm_chain_workspace_bytes(t, B, N);
+        case REDO_OP_EXPM_GRAPE: return GrapeWS(t, B, N, (int)ceil_sqrt_ll(N), nullptr, 1).bytes;
         default: return 0;
     }
 }
 
 size_t large_grape_workspace_bytes(const redo_table_s* t, int B, int N, int C) {
     return GrapeWS(t, B, N, C, nullptr).bytes;
+}
+
+size_t large_grape_workspace_bytes_mode(const redo_table_s* t, int B, int N, int C, int expm) {
+    return GrapeWS(t, B, N, C, nullptr, expm).bytes;
 }
 
 redo_status large_compose(redo_table_s* t, int precision, const float* u, int B, int N, float* U_out, void* workspace,
@@ -296,13 +302,13 @@ redo_status large_chain(redo_table_s* t, int precision, const float* u, const in
 
 redo_status large_grape(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N,
                         const float* U_target, int C, double* fidelity, double* overlap, float* grad, void* workspace,
-                        size_t workspace_bytes, hipStream_t st) {
+                        size_t workspace_bytes, hipStream_t st, int expm) {
     redo_status s = check_precision(precision);
     if (s != REDO_OK) return s;
-    GrapeWS need(t, B, N, C, nullptr);
+    GrapeWS need(t, B, N, C, nullptr, expm);
     if (!workspace || workspace_bytes < need.bytes)
         return fail(REDO_ERR_WORKSPACE, "GRAPE workspace needs " + std::to_string(need.bytes) + " bytes");
-    GrapeWS w(t, B, N, C, workspace);
+    GrapeWS w(t, B, N, C, workspace, expm);
     ComposeWS cw(t, (long long)B * N, w.comp_base);
     const int d = t->desc.d, K = t->desc.K;
     const long long mat = t->entry_elems;
@@ -310,26 +316,51 @@ redo_status large_grape(redo_table_s* t, int precision, const float* u, const in
     const float2* Uf = reinterpret_cast<const float2*>(U_target);
     // every step propagator once
     REDO_HIP(quantise_all(t, u, B, N, cw.codes, cw.phi, st));
-    s = compose_pairs(t, precision, (long long)B * N, N, cw, w.Ustore, st);
+    if (expm) {
+        // the codes and phases stay at the front of the compose area; the exponential scratch follows them
+        char* ex = static_cast<char*>(w.comp_base) + align_up(sizeof(int) * (size_t)B * N * K) +
+                   align_up(sizeof(double) * (size_t)B * N * K);
+        s = expm_compose_pairs(t, precision, (long long)B * N, N, u, w.Ustore, ex, st, nullptr);
+    } else {
+        s = compose_pairs(t, precision, (long long)B * N, N, cw, w.Ustore, st);
+    }
     if (s != REDO_OK) return s;
     REDO_HIP(frob_norms(d, B, Uf, w.nu, st));
-    // forward chain with checkpoints
-    REDO_HIP(fill_identity(d, B, w.Xa, mat, st));
-    float2* cur = w.Xa;
-    float2* nxt = w.Xb;
+    // forward chain with checkpoints X_0, X_C, ...; the states of the last segment go
+    // straight into a segment buffer so that segment needs no recomputation
     const int nck = (N + C - 1) / C;
+    const int last0 = (nck - 1) * C;
+    float2* segbuf[2] = {w.seg, w.seg + (size_t)B * C * mat};
+    int cur_seg = 0;
+    REDO_HIP(fill_identity(d, B, w.Xa, mat, st));
+    const float2* xin = w.Xa;
+    long long xin_stride = mat;
+    float2* pp[2] = {w.Xa, w.Xb};
+    int pp_i = 0;
     for (int n = 0; n < N; ++n) {
         if (n % C == 0) {
-            REDO_HIP(fill_descs(w.descs, B, nullptr, 0, 0, cur, mat, 0, w.ckpt + (size_t)(n / C) * mat, mat * nck, n_steps,
-                                n, 0, 1.f, 0.f, st));
+            REDO_HIP(fill_descs(w.descs, B, nullptr, 0, 0, xin, xin_stride, 0, w.ckpt + (size_t)(n / C) * mat, mat * nck,
+                                n_steps, n, 0, 1.f, 0.f, st));
             REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
         }
-        REDO_HIP(fill_descs(w.descs, B, w.Ustore + (size_t)n * mat, mat * N, 0, cur, mat, 0, nxt, mat, n_steps, n, 1, 1.f,
-                            0.f, st));
+        float2* out;
+        long long out_stride;
+        if (n >= last0) {
+            out = segbuf[cur_seg] + (size_t)(n - last0) * mat;
+            out_stride = mat * C;
+        } else {
+            pp_i ^= 1;
+            out = pp[pp_i];
+            out_stride = mat;
+        }
+        // inactive steps copy the state forward
+        REDO_HIP(fill_descs(w.descs, B, w.Ustore + (size_t)n * mat, mat * N, 0, xin, xin_stride, 0, out, out_stride,
+                            n_steps, n, 1, 1.f, 0.f, st));
         REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
-        std::swap(cur, nxt);
+        xin = out;
+        xin_stride = out_stride;
     }
-    REDO_HIP(unitary_fidelity(d, B, Uf, cur, w.ov, fidelity, st));
+    REDO_HIP(unitary_fidelity_strided(d, B, Uf, mat, xin, xin_stride, w.ov, fidelity, st));
     if (overlap) REDO_HIP(hipMemcpyAsync(overlap, w.ov, sizeof(double2) * B, hipMemcpyDeviceToDevice, st));
     // backward: L_N = U_f^dag
     float2* L = w.La;
@@ -339,30 +370,45 @@ redo_status large_grape(redo_table_s* t, int precision, const float* u, const in
     const long long code_stride = (long long)N * K;
     for (int sg = nck - 1; sg >= 0; --sg) {
         const int s0 = sg * C, s1 = std::min(N, s0 + C);
-        // recompute X_{s0+1} .. X_{s1} into the segment buffer
-        for (int n = s0; n < s1; ++n) {
-            const float2* src = n == s0 ? w.ckpt + (size_t)sg * mat : w.seg + (size_t)(n - s0 - 1) * mat;
-            const long long src_stride = n == s0 ? mat * nck : mat * C;
-            REDO_HIP(fill_descs(w.descs, B, w.Ustore + (size_t)n * mat, mat * N, 0, src, src_stride, 0,
-                                w.seg + (size_t)(n - s0) * mat, mat * C, n_steps, n, 0, 1.f, 0.f, st));
-            REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
-        }
+        const int p0 = (sg - 1) * C;               // the previous segment [p0, s0), full length C
+        float2* nseg = segbuf[cur_seg ^ 1];
+        int rec = 0;                                // recompute steps of the previous segment issued so far
+        auto rec_descs = [&](GemmDesc* dst) -> hipError_t {
+            const int n = p0 + rec;
+            const float2* src = rec == 0 ? w.ckpt + (size_t)(sg - 1) * mat : nseg + (size_t)(rec - 1) * mat;
+            const long long src_stride = rec == 0 ? mat * nck : mat * C;
+            return fill_descs(dst, B, w.Ustore + (size_t)n * mat, mat * N, 0, src, src_stride, 0,
+                              nseg + (size_t)rec * mat, mat * C, n_steps, n, 0, 1.f, 0.f, st);
+        };
         for (int sidx = s1 - 1; sidx >= s0; --sidx) {
-            // Y = X_{s+1} L  and  L' = L U_s in one launch
-            REDO_HIP(fill_descs(w.descs, B, w.seg + (size_t)(sidx - s0) * mat, mat * C, 0, L, mat, 0, w.Y, mat, n_steps,
-                                sidx, 0, 1.f, 0.f, st));
+            // Y = X_{s+1} L, L' = L U_s, and one recompute step of the previous segment, in one launch
+            REDO_HIP(fill_descs(w.descs, B, segbuf[cur_seg] + (size_t)(sidx - s0) * mat, mat * C, 0, L, mat, 0, w.Y, mat,
+                                n_steps, sidx, 0, 1.f, 0.f, st));
             REDO_HIP(fill_descs(w.descs + B, B, L, mat, 0, w.Ustore + (size_t)sidx * mat, mat * N, 0, Ln, mat, n_steps,
                                 sidx, 2, 1.f, 0.f, st));
-            REDO_HIP(cgemm_batched(d, 2 * B, w.descs, prec, st));
+            int batch = 2 * B;
+            if (sg > 0 && rec < C) {
+                REDO_HIP(rec_descs(w.descs + 2 * B));
+                ++rec;
+                batch = 3 * B;
+            }
+            REDO_HIP(cgemm_batched(d, batch, w.descs, prec, st));
             REDO_HIP(traces(d, B, K, t->desc.phased, w.Y, mat, t->S32, t->g64, cw.codes + (size_t)sidx * K,
                             t->desc.phased ? cw.phi + (size_t)sidx * K : nullptr, code_stride, n_steps, sidx, w.tpart,
-                            w.tr + (size_t)sidx * K * 6, code_stride * 6, st));
+                            w.tr + (size_t)sidx * K * 6, code_stride * 6, expm, st));
             std::swap(L, Ln);
         }
+        // the rest of the previous segment when this one was shorter
+        while (sg > 0 && rec < C) {
+            REDO_HIP(rec_descs(w.descs));
+            REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
+            ++rec;
+        }
+        cur_seg ^= 1;
     }
     REDO_HIP(d0_traces(d, B, K, t->desc.phased, L, mat, t->g64, w.d0, st));
     REDO_HIP(grad_assemble(B, N, K, t->desc.phased, t->desc.eps, t->desc.dt, cw.codes,
-                           t->desc.phased ? cw.phi : nullptr, w.tr, w.d0, w.ov, w.nu, n_steps, grad, st));
+                           t->desc.phased ? cw.phi : nullptr, w.tr, w.d0, w.ov, w.nu, n_steps, grad, expm, st));
     return REDO_OK;
 }
 

@@ -15,9 +15,20 @@ redo_status large_chain(redo_table_s* t, int precision, const float* u, const in
                         const float* obs_vals, int obs_width, double* obs_out, void* workspace,
                         size_t workspace_bytes, hipStream_t st);
 
+// expm = 1: the plain per-step exponential with the first-order GRAPE gradient (the comparison point)
 redo_status large_grape(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N_max,
                         const float* U_target, int checkpoint_every, double* fidelity, double* overlap, float* grad,
-                        void* workspace, size_t workspace_bytes, hipStream_t st);
+                        void* workspace, size_t workspace_bytes, hipStream_t st, int expm);
+size_t large_grape_workspace_bytes_mode(const redo_table_s* t, int B, int N_max, int checkpoint_every, int expm);
+
+// plain per-step exponential (expm_path.cpp)
+size_t expm_chain_workspace_bytes(const redo_table_s* t, int B, int N);
+size_t expm_compose_workspace_bytes(const redo_table_s* t);
+redo_status expm_compose_pairs(const redo_table_s* t, int precision, long long I, int N, const float* u, float2* U_out,
+                               void* ws, hipStream_t st, int* gemms_per_step);
+redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N, int step_offset,
+                       int reproject_every, const float* X0, float* U_total, const int* obs_cols, const float* obs_vals,
+                       int obs_width, double* obs_out, void* workspace, size_t workspace_bytes, hipStream_t st);
 
 // ---- kernels of large_kernels.hip
 struct PlanLaunch {
@@ -59,12 +70,13 @@ hipError_t reproject_descs(GemmDesc* descs, int count, int b0, float2* X0, float
 hipError_t gather_back(int d, int B, float2* X0, const float2* X1, long long xstride, const int* loc, hipStream_t st);
 hipError_t fill_int(int* p, int n, int v, hipStream_t st);
 size_t trace_partial_doubles(int d, int B, int K);
+// cartesian = 1: every step takes the traces of the x and y generators (first-order GRAPE gradient)
 hipError_t traces(int d, int B, int K, int phased, const float2* Y, long long ystride, const float2* S,
                   const double* g, const int* codes, const double* phi, long long code_stride, const int* n_steps,
-                  int step, double* partial, double* out, long long out_bstride, hipStream_t st);
+                  int step, double* partial, double* out, long long out_bstride, int cartesian, hipStream_t st);
 hipError_t grad_assemble(int B, int N, int K, int phased, double eps, double dt, const int* codes, const double* phi,
                          const double* tr, const double* d0, const double2* overlap, const double* nu,
-                         const int* n_steps, float* grad, hipStream_t st);
+                         const int* n_steps, float* grad, int cartesian, hipStream_t st);
 hipError_t d0_traces(int d, int B, int K, int phased, const float2* L, long long lstride, const double* g, double* d0,
                      hipStream_t st);
 hipError_t frob_norms(int d, int B, const float2* U, double* nu, hipStream_t st);

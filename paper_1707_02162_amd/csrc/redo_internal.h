@@ -102,6 +102,9 @@ struct redo_table_s {
     float2* V32 = nullptr;  // drift propagators: diag [n_drift][d] or dense [n_drift][d][d]
     double* g64 = nullptr;  // phase generators [K][d] (phased)
     float2* S32 = nullptr;  // generators rounded to FP32, [K][d][d]
+    float2* Sy32 = nullptr; // y-partners exp(-i pi/2 G) S exp(i pi/2 G) of phased generators, FP32 [K][d][d]
+    float2* H32 = nullptr;  // dense drifts rounded to FP32 [n_drift][d][d] (dense drift only)
+    std::vector<double> h_norm;  // ||H0_r||_1
     double2* S64 = nullptr; // generators as given (FP64), [K][d][d]: source of every FP64 rebuild
     std::vector<double> s_norm;  // ||S_k||_1
     redo::DeviceFlags* flags = nullptr;
@@ -180,6 +183,8 @@ hipError_t small_grape(const redo_table_s* t, const SmallGrapeArgs& a, hipStream
 // fidelity reduction, FP64
 hipError_t unitary_fidelity(int d, int B, const float2* Uf, const float2* U, double2* overlap,
                             double* fidelity, hipStream_t st);
+hipError_t unitary_fidelity_strided(int d, int B, const float2* Uf, long long sf, const float2* U, long long su,
+                                    double2* overlap, double* fidelity, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // large-d path (d >= 128, d % 64 == 0): batched complex GEMM on MFMA
@@ -197,6 +202,7 @@ struct GemmDesc {
     float beta_identity; // C += beta * I after scaling (Newton-Schulz), usually 0
     float alpha;         // C = alpha * (...)
     int pad;
+    const float2* addend;  // C += addend (d x d) after alpha, or null
 };
 static_assert(sizeof(GemmDesc) % 8 == 0, "desc alignment");
 

@@ -16,13 +16,13 @@ __global__ void quantise_kernel(long long count, int phased, double eps, double 
 }
 
 // one workgroup per instance; FP64 accumulation of Tr(U_f^dag U) and Tr(U_f^dag U_f)
-__global__ __launch_bounds__(256) void fidelity_kernel(long long nn, const float2* __restrict__ Uf,
-                                                       const float2* __restrict__ U, double2* overlap,
+__global__ __launch_bounds__(256) void fidelity_kernel(long long nn, const float2* __restrict__ Uf, long long sf,
+                                                       const float2* __restrict__ U, long long su, double2* overlap,
                                                        double* fidelity) {
     __shared__ double sr[256], si[256], sn[256];
     const long long b = blockIdx.x;
-    const float2* f = Uf + b * nn;
-    const float2* x = U + b * nn;
+    const float2* f = Uf + b * sf;
+    const float2* x = U + b * su;
     double ar = 0.0, ai = 0.0, an = 0.0;
     for (long long e = threadIdx.x; e < nn; e += 256) {
         const float2 a = f[e], c = x[e];
@@ -62,7 +62,14 @@ hipError_t quantise_all(const redo_table_s* t, const float* u, int B, int N, int
 
 hipError_t unitary_fidelity(int d, int B, const float2* Uf, const float2* U, double2* overlap, double* fidelity,
                             hipStream_t st) {
-    hipLaunchKernelGGL(fidelity_kernel, dim3(B), dim3(256), 0, st, (long long)d * d, Uf, U, overlap, fidelity);
+    const long long nn = (long long)d * d;
+    hipLaunchKernelGGL(fidelity_kernel, dim3(B), dim3(256), 0, st, nn, Uf, nn, U, nn, overlap, fidelity);
+    return hipGetLastError();
+}
+
+hipError_t unitary_fidelity_strided(int d, int B, const float2* Uf, long long sf, const float2* U, long long su,
+                                    double2* overlap, double* fidelity, hipStream_t st) {
+    hipLaunchKernelGGL(fidelity_kernel, dim3(B), dim3(256), 0, st, (long long)d * d, Uf, sf, U, su, overlap, fidelity);
     return hipGetLastError();
 }
 

@@ -37,6 +37,8 @@ _SIG = {
                                    ctypes.c_size_t, _P]),
     "redo_unitary_fidelity": (_I, [_I, _I, _P, _P, _P, _P, _P]),
     "redo_grape_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _I, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "redo_expm_chain": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P, _P, ctypes.c_size_t, _P]),
+    "redo_expm_grape_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _I, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "redo_get_device_status": (_I, [_P, _P, ctypes.POINTER(ctypes.c_int64)]),
     "redo_profile_enable": (_I, [_I]),
     "redo_profile_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _I]),
@@ -225,6 +227,41 @@ class RedoTable:
         _check(lib().redo_grape_fidelity_grad(self._h, precision, _ptr(ut), _ptr(ns), B, N, _ptr(Uf),
                                               checkpoint_every, _ptr(F), _ptr(ov), _ptr(grad), _ptr(ws),
                                               ws.numel(), _stream()))
+        return F, ov, grad
+
+    def expm_chain(self, u, n_steps=None, precision: int = PREC_F32, X0=None, reproject_every: int = 0,
+                   step_offset: int = 0, observable=None, out: Optional[torch.Tensor] = None):
+        """The plain per-step exponential chain (comparison point).  Returns (U_total, obs or None)."""
+        ut = self._u(u)
+        B, N = ut.shape[:2]
+        ns = None if n_steps is None else _dev(n_steps, torch.int32, self.device)
+        X0t = None if X0 is None else _dev(X0, torch.complex64, self.device)
+        U = out if out is not None else torch.empty((B, self.d, self.d), dtype=torch.complex64, device=self.device)
+        cols = vals = obs = None
+        w = 0
+        if observable is not None:
+            cols = _dev(observable[0], torch.int32, self.device)
+            vals = _dev(observable[1], torch.complex64, self.device)
+            w = cols.shape[1]
+            obs = torch.empty((B, N), dtype=torch.float64, device=self.device)
+        ws = self.workspace(OP_EXPM_CHAIN, B, N)
+        _check(lib().redo_expm_chain(self._h, precision, _ptr(ut), _ptr(ns), B, N, step_offset, reproject_every,
+                                     _ptr(X0t), _ptr(U), _ptr(cols), _ptr(vals), w, _ptr(obs), _ptr(ws), ws.numel(),
+                                     _stream()))
+        return U, obs
+
+    def expm_grape(self, u, U_target, n_steps=None, precision: int = PREC_F32):
+        """GRAPE objective and first-order gradient with the plain per-step exponential."""
+        ut = self._u(u)
+        B, N = ut.shape[:2]
+        ns = None if n_steps is None else _dev(n_steps, torch.int32, self.device)
+        Uf = _dev(U_target, torch.complex64, self.device)
+        F = torch.empty(B, dtype=torch.float64, device=self.device)
+        ov = torch.empty(B, dtype=torch.complex128, device=self.device)
+        grad = torch.empty_like(ut)
+        ws = self.workspace(OP_EXPM_GRAPE, B, N)
+        _check(lib().redo_expm_grape_fidelity_grad(self._h, precision, _ptr(ut), _ptr(ns), B, N, _ptr(Uf), 0,
+                                                   _ptr(F), _ptr(ov), _ptr(grad), _ptr(ws), ws.numel(), _stream()))
         return F, ov, grad
 
     def device_status(self):

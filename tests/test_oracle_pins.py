@@ -377,3 +377,18 @@ def test_t1_exact_step_is_rotation_about_total_field():
         want = _rot(np.linalg.norm(B) * p.dt, B / np.linalg.norm(B))
         got = O.step_exact(H0m, p.S, p.g, p.u[0, n].astype(float), p.dt)
         assert np.abs(got - want).max() < 1e-14
+
+
+def test_first_order_gradient_converges_to_exact_as_dt_shrinks():
+    """The first-order GRAPE derivative -i dt H_k U_n differs from the exact
+    derivative by O(dt^2) per step; at fixed total time its error relative to
+    the exact gradient falls linearly with dt."""
+    errs = []
+    for N in (10, 20, 40):
+        p = W.c1_two_spin(B=1, N=N)
+        p.dt = 5e-6 * 10 / N
+        _, _, ge = O.fidelity_and_gradient(p, 0, model="exact")
+        _, _, g1 = O.fidelity_and_gradient(p, 0, model="exact_first_order")
+        errs.append(np.linalg.norm(g1 - ge) / np.linalg.norm(ge))
+    assert errs[0] > errs[1] > errs[2]
+    assert 1.6 < errs[0] / errs[1] < 2.5 and 1.6 < errs[1] / errs[2] < 2.5
