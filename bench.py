@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--no-expm", action="store_true")
     ap.add_argument("--expm-steps", type=int, default=4)
     ap.add_argument("--chunk", type=int, default=4, help="time segments advanced per library call")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for hardware byte counters)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-cache", dest="cache", action="store_false",
                     help="apply one product per non-zero digit instead of the composed level of each amplitude")
@@ -199,6 +201,14 @@ def main():
     free, total = torch.cuda.mem_get_info()
     log(f"[bench] device {torch.cuda.get_device_name(0)}, {free / 2**30:.0f}/{total / 2**30:.0f} GiB free")
 
+    if args.calibrate:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] calibration copy: 3 x 1 GiB read + 1 GiB write")
     fr, p = bench_freezing(args, redo, W, torch)
     torch.cuda.empty_cache()
     gr = None if args.no_grape else bench_grape(args, redo, W, torch)

@@ -260,6 +260,52 @@ redo_status redo_expm_grape_fidelity_grad(redo_table table, int32_t precision, c
 redo_status redo_get_device_status(redo_table table, void* stream, int64_t* n_clamped);
 
 /*
+ * ---- Learned warm start (not part of the paper's method) ----
+ * A three-layer perceptron maps a target unitary to initial control amplitudes
+ * for a REDO-GRAPE run (plain REDO-GRAPE remains the fallback and the judge of
+ * its fidelity):  h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), y = tanh(W3 h2 + b3).
+ * Weights and activations enter the products as BF16 (round to nearest even),
+ * products accumulate in FP32 on the matrix cores.
+ */
+typedef struct {
+    int32_t sizes[4];          /* n_in, h1, h2, n_out */
+    const uint16_t* W[3];      /* BF16 weights of layer l, [sizes[l+1]][sizes[l]] row-major (device) */
+    const float* b[3];         /* FP32 biases of layer l, [sizes[l+1]] (device) */
+} redo_mlp;
+
+typedef struct {
+    float* W[3];               /* FP32 gradients, shaped like the weights (device) */
+    float* b[3];
+} redo_mlp_grads;
+
+/* Network input of a target: its 2 d^2 real entries [Re | Im] after removing the
+ * global phase (trace rotated onto the non-negative real axis).
+ *   U c64 [B][d][d] -> features float [B][2 d d] */
+redo_status redo_mlp_target_features(int32_t d, int32_t B, const float* U, float* features, void* stream);
+
+/* Forward pass of `batch` rows x [batch][sizes[0]]; acts receives h1, h2, y
+ * back to back: float [batch][sizes[1] + sizes[2] + sizes[3]]. */
+redo_status redo_mlp_forward(const redo_mlp* net, int32_t batch, const float* x, float* acts, void* stream);
+
+/* Mean squared error of y against target [batch][sizes[3]] (FP64, written to the
+ * device double *loss) and its gradients with respect to every weight and bias
+ * (forward included).  scratch: float [2][batch][max(sizes[1..3])]. */
+redo_status redo_mlp_loss_grad(const redo_mlp* net, int32_t batch, const float* x, const float* target,
+                               float* acts, float* scratch, const redo_mlp_grads* grads, double* loss,
+                               void* stream);
+
+/* One Adam step on n parameters (bias-corrected with step >= 1): descent when
+ * sign = 1, ascent when sign = -1, result clamped to [lo, hi]; when param_bf16
+ * is not NULL it receives the updated parameters rounded to BF16.  Also the
+ * amplitude update of REDO-GRAPE. */
+redo_status redo_adam_update(int64_t n, float* param, uint16_t* param_bf16, const float* grad, float* m,
+                             float* v, float lr, float beta1, float beta2, float eps, int32_t step, float sign,
+                             float lo, float hi, void* stream);
+
+/* Round n floats to BF16 (nearest even). */
+redo_status redo_to_bf16(int64_t n, const float* in, uint16_t* out, void* stream);
+
+/*
  * Launch timing (diagnostics, not part of the method).  While enabled, every
  * batched complex-GEMM launch of the large-d path is bracketed by HIP events
  * recorded on the stream it runs on.  redo_profile_read waits for those

@@ -13,6 +13,9 @@
 // real products (4M) or three (Gauss, 3M); FP32 accumulation throughout.
 // Tiles are staged through double-buffered LDS; tiles of one batch entry
 // are mapped to one XCD so its operands are shared in that XCD's L2.
+#include <cstdlib>
+#include <string>
+
 #include "redo_internal.h"
 
 namespace redo {
@@ -542,10 +545,16 @@ hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision,
     void* tok = nullptr;
     const bool prof = profiling_on();
     if (prof) profile_begin(st, &tok);
+    static const int tile_pref = [] {
+        const char* v = getenv("REDO_TILE");
+        return v && std::string(v) == "128x64" ? 1 : 0;
+    }();
     if (precision == 2)
         e = big ? launch_bf<128, 128>(d, batch, descs, st) : launch_bf<64, 64>(d, batch, descs, st);
     else if (precision == 1)
         e = big ? launch<128, 128, 1>(d, batch, descs, st) : launch<64, 64, 1>(d, batch, descs, st);
+    else if (big && tile_pref == 1)
+        e = launch<128, 64, 0>(d, batch, descs, st);
     else
         e = big ? launch<128, 128, 0>(d, batch, descs, st) : launch<64, 64, 0>(d, batch, descs, st);
     if (prof) profile_end(st, tok);

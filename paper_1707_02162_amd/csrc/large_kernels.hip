@@ -200,10 +200,10 @@ __global__ void fill_descs_kernel(GemmDesc* descs, int count, const float2* A, l
 // The block's rows of X sit in LDS: (X M)_ac = sum_t X_a,cols[c][t] conj(vals[c][t]) gathers inside
 // them; (M X)_ac = sum_t vals[a][t] X_cols[a][t],c reads LDS for rows of the block and coalesced
 // rows from L2 otherwise.  Every thread owns columns c = tid, tid + 256, ...
-constexpr int OBS_ROWS_MAX = 8;
+constexpr int OBS_ROWS_MAX = 4;
 constexpr int OBS_WMAX = 16;
 // rows per block: LDS holds OBS_ROWS rows of d complex values (<= 128 KiB)
-inline int obs_rows(int d) { return std::max(1, std::min(OBS_ROWS_MAX, 16384 / d)); }
+inline int obs_rows(int d) { return std::max(1, std::min(OBS_ROWS_MAX, 8192 / d)); }
 __global__ __launch_bounds__(256) void observable_partial_kernel(int d, int OBS_ROWS, const float2* __restrict__ X0,
                                                                  const float2* __restrict__ X1, const int* loc,
                                                                  long long xstride, const int* __restrict__ cols,
@@ -211,7 +211,13 @@ __global__ __launch_bounds__(256) void observable_partial_kernel(int d, int OBS_
                                                                  const int* n_steps, int step, double* partial) {
     extern __shared__ float2 rows[];   // [OBS_ROWS][d]
     __shared__ double red[256];
-    const int b = blockIdx.y, rb = blockIdx.x;
+    // all row blocks of one instance on one XCD (workgroups are dispatched round-robin over 8 XCDs),
+    // so the partner rows each block reads are shared in that XCD's L2
+    const int nrb = d / OBS_ROWS;
+    long long bid = blockIdx.x;
+    const long long nb = gridDim.x;
+    if (nb % 8 == 0) bid = (bid % 8) * (nb / 8) + bid / 8;
+    const int b = (int)(bid / nrb), rb = (int)(bid % nrb);
     const int a0 = rb * OBS_ROWS;
     const float2* Xb = ((loc && loc[b]) ? X1 : X0) + (long long)b * xstride;
     const bool active = n_steps ? step < n_steps[b] : true;
@@ -254,7 +260,7 @@ __global__ __launch_bounds__(256) void observable_partial_kernel(int d, int OBS_
         if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[(long long)b * gridDim.x + rb] = red[0];
+    if (threadIdx.x == 0) partial[(long long)b * nrb + rb] = red[0];
 }
 
 __global__ void observable_final_kernel(int nparts, const double* partial, const float2* vals, int nvals,
@@ -569,8 +575,8 @@ hipError_t observable(int d, int B, const float2* X0, const float2* X1, const in
     hipError_t e0 = hipFuncSetAttribute((const void*)observable_partial_kernel,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e0 != hipSuccess) return e0;
-    hipLaunchKernelGGL(observable_partial_kernel, dim3(d / R, B), dim3(256), lds, st, d, R, X0, X1, loc, xstride,
-                       cols, vals, w, n_steps, step, partial);
+    hipLaunchKernelGGL(observable_partial_kernel, dim3((unsigned)((long long)(d / R) * B)), dim3(256), lds, st, d, R, X0,
+                       X1, loc, xstride, cols, vals, w, n_steps, step, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(observable_final_kernel, dim3(B), dim3(256), 0, st, d / R, partial, vals, d * w, n_steps,

@@ -42,6 +42,12 @@ _SIG = {
     "redo_get_device_status": (_I, [_P, _P, ctypes.POINTER(ctypes.c_int64)]),
     "redo_profile_enable": (_I, [_I]),
     "redo_profile_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _I]),
+    "redo_mlp_target_features": (_I, [_I, _I, _P, _P, _P]),
+    "redo_mlp_forward": (_I, [_P, _I, _P, _P, _P]),
+    "redo_mlp_loss_grad": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P]),
+    "redo_adam_update": (_I, [ctypes.c_int64, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
+    "redo_to_bf16": (_I, [ctypes.c_int64, _P, _P, _P]),
     "redo_status_string": (ctypes.c_char_p, [_I]),
     "redo_last_error": (ctypes.c_char_p, []),
 }
@@ -49,6 +55,14 @@ _SIG = {
 
 def exported_symbols():
     return list(_SIG)
+
+
+class _Mlp(ctypes.Structure):
+    _fields_ = [("sizes", _I * 4), ("W", _P * 3), ("b", _P * 3)]
+
+
+class _MlpGrads(ctypes.Structure):
+    _fields_ = [("W", _P * 3), ("b", _P * 3)]
 
 
 class _Desc(ctypes.Structure):

@@ -1,0 +1,219 @@
+"""Learned warm start for REDO-GRAPE (spec extension; not in the paper).
+
+A three-layer perceptron (tanh, BF16 weights, FP32 accumulation) maps the
+2 d^2 real entries of a global-phase-free target unitary to the initial
+control amplitudes of a REDO-GRAPE run.  It is trained on pulses that
+REDO-GRAPE itself optimised.  Plain REDO-GRAPE stays both the fallback (a
+random start is used whenever it starts better than the network's proposal)
+and the judge: every reported fidelity is the library's REDO fidelity.
+
+Every arithmetic step runs in libredo.so: the network's forward and backward
+passes, its Adam updates, the target features, the REDO chains and the GRAPE
+gradients and amplitude updates.  This module only sequences the calls.
+
+    python -m paper_1707_02162_amd.warmstart --train 20000 --test 256
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import sys
+import time
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import redo as R
+from . import workloads as W
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def adam_(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float,
+          sign: float = 1.0, lo: float = -3.0e38, hi: float = 3.0e38, bf16: Optional[torch.Tensor] = None,
+          beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+    R._check(R.lib().redo_adam_update(param.numel(), _p(param), _p(bf16), _p(grad), _p(m), _p(v), lr, beta1, beta2,
+                                      eps, step, sign, lo, hi, R._stream()))
+
+
+def target_features(U: torch.Tensor) -> torch.Tensor:
+    B, d = U.shape[0], U.shape[-1]
+    Uc = U.to(torch.complex64).contiguous()
+    out = torch.empty((B, 2 * d * d), dtype=torch.float32, device=U.device)
+    R._check(R.lib().redo_mlp_target_features(d, B, _p(Uc), _p(out), R._stream()))
+    return out
+
+
+class WarmStartMLP:
+    """FP32 master weights with BF16 copies for the products; Adam state."""
+
+    def __init__(self, sizes, device="cuda", seed: int = 0):
+        self.sizes = list(sizes)
+        gen = np.random.default_rng(seed)
+        self.W, self.b, self.Wh = [], [], []
+        for i, o in zip(self.sizes[:-1], self.sizes[1:]):
+            lim = math.sqrt(6.0 / (i + o))
+            Wl = torch.tensor(gen.uniform(-lim, lim, (o, i)), dtype=torch.float32, device=device)
+            self.W.append(Wl)
+            self.b.append(torch.zeros(o, dtype=torch.float32, device=device))
+            self.Wh.append(Wl.to(torch.bfloat16).contiguous())
+        self.gW = [torch.zeros_like(w) for w in self.W]
+        self.gb = [torch.zeros_like(b) for b in self.b]
+        self.mW = [torch.zeros_like(w) for w in self.W]
+        self.vW = [torch.zeros_like(w) for w in self.W]
+        self.mb = [torch.zeros_like(b) for b in self.b]
+        self.vb = [torch.zeros_like(b) for b in self.b]
+        self.step = 0
+        self.device = device
+        self._loss = torch.zeros(1, dtype=torch.float64, device=device)
+
+    def _net(self):
+        n = R._Mlp()
+        for l in range(4):
+            n.sizes[l] = self.sizes[l]
+        for l in range(3):
+            n.W[l] = self.Wh[l].data_ptr()
+            n.b[l] = self.b[l].data_ptr()
+        return n
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        B = x.shape[0]
+        acts = torch.empty(B * sum(self.sizes[1:]), dtype=torch.float32, device=self.device)
+        net = self._net()
+        R._check(R.lib().redo_mlp_forward(ctypes.byref(net), B, _p(x.contiguous()), _p(acts), R._stream()))
+        return acts[B * (self.sizes[1] + self.sizes[2]):].view(B, self.sizes[3])
+
+    def loss_and_grads(self, x: torch.Tensor, target: torch.Tensor) -> float:
+        B = x.shape[0]
+        acts = torch.empty(B * sum(self.sizes[1:]), dtype=torch.float32, device=self.device)
+        scratch = torch.empty(2 * B * max(self.sizes[1:]), dtype=torch.float32, device=self.device)
+        g = R._MlpGrads()
+        for l in range(3):
+            g.W[l] = self.gW[l].data_ptr()
+            g.b[l] = self.gb[l].data_ptr()
+        net = self._net()
+        R._check(R.lib().redo_mlp_loss_grad(ctypes.byref(net), B, _p(x.contiguous()), _p(target.contiguous()),
+                                            _p(acts), _p(scratch), ctypes.byref(g), _p(self._loss), R._stream()))
+        return self._loss
+
+    def train_step(self, x, target, lr: float):
+        loss = self.loss_and_grads(x, target)
+        self.step += 1
+        for l in range(3):
+            adam_(self.W[l], self.gW[l], self.mW[l], self.vW[l], self.step, lr, bf16=self.Wh[l])
+            adam_(self.b[l], self.gb[l], self.mb[l], self.vb[l], self.step, lr)
+        return loss
+
+
+def grape(table: R.RedoTable, u0: torch.Tensor, Uf: torch.Tensor, u_max: float, iters: int, lr: float,
+          goal: float = 1e-4, history: bool = False):
+    """Batched REDO-GRAPE: Adam ascent on F, amplitudes clamped to [-u_max, u_max].
+    Returns (u, F, iterations to reach infidelity <= goal (or -1))."""
+    u = u0.clone().contiguous()
+    m = torch.zeros_like(u)
+    v = torch.zeros_like(u)
+    B = u.shape[0]
+    reached = torch.full((B,), -1, dtype=torch.int64, device=u.device)
+    F = None
+    hist = []
+    for it in range(iters + 1):
+        F, _, g = table.grape(u, Uf)
+        ok = (1.0 - F) <= goal
+        reached = torch.where((reached < 0) & ok, torch.full_like(reached, it), reached)
+        if history:
+            hist.append(F.clone())
+        if it == iters or bool(ok.all()):
+            break
+        adam_(u, g, m, v, it + 1, lr, sign=-1.0, lo=-u_max, hi=u_max)
+    return u, F, reached, hist
+
+
+def reachable_targets(table: R.RedoTable, p: W.Problem, config_id: int, B: int, start: int = 0) -> torch.Tensor:
+    """Targets reached by smooth seeded pulses (so that a solution exists)."""
+    gen = W.nmr_chain(4, B, p.N, p.dt, p.base, p.digits, config_id, species=[[0, 1], [2, 3]],
+                      targets=False)
+    U, _, _ = table.chain(torch.tensor(gen.u, device="cuda"))
+    return U
+
+
+def random_starts(p: W.Problem, config_id: int, B: int) -> torch.Tensor:
+    st = W.nmr_chain(4, B, p.N, p.dt, p.base, p.digits, config_id, species=[[0, 1], [2, 3]], targets=False)
+    return torch.tensor(st.u, device="cuda")
+
+
+def experiment(n_train: int, n_test: int, N: int = 500, grape_iters: int = 400, lr_grape: float = 300.0,
+               epochs: int = 40, batch: int = 256, lr_net: float = 1e-3, width: int = 512, goal: float = 1e-4,
+               log=print):
+    """C5-shaped run: d = 16, two species with collective X/Y, N steps of 2 us."""
+    p = W.c5_four_qubit(B=1, N=N)
+    table = R.RedoTable.from_problem(p)
+    table.cache_levels()
+    u_max = float(p.u_scale)
+    t0 = time.time()
+    # training set: reachable targets, REDO-GRAPE from random smooth starts
+    Uf = reachable_targets(table, p, 501, n_train)
+    u0 = random_starts(p, 502, n_train)
+    u_opt, F_opt, it_opt, _ = grape(table, u0, Uf, u_max, grape_iters, lr_grape, goal=goal)
+    keep = (1.0 - F_opt) <= goal
+    log(f"[warmstart] dataset: {int(keep.sum())}/{n_train} optimised to {goal:g} in {time.time() - t0:.1f}s")
+    X = target_features(Uf)[keep]
+    Y = (u_opt[keep] / u_max).reshape(int(keep.sum()), -1)
+    sizes = [X.shape[1], width, width, Y.shape[1]]
+    net = WarmStartMLP(sizes, seed=503)
+    nb = max(1, X.shape[0] // batch)
+    losses = []
+    for ep in range(epochs):
+        perm = torch.randperm(X.shape[0], device="cuda", generator=torch.Generator(device="cuda").manual_seed(ep))
+        tot = 0.0
+        for i in range(nb):
+            idx = perm[i * batch:(i + 1) * batch]
+            tot += float(net.train_step(X[idx], Y[idx], lr_net).item())
+        losses.append(tot / nb)
+    log(f"[warmstart] trained {epochs} epochs, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    # held-out targets: network start (with fallback) vs random start
+    Ut = reachable_targets(table, p, 601, n_test)
+    ur = random_starts(p, 602, n_test)
+    un = (net.forward(target_features(Ut)) * u_max).reshape(ur.shape).contiguous()
+    Fr0, _, _ = table.grape(ur, Ut)
+    Fn0, _, _ = table.grape(un, Ut)
+    use_net = Fn0 >= Fr0                       # fallback to the random start when it starts better
+    us = torch.where(use_net.view(-1, 1, 1, 1), un, ur)
+    _, Fr, itr, _ = grape(table, ur, Ut, u_max, grape_iters, lr_grape, goal=goal)
+    _, Fs, its, _ = grape(table, us, Ut, u_max, grape_iters, lr_grape, goal=goal)
+    conv_r = itr >= 0
+    conv_s = its >= 0
+    res = dict(
+        n_train=n_train, n_train_converged=int(keep.sum()), n_test=n_test, N=N, epochs=epochs, goal=goal,
+        loss_first=losses[0], loss_last=losses[-1],
+        start_infidelity_random_median=float((1 - Fr0).median()), start_infidelity_net_median=float((1 - Fn0).median()),
+        net_start_used=int(use_net.sum()),
+        converged_random=int(conv_r.sum()), converged_warm=int(conv_s.sum()),
+        iters_random_median=float(itr[conv_r].double().median()) if conv_r.any() else None,
+        iters_warm_median=float(its[conv_s].double().median()) if conv_s.any() else None,
+        final_infidelity_random_median=float((1 - Fr).median()), final_infidelity_warm_median=float((1 - Fs).median()),
+        seconds=time.time() - t0,
+    )
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=20000)
+    ap.add_argument("--test", type=int, default=256)
+    ap.add_argument("--N", type=int, default=500)
+    ap.add_argument("--grape-iters", type=int, default=400)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--goal", type=float, default=1e-4)
+    a = ap.parse_args()
+    res = experiment(a.train, a.test, N=a.N, grape_iters=a.grape_iters, epochs=a.epochs, goal=a.goal,
+                     log=lambda s: print(s, file=sys.stderr, flush=True))
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -392,3 +392,34 @@ def test_first_order_gradient_converges_to_exact_as_dt_shrinks():
         errs.append(np.linalg.norm(g1 - ge) / np.linalg.norm(ge))
     assert errs[0] > errs[1] > errs[2]
     assert 1.6 < errs[0] / errs[1] < 2.5 and 1.6 < errs[1] / errs[2] < 2.5
+
+
+def test_mlp_oracle_gradients_vs_central_differences():
+    from oracle import mlp_oracle as M
+    rng = np.random.default_rng(13)
+    sizes = [6, 5, 4, 3]
+    params = [(rng.normal(size=(o, i)) * 0.7, rng.normal(size=o) * 0.1) for i, o in zip(sizes[:-1], sizes[1:])]
+    x = rng.normal(size=(7, sizes[0]))
+    t = rng.uniform(-0.9, 0.9, size=(7, sizes[-1]))
+    loss, grads, _ = M.mlp_loss_and_grads(params, x, t)
+    h = 1e-6
+    for l, (W, b) in enumerate(params):
+        for arr, g in ((W, grads[l][0]), (b, grads[l][1])):
+            fd = np.zeros_like(arr)
+            for idx in np.ndindex(*arr.shape):
+                old = arr[idx]
+                arr[idx] = old + h
+                lp = M.mlp_loss_and_grads(params, x, t)[0]
+                arr[idx] = old - h
+                lm = M.mlp_loss_and_grads(params, x, t)[0]
+                arr[idx] = old
+                fd[idx] = (lp - lm) / (2 * h)
+            assert np.linalg.norm(g - fd) <= 1e-7 * max(np.linalg.norm(fd), 1e-12)
+
+
+def test_canonical_features_remove_global_phase():
+    from oracle import mlp_oracle as M
+    U = W.haar_unitary(4, W.rng(5, 2, 0))
+    a = M.canonical_target_features(U)
+    b = M.canonical_target_features(np.exp(1.3j) * U)
+    assert a.shape == (32,) and np.abs(a - b).max() < 1e-12
