@@ -226,8 +226,9 @@ redo_status redo_grape_fidelity_grad(redo_table table, int32_t precision, const 
  * Taylor polynomial in Paterson-Stockmeyer form whose degree and squarings
  * keep the truncation below the FP32 unit roundoff for a bound of
  * ||dt (H0 + H_n)||_1 over the call (one device-to-host read per call).  Same
- * arguments, layouts and batched GEMMs as redo_chain_propagator; d >= 128 only,
- * FP32 (REDO_PREC_F32 or REDO_PREC_F32_3M).  Amplitudes are used unquantised.
+ * arguments, layouts and batched GEMMs as redo_chain_propagator; d a multiple
+ * of 64 (so also d = 64, on the batched GEMMs), FP32 (REDO_PREC_F32 or
+ * REDO_PREC_F32_3M).  Amplitudes are used unquantised.
  * Workspace: redo_workspace_bytes(table, REDO_OP_EXPM_CHAIN, B, N_max).
  */
 redo_status redo_expm_chain(redo_table table, int32_t precision, const float* u, const int32_t* n_steps,
@@ -241,7 +242,7 @@ redo_status redo_expm_chain(redo_table table, int32_t precision, const float* u,
  * fidelity of the unquantised chain and the usual first-order gradient
  * dU_n/du ~ -i dt H_k U_n (the GRAPE approximation of Khaneja et al., cited in
  * Sec. III), through the same checkpointed forward and backward scans as
- * redo_grape_fidelity_grad.  d >= 128, FP32.
+ * redo_grape_fidelity_grad.  d a multiple of 64, FP32.
  * Workspace: redo_workspace_bytes(table, REDO_OP_EXPM_GRAPE, B, N_max)
  * (default checkpoint interval).
  */

@@ -466,6 +466,7 @@ size_t redo_workspace_bytes(redo_table t, int32_t op, int32_t B, int32_t N_max) 
     if (!t || B < 1 || N_max < 1) return 0;
     const int d = t->desc.d;
     const size_t mat = sizeof(float2) * (size_t)d * d;
+    if ((op == REDO_OP_EXPM_CHAIN || op == REDO_OP_EXPM_GRAPE) && d % 64 == 0) return large_workspace_bytes(t, op, B, N_max);
     if (small_dim(d)) {
         switch (op) {
             case REDO_OP_COMPOSE:
@@ -627,7 +628,7 @@ redo_status redo_expm_chain(redo_table t, int32_t precision, const float* u, con
     if (precision < REDO_PREC_F32 || precision > REDO_PREC_BF16X3) return fail(REDO_ERR_ARG, "unknown precision");
     if (obs_out && (!obs_cols || !obs_vals || obs_width < 1))
         return fail(REDO_ERR_ARG, "obs_out needs obs_cols, obs_vals and obs_width >= 1");
-    if (small_dim(t->desc.d)) return fail(REDO_ERR_UNSUPPORTED, "the exponential baseline runs on the d >= 128 path");
+    if (t->desc.d % 64 != 0) return fail(REDO_ERR_UNSUPPORTED, "the exponential baseline needs d a multiple of 64");
     if (obs_out && obs_width > 16) return fail(REDO_ERR_UNSUPPORTED, "observables with more than 16 entries per row");
     return expm_chain(t, precision, u, n_steps, B, N_max, step_offset, reproject_every, X0, U_total, obs_cols, obs_vals,
                       obs_width, obs_out, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
@@ -643,7 +644,7 @@ redo_status redo_expm_grape_fidelity_grad(redo_table t, int32_t precision, const
     if (!u || !U_target || !fidelity || !grad) return fail(REDO_ERR_ARG, "u, U_target, fidelity, grad must not be NULL");
     if (checkpoint_every < 0) return fail(REDO_ERR_ARG, "checkpoint_every must be >= 0");
     if (precision < REDO_PREC_F32 || precision > REDO_PREC_BF16X3) return fail(REDO_ERR_ARG, "unknown precision");
-    if (small_dim(t->desc.d)) return fail(REDO_ERR_UNSUPPORTED, "the exponential baseline runs on the d >= 128 path");
+    if (t->desc.d % 64 != 0) return fail(REDO_ERR_UNSUPPORTED, "the exponential baseline needs d a multiple of 64");
     if (precision == REDO_PREC_BF16X3) return fail(REDO_ERR_UNSUPPORTED, "the exponential baseline runs in FP32");
     const long long C = checkpoint_every > 0 ? checkpoint_every : ceil_sqrt(N_max);
     return large_grape(t, precision, u, n_steps, B, N_max, U_target, (int)C, fidelity, overlap, grad, workspace,

@@ -541,22 +541,17 @@ hipError_t launch(int d, int batch, const GemmDesc* descs, hipStream_t st) {
 hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision, hipStream_t st) {
     if (d % 64 != 0 || batch < 1) return hipErrorInvalidValue;
     hipError_t e = hipSuccess;
-    const bool big = d % 128 == 0 && (long long)(d / 128) * (d / 128) * batch >= 512;
+    const bool big = d % 128 == 0 && (long long)(d / 128) * (d / 64) * batch >= 512;
     void* tok = nullptr;
     const bool prof = profiling_on();
     if (prof) profile_begin(st, &tok);
-    static const int tile_pref = [] {
-        const char* v = getenv("REDO_TILE");
-        return v && std::string(v) == "128x64" ? 1 : 0;
-    }();
+    // 128x64 tiles keep three workgroups per CU (accumulators 64 registers per lane)
     if (precision == 2)
         e = big ? launch_bf<128, 128>(d, batch, descs, st) : launch_bf<64, 64>(d, batch, descs, st);
     else if (precision == 1)
         e = big ? launch<128, 128, 1>(d, batch, descs, st) : launch<64, 64, 1>(d, batch, descs, st);
-    else if (big && tile_pref == 1)
-        e = launch<128, 64, 0>(d, batch, descs, st);
     else
-        e = big ? launch<128, 128, 0>(d, batch, descs, st) : launch<64, 64, 0>(d, batch, descs, st);
+        e = big ? launch<128, 64, 0>(d, batch, descs, st) : launch<64, 64, 0>(d, batch, descs, st);
     if (prof) profile_end(st, tok);
     return e;
 }

@@ -158,7 +158,8 @@ int ps_r_max(int d) { return 5; }
 size_t expm_chain_workspace_bytes(const redo_table_s* t, int B, int N) {
     const int d = t->desc.d;
     const size_t mat = sizeof(float2) * (size_t)d * d;
-    return align_up(mat * B) + align_up(mat * std::min(B, 256)) + align_up(sizeof(double) * observable_partial_doubles(d, B)) +
+    return align_up(mat * B) + align_up(mat * std::min(B, 256)) + align_up(mat * std::min(B, OBS_CHUNK)) +
+           align_up(sizeof(double) * observable_partial_doubles(d, B)) +
            align_up(sizeof(int) * B) + align_up(sizeof(GemmDesc) * std::max(B, 256)) + align_up(8) +
            ExpmChunkWS::bytes(d, ps_r_max(d));
 }
@@ -205,6 +206,8 @@ redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int
     off += align_up(mat * B);
     float2* Z = reinterpret_cast<float2*>(base + off);
     off += align_up(mat * std::min(B, 256));
+    float2* obsT = reinterpret_cast<float2*>(base + off);
+    off += align_up(mat * std::min(B, OBS_CHUNK));
     double* obs_partial = reinterpret_cast<double*>(base + off);
     off += align_up(sizeof(double) * observable_partial_doubles(d, B));
     int* loc = reinterpret_cast<int*>(base + off);
@@ -246,7 +249,7 @@ redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int
         }
         if (obs_out)
             REDO_HIP(observable(d, B, X[0], X[1], loc, nn, obs_cols, reinterpret_cast<const float2*>(obs_vals), obs_width,
-                                n_steps, n, obs_partial, obs_out + n, N, st));
+                                n_steps, n, obs_partial, obs_out + n, N, obsT, OBS_CHUNK, st));
     }
     REDO_HIP(gather_back(d, B, X[0], X[1], nn, loc, st));
     return REDO_OK;

@@ -196,60 +196,82 @@ __global__ void fill_descs_kernel(GemmDesc* descs, int count, const float2* A, l
     descs[b] = g;
 }
 
-// observable partial sums: block (rb, b) handles rows [OBS_ROWS rb, OBS_ROWS (rb + 1)) of instance b.
-// The block's rows of X sit in LDS: (X M)_ac = sum_t X_a,cols[c][t] conj(vals[c][t]) gathers inside
-// them; (M X)_ac = sum_t vals[a][t] X_cols[a][t],c reads LDS for rows of the block and coalesced
-// rows from L2 otherwise.  Every thread owns columns c = tid, tid + 256, ...
-constexpr int OBS_ROWS_MAX = 4;
+// Observable in two passes over the instance (each pass reads X once):
+//   pass 1: T = M X from column strips of X held in LDS (every row index available),
+//   pass 2: (X M)_ac = sum_t X_a,cols[c][t] conj(vals[c][t]) from row blocks in LDS,
+//           partial sums of (X M)_ac conj(T_ac).
+// Workgroups of one instance are kept on one XCD (round-robin dispatch over 8 XCDs).
 constexpr int OBS_WMAX = 16;
-// rows per block: LDS holds OBS_ROWS rows of d complex values (<= 128 KiB)
-inline int obs_rows(int d) { return std::max(1, std::min(OBS_ROWS_MAX, 8192 / d)); }
-__global__ __launch_bounds__(256) void observable_partial_kernel(int d, int OBS_ROWS, const float2* __restrict__ X0,
-                                                                 const float2* __restrict__ X1, const int* loc,
-                                                                 long long xstride, const int* __restrict__ cols,
-                                                                 const float2* __restrict__ vals, int w,
-                                                                 const int* n_steps, int step, double* partial) {
-    extern __shared__ float2 rows[];   // [OBS_ROWS][d]
-    __shared__ double red[256];
-    // all row blocks of one instance on one XCD (workgroups are dispatched round-robin over 8 XCDs),
-    // so the partner rows each block reads are shared in that XCD's L2
-    const int nrb = d / OBS_ROWS;
-    long long bid = blockIdx.x;
-    const long long nb = gridDim.x;
-    if (nb % 8 == 0) bid = (bid % 8) * (nb / 8) + bid / 8;
-    const int b = (int)(bid / nrb), rb = (int)(bid % nrb);
-    const int a0 = rb * OBS_ROWS;
+inline int obs_strip(int d) { return std::max(1, std::min(16, 16384 / d)); }   // columns per strip (<= 128 KiB LDS)
+inline int obs_rows(int d) { return std::max(1, std::min(4, 8192 / d)); }      // rows per block (<= 64 KiB LDS)
+
+__device__ inline long long xcd_local(long long bid, long long nb) {
+    return (nb % 8 == 0) ? (bid % 8) * (nb / 8) + bid / 8 : bid;
+}
+
+__global__ __launch_bounds__(256) void observable_mx_kernel(int d, int SW, int b0, const float2* __restrict__ X0,
+                                                            const float2* __restrict__ X1, const int* loc,
+                                                            long long xstride, const int* __restrict__ cols,
+                                                            const float2* __restrict__ vals, int w,
+                                                            const int* n_steps, int step, float2* T) {
+    extern __shared__ float2 strip[];   // [d][SW]
+    const int nstrip = d / SW;
+    const long long bid = xcd_local(blockIdx.x, gridDim.x);
+    const int i = (int)(bid / nstrip), sidx = (int)(bid % nstrip);
+    const int b = b0 + i;
+    if (n_steps && step >= n_steps[b]) return;
     const float2* Xb = ((loc && loc[b]) ? X1 : X0) + (long long)b * xstride;
-    const bool active = n_steps ? step < n_steps[b] : true;
-    double acc = 0.0;
-    if (active) {
-        for (int e = threadIdx.x; e < OBS_ROWS * d; e += 256) rows[e] = Xb[(long long)a0 * d + e];
+    const int c0 = sidx * SW;
+    for (int e = threadIdx.x; e < d * SW; e += 256) {
+        const int r = e / SW, c = e % SW;
+        strip[e] = Xb[(long long)r * d + c0 + c];
     }
+    __syncthreads();
+    float2* Tb = T + (long long)i * d * d;
+    for (int e = threadIdx.x; e < d * SW; e += 256) {
+        const int a = e / SW, c = e % SW;
+        float2 acc = make_float2(0.f, 0.f);
+        for (int t = 0; t < w; ++t) cfma(acc, vals[a * w + t], strip[cols[a * w + t] * SW + c]);
+        Tb[(long long)a * d + c0 + c] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void observable_dot_kernel(int d, int R, int b0, const float2* __restrict__ X0,
+                                                             const float2* __restrict__ X1, const int* loc,
+                                                             long long xstride, const int* __restrict__ cols,
+                                                             const float2* __restrict__ vals, int w,
+                                                             const int* n_steps, int step, const float2* __restrict__ T,
+                                                             double* partial) {
+    extern __shared__ float2 rows[];   // [R][d]
+    __shared__ double red[256];
+    const int nrb = d / R;
+    const long long bid = xcd_local(blockIdx.x, gridDim.x);
+    const int i = (int)(bid / nrb), rb = (int)(bid % nrb);
+    const int b = b0 + i;
+    const bool active = n_steps ? step < n_steps[b] : true;
+    const float2* Xb = ((loc && loc[b]) ? X1 : X0) + (long long)b * xstride;
+    const float2* Tb = T + (long long)i * d * d;
+    const int a0 = rb * R;
+    double acc = 0.0;
+    if (active)
+        for (int e = threadIdx.x; e < R * d; e += 256) rows[e] = Xb[(long long)a0 * d + e];
     __syncthreads();
     if (active) {
         for (int c = threadIdx.x; c < d; c += 256) {
             int cc[OBS_WMAX];
             float2 cv[OBS_WMAX];
 #pragma unroll
-            for (int t = 0; t < OBS_WMAX; ++t) {
+            for (int t = 0; t < OBS_WMAX; ++t)
                 if (t < w) {
                     cc[t] = cols[c * w + t];
                     cv[t] = cconj(vals[c * w + t]);
                 }
-            }
-            for (int r = 0; r < OBS_ROWS; ++r) {
-                const int a = a0 + r;
-                float2 xm = make_float2(0.f, 0.f), mx = make_float2(0.f, 0.f);
+            for (int r = 0; r < R; ++r) {
+                float2 xm = make_float2(0.f, 0.f);
 #pragma unroll
-                for (int t = 0; t < OBS_WMAX; ++t) {
+                for (int t = 0; t < OBS_WMAX; ++t)
                     if (t < w) cfma(xm, rows[r * d + cc[t]], cv[t]);
-                }
-                for (int t = 0; t < w; ++t) {
-                    const int ra = cols[a * w + t];
-                    const float2 xv = (ra >= a0 && ra < a0 + OBS_ROWS) ? rows[(ra - a0) * d + c]
-                                                                       : Xb[(long long)ra * d + c];
-                    cfma(mx, vals[a * w + t], xv);
-                }
+                const float2 mx = Tb[(long long)(a0 + r) * d + c];
                 acc += (double)xm.x * mx.x + (double)xm.y * mx.y;
             }
         }
@@ -568,19 +590,28 @@ size_t observable_partial_doubles(int d, int B) { return (size_t)B * (d / obs_ro
 
 hipError_t observable(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
                       const int* cols, const float2* vals, int w, const int* n_steps, int step, double* partial,
-                      double* out, long long out_stride, hipStream_t st) {
+                      double* out, long long out_stride, float2* T, int chunk, hipStream_t st) {
     if (w > OBS_WMAX) return hipErrorInvalidValue;
-    const int R = obs_rows(d);
-    const size_t lds = sizeof(float2) * R * (size_t)d;
-    hipError_t e0 = hipFuncSetAttribute((const void*)observable_partial_kernel,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e0 != hipSuccess) return e0;
-    hipLaunchKernelGGL(observable_partial_kernel, dim3((unsigned)((long long)(d / R) * B)), dim3(256), lds, st, d, R, X0,
-                       X1, loc, xstride, cols, vals, w, n_steps, step, partial);
-    hipError_t e = hipGetLastError();
+    const int SW = obs_strip(d), R = obs_rows(d);
+    const size_t lds1 = sizeof(float2) * (size_t)SW * d, lds2 = sizeof(float2) * (size_t)R * d;
+    hipError_t e = hipFuncSetAttribute((const void*)observable_mx_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds1);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(observable_final_kernel, dim3(B), dim3(256), 0, st, d / R, partial, vals, d * w, n_steps,
-                       step, out, out_stride);
+    e = hipFuncSetAttribute((const void*)observable_dot_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
+    if (e != hipSuccess) return e;
+    for (int b0 = 0; b0 < B; b0 += chunk) {
+        const int cnt = std::min(chunk, B - b0);
+        hipLaunchKernelGGL(observable_mx_kernel, dim3((unsigned)((long long)(d / SW) * cnt)), dim3(256), lds1, st, d, SW,
+                           b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(observable_dot_kernel, dim3((unsigned)((long long)(d / R) * cnt)), dim3(256), lds2, st, d, R,
+                           b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T, partial);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(observable_final_kernel, dim3(B), dim3(256), 0, st, d / R, partial, vals, d * w, n_steps, step,
+                       out, out_stride);
     return hipGetLastError();
 }
 

@@ -55,6 +55,7 @@ struct ChainWS {
     float2* Z;
     double* obs_partial;
     int* loc;
+    float2* obsT;
     size_t bytes;
     ChainWS(const redo_table_s* t, int B, int N, void* base) {
         const int d = t->desc.d, K = t->desc.K;
@@ -70,6 +71,7 @@ struct ChainWS {
         Z = c.take<float2>(mat * std::min(B, REPROJECT_CHUNK));
         obs_partial = c.take<double>(observable_partial_doubles(d, B));
         loc = c.take<int>(B);
+        obsT = c.take<float2>(mat * std::min(B, OBS_CHUNK));
         bytes = c.used;
     }
 };
@@ -294,7 +296,7 @@ redo_status large_chain(redo_table_s* t, int precision, const float* u, const in
         }
         if (obs_out)
             REDO_HIP(observable(d, B, X[0], X[1], w.loc, mat, obs_cols, reinterpret_cast<const float2*>(obs_vals),
-                                obs_width, n_steps, n, w.obs_partial, obs_out + n, N, st));
+                                obs_width, n_steps, n, w.obs_partial, obs_out + n, N, w.obsT, OBS_CHUNK, st));
     }
     REDO_HIP(gather_back(d, B, X[0], X[1], mat, w.loc, st));
     return REDO_OK;

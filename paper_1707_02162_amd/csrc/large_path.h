@@ -62,9 +62,11 @@ hipError_t fill_descs(GemmDesc* descs, int count, const float2* A, long long sA,
                       long long sB, int opB, float2* C, long long sC, const int* n_steps, int step,
                       int inactive_mode, float alpha, float beta, hipStream_t st);
 size_t observable_partial_doubles(int d, int B);
+// T: scratch of `chunk` d x d matrices (instances processed `chunk` at a time)
+constexpr int OBS_CHUNK = 256;
 hipError_t observable(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
                       const int* cols, const float2* vals, int w, const int* n_steps, int step, double* partial,
-                      double* out, long long out_stride, hipStream_t st);
+                      double* out, long long out_stride, float2* T, int chunk, hipStream_t st);
 hipError_t reproject_descs(GemmDesc* descs, int count, int b0, float2* X0, float2* X1, long long xstride, float2* Z,
                            long long zstride, int* loc, const int* n_steps, int step, int phase, hipStream_t st);
 hipError_t gather_back(int d, int B, float2* X0, const float2* X1, long long xstride, const int* loc, hipStream_t st);

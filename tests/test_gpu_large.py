@@ -324,3 +324,14 @@ def test_bf16x3_ising_d1024_sampled_vs_oracle():
     mo, X = O.magnetisation_series(O.compose_all_redo(p, tab, 5), p.M)
     assert nfrob(U[5].cpu().numpy(), X) < BF_TOL
     assert np.abs(m[5].cpu().numpy() - mo).max() < BF_TOL
+
+
+def test_large_batch_and_single_calls_bitwise_equal():
+    """A batch of instances gives bitwise the results of one call per instance."""
+    p = W.nmr_chain(7, 3, 12, 2e-6, 32, 2, 212)
+    t = R().RedoTable.from_problem(p)
+    u = torch.tensor(p.u).cuda()
+    U_all, _, _ = t.chain(u, reproject_every=5)
+    for b in range(p.B):
+        U1, _, _ = t.chain(u[b:b + 1].contiguous(), reproject_every=5)
+        assert torch.equal(U1[0], U_all[b])
