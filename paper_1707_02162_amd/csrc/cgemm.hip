@@ -547,7 +547,7 @@ hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision,
     if (prof) profile_begin(st, &tok);
     // 128x64 tiles keep three workgroups per CU (accumulators 64 registers per lane)
     if (precision == 2)
-        e = big ? launch_bf<128, 128>(d, batch, descs, st) : launch_bf<64, 64>(d, batch, descs, st);
+        e = big ? launch_bf<128, 64>(d, batch, descs, st) : launch_bf<64, 64>(d, batch, descs, st);
     else if (precision == 1)
         e = big ? launch<128, 128, 1>(d, batch, descs, st) : launch<64, 64, 1>(d, batch, descs, st);
     else

@@ -203,7 +203,7 @@ __global__ void fill_descs_kernel(GemmDesc* descs, int count, const float2* A, l
 // Workgroups of one instance are kept on one XCD (round-robin dispatch over 8 XCDs).
 constexpr int OBS_WMAX = 16;
 inline int obs_strip(int d) { return std::max(1, std::min(16, 16384 / d)); }   // columns per strip (<= 128 KiB LDS)
-inline int obs_rows(int d) { return std::max(1, std::min(4, 8192 / d)); }      // rows per block (<= 64 KiB LDS)
+inline int obs_rows(int d) { return std::max(1, std::min(8, 8192 / d)); }      // rows per block (<= 64 KiB LDS)
 
 __device__ inline long long xcd_local(long long bid, long long nb) {
     return (nb % 8 == 0) ? (bid % 8) * (nb / 8) + bid / 8 : bid;
@@ -228,11 +228,22 @@ __global__ __launch_bounds__(256) void observable_mx_kernel(int d, int SW, int b
     }
     __syncthreads();
     float2* Tb = T + (long long)i * d * d;
-    for (int e = threadIdx.x; e < d * SW; e += 256) {
-        const int a = e / SW, c = e % SW;
-        float2 acc = make_float2(0.f, 0.f);
-        for (int t = 0; t < w; ++t) cfma(acc, vals[a * w + t], strip[cols[a * w + t] * SW + c]);
-        Tb[(long long)a * d + c0 + c] = acc;
+    // each thread owns whole rows a of the strip: the row list of a is read once
+    for (int a = threadIdx.x; a < d; a += 256) {
+        float2 acc[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[c] = make_float2(0.f, 0.f);
+        for (int t = 0; t < w; ++t) {
+            const int src = cols[a * w + t];
+            const float2 v = vals[a * w + t];
+            const float2* row = strip + (long long)src * SW;
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (c < SW) cfma(acc[c], v, row[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (c < SW) Tb[(long long)a * d + c0 + c] = acc[c];
     }
 }
 

@@ -306,3 +306,31 @@ def test_nonfinite_amplitude_flagged():
     assert st == 5
     st2, _ = t.device_status()
     assert st2 == 0
+
+
+def test_grape_c4_full_size_sampled_vs_oracle():
+    """The batched-GRAPE workload at full size (64 systems, d = 32, five phased
+    channels, N_b ~ U{500..3000}, checkpoints every ceil(sqrt(N))) in one call;
+    two sampled systems (the shortest and the longest) against the oracle
+    gradient, every system against the properties that hold at any size."""
+    p = W.c4_batched_grape()
+    t = table(p)
+    F, ov, grad = t.grape(torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda(), n_steps=torch.tensor(p.n_steps))
+    F, ov, grad = F.cpu().numpy(), ov.cpu().numpy(), grad.cpu().numpy()
+    assert np.all((F >= 0) & (F <= 1 + 1e-6)) and np.allclose(F, np.abs(ov) ** 2, atol=1e-12)
+    for b in range(p.B):
+        assert np.all(grad[b, p.n_steps[b]:] == 0) and np.all(np.isfinite(grad[b]))
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    _grape_check(p, tab, F, ov, grad, [int(np.argmin(p.n_steps)), int(np.argmax(p.n_steps))])
+
+
+def test_expm_baseline_d64_vs_oracle_exact():
+    """The comparison point at d = 64 (six-qubit chain) runs on the batched GEMMs."""
+    p = W.c2_six_qubit(B=2, N=200)
+    t = table(p)
+    U, _ = t.expm_chain(torch.tensor(p.u).cuda())
+    U = U.cpu().numpy()
+    for b in range(p.B):
+        H0m = np.diag(p.H0[0]).astype(complex)
+        X = O.chain([O.step_exact(H0m, p.S, p.g, p.u[b, n].astype(np.float64), p.dt) for n in range(p.N)])
+        assert nfrob(U[b], X) < FROB_TOL
