@@ -130,11 +130,12 @@ redo_status redo_table_query(redo_table table, redo_table_desc* desc, size_t* de
 
 /* Bytes of workspace that `op` needs for B instances of up to N_max steps
  * (0 on invalid arguments).  Workspace is caller-owned device memory.  For
- * REDO_OP_GRAPE this assumes the default checkpoint interval ceil(sqrt(N_max)). */
+ * REDO_OP_GRAPE and REDO_OP_EXPM_GRAPE this assumes the automatic checkpoint
+ * interval (checkpoint_every = 0, see redo_grape_fidelity_grad). */
 size_t redo_workspace_bytes(redo_table table, int32_t op, int32_t B, int32_t N_max);
 
-/* Workspace of redo_grape_fidelity_grad for an explicit checkpoint interval
- * (0 = ceil(sqrt(N_max))). */
+/* Workspace of redo_grape_fidelity_grad for a checkpoint interval
+ * (0 = automatic). */
 size_t redo_grape_workspace_bytes(redo_table table, int32_t B, int32_t N_max, int32_t checkpoint_every);
 
 /*
@@ -197,9 +198,8 @@ redo_status redo_unitary_fidelity(int32_t d, int32_t B, const float* U_target, c
 /*
  * GRAPE objective and gradient through REDO (Sec. III; the table stays
  * outside the iteration loop): F_b = |Tr(U_f^dag X_N) / Tr(U_f^dag U_f)|^2
- * and dF_b/du at the quantised amplitudes, by a forward chain with
- * checkpoints every `checkpoint_every` steps (0: ceil(sqrt(N_b))), a
- * recomputation of each segment and a backward scan
+ * and dF_b/du at the quantised amplitudes, by a forward chain
+ * X_n = U_n X_{n-1} and a backward scan
  *     L_N = U_f^dag,  L_{n-1} = L_n U_n,  Y_n = X_n L_n,
  *     dg/dOmega_kn = -i dt Tr(Z S_k Z^dag Y_n) / Tr(U_f^dag U_f),
  *     dg/dphi_kn   = -i (Tr(G_k Y_n) - Tr(G_k Y_{n-1})) / Tr(U_f^dag U_f),
@@ -208,6 +208,15 @@ redo_status redo_unitary_fidelity(int32_t d, int32_t B, const float* U_target, c
  * point (straight-through).  Needs channels whose generators commute with
  * each other and whose phase generators commute with the drift and with the
  * other channels (REDO_ERR_UNSUPPORTED otherwise).
+ * Memory schedule: with checkpoint_every = 1 every forward state and every
+ * backward factor is kept (3 B N_max d^2 complex entries of workspace at
+ * d >= 128): the two scans run side by side in one batched launch per step
+ * and nothing is recomputed; when the generators have at most 16 nonzeros per
+ * row the traces read Y_n only at those entries, as FP64 dot products of rows
+ * of X_n and L_n^dag.  With checkpoint_every = C > 1 only every C-th state is
+ * kept and each segment is recomputed during the backward scan.  0 selects 1
+ * when that workspace is at most 48 GiB (d >= 128), else ceil(sqrt(N_max));
+ * at d <= 64 the fused kernel always checkpoints (0: ceil(sqrt(N_max))).
  *   U_target  c64 [B][d][d];  fidelity double [B];  overlap c128 [B] or NULL
  *   grad      float, same layout as u (entries of steps >= n_steps[b] are set to 0)
  * Workspace: redo_workspace_bytes(table, REDO_OP_GRAPE, B, N_max).
@@ -241,10 +250,10 @@ redo_status redo_expm_chain(redo_table table, int32_t precision, const float* u,
  * GRAPE with the plain per-step exponential (the comparison point): the
  * fidelity of the unquantised chain and the usual first-order gradient
  * dU_n/du ~ -i dt H_k U_n (the GRAPE approximation of Khaneja et al., cited in
- * Sec. III), through the same checkpointed forward and backward scans as
- * redo_grape_fidelity_grad.  d a multiple of 64, FP32.
+ * Sec. III), through the same forward and backward scans (and the same
+ * memory schedule) as redo_grape_fidelity_grad.  d a multiple of 64, FP32.
  * Workspace: redo_workspace_bytes(table, REDO_OP_EXPM_GRAPE, B, N_max)
- * (default checkpoint interval).
+ * (automatic checkpoint interval).
  */
 redo_status redo_expm_grape_fidelity_grad(redo_table table, int32_t precision, const float* u,
                                           const int32_t* n_steps, int32_t B, int32_t N_max,

@@ -282,6 +282,45 @@ redo_status redo_build_table(const redo_table_desc* desc, const double* H0, cons
         REDO_HIP(alloc((void**)&t->V32, sizeof(float2) * nn * R));
     }
     if (desc->phased) REDO_HIP(alloc((void**)&t->g64, sizeof(double) * d * K));
+    // sparsity pattern of the generators (the adjoint's traces then need only these entries)
+    {
+        std::vector<std::vector<int>> rows(d);
+        size_t wmax = 0;
+        for (int a = 0; a < d && wmax <= (size_t)SPAT_WMAX; ++a) {
+            for (int j = 0; j < d; ++j) {
+                bool nz = false;
+                for (int k = 0; k < K && !nz; ++k) {
+                    const size_t e = nn * k + (size_t)a * d + j;
+                    nz = hS[2 * e] != 0.0 || hS[2 * e + 1] != 0.0;
+                }
+                if (nz) rows[a].push_back(j);
+            }
+            wmax = std::max(wmax, rows[a].size());
+        }
+        if (wmax >= 1 && wmax <= (size_t)SPAT_WMAX) {
+            const int w = (int)wmax;
+            std::vector<int> hc((size_t)d * w);
+            std::vector<double> hv(2 * (size_t)K * d * w, 0.0);
+            for (int a = 0; a < d; ++a)
+                for (int t2 = 0; t2 < w; ++t2) {
+                    const bool real = t2 < (int)rows[a].size();
+                    const int j = real ? rows[a][t2] : a;
+                    hc[(size_t)a * w + t2] = j;
+                    if (real)
+                        for (int k = 0; k < K; ++k) {
+                            const size_t e = nn * k + (size_t)a * d + j, o = ((size_t)k * d + a) * w + t2;
+                            hv[2 * o] = hS[2 * e];
+                            hv[2 * o + 1] = hS[2 * e + 1];
+                        }
+                }
+            REDO_HIP(alloc((void**)&t->spat_cols, sizeof(int) * hc.size()));
+            REDO_HIP(alloc((void**)&t->spat_vals, sizeof(double) * hv.size()));
+            REDO_HIP(hipMemcpyAsync(t->spat_cols, hc.data(), sizeof(int) * hc.size(), hipMemcpyHostToDevice, hs));
+            REDO_HIP(hipMemcpyAsync(t->spat_vals, hv.data(), sizeof(double) * hv.size(), hipMemcpyHostToDevice, hs));
+            REDO_HIP(hipStreamSynchronize(hs));
+            t->spat_w = w;
+        }
+    }
 
     // ---- FP64 build: E_kj = exp(-i b^j eps dt S_k), T_kj[c] = E_kj^c
     {
@@ -363,7 +402,8 @@ redo_status redo_build_table(const redo_table_desc* desc, const double* H0, cons
 redo_status redo_table_destroy(redo_table t) {
     if (!t) return REDO_OK;
     (void)hipDeviceSynchronize();
-    void* bufs[] = {t->T32, t->h64, t->V32, t->g64, t->S32, t->S64, t->Sy32, t->H32, t->flags, t->T16hi, t->T16lo, t->cache};
+    void* bufs[] = {t->T32,   t->h64,   t->V32,   t->g64,   t->S32,       t->S64,      t->Sy32,
+                    t->H32,   t->flags, t->T16hi, t->T16lo, t->cache, t->spat_cols, t->spat_vals};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     delete t;
@@ -484,13 +524,13 @@ size_t redo_workspace_bytes(redo_table t, int32_t op, int32_t B, int32_t N_max) 
 
 size_t redo_grape_workspace_bytes(redo_table t, int32_t B, int32_t N_max, int32_t checkpoint_every) {
     if (!t || B < 1 || N_max < 1 || checkpoint_every < 0) return 0;
-    const long long C = checkpoint_every > 0 ? checkpoint_every : ceil_sqrt(N_max);
     const int d = t->desc.d;
     if (small_dim(d)) {
+        const long long C = checkpoint_every > 0 ? checkpoint_every : ceil_sqrt(N_max);
         const long long nck = (N_max + C - 1) / C;
         return sizeof(float2) * (size_t)d * d * (size_t)B * (size_t)(nck + C);
     }
-    return large_grape_workspace_bytes(t, B, N_max, (int)C);
+    return large_grape_workspace_bytes(t, B, N_max, checkpoint_every);
 }
 
 redo_status redo_quantise(redo_table t, const float* u, int32_t B, int32_t N_max, int32_t* codes, double* phi,
@@ -612,8 +652,8 @@ redo_status redo_grape_fidelity_grad(redo_table t, int32_t precision, const floa
         REDO_HIP(small_grape(t, a, hs));
         return REDO_OK;
     }
-    return large_grape(t, precision, u, n_steps, B, N_max, U_target, (int)C, fidelity, overlap, grad, workspace,
-                       workspace_bytes, hs, 0);
+    return large_grape(t, precision, u, n_steps, B, N_max, U_target, checkpoint_every, fidelity, overlap, grad,
+                       workspace, workspace_bytes, hs, 0);
 }
 
 redo_status redo_expm_chain(redo_table t, int32_t precision, const float* u, const int32_t* n_steps, int32_t B,
@@ -646,9 +686,8 @@ redo_status redo_expm_grape_fidelity_grad(redo_table t, int32_t precision, const
     if (precision < REDO_PREC_F32 || precision > REDO_PREC_BF16X3) return fail(REDO_ERR_ARG, "unknown precision");
     if (t->desc.d % 64 != 0) return fail(REDO_ERR_UNSUPPORTED, "the exponential baseline needs d a multiple of 64");
     if (precision == REDO_PREC_BF16X3) return fail(REDO_ERR_UNSUPPORTED, "the exponential baseline runs in FP32");
-    const long long C = checkpoint_every > 0 ? checkpoint_every : ceil_sqrt(N_max);
-    return large_grape(t, precision, u, n_steps, B, N_max, U_target, (int)C, fidelity, overlap, grad, workspace,
-                       workspace_bytes, static_cast<hipStream_t>(stream), 1);
+    return large_grape(t, precision, u, n_steps, B, N_max, U_target, checkpoint_every, fidelity, overlap, grad,
+                       workspace, workspace_bytes, static_cast<hipStream_t>(stream), 1);
 }
 
 redo_status redo_get_device_status(redo_table t, void* stream, int64_t* n_clamped) {

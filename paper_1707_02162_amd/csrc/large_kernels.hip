@@ -199,101 +199,216 @@ __global__ void fill_descs_kernel(GemmDesc* descs, int count, const float2* A, l
 // Observable in two passes over the instance (each pass reads X once):
 //   pass 1: T = M X from column strips of X held in LDS (every row index available),
 //   pass 2: (X M)_ac = sum_t X_a,cols[c][t] conj(vals[c][t]) from row blocks in LDS,
-//           partial sums of (X M)_ac conj(T_ac).
-// Workgroups of one instance are kept on one XCD (round-robin dispatch over 8 XCDs).
+//           partial sums of Re((X M)_ac conj(T_ac)).
+// Both passes stage their LDS fill through registers (several loads in flight
+// per lane) and keep at most 64 KiB (pass 1) / 32 KiB (pass 2) of LDS per
+// workgroup, so that workgroups share a CU and one's fill overlaps another's
+// arithmetic.  Row lists are read two passes ahead (pass 1); column lists and
+// the entries of T one column ahead (pass 2).  The list width is padded to WP
+// (a multiple of 4) with zero-valued entries; padded entries load a valid
+// index and contribute nothing.  Workgroups of one instance are kept on one
+// XCD (round-robin dispatch over 8 XCDs).  Measured at d = 1024 (4096
+// instances) this pair beat a single pass that gathers the rows of M X from
+// L2 instead of writing T (26 vs 16 ms per step of 1024 instances).
 constexpr int OBS_WMAX = 16;
-inline int obs_strip(int d) { return std::max(1, std::min(16, 16384 / d)); }   // columns per strip (<= 128 KiB LDS)
-inline int obs_rows(int d) { return std::max(1, std::min(8, 8192 / d)); }      // rows per block (<= 64 KiB LDS)
+inline int pow2_floor(int x) {
+    int p = 1;
+    while (p * 2 <= x) p *= 2;
+    return p;
+}
+// strip width and row-block height: at most 64 KiB (8 x 1024 complex) and 32 KiB
+// (4 x 1024 complex) of LDS, powers of two so that they divide d
+inline int obs_strip(int d) { return pow2_floor(std::max(1, std::min(8, 8 * 1024 / d))); }
+inline int obs_rows(int d) { return pow2_floor(std::max(1, std::min(4, 4 * 1024 / d))); }
 
 __device__ inline long long xcd_local(long long bid, long long nb) {
     return (nb % 8 == 0) ? (bid % 8) * (nb / 8) + bid / 8 : bid;
 }
 
-__global__ __launch_bounds__(256) void observable_mx_kernel(int d, int SW, int b0, const float2* __restrict__ X0,
-                                                            const float2* __restrict__ X1, const int* loc,
-                                                            long long xstride, const int* __restrict__ cols,
-                                                            const float2* __restrict__ vals, int w,
-                                                            const int* n_steps, int step, float2* T) {
-    extern __shared__ float2 strip[];   // [d][SW]
+template <int WP>
+__device__ inline void obs_list(const int* __restrict__ cols, const float2* __restrict__ vals, int w, int a,
+                                int (&cc)[WP], float2 (&cv)[WP]) {
+#pragma unroll
+    for (int t = 0; t < WP; ++t) {
+        const int tt = t < w ? t : w - 1;     // always a valid entry of row a
+        const int c = cols[(long long)a * w + tt];
+        const float2 v = vals[(long long)a * w + tt];
+        cc[t] = t < w ? c : a;
+        cv[t] = t < w ? v : make_float2(0.f, 0.f);
+    }
+}
+
+// Pass 1.  SW columns per strip; CPL complex entries per lane, LPR lanes per
+// row; row lists are read two passes ahead.
+template <int SW, int WP, int NT>
+__global__ __launch_bounds__(NT, NT / 128) void observable_mx_kernel(int d, int b0, const float2* __restrict__ X0,
+                                                           const float2* __restrict__ X1, const int* loc,
+                                                           long long xstride, const int* __restrict__ cols,
+                                                           const float2* __restrict__ vals, int w,
+                                                           const int* n_steps, int step, float2* T) {
+    constexpr int CPL = SW >= 2 ? 2 : 1;
+    constexpr int LPR = SW / CPL;
+    constexpr int RPP = NT / LPR;                   // rows per pass of the workgroup
+    extern __shared__ float2 strip[];               // [d][SW]
     const int nstrip = d / SW;
     const long long bid = xcd_local(blockIdx.x, gridDim.x);
     const int i = (int)(bid / nstrip), sidx = (int)(bid % nstrip);
     const int b = b0 + i;
-    if (n_steps && step >= n_steps[b]) return;
+    if (n_steps && step >= n_steps[b]) return;      // uniform over the workgroup
     const float2* Xb = ((loc && loc[b]) ? X1 : X0) + (long long)b * xstride;
     const int c0 = sidx * SW;
-    for (int e = threadIdx.x; e < d * SW; e += 256) {
-        const int r = e / SW, c = e % SW;
-        strip[e] = Xb[(long long)r * d + c0 + c];
+    const int tid = threadIdx.x;
+    const int cp = (tid % LPR) * CPL;
+    int a = tid / LPR;
+    int cc0[WP], cc1[WP];
+    float2 cv0[WP], cv1[WP];
+    obs_list<WP>(cols, vals, w, min(a, d - 1), cc0, cv0);
+    obs_list<WP>(cols, vals, w, min(a + RPP, d - 1), cc1, cv1);
+    const int n = d * SW;
+    if (n % (NT * 16) == 0) {
+        for (int base = 0; base < n; base += NT * 16) {
+            float2 r[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = base + u * NT + tid;
+                r[u] = Xb[(long long)(e / SW) * d + c0 + e % SW];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) strip[base + u * NT + tid] = r[u];
+        }
+    } else {
+        for (int e = tid; e < n; e += NT) strip[e] = Xb[(long long)(e / SW) * d + c0 + e % SW];
     }
     __syncthreads();
     float2* Tb = T + (long long)i * d * d;
-    // each thread owns whole rows a of the strip: the row list of a is read once
-    for (int a = threadIdx.x; a < d; a += 256) {
-        float2 acc[16];
+    for (; a < d; a += RPP) {
+        int cc2[WP];
+        float2 cv2[WP];
+        const int a2 = a + 2 * RPP;
+        if (a2 < d) obs_list<WP>(cols, vals, w, a2, cc2, cv2);
+        float2 acc[CPL];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) acc[c] = make_float2(0.f, 0.f);
-        for (int t = 0; t < w; ++t) {
-            const int src = cols[a * w + t];
-            const float2 v = vals[a * w + t];
-            const float2* row = strip + (long long)src * SW;
+        for (int u = 0; u < CPL; ++u) acc[u] = make_float2(0.f, 0.f);
 #pragma unroll
-            for (int c = 0; c < 16; ++c)
-                if (c < SW) cfma(acc[c], v, row[c]);
+        for (int t = 0; t < WP; ++t) {
+            const float2* src = strip + (long long)cc0[t] * SW + cp;
+            if constexpr (CPL == 2) {
+                const float4 x = *reinterpret_cast<const float4*>(src);
+                cfma(acc[0], cv0[t], make_float2(x.x, x.y));
+                cfma(acc[1], cv0[t], make_float2(x.z, x.w));
+            } else {
+                cfma(acc[0], cv0[t], src[0]);
+            }
         }
+        float2* dst = Tb + (long long)a * d + c0 + cp;
+        if constexpr (CPL == 2)
+            *reinterpret_cast<float4*>(dst) = make_float4(acc[0].x, acc[0].y, acc[1].x, acc[1].y);
+        else
+            dst[0] = acc[0];
 #pragma unroll
-        for (int c = 0; c < 16; ++c)
-            if (c < SW) Tb[(long long)a * d + c0 + c] = acc[c];
+        for (int t = 0; t < WP; ++t) {
+            cc0[t] = cc1[t];
+            cv0[t] = cv1[t];
+            cc1[t] = cc2[t];
+            cv1[t] = cv2[t];
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void observable_dot_kernel(int d, int R, int b0, const float2* __restrict__ X0,
-                                                             const float2* __restrict__ X1, const int* loc,
-                                                             long long xstride, const int* __restrict__ cols,
-                                                             const float2* __restrict__ vals, int w,
-                                                             const int* n_steps, int step, const float2* __restrict__ T,
-                                                             double* partial) {
-    extern __shared__ float2 rows[];   // [R][d]
-    __shared__ double red[256];
+// Pass 2.  R rows of X per workgroup, held column-major in LDS ([d][R]: the R
+// entries of a column are one contiguous run, read as R/2 16-byte words);
+// each lane takes columns c, c + NT, ...; the R entries of T and the row list
+// of the next column are read while the current column is summed.
+template <int R, int WP, int NT>
+__global__ __launch_bounds__(NT, NT / 128) void observable_dot_kernel(int d, int b0, const float2* __restrict__ X0,
+                                                            const float2* __restrict__ X1, const int* loc,
+                                                            long long xstride, const int* __restrict__ cols,
+                                                            const float2* __restrict__ vals, int w,
+                                                            const int* n_steps, int step, const float2* __restrict__ T,
+                                                            double* partial) {
+    extern __shared__ float2 rowsT[];   // [d][R]
+    __shared__ double red[NT];
     const int nrb = d / R;
     const long long bid = xcd_local(blockIdx.x, gridDim.x);
     const int i = (int)(bid / nrb), rb = (int)(bid % nrb);
     const int b = b0 + i;
+    const int tid = threadIdx.x;
     const bool active = n_steps ? step < n_steps[b] : true;
-    const float2* Xb = ((loc && loc[b]) ? X1 : X0) + (long long)b * xstride;
-    const float2* Tb = T + (long long)i * d * d;
-    const int a0 = rb * R;
+    const float2* Xb = ((loc && loc[b]) ? X1 : X0) + (long long)b * xstride + (long long)rb * R * d;
+    const float2* Tb = T + (long long)i * d * d + (long long)rb * R * d;
     double acc = 0.0;
-    if (active)
-        for (int e = threadIdx.x; e < R * d; e += 256) rows[e] = Xb[(long long)a0 * d + e];
-    __syncthreads();
+    int c = tid;
+    int cc[WP];
+    float2 cv[WP], mx[R];
     if (active) {
-        for (int c = threadIdx.x; c < d; c += 256) {
-            int cc[OBS_WMAX];
-            float2 cv[OBS_WMAX];
+        const int c_ = min(c, d - 1);
+        obs_list<WP>(cols, vals, w, c_, cc, cv);
 #pragma unroll
-            for (int t = 0; t < OBS_WMAX; ++t)
-                if (t < w) {
-                    cc[t] = cols[c * w + t];
-                    cv[t] = cconj(vals[c * w + t]);
-                }
+        for (int r = 0; r < R; ++r) mx[r] = Tb[(long long)r * d + c_];
+        // rows rb R .. rb R + R - 1, R 16-byte loads in flight per lane and pass
+        const float4* src = reinterpret_cast<const float4*>(Xb);
+        const int half = d / 2;
+        for (int cp = tid; cp < half; cp += NT) {
+            float4 v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = src[(long long)r * half + cp];
+#pragma unroll
             for (int r = 0; r < R; ++r) {
-                float2 xm = make_float2(0.f, 0.f);
-#pragma unroll
-                for (int t = 0; t < OBS_WMAX; ++t)
-                    if (t < w) cfma(xm, rows[r * d + cc[t]], cv[t]);
-                const float2 mx = Tb[(long long)(a0 + r) * d + c];
-                acc += (double)xm.x * mx.x + (double)xm.y * mx.y;
+                rowsT[(2 * cp) * R + r] = make_float2(v[r].x, v[r].y);
+                rowsT[(2 * cp + 1) * R + r] = make_float2(v[r].z, v[r].w);
             }
         }
     }
-    red[threadIdx.x] = acc;
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    if (active) {
+        for (; c < d; c += NT) {
+            const int cn = c + NT;
+            int nc[WP];
+            float2 nv[WP], nm[R];
+            if (cn < d) {
+                obs_list<WP>(cols, vals, w, cn, nc, nv);
+#pragma unroll
+                for (int r = 0; r < R; ++r) nm[r] = Tb[(long long)r * d + cn];
+            }
+            float2 xm[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) xm[r] = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int t = 0; t < WP; ++t) {
+                const float2 m = cconj(cv[t]);
+                const float2* col = rowsT + (long long)cc[t] * R;
+                if constexpr (R >= 2) {
+#pragma unroll
+                    for (int r = 0; r < R; r += 2) {
+                        const float4 x = *reinterpret_cast<const float4*>(col + r);
+                        cfma(xm[r], make_float2(x.x, x.y), m);
+                        cfma(xm[r + 1], make_float2(x.z, x.w), m);
+                    }
+                } else {
+                    cfma(xm[0], col[0], m);
+                }
+                asm volatile("" ::: "memory");   // one list entry's gathers at a time (register pressure)
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc += (double)xm[r].x * mx[r].x + (double)xm[r].y * mx[r].y;
+            if (cn < d) {
+#pragma unroll
+                for (int t = 0; t < WP; ++t) {
+                    cc[t] = nc[t];
+                    cv[t] = nv[t];
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) mx[r] = nm[r];
+            }
+        }
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (int st = NT / 2; st > 0; st >>= 1) {
+        if (tid < st) red[tid] += red[tid + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[(long long)b * nrb + rb] = red[0];
+    if (tid == 0) partial[(long long)b * nrb + rb] = red[0];
 }
 
 __global__ void observable_final_kernel(int nparts, const double* partial, const float2* vals, int nvals,
@@ -422,6 +537,132 @@ __global__ void trace_final_kernel(int ntile, int K, const double* partial, doub
     if (threadIdx.x < 6) out[(long long)b * out_bstride + k * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// GRAPE traces from stored factors, for generators with a sparse pattern:
+// Y = X_{s+1} L_{s+1} is needed only where S_k^T (and the diagonal) is
+// nonzero, and L = LH^H is stored conjugate-transposed so that both operands
+// of Y[j][a] = sum_c X[j][c] conj(LH[a][c]) are contiguous rows.  One wave per
+// row a (SPT_RPB rows per workgroup); the dot products accumulate in FP64.
+// For every channel k the row's share of T1 = Tr(S^psi Y), T2 = Tr(S^{pi/2} Y)
+// (phased, q = 0 or Cartesian) and D = Tr(G Y) goes to partial[(b N + s)][k][blk][6]
+// (s counted from step0).
+constexpr int SPT_RPB = 4;
+template <int WP>
+__global__ __launch_bounds__(256) void sparse_trace_kernel(int d, int N, int step0, int K, int phased, int cartesian,
+                                                           int sw, const float2* __restrict__ X, long long xsb,
+                                                           const float2* __restrict__ LH, long long lsb,
+                                                           const int* __restrict__ spc,
+                                                           const double2* __restrict__ spv,
+                                                           const double* __restrict__ g,
+                                                           const int* __restrict__ codes,
+                                                           const double* __restrict__ phi, const int* n_steps,
+                                                           double* partial) {
+    constexpr int NE = WP + 1;                      // pattern entries + the diagonal
+    __shared__ double red[SPT_RPB][NE][6];
+    const int blk = blockIdx.x, sl = blockIdx.y, b = blockIdx.z;
+    const int s = step0 + sl, nblk = gridDim.x, nsl = gridDim.y;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int a = blk * SPT_RPB + wave;
+    const long long mat = (long long)d * d;
+    const bool active = (!n_steps || s < n_steps[b]) && s < N;
+    double yr[NE], yi[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) yr[e] = yi[e] = 0.0;
+    int jt[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) jt[e] = e < sw ? spc[(long long)a * sw + e] : a;
+    if (active) {
+        const float2* Xs = X + (long long)b * xsb + (long long)s * mat;
+        const float2* Lr = LH + (long long)b * lsb + (long long)(s + 1) * mat + (long long)a * d;
+        for (int c0 = 0; c0 < d; c0 += 64 * 8) {
+            float2 l[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int c = c0 + lane + 64 * u;
+                l[u] = c < d ? Lr[c] : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                if (e < sw || e == WP) {
+                    const float2* xr = Xs + (long long)jt[e] * d;
+                    float2 x[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int c = c0 + lane + 64 * u;
+                        x[u] = c < d ? xr[c] : make_float2(0.f, 0.f);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        // x conj(l)
+                        yr[e] += (double)x[u].x * l[u].x + (double)x[u].y * l[u].y;
+                        yi[e] += (double)x[u].y * l[u].x - (double)x[u].x * l[u].y;
+                    }
+                }
+                asm volatile("" ::: "memory");   // one row's loads in flight at a time (register pressure)
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                yr[e] += __shfl_xor(yr[e], o);
+                yi[e] += __shfl_xor(yi[e], o);
+            }
+    }
+    // lane e (< sw) owns pattern entry e, lane WP the diagonal
+    double my_r = 0.0, my_i = 0.0;
+    int my_j = a;
+#pragma unroll
+    for (int e = 0; e < NE; ++e)
+        if (lane == e) {
+            my_r = yr[e];
+            my_i = yi[e];
+            my_j = jt[e];
+        }
+    const bool mine = active && (lane < sw || lane == WP);
+    for (int k = 0; k < K; ++k) {
+        double v[6] = {0, 0, 0, 0, 0, 0};
+        if (mine) {
+            const long long ci = ((long long)b * N + s) * K + k;
+            const int q = codes[ci];
+            const bool origin = phased && (q == 0 || cartesian);
+            const double psi = phased && !origin ? phi[ci] : 0.0;
+            if (lane < sw) {
+                const double2 sv = spv[((long long)k * d + a) * sw + lane];
+                double cr = sv.x, cim = sv.y;
+                if (phased && psi != 0.0) {
+                    const double2 p = expmi(psi * (g[(long long)k * d + a] - g[(long long)k * d + my_j]));
+                    cr = p.x * sv.x - p.y * sv.y;
+                    cim = p.x * sv.y + p.y * sv.x;
+                }
+                v[0] = cr * my_r - cim * my_i;
+                v[1] = cr * my_i + cim * my_r;
+                if (origin) {
+                    const double2 p =
+                        expmi(1.5707963267948966 * (g[(long long)k * d + a] - g[(long long)k * d + my_j]));
+                    const double r_ = p.x * sv.x - p.y * sv.y, i_ = p.x * sv.y + p.y * sv.x;
+                    v[2] = r_ * my_r - i_ * my_i;
+                    v[3] = r_ * my_i + i_ * my_r;
+                }
+            } else if (phased) {
+                const double ga = g[(long long)k * d + a];
+                v[4] = ga * my_r;
+                v[5] = ga * my_i;
+            }
+        }
+        if (lane < NE)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) red[wave][lane][c] = v[c];
+        __syncthreads();
+        if (threadIdx.x < 6) {
+            double acc = 0.0;
+            for (int w2 = 0; w2 < SPT_RPB; ++w2)
+                for (int e = 0; e < NE; ++e) acc += red[w2][e][threadIdx.x];
+            partial[((((long long)b * nsl + sl) * K + k) * nblk + blk) * 6 + threadIdx.x] = acc;
+        }
+        __syncthreads();
+    }
+}
+
 // gradient assembly for every (b, s, k):
 //   tr[b][s][k][6]: traces of Y_{s+1}; dm[b][m][k][2]: Tr(G Y_m) for m = 0 .. N (from tr and D_0)
 __global__ void grad_kernel(int B, int N, int K, int phased, double eps, double dt, const int* codes,
@@ -474,7 +715,8 @@ __global__ void grad_kernel(int B, int N, int K, int phased, double eps, double 
 }
 
 // D_0 = Tr(G_k L_0) per instance and channel, plus nu = Tr(U_f^dag U_f)
-__global__ void d0_kernel(int d, int K, int phased, const float2* L, long long lstride, const double* g, double* d0) {
+__global__ void d0_kernel(int d, int K, int phased, const float2* L, long long lstride, const double* g, double* d0,
+                          int conj_l) {
     const int b = blockIdx.x, k = blockIdx.y;
     __shared__ double rr[256], ri[256];
     double sr = 0, si = 0;
@@ -482,7 +724,7 @@ __global__ void d0_kernel(int d, int K, int phased, const float2* L, long long l
         for (int a = threadIdx.x; a < d; a += 256) {
             const float2 v = L[(long long)b * lstride + (long long)a * d + a];
             sr += g[(long long)k * d + a] * v.x;
-            si += g[(long long)k * d + a] * v.y;
+            si += g[(long long)k * d + a] * (conj_l ? -v.y : v.y);
         }
     rr[threadIdx.x] = sr;
     ri[threadIdx.x] = si;
@@ -599,30 +841,74 @@ hipError_t fill_descs(GemmDesc* descs, int count, const float2* A, long long sA,
 
 size_t observable_partial_doubles(int d, int B) { return (size_t)B * (d / obs_rows(d)); }
 
+template <int SW, int WP, int NT>
+static hipError_t launch_mx(int d, int cnt, int b0, const float2* X0, const float2* X1, const int* loc,
+                            long long xstride, const int* cols, const float2* vals, int w, const int* n_steps,
+                            int step, float2* T, hipStream_t st) {
+    const void* k = (const void*)observable_mx_kernel<SW, WP, NT>;
+    const size_t lds = sizeof(float2) * (size_t)SW * d;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((observable_mx_kernel<SW, WP, NT>), dim3((unsigned)((long long)(d / SW) * cnt)), dim3(NT), lds,
+                       st, d, b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T);
+    return hipGetLastError();
+}
+
+template <int R, int WP, int NT>
+static hipError_t launch_dot(int d, int cnt, int b0, const float2* X0, const float2* X1, const int* loc,
+                             long long xstride, const int* cols, const float2* vals, int w, const int* n_steps,
+                             int step, const float2* T, double* partial, hipStream_t st) {
+    const void* k = (const void*)observable_dot_kernel<R, WP, NT>;
+    const size_t lds = sizeof(float2) * (size_t)R * d;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((observable_dot_kernel<R, WP, NT>), dim3((unsigned)((long long)(d / R) * cnt)), dim3(NT), lds,
+                       st, d, b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T, partial);
+    return hipGetLastError();
+}
+
+template <int WP>
+static hipError_t obs_chunk(int d, int cnt, int b0, const float2* X0, const float2* X1, const int* loc,
+                            long long xstride, const int* cols, const float2* vals, int w, const int* n_steps,
+                            int step, float2* T, double* partial, hipStream_t st) {
+    const int SW = obs_strip(d), R = obs_rows(d);
+    hipError_t e;
+#define MXA d, cnt, b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T, st
+#define DTA d, cnt, b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T, partial, st
+    switch (SW) {
+        case 8: e = launch_mx<8, WP, 256>(MXA); break;
+        case 4: e = launch_mx<4, WP, 256>(MXA); break;
+        case 2: e = launch_mx<2, WP, 256>(MXA); break;
+        default: e = launch_mx<1, WP, 256>(MXA);
+    }
+    if (e != hipSuccess) return e;
+    switch (R) {
+        case 4: return launch_dot<4, WP, 256>(DTA);
+        case 2: return launch_dot<2, WP, 256>(DTA);
+        default: return launch_dot<1, WP, 256>(DTA);
+    }
+#undef MXA
+#undef DTA
+}
+
 hipError_t observable(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
                       const int* cols, const float2* vals, int w, const int* n_steps, int step, double* partial,
                       double* out, long long out_stride, float2* T, int chunk, hipStream_t st) {
-    if (w > OBS_WMAX) return hipErrorInvalidValue;
-    const int SW = obs_strip(d), R = obs_rows(d);
-    const size_t lds1 = sizeof(float2) * (size_t)SW * d, lds2 = sizeof(float2) * (size_t)R * d;
-    hipError_t e = hipFuncSetAttribute((const void*)observable_mx_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds1);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)observable_dot_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
-    if (e != hipSuccess) return e;
+    if (w < 1 || w > OBS_WMAX) return hipErrorInvalidValue;
+    const int wp = (w + 3) / 4 * 4;
     for (int b0 = 0; b0 < B; b0 += chunk) {
         const int cnt = std::min(chunk, B - b0);
-        hipLaunchKernelGGL(observable_mx_kernel, dim3((unsigned)((long long)(d / SW) * cnt)), dim3(256), lds1, st, d, SW,
-                           b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(observable_dot_kernel, dim3((unsigned)((long long)(d / R) * cnt)), dim3(256), lds2, st, d, R,
-                           b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T, partial);
-        e = hipGetLastError();
+        hipError_t e;
+        switch (wp) {
+            case 4: e = obs_chunk<4>(d, cnt, b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T, partial, st); break;
+            case 8: e = obs_chunk<8>(d, cnt, b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T, partial, st); break;
+            case 12: e = obs_chunk<12>(d, cnt, b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T, partial, st); break;
+            default: e = obs_chunk<16>(d, cnt, b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T, partial, st);
+        }
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(observable_final_kernel, dim3(B), dim3(256), 0, st, d / R, partial, vals, d * w, n_steps, step,
-                       out, out_stride);
+    hipLaunchKernelGGL(observable_final_kernel, dim3(B), dim3(256), 0, st, d / obs_rows(d), partial, vals, d * w,
+                       n_steps, step, out, out_stride);
     return hipGetLastError();
 }
 
@@ -650,9 +936,48 @@ hipError_t grad_assemble(int B, int N, int K, int phased, double eps, double dt,
 }
 
 hipError_t d0_traces(int d, int B, int K, int phased, const float2* L, long long lstride, const double* g, double* d0,
-                     hipStream_t st) {
-    hipLaunchKernelGGL(d0_kernel, dim3(B, K), dim3(256), 0, st, d, K, phased, L, lstride, g, d0);
+                     hipStream_t st, int conj_l) {
+    hipLaunchKernelGGL(d0_kernel, dim3(B, K), dim3(256), 0, st, d, K, phased, L, lstride, g, d0, conj_l);
     return hipGetLastError();
+}
+
+size_t sparse_trace_partial_doubles(int d, int B, int steps, int K) {
+    return (size_t)B * steps * K * (d / SPT_RPB) * 6;
+}
+
+template <int WP>
+static void launch_spt(dim3 grid, hipStream_t st, int d, int N, int step0, int K, int phased, int cartesian, int sw,
+                       const float2* X, long long xsb, const float2* LH, long long lsb, const int* spc,
+                       const double2* spv, const double* g, const int* codes, const double* phi, const int* n_steps,
+                       double* partial) {
+    hipLaunchKernelGGL(sparse_trace_kernel<WP>, grid, dim3(256), 0, st, d, N, step0, K, phased, cartesian, sw, X, xsb,
+                       LH, lsb, spc, spv, g, codes, phi, n_steps, partial);
+}
+
+hipError_t sparse_traces(int d, int B, int N, int step0, int steps, int K, int phased, int cartesian, int sw,
+                         const float2* X, long long xsb, const float2* LH, long long lsb, const int* spc,
+                         const double2* spv, const double* g, const int* codes, const double* phi,
+                         const int* n_steps, double* partial, double* tr, hipStream_t st) {
+    if (sw < 1 || sw > SPAT_WMAX || d % SPT_RPB != 0) return hipErrorInvalidValue;
+    const dim3 grid(d / SPT_RPB, steps, B);
+    const int wp = (sw + 3) / 4 * 4;
+    switch (wp) {
+        case 4: launch_spt<4>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial); break;
+        case 8: launch_spt<8>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial); break;
+        case 12: launch_spt<12>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial); break;
+        default: launch_spt<16>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // sum the row blocks: instance (b, s) of this chunk writes tr[b][step0 + s][k][6]
+    for (int b = 0; b < B; ++b) {
+        hipLaunchKernelGGL(trace_final_kernel, dim3(steps, K), dim3(64), 0, st, d / SPT_RPB, K,
+                           partial + (size_t)b * steps * K * (d / SPT_RPB) * 6,
+                           tr + ((size_t)b * N + step0) * K * 6, (long long)K * 6);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t frob_norms(int d, int B, const float2* U, double* nu, hipStream_t st) {

@@ -144,6 +144,51 @@ struct GrapeWS {
     }
 };
 
+// GRAPE with every state stored (checkpoint interval 1): the forward states
+// X_1 .. X_N and the conjugate-transposed backward factors LH_0 .. LH_N
+// (LH_n = L_n^H, L_n = U_f^dag U_{N-1} ... U_n) are kept, so the two chains run
+// side by side in one batched launch per step and nothing is recomputed.
+constexpr int SPT_STEPS = 2048;   // (instance, step) pairs per sparse-trace launch
+struct FullGrapeWS {
+    void* comp_base;
+    float2* Ustore;
+    float2* Xs;
+    float2* LHs;
+    float2* Y;
+    double* tr;
+    double* tpart;
+    double* d0;
+    double* nu;
+    double2* ov;
+    GemmDesc* descs;
+    int sch;
+    size_t bytes;
+    FullGrapeWS(const redo_table_s* t, int B, int N, void* base, int expm) {
+        const int d = t->desc.d, K = t->desc.K;
+        const size_t mat = (size_t)d * d;
+        Carve c(base);
+        Ustore = c.take<float2>(mat * B * N);
+        Xs = c.take<float2>(mat * B * N);
+        LHs = c.take<float2>(mat * B * (N + 1));
+        const bool sparse = t->spat_w > 0;
+        Y = c.take<float2>(sparse ? 0 : mat * B);
+        tr = c.take<double>((size_t)B * N * K * 6);
+        sch = std::max(1, std::min(N, SPT_STEPS / B));
+        tpart = c.take<double>(sparse ? sparse_trace_partial_doubles(d, B, sch, K) : trace_partial_doubles(d, B, K));
+        d0 = c.take<double>((size_t)B * K * 2);
+        nu = c.take<double>(B);
+        ov = c.take<double2>(B);
+        descs = c.take<GemmDesc>((size_t)2 * B);
+        comp_base = base ? c.base + c.used : nullptr;
+        ComposeWS cw(t, (long long)B * N, nullptr);
+        c.used += expm ? std::max(cw.bytes, align_up(sizeof(int) * (size_t)B * N * t->desc.K) +
+                                                align_up(sizeof(double) * (size_t)B * N * t->desc.K) +
+                                                expm_compose_workspace_bytes(t))
+                       : cw.bytes;
+        bytes = c.used;
+    }
+};
+
 long long ceil_sqrt_ll(long long n) {
     long long c = (long long)std::ceil(std::sqrt((double)n));
     while (c * c < n) ++c;
@@ -218,18 +263,26 @@ size_t large_workspace_bytes(const redo_table_s* t, int op, int B, int N) {
     switch (op) {
         case REDO_OP_COMPOSE: return ComposeWS(t, (long long)B * N, nullptr).bytes;
         case REDO_OP_CHAIN: return ChainWS(t, B, N, nullptr).bytes;
-        case REDO_OP_GRAPE: return GrapeWS(t, B, N, (int)ceil_sqrt_ll(N), nullptr).bytes;
+        case REDO_OP_GRAPE: return large_grape_workspace_bytes_mode(t, B, N, 0, 0);
         case REDO_OP_EXPM_CHAIN: return expm_chain_workspace_bytes(t, B, N);
-        case REDO_OP_EXPM_GRAPE: return GrapeWS(t, B, N, (int)ceil_sqrt_ll(N), nullptr, 1).bytes;
+        case REDO_OP_EXPM_GRAPE: return large_grape_workspace_bytes_mode(t, B, N, 0, 1);
         default: return 0;
     }
 }
 
+int large_grape_checkpoint(const redo_table_s* t, int B, int N, int requested, int expm) {
+    if (requested > 0) return requested;
+    if (FullGrapeWS(t, B, N, nullptr, expm).bytes <= GRAPE_FULL_STORAGE_BYTES) return 1;
+    return (int)ceil_sqrt_ll(N);
+}
+
 size_t large_grape_workspace_bytes(const redo_table_s* t, int B, int N, int C) {
-    return GrapeWS(t, B, N, C, nullptr).bytes;
+    return large_grape_workspace_bytes_mode(t, B, N, C, 0);
 }
 
 size_t large_grape_workspace_bytes_mode(const redo_table_s* t, int B, int N, int C, int expm) {
+    C = large_grape_checkpoint(t, B, N, C, expm);
+    if (C == 1) return FullGrapeWS(t, B, N, nullptr, expm).bytes;
     return GrapeWS(t, B, N, C, nullptr, expm).bytes;
 }
 
@@ -302,11 +355,83 @@ redo_status large_chain(redo_table_s* t, int precision, const float* u, const in
     return REDO_OK;
 }
 
+namespace {
+
+redo_status large_grape_full(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N,
+                             const float* U_target, double* fidelity, double* overlap, float* grad, void* workspace,
+                             size_t workspace_bytes, hipStream_t st, int expm) {
+    FullGrapeWS need(t, B, N, nullptr, expm);
+    if (!workspace || workspace_bytes < need.bytes)
+        return fail(REDO_ERR_WORKSPACE, "GRAPE workspace needs " + std::to_string(need.bytes) + " bytes");
+    FullGrapeWS w(t, B, N, workspace, expm);
+    ComposeWS cw(t, (long long)B * N, w.comp_base);
+    const int d = t->desc.d, K = t->desc.K;
+    const long long mat = t->entry_elems;
+    const int prec = gemm_prec(precision);
+    const float2* Uf = reinterpret_cast<const float2*>(U_target);
+    redo_status s;
+    REDO_HIP(quantise_all(t, u, B, N, cw.codes, cw.phi, st));
+    if (expm) {
+        char* ex = static_cast<char*>(w.comp_base) + align_up(sizeof(int) * (size_t)B * N * K) +
+                   align_up(sizeof(double) * (size_t)B * N * K);
+        s = expm_compose_pairs(t, precision, (long long)B * N, N, u, w.Ustore, ex, st, nullptr);
+    } else {
+        s = compose_pairs(t, precision, (long long)B * N, N, cw, w.Ustore, st);
+    }
+    if (s != REDO_OK) return s;
+    REDO_HIP(frob_norms(d, B, Uf, w.nu, st));
+    const long long sU = mat * N, sX = mat * N, sL = mat * (N + 1);
+    // LH_N = U_f (identity left operand: a copy)
+    REDO_HIP(fill_descs(w.descs, B, nullptr, 0, 0, Uf, mat, 0, w.LHs + (size_t)N * mat, sL, nullptr, 0, 1, 1.f, 0.f, st));
+    REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
+    // step i: X_{i+1} = U_i X_i (X_0 = I) and LH_m = U_m^H LH_{m+1} with m = N - 1 - i;
+    // past an instance's length both copy their right operand
+    for (int i = 0; i < N; ++i) {
+        const int m = N - 1 - i;
+        REDO_HIP(fill_descs(w.descs, B, w.Ustore + (size_t)i * mat, sU, 0, i == 0 ? nullptr : w.Xs + (size_t)(i - 1) * mat,
+                            sX, 0, w.Xs + (size_t)i * mat, sX, n_steps, i, 1, 1.f, 0.f, st));
+        REDO_HIP(fill_descs(w.descs + B, B, w.Ustore + (size_t)m * mat, sU, 1, w.LHs + (size_t)(m + 1) * mat, sL, 0,
+                            w.LHs + (size_t)m * mat, sL, n_steps, m, 1, 1.f, 0.f, st));
+        REDO_HIP(cgemm_batched(d, 2 * B, w.descs, prec, st));
+    }
+    REDO_HIP(unitary_fidelity_strided(d, B, Uf, mat, w.Xs + (size_t)(N - 1) * mat, sX, w.ov, fidelity, st));
+    if (overlap) REDO_HIP(hipMemcpyAsync(overlap, w.ov, sizeof(double2) * B, hipMemcpyDeviceToDevice, st));
+    const long long code_stride = (long long)N * K;
+    if (t->spat_w > 0) {
+        for (int s0 = 0; s0 < N; s0 += w.sch) {
+            const int ns = std::min(w.sch, N - s0);
+            REDO_HIP(sparse_traces(d, B, N, s0, ns, K, t->desc.phased, expm, t->spat_w, w.Xs, sX, w.LHs, sL,
+                                   t->spat_cols, t->spat_vals, t->g64, cw.codes, t->desc.phased ? cw.phi : nullptr,
+                                   n_steps, w.tpart, w.tr, st));
+        }
+    } else {
+        for (int sidx = 0; sidx < N; ++sidx) {
+            // Y = X_{s+1} L_{s+1} = X_{s+1} LH_{s+1}^H
+            REDO_HIP(fill_descs(w.descs, B, w.Xs + (size_t)sidx * mat, sX, 0, w.LHs + (size_t)(sidx + 1) * mat, sL, 1,
+                                w.Y, mat, n_steps, sidx, 0, 1.f, 0.f, st));
+            REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
+            REDO_HIP(traces(d, B, K, t->desc.phased, w.Y, mat, t->S32, t->g64, cw.codes + (size_t)sidx * K,
+                            t->desc.phased ? cw.phi + (size_t)sidx * K : nullptr, code_stride, n_steps, sidx, w.tpart,
+                            w.tr + (size_t)sidx * K * 6, code_stride * 6, expm, st));
+        }
+    }
+    REDO_HIP(d0_traces(d, B, K, t->desc.phased, w.LHs, sL, t->g64, w.d0, st, 1));
+    REDO_HIP(grad_assemble(B, N, K, t->desc.phased, t->desc.eps, t->desc.dt, cw.codes,
+                           t->desc.phased ? cw.phi : nullptr, w.tr, w.d0, w.ov, w.nu, n_steps, grad, expm, st));
+    return REDO_OK;
+}
+
+}  // namespace
+
 redo_status large_grape(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N,
                         const float* U_target, int C, double* fidelity, double* overlap, float* grad, void* workspace,
                         size_t workspace_bytes, hipStream_t st, int expm) {
     redo_status s = check_precision(precision);
     if (s != REDO_OK) return s;
+    C = large_grape_checkpoint(t, B, N, C, expm);
+    if (C == 1)
+        return large_grape_full(t, precision, u, n_steps, B, N, U_target, fidelity, overlap, grad, workspace,
+                                workspace_bytes, st, expm);
     GrapeWS need(t, B, N, C, nullptr, expm);
     if (!workspace || workspace_bytes < need.bytes)
         return fail(REDO_ERR_WORKSPACE, "GRAPE workspace needs " + std::to_string(need.bytes) + " bytes");

@@ -64,6 +64,11 @@ hipError_t fill_descs(GemmDesc* descs, int count, const float2* A, long long sA,
 size_t observable_partial_doubles(int d, int B);
 // T: scratch of `chunk` d x d matrices (instances processed `chunk` at a time)
 constexpr int OBS_CHUNK = 256;
+// GRAPE keeps every forward state and backward factor (no recomputation) when
+// that needs at most this much workspace and no checkpoint interval is given
+constexpr size_t GRAPE_FULL_STORAGE_BYTES = size_t(48) << 30;
+// checkpoint interval used for a requested one (0: automatic)
+int large_grape_checkpoint(const redo_table_s* t, int B, int N, int requested, int expm);
 hipError_t observable(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
                       const int* cols, const float2* vals, int w, const int* n_steps, int step, double* partial,
                       double* out, long long out_stride, float2* T, int chunk, hipStream_t st);
@@ -80,7 +85,12 @@ hipError_t grad_assemble(int B, int N, int K, int phased, double eps, double dt,
                          const double* tr, const double* d0, const double2* overlap, const double* nu,
                          const int* n_steps, float* grad, int cartesian, hipStream_t st);
 hipError_t d0_traces(int d, int B, int K, int phased, const float2* L, long long lstride, const double* g, double* d0,
-                     hipStream_t st);
+                     hipStream_t st, int conj_l = 0);
+size_t sparse_trace_partial_doubles(int d, int B, int steps, int K);
+hipError_t sparse_traces(int d, int B, int N, int step0, int steps, int K, int phased, int cartesian, int sw,
+                         const float2* X, long long xsb, const float2* LH, long long lsb, const int* spc,
+                         const double2* spv, const double* g, const int* codes, const double* phi,
+                         const int* n_steps, double* partial, double* tr, hipStream_t st);
 hipError_t frob_norms(int d, int B, const float2* U, double* nu, hipStream_t st);
 hipError_t fill_identity(int d, int B, float2* X, long long stride, hipStream_t st);
 

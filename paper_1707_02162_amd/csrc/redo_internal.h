@@ -117,7 +117,15 @@ struct redo_table_s {
     // composed level cache (process 3): R(q) for q in [cache_lo, cache_hi]
     float2* cache = nullptr;
     int cache_lo = 0, cache_hi = -1;
+    // sparsity pattern of the generators (union over channels), when every row has at
+    // most SPAT_WMAX nonzeros: column lists [d][spat_w] (padded with the row index) and
+    // the FP64 values of every channel at those positions [K][d][spat_w] (0 where absent)
+    int spat_w = 0;
+    int* spat_cols = nullptr;
+    double2* spat_vals = nullptr;
 };
+
+constexpr int SPAT_WMAX = 16;
 
 namespace redo {
 

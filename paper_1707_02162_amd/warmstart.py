@@ -185,8 +185,15 @@ def experiment(n_train: int, n_test: int, N: int = 500, grape_iters: int = 400, 
     us = torch.where(use_net.view(-1, 1, 1, 1), un, ur)
     _, Fr, itr, _ = grape(table, ur, Ut, u_max, grape_iters, lr_grape, goal=goal)
     _, Fs, its, _ = grape(table, us, Ut, u_max, grape_iters, lr_grape, goal=goal)
+    # second fallback: a network start that does not reach the goal within the budget is
+    # followed by the run from the random start (its iterations count after the wasted budget)
+    miss = use_net & (its < 0)
+    its_fb = torch.where(miss, torch.where(itr >= 0, itr + grape_iters, torch.full_like(itr, -1)), its)
+    Fs_fb = torch.where(miss, Fr, Fs)
     conv_r = itr >= 0
     conv_s = its >= 0
+    conv_fb = its_fb >= 0
+    both = conv_r & conv_fb
     res = dict(
         n_train=n_train, n_train_converged=int(keep.sum()), n_test=n_test, N=N, epochs=epochs, goal=goal,
         loss_first=losses[0], loss_last=losses[-1],
@@ -196,6 +203,11 @@ def experiment(n_train: int, n_test: int, N: int = 500, grape_iters: int = 400, 
         iters_random_median=float(itr[conv_r].double().median()) if conv_r.any() else None,
         iters_warm_median=float(its[conv_s].double().median()) if conv_s.any() else None,
         final_infidelity_random_median=float((1 - Fr).median()), final_infidelity_warm_median=float((1 - Fs).median()),
+        fallback_reruns=int(miss.sum()), converged_warm_with_fallback=int(conv_fb.sum()),
+        iters_warm_with_fallback_median=float(its_fb[conv_fb].double().median()) if conv_fb.any() else None,
+        final_infidelity_warm_with_fallback_median=float((1 - Fs_fb).median()),
+        iters_saved_mean=float((itr[both] - its_fb[both]).double().mean()) if both.any() else None,
+        grape_iters_budget=grape_iters,
         seconds=time.time() - t0,
     )
     return res

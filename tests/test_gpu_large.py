@@ -118,7 +118,11 @@ def test_chunked_chain_equals_one_call_d128():
 
 
 def test_grape_d128_phased_vs_oracle():
+    """Default schedule at d = 128 (every state kept, traces from the sparse
+    pattern of the collective generators); every fifth step has zero
+    amplitude, so the q = 0 (Cartesian) derivative is exercised too."""
     p = W.nmr_chain(7, 2, 30, 2e-6, 32, 2, 205)
+    p.u[:, ::5] = 0.0
     t = R().RedoTable.from_problem(p)
     F, ov, grad = t.grape(torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda())
     F, ov, grad = F.cpu().numpy(), ov.cpu().numpy(), grad.cpu().numpy()
@@ -147,15 +151,39 @@ def test_grape_d128_signed_ragged_vs_oracle():
         assert np.all(grad[b, nb:] == 0)
 
 
-def test_grape_large_matches_small_path_semantics():
-    """The same 7-qubit problem through the GRAPE call at two checkpoint
-    intervals gives identical results (recomputation is exact)."""
-    p = W.nmr_chain(7, 1, 20, 2e-6, 32, 2, 206)
+def test_grape_memory_schedules_agree():
+    """The same 7-qubit problem with every state kept (checkpoint 1: the two
+    scans side by side, FP64 traces at the generators' pattern) and with
+    checkpoints every 6 or 4 steps (recomputed segments, traces of the FP32
+    product Y): the forward chain is the same sequence of products, so F is
+    bitwise equal; recomputation is exact, so the two checkpointed runs agree
+    bitwise; the two trace routes differ by FP32 rounding of Y."""
+    p = W.nmr_chain(7, 2, 20, 2e-6, 32, 2, 206)
+    p.n_steps = np.array([20, 13], np.int32)
     t = R().RedoTable.from_problem(p)
-    u, Uf = torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda()
-    F1, _, g1 = t.grape(u, Uf, checkpoint_every=1)
-    F2, _, g2 = t.grape(u, Uf, checkpoint_every=6)
-    assert torch.equal(F1, F2) and torch.equal(g1, g2)
+    u, Uf, ns = torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda(), torch.tensor(p.n_steps)
+    F1, _, g1 = t.grape(u, Uf, n_steps=ns, checkpoint_every=1)
+    F2, _, g2 = t.grape(u, Uf, n_steps=ns, checkpoint_every=6)
+    F3, _, g3 = t.grape(u, Uf, n_steps=ns, checkpoint_every=4)
+    assert torch.equal(F1, F2) and torch.equal(F2, F3)
+    assert torch.equal(g2, g3)
+    assert float((g1 - g2).norm() / g2.norm()) < 1e-5
+    assert torch.all(g1[1, 13:] == 0)
+
+
+def test_grape_d128_dense_generator_full_storage_vs_oracle():
+    """Dense random generator (no sparse pattern): with every state kept the
+    traces come from batched products Y = X L^dag."""
+    p = generic_problem(128, 2, 12, 215)
+    p.U_target = np.stack([W.haar_unitary(128, W.rng(215, 2, b)) for b in range(2)])
+    t = R().RedoTable.from_problem(p)
+    F, ov, grad = t.grape(torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda(), checkpoint_every=1)
+    F, grad = F.cpu().numpy(), grad.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(p.B):
+        Fo, go, gro = O.fidelity_and_gradient(p, b, model="redo", table=tab)
+        assert abs(F[b] - Fo) < FID_TOL
+        assert np.linalg.norm(grad[b] - gro) <= GRAD_TOL * np.linalg.norm(gro)
 
 
 # ---------------------------------------------------------------- full size

@@ -65,6 +65,8 @@ def test_warm_start_small_run_reports_gain():
     print(json.dumps(res))
     assert res["n_train_converged"] > 0
     assert res["loss_last"] < res["loss_first"]
-    # the fallback picks whichever start is better, so the warm run never starts worse
-    assert res["start_infidelity_net_median"] >= 0.0
-    assert res["converged_warm"] >= 0
+    # what the trained network gains: its proposal starts closer to the target than the
+    # random start for most held-out targets
+    assert res["net_start_used"] > res["n_test"] // 2
+    # with both fallbacks every target the random start solves is solved
+    assert res["converged_warm_with_fallback"] >= res["converged_random"]
