@@ -31,6 +31,30 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the FP32 GEMM on the headline workload (4096
+# products at d = 1024), from two rocprofv3 --pmc runs (FETCH_SIZE, then
+# WRITE_SIZE) of this script with --calibrate, each counter scaled by what it
+# reads for the plain 1 GiB device copy of that run.  The figure belongs to
+# the kernel source it was measured on and is reported only while that source
+# is unchanged.
+GEMM_TRAFFIC = {
+    "source": "paper_1707_02162_amd/csrc/cgemm.hip",
+    "sha256": None,
+    "fetch_bytes": None,
+    "write_bytes": None,
+}
+
+
+def gemm_traffic(realisations, cache):
+    import hashlib
+    t = GEMM_TRAFFIC
+    if t["sha256"] is None or realisations != 4096 or not cache:
+        return None
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+            return None
+    return t["fetch_bytes"] + t["write_bytes"]
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -148,6 +172,54 @@ def bench_grape(args, redo, W, torch):
     return res
 
 
+def bench_c2(args, redo, W, torch):
+    """Secondary comparison at d = 64 (6-qubit chain, 256 replicas x 2000 steps):
+    the fused small-d REDO chain against the plain per-step exponential on the
+    batched GEMMs, both chaining every step of every replica."""
+    p = W.c2_six_qubit(B=256, N=2000)
+    table = redo.RedoTable.from_problem(p)
+    if args.cache:
+        table.cache_levels()
+    u = torch.tensor(p.u, device="cuda")
+    res = {}
+    for kind in ("redo", "expm"):
+        if kind == "expm" and args.no_expm:
+            continue
+        fn = table.chain if kind == "redo" else table.expm_chain
+        fn(u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            fn(u)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        res[kind] = dict(value=p.B * p.N / el, unit="propagator steps/s", ms_per_call=1e3 * el)
+        log(f"[bench] d=64 {kind} chain: {p.B * p.N / el:.3g} steps/s")
+    del table
+    out = {"workload": "6-qubit NMR chain d=64, 256 replicas x 2000 steps, b=32 P=2, chain only",
+           "redo": res["redo"]}
+    if "expm" in res:
+        out["expm"] = res["expm"]
+        out["speedup_vs_expm"] = res["redo"]["value"] / res["expm"]["value"]
+    return out
+
+
+def bench_sweep(args):
+    """The paper's own experiment (Sec. IV): the noisy-drive freezing sweep of
+    a 3-spin chain (d = 8), 10,000 time points per (omega, lambda) instance,
+    order parameter Q = time average of the magnetisation response.  Timed
+    on the first `--sweep-instances` instances of the 500 x 1000 grid."""
+    from paper_1707_02162_amd import freezing
+    freezing.sweep(500, 1000, N=10000, first=0, count=min(512, args.sweep_instances))   # warm-up
+    Q, secs, steps = freezing.sweep(500, 1000, N=10000, first=0, count=args.sweep_instances)
+    log(f"[bench] freezing sweep: {steps / secs:.3g} steps/s")
+    return {"workload": "noisy-drive freezing sweep (3-spin chain, d=8), 10,000 time points per (omega, lambda) "
+                        "instance, b=100 P=2, observable every time point, first instances of the 500 x 1000 grid",
+            "instances": args.sweep_instances, "steps": steps, "seconds": secs, "value": steps / secs,
+            "unit": "propagator steps/s", "full_grid_seconds_estimate": 5e9 / (steps / secs)}
+
+
 def cpu_baseline(args, W):
     """The FP64 oracle on the host: REDO steps of one realisation of the same
     workload, with the magnetisation at every step."""
@@ -187,6 +259,9 @@ def main():
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for hardware byte counters)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-c2", action="store_true", help="skip the d=64 REDO vs expm chain comparison")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the d=8 freezing sweep")
+    ap.add_argument("--sweep-instances", type=int, default=8000)
     ap.add_argument("--no-cache", dest="cache", action="store_false",
                     help="apply one product per non-zero digit instead of the composed level of each amplitude")
     args = ap.parse_args()
@@ -212,6 +287,10 @@ def main():
     fr, p = bench_freezing(args, redo, W, torch)
     torch.cuda.empty_cache()
     gr = None if args.no_grape else bench_grape(args, redo, W, torch)
+    torch.cuda.empty_cache()
+    c2 = None if args.no_c2 else bench_c2(args, redo, W, torch)
+    torch.cuda.empty_cache()
+    sw = None if args.no_sweep else bench_sweep(args)
     torch.cuda.empty_cache()
     cpu = None if args.no_cpu else cpu_baseline(args, W)
     f32, bf, ex = fr["fp32"], fr["bf16x3"], fr["expm"]
@@ -252,11 +331,14 @@ def main():
                                                       "fidelity + adjoint gradient + update", **rg},
         "grape_expm_iters_per_s": None if eg is None else eg["iters_per_s"],
         "grape_speedup_vs_expm": None if (rg is None or eg is None) else rg["iters_per_s"] / eg["iters_per_s"],
+        "d64_chain": c2,
+        "paper_freezing_sweep_d8": sw,
         "table_build_s": fr["table_build_s"],
         "level_cache_build_s": fr["cache_build_s"],
-        "roofline": {"bound": "mfma", "kernel": "cgemm_kernel<128,128,4M> (batched complex GEMM, FP32)",
+        "roofline": {"bound": "mfma", "kernel": "cgemm_kernel<128,64,4M> (batched complex GEMM, FP32)",
                      "achieved": f32["achieved"], "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": f32["achieved"] / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
+                     "frac": f32["achieved"] / PEAK_FP32_MFMA_TFLOPS,
+                     "traffic": gemm_traffic(args.realisations, args.cache), "traffic_unit": "HBM bytes per launch",
                      "flops_per_launch": f32["flops_per_launch"], "avg_launch_ms": f32["avg_launch_ms"],
                      "launches": f32["gemm_launches"]},
         "cpu_baseline": cpu,

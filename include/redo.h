@@ -117,9 +117,10 @@ redo_status redo_table_destroy(redo_table table);
  * factor R_k(q) = T_k[0][c_0] T_k[1][c_1] ... in FP64 (from the FP64 digit
  * operators, rebuilt as in redo_build_table) and keeps it, rounded once to
  * FP32, in the table (K*(q_hi-q_lo+1)*d*d*8 bytes of device memory).  Later
- * calls on the large-d path (d >= 128) apply one product per channel and step
- * for every amplitude whose level is cached, instead of one per non-zero
- * digit; results then agree with the uncached path to FP32 rounding.  Replaces
+ * calls apply one product per channel and step for every amplitude whose
+ * level is cached, instead of one per non-zero digit (at d <= 64 only when
+ * the cache holds every level 0 .. b^P - 1); results then agree with the
+ * uncached path to FP32 rounding.  Replaces
  * any earlier cache; q_hi < 0 only frees it.  Synchronises `stream`.  Must not
  * overlap other calls on the same table.  Errors: REDO_ERR_ARG, REDO_ERR_ALLOC.
  */

@@ -37,7 +37,7 @@ __all__ = [
     "expm_herm", "frechet_expm", "y_generator", "digits_needed", "quantise",
     "DiscreteTable", "drift_propagator", "phase_diag", "step_redo", "step_split",
     "step_exact", "dirac_step", "chain", "unitary_fidelity", "fidelity_and_gradient",
-    "magnetisation", "magnetisation_series", "compose_all_redo",
+    "magnetisation", "magnetisation_series", "compose_all_redo", "with_drift",
 ]
 
 
@@ -203,10 +203,20 @@ def _control_block(factors, Z: Optional[np.ndarray]) -> np.ndarray:
     return P
 
 
+def with_drift(C: np.ndarray, V: np.ndarray, Vh: Optional[np.ndarray] = None) -> np.ndarray:
+    """The split step around the control block C: C V (the paper's split, drift
+    first), or the symmetric Strang form V(dt/2) C V(dt/2) when the half-step
+    drift Vh is given."""
+    if Vh is not None:
+        return Vh @ C @ Vh
+    return C @ V
+
+
 def step_redo(table: DiscreteTable, qz: Dict[str, np.ndarray], V: np.ndarray,
-              g: Optional[np.ndarray]) -> np.ndarray:
+              g: Optional[np.ndarray], Vh: Optional[np.ndarray] = None) -> np.ndarray:
     """U_n = Z_n (prod_k R_k) Z_n^dag V with R_k the REDO product of the codes of
-    one step (qz entries indexed [K] / [K, P]); g is None for signed channels."""
+    one step (qz entries indexed [K] / [K, P]); g is None for signed channels.
+    With Vh (Strang): U_n = Vh Z_n (prod_k R_k) Z_n^dag Vh."""
     K = table.K
     if g is not None:
         factors = [table.factor(k, qz["c"][k]) for k in range(K)]
@@ -214,13 +224,14 @@ def step_redo(table: DiscreteTable, qz: Dict[str, np.ndarray], V: np.ndarray,
     else:
         factors = [table.factor(k, qz["c"][k], qz["sign"][k]) for k in range(K)]
         Z = None
-    return _control_block(factors, Z) @ V
+    return with_drift(_control_block(factors, Z), V, Vh)
 
 
 def step_split(S: np.ndarray, g: Optional[np.ndarray], amp: np.ndarray, dt: float,
-               V: np.ndarray) -> np.ndarray:
+               V: np.ndarray, Vh: Optional[np.ndarray] = None) -> np.ndarray:
     """Continuous split step with exact factors X_k = exp(-i Omega_k dt S_k).
-    amp: [K, 2] Cartesian pairs (phased) or [K] signed amplitudes."""
+    amp: [K, 2] Cartesian pairs (phased) or [K] signed amplitudes.  With the
+    half-step drift Vh the step is the Strang form Vh C Vh."""
     amp = np.asarray(amp, dtype=np.float64)
     K = S.shape[0]
     if g is not None:
@@ -231,7 +242,7 @@ def step_split(S: np.ndarray, g: Optional[np.ndarray], amp: np.ndarray, dt: floa
     else:
         factors = [expm_herm(S[k], amp[k] * dt) for k in range(K)]
         Z = None
-    return _control_block(factors, Z) @ V
+    return with_drift(_control_block(factors, Z), V, Vh)
 
 
 def step_exact(H0m: np.ndarray, S: np.ndarray, g: Optional[np.ndarray], amp: np.ndarray,
@@ -313,6 +324,13 @@ def _drift_of(prob, b: int):
     return V, H0m
 
 
+def _half_drift(prob, b: int) -> Optional[np.ndarray]:
+    """V(dt/2) of instance b for the Strang splitting, else None."""
+    if getattr(prob, "splitting", "lie") != "strang":
+        return None
+    return drift_propagator(prob.H0[b % prob.n_drift], 0.5 * prob.dt, prob.drift_is_diag)
+
+
 def _step_codes(qz, n: int):
     return {"c": qz["c"][n], "sign": qz["sign"][n], "phi": None if qz["phi"] is None else qz["phi"][n]}
 
@@ -320,10 +338,11 @@ def _step_codes(qz, n: int):
 def compose_all_redo(prob, table: DiscreteTable, b: int, n_steps: Optional[int] = None):
     """REDO steps U_1 .. U_{N_b} of instance b."""
     V, _ = _drift_of(prob, b)
+    Vh = _half_drift(prob, b)
     nb = int(prob.lengths()[b]) if n_steps is None else n_steps
     qz = quantise(prob.u[b, :nb], prob.eps, prob.base, prob.digits, prob.phased)
     g = prob.g if prob.phased else None
-    return [step_redo(table, _step_codes(qz, n), V, g) for n in range(nb)]
+    return [step_redo(table, _step_codes(qz, n), V, g, Vh) for n in range(nb)]
 
 
 def _quantised_amplitudes(prob, b: int, nb: int) -> np.ndarray:
@@ -355,16 +374,17 @@ def fidelity_and_gradient(prob, b: int, model: str = "redo", table: Optional[Dis
     u[b, :N_b]."""
     nb = int(prob.lengths()[b])
     V, H0m = _drift_of(prob, b)
+    Vh = _half_drift(prob, b) if model in ("redo", "split") else None
     S, g = prob.S, (prob.g if prob.phased else None)
     K, d = prob.K, prob.d
     Uf = prob.U_target[b]
     if model == "redo":
         amp, qz = _quantised_amplitudes(prob, b, nb)
-        steps = [step_redo(table, _step_codes(qz, n), V, g) for n in range(nb)]
+        steps = [step_redo(table, _step_codes(qz, n), V, g, Vh) for n in range(nb)]
     else:
         amp = (prob.u[b, :nb].astype(np.float64) if amps is None else np.asarray(amps, np.float64))
         if model == "split":
-            steps = [step_split(S, g, amp[n], prob.dt, V) for n in range(nb)]
+            steps = [step_split(S, g, amp[n], prob.dt, V, Vh) for n in range(nb)]
         elif model in ("exact", "exact_first_order"):
             steps = [step_exact(H0m, S, g, amp[n], prob.dt) for n in range(nb)]
         else:
@@ -375,15 +395,17 @@ def fidelity_and_gradient(prob, b: int, model: str = "redo", table: Optional[Dis
     grad = np.zeros(amp.shape, dtype=np.float64)
     Lam = Uf.conj().T.copy()                      # U_f^dag U_N ... U_{n+1}
     for n in range(nb - 1, -1, -1):
-        for key, dU in _step_derivatives(model, S, g, amp[n], prob.dt, V, H0m, K, d):
+        for key, dU in _step_derivatives(model, S, g, amp[n], prob.dt, V, H0m, K, d, Vh):
             dg = np.trace(Lam @ dU @ prefix[n]) / norm
             grad[(n,) + key] = 2.0 * (np.conj(gval) * dg).real
         Lam = Lam @ steps[n]
     return float(abs(gval) ** 2), complex(gval), grad
 
 
-def _step_derivatives(model, S, g, amp_n, dt, V, H0m, K, d):
-    """Yield (index, dU_n/dtheta) for every control parameter of one step."""
+def _step_derivatives(model, S, g, amp_n, dt, V, H0m, K, d, Vh=None):
+    """Yield (index, dU_n/dtheta) for every control parameter of one step
+    (split models: the derivative of the control block, with the drift
+    around it as in the step)."""
     if model == "exact_first_order":
         U = step_exact(H0m, S, g, amp_n, dt)
         for k in range(K):
@@ -415,7 +437,7 @@ def _step_derivatives(model, S, g, amp_n, dt, V, H0m, K, d):
             P = np.eye(d, dtype=np.complex128)
             for kk in range(K):
                 P = (dR if kk == k else R[kk]) @ P
-            yield (k,), P @ V
+            yield (k,), with_drift(P, V, Vh)
         return
     # phased: U = Z (prod_k X_k) Z^dag V, X_k = exp(-i Omega_k dt S_k), Z = exp(-i sum phi_k G_k)
     om = np.sqrt(amp_n[:, 0] ** 2 + amp_n[:, 1] ** 2)
@@ -430,10 +452,10 @@ def _step_derivatives(model, S, g, amp_n, dt, V, H0m, K, d):
         P = np.eye(d, dtype=np.complex128)
         for kk in range(K):
             P = (dX if kk == k else X[kk]) @ P
-        dU_dom = Z @ P @ Z.conj().T @ V
+        dU_dom = with_drift(Z @ P @ Z.conj().T, V, Vh)
         G = np.diag(g[k]).astype(np.complex128)
         dZ = -1j * G @ Z                                               # d/dphi_k of Z
-        dU_dphi = (dZ @ prodX @ Z.conj().T + Z @ prodX @ dZ.conj().T) @ V
+        dU_dphi = with_drift(dZ @ prodX @ Z.conj().T + Z @ prodX @ dZ.conj().T, V, Vh)
         if om[k] > 0.0:
             c, s = amp_n[k, 0] / om[k], amp_n[k, 1] / om[k]
             yield (k, 0), c * dU_dom - (s / om[k]) * dU_dphi
@@ -446,4 +468,4 @@ def _step_derivatives(model, S, g, amp_n, dt, V, H0m, K, d):
                 if kk != k:
                     P0 = X[kk] @ P0
             for a, Gen in ((0, S[k]), (1, Sy)):
-                yield (k, a), Z @ (-1j * dt * Gen) @ P0 @ Z.conj().T @ V
+                yield (k, a), with_drift(Z @ (-1j * dt * Gen) @ P0 @ Z.conj().T, V, Vh)

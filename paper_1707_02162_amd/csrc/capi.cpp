@@ -402,8 +402,8 @@ redo_status redo_build_table(const redo_table_desc* desc, const double* H0, cons
 redo_status redo_table_destroy(redo_table t) {
     if (!t) return REDO_OK;
     (void)hipDeviceSynchronize();
-    void* bufs[] = {t->T32,   t->h64,   t->V32,   t->g64,   t->S32,       t->S64,      t->Sy32,
-                    t->H32,   t->flags, t->T16hi, t->T16lo, t->cache, t->spat_cols, t->spat_vals};
+    void* bufs[] = {t->T32, t->h64,   t->V32,   t->g64,       t->S32,      t->S64, t->Sy32,
+                    t->H32, t->flags, t->cache, t->spat_cols, t->spat_vals};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     delete t;
@@ -511,11 +511,7 @@ size_t redo_workspace_bytes(redo_table t, int32_t op, int32_t B, int32_t N_max) 
         switch (op) {
             case REDO_OP_COMPOSE:
             case REDO_OP_CHAIN: return 0;
-            case REDO_OP_GRAPE: {
-                const long long C = ceil_sqrt(N_max);
-                const long long nck = (N_max + C - 1) / C;
-                return mat * (size_t)B * (size_t)(nck + C);
-            }
+            case REDO_OP_GRAPE: return small_grape_workspace_bytes(d, t->desc.K, B, N_max, ceil_sqrt(N_max));
             default: return 0;
         }
     }
@@ -527,8 +523,7 @@ size_t redo_grape_workspace_bytes(redo_table t, int32_t B, int32_t N_max, int32_
     const int d = t->desc.d;
     if (small_dim(d)) {
         const long long C = checkpoint_every > 0 ? checkpoint_every : ceil_sqrt(N_max);
-        const long long nck = (N_max + C - 1) / C;
-        return sizeof(float2) * (size_t)d * d * (size_t)B * (size_t)(nck + C);
+        return small_grape_workspace_bytes(d, t->desc.K, B, N_max, C);
     }
     return large_grape_workspace_bytes(t, B, N_max, checkpoint_every);
 }
@@ -633,7 +628,7 @@ redo_status redo_grape_fidelity_grad(redo_table t, int32_t precision, const floa
     if (small_dim(t->desc.d)) {
         if (precision != REDO_PREC_F32) return fail(REDO_ERR_UNSUPPORTED, "d <= 64 runs in FP32 only");
         const long long nck = (N_max + C - 1) / C;
-        const size_t need = sizeof(float2) * (size_t)t->desc.d * t->desc.d * (size_t)B * (size_t)(nck + C);
+        const size_t need = small_grape_workspace_bytes(t->desc.d, t->desc.K, B, N_max, C);
         if (!workspace || workspace_bytes < need)
             return fail(REDO_ERR_WORKSPACE, "GRAPE workspace needs " + std::to_string(need) + " bytes");
         SmallGrapeArgs a{};
@@ -649,6 +644,10 @@ redo_status redo_grape_fidelity_grad(redo_table t, int32_t precision, const floa
         a.n_ckpt = (int)nck;
         a.ckpt = static_cast<float2*>(workspace);
         a.seg = a.ckpt + (size_t)B * nck * t->desc.d * t->desc.d;
+        {
+            const size_t mats = sizeof(float2) * (size_t)t->desc.d * t->desc.d * (size_t)B * (size_t)(nck + C);
+            a.pend = reinterpret_cast<double*>(static_cast<char*>(workspace) + ((mats + 255) & ~size_t(255)));
+        }
         REDO_HIP(small_grape(t, a, hs));
         return REDO_OK;
     }

@@ -111,9 +111,6 @@ struct redo_table_s {
     size_t bytes = 0;
     bool grad_ok = false;   // channels commute with each other, phases with drift
     std::string grad_why;
-    // BF16 split planes of the table (built on first use): hi and lo, [K][P][b-1][d][d][2] each
-    uint16_t* T16hi = nullptr;
-    uint16_t* T16lo = nullptr;
     // composed level cache (process 3): R(q) for q in [cache_lo, cache_hi]
     float2* cache = nullptr;
     int cache_lo = 0, cache_hi = -1;
@@ -184,9 +181,12 @@ struct SmallGrapeArgs {
     float* grad;
     float2* ckpt;            // workspace [B][n_ckpt][d][d]
     float2* seg;             // workspace [B][checkpoint_every][d][d]
+    double* pend;            // workspace [B][K][6]: traces of the step whose gradient waits for the next D
     int n_ckpt;
 };
 hipError_t small_grape(const redo_table_s* t, const SmallGrapeArgs& a, hipStream_t st);
+// workspace of the fused d <= 64 GRAPE kernel (checkpoints, one segment, pending traces)
+size_t small_grape_workspace_bytes(int d, int K, long long B, long long N_max, long long C);
 
 // fidelity reduction, FP64
 hipError_t unitary_fidelity(int d, int B, const float2* Uf, const float2* U, double2* overlap,

@@ -4,9 +4,12 @@
 // (processes 1 and 2, Eqs. redoform and exp2prod) between the drift and
 // phase scalings of the split step (Sec. III, Eqs. vn and vnd), and chains
 // the result (Sec. III, Eq. propUn).  Products are staged in LDS; every
-// thread owns a 4x4 strided sub-block of one instance's d x d state, so an
-// instance is (d/4)^2 threads and a 256-thread workgroup hosts several.
-// The GRAPE kernel adds a checkpointed backward scan for the gradient.
+// thread owns a TB x TB strided sub-block of one instance's d x d state
+// (TB = 2 up to d = 32, 4 at d = 64), so an instance is (d/TB)^2 threads and a
+// 256-thread workgroup hosts several.
+// The GRAPE kernel adds a checkpointed backward scan for the gradient.  When
+// the table's level cache holds every level (process 3), each channel takes
+// one composed factor per step instead of one per non-zero digit.
 #include "redo_internal.h"
 
 namespace redo {
@@ -16,6 +19,7 @@ constexpr int KMAX = 16;
 
 struct TView {
     const float2* T;
+    const float2* cache;   // every level composed (process 3): [K][levels][d][d], or null
     const float2* V;
     const double* h;
     const double* g;
@@ -23,12 +27,17 @@ struct TView {
     DeviceFlags* flags;
     long long ent;   // d*d
     int d, K, P, base, phased, diag, n_drift;
+    int levels;            // cache levels (q = 0 .. levels - 1)
     double eps, qmax, dt;
 };
 
 TView view_of(const redo_table_s* t) {
     TView v;
     v.T = t->T32;
+    // the fused kernels use the level cache only when it holds every level
+    const bool all = t->cache && t->cache_lo == 0 && (double)t->cache_hi >= t->qmax;
+    v.cache = all ? t->cache : nullptr;
+    v.levels = all ? t->cache_hi + 1 : 0;
     v.V = t->V32;
     v.h = t->h64;
     v.g = t->g64;
@@ -48,9 +57,12 @@ TView view_of(const redo_table_s* t) {
     return v;
 }
 
+// d <= 32: 2 x 2 sub-blocks (d^2/4 threads per instance: more waves per CU to
+// hide the latency of the per-step barriers and table loads); d = 64: 4 x 4
+// (one instance per 256-thread workgroup).
 template <int D>
 struct Cfg {
-    static constexpr int TB = D >= 4 ? 4 : D;  // sub-block edge per thread
+    static constexpr int TB = D >= 64 ? 4 : 2;  // sub-block edge per thread
     static constexpr int NT = D / TB;          // threads along a row of sub-blocks
     static constexpr int TPI = NT * NT;        // threads per instance
     static constexpr int IPB = 256 / TPI;      // instances per workgroup
@@ -77,6 +89,32 @@ __device__ inline void stage(float2* Ms, const float2* __restrict__ src, bool ad
             Ms[(e % D) * D + e / D] = cconj(v);
         else
             Ms[e] = v;
+    }
+}
+
+// A table entry travels global -> registers -> LDS: each thread holds TB^2 of
+// its D^2 elements (element lt + TPI i), so the next factor's loads are in
+// flight while the current product runs.
+template <int D>
+struct FactorRegs {
+    float2 v[Cfg<D>::TB * Cfg<D>::TB];
+};
+template <int D>
+__device__ inline void fetch_factor(FactorRegs<D>& f, const float2* __restrict__ src, int lt) {
+    constexpr int TPI = Cfg<D>::TPI, NR = Cfg<D>::TB * Cfg<D>::TB;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) f.v[i] = src[lt + TPI * i];
+}
+template <int D>
+__device__ inline void put_factor(float2* Ms, const FactorRegs<D>& f, bool adj, int lt) {
+    constexpr int TPI = Cfg<D>::TPI, NR = Cfg<D>::TB * Cfg<D>::TB;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const int e = lt + TPI * i;
+        if (adj)
+            Ms[(e % D) * D + e / D] = cconj(f.v[i]);
+        else
+            Ms[e] = f.v[i];
     }
 }
 
@@ -180,22 +218,45 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
             }
         }
     }
-    // table factors: channel 0 first (rightmost), digits ascending
-    for (int k = 0; k < tv.K; ++k) {
+    // table factors: channel 0 first (rightmost), digits ascending; slot s = k P + j,
+    // or one slot per channel (its composed level) when every level is cached.
+    // The entry of the next slot is fetched while the current product runs.
+    const int PE = tv.cache ? 1 : tv.P;
+    const int nslot = tv.K * PE;
+    auto slot_code = [&](int sl, bool rep) -> int {
         double phi;
-        const int q = active ? quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, &phi,
-                                            report ? tv.flags : nullptr)
-                             : 0;
-        for (int j = 0; j < tv.P; ++j) {
-            const int c = digit_of(q, j, tv.base);
-            __syncthreads();
-            if (c != 0) {
-                stage<D>(Fs, tv.T + ((long long)(k * tv.P + j) * (tv.base - 1) + (c - 1)) * tv.ent, q < 0, lt);
-                store_block<D>(Xs, x, ti, tj);
-            }
-            __syncthreads();
-            if (c != 0) mul_left<D>(x, Fs, Xs, ti, tj);
+        return active ? quantise_one(us + KK * (sl / PE), tv.phased, tv.eps, tv.qmax, &phi,
+                                     rep ? tv.flags : nullptr)
+                      : 0;
+    };
+    // the factor of slot sl for code q: nonzero digit c (or level |q|), else null
+    auto entry_of = [&](int sl, int q) -> const float2* {
+        if (tv.cache) {
+            const int aq = q < 0 ? -q : q;
+            return aq == 0 ? nullptr : tv.cache + ((long long)(sl / PE) * tv.levels + aq) * tv.ent;
         }
+        const int c = digit_of(q, sl % PE, tv.base);
+        return c == 0 ? nullptr : tv.T + ((long long)sl * (tv.base - 1) + (c - 1)) * tv.ent;
+    };
+    FactorRegs<D> fr;
+    int q = slot_code(0, report);
+    const float2* f = entry_of(0, q);
+    if (f) fetch_factor<D>(fr, f, lt);
+    for (int sl = 0; sl < nslot; ++sl) {
+        __syncthreads();
+        if (f) {
+            put_factor<D>(Fs, fr, q < 0, lt);
+            store_block<D>(Xs, x, ti, tj);
+        }
+        __syncthreads();
+        const bool mult = f != nullptr;
+        if (sl + 1 < nslot) {
+            const int sn = sl + 1;
+            if (sn % PE == 0) q = slot_code(sn, report);
+            f = entry_of(sn, q);
+            if (f) fetch_factor<D>(fr, f, lt);
+        }
+        if (mult) mul_left<D>(x, Fs, Xs, ti, tj);
     }
     // Z
     if (active && tv.phased) {
@@ -227,18 +288,42 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
             for (int r = 0; r < TB; ++r) l[r][c] = cmul(l[r][c], s);
         }
     }
-    for (int k = tv.K - 1; k >= 0; --k) {
-        double phi;
-        const int q = active ? quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, &phi, nullptr) : 0;
-        for (int j = tv.P - 1; j >= 0; --j) {
-            const int c = digit_of(q, j, tv.base);
+    // slots in reverse order (last channel, highest digit first); next entry prefetched
+    {
+        const int PE = tv.cache ? 1 : tv.P;
+        const int nslot = tv.K * PE;
+        auto slot_code = [&](int sl) -> int {
+            double phi;
+            return active ? quantise_one(us + KK * (sl / PE), tv.phased, tv.eps, tv.qmax, &phi, nullptr) : 0;
+        };
+        auto entry_of = [&](int sl, int q) -> const float2* {
+            if (tv.cache) {
+                const int aq = q < 0 ? -q : q;
+                return aq == 0 ? nullptr : tv.cache + ((long long)(sl / PE) * tv.levels + aq) * tv.ent;
+            }
+            const int c = digit_of(q, sl % PE, tv.base);
+            return c == 0 ? nullptr : tv.T + ((long long)sl * (tv.base - 1) + (c - 1)) * tv.ent;
+        };
+        FactorRegs<D> fr;
+        int sl = nslot - 1;
+        int q = slot_code(sl);
+        const float2* f = entry_of(sl, q);
+        if (f) fetch_factor<D>(fr, f, lt);
+        for (; sl >= 0; --sl) {
             __syncthreads();
-            if (c != 0) {
-                stage<D>(Fs, tv.T + ((long long)(k * tv.P + j) * (tv.base - 1) + (c - 1)) * tv.ent, q < 0, lt);
+            if (f) {
+                put_factor<D>(Fs, fr, q < 0, lt);
                 store_block<D>(Ls, l, ti, tj);
             }
             __syncthreads();
-            if (c != 0) mul_left<D>(l, Ls, Fs, ti, tj);  // (Ls Fs) restricted to own block
+            const bool mult = f != nullptr;
+            if (sl > 0) {
+                const int sn = sl - 1;
+                if (sn % PE == PE - 1) q = slot_code(sn);
+                f = entry_of(sn, q);
+                if (f) fetch_factor<D>(fr, f, lt);
+            }
+            if (mult) mul_left<D>(l, Ls, Fs, ti, tj);  // (Ls Fs) restricted to own block
         }
     }
     if (tv.diag) {
@@ -355,11 +440,19 @@ __global__ __launch_bounds__(256) void small_chain_kernel(TView tv, SmallChainAr
         }
 
     double obs_norm = 1.0;
+    // the observable's row lists, once per workgroup, after the instances' buffers
+    float2* ovs = lds + (long long)IPB * 2 * D * D;
+    int* ocs = reinterpret_cast<int*>(ovs + (a.obs_out ? D * a.obs_width : 0));
     if (a.obs_out) {
+        for (int e = tid; e < D * a.obs_width; e += 256) {
+            ovs[e] = a.obs_vals[e];
+            ocs[e] = a.obs_cols[e];
+        }
+        __syncthreads();
         // Tr(M M) = sum of |M_ab|^2 over the row lists (M Hermitian)
         double s = 0.0;
         for (int e = lt; e < D * a.obs_width; e += TPI) {
-            const float2 v = a.obs_vals[e];
+            const float2 v = ovs[e];
             s += (double)v.x * v.x + (double)v.y * v.y;
         }
         obs_norm = inst_sum<D>(s, red);
@@ -390,10 +483,10 @@ __global__ __launch_bounds__(256) void small_chain_kernel(TView tv, SmallChainAr
                         const int ra = ti + NT * r, cb = tj + NT * c;
                         float2 xm = make_float2(0.f, 0.f), mx = make_float2(0.f, 0.f);
                         for (int t = 0; t < a.obs_width; ++t) {
-                            const int colb = a.obs_cols[cb * a.obs_width + t];
-                            cfma(xm, Xs[ra * D + colb], cconj(a.obs_vals[cb * a.obs_width + t]));
-                            const int cola = a.obs_cols[ra * a.obs_width + t];
-                            cfma(mx, a.obs_vals[ra * a.obs_width + t], Xs[cola * D + cb]);
+                            const int colb = ocs[cb * a.obs_width + t];
+                            cfma(xm, Xs[ra * D + colb], cconj(ovs[cb * a.obs_width + t]));
+                            const int cola = ocs[ra * a.obs_width + t];
+                            cfma(mx, ovs[ra * a.obs_width + t], Xs[cola * D + cb]);
                         }
                         acc += (double)xm.x * mx.x + (double)xm.y * mx.y;
                     }
@@ -431,12 +524,6 @@ __device__ inline void save_block(const float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], flo
 #pragma unroll
         for (int c = 0; c < TB; ++c) dst[(ti + NT * r) * D + tj + NT * c] = x[r][c];
 }
-
-struct Pending {
-    double tr[KMAX], ti_[KMAX];   // Tr(S^psi Y) (real, imag)
-    double ur[KMAX], ui[KMAX];    // second trace at the origin (phased, q = 0)
-    double dr[KMAX], di[KMAX];    // D = Tr(G Y) of the later state
-};
 
 template <int D>
 __global__ __launch_bounds__(256) void small_grape_kernel(TView tv, SmallGrapeArgs a) {
@@ -505,40 +592,37 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv, SmallGrapeAr
     for (int r = 0; r < TB; ++r)
 #pragma unroll
         for (int c = 0; c < TB; ++c) l[r][c] = cconj(Uf[(tj + NT * c) * D + ti + NT * r]);
-    Pending pend;
     bool has_pend = false;
     int pend_step = -1;
     const double scale = 2.0 / nu;   // dF = 2 Re(conj(g) dg) with the 1/nu of g folded in
     float* gb = a.grad + (long long)b * a.N_max * ustride;
+    double* pb_ = a.pend + (long long)(valid ? b : 0) * tv.K * 6;   // [K][6]: T1 re/im, T2 re/im, D re/im
     // zero the gradient of steps past this instance's length
     if (valid)
         for (long long e = (long long)len * ustride + lt; e < (long long)a.N_max * ustride; e += TPI) gb[e] = 0.f;
 
-    auto finalize = [&](int s, const double* Dr, const double* Di) {
-        // gradient of step s from pend (its traces) and D of the earlier state
+    // gradient of channel k of step s from its traces (pb_[k]) and D of the earlier state
+    auto finalize = [&](int s, int k, double Dr, double Di) {
         const float* us = ub + (long long)s * ustride;
-        for (int k = 0; k < tv.K; ++k) {
-            double phi;
-            const int q = quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, &phi, nullptr);
-            // Im(conj(g) * z)
-            auto im_gc = [&](double zr, double zi) { return gr * zi - gi * zr; };
-            if (!tv.phased) {
-                gb[(long long)s * ustride + k] = (float)(scale * tv.dt * im_gc(pend.tr[k], pend.ti_[k]));
-            } else if (q == 0) {
-                gb[(long long)s * ustride + 2 * k] = (float)(scale * tv.dt * im_gc(pend.tr[k], pend.ti_[k]));
-                gb[(long long)s * ustride + 2 * k + 1] = (float)(scale * tv.dt * im_gc(pend.ur[k], pend.ui[k]));
-            } else {
-                const double om = (double)q * tv.eps;
-                const double dFo = scale * tv.dt * im_gc(pend.tr[k], pend.ti_[k]);
-                const double dFp = scale * im_gc(pend.dr[k] - Dr[k], pend.di[k] - Di[k]);
-                const double cp = cos(phi), sp = sin(phi);
-                gb[(long long)s * ustride + 2 * k] = (float)(cp * dFo - sp * dFp / om);
-                gb[(long long)s * ustride + 2 * k + 1] = (float)(sp * dFo + cp * dFp / om);
-            }
+        const double* pk = pb_ + k * 6;
+        double phi;
+        const int q = quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, &phi, nullptr);
+        auto im_gc = [&](double zr, double zi) { return gr * zi - gi * zr; };   // Im(conj(g) z)
+        if (!tv.phased) {
+            gb[(long long)s * ustride + k] = (float)(scale * tv.dt * im_gc(pk[0], pk[1]));
+        } else if (q == 0) {
+            gb[(long long)s * ustride + 2 * k] = (float)(scale * tv.dt * im_gc(pk[0], pk[1]));
+            gb[(long long)s * ustride + 2 * k + 1] = (float)(scale * tv.dt * im_gc(pk[2], pk[3]));
+        } else {
+            const double om = (double)q * tv.eps;
+            const double dFo = scale * tv.dt * im_gc(pk[0], pk[1]);
+            const double dFp = scale * im_gc(pk[4] - Dr, pk[5] - Di);
+            const double cp = cos(phi), sp = sin(phi);
+            gb[(long long)s * ustride + 2 * k] = (float)(cp * dFo - sp * dFp / om);
+            gb[(long long)s * ustride + 2 * k + 1] = (float)(sp * dFo + cp * dFp / om);
         }
     };
 
-    double Dr[KMAX], Di[KMAX];
     const int nseg = (N + C - 1) / C;
     for (int sgi = nseg - 1; sgi >= 0; --sgi) {
         const int s0 = sgi * C, s1 = min(N, s0 + C);
@@ -563,9 +647,8 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv, SmallGrapeAr
             __syncthreads();
             float2 y[TB][TB];
             if (active) mul_left<D>(y, Xs, Ls, ti, tj);
-            // traces per channel
+            // traces per channel; lane 0 completes the gradient of the pending (later) step
             const float* us = ub + (long long)s * ustride;
-            double st_tr[KMAX], st_ti[KMAX], st_ur[KMAX], st_ui[KMAX];
             for (int k = 0; k < tv.K; ++k) {
                 double phi = 0.0;
                 const int q = active ? quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, &phi, nullptr) : 0;
@@ -575,6 +658,23 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv, SmallGrapeAr
                 if (active) {
                     const double* gk = tv.phased ? tv.g + (long long)k * D : nullptr;
                     const float2* Sk = tv.S + (long long)k * D * D;
+                    // exp(-i psi (g_aa - g_bb)) = pa[c] pb[r] (aa = column index of the block, bb = row)
+                    double2 pa[TB], pb[TB], qa[TB], qb[TB];
+#pragma unroll
+                    for (int t2 = 0; t2 < TB; ++t2) {
+                        pa[t2] = make_double2(1.0, 0.0);
+                        pb[t2] = make_double2(1.0, 0.0);
+                        qa[t2] = pa[t2];
+                        qb[t2] = pb[t2];
+                        if (gk && psi != 0.0) {
+                            pa[t2] = expmi(psi * gk[tj + NT * t2]);
+                            pb[t2] = zconj(expmi(psi * gk[ti + NT * t2]));
+                        }
+                        if (origin) {
+                            qa[t2] = expmi(1.5707963267948966 * gk[tj + NT * t2]);
+                            qb[t2] = zconj(expmi(1.5707963267948966 * gk[ti + NT * t2]));
+                        }
+                    }
 #pragma unroll
                     for (int r = 0; r < TB; ++r)
 #pragma unroll
@@ -583,18 +683,12 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv, SmallGrapeAr
                             const int bb = ti + NT * r, aa = tj + NT * c;
                             const float2 sv = Sk[aa * D + bb];
                             const double yr = y[r][c].x, yi = y[r][c].y;
-                            double pr = 1.0, pim = 0.0;
-                            if (gk && psi != 0.0) {
-                                const double2 e = expmi(psi * (gk[aa] - gk[bb]));
-                                pr = e.x;
-                                pim = e.y;
-                            }
-                            const double s_r = pr * sv.x - pim * sv.y, s_i = pr * sv.y + pim * sv.x;
+                            const double2 p = zmul(pa[c], pb[r]);
+                            const double s_r = p.x * sv.x - p.y * sv.y, s_i = p.x * sv.y + p.y * sv.x;
                             tr += s_r * yr - s_i * yi;
                             tim += s_r * yi + s_i * yr;
                             if (origin) {
-                                // psi = pi/2: exp(-i pi/2 (g_a - g_b))
-                                const double2 e = expmi(1.5707963267948966 * (gk[aa] - gk[bb]));
+                                const double2 e = zmul(qa[c], qb[r]);
                                 const double t_r = e.x * sv.x - e.y * sv.y, t_i = e.x * sv.y + e.y * sv.x;
                                 ur += t_r * yr - t_i * yi;
                                 ui += t_r * yi + t_i * yr;
@@ -613,23 +707,18 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv, SmallGrapeAr
                     dr = inst_sum<D>(dr, red);
                     di = inst_sum<D>(di, red);
                 }
-                Dr[k] = dr;
-                Di[k] = di;
-                st_tr[k] = tr;
-                st_ti[k] = tim;
-                st_ur[k] = ur;
-                st_ui[k] = ui;
-            }
-            if (active && lt == 0 && has_pend) finalize(pend_step, Dr, Di);
-            if (active) {
-                for (int k = 0; k < tv.K; ++k) {
-                    pend.tr[k] = st_tr[k];
-                    pend.ti_[k] = st_ti[k];
-                    pend.ur[k] = st_ur[k];
-                    pend.ui[k] = st_ui[k];
-                    pend.dr[k] = Dr[k];
-                    pend.di[k] = Di[k];
+                if (active && lt == 0) {
+                    if (has_pend) finalize(pend_step, k, dr, di);
+                    double* pk = pb_ + k * 6;
+                    pk[0] = tr;
+                    pk[1] = tim;
+                    pk[2] = ur;
+                    pk[3] = ui;
+                    pk[4] = dr;
+                    pk[5] = di;
                 }
+            }
+            if (active) {
                 has_pend = true;
                 pend_step = s;
             }
@@ -655,16 +744,15 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv, SmallGrapeAr
             dr = inst_sum<D>(dr, red);
             di = inst_sum<D>(di, red);
         }
-        Dr[k] = dr;
-        Di[k] = di;
+        if (valid && lt == 0 && has_pend) finalize(pend_step, k, dr, di);
     }
-    if (valid && lt == 0 && has_pend) finalize(pend_step, Dr, Di);
 }
 
 template <int D>
 hipError_t launch_chain(const TView& tv, const SmallChainArgs& a, int ninst, hipStream_t st) {
     constexpr int IPB = Cfg<D>::IPB;
-    const size_t lds = (size_t)IPB * 2 * D * D * sizeof(float2);
+    const size_t lds = (size_t)IPB * 2 * D * D * sizeof(float2) +
+                       (a.obs_out ? (size_t)D * a.obs_width * (sizeof(float2) + sizeof(int)) : 0);
     hipError_t e = hipFuncSetAttribute((const void*)small_chain_kernel<D>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -699,6 +787,12 @@ hipError_t small_chain(const redo_table_s* t, const SmallChainArgs& a, hipStream
         case 64: return launch_chain<64>(tv, a, ninst, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+size_t small_grape_workspace_bytes(int d, int K, long long B, long long N_max, long long C) {
+    const long long nck = (N_max + C - 1) / C;
+    const size_t mats = sizeof(float2) * (size_t)d * d * (size_t)B * (size_t)(nck + C);
+    return ((mats + 255) & ~size_t(255)) + sizeof(double) * (size_t)B * K * 6;
 }
 
 hipError_t small_grape(const redo_table_s* t, const SmallGrapeArgs& a, hipStream_t st) {

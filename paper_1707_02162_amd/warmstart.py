@@ -111,9 +111,13 @@ class WarmStartMLP:
 
 
 def grape(table: R.RedoTable, u0: torch.Tensor, Uf: torch.Tensor, u_max: float, iters: int, lr: float,
-          goal: float = 1e-4, history: bool = False):
-    """Batched REDO-GRAPE: Adam ascent on F, amplitudes clamped to [-u_max, u_max].
-    Returns (u, F, iterations to reach infidelity <= goal (or -1))."""
+          goal: float = 1e-4, history: bool = False, log=None, tag: str = "grape", lr_final: Optional[float] = None):
+    """Batched REDO-GRAPE: Adam ascent on F, amplitudes clamped to [-u_max, u_max],
+    step size decaying geometrically from lr to lr_final (default: constant).
+    An instance that reaches infidelity <= goal keeps the amplitudes of that
+    iteration.  Returns (u, F, iterations to reach the goal (or -1), history);
+    progress goes to `log` every 50 iterations."""
+    decay = 1.0 if lr_final is None or iters < 1 else (lr_final / lr) ** (1.0 / iters)
     u = u0.clone().contiguous()
     m = torch.zeros_like(u)
     v = torch.zeros_like(u)
@@ -121,16 +125,30 @@ def grape(table: R.RedoTable, u0: torch.Tensor, Uf: torch.Tensor, u_max: float, 
     reached = torch.full((B,), -1, dtype=torch.int64, device=u.device)
     F = None
     hist = []
+    u_best = u.clone()
+    F_best = None
     for it in range(iters + 1):
         F, _, g = table.grape(u, Uf)
+        if F_best is None:
+            F_best = F.clone()
+        # instances that already reached the goal keep that point
+        frozen = reached >= 0
+        F = torch.where(frozen, F_best, F)
         ok = (1.0 - F) <= goal
         reached = torch.where((reached < 0) & ok, torch.full_like(reached, it), reached)
+        newly = ok & ~frozen
+        u_best = torch.where(newly.view(-1, *([1] * (u.dim() - 1))), u, u_best)
+        F_best = torch.where(newly | ~frozen, F, F_best)
         if history:
             hist.append(F.clone())
         if it == iters or bool(ok.all()):
             break
-        adam_(u, g, m, v, it + 1, lr, sign=-1.0, lo=-u_max, hi=u_max)
-    return u, F, reached, hist
+        if log is not None and it % 50 == 0:
+            log(f"[warmstart] {tag} iteration {it}: {int(ok.sum())}/{B} at infidelity <= {goal:g}, "
+                f"median infidelity {float((1 - F).median()):.2e}")
+        adam_(u, g, m, v, it + 1, lr * decay ** it, sign=-1.0, lo=-u_max, hi=u_max)
+    done = (reached >= 0).view(-1, *([1] * (u.dim() - 1)))
+    return torch.where(done, u_best, u), F, reached, hist
 
 
 def reachable_targets(table: R.RedoTable, p: W.Problem, config_id: int, B: int, start: int = 0) -> torch.Tensor:
@@ -146,7 +164,7 @@ def random_starts(p: W.Problem, config_id: int, B: int) -> torch.Tensor:
     return torch.tensor(st.u, device="cuda")
 
 
-def experiment(n_train: int, n_test: int, N: int = 500, grape_iters: int = 400, lr_grape: float = 300.0,
+def experiment(n_train: int, n_test: int, N: int = 500, grape_iters: int = 2000, lr_grape: float = 1000.0,
                epochs: int = 40, batch: int = 256, lr_net: float = 1e-3, width: int = 512, goal: float = 1e-4,
                log=print):
     """C5-shaped run: d = 16, two species with collective X/Y, N steps of 2 us."""
@@ -158,7 +176,7 @@ def experiment(n_train: int, n_test: int, N: int = 500, grape_iters: int = 400, 
     # training set: reachable targets, REDO-GRAPE from random smooth starts
     Uf = reachable_targets(table, p, 501, n_train)
     u0 = random_starts(p, 502, n_train)
-    u_opt, F_opt, it_opt, _ = grape(table, u0, Uf, u_max, grape_iters, lr_grape, goal=goal)
+    u_opt, F_opt, it_opt, _ = grape(table, u0, Uf, u_max, grape_iters, lr_grape, goal=goal, log=log, tag="dataset")
     keep = (1.0 - F_opt) <= goal
     log(f"[warmstart] dataset: {int(keep.sum())}/{n_train} optimised to {goal:g} in {time.time() - t0:.1f}s")
     X = target_features(Uf)[keep]
@@ -174,6 +192,8 @@ def experiment(n_train: int, n_test: int, N: int = 500, grape_iters: int = 400, 
             idx = perm[i * batch:(i + 1) * batch]
             tot += float(net.train_step(X[idx], Y[idx], lr_net).item())
         losses.append(tot / nb)
+        if ep % 10 == 0:
+            log(f"[warmstart] epoch {ep}: loss {losses[-1]:.4f}")
     log(f"[warmstart] trained {epochs} epochs, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     # held-out targets: network start (with fallback) vs random start
     Ut = reachable_targets(table, p, 601, n_test)
@@ -183,8 +203,8 @@ def experiment(n_train: int, n_test: int, N: int = 500, grape_iters: int = 400, 
     Fn0, _, _ = table.grape(un, Ut)
     use_net = Fn0 >= Fr0                       # fallback to the random start when it starts better
     us = torch.where(use_net.view(-1, 1, 1, 1), un, ur)
-    _, Fr, itr, _ = grape(table, ur, Ut, u_max, grape_iters, lr_grape, goal=goal)
-    _, Fs, its, _ = grape(table, us, Ut, u_max, grape_iters, lr_grape, goal=goal)
+    _, Fr, itr, _ = grape(table, ur, Ut, u_max, grape_iters, lr_grape, goal=goal, log=log, tag="random start")
+    _, Fs, its, _ = grape(table, us, Ut, u_max, grape_iters, lr_grape, goal=goal, log=log, tag="network start")
     # second fallback: a network start that does not reach the goal within the budget is
     # followed by the run from the random start (its iterations count after the wasted budget)
     miss = use_net & (its < 0)
@@ -218,12 +238,14 @@ def main():
     ap.add_argument("--train", type=int, default=20000)
     ap.add_argument("--test", type=int, default=256)
     ap.add_argument("--N", type=int, default=500)
-    ap.add_argument("--grape-iters", type=int, default=400)
+    ap.add_argument("--grape-iters", type=int, default=2000)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--goal", type=float, default=1e-4)
+    ap.add_argument("--lr-grape", type=float, default=1000.0)
+    ap.add_argument("--width", type=int, default=512)
     a = ap.parse_args()
-    res = experiment(a.train, a.test, N=a.N, grape_iters=a.grape_iters, epochs=a.epochs, goal=a.goal,
-                     log=lambda s: print(s, file=sys.stderr, flush=True))
+    res = experiment(a.train, a.test, N=a.N, grape_iters=a.grape_iters, lr_grape=a.lr_grape, epochs=a.epochs,
+                     goal=a.goal, width=a.width, log=lambda s: print(s, file=sys.stderr, flush=True))
     print(json.dumps(res))
 
 

@@ -122,6 +122,8 @@ class Problem:
     n_steps       int32 [B] per-instance lengths (None: all N)
     U_target      complex [B, d, d] targets (or None)
     M             observable, complex Hermitian [d, d] (or None)
+    splitting     "lie": U_n = C_n V (drift first, the paper's split);
+                  "strang": U_n = V(dt/2) C_n V(dt/2)
     """
     name: str
     d: int
@@ -141,6 +143,7 @@ class Problem:
     M: Optional[np.ndarray] = None
     u_scale: float = 1.0
     meta: dict = dataclasses.field(default_factory=dict)
+    splitting: str = "lie"
 
     @property
     def B(self) -> int:
@@ -306,6 +309,47 @@ def ising_freezing(n: int = 10, B: int = 4096, N: int = 5000, sigma: float = 0.0
     return Problem(name, d, 1, False, H0, True, S, None, dt, eps, base, digits, u,
                    None, None, M, u_scale=h0,
                    meta=dict(h0=h0, J=J, omega=omega, sigma=sigma, n_spins=n))
+
+
+def freezing_sweep(omegas, lambdas, n: int = 3, N: int = 10000, T: float = 20.0 * math.pi,
+                   h0: float = 5.0 * math.pi, J_ratio: float = 1.0 / 20.0, base: int = 100, digits: int = 2,
+                   coef_eps: float = 1e-4, config_id: int = 7, first: int = 0, count: Optional[int] = None,
+                   name: str = "freezing_sweep") -> Problem:
+    """The paper's noisy-drive freezing sweep (Sec. IV): an open chain of n
+    spins, H(t) = -J sum_i 2 I_iz I_{i+1,z} - h0 c(t) sum_i I_ix with drive
+    coefficient c(t) = (1 - lambda) cos(omega t) + lambda eta(t), eta ~ U(-1, 1)
+    drawn per time point, J = h0/20, h0 = 5 pi; N time points over [0, T]
+    (midpoints of N segments); c is coarse grained with quantum coef_eps
+    (b = 100, l = -2, m = -1: eps = 1e-4, P = 2).  Instances are the pairs
+    (omega_i, lambda_j), instance index j * len(omegas) + i; this returns
+    instances first .. first + count - 1 (seeded per instance index).
+    Observable and initial state M = sum_i I_ix; the order parameter is the
+    time average of Tr(X M X^dag M) / Tr(M^2)."""
+    omegas = np.asarray(omegas, dtype=np.float64)
+    lambdas = np.asarray(lambdas, dtype=np.float64)
+    total = len(omegas) * len(lambdas)
+    if count is None:
+        count = total - first
+    d = 2 ** n
+    dt = T / N
+    J = J_ratio * h0
+    h = np.zeros(d)
+    for i in range(n - 1):
+        h += -J * 2.0 * spin_z_diag(n, i) * spin_z_diag(n, i + 1)
+    S = collective(n, range(n), "x")[None]
+    t = (np.arange(N) + 0.5) * dt
+    u = np.empty((count, N, 1), dtype=np.float32)
+    om = np.empty(count)
+    la = np.empty(count)
+    for r in range(count):
+        idx = first + r
+        om[r] = omegas[idx % len(omegas)]
+        la[r] = lambdas[idx // len(omegas)]
+        eta = rng(config_id, STREAM_NOISE, idx).uniform(-1.0, 1.0, N)
+        u[r, :, 0] = (-h0 * ((1.0 - la[r]) * np.cos(om[r] * t) + la[r] * eta)).astype(np.float32)
+    return Problem(name, d, 1, False, h[None, :], True, S, None, dt, coef_eps * h0, base, digits, u,
+                   None, None, S[0].copy(), u_scale=h0,
+                   meta=dict(h0=h0, J=J, omega=om, lam=la, first=first, n_spins=n))
 
 
 def observable_ell(M: np.ndarray):

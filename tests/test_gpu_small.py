@@ -334,3 +334,54 @@ def test_expm_baseline_d64_vs_oracle_exact():
         H0m = np.diag(p.H0[0]).astype(complex)
         X = O.chain([O.step_exact(H0m, p.S, p.g, p.u[b, n].astype(np.float64), p.dt) for n in range(p.N)])
         assert nfrob(U[b], X) < FROB_TOL
+
+
+# ---------------------------------------------------------------- level cache on the fused path
+@pytest.mark.parametrize("n", [1, 3, 4, 5, 6])
+def test_level_cache_chain_every_dimension_vs_oracle(n):
+    """With every level composed once (process 3) the fused kernels apply one
+    factor per channel and step; the result is the oracle's REDO chain to
+    FP32 rounding (each level carries one rounding of its FP64 product)."""
+    d = 2 ** n
+    B = {1: 40, 3: 12, 4: 9, 5: 4, 6: 2}[n]
+    lens = W.rng(90 + n, 4).integers(20, 61, B)
+    p = W.nmr_chain(n, B, 60, 2e-6, 16, 2, 90 + n, lengths=lens)
+    t = table(p)
+    t.cache_levels()
+    U, Xp, _ = t.chain(torch.tensor(p.u).cuda(), n_steps=torch.tensor(lens), prefix=True)
+    U, Xp = U.cpu().numpy(), Xp.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in [0, B - 1]:
+        pref = O.chain(O.compose_all_redo(p, tab, b), keep=True)
+        assert nfrob(U[b], pref[-1]) < FROB_TOL
+        for m in (1, lens[b] // 2, lens[b]):
+            assert nfrob(Xp[b, m - 1], pref[m]) < FROB_TOL
+
+
+def test_level_cache_grape_phased_and_signed_vs_oracle():
+    p = W.c5_four_qubit(B=3, N=80)
+    p.u[:, ::7] = 0.0
+    t = table(p)
+    t.cache_levels()
+    F, ov, grad = t.grape(torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda())
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    _grape_check(p, tab, F.cpu().numpy(), ov.cpu().numpy(), grad.cpu().numpy(), range(p.B))
+    q = W.ising_freezing(n=3, B=2, N=90)
+    q.U_target = np.stack([W.haar_unitary(8, W.rng(32, 2, b)) for b in range(2)])
+    t2 = table(q)
+    t2.cache_levels()
+    F, ov, grad = t2.grape(torch.tensor(q.u).cuda(), torch.tensor(q.U_target).cuda())
+    tab2 = O.DiscreteTable(q.S, q.dt, q.eps, q.base, q.digits)
+    _grape_check(q, tab2, F.cpu().numpy(), ov.cpu().numpy(), grad.cpu().numpy(), range(q.B))
+
+
+def test_level_cache_partial_range_is_not_used_on_fused_path():
+    """A cache that does not hold every level leaves the fused kernels on the
+    digit factors: results are bitwise those of the uncached table."""
+    p = W.c5_four_qubit(B=2, N=40)
+    t = table(p)
+    u = torch.tensor(p.u).cuda()
+    U0, _, _ = t.chain(u)
+    t.cache_levels(0, 100)
+    U1, _, _ = t.chain(u)
+    assert torch.equal(U0, U1)

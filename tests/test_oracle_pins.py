@@ -423,3 +423,81 @@ def test_canonical_features_remove_global_phase():
     a = M.canonical_target_features(U)
     b = M.canonical_target_features(np.exp(1.3j) * U)
     assert a.shape == (32,) and np.abs(a - b).max() < 1e-12
+
+
+# ------------------------------------------------------------------ Strang splitting (NEXT row f1)
+def _local_errors(p, dts, splitting):
+    """|U_split(dt) - U_exact(dt)| of one step for the given step lengths."""
+    out = []
+    amp = p.u[0, 0].astype(float)
+    H0m = np.diag(p.H0[0]).astype(np.complex128)
+    for dt in dts:
+        V = O.drift_propagator(p.H0[0], dt, True)
+        Vh = O.drift_propagator(p.H0[0], dt / 2, True) if splitting == "strang" else None
+        Us = O.step_split(p.S, p.g, amp, dt, V, Vh)
+        Ue = O.step_exact(H0m, p.S, p.g, amp, dt)
+        out.append(np.linalg.norm(Us - Ue))
+    return np.array(out)
+
+
+def test_strang_step_is_third_order_lie_second_order():
+    """Local error of one step: Lie (the paper's split) O(dt^2), Strang O(dt^3):
+    halving dt divides it by ~4 and ~8."""
+    p = W.c1_two_spin(B=1, N=1)
+    dts = 2e-5 / 2.0 ** np.arange(4)
+    el = _local_errors(p, dts, "lie")
+    es = _local_errors(p, dts, "strang")
+    rl, rs = el[:-1] / el[1:], es[:-1] / es[1:]
+    assert np.all(np.abs(rl - 4) < 0.25), rl
+    assert np.all(np.abs(rs - 8) < 0.5), rs
+
+
+def test_strang_step_matches_bch_to_fifth_order():
+    """exp(A/2) exp(B) exp(A/2) = exp(A + B - [A,[A,B]]/24 - [B,[A,B]]/12 + O(5))
+    (symmetric BCH, A = -i dt H0, B = -i dt H_c): the residual after the two
+    third-order terms falls ~32x per halving of dt."""
+    p = W.c1_two_spin(B=1, N=1)
+    amp = p.u[0, 0].astype(float)
+    H0m = np.diag(p.H0[0]).astype(np.complex128)
+    # the control Hamiltonian of the step: sum_k u_x S_k + u_y S_k^y
+    Hc_gen = sum(amp[k, 0] * p.S[k] + amp[k, 1] * O.y_generator(p.S[k], p.g[k]) for k in range(p.K))
+    res = []
+    for dt in 1e-5 / 2.0 ** np.arange(3):
+        A, Bm = -1j * dt * H0m, -1j * dt * Hc_gen
+        comm = lambda X, Y: X @ Y - Y @ X
+        G = A + Bm - comm(A, comm(A, Bm)) / 24 - comm(Bm, comm(A, Bm)) / 12
+        w2, Q2 = np.linalg.eig(G)
+        E = Q2 @ np.diag(np.exp(w2)) @ np.linalg.inv(Q2)
+        Vh = O.drift_propagator(p.H0[0], dt / 2, True)
+        Ustr = Vh @ O.expm_herm(Hc_gen, dt) @ Vh
+        res.append(np.linalg.norm(Ustr - E))
+    res = np.array(res)
+    r = res[:-1] / res[1:]
+    assert np.all(r > 24), (res, r)
+
+
+def test_strang_chain_is_lie_chain_conjugated_by_half_drift():
+    """prod_n Vh C_n Vh = Vh (prod_n C_n V) Vh^dag: the Strang chain is the Lie
+    chain conjugated by the half-step drift."""
+    p = W.c1_two_spin(B=1, N=30)
+    ps = W.Problem(**{**p.__dict__, "splitting": "strang"})
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    Xl = O.chain(O.compose_all_redo(p, tab, 0))
+    Xs = O.chain(O.compose_all_redo(ps, tab, 0))
+    Vh = O.drift_propagator(p.H0[0], p.dt / 2, True)
+    assert np.linalg.norm(Xs - Vh @ Xl @ Vh.conj().T) < 1e-12
+    assert np.linalg.norm(Xs - Xl) > 1e-6
+
+
+@pytest.mark.parametrize("maker", ["phased", "signed"])
+def test_strang_gradient_vs_central_differences(maker):
+    if maker == "phased":
+        p = W.c1_two_spin(B=1, N=6)
+    else:
+        p = W.ising_freezing(n=3, B=1, N=8)
+        p.U_target = W.haar_unitary(8, W.rng(3, 2, 0))[None]
+    p = W.Problem(**{**p.__dict__, "splitting": "strang"})
+    amp0 = p.u[0].astype(float)
+    _, _, grad = O.fidelity_and_gradient(p, 0, model="split")
+    fd = _fd_grad(p, 0, amp0, "split", 1e-6 * p.u_scale)
+    assert np.linalg.norm(grad - fd) <= 1e-7 * np.linalg.norm(fd)
