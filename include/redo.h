@@ -87,7 +87,9 @@ typedef struct {
                               0: channel k takes a signed amplitude, H_kn = u_kn S_k */
     int32_t drift_is_diag; /* 1: H0 is real diagonal, double [n_drift][d]; 0: c128 [n_drift][d][d] */
     int32_t n_drift;       /* number of drift Hamiltonians (>= 1); instance b uses drift b % n_drift */
-    int32_t reserved;      /* must be 0 */
+    int32_t splitting;     /* 0: U_n = C_n V, the drift split off before the controls (Sec. III, the paper's
+                                 split); 1: the symmetric Strang form U_n = V(dt/2) C_n V(dt/2), second
+                                 order in dt (diagonal drifts only) */
 } redo_table_desc;
 
 /*

@@ -108,7 +108,9 @@ redo_status check_desc(const redo_table_desc* d) {
     if (d->phased != 0 && d->phased != 1) return fail(REDO_ERR_ARG, "phased must be 0 or 1");
     if (d->drift_is_diag != 0 && d->drift_is_diag != 1) return fail(REDO_ERR_ARG, "drift_is_diag must be 0 or 1");
     if (d->n_drift < 1) return fail(REDO_ERR_ARG, "n_drift must be >= 1");
-    if (d->reserved != 0) return fail(REDO_ERR_ARG, "reserved must be 0");
+    if (d->splitting != 0 && d->splitting != 1) return fail(REDO_ERR_ARG, "splitting must be 0 or 1");
+    if (d->splitting == 1 && !d->drift_is_diag)
+        return fail(REDO_ERR_UNSUPPORTED, "the Strang splitting is provided for diagonal drifts");
     return REDO_OK;
 }
 

@@ -38,6 +38,25 @@ struct GCfg {
 
 __device__ inline float2 f2(float a, float b) { return make_float2(a, b); }
 
+// The operands come through descriptor pointers, which the compiler cannot
+// place in an address space: these accessors mark them as global memory so
+// that loads and stores are global (vector-memory counter only) instead of
+// flat ones, which would also hold up every LDS wait in the MFMA loop.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const v4f gcv4;
+typedef __attribute__((address_space(1))) const v2f gcv2;
+typedef __attribute__((address_space(1))) v2f gv2;
+__device__ inline float4 ldg4(const float2* p) {
+    const v4f v = *(gcv4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ inline float2 ldg2(const float2* p) {
+    const v2f v = *(gcv2*)p;
+    return make_float2(v.x, v.y);
+}
+__device__ inline void stg2(float2* p, float2 v) { *(gv2*)p = v2f{v.x, v.y}; }
+
 // global -> registers for one stage
 template <int BM, int BN>
 __device__ inline void load_stage(const GemmDesc& g, int d, int i0, int j0, int k0, float4 (&ra)[GCfg<BM, BN>::AV],
@@ -49,10 +68,10 @@ __device__ inline void load_stage(const GemmDesc& g, int d, int i0, int j0, int 
         const int e = t + C::THREADS * m;
         if (g.opA == 0) {
             const int row = e / (KT / 2), kq = e % (KT / 2);
-            ra[m] = *reinterpret_cast<const float4*>(g.A + (long long)(i0 + row) * d + k0 + 2 * kq);
+            ra[m] = ldg4(g.A + (long long)(i0 + row) * d + k0 + 2 * kq);
         } else {
             const int kr = e / (BM / 2), iq = e % (BM / 2);
-            ra[m] = *reinterpret_cast<const float4*>(g.A + (long long)(k0 + kr) * d + i0 + 2 * iq);
+            ra[m] = ldg4(g.A + (long long)(k0 + kr) * d + i0 + 2 * iq);
         }
     }
 #pragma unroll
@@ -60,10 +79,10 @@ __device__ inline void load_stage(const GemmDesc& g, int d, int i0, int j0, int 
         const int e = t + C::THREADS * m;
         if (g.opB == 0) {
             const int kr = e / (BN / 2), jq = e % (BN / 2);
-            rb[m] = *reinterpret_cast<const float4*>(g.B + (long long)(k0 + kr) * d + j0 + 2 * jq);
+            rb[m] = ldg4(g.B + (long long)(k0 + kr) * d + j0 + 2 * jq);
         } else {
             const int row = e / (KT / 2), kq = e % (KT / 2);
-            rb[m] = *reinterpret_cast<const float4*>(g.B + (long long)(j0 + row) * d + k0 + 2 * kq);
+            rb[m] = ldg4(g.B + (long long)(j0 + row) * d + k0 + 2 * kq);
         }
     }
 }
@@ -95,7 +114,7 @@ __device__ inline void store_stage(const GemmDesc& g, int k0, const float4 (&ra)
             const int kr = e / (BN / 2), jq = e % (BN / 2);
             float2 a = f2(v.x, v.y), b = f2(v.z, v.w);
             if (g.kscale) {
-                const float2 s = g.kscale[k0 + kr];
+                const float2 s = ldg2(g.kscale + k0 + kr);
                 a = cmul(s, a);
                 b = cmul(s, b);
             }
@@ -104,8 +123,8 @@ __device__ inline void store_stage(const GemmDesc& g, int k0, const float4 (&ra)
             const int row = e / (KT / 2), kq = e % (KT / 2);
             float2 a = f2(v.x, -v.y), b = f2(v.z, -v.w);
             if (g.kscale) {
-                a = cmul(g.kscale[k0 + 2 * kq], a);
-                b = cmul(g.kscale[k0 + 2 * kq + 1], b);
+                a = cmul(ldg2(g.kscale + k0 + 2 * kq), a);
+                b = cmul(ldg2(g.kscale + k0 + 2 * kq + 1), b);
             }
             Bs[(2 * kq) * C::LDB + row] = a;
             Bs[(2 * kq + 1) * C::LDB + row] = b;
@@ -121,21 +140,21 @@ __device__ inline void copy_tile(const GemmDesc& g, int d, int i0, int j0, int B
         float2 v;
         if (g.A == nullptr && g.B == nullptr) {
             v = f2(i == j ? 1.f : 0.f, 0.f);
-            if (g.kscale && i == j) v = g.kscale[i];
+            if (g.kscale && i == j) v = ldg2(g.kscale + i);
         } else if (g.A == nullptr) {
-            v = g.opB == 0 ? g.B[ij] : cconj(g.B[ji]);   // diag(ks) op(B)
-            if (g.kscale) v = cmul(g.kscale[i], v);
+            v = g.opB == 0 ? ldg2(g.B + ij) : cconj(ldg2(g.B + ji));   // diag(ks) op(B)
+            if (g.kscale) v = cmul(ldg2(g.kscale + i), v);
         } else {
-            v = g.opA == 0 ? g.A[ij] : cconj(g.A[ji]);   // op(A) diag(ks)
-            if (g.kscale) v = cmul(v, g.kscale[j]);
+            v = g.opA == 0 ? ldg2(g.A + ij) : cconj(ldg2(g.A + ji));   // op(A) diag(ks)
+            if (g.kscale) v = cmul(v, ldg2(g.kscale + j));
         }
-        if (g.rscale) v = cmul(g.rscale[i], v);
-        if (g.cscale) v = cmul(v, g.cscale[j]);
+        if (g.rscale) v = cmul(ldg2(g.rscale + i), v);
+        if (g.cscale) v = cmul(v, ldg2(g.cscale + j));
         v.x *= g.alpha;
         v.y *= g.alpha;
-        if (g.addend) v = cadd(v, g.addend[ij]);
+        if (g.addend) v = cadd(v, ldg2(g.addend + ij));
         if (i == j) v.x += g.beta_identity;
-        g.C[ij] = v;
+        stg2(g.C + ij, v);
     }
 }
 
@@ -248,13 +267,13 @@ __global__ __launch_bounds__(256) void cgemm_kernel(int d, int batch, const Gemm
                     const float t1 = acc[0][ib][jb][r], t2 = acc[1][ib][jb][r], t3 = acc[2][ib][jb][r];
                     v = f2(t1 - t2, t3 - t1 - t2);
                 }
-                if (g.rscale) v = cmul(g.rscale[i], v);
-                if (g.cscale) v = cmul(v, g.cscale[j]);
+                if (g.rscale) v = cmul(ldg2(g.rscale + i), v);
+                if (g.cscale) v = cmul(v, ldg2(g.cscale + j));
                 v.x *= g.alpha;
                 v.y *= g.alpha;
-                if (g.addend) v = cadd(v, g.addend[(long long)i * d + j]);
+                if (g.addend) v = cadd(v, ldg2(g.addend + (long long)i * d + j));
                 if (i == j) v.x += g.beta_identity;
-                g.C[(long long)i * d + j] = v;
+                stg2(g.C + (long long)i * d + j, v);
             }
 }
 
@@ -341,7 +360,7 @@ __device__ inline void store_stage_bf(const GemmDesc& g, int k0, const float4 (&
             const int kr = e / (BN / 2), jq = e % (BN / 2);
             float2 a = f2(v.x, v.y), b = f2(v.z, v.w);
             if (g.kscale) {
-                const float2 sc = g.kscale[k0 + kr];
+                const float2 sc = ldg2(g.kscale + k0 + kr);
                 a = cmul(sc, a);
                 b = cmul(sc, b);
             }
@@ -363,8 +382,8 @@ __device__ inline void store_stage_bf(const GemmDesc& g, int k0, const float4 (&
             const int row = e / (KT / 2), kq = e % (KT / 2);
             float2 a = f2(v.x, -v.y), b = f2(v.z, -v.w);
             if (g.kscale) {
-                a = cmul(g.kscale[k0 + 2 * kq], a);
-                b = cmul(g.kscale[k0 + 2 * kq + 1], b);
+                a = cmul(ldg2(g.kscale + k0 + 2 * kq), a);
+                b = cmul(ldg2(g.kscale + k0 + 2 * kq + 1), b);
             }
             split_bf16(a.x, h[0], l[0]);
             split_bf16(a.y, h[1], l[1]);
@@ -508,13 +527,13 @@ __global__ __launch_bounds__(256) void cgemm_bf16x3_kernel(int d, int batch, con
                 const int i = i0 + wi0 + ib * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
                 const int j = j0 + wj0 + jb * 32 + (lane & 31);
                 float2 v = f2(accR[ib][jb][r], accI[ib][jb][r]);
-                if (g.rscale) v = cmul(g.rscale[i], v);
-                if (g.cscale) v = cmul(v, g.cscale[j]);
+                if (g.rscale) v = cmul(ldg2(g.rscale + i), v);
+                if (g.cscale) v = cmul(v, ldg2(g.cscale + j));
                 v.x *= g.alpha;
                 v.y *= g.alpha;
-                if (g.addend) v = cadd(v, g.addend[(long long)i * d + j]);
+                if (g.addend) v = cadd(v, ldg2(g.addend + (long long)i * d + j));
                 if (i == j) v.x += g.beta_identity;
-                g.C[(long long)i * d + j] = v;
+                stg2(g.C + (long long)i * d + j, v);
             }
 }
 #undef MF16

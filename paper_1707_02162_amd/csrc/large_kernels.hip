@@ -33,6 +33,7 @@ struct PlanArgs {
     int compose;            // 1: the state starts as the identity (no B operand)
     int slots;              // launched slots: dense + K (all levels cached) or dense + K * P
     int all_cached;
+    int strang;             // U_n = V(dt/2) C_n V(dt/2): half drift in pre, half in post (diagonal drift)
     float2* pre;            // [B][d] scale vectors of this step
     float2* post;
     float2* pstar;
@@ -57,11 +58,13 @@ __global__ __launch_bounds__(256) void plan_step_kernel(PlanArgs a) {
             double th = 0.0;
             if (a.phased)
                 for (int k = 0; k < a.K; ++k) th += pb[k] * a.g[(long long)k * d + r];
-            const double2 po = expmi(th);                        // e^{-i theta}
+            const double hd = (!a.dense && a.strang) ? 0.5 * a.dt * a.h[(long long)drift * d + r] : 0.0;
+            const double2 po = expmi(th + hd);                   // e^{-i theta} (times v^{1/2}, Strang)
             a.post[(long long)b * d + r] = make_float2((float)po.x, (float)po.y);
             a.pstar[(long long)b * d + r] = make_float2((float)po.x, (float)-po.y);
             if (!a.dense) {
-                const double2 pr = expmi(a.dt * a.h[(long long)drift * d + r] - th);   // v e^{+i theta}
+                const double hdt = a.strang ? 0.5 * a.dt : a.dt;
+                const double2 pr = expmi(hdt * a.h[(long long)drift * d + r] - th);   // v e^{+i theta}
                 a.pre[(long long)b * d + r] = make_float2((float)pr.x, (float)pr.y);
             }
         }
@@ -115,7 +118,8 @@ __global__ __launch_bounds__(256) void plan_step_kernel(PlanArgs a) {
             } else if (s == first_table || s == copy_slot) {
                 g.kscale = a.pre + (long long)b * d;
             }
-            if (a.phased && (s == last || s == copy_slot) && (s != 0 || !a.dense)) g.rscale = a.post + (long long)b * d;
+            if ((a.phased || a.strang) && (s == last || s == copy_slot) && (s != 0 || !a.dense))
+                g.rscale = a.post + (long long)b * d;
             loc ^= 1;
             first_op = false;
         }
@@ -447,7 +451,8 @@ __global__ __launch_bounds__(256) void trace_partial_kernel(int d, int K, int ph
                                                             const int* __restrict__ codes,
                                                             const double* __restrict__ phi, long long code_stride,
                                                             const int* n_steps, int step, double* partial,
-                                                            int cartesian) {
+                                                            int cartesian, const double* h, int n_drift,
+                                                            double hdt) {
     const int ntile = (d / TT) * (d / TT);
     const int tile = blockIdx.x, k = blockIdx.y, b = blockIdx.z;
     const int a0 = (tile / (d / TT)) * TT, b0 = (tile % (d / TT)) * TT;
@@ -475,6 +480,15 @@ __global__ __launch_bounds__(256) void trace_partial_kernel(int d, int K, int ph
         pb[r] = zconj(expmi(psi * gb));             // e^{+i psi g_b}
         qa[r] = expmi(1.5707963267948966 * ga);
         qb[r] = zconj(expmi(1.5707963267948966 * gb));
+        if (hdt != 0.0) {
+            // Strang: the generator seen by the trace is V(dt/2) S V(dt/2)^dag
+            const long long hb_ = (long long)(b % n_drift) * d;
+            const double2 ea = expmi(hdt * h[hb_ + a0 + r]), eb = zconj(expmi(hdt * h[hb_ + b0 + r]));
+            pa[r] = zmul(pa[r], ea);
+            pb[r] = zmul(pb[r], eb);
+            qa[r] = zmul(qa[r], ea);
+            qb[r] = zmul(qb[r], eb);
+        }
     }
     __syncthreads();
     double t1r = 0, t1i = 0, t2r = 0, t2i = 0, dr = 0, di = 0;
@@ -484,7 +498,7 @@ __global__ __launch_bounds__(256) void trace_partial_kernel(int d, int K, int ph
         const float2 y = Ys[bb][aa];
         const double yr = y.x, yi = y.y;
         double sr = sv.x, si = sv.y;
-        if (phased) {
+        if (phased || hdt != 0.0) {
             const double2 p = zmul(pa[aa], pb[bb]);
             const double r_ = p.x * sr - p.y * si, i_ = p.x * si + p.y * sr;
             sr = r_;
@@ -555,7 +569,8 @@ __global__ __launch_bounds__(256) void sparse_trace_kernel(int d, int N, int ste
                                                            const double* __restrict__ g,
                                                            const int* __restrict__ codes,
                                                            const double* __restrict__ phi, const int* n_steps,
-                                                           double* partial) {
+                                                           double* partial, const double* __restrict__ h,
+                                                           int n_drift, double hdt) {
     constexpr int NE = WP + 1;                      // pattern entries + the diagonal
     __shared__ double red[SPT_RPB][NE][6];
     const int blk = blockIdx.x, sl = blockIdx.y, b = blockIdx.z;
@@ -627,7 +642,12 @@ __global__ __launch_bounds__(256) void sparse_trace_kernel(int d, int N, int ste
             const bool origin = phased && (q == 0 || cartesian);
             const double psi = phased && !origin ? phi[ci] : 0.0;
             if (lane < sw) {
-                const double2 sv = spv[((long long)k * d + a) * sw + lane];
+                double2 sv = spv[((long long)k * d + a) * sw + lane];
+                if (hdt != 0.0) {
+                    // Strang: V(dt/2) S V(dt/2)^dag at entry (a, j)
+                    const long long hb_ = (long long)(b % n_drift) * d;
+                    sv = zmul(expmi(hdt * (h[hb_ + a] - h[hb_ + my_j])), sv);
+                }
                 double cr = sv.x, cim = sv.y;
                 if (phased && psi != 0.0) {
                     const double2 p = expmi(psi * (g[(long long)k * d + a] - g[(long long)k * d + my_j]));
@@ -788,6 +808,7 @@ hipError_t plan_step(const PlanLaunch& p, hipStream_t st) {
     a.n_drift = p.n_drift;
     a.phased = p.phased;
     a.dense = p.dense;
+    a.strang = p.strang;
     a.cache_lo = p.cache_lo;
     a.cache_hi = p.cache_hi;
     a.cache_levels = p.cache_hi - p.cache_lo + 1;
@@ -916,10 +937,11 @@ size_t trace_partial_doubles(int d, int B, int K) { return (size_t)B * K * (d / 
 
 hipError_t traces(int d, int B, int K, int phased, const float2* Y, long long ystride, const float2* S,
                   const double* g, const int* codes, const double* phi, long long code_stride, const int* n_steps,
-                  int step, double* partial, double* out, long long out_bstride, int cartesian, hipStream_t st) {
+                  int step, double* partial, double* out, long long out_bstride, int cartesian, hipStream_t st,
+                  const double* h, int n_drift, double hdt) {
     const int ntile = (d / TT) * (d / TT);
     hipLaunchKernelGGL(trace_partial_kernel, dim3(ntile, K, B), dim3(256), 0, st, d, K, phased, Y, ystride, S, g, codes,
-                       phi, code_stride, n_steps, step, partial, cartesian);
+                       phi, code_stride, n_steps, step, partial, cartesian, h, n_drift, hdt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(trace_final_kernel, dim3(B, K), dim3(64), 0, st, ntile, K, partial, out, out_bstride);
@@ -949,23 +971,24 @@ template <int WP>
 static void launch_spt(dim3 grid, hipStream_t st, int d, int N, int step0, int K, int phased, int cartesian, int sw,
                        const float2* X, long long xsb, const float2* LH, long long lsb, const int* spc,
                        const double2* spv, const double* g, const int* codes, const double* phi, const int* n_steps,
-                       double* partial) {
+                       double* partial, const double* h, int n_drift, double hdt) {
     hipLaunchKernelGGL(sparse_trace_kernel<WP>, grid, dim3(256), 0, st, d, N, step0, K, phased, cartesian, sw, X, xsb,
-                       LH, lsb, spc, spv, g, codes, phi, n_steps, partial);
+                       LH, lsb, spc, spv, g, codes, phi, n_steps, partial, h, n_drift, hdt);
 }
 
 hipError_t sparse_traces(int d, int B, int N, int step0, int steps, int K, int phased, int cartesian, int sw,
                          const float2* X, long long xsb, const float2* LH, long long lsb, const int* spc,
                          const double2* spv, const double* g, const int* codes, const double* phi,
-                         const int* n_steps, double* partial, double* tr, hipStream_t st) {
+                         const int* n_steps, double* partial, double* tr, hipStream_t st, const double* h,
+                         int n_drift, double hdt) {
     if (sw < 1 || sw > SPAT_WMAX || d % SPT_RPB != 0) return hipErrorInvalidValue;
     const dim3 grid(d / SPT_RPB, steps, B);
     const int wp = (sw + 3) / 4 * 4;
     switch (wp) {
-        case 4: launch_spt<4>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial); break;
-        case 8: launch_spt<8>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial); break;
-        case 12: launch_spt<12>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial); break;
-        default: launch_spt<16>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial);
+        case 4: launch_spt<4>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial, h, n_drift, hdt); break;
+        case 8: launch_spt<8>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial, h, n_drift, hdt); break;
+        case 12: launch_spt<12>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial, h, n_drift, hdt); break;
+        default: launch_spt<16>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial, h, n_drift, hdt);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

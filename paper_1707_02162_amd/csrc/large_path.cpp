@@ -196,6 +196,10 @@ long long ceil_sqrt_ll(long long n) {
     return std::max(1LL, c);
 }
 
+// half step of the Strang splitting seen by the adjoint's traces (0: drift-first split, or the
+// plain exponential, which is not split)
+double strang_hdt(const redo_table_s* t, int expm) { return (t->desc.splitting && !expm) ? 0.5 * t->desc.dt : 0.0; }
+
 int gemm_prec(int precision) { return precision == REDO_PREC_F32_3M ? 1 : precision == REDO_PREC_BF16X3 ? 2 : 0; }
 
 redo_status check_precision(int) { return REDO_OK; }
@@ -222,6 +226,7 @@ PlanLaunch plan_base(const redo_table_s* t) {
     p.cache_hi = t->cache_hi;
     p.slots = launch_slots(t);
     p.all_cached = all_cached(t) ? 1 : 0;
+    p.strang = t->desc.splitting;
     return p;
 }
 
@@ -402,7 +407,7 @@ redo_status large_grape_full(redo_table_s* t, int precision, const float* u, con
             const int ns = std::min(w.sch, N - s0);
             REDO_HIP(sparse_traces(d, B, N, s0, ns, K, t->desc.phased, expm, t->spat_w, w.Xs, sX, w.LHs, sL,
                                    t->spat_cols, t->spat_vals, t->g64, cw.codes, t->desc.phased ? cw.phi : nullptr,
-                                   n_steps, w.tpart, w.tr, st));
+                                   n_steps, w.tpart, w.tr, st, t->h64, t->desc.n_drift, strang_hdt(t, expm)));
         }
     } else {
         for (int sidx = 0; sidx < N; ++sidx) {
@@ -412,7 +417,8 @@ redo_status large_grape_full(redo_table_s* t, int precision, const float* u, con
             REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
             REDO_HIP(traces(d, B, K, t->desc.phased, w.Y, mat, t->S32, t->g64, cw.codes + (size_t)sidx * K,
                             t->desc.phased ? cw.phi + (size_t)sidx * K : nullptr, code_stride, n_steps, sidx, w.tpart,
-                            w.tr + (size_t)sidx * K * 6, code_stride * 6, expm, st));
+                            w.tr + (size_t)sidx * K * 6, code_stride * 6, expm, st, t->h64, t->desc.n_drift,
+                            strang_hdt(t, expm)));
         }
     }
     REDO_HIP(d0_traces(d, B, K, t->desc.phased, w.LHs, sL, t->g64, w.d0, st, 1));
@@ -522,7 +528,8 @@ redo_status large_grape(redo_table_s* t, int precision, const float* u, const in
             REDO_HIP(cgemm_batched(d, batch, w.descs, prec, st));
             REDO_HIP(traces(d, B, K, t->desc.phased, w.Y, mat, t->S32, t->g64, cw.codes + (size_t)sidx * K,
                             t->desc.phased ? cw.phi + (size_t)sidx * K : nullptr, code_stride, n_steps, sidx, w.tpart,
-                            w.tr + (size_t)sidx * K * 6, code_stride * 6, expm, st));
+                            w.tr + (size_t)sidx * K * 6, code_stride * 6, expm, st, t->h64, t->desc.n_drift,
+                            strang_hdt(t, expm)));
             std::swap(L, Ln);
         }
         // the rest of the previous segment when this one was shorter

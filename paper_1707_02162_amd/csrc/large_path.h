@@ -49,6 +49,7 @@ struct PlanLaunch {
     long long xstride;
     int* loc;
     int compose, slots, all_cached;
+    int strang;              // 1: half the drift before the controls, half after
     float2* pre;
     float2* post;
     float2* pstar;
@@ -80,7 +81,8 @@ size_t trace_partial_doubles(int d, int B, int K);
 // cartesian = 1: every step takes the traces of the x and y generators (first-order GRAPE gradient)
 hipError_t traces(int d, int B, int K, int phased, const float2* Y, long long ystride, const float2* S,
                   const double* g, const int* codes, const double* phi, long long code_stride, const int* n_steps,
-                  int step, double* partial, double* out, long long out_bstride, int cartesian, hipStream_t st);
+                  int step, double* partial, double* out, long long out_bstride, int cartesian, hipStream_t st,
+                  const double* h = nullptr, int n_drift = 1, double hdt = 0.0);
 hipError_t grad_assemble(int B, int N, int K, int phased, double eps, double dt, const int* codes, const double* phi,
                          const double* tr, const double* d0, const double2* overlap, const double* nu,
                          const int* n_steps, float* grad, int cartesian, hipStream_t st);
@@ -90,7 +92,8 @@ size_t sparse_trace_partial_doubles(int d, int B, int steps, int K);
 hipError_t sparse_traces(int d, int B, int N, int step0, int steps, int K, int phased, int cartesian, int sw,
                          const float2* X, long long xsb, const float2* LH, long long lsb, const int* spc,
                          const double2* spv, const double* g, const int* codes, const double* phi,
-                         const int* n_steps, double* partial, double* tr, hipStream_t st);
+                         const int* n_steps, double* partial, double* tr, hipStream_t st, const double* h,
+                         int n_drift, double hdt);
 hipError_t frob_norms(int d, int B, const float2* U, double* nu, hipStream_t st);
 hipError_t fill_identity(int d, int B, float2* X, long long stride, hipStream_t st);
 

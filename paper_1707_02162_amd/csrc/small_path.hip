@@ -28,6 +28,7 @@ struct TView {
     long long ent;   // d*d
     int d, K, P, base, phased, diag, n_drift;
     int levels;            // cache levels (q = 0 .. levels - 1)
+    int strang;            // 1: U_n = V(dt/2) C_n V(dt/2) (diagonal drift)
     double eps, qmax, dt;
 };
 
@@ -54,6 +55,7 @@ TView view_of(const redo_table_s* t) {
     v.eps = t->desc.eps;
     v.qmax = t->qmax;
     v.dt = t->desc.dt;
+    v.strang = t->desc.splitting;
     return v;
 }
 
@@ -187,12 +189,13 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
     const int KK = tv.phased ? 2 : 1;
     double th[TB];
     step_phases<D>(tv, us, active, ti, th);
-    // drift, then Z^dag (diagonal scalings of rows)
+    // drift (or its first half, Strang), then Z^dag (diagonal scalings of rows)
+    const double hdt = tv.strang ? 0.5 * tv.dt : tv.dt;
     if (tv.diag) {
         if (active) {
 #pragma unroll
             for (int r = 0; r < TB; ++r) {
-                const double2 e = expmi(tv.dt * tv.h[(long long)drift * D + ti + NT * r] - th[r]);
+                const double2 e = expmi(hdt * tv.h[(long long)drift * D + ti + NT * r] - th[r]);
                 const float2 s = make_float2((float)e.x, (float)e.y);
 #pragma unroll
                 for (int c = 0; c < TB; ++c) x[r][c] = cmul(s, x[r][c]);
@@ -258,11 +261,11 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
         }
         if (mult) mul_left<D>(x, Fs, Xs, ti, tj);
     }
-    // Z
-    if (active && tv.phased) {
+    // Z, then the second half of the drift (Strang)
+    if (active && (tv.phased || tv.strang)) {
 #pragma unroll
         for (int r = 0; r < TB; ++r) {
-            const double2 e = expmi(th[r]);
+            const double2 e = expmi(th[r] + (tv.strang ? hdt * tv.h[(long long)drift * D + ti + NT * r] : 0.0));
             const float2 s = make_float2((float)e.x, (float)e.y);
 #pragma unroll
             for (int c = 0; c < TB; ++c) x[r][c] = cmul(s, x[r][c]);
@@ -279,10 +282,12 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
     // column phases: theta_c for the columns the thread owns
     double thc[TB];
     step_phases<D>(tv, us, active, tj, thc);
-    if (active && tv.phased) {
+    const double hdt = tv.strang ? 0.5 * tv.dt : tv.dt;
+    // columns: the second half of the drift (Strang), then Z
+    if (active && (tv.phased || tv.strang)) {
 #pragma unroll
         for (int c = 0; c < TB; ++c) {
-            const double2 e = expmi(thc[c]);
+            const double2 e = expmi(thc[c] + (tv.strang ? hdt * tv.h[(long long)drift * D + tj + NT * c] : 0.0));
             const float2 s = make_float2((float)e.x, (float)e.y);
 #pragma unroll
             for (int r = 0; r < TB; ++r) l[r][c] = cmul(l[r][c], s);
@@ -330,7 +335,7 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
         if (active) {
 #pragma unroll
             for (int c = 0; c < TB; ++c) {
-                const double2 e = expmi(tv.dt * tv.h[(long long)drift * D + tj + NT * c] - thc[c]);
+                const double2 e = expmi(hdt * tv.h[(long long)drift * D + tj + NT * c] - thc[c]);
                 const float2 s = make_float2((float)e.x, (float)e.y);
 #pragma unroll
                 for (int r = 0; r < TB; ++r) l[r][c] = cmul(l[r][c], s);
@@ -658,21 +663,27 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv, SmallGrapeAr
                 if (active) {
                     const double* gk = tv.phased ? tv.g + (long long)k * D : nullptr;
                     const float2* Sk = tv.S + (long long)k * D * D;
-                    // exp(-i psi (g_aa - g_bb)) = pa[c] pb[r] (aa = column index of the block, bb = row)
+                    // exp(-i psi (g_aa - g_bb)) = pa[c] pb[r] (aa = column index of the block, bb = row);
+                    // Strang: the generator seen by the trace is V(dt/2) S V(dt/2)^dag, one more phase
+                    // exp(-i dt/2 (h_aa - h_bb)) in both products
                     double2 pa[TB], pb[TB], qa[TB], qb[TB];
 #pragma unroll
                     for (int t2 = 0; t2 < TB; ++t2) {
                         pa[t2] = make_double2(1.0, 0.0);
                         pb[t2] = make_double2(1.0, 0.0);
+                        if (tv.strang) {
+                            pa[t2] = expmi(0.5 * tv.dt * tv.h[(long long)drift * D + tj + NT * t2]);
+                            pb[t2] = zconj(expmi(0.5 * tv.dt * tv.h[(long long)drift * D + ti + NT * t2]));
+                        }
                         qa[t2] = pa[t2];
                         qb[t2] = pb[t2];
                         if (gk && psi != 0.0) {
-                            pa[t2] = expmi(psi * gk[tj + NT * t2]);
-                            pb[t2] = zconj(expmi(psi * gk[ti + NT * t2]));
+                            pa[t2] = zmul(pa[t2], expmi(psi * gk[tj + NT * t2]));
+                            pb[t2] = zmul(pb[t2], zconj(expmi(psi * gk[ti + NT * t2])));
                         }
                         if (origin) {
-                            qa[t2] = expmi(1.5707963267948966 * gk[tj + NT * t2]);
-                            qb[t2] = zconj(expmi(1.5707963267948966 * gk[ti + NT * t2]));
+                            qa[t2] = zmul(qa[t2], expmi(1.5707963267948966 * gk[tj + NT * t2]));
+                            qb[t2] = zmul(qb[t2], zconj(expmi(1.5707963267948966 * gk[ti + NT * t2])));
                         }
                     }
 #pragma unroll

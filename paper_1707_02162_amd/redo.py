@@ -68,7 +68,7 @@ class _MlpGrads(ctypes.Structure):
 class _Desc(ctypes.Structure):
     _fields_ = [("d", _I), ("K", _I), ("base", _I), ("digits", _I), ("dt", ctypes.c_double),
                 ("eps", ctypes.c_double), ("phased", _I), ("drift_is_diag", _I), ("n_drift", _I),
-                ("reserved", _I)]
+                ("splitting", _I)]
 
 
 def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
@@ -128,7 +128,7 @@ class RedoTable:
     """A built table of discrete operators (process 1) plus drift propagators."""
 
     def __init__(self, d: int, K: int, base: int, digits: int, dt: float, eps: float, phased: bool,
-                 H0, S, g=None, drift_is_diag: bool = True, device: str = "cuda"):
+                 H0, S, g=None, drift_is_diag: bool = True, device: str = "cuda", splitting: str = "lie"):
         self.device = torch.device(device)
         self.d, self.K, self.base, self.digits = d, K, base, digits
         self.dt, self.eps, self.phased = float(dt), float(eps), bool(phased)
@@ -138,7 +138,11 @@ class RedoTable:
         St = _dev(S, torch.complex128, self.device)
         gt = _dev(g, torch.float64, self.device) if phased else None
         self.n_drift = H0t.shape[0]
-        desc = _Desc(d, K, base, digits, self.dt, self.eps, int(phased), int(drift_is_diag), self.n_drift, 0)
+        if splitting not in ("lie", "strang"):
+            raise ValueError("splitting is 'lie' or 'strang'")
+        self.splitting = splitting
+        desc = _Desc(d, K, base, digits, self.dt, self.eps, int(phased), int(drift_is_diag), self.n_drift,
+                     1 if splitting == "strang" else 0)
         h = ctypes.c_void_p()
         _check(lib().redo_build_table(ctypes.byref(desc), _ptr(H0t), _ptr(St), _ptr(gt), _stream(),
                                       ctypes.byref(h)))
@@ -148,7 +152,7 @@ class RedoTable:
     @classmethod
     def from_problem(cls, p, device: str = "cuda") -> "RedoTable":
         return cls(p.d, p.K, p.base, p.digits, p.dt, p.eps, p.phased, p.H0, p.S,
-                   p.g if p.phased else None, p.drift_is_diag, device)
+                   p.g if p.phased else None, p.drift_is_diag, device, getattr(p, "splitting", "lie"))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -39,9 +39,9 @@ def _lib():
 
 def test_bad_descriptors_rejected_on_host():
     R, lib = _lib()
-    good = dict(d=4, K=1, base=16, digits=2, dt=1e-6, eps=1.0, phased=0, drift_is_diag=1, n_drift=1, reserved=0)
+    good = dict(d=4, K=1, base=16, digits=2, dt=1e-6, eps=1.0, phased=0, drift_is_diag=1, n_drift=1, splitting=0)
     bad = [dict(d=3), dict(d=96), dict(K=0), dict(K=17), dict(base=1), dict(digits=0), dict(base=65536, digits=2),
-           dict(dt=0.0), dict(eps=-1.0), dict(phased=2), dict(n_drift=0), dict(reserved=1)]
+           dict(dt=0.0), dict(eps=-1.0), dict(phased=2), dict(n_drift=0), dict(splitting=2)]
     dummy = ctypes.c_void_p(16)
     for b in bad:
         f = dict(good)
@@ -52,6 +52,12 @@ def test_bad_descriptors_rejected_on_host():
         assert st == 1, (b, st)
         assert h.value is None
         assert len(lib.redo_last_error()) > 0
+    # the Strang splitting is provided for diagonal drifts only
+    f = dict(good, splitting=1, drift_is_diag=0)
+    desc = R._Desc(**f)
+    h = ctypes.c_void_p()
+    assert lib.redo_build_table(ctypes.byref(desc), dummy, dummy, None, None, ctypes.byref(h)) == 6
+    assert h.value is None
     # NULL operands and missing phase generators
     desc = R._Desc(**good)
     h = ctypes.c_void_p()

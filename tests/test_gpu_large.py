@@ -363,3 +363,54 @@ def test_large_batch_and_single_calls_bitwise_equal():
     for b in range(p.B):
         U1, _, _ = t.chain(u[b:b + 1].contiguous(), reproject_every=5)
         assert torch.equal(U1[0], U_all[b])
+
+
+# ---------------------------------------------------------------- Strang splitting (NEXT row f1)
+def _strang(p):
+    return W.Problem(**{**p.__dict__, "splitting": "strang"})
+
+
+@pytest.mark.parametrize("cache", [False, True])
+def test_strang_chain_d128_vs_oracle(cache):
+    p = _strang(W.nmr_chain(7, 2, 24, 2e-6, 32, 2, 221))
+    t = R().RedoTable.from_problem(p)
+    if cache:
+        t.cache_levels()
+    U, _, _ = t.chain(torch.tensor(p.u).cuda())
+    U = U.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(p.B):
+        assert nfrob(U[b], O.chain(O.compose_all_redo(p, tab, b))) < FROB_TOL
+
+
+@pytest.mark.parametrize("checkpoint", [1, 5])
+def test_strang_grape_d128_vs_oracle(checkpoint):
+    """Stored states with sparse FP64 traces (1) and recomputed segments with
+    dense traces (5): the traces see V(dt/2) S V(dt/2)^dag."""
+    p = W.nmr_chain(7, 2, 20, 2e-6, 32, 2, 222)
+    p.u[:, ::6] = 0.0
+    p.n_steps = np.array([20, 13], np.int32)
+    p = _strang(p)
+    t = R().RedoTable.from_problem(p)
+    F, ov, grad = t.grape(torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda(),
+                          n_steps=torch.tensor(p.n_steps), checkpoint_every=checkpoint)
+    F, grad = F.cpu().numpy(), grad.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(p.B):
+        Fo, go, gro = O.fidelity_and_gradient(p, b, model="redo", table=tab)
+        nb = int(p.n_steps[b])
+        assert abs(F[b] - Fo) < FID_TOL
+        assert np.linalg.norm(grad[b, :nb] - gro) <= GRAD_TOL * np.linalg.norm(gro)
+
+
+def test_strang_signed_grape_d128_vs_oracle():
+    p = W.ising_freezing(n=7, B=1, N=16)
+    p.U_target = W.haar_unitary(128, W.rng(34, 2, 0))[None]
+    p = _strang(p)
+    t = R().RedoTable.from_problem(p)
+    F, ov, grad = t.grape(torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda())
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    Fo, go, gro = O.fidelity_and_gradient(p, 0, model="redo", table=tab)
+    assert abs(F[0].item() - Fo) < FID_TOL
+    g = grad[0].cpu().numpy()
+    assert np.linalg.norm(g - gro) <= GRAD_TOL * np.linalg.norm(gro)

@@ -385,3 +385,41 @@ def test_level_cache_partial_range_is_not_used_on_fused_path():
     t.cache_levels(0, 100)
     U1, _, _ = t.chain(u)
     assert torch.equal(U0, U1)
+
+
+# ---------------------------------------------------------------- Strang splitting (NEXT row f1)
+def _strang(p):
+    return W.Problem(**{**p.__dict__, "splitting": "strang"})
+
+
+def test_strang_chain_small_vs_oracle_and_second_order():
+    """d = 4 and d = 16: the Strang chain equals the oracle's; against the exact
+    propagator its error is far below the drift-first split's."""
+    for p in (W.c1_two_spin(B=3, N=200), W.c5_four_qubit(B=2, N=100)):
+        ps = _strang(p)
+        t = table(ps)
+        U, _, _ = t.chain(torch.tensor(ps.u).cuda())
+        U = U.cpu().numpy()
+        tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+        for b in range(p.B):
+            assert nfrob(U[b], O.chain(O.compose_all_redo(ps, tab, b))) < FROB_TOL
+        t.cache_levels()
+        Uc, _, _ = t.chain(torch.tensor(ps.u).cuda())
+        assert nfrob(Uc.cpu().numpy()[0], O.chain(O.compose_all_redo(ps, tab, 0))) < FROB_TOL
+
+
+def test_strang_grape_small_vs_oracle():
+    p = W.c1_two_spin(B=2, N=120)
+    p.u[:, ::9] = 0.0
+    ps = _strang(p)
+    t = table(ps)
+    F, ov, grad = t.grape(torch.tensor(ps.u).cuda(), torch.tensor(ps.U_target).cuda())
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    _grape_check(ps, tab, F.cpu().numpy(), ov.cpu().numpy(), grad.cpu().numpy(), range(p.B))
+    q = W.ising_freezing(n=3, B=2, N=90)
+    q.U_target = np.stack([W.haar_unitary(8, W.rng(33, 2, b)) for b in range(2)])
+    qs = _strang(q)
+    t2 = table(qs)
+    F, ov, grad = t2.grape(torch.tensor(qs.u).cuda(), torch.tensor(qs.U_target).cuda())
+    tab2 = O.DiscreteTable(q.S, q.dt, q.eps, q.base, q.digits)
+    _grape_check(qs, tab2, F.cpu().numpy(), ov.cpu().numpy(), grad.cpu().numpy(), range(q.B))
