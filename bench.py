@@ -39,9 +39,11 @@ PEAK_HBM_GBS = 8000.0
 # is unchanged.
 GEMM_TRAFFIC = {
     "source": "paper_1707_02162_amd/csrc/cgemm.hip",
-    "sha256": None,
-    "fetch_bytes": None,
-    "write_bytes": None,
+    "sha256": "12c4c9a468603942a9f7a3d9e64eacf98f3dfbeb9b3d87da1bca0868b4010b70",
+    # FETCH_SIZE 83,942,600 KiB per launch x 2.0000 (a 1 GiB copy reads as 524,302 KiB)
+    "fetch_bytes": 171909689901,
+    # WRITE_SIZE 33,554,432 KiB per launch x 1.0000 (a 1 GiB copy writes 1,048,576 KiB)
+    "write_bytes": 34359738368,
 }
 
 

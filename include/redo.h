@@ -71,7 +71,8 @@ typedef enum {
     REDO_OP_CHAIN = 1,
     REDO_OP_GRAPE = 2,
     REDO_OP_EXPM_CHAIN = 3,
-    REDO_OP_EXPM_GRAPE = 4
+    REDO_OP_EXPM_GRAPE = 4,
+    REDO_OP_STATE_GRAPE = 5
 } redo_op;
 
 /* Problem description of one table (Sec. II coarse graining; Sec. III model). */
@@ -229,6 +230,25 @@ redo_status redo_grape_fidelity_grad(redo_table table, int32_t precision, const 
                                      const float* U_target, int32_t checkpoint_every,
                                      double* fidelity, double* overlap, float* grad,
                                      void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * State-transfer GRAPE through REDO (Sec. III, the state fidelity):
+ *     F_S,b = |<psi_f,b| U_b |psi_0,b>|^2,  U_b = U_N ... U_1 (REDO steps, as in
+ * redo_chain_propagator, the level cache used when it holds every level), and
+ * dF_S/du at the quantised amplitudes, by the forward chain psi_n = U_n psi_{n-1}
+ * and the backward scan chi_{n-1} = U_n^dag chi_n, chi_N = psi_f, with the trace
+ * identities of redo_grape_fidelity_grad on the rank-one Y_n = psi_n chi_n^dag
+ * (no normalisation: g = <psi_f|psi_N>).  Every product is a batched
+ * matrix-vector product (FP32, REDO_PREC_F32 only); every state is kept.
+ * Same channel conditions as redo_grape_fidelity_grad.
+ *   psi0, psi_f  c64 [B][d] (the caller normalises them)
+ *   fidelity double [B];  overlap c128 [B] (g) or NULL;  grad float, same layout as u
+ * Workspace: redo_workspace_bytes(table, REDO_OP_STATE_GRAPE, B, N_max).
+ */
+redo_status redo_grape_state_fidelity_grad(redo_table table, int32_t precision, const float* u,
+                                           const int32_t* n_steps, int32_t B, int32_t N_max, const float* psi0,
+                                           const float* psi_f, double* fidelity, double* overlap, float* grad,
+                                           void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * The comparison point of the method (not REDO): the same chain with every

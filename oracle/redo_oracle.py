@@ -38,6 +38,7 @@ __all__ = [
     "DiscreteTable", "drift_propagator", "phase_diag", "step_redo", "step_split",
     "step_exact", "dirac_step", "chain", "unitary_fidelity", "fidelity_and_gradient",
     "magnetisation", "magnetisation_series", "compose_all_redo", "with_drift",
+    "state_fidelity_and_gradient",
 ]
 
 
@@ -399,6 +400,46 @@ def fidelity_and_gradient(prob, b: int, model: str = "redo", table: Optional[Dis
             dg = np.trace(Lam @ dU @ prefix[n]) / norm
             grad[(n,) + key] = 2.0 * (np.conj(gval) * dg).real
         Lam = Lam @ steps[n]
+    return float(abs(gval) ** 2), complex(gval), grad
+
+
+def state_fidelity_and_gradient(prob, b: int, psi0: np.ndarray, psif: np.ndarray, model: str = "redo",
+                                table: Optional[DiscreteTable] = None, amps: Optional[np.ndarray] = None):
+    """State fidelity of Sec. III, F_S = |<psi_f| U |psi_0>|^2 (unit vectors), and
+    dF_S/du for instance b, with the same step models and step derivatives as
+    fidelity_and_gradient:
+        dg/dtheta_n = <psi_f| U_N .. U_{n+1} dU_n U_{n-1} .. U_1 |psi_0>,
+        dF_S = 2 Re(conj(g) dg).
+    Returns (F_S, g, grad) with grad shaped like u[b, :N_b]."""
+    nb = int(prob.lengths()[b])
+    V, H0m = _drift_of(prob, b)
+    Vh = _half_drift(prob, b) if model in ("redo", "split") else None
+    S, g = prob.S, (prob.g if prob.phased else None)
+    K, d = prob.K, prob.d
+    psi0 = np.asarray(psi0, dtype=np.complex128)
+    psif = np.asarray(psif, dtype=np.complex128)
+    if model == "redo":
+        amp, qz = _quantised_amplitudes(prob, b, nb)
+        steps = [step_redo(table, _step_codes(qz, n), V, g, Vh) for n in range(nb)]
+    else:
+        amp = (prob.u[b, :nb].astype(np.float64) if amps is None else np.asarray(amps, np.float64))
+        if model == "split":
+            steps = [step_split(S, g, amp[n], prob.dt, V, Vh) for n in range(nb)]
+        elif model == "exact":
+            steps = [step_exact(H0m, S, g, amp[n], prob.dt) for n in range(nb)]
+        else:
+            raise ValueError(model)
+    psi = [psi0]                                  # psi_n = U_n .. U_1 psi_0
+    for U in steps:
+        psi.append(U @ psi[-1])
+    gval = np.vdot(psif, psi[-1])
+    grad = np.zeros(amp.shape, dtype=np.float64)
+    chi = psif.copy()                             # chi_n = U_{n+1}^dag .. U_N^dag psi_f
+    for n in range(nb - 1, -1, -1):
+        for key, dU in _step_derivatives(model, S, g, amp[n], prob.dt, V, H0m, K, d, Vh):
+            dg = np.vdot(chi, dU @ psi[n])
+            grad[(n,) + key] = 2.0 * (np.conj(gval) * dg).real
+        chi = steps[n].conj().T @ chi
     return float(abs(gval) ** 2), complex(gval), grad
 
 

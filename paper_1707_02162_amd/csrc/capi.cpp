@@ -509,6 +509,7 @@ size_t redo_workspace_bytes(redo_table t, int32_t op, int32_t B, int32_t N_max) 
     const int d = t->desc.d;
     const size_t mat = sizeof(float2) * (size_t)d * d;
     if ((op == REDO_OP_EXPM_CHAIN || op == REDO_OP_EXPM_GRAPE) && d % 64 == 0) return large_workspace_bytes(t, op, B, N_max);
+    if (op == REDO_OP_STATE_GRAPE) return state_grape_workspace_bytes(t, B, N_max);
     if (small_dim(d)) {
         switch (op) {
             case REDO_OP_COMPOSE:
@@ -655,6 +656,21 @@ redo_status redo_grape_fidelity_grad(redo_table t, int32_t precision, const floa
     }
     return large_grape(t, precision, u, n_steps, B, N_max, U_target, checkpoint_every, fidelity, overlap, grad,
                        workspace, workspace_bytes, hs, 0);
+}
+
+redo_status redo_grape_state_fidelity_grad(redo_table t, int32_t precision, const float* u, const int32_t* n_steps,
+                                           int32_t B, int32_t N_max, const float* psi0, const float* psi_f,
+                                           double* fidelity, double* overlap, float* grad, void* workspace,
+                                           size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    if (B < 1 || N_max < 1) return fail(REDO_ERR_ARG, "B and N_max must be >= 1");
+    if (!u || !psi0 || !psi_f || !fidelity || !grad)
+        return fail(REDO_ERR_ARG, "u, psi0, psi_f, fidelity, grad must not be NULL");
+    if (precision != REDO_PREC_F32) return fail(REDO_ERR_UNSUPPORTED, "state GRAPE runs in FP32");
+    if (!t->grad_ok) return fail(REDO_ERR_UNSUPPORTED, "adjoint needs commuting channels: " + t->grad_why);
+    return state_grape(t, u, n_steps, B, N_max, psi0, psi_f, fidelity, overlap, grad, workspace, workspace_bytes,
+                       static_cast<hipStream_t>(stream));
 }
 
 redo_status redo_expm_chain(redo_table t, int32_t precision, const float* u, const int32_t* n_steps, int32_t B,

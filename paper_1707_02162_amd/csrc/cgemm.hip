@@ -158,8 +158,10 @@ __device__ inline void copy_tile(const GemmDesc& g, int d, int i0, int j0, int B
     }
 }
 
-// MODE 0: 4M, MODE 1: 3M (Gauss)
-template <int BM, int BN, int MODE>
+// MODE 0: 4M, MODE 1: 3M (Gauss).  ROLE only separates the instantiation that
+// the plain-exponential comparison point launches (1) from the method's (0), so
+// that profiles attribute their time apart; the code is the same.
+template <int BM, int BN, int MODE, int ROLE>
 __global__ __launch_bounds__(256) void cgemm_kernel(int d, int batch, const GemmDesc* __restrict__ descs) {
     using C = GCfg<BM, BN>;
     __shared__ float2 As[2][KT * C::LDA];
@@ -547,17 +549,20 @@ hipError_t launch_bf(int d, int batch, const GemmDesc* descs, hipStream_t st) {
 }
 
 template <int BM, int BN, int MODE>
-hipError_t launch(int d, int batch, const GemmDesc* descs, hipStream_t st) {
+hipError_t launch(int d, int batch, const GemmDesc* descs, hipStream_t st, int role) {
     const long long blocks = (long long)(d / BM) * (d / BN) * batch;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((cgemm_kernel<BM, BN, MODE>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
+    if (role)
+        hipLaunchKernelGGL((cgemm_kernel<BM, BN, MODE, 1>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
+    else
+        hipLaunchKernelGGL((cgemm_kernel<BM, BN, MODE, 0>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
     return hipGetLastError();
 }
 
 }  // namespace
 
 // precision: 0 = 4M FP32, 1 = 3M FP32, 2 = split BF16 (hi*hi + hi*lo + lo*hi)
-hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision, hipStream_t st) {
+hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision, hipStream_t st, int role) {
     if (d % 64 != 0 || batch < 1) return hipErrorInvalidValue;
     hipError_t e = hipSuccess;
     const bool big = d % 128 == 0 && (long long)(d / 128) * (d / 64) * batch >= 512;
@@ -568,9 +573,9 @@ hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision,
     if (precision == 2)
         e = big ? launch_bf<128, 64>(d, batch, descs, st) : launch_bf<64, 64>(d, batch, descs, st);
     else if (precision == 1)
-        e = big ? launch<128, 128, 1>(d, batch, descs, st) : launch<64, 64, 1>(d, batch, descs, st);
+        e = big ? launch<128, 128, 1>(d, batch, descs, st, role) : launch<64, 64, 1>(d, batch, descs, st, role);
     else
-        e = big ? launch<128, 64, 0>(d, batch, descs, st) : launch<64, 64, 0>(d, batch, descs, st);
+        e = big ? launch<128, 64, 0>(d, batch, descs, st, role) : launch<64, 64, 0>(d, batch, descs, st, role);
     if (prof) profile_end(st, tok);
     return e;
 }

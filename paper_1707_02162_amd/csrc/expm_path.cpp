@@ -105,7 +105,7 @@ redo_status expm_chunk(const redo_table_s* t, const PSPlan& pl, int prec, int cn
     for (int j = 2; j <= pl.r; ++j) {
         REDO_HIP(expm_descs(w.descs, cnt, w.pw + (size_t)(j - 2) * cnt * nn, nn, w.pw, nn,
                             w.pw + (size_t)(j - 1) * cnt * nn, nn, nullptr, 0, st));
-        REDO_HIP(cgemm_batched(d, cnt, w.descs, prec, st));
+        REDO_HIP(cgemm_batched(d, cnt, w.descs, prec, st, 1));
     }
     // Taylor coefficients 1/i!, block i holds c_{i r} .. c_{i r + r - 1}
     auto coef = [&](int i) { return i > pl.m ? 0.0 : 1.0 / std::tgamma(i + 1.0); };
@@ -124,12 +124,12 @@ redo_status expm_chunk(const redo_table_s* t, const PSPlan& pl, int prec, int cn
         block(i, c);
         REDO_HIP(expm_lincomb(d, cnt, pl.r, c, w.pw, w.Bi, st));
         REDO_HIP(expm_descs(w.descs, cnt, P, nn, w.pw + (size_t)(pl.r - 1) * cnt * nn, nn, P2, nn, w.Bi, nn, st));
-        REDO_HIP(cgemm_batched(d, cnt, w.descs, prec, st));
+        REDO_HIP(cgemm_batched(d, cnt, w.descs, prec, st, 1));
         std::swap(P, P2);
     }
     for (int s = 0; s < pl.s; ++s) {
         REDO_HIP(expm_descs(w.descs, cnt, P, nn, P, nn, P2, nn, nullptr, 0, st));
-        REDO_HIP(cgemm_batched(d, cnt, w.descs, prec, st));
+        REDO_HIP(cgemm_batched(d, cnt, w.descs, prec, st, 1));
         std::swap(P, P2);
     }
     if (P != w.P) REDO_HIP(hipMemcpyAsync(w.P, P, sizeof(float2) * nn * cnt, hipMemcpyDeviceToDevice, st));
@@ -236,15 +236,15 @@ redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int
             s = expm_chunk(t, pl, prec, cnt, b0, 1, u + (long long)n * ustride_pair, ustride_pair * N, w, st);
             if (s != REDO_OK) return s;
             REDO_HIP(chain_descs(descs, cnt, b0, w.P, nn, X[0], X[1], nn, loc, n_steps, n, st));
-            REDO_HIP(cgemm_batched(d, cnt, descs, prec, st));
+            REDO_HIP(cgemm_batched(d, cnt, descs, prec, st, 1));
         }
         if (reproject_every > 0 && ((long long)step_offset + n + 1) % reproject_every == 0) {
             for (int b0 = 0; b0 < B; b0 += 256) {
                 const int ch = std::min(256, B - b0);
                 REDO_HIP(reproject_descs(descs, ch, b0, X[0], X[1], nn, Z, nn, loc, n_steps, n, 0, st));
-                REDO_HIP(cgemm_batched(d, ch, descs, prec, st));
+                REDO_HIP(cgemm_batched(d, ch, descs, prec, st, 1));
                 REDO_HIP(reproject_descs(descs, ch, b0, X[0], X[1], nn, Z, nn, loc, n_steps, n, 1, st));
-                REDO_HIP(cgemm_batched(d, ch, descs, prec, st));
+                REDO_HIP(cgemm_batched(d, ch, descs, prec, st, 1));
             }
         }
         if (obs_out)

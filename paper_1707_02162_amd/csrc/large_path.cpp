@@ -388,7 +388,7 @@ redo_status large_grape_full(redo_table_s* t, int precision, const float* u, con
     const long long sU = mat * N, sX = mat * N, sL = mat * (N + 1);
     // LH_N = U_f (identity left operand: a copy)
     REDO_HIP(fill_descs(w.descs, B, nullptr, 0, 0, Uf, mat, 0, w.LHs + (size_t)N * mat, sL, nullptr, 0, 1, 1.f, 0.f, st));
-    REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
+    REDO_HIP(cgemm_batched(d, B, w.descs, prec, st, expm));
     // step i: X_{i+1} = U_i X_i (X_0 = I) and LH_m = U_m^H LH_{m+1} with m = N - 1 - i;
     // past an instance's length both copy their right operand
     for (int i = 0; i < N; ++i) {
@@ -397,7 +397,7 @@ redo_status large_grape_full(redo_table_s* t, int precision, const float* u, con
                             sX, 0, w.Xs + (size_t)i * mat, sX, n_steps, i, 1, 1.f, 0.f, st));
         REDO_HIP(fill_descs(w.descs + B, B, w.Ustore + (size_t)m * mat, sU, 1, w.LHs + (size_t)(m + 1) * mat, sL, 0,
                             w.LHs + (size_t)m * mat, sL, n_steps, m, 1, 1.f, 0.f, st));
-        REDO_HIP(cgemm_batched(d, 2 * B, w.descs, prec, st));
+        REDO_HIP(cgemm_batched(d, 2 * B, w.descs, prec, st, expm));
     }
     REDO_HIP(unitary_fidelity_strided(d, B, Uf, mat, w.Xs + (size_t)(N - 1) * mat, sX, w.ov, fidelity, st));
     if (overlap) REDO_HIP(hipMemcpyAsync(overlap, w.ov, sizeof(double2) * B, hipMemcpyDeviceToDevice, st));
@@ -414,7 +414,7 @@ redo_status large_grape_full(redo_table_s* t, int precision, const float* u, con
             // Y = X_{s+1} L_{s+1} = X_{s+1} LH_{s+1}^H
             REDO_HIP(fill_descs(w.descs, B, w.Xs + (size_t)sidx * mat, sX, 0, w.LHs + (size_t)(sidx + 1) * mat, sL, 1,
                                 w.Y, mat, n_steps, sidx, 0, 1.f, 0.f, st));
-            REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
+            REDO_HIP(cgemm_batched(d, B, w.descs, prec, st, expm));
             REDO_HIP(traces(d, B, K, t->desc.phased, w.Y, mat, t->S32, t->g64, cw.codes + (size_t)sidx * K,
                             t->desc.phased ? cw.phi + (size_t)sidx * K : nullptr, code_stride, n_steps, sidx, w.tpart,
                             w.tr + (size_t)sidx * K * 6, code_stride * 6, expm, st, t->h64, t->desc.n_drift,
@@ -474,7 +474,7 @@ redo_status large_grape(redo_table_s* t, int precision, const float* u, const in
         if (n % C == 0) {
             REDO_HIP(fill_descs(w.descs, B, nullptr, 0, 0, xin, xin_stride, 0, w.ckpt + (size_t)(n / C) * mat, mat * nck,
                                 n_steps, n, 0, 1.f, 0.f, st));
-            REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
+            REDO_HIP(cgemm_batched(d, B, w.descs, prec, st, expm));
         }
         float2* out;
         long long out_stride;
@@ -489,7 +489,7 @@ redo_status large_grape(redo_table_s* t, int precision, const float* u, const in
         // inactive steps copy the state forward
         REDO_HIP(fill_descs(w.descs, B, w.Ustore + (size_t)n * mat, mat * N, 0, xin, xin_stride, 0, out, out_stride,
                             n_steps, n, 1, 1.f, 0.f, st));
-        REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
+        REDO_HIP(cgemm_batched(d, B, w.descs, prec, st, expm));
         xin = out;
         xin_stride = out_stride;
     }
@@ -499,7 +499,7 @@ redo_status large_grape(redo_table_s* t, int precision, const float* u, const in
     float2* L = w.La;
     float2* Ln = w.Lb;
     REDO_HIP(fill_descs(w.descs, B, nullptr, 0, 0, Uf, mat, 1, L, mat, nullptr, 0, 1, 1.f, 0.f, st));
-    REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
+    REDO_HIP(cgemm_batched(d, B, w.descs, prec, st, expm));
     const long long code_stride = (long long)N * K;
     for (int sg = nck - 1; sg >= 0; --sg) {
         const int s0 = sg * C, s1 = std::min(N, s0 + C);
@@ -525,7 +525,7 @@ redo_status large_grape(redo_table_s* t, int precision, const float* u, const in
                 ++rec;
                 batch = 3 * B;
             }
-            REDO_HIP(cgemm_batched(d, batch, w.descs, prec, st));
+            REDO_HIP(cgemm_batched(d, batch, w.descs, prec, st, expm));
             REDO_HIP(traces(d, B, K, t->desc.phased, w.Y, mat, t->S32, t->g64, cw.codes + (size_t)sidx * K,
                             t->desc.phased ? cw.phi + (size_t)sidx * K : nullptr, code_stride, n_steps, sidx, w.tpart,
                             w.tr + (size_t)sidx * K * 6, code_stride * 6, expm, st, t->h64, t->desc.n_drift,
@@ -535,7 +535,7 @@ redo_status large_grape(redo_table_s* t, int precision, const float* u, const in
         // the rest of the previous segment when this one was shorter
         while (sg > 0 && rec < C) {
             REDO_HIP(rec_descs(w.descs));
-            REDO_HIP(cgemm_batched(d, B, w.descs, prec, st));
+            REDO_HIP(cgemm_batched(d, B, w.descs, prec, st, expm));
             ++rec;
         }
         cur_seg ^= 1;

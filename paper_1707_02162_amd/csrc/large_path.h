@@ -69,6 +69,11 @@ constexpr int OBS_CHUNK = 256;
 // that needs at most this much workspace and no checkpoint interval is given
 constexpr size_t GRAPE_FULL_STORAGE_BYTES = size_t(48) << 30;
 // checkpoint interval used for a requested one (0: automatic)
+// state-transfer GRAPE on vectors (every d)
+size_t state_grape_workspace_bytes(const redo_table_s* t, int B, int N);
+redo_status state_grape(redo_table_s* t, const float* u, const int* n_steps, int B, int N, const float* psi0,
+                        const float* psif, double* fidelity, double* overlap, float* grad, void* workspace,
+                        size_t workspace_bytes, hipStream_t st);
 int large_grape_checkpoint(const redo_table_s* t, int B, int N, int requested, int expm);
 hipError_t observable(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
                       const int* cols, const float2* vals, int w, const int* n_steps, int step, double* partial,

@@ -214,7 +214,8 @@ struct GemmDesc {
 };
 static_assert(sizeof(GemmDesc) % 8 == 0, "desc alignment");
 
-hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision, hipStream_t st);
+// role 1: the plain-exponential comparison point (a separate kernel instantiation for profiles)
+hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision, hipStream_t st, int role = 0);
 
 // launch timing (profile.cpp)
 bool profiling_on();

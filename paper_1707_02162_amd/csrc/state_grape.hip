@@ -1,0 +1,499 @@
+// State-transfer GRAPE (Sec. III, the state fidelity F_S = |<psi_f|psi(T)>|^2):
+// the forward chain psi_n = U_n psi_{n-1} and the backward scan
+// chi_{n-1} = U_n^dag chi_n (chi_N = psi_f) on vectors, with every step
+// applied as its REDO factors (process 2, or the composed levels of process
+// 3) between the drift and phase scalings of the split step (Sec. III, Eqs.
+// vn and vnd).  The gradient uses the same trace identities as the unitary
+// adjoint with the rank-one Y_n = psi_n chi_n^dag:
+//     dg/dOmega_kn = -i dt chi_n^dag Z S_k Z^dag psi_n,
+//     dg/dphi_kn   = -i (chi_n^dag G_k psi_n - chi_{n-1}^dag G_k psi_{n-1}),
+// g = <psi_f|psi_N>, dF_S = 2 Re(conj(g) dg).  Every product is a batched
+// matrix-vector product over the instances; traces accumulate in FP64.
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "large_path.h"
+
+namespace redo {
+namespace {
+
+struct MvDesc {
+    const float2* F;      // d x d factor, or null (identity)
+    const float2* pre;    // scaling of the input vector, or null
+    const float2* post;   // scaling of the output vector, or null
+    const float2* x;
+    float2* y;
+    int adj;              // 1: y = post . F^dag (pre . x)
+    int conj_scales;      // 1: conj(pre), conj(post)
+};
+
+constexpr int MV_ROWS = 64;   // output rows per workgroup
+
+// y = post . op(F) (pre . x) for rows [r0, r0 + 64) of one instance
+__global__ __launch_bounds__(256) void matvec_kernel(int d, const MvDesc* __restrict__ descs, int B) {
+    extern __shared__ float2 xs[];   // pre . x, d entries
+    __shared__ float2 part[4][MV_ROWS];
+    const int b = blockIdx.y;
+    const int r0 = blockIdx.x * MV_ROWS;
+    const MvDesc m = descs[b];
+    const int tid = threadIdx.x;
+    for (int c = tid; c < d; c += 256) {
+        float2 v = m.x[c];
+        if (m.pre) {
+            const float2 p = m.pre[c];
+            v = cmul(m.conj_scales ? cconj(p) : p, v);
+        }
+        xs[c] = v;
+    }
+    __syncthreads();
+    float2 acc = make_float2(0.f, 0.f);
+    const int lane = tid & 63, wave = tid >> 6;
+    int r = r0 + lane;
+    if (!m.F) {
+        // identity factor: a scaled copy
+        if (wave == 0 && r < d) {
+            float2 v = xs[r];
+            if (m.post) {
+                const float2 p = m.post[r];
+                v = cmul(m.conj_scales ? cconj(p) : p, v);
+            }
+            m.y[r] = v;
+        }
+        return;
+    }
+    if (m.adj) {
+        // y_r = sum_c conj(F[c][r]) x_c: lanes over r (coalesced rows of F), waves split c
+        if (r < d)
+            for (int c = wave; c < d; c += 4) cfma(acc, cconj(m.F[(long long)c * d + r]), xs[c]);
+        part[wave][lane] = acc;
+        __syncthreads();
+        if (wave == 0 && r < d) {
+            float2 v = make_float2(part[0][lane].x + part[1][lane].x + part[2][lane].x + part[3][lane].x,
+                                   part[0][lane].y + part[1][lane].y + part[2][lane].y + part[3][lane].y);
+            if (m.post) {
+                const float2 p = m.post[r];
+                v = cmul(m.conj_scales ? cconj(p) : p, v);
+            }
+            m.y[r] = v;
+        }
+    } else {
+        // y_r = sum_c F[r][c] x_c: a wave per row, lanes over c (coalesced), shuffle reduction
+        for (int rr = wave; rr < MV_ROWS; rr += 4) {
+            const int row = r0 + rr;
+            if (row >= d) break;
+            float2 a = make_float2(0.f, 0.f);
+            for (int c = lane; c < d; c += 64) cfma(a, m.F[(long long)row * d + c], xs[c]);
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                a.x += __shfl_xor(a.x, o);
+                a.y += __shfl_xor(a.y, o);
+            }
+            if (lane == 0) {
+                if (m.post) {
+                    const float2 p = m.post[row];
+                    a = cmul(m.conj_scales ? cconj(p) : p, a);
+                }
+                m.y[row] = a;
+            }
+        }
+    }
+}
+
+struct StatePlan {
+    const float2* T;
+    const float2* V;        // dense drifts or null
+    const double* h;        // diagonal drifts or null
+    const double* g;
+    const float2* cache;
+    const int* codes;       // [B][N][K] (this step at + step * K)
+    const double* phi;
+    const int* n_steps;
+    long long ent;
+    int d, K, P, base, n_drift, phased, dense, strang, cache_levels, all_cached, slots, N, step, backward;
+    double dt;
+    const float2* src;      // input vectors [B], stride vs
+    float2* dst;            // output vectors [B], stride vs
+    long long src_stride, dst_stride;
+    float2* tmp0;           // [B][d] ping-pong for the slots in between
+    float2* tmp1;
+    float2 *pre, *post, *pstar;   // [B][d]
+    MvDesc* descs;          // [slots][B]
+    int B;
+};
+
+// per instance: the step's scale vectors and one descriptor per slot.  Forward
+// (psi <- U psi): pre on slot 0 (with the dense drift as slot 0 and Z^dag after it),
+// post on the last slot.  Backward (chi <- U^dag chi): the slots in reverse order,
+// adjoint factors, conjugated scalings.
+__global__ void state_plan_kernel(StatePlan a) {
+    const int b = blockIdx.x, d = a.d;
+    const bool active = a.n_steps ? a.step < a.n_steps[b] : true;
+    const int* cb = a.codes + ((long long)b * a.N + a.step) * a.K;
+    const double* pb = a.phi ? a.phi + ((long long)b * a.N + a.step) * a.K : nullptr;
+    const int drift = b % a.n_drift;
+    for (int r = threadIdx.x; r < d; r += blockDim.x) {
+        double th = 0.0;
+        if (a.phased)
+            for (int k = 0; k < a.K; ++k) th += pb[k] * a.g[(long long)k * d + r];
+        const double hd = (!a.dense && a.strang) ? 0.5 * a.dt * a.h[(long long)drift * d + r] : 0.0;
+        const double2 po = expmi(th + hd);
+        a.post[(long long)b * d + r] = make_float2((float)po.x, (float)po.y);
+        a.pstar[(long long)b * d + r] = make_float2((float)po.x, (float)-po.y);
+        if (!a.dense) {
+            const double hdt = a.strang ? 0.5 * a.dt : a.dt;
+            const double2 pr = expmi(hdt * a.h[(long long)drift * d + r] - th);
+            a.pre[(long long)b * d + r] = make_float2((float)pr.x, (float)pr.y);
+        }
+    }
+    if (threadIdx.x != 0) return;
+    const int S = a.slots;
+    for (int i = 0; i < S; ++i) {
+        // forward slot index of the i-th application
+        const int s = a.backward ? S - 1 - i : i;
+        MvDesc m{};
+        m.x = i == 0 ? a.src + (long long)b * a.src_stride : ((i - 1) % 2 == 0 ? a.tmp0 : a.tmp1) + (long long)b * d;
+        m.y = i == S - 1 ? a.dst + (long long)b * a.dst_stride : (i % 2 == 0 ? a.tmp0 : a.tmp1) + (long long)b * d;
+        if (active) {
+            int fadj = 0;
+            if (a.dense && s == 0) {
+                m.F = a.V + (long long)drift * a.ent;
+            } else {
+                const int slot = s - a.dense;
+                const int k = a.all_cached ? slot : slot / a.P;
+                const int j = a.all_cached ? 0 : slot % a.P;
+                const int q = cb[k];
+                const int aq = q < 0 ? -q : q;
+                fadj = q < 0 ? 1 : 0;
+                if (a.all_cached) {
+                    if (aq != 0) m.F = a.cache + ((long long)k * a.cache_levels + aq) * a.ent;
+                } else {
+                    const int c = digit_of(q, j, a.base);
+                    if (c) m.F = a.T + ((long long)(k * a.P + j) * (a.base - 1) + (c - 1)) * a.ent;
+                }
+            }
+            m.adj = a.backward ? 1 - fadj : fadj;
+            // the scalings of the forward step: pre before slot 0 (diagonal drift), Z^dag after
+            // the dense drift (slot 0), Z (times the second half drift, Strang) after the last slot
+            const float2* fpre = (!a.dense && s == 0) ? a.pre + (long long)b * d : nullptr;
+            const float2* fpost = nullptr;
+            if (a.dense && s == 0 && a.phased) fpost = a.pstar + (long long)b * d;
+            if (s == S - 1 && (a.phased || a.strang) && !(a.dense && s == 0)) {
+                fpost = a.post + (long long)b * d;
+            }
+            if (!a.backward) {
+                m.pre = fpre;
+                m.post = fpost;
+            } else {
+                m.pre = fpost;
+                m.post = fpre;
+                m.conj_scales = 1;
+            }
+        }
+        a.descs[(long long)i * a.B + b] = m;
+    }
+}
+
+// Traces of Y = psi chi^dag for step s (psi = psi_{s+1}, chi = chi_{s+1}) and every channel:
+//   T1 = chi^dag S^psi psi, T2 = chi^dag S^{pi/2} psi (phased, q = 0), D = chi^dag G psi,
+// with S^psi_aj = exp(-i psi (g_a - g_j)) S_aj (times exp(-i dt/2 (h_a - h_j)), Strang).
+// One workgroup per (instance, step); the column phases ride on psi (rounded to FP32 in
+// LDS), the row phases on chi; sums in FP64.
+__global__ __launch_bounds__(256) void state_trace_kernel(int d, int N, int K, int phased, int strang, double dt,
+                                                          int n_drift, const float2* __restrict__ Psi,
+                                                          const float2* __restrict__ Chi, long long vs,
+                                                          const float2* __restrict__ S32, const int* spc,
+                                                          const double2* spv, int sw, const double* g,
+                                                          const double* h, const int* codes, const double* phi,
+                                                          const int* n_steps, double* tr) {
+    extern __shared__ float2 pv[];   // [2][d]: psi with the column phases of T1 and of T2
+    __shared__ double red[6][256];
+    const int s = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+    const bool active = n_steps ? s < n_steps[b] : true;
+    const float2* psi = Psi + (long long)b * vs + (long long)(s + 1) * d;
+    const float2* chi = Chi + (long long)b * vs + (long long)(s + 1) * d;
+    const long long hb = (long long)(b % n_drift) * d;
+    for (int k = 0; k < K; ++k) {
+        const long long ci = ((long long)b * N + s) * K + k;
+        const int q = active ? codes[ci] : 1;
+        const bool origin = phased && q == 0;
+        const double ps = (phased && !origin && active) ? phi[ci] : 0.0;
+        const double hdt = strang ? 0.5 * dt : 0.0;
+        __syncthreads();
+        for (int j = tid; j < d; j += 256) {
+            const double gj = phased ? g[(long long)k * d + j] : 0.0;
+            const double hj = strang ? h[hb + j] : 0.0;
+            const float2 x = psi[j];
+            const double2 e1 = zconj(expmi(ps * gj + hdt * hj));
+            pv[j] = make_float2((float)(e1.x * x.x - e1.y * x.y), (float)(e1.x * x.y + e1.y * x.x));
+            if (origin) {
+                const double2 e2 = zconj(expmi(1.5707963267948966 * gj + hdt * hj));
+                pv[d + j] = make_float2((float)(e2.x * x.x - e2.y * x.y), (float)(e2.x * x.y + e2.y * x.x));
+            }
+        }
+        __syncthreads();
+        double v[6] = {0, 0, 0, 0, 0, 0};
+        if (active)
+            for (int a = tid; a < d; a += 256) {
+                const double ga = phased ? g[(long long)k * d + a] : 0.0;
+                const double ha = strang ? h[hb + a] : 0.0;
+                const float2 c = chi[a];
+                // row factor conj(chi_a) exp(-i (psi g_a + dt/2 h_a))
+                const double2 ra = zmul(make_double2(c.x, -c.y), expmi(ps * ga + hdt * ha));
+                double s1r = 0, s1i = 0, s2r = 0, s2i = 0;
+                if (sw > 0) {
+                    for (int t = 0; t < sw; ++t) {
+                        const int j = spc[(long long)a * sw + t];
+                        const double2 sv = spv[((long long)k * d + a) * sw + t];
+                        const float2 x = pv[j];
+                        s1r += sv.x * x.x - sv.y * x.y;
+                        s1i += sv.x * x.y + sv.y * x.x;
+                        if (origin) {
+                            const float2 x2 = pv[d + j];
+                            s2r += sv.x * x2.x - sv.y * x2.y;
+                            s2i += sv.x * x2.y + sv.y * x2.x;
+                        }
+                    }
+                } else {
+                    const float2* Sr = S32 + (long long)k * d * d + (long long)a * d;
+                    for (int j = 0; j < d; ++j) {
+                        const float2 sv = Sr[j];
+                        const float2 x = pv[j];
+                        s1r += (double)sv.x * x.x - (double)sv.y * x.y;
+                        s1i += (double)sv.x * x.y + (double)sv.y * x.x;
+                        if (origin) {
+                            const float2 x2 = pv[d + j];
+                            s2r += (double)sv.x * x2.x - (double)sv.y * x2.y;
+                            s2i += (double)sv.x * x2.y + (double)sv.y * x2.x;
+                        }
+                    }
+                }
+                v[0] += ra.x * s1r - ra.y * s1i;
+                v[1] += ra.x * s1i + ra.y * s1r;
+                if (origin) {
+                    const double2 ra2 = zmul(make_double2(c.x, -c.y), expmi(1.5707963267948966 * ga + hdt * ha));
+                    v[2] += ra2.x * s2r - ra2.y * s2i;
+                    v[3] += ra2.x * s2i + ra2.y * s2r;
+                }
+                if (phased) {
+                    const float2 x = psi[a];
+                    // conj(chi_a) g_a psi_a
+                    v[4] += ga * ((double)c.x * x.x + (double)c.y * x.y);
+                    v[5] += ga * ((double)c.x * x.y - (double)c.y * x.x);
+                }
+            }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) red[c][tid] = v[c];
+        __syncthreads();
+        for (int st = 128; st > 0; st >>= 1) {
+            if (tid < st)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) red[c][tid] += red[c][tid + st];
+            __syncthreads();
+        }
+        if (tid < 6) tr[(((long long)b * N + s) * K + k) * 6 + tid] = red[tid][0];
+    }
+}
+
+// overlap g = <psi_f|psi_N> (FP64), F_S = |g|^2; D_0 = chi_0^dag G psi_0; nu = 1
+__global__ void state_final_kernel(int d, int K, int phased, const float2* psif, const float2* Psi, const float2* Chi,
+                                   long long vs, int N, const int* n_steps, const double* g, double2* ov,
+                                   double* fidelity, double* d0, double* nu) {
+    const int b = blockIdx.x, tid = threadIdx.x;
+    __shared__ double red[2][256];
+    const float2* pn = Psi + (long long)b * vs + (long long)N * d;
+    double gr = 0, gi = 0;
+    for (int a = tid; a < d; a += 256) {
+        const float2 f = psif[(long long)b * d + a], x = pn[a];
+        gr += (double)f.x * x.x + (double)f.y * x.y;
+        gi += (double)f.x * x.y - (double)f.y * x.x;
+    }
+    red[0][tid] = gr;
+    red[1][tid] = gi;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st) {
+            red[0][tid] += red[0][tid + st];
+            red[1][tid] += red[1][tid + st];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        ov[b] = make_double2(red[0][0], red[1][0]);
+        if (fidelity) fidelity[b] = red[0][0] * red[0][0] + red[1][0] * red[1][0];
+        nu[b] = 1.0;
+    }
+    const float2* p0 = Psi + (long long)b * vs;
+    const float2* c0 = Chi + (long long)b * vs;
+    for (int k = 0; k < K; ++k) {
+        __syncthreads();
+        double dr = 0, di = 0;
+        if (phased)
+            for (int a = tid; a < d; a += 256) {
+                const double ga = g[(long long)k * d + a];
+                const float2 c = c0[a], x = p0[a];
+                dr += ga * ((double)c.x * x.x + (double)c.y * x.y);
+                di += ga * ((double)c.x * x.y - (double)c.y * x.x);
+            }
+        red[0][tid] = dr;
+        red[1][tid] = di;
+        __syncthreads();
+        for (int st = 128; st > 0; st >>= 1) {
+            if (tid < st) {
+                red[0][tid] += red[0][tid + st];
+                red[1][tid] += red[1][tid + st];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            d0[((long long)b * K + k) * 2] = red[0][0];
+            d0[((long long)b * K + k) * 2 + 1] = red[1][0];
+        }
+    }
+}
+
+__global__ void copy_vectors_kernel(int d, int B, const float2* src, long long ss, float2* dst, long long ds) {
+    const int b = blockIdx.y;
+    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < d; a += gridDim.x * blockDim.x)
+        dst[(long long)b * ds + a] = src[(long long)b * ss + a];
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct StateWS {
+    int* codes;
+    double* phi;
+    float2 *Psi, *Chi, *tmp0, *tmp1, *pre, *post, *pstar;
+    MvDesc* descs;
+    double *tr, *d0, *nu;
+    double2* ov;
+    size_t bytes;
+    StateWS(const redo_table_s* t, int B, int N, int slots, void* base) {
+        const int d = t->desc.d, K = t->desc.K;
+        char* p = static_cast<char*>(base);
+        size_t used = 0;
+        auto take = [&](size_t n) {
+            char* q = p ? p + used : nullptr;
+            used += align_up(n);
+            return q;
+        };
+        codes = reinterpret_cast<int*>(take(sizeof(int) * (size_t)B * N * K));
+        phi = reinterpret_cast<double*>(take(sizeof(double) * (size_t)B * N * K));
+        Psi = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * (N + 1) * d));
+        Chi = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * (N + 1) * d));
+        tmp0 = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * d));
+        tmp1 = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * d));
+        pre = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * d));
+        post = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * d));
+        pstar = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * d));
+        descs = reinterpret_cast<MvDesc*>(take(sizeof(MvDesc) * (size_t)B * slots));
+        tr = reinterpret_cast<double*>(take(sizeof(double) * (size_t)B * N * K * 6));
+        d0 = reinterpret_cast<double*>(take(sizeof(double) * (size_t)B * K * 2));
+        nu = reinterpret_cast<double*>(take(sizeof(double) * (size_t)B));
+        ov = reinterpret_cast<double2*>(take(sizeof(double2) * (size_t)B));
+        bytes = used;
+    }
+};
+
+bool cached_all(const redo_table_s* t) {
+    return t->cache && t->cache_lo == 0 && (double)t->cache_hi >= t->qmax;
+}
+
+int state_slots(const redo_table_s* t) {
+    return (t->desc.drift_is_diag ? 0 : 1) + (cached_all(t) ? t->desc.K : t->desc.K * t->desc.digits);
+}
+
+}  // namespace
+
+size_t state_grape_workspace_bytes(const redo_table_s* t, int B, int N) {
+    return StateWS(t, B, N, state_slots(t), nullptr).bytes;
+}
+
+redo_status state_grape(redo_table_s* t, const float* u, const int* n_steps, int B, int N, const float* psi0,
+                        const float* psif, double* fidelity, double* overlap, float* grad, void* workspace,
+                        size_t workspace_bytes, hipStream_t st) {
+    const int S = state_slots(t);
+    StateWS need(t, B, N, S, nullptr);
+    if (!workspace || workspace_bytes < need.bytes)
+        return fail(REDO_ERR_WORKSPACE, "state GRAPE workspace needs " + std::to_string(need.bytes) + " bytes");
+    StateWS w(t, B, N, S, workspace);
+    const int d = t->desc.d, K = t->desc.K;
+    const long long vs = (long long)(N + 1) * d;
+    REDO_HIP(quantise_all(t, u, B, N, w.codes, w.phi, st));
+    // psi_0 and chi_N
+    REDO_HIP(hipMemcpy2DAsync(w.Psi, sizeof(float2) * vs, psi0, sizeof(float2) * d, sizeof(float2) * d, B,
+                              hipMemcpyDeviceToDevice, st));
+    REDO_HIP(hipMemcpy2DAsync(w.Chi + (size_t)N * d, sizeof(float2) * vs, psif, sizeof(float2) * d, sizeof(float2) * d,
+                              B, hipMemcpyDeviceToDevice, st));
+    StatePlan p{};
+    p.T = t->T32;
+    p.V = t->desc.drift_is_diag ? nullptr : t->V32;
+    p.h = t->h64;
+    p.g = t->g64;
+    p.cache = t->cache;
+    p.codes = w.codes;
+    p.phi = t->desc.phased ? w.phi : nullptr;
+    p.n_steps = n_steps;
+    p.ent = t->entry_elems;
+    p.d = d;
+    p.K = K;
+    p.P = t->desc.digits;
+    p.base = t->desc.base;
+    p.n_drift = t->desc.n_drift;
+    p.phased = t->desc.phased;
+    p.dense = t->desc.drift_is_diag ? 0 : 1;
+    p.strang = t->desc.splitting;
+    p.cache_levels = t->cache ? t->cache_hi - t->cache_lo + 1 : 0;
+    p.all_cached = cached_all(t) ? 1 : 0;
+    p.slots = S;
+    p.N = N;
+    p.dt = t->desc.dt;
+    p.tmp0 = w.tmp0;
+    p.tmp1 = w.tmp1;
+    p.pre = w.pre;
+    p.post = w.post;
+    p.pstar = w.pstar;
+    p.descs = w.descs;
+    p.B = B;
+    p.src_stride = vs;
+    p.dst_stride = vs;
+    const dim3 mv_grid((d + MV_ROWS - 1) / MV_ROWS, B);
+    const size_t mv_lds = sizeof(float2) * (size_t)d;
+    REDO_HIP(hipFuncSetAttribute((const void*)matvec_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mv_lds));
+    auto run_step = [&](int n, int backward) -> hipError_t {
+        p.step = n;
+        p.backward = backward;
+        p.src = backward ? w.Chi + (size_t)(n + 1) * d : w.Psi + (size_t)n * d;
+        p.dst = backward ? w.Chi + (size_t)n * d : w.Psi + (size_t)(n + 1) * d;
+        hipLaunchKernelGGL(state_plan_kernel, dim3(B), dim3(256), 0, st, p);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        for (int i = 0; i < S; ++i) {
+            hipLaunchKernelGGL(matvec_kernel, mv_grid, dim3(256), mv_lds, st, d, w.descs + (size_t)i * B, B);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    if (S == 0) return fail(REDO_ERR_UNSUPPORTED, "no factor slots");
+    for (int n = 0; n < N; ++n) REDO_HIP(run_step(n, 0));
+    for (int n = N - 1; n >= 0; --n) REDO_HIP(run_step(n, 1));
+    hipLaunchKernelGGL(state_final_kernel, dim3(B), dim3(256), 0, st, d, K, t->desc.phased,
+                       reinterpret_cast<const float2*>(psif), w.Psi, w.Chi, vs, N, n_steps, t->g64, w.ov, fidelity,
+                       w.d0, w.nu);
+    REDO_HIP(hipGetLastError());
+    if (overlap) REDO_HIP(hipMemcpyAsync(overlap, w.ov, sizeof(double2) * B, hipMemcpyDeviceToDevice, st));
+    const size_t tr_lds = sizeof(float2) * 2 * (size_t)d;
+    REDO_HIP(hipFuncSetAttribute((const void*)state_trace_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)tr_lds));
+    hipLaunchKernelGGL(state_trace_kernel, dim3(N, B), dim3(256), tr_lds, st, d, N, K, t->desc.phased,
+                       t->desc.splitting, t->desc.dt, t->desc.n_drift, w.Psi, w.Chi, vs, t->S32, t->spat_cols,
+                       t->spat_vals, t->spat_w, t->g64, t->h64, w.codes, t->desc.phased ? w.phi : nullptr, n_steps,
+                       w.tr);
+    REDO_HIP(hipGetLastError());
+    REDO_HIP(grad_assemble(B, N, K, t->desc.phased, t->desc.eps, t->desc.dt, w.codes,
+                           t->desc.phased ? w.phi : nullptr, w.tr, w.d0, w.ov, w.nu, n_steps, grad, 0, st));
+    return REDO_OK;
+}
+
+}  // namespace redo

@@ -17,7 +17,7 @@ import torch
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libredo.so")
 
 PREC_F32, PREC_F32_3M, PREC_BF16X3 = 0, 1, 2
-OP_COMPOSE, OP_CHAIN, OP_GRAPE, OP_EXPM_CHAIN, OP_EXPM_GRAPE = 0, 1, 2, 3, 4
+OP_COMPOSE, OP_CHAIN, OP_GRAPE, OP_EXPM_CHAIN, OP_EXPM_GRAPE, OP_STATE_GRAPE = 0, 1, 2, 3, 4, 5
 STATUS = {0: "REDO_OK", 1: "REDO_ERR_ARG", 2: "REDO_ERR_ALLOC", 3: "REDO_ERR_HIP", 4: "REDO_ERR_NOT_HERMITIAN",
           5: "REDO_ERR_NONFINITE", 6: "REDO_ERR_UNSUPPORTED", 7: "REDO_ERR_WORKSPACE", 100: "REDO_WARN_CLAMPED"}
 
@@ -39,6 +39,7 @@ _SIG = {
     "redo_grape_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _I, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "redo_expm_chain": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P, _P, ctypes.c_size_t, _P]),
     "redo_expm_grape_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _I, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "redo_grape_state_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "redo_get_device_status": (_I, [_P, _P, ctypes.POINTER(ctypes.c_int64)]),
     "redo_profile_enable": (_I, [_I]),
     "redo_profile_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _I]),
@@ -267,6 +268,22 @@ class RedoTable:
                                      _ptr(X0t), _ptr(U), _ptr(cols), _ptr(vals), w, _ptr(obs), _ptr(ws), ws.numel(),
                                      _stream()))
         return U, obs
+
+    def state_grape(self, u, psi0, psi_f, n_steps=None):
+        """State-transfer GRAPE: F_S = |<psi_f|U|psi_0>|^2 and dF_S/du.
+        psi0, psi_f complex [B, d].  Returns (F double [B], overlap complex128 [B], grad like u)."""
+        ut = self._u(u)
+        B, N = ut.shape[:2]
+        ns = None if n_steps is None else _dev(n_steps, torch.int32, self.device)
+        p0 = _dev(psi0, torch.complex64, self.device)
+        pf = _dev(psi_f, torch.complex64, self.device)
+        F = torch.empty(B, dtype=torch.float64, device=self.device)
+        ov = torch.empty(B, dtype=torch.complex128, device=self.device)
+        grad = torch.empty_like(ut)
+        ws = self.workspace(OP_STATE_GRAPE, B, N)
+        _check(lib().redo_grape_state_fidelity_grad(self._h, PREC_F32, _ptr(ut), _ptr(ns), B, N, _ptr(p0), _ptr(pf),
+                                                    _ptr(F), _ptr(ov), _ptr(grad), _ptr(ws), ws.numel(), _stream()))
+        return F, ov, grad
 
     def expm_grape(self, u, U_target, n_steps=None, precision: int = PREC_F32):
         """GRAPE objective and first-order gradient with the plain per-step exponential."""

@@ -2,10 +2,17 @@
 
 A three-layer perceptron (tanh, BF16 weights, FP32 accumulation) maps the
 2 d^2 real entries of a global-phase-free target unitary to the initial
-control amplitudes of a REDO-GRAPE run.  It is trained on pulses that
-REDO-GRAPE itself optimised.  Plain REDO-GRAPE stays both the fallback (a
-random start is used whenever it starts better than the network's proposal)
-and the judge: every reported fidelity is the library's REDO fidelity.
+control amplitudes of a REDO-GRAPE run.  It is trained on (target, pulse)
+pairs whose pulses REDO-GRAPE brought to infidelity <= 1e-4: by default the
+smooth pulse that produced each reachable target, refined by REDO-GRAPE where
+needed, so that the target -> pulse map it learns is single valued (labels
+from REDO-GRAPE runs started at independent random pulses land on different
+solutions for the same target, and a least-squares fit averages them into
+nothing useful; `--labels grape` keeps that variant).  Plain REDO-GRAPE stays
+both the fallback (a random start is used whenever it starts better than the
+network's proposal, and after a network start that misses the goal within the
+budget) and the judge: every reported fidelity is the library's REDO
+fidelity.
 
 Every arithmetic step runs in libredo.so: the network's forward and backward
 passes, its Adam updates, the target features, the REDO chains and the GRAPE
@@ -109,6 +116,14 @@ class WarmStartMLP:
             adam_(self.b[l], self.gb[l], self.mb[l], self.vb[l], self.step, lr)
         return loss
 
+    def train_step_upstream(self, x, y, dl_dy, lr: float):
+        """One Adam step for an arbitrary loss whose gradient with respect to the
+        output y (computed by forward(x)) is dl_dy: the least-squares backward
+        with the pseudo-target y - (n/2) dl_dy has exactly that upstream
+        gradient (n = number of output entries of the batch)."""
+        n = y.numel()
+        return self.train_step(x, (y - 0.5 * n * dl_dy).contiguous(), lr)
+
 
 def grape(table: R.RedoTable, u0: torch.Tensor, Uf: torch.Tensor, u_max: float, iters: int, lr: float,
           goal: float = 1e-4, history: bool = False, log=None, tag: str = "grape", lr_final: Optional[float] = None):
@@ -151,12 +166,14 @@ def grape(table: R.RedoTable, u0: torch.Tensor, Uf: torch.Tensor, u_max: float, 
     return torch.where(done, u_best, u), F, reached, hist
 
 
-def reachable_targets(table: R.RedoTable, p: W.Problem, config_id: int, B: int, start: int = 0) -> torch.Tensor:
-    """Targets reached by smooth seeded pulses (so that a solution exists)."""
+def reachable_targets(table: R.RedoTable, p: W.Problem, config_id: int, B: int):
+    """Targets reached by smooth seeded pulses (so that a solution exists).
+    Returns (U_f, the pulses that produce them)."""
     gen = W.nmr_chain(4, B, p.N, p.dt, p.base, p.digits, config_id, species=[[0, 1], [2, 3]],
                       targets=False)
-    U, _, _ = table.chain(torch.tensor(gen.u, device="cuda"))
-    return U
+    ug = torch.tensor(gen.u, device="cuda")
+    U, _, _ = table.chain(ug)
+    return U, ug
 
 
 def random_starts(p: W.Problem, config_id: int, B: int) -> torch.Tensor:
@@ -166,16 +183,29 @@ def random_starts(p: W.Problem, config_id: int, B: int) -> torch.Tensor:
 
 def experiment(n_train: int, n_test: int, N: int = 500, grape_iters: int = 2000, lr_grape: float = 1000.0,
                epochs: int = 40, batch: int = 256, lr_net: float = 1e-3, width: int = 512, goal: float = 1e-4,
-               log=print):
-    """C5-shaped run: d = 16, two species with collective X/Y, N steps of 2 us."""
+               labels: str = "source", loss: str = "both", fid_epochs: int = 40, log=print):
+    """C5-shaped run: d = 16, two species with collective X/Y, N steps of 2 us.
+
+    labels "source": each training target is labelled with the smooth pulse
+      that produced it, refined by REDO-GRAPE from that pulse to infidelity
+      <= goal where needed (a single-valued target -> pulse map);
+    labels "grape": REDO-GRAPE from an independent random smooth start (the
+      solution reached depends on the start, so the same target can carry
+      very different labels).
+
+    loss "mse": least squares to the labels; "fidelity": 1 - F of the
+      proposed pulse for its target, its gradient dF/du from the library's
+      REDO-GRAPE adjoint back-propagated through the network (any pulse that
+      reaches the target is a right answer); "both": least squares, then
+      fid_epochs of the fidelity loss."""
     p = W.c5_four_qubit(B=1, N=N)
     table = R.RedoTable.from_problem(p)
     table.cache_levels()
     u_max = float(p.u_scale)
     t0 = time.time()
-    # training set: reachable targets, REDO-GRAPE from random smooth starts
-    Uf = reachable_targets(table, p, 501, n_train)
-    u0 = random_starts(p, 502, n_train)
+    # training set: reachable targets and REDO-GRAPE-optimised pulses for them
+    Uf, ug = reachable_targets(table, p, 501, n_train)
+    u0 = ug if labels == "source" else random_starts(p, 502, n_train)
     u_opt, F_opt, it_opt, _ = grape(table, u0, Uf, u_max, grape_iters, lr_grape, goal=goal, log=log, tag="dataset")
     keep = (1.0 - F_opt) <= goal
     log(f"[warmstart] dataset: {int(keep.sum())}/{n_train} optimised to {goal:g} in {time.time() - t0:.1f}s")
@@ -195,8 +225,28 @@ def experiment(n_train: int, n_test: int, N: int = 500, grape_iters: int = 2000,
         if ep % 10 == 0:
             log(f"[warmstart] epoch {ep}: loss {losses[-1]:.4f}")
     log(f"[warmstart] trained {epochs} epochs, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    fid_losses = []
+    if loss in ("fidelity", "both"):
+        Ufk = Uf[keep].contiguous()
+        shape = (batch,) + tuple(u0.shape[1:])
+        for ep in range(fid_epochs):
+            perm = torch.randperm(X.shape[0], device="cuda", generator=torch.Generator(device="cuda").manual_seed(1000 + ep))
+            tot = 0.0
+            for i in range(nb):
+                idx = perm[i * batch:(i + 1) * batch]
+                y = net.forward(X[idx])
+                u_b = (y * u_max).reshape((len(idx),) + shape[1:]).contiguous()
+                Fb, _, gb = table.grape(u_b, Ufk[idx])
+                # loss = mean over the batch of (1 - F); dF/dy = dF/du * u_max
+                dl_dy = -(gb.reshape(len(idx), -1) * u_max) / len(idx)
+                net.train_step_upstream(X[idx], y, dl_dy, lr_net)
+                tot += float((1.0 - Fb).mean())
+            fid_losses.append(tot / nb)
+            if ep % 10 == 0:
+                log(f"[warmstart] fidelity epoch {ep}: mean infidelity of the proposals {fid_losses[-1]:.4f}")
+        log(f"[warmstart] fidelity training: mean infidelity {fid_losses[0]:.4f} -> {fid_losses[-1]:.4f}")
     # held-out targets: network start (with fallback) vs random start
-    Ut = reachable_targets(table, p, 601, n_test)
+    Ut, _ = reachable_targets(table, p, 601, n_test)
     ur = random_starts(p, 602, n_test)
     un = (net.forward(target_features(Ut)) * u_max).reshape(ur.shape).contiguous()
     Fr0, _, _ = table.grape(ur, Ut)
@@ -215,8 +265,11 @@ def experiment(n_train: int, n_test: int, N: int = 500, grape_iters: int = 2000,
     conv_fb = its_fb >= 0
     both = conv_r & conv_fb
     res = dict(
+        labels=labels, dataset_grape_iters_median=float(it_opt[keep].double().median()) if keep.any() else None,
         n_train=n_train, n_train_converged=int(keep.sum()), n_test=n_test, N=N, epochs=epochs, goal=goal,
-        loss_first=losses[0], loss_last=losses[-1],
+        loss_first=losses[0], loss_last=losses[-1], loss_kind=loss,
+        fidelity_loss_first=fid_losses[0] if fid_losses else None,
+        fidelity_loss_last=fid_losses[-1] if fid_losses else None,
         start_infidelity_random_median=float((1 - Fr0).median()), start_infidelity_net_median=float((1 - Fn0).median()),
         net_start_used=int(use_net.sum()),
         converged_random=int(conv_r.sum()), converged_warm=int(conv_s.sum()),
@@ -243,9 +296,13 @@ def main():
     ap.add_argument("--goal", type=float, default=1e-4)
     ap.add_argument("--lr-grape", type=float, default=1000.0)
     ap.add_argument("--width", type=int, default=512)
+    ap.add_argument("--labels", choices=["source", "grape"], default="source")
+    ap.add_argument("--loss", choices=["mse", "fidelity", "both"], default="both")
+    ap.add_argument("--fid-epochs", type=int, default=40)
     a = ap.parse_args()
     res = experiment(a.train, a.test, N=a.N, grape_iters=a.grape_iters, lr_grape=a.lr_grape, epochs=a.epochs,
-                     goal=a.goal, width=a.width, log=lambda s: print(s, file=sys.stderr, flush=True))
+                     goal=a.goal, width=a.width, labels=a.labels, loss=a.loss, fid_epochs=a.fid_epochs,
+                     log=lambda s: print(s, file=sys.stderr, flush=True))
     print(json.dumps(res))
 
 

@@ -501,3 +501,48 @@ def test_strang_gradient_vs_central_differences(maker):
     _, _, grad = O.fidelity_and_gradient(p, 0, model="split")
     fd = _fd_grad(p, 0, amp0, "split", 1e-6 * p.u_scale)
     assert np.linalg.norm(grad - fd) <= 1e-7 * np.linalg.norm(fd)
+
+
+# ------------------------------------------------------------------ state-transfer fidelity (NEXT row f2)
+def _fd_state(p, b, amp0, psi0, psif, model, h):
+    fd = np.zeros_like(amp0)
+    for idx in np.ndindex(*amp0.shape):
+        a1 = amp0.copy(); a1[idx] += h
+        a2 = amp0.copy(); a2[idx] -= h
+        F1 = O.state_fidelity_and_gradient(p, b, psi0, psif, model=model, amps=a1)[0]
+        F2 = O.state_fidelity_and_gradient(p, b, psi0, psif, model=model, amps=a2)[0]
+        fd[idx] = (F1 - F2) / (2 * h)
+    return fd
+
+
+def test_state_fidelity_single_spin_closed_form():
+    """One spin, no drift, x drive of area theta: |<up| exp(-i theta I_x) |up>|^2 = cos^2(theta/2)."""
+    S = W.collective(1, [0], "x")[None]
+    dt, N = 1e-5, 7
+    u = np.full((1, N, 1), 2 * np.pi * 3e3, np.float32)
+    p = W.Problem("spin", 2, 1, False, np.zeros((1, 2)), True, S, None, dt, 1.0, 2, 1, u)
+    up = np.array([1.0, 0.0])
+    F, g, _ = O.state_fidelity_and_gradient(p, 0, up, up, model="split")
+    theta = float(u[0, 0, 0]) * dt * N
+    assert abs(F - np.cos(theta / 2) ** 2) < 1e-12
+    dn = np.array([0.0, 1.0])
+    F2, _, _ = O.state_fidelity_and_gradient(p, 0, up, dn, model="split")
+    assert abs(F2 - np.sin(theta / 2) ** 2) < 1e-12
+
+
+def test_state_fidelity_is_a_propagator_entry_and_gradient_matches_fd():
+    p = W.c1_two_spin(B=1, N=6)
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    X = O.chain(O.compose_all_redo(p, tab, 0))
+    e = np.eye(4)
+    F, g, _ = O.state_fidelity_and_gradient(p, 0, e[1], e[2], model="redo", table=tab)
+    assert abs(g - X[2, 1]) < 1e-12 and abs(F - abs(X[2, 1]) ** 2) < 1e-12
+    rng = np.random.default_rng(5)
+    psi0 = rng.normal(size=4) + 1j * rng.normal(size=4)
+    psif = rng.normal(size=4) + 1j * rng.normal(size=4)
+    psi0 /= np.linalg.norm(psi0)
+    psif /= np.linalg.norm(psif)
+    for model in ("split", "exact"):
+        _, _, grad = O.state_fidelity_and_gradient(p, 0, psi0, psif, model=model)
+        fd = _fd_state(p, 0, p.u[0].astype(float), psi0, psif, model, 1e-6 * p.u_scale)
+        assert np.linalg.norm(grad - fd) <= 1e-7 * np.linalg.norm(fd)
