@@ -39,9 +39,9 @@ PEAK_HBM_GBS = 8000.0
 # is unchanged.
 GEMM_TRAFFIC = {
     "source": "paper_1707_02162_amd/csrc/cgemm.hip",
-    "sha256": "12c4c9a468603942a9f7a3d9e64eacf98f3dfbeb9b3d87da1bca0868b4010b70",
-    # FETCH_SIZE 83,942,600 KiB per launch x 2.0000 (a 1 GiB copy reads as 524,302 KiB)
-    "fetch_bytes": 171909689901,
+    "sha256": "a852b0a6c75d1031a542857e2cf42b11b70409afc6f5b2f0008b612dae335cc7",
+    # FETCH_SIZE 83,943,145 KiB per launch (mean of 3) x 1.99994 (a 1 GiB copy reads as 524,302.5 KiB)
+    "fetch_bytes": 171910805945,
     # WRITE_SIZE 33,554,432 KiB per launch x 1.0000 (a 1 GiB copy writes 1,048,576 KiB)
     "write_bytes": 34359738368,
 }

@@ -200,6 +200,34 @@ __global__ void fill_descs_kernel(GemmDesc* descs, int count, const float2* A, l
     descs[b] = g;
 }
 
+// GRAPE with every state kept: descriptors of all paired launches in one pass
+__global__ void grape_pair_descs_kernel(GemmDesc* descs, int N, int B, const float2* U, long long sU, float2* X,
+                                        long long sX, float2* LH, long long sL, long long mat, const int* n_steps) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)2 * N * B) return;
+    const int b = (int)(e % B);
+    const int which = (int)((e / B) % 2);
+    const int i = (int)(e / (2LL * B));
+    const int len = n_steps ? n_steps[b] : N;
+    GemmDesc g{};
+    g.active = 1;
+    g.alpha = 1.f;
+    if (which == 0) {
+        // X_{i+1} = U_i X_i (X_0 = I: the identity right operand is a copy)
+        g.A = i < len ? U + b * sU + (long long)i * mat : nullptr;
+        g.B = i == 0 ? nullptr : X + b * sX + (long long)(i - 1) * mat;
+        g.C = X + b * sX + (long long)i * mat;
+    } else {
+        // LH_m = U_m^H LH_{m+1}; past the length a copy of LH_{m+1}
+        const int m = N - 1 - i;
+        g.A = m < len ? U + b * sU + (long long)m * mat : nullptr;
+        g.opA = 1;
+        g.B = LH + b * sL + (long long)(m + 1) * mat;
+        g.C = LH + b * sL + (long long)m * mat;
+    }
+    descs[e] = g;
+}
+
 // Observable in two passes over the instance (each pass reads X once):
 //   pass 1: T = M X from column strips of X held in LDS (every row index available),
 //   pass 2: (X M)_ac = sum_t X_a,cols[c][t] conj(vals[c][t]) from row blocks in LDS,
@@ -857,6 +885,14 @@ hipError_t fill_descs(GemmDesc* descs, int count, const float2* A, long long sA,
                       float beta, hipStream_t st) {
     hipLaunchKernelGGL(fill_descs_kernel, dim3((count + 63) / 64), dim3(64), 0, st, descs, count, A, sA, opA, B, sB,
                        opB, C, sC, n_steps, step, inactive_mode, alpha, beta);
+    return hipGetLastError();
+}
+
+hipError_t grape_pair_descs(GemmDesc* descs, int N, int B, const float2* U, long long sU, float2* X, long long sX,
+                            float2* LH, long long sL, long long mat, const int* n_steps, hipStream_t st) {
+    const long long n = (long long)2 * N * B;
+    hipLaunchKernelGGL(grape_pair_descs_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, descs, N, B, U, sU,
+                       X, sX, LH, sL, mat, n_steps);
     return hipGetLastError();
 }
 

@@ -178,7 +178,7 @@ struct FullGrapeWS {
         d0 = c.take<double>((size_t)B * K * 2);
         nu = c.take<double>(B);
         ov = c.take<double2>(B);
-        descs = c.take<GemmDesc>((size_t)2 * B);
+        descs = c.take<GemmDesc>((size_t)2 * B * N);   // the paired launches of every step
         comp_base = base ? c.base + c.used : nullptr;
         ComposeWS cw(t, (long long)B * N, nullptr);
         c.used += expm ? std::max(cw.bytes, align_up(sizeof(int) * (size_t)B * N * t->desc.K) +
@@ -391,14 +391,9 @@ redo_status large_grape_full(redo_table_s* t, int precision, const float* u, con
     REDO_HIP(cgemm_batched(d, B, w.descs, prec, st, expm));
     // step i: X_{i+1} = U_i X_i (X_0 = I) and LH_m = U_m^H LH_{m+1} with m = N - 1 - i;
     // past an instance's length both copy their right operand
-    for (int i = 0; i < N; ++i) {
-        const int m = N - 1 - i;
-        REDO_HIP(fill_descs(w.descs, B, w.Ustore + (size_t)i * mat, sU, 0, i == 0 ? nullptr : w.Xs + (size_t)(i - 1) * mat,
-                            sX, 0, w.Xs + (size_t)i * mat, sX, n_steps, i, 1, 1.f, 0.f, st));
-        REDO_HIP(fill_descs(w.descs + B, B, w.Ustore + (size_t)m * mat, sU, 1, w.LHs + (size_t)(m + 1) * mat, sL, 0,
-                            w.LHs + (size_t)m * mat, sL, n_steps, m, 1, 1.f, 0.f, st));
-        REDO_HIP(cgemm_batched(d, 2 * B, w.descs, prec, st, expm));
-    }
+    // the descriptors of every paired launch at once, then one batched GEMM per step
+    REDO_HIP(grape_pair_descs(w.descs, N, B, w.Ustore, sU, w.Xs, sX, w.LHs, sL, mat, n_steps, st));
+    for (int i = 0; i < N; ++i) REDO_HIP(cgemm_batched(d, 2 * B, w.descs + (size_t)i * 2 * B, prec, st, expm));
     REDO_HIP(unitary_fidelity_strided(d, B, Uf, mat, w.Xs + (size_t)(N - 1) * mat, sX, w.ov, fidelity, st));
     if (overlap) REDO_HIP(hipMemcpyAsync(overlap, w.ov, sizeof(double2) * B, hipMemcpyDeviceToDevice, st));
     const long long code_stride = (long long)N * K;

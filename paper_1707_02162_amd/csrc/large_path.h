@@ -69,6 +69,10 @@ constexpr int OBS_CHUNK = 256;
 // that needs at most this much workspace and no checkpoint interval is given
 constexpr size_t GRAPE_FULL_STORAGE_BYTES = size_t(48) << 30;
 // checkpoint interval used for a requested one (0: automatic)
+// descriptors of the paired GRAPE launches of every step i (forward X_{i+1} = U_i X_i, backward
+// LH_m = U_m^H LH_{m+1}, m = N - 1 - i): descs[(2 i + which) B + b]
+hipError_t grape_pair_descs(GemmDesc* descs, int N, int B, const float2* U, long long sU, float2* X, long long sX,
+                            float2* LH, long long sL, long long mat, const int* n_steps, hipStream_t st);
 // state-transfer GRAPE on vectors (every d)
 size_t state_grape_workspace_bytes(const redo_table_s* t, int B, int N);
 redo_status state_grape(redo_table_s* t, const float* u, const int* n_steps, int B, int N, const float* psi0,
