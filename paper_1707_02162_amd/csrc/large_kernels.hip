@@ -790,23 +790,6 @@ __global__ void d0_kernel(int d, int K, int phased, const float2* L, long long l
     }
 }
 
-__global__ void norm_kernel(long long nn, const float2* U, double* nu) {
-    const int b = blockIdx.x;
-    __shared__ double r[256];
-    double s = 0;
-    for (long long e = threadIdx.x; e < nn; e += 256) {
-        const float2 v = U[b * nn + e];
-        s += (double)v.x * v.x + (double)v.y * v.y;
-    }
-    r[threadIdx.x] = s;
-    __syncthreads();
-    for (int t = 128; t > 0; t >>= 1) {
-        if ((int)threadIdx.x < t) r[threadIdx.x] += r[threadIdx.x + t];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) nu[b] = r[0];
-}
-
 __global__ void identity_kernel(long long nn, int d, int B, float2* X, long long stride) {
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn * B;
          e += (long long)gridDim.x * blockDim.x) {
@@ -1037,11 +1020,6 @@ hipError_t sparse_traces(int d, int B, int N, int step0, int steps, int K, int p
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
-}
-
-hipError_t frob_norms(int d, int B, const float2* U, double* nu, hipStream_t st) {
-    hipLaunchKernelGGL(norm_kernel, dim3(B), dim3(256), 0, st, (long long)d * d, U, nu);
-    return hipGetLastError();
 }
 
 hipError_t fill_identity(int d, int B, float2* X, long long stride, hipStream_t st) {

@@ -113,6 +113,7 @@ struct GrapeWS {
     double* d0;
     double* nu;
     double2* ov;
+    double* fpart;
     GemmDesc* descs;
     size_t bytes;
     GrapeWS(const redo_table_s* t, int B, int N, int C, void* base, int expm = 0) {
@@ -133,6 +134,7 @@ struct GrapeWS {
         d0 = c.take<double>((size_t)B * K * 2);
         nu = c.take<double>(B);
         ov = c.take<double2>(B);
+        fpart = c.take<double>(fidelity_partial_doubles(B));
         descs = c.take<GemmDesc>((size_t)3 * B);
         comp_base = base ? c.base + c.used : nullptr;
         ComposeWS cw(t, (long long)B * N, nullptr);
@@ -160,6 +162,7 @@ struct FullGrapeWS {
     double* d0;
     double* nu;
     double2* ov;
+    double* fpart;
     GemmDesc* descs;
     int sch;
     size_t bytes;
@@ -178,6 +181,7 @@ struct FullGrapeWS {
         d0 = c.take<double>((size_t)B * K * 2);
         nu = c.take<double>(B);
         ov = c.take<double2>(B);
+        fpart = c.take<double>(fidelity_partial_doubles(B));
         descs = c.take<GemmDesc>((size_t)2 * B * N);   // the paired launches of every step
         comp_base = base ? c.base + c.used : nullptr;
         ComposeWS cw(t, (long long)B * N, nullptr);
@@ -384,7 +388,6 @@ redo_status large_grape_full(redo_table_s* t, int precision, const float* u, con
         s = compose_pairs(t, precision, (long long)B * N, N, cw, w.Ustore, st);
     }
     if (s != REDO_OK) return s;
-    REDO_HIP(frob_norms(d, B, Uf, w.nu, st));
     const long long sU = mat * N, sX = mat * N, sL = mat * (N + 1);
     // LH_N = U_f (identity left operand: a copy)
     REDO_HIP(fill_descs(w.descs, B, nullptr, 0, 0, Uf, mat, 0, w.LHs + (size_t)N * mat, sL, nullptr, 0, 1, 1.f, 0.f, st));
@@ -394,7 +397,7 @@ redo_status large_grape_full(redo_table_s* t, int precision, const float* u, con
     // the descriptors of every paired launch at once, then one batched GEMM per step
     REDO_HIP(grape_pair_descs(w.descs, N, B, w.Ustore, sU, w.Xs, sX, w.LHs, sL, mat, n_steps, st));
     for (int i = 0; i < N; ++i) REDO_HIP(cgemm_batched(d, 2 * B, w.descs + (size_t)i * 2 * B, prec, st, expm));
-    REDO_HIP(unitary_fidelity_strided(d, B, Uf, mat, w.Xs + (size_t)(N - 1) * mat, sX, w.ov, fidelity, st));
+    REDO_HIP(unitary_fidelity_sliced(d, B, Uf, mat, w.Xs + (size_t)(N - 1) * mat, sX, w.ov, fidelity, w.nu, w.fpart, st));
     if (overlap) REDO_HIP(hipMemcpyAsync(overlap, w.ov, sizeof(double2) * B, hipMemcpyDeviceToDevice, st));
     const long long code_stride = (long long)N * K;
     if (t->spat_w > 0) {
@@ -453,7 +456,6 @@ redo_status large_grape(redo_table_s* t, int precision, const float* u, const in
         s = compose_pairs(t, precision, (long long)B * N, N, cw, w.Ustore, st);
     }
     if (s != REDO_OK) return s;
-    REDO_HIP(frob_norms(d, B, Uf, w.nu, st));
     // forward chain with checkpoints X_0, X_C, ...; the states of the last segment go
     // straight into a segment buffer so that segment needs no recomputation
     const int nck = (N + C - 1) / C;
@@ -488,7 +490,7 @@ redo_status large_grape(redo_table_s* t, int precision, const float* u, const in
         xin = out;
         xin_stride = out_stride;
     }
-    REDO_HIP(unitary_fidelity_strided(d, B, Uf, mat, xin, xin_stride, w.ov, fidelity, st));
+    REDO_HIP(unitary_fidelity_sliced(d, B, Uf, mat, xin, xin_stride, w.ov, fidelity, w.nu, w.fpart, st));
     if (overlap) REDO_HIP(hipMemcpyAsync(overlap, w.ov, sizeof(double2) * B, hipMemcpyDeviceToDevice, st));
     // backward: L_N = U_f^dag
     float2* L = w.La;

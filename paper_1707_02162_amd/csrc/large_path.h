@@ -103,7 +103,6 @@ hipError_t sparse_traces(int d, int B, int N, int step0, int steps, int K, int p
                          const double2* spv, const double* g, const int* codes, const double* phi,
                          const int* n_steps, double* partial, double* tr, hipStream_t st, const double* h,
                          int n_drift, double hdt);
-hipError_t frob_norms(int d, int B, const float2* U, double* nu, hipStream_t st);
 hipError_t fill_identity(int d, int B, float2* X, long long stride, hipStream_t st);
 
 }  // namespace redo

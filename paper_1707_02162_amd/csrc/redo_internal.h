@@ -191,8 +191,11 @@ size_t small_grape_workspace_bytes(int d, int K, long long B, long long N_max, l
 // fidelity reduction, FP64
 hipError_t unitary_fidelity(int d, int B, const float2* Uf, const float2* U, double2* overlap,
                             double* fidelity, hipStream_t st);
-hipError_t unitary_fidelity_strided(int d, int B, const float2* Uf, long long sf, const float2* U, long long su,
-                                    double2* overlap, double* fidelity, hipStream_t st);
+// the same over many workgroups per instance (slices), FP64 partials in part
+// (fidelity_partial_doubles(B) doubles); also writes nu = Tr(U_f^dag U_f) when nu is not null
+size_t fidelity_partial_doubles(int B);
+hipError_t unitary_fidelity_sliced(int d, int B, const float2* Uf, long long sf, const float2* U, long long su,
+                                   double2* overlap, double* fidelity, double* nu, double* part, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // large-d path (d >= 128, d % 64 == 0): batched complex GEMM on MFMA

@@ -414,3 +414,4 @@ def test_strang_signed_grape_d128_vs_oracle():
     assert abs(F[0].item() - Fo) < FID_TOL
     g = grad[0].cpu().numpy()
     assert np.linalg.norm(g - gro) <= GRAD_TOL * np.linalg.norm(gro)
+
