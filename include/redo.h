@@ -72,7 +72,8 @@ typedef enum {
     REDO_OP_GRAPE = 2,
     REDO_OP_EXPM_CHAIN = 3,
     REDO_OP_EXPM_GRAPE = 4,
-    REDO_OP_STATE_GRAPE = 5
+    REDO_OP_STATE_GRAPE = 5,
+    REDO_OP_KRON_CHAIN = 6
 } redo_op;
 
 /* Problem description of one table (Sec. II coarse graining; Sec. III model). */
@@ -190,6 +191,37 @@ redo_status redo_chain_propagator(redo_table table, int32_t precision, const flo
                                   float* U_total, float* X_prefix, const int32_t* obs_cols,
                                   const float* obs_vals, int32_t obs_width, double* obs_out,
                                   void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Spin structure of the table's generators: *n_spins = n when d = 2^n and every
+ * S_k is a sum of single-spin terms, S_k = sum_q s_kq with s_kq a 2 x 2
+ * Hermitian acting on bit q of the basis index (checked when the table is
+ * built, entry by entry in FP64 to 1e-12 relative), else 0.
+ */
+redo_status redo_table_spins(redo_table table, int32_t* n_spins);
+
+/*
+ * Structure-aware chain: a competitor of the dense REDO factors, not the
+ * paper's method.  With spin-structured generators (redo_table_spins > 0) the
+ * control factors of one step factorise over the spins,
+ *     exp(-i theta S_k) = (x)_q exp(-i theta s_kq),
+ * so the split step of Sec. III (Eq. propUn: U_n = Z_n (prod_k R_k) Z_n^dag V,
+ * or the Strang form) acts on the rows of X as a diagonal scaling, one 2 x 2
+ * unitary per spin g_q = prod_k exp(-i theta_k s_kq) (FP64, rounded once to
+ * FP32), and a diagonal scaling: O(n d^2) work per step instead of O(d^3).
+ *   quantised  1: theta_k = dt x the REDO-quantised amplitude (Sec. II, Eq.
+ *                 cgrain), the same U_n as redo_chain_propagator up to
+ *                 rounding; 0: the amplitudes as given (the exact split step)
+ * Other arguments, layouts, the observable and the re-projection as
+ * redo_chain_propagator (FP32).  Needs d = 128 .. 4096 and a diagonal drift;
+ * REDO_ERR_UNSUPPORTED otherwise.
+ * Workspace: redo_workspace_bytes(table, REDO_OP_KRON_CHAIN, B, N_max).
+ */
+redo_status redo_kron_chain(redo_table table, int32_t quantised, const float* u, const int32_t* n_steps,
+                            int32_t B, int32_t N_max, int32_t step_offset, int32_t reproject_every,
+                            const float* X0, float* U_total, const int32_t* obs_cols, const float* obs_vals,
+                            int32_t obs_width, double* obs_out, void* workspace, size_t workspace_bytes,
+                            void* stream);
 
 /*
  * Unitary fidelity (Sec. III): g_b = Tr(U_f^dag U) / Tr(U_f^dag U_f),

@@ -324,6 +324,56 @@ redo_status redo_build_table(const redo_table_desc* desc, const double* H0, cons
         }
     }
 
+    // single-spin structure of the generators: S_k = sum_q s_kq, s_kq acting on bit q of the
+    // basis index.  The off-diagonal entries of s_kq are S_k[0][2^q] and S_k[2^q][0]; the
+    // diagonal of S_k must be c + sum_q D_q bit_q(a), split as c/n + D_q bit_q(a) over the
+    // spins.  Accepted when the sum reproduces S_k entry by entry to 1e-12 relative.
+    {
+        int n = 0;
+        while ((1 << n) < d) ++n;
+        if ((1 << n) == d && n >= 1) {
+            std::vector<double> ks((size_t)K * n * 8, 0.0);
+            bool ok = true;
+            for (int k = 0; k < K && ok; ++k) {
+                const double* m = hS.data() + 2 * nn * k;
+                auto at = [&](size_t i, size_t j, int c) { return m[2 * (i * d + j) + c]; };
+                double scale = 0.0;
+                for (size_t e = 0; e < nn; ++e) scale = std::max(scale, std::hypot(m[2 * e], m[2 * e + 1]));
+                const double tol = 1e-12 * std::max(scale, 1e-300);
+                const double c0 = at(0, 0, 0);
+                for (int q = 0; q < n; ++q) {
+                    double* o = ks.data() + ((size_t)k * n + q) * 8;
+                    const size_t p = (size_t)1 << q;
+                    o[0] = c0 / n;                                   // s[0][0]
+                    o[2] = at(0, p, 0), o[3] = at(0, p, 1);          // s[0][1]
+                    o[4] = at(p, 0, 0), o[5] = at(p, 0, 1);          // s[1][0]
+                    o[6] = c0 / n + (at(p, p, 0) - c0);              // s[1][1]
+                }
+                for (size_t a = 0; a < (size_t)d && ok; ++a)
+                    for (size_t j = 0; j < (size_t)d && ok; ++j) {
+                        double er = 0.0, ei = 0.0;
+                        const size_t x = a ^ j;
+                        if (x == 0) {
+                            for (int q = 0; q < n; ++q) er += ks[((size_t)k * n + q) * 8 + (((a >> q) & 1) ? 6 : 0)];
+                        } else if ((x & (x - 1)) == 0) {
+                            int q = 0;
+                            while (((size_t)1 << q) != x) ++q;
+                            const double* o = ks.data() + ((size_t)k * n + q) * 8 + (((a >> q) & 1) ? 4 : 2);
+                            er = o[0];
+                            ei = o[1];
+                        }
+                        if (std::fabs(at(a, j, 0) - er) > tol || std::fabs(at(a, j, 1) - ei) > tol) ok = false;
+                    }
+            }
+            if (ok) {
+                REDO_HIP(alloc((void**)&t->kron_s, sizeof(double) * ks.size()));
+                REDO_HIP(hipMemcpyAsync(t->kron_s, ks.data(), sizeof(double) * ks.size(), hipMemcpyHostToDevice, hs));
+                REDO_HIP(hipStreamSynchronize(hs));
+                t->kron_n = n;
+            }
+        }
+    }
+
     // ---- FP64 build: E_kj = exp(-i b^j eps dt S_k), T_kj[c] = E_kj^c
     {
         const int KP = K * P;
@@ -404,8 +454,8 @@ redo_status redo_build_table(const redo_table_desc* desc, const double* H0, cons
 redo_status redo_table_destroy(redo_table t) {
     if (!t) return REDO_OK;
     (void)hipDeviceSynchronize();
-    void* bufs[] = {t->T32, t->h64,   t->V32,   t->g64,       t->S32,      t->S64, t->Sy32,
-                    t->H32, t->flags, t->cache, t->spat_cols, t->spat_vals};
+    void* bufs[] = {t->T32, t->h64,   t->V32,   t->g64,       t->S32,      t->S64,      t->Sy32,
+                    t->H32, t->flags, t->cache, t->spat_cols, t->spat_vals, t->kron_s};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     delete t;
@@ -510,6 +560,7 @@ size_t redo_workspace_bytes(redo_table t, int32_t op, int32_t B, int32_t N_max) 
     const size_t mat = sizeof(float2) * (size_t)d * d;
     if ((op == REDO_OP_EXPM_CHAIN || op == REDO_OP_EXPM_GRAPE) && d % 64 == 0) return large_workspace_bytes(t, op, B, N_max);
     if (op == REDO_OP_STATE_GRAPE) return state_grape_workspace_bytes(t, B, N_max);
+    if (op == REDO_OP_KRON_CHAIN) return kron_supported(t) ? kron_workspace_bytes(t, B, N_max) : 0;
     if (small_dim(d)) {
         switch (op) {
             case REDO_OP_COMPOSE:
@@ -603,6 +654,33 @@ redo_status redo_chain_propagator(redo_table t, int32_t precision, const float* 
     if (obs_out && obs_width > 16) return fail(REDO_ERR_UNSUPPORTED, "observables with more than 16 entries per row");
     return large_chain(t, precision, u, n_steps, B, N_max, step_offset, reproject_every, X0, U_total, obs_cols,
                        obs_vals, obs_width, obs_out, workspace, workspace_bytes, hs);
+}
+
+redo_status redo_table_spins(redo_table t, int32_t* n_spins) {
+    g_last_error.clear();
+    if (!t || !n_spins) return fail(REDO_ERR_ARG, "table and n_spins must not be NULL");
+    *n_spins = t->kron_n;
+    return REDO_OK;
+}
+
+redo_status redo_kron_chain(redo_table t, int32_t quantised, const float* u, const int32_t* n_steps, int32_t B,
+                            int32_t N_max, int32_t step_offset, int32_t reproject_every, const float* X0,
+                            float* U_total, const int32_t* obs_cols, const float* obs_vals, int32_t obs_width,
+                            double* obs_out, void* workspace, size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    if (B < 1 || N_max < 1) return fail(REDO_ERR_ARG, "B and N_max must be >= 1");
+    if (!u || !U_total) return fail(REDO_ERR_ARG, "u and U_total must not be NULL");
+    if (quantised != 0 && quantised != 1) return fail(REDO_ERR_ARG, "quantised must be 0 or 1");
+    if (step_offset < 0 || reproject_every < 0) return fail(REDO_ERR_ARG, "step_offset, reproject_every must be >= 0");
+    if (obs_out && (!obs_cols || !obs_vals || obs_width < 1))
+        return fail(REDO_ERR_ARG, "obs_out needs obs_cols, obs_vals and obs_width >= 1");
+    if (t->kron_n == 0) return fail(REDO_ERR_UNSUPPORTED, "the generators are not sums of single-spin terms");
+    if (!kron_supported(t))
+        return fail(REDO_ERR_UNSUPPORTED, "the structure-aware chain needs a diagonal drift and d = 128 .. 4096");
+    if (obs_out && obs_width > 16) return fail(REDO_ERR_UNSUPPORTED, "observables with more than 16 entries per row");
+    return kron_chain(t, quantised, u, n_steps, B, N_max, step_offset, reproject_every, X0, U_total, obs_cols,
+                      obs_vals, obs_width, obs_out, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
 
 redo_status redo_unitary_fidelity(int32_t d, int32_t B, const float* U_target, const float* U, double* overlap,

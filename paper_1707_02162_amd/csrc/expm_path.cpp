@@ -28,7 +28,6 @@ namespace {
 
 constexpr int EXPM_CHUNK = 128;
 
-size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct PSPlan {
     int m = 0, r = 1, q = 0, s = 0;

@@ -18,23 +18,7 @@
 namespace redo {
 namespace {
 
-constexpr int REPROJECT_CHUNK = 256;   // instances re-projected per launch (scratch bound)
 constexpr int COMPOSE_CHUNK = 64;      // (instance, step) pairs composed per launch
-
-size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
-
-// bump allocator over the caller's workspace
-struct Carve {
-    char* base;
-    size_t used = 0;
-    explicit Carve(void* p) : base(static_cast<char*>(p)) {}
-    template <class T>
-    T* take(size_t count) {
-        T* p = reinterpret_cast<T*>(base ? base + used : nullptr);
-        used += align_up(sizeof(T) * count);
-        return p;
-    }
-};
 
 int slots_of(const redo_table_s* t) { return (t->desc.drift_is_diag ? 0 : 1) + t->desc.K * t->desc.digits; }
 

@@ -65,6 +65,30 @@ hipError_t fill_descs(GemmDesc* descs, int count, const float2* A, long long sA,
 size_t observable_partial_doubles(int d, int B);
 // T: scratch of `chunk` d x d matrices (instances processed `chunk` at a time)
 constexpr int OBS_CHUNK = 256;
+constexpr int REPROJECT_CHUNK = 256;   // instances re-projected per launch (scratch bound)
+
+inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// bump allocator over the caller's workspace (with base == nullptr it only measures)
+struct Carve {
+    char* base;
+    size_t used = 0;
+    explicit Carve(void* p) : base(static_cast<char*>(p)) {}
+    template <class T>
+    T* take(size_t count) {
+        T* p = reinterpret_cast<T*>(base ? base + used : nullptr);
+        used += align_up(sizeof(T) * count);
+        return p;
+    }
+};
+
+// structure-aware chain (spin-factorised control blocks), d = 2^n, 128 <= d <= 4096
+bool kron_supported(const redo_table_s* t);
+size_t kron_workspace_bytes(const redo_table_s* t, int B, int N);
+redo_status kron_chain(redo_table_s* t, int quantised, const float* u, const int* n_steps, int B, int N,
+                       int step_offset, int reproject_every, const float* X0, float* U_total, const int* obs_cols,
+                       const float* obs_vals, int obs_width, double* obs_out, void* workspace, size_t workspace_bytes,
+                       hipStream_t st);
 // GRAPE keeps every forward state and backward factor (no recomputation) when
 // that needs at most this much workspace and no checkpoint interval is given
 constexpr size_t GRAPE_FULL_STORAGE_BYTES = size_t(48) << 30;

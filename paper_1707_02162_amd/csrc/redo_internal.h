@@ -120,6 +120,10 @@ struct redo_table_s {
     int spat_w = 0;
     int* spat_cols = nullptr;
     double2* spat_vals = nullptr;
+    // d = 2^n and every generator a sum of single-spin terms, S_k = sum_q s_kq on spin q
+    // (bit q of the basis index): n, and the 2 x 2 terms [K][n][2][2] in FP64; else 0
+    int kron_n = 0;
+    double2* kron_s = nullptr;
 };
 
 constexpr int SPAT_WMAX = 16;

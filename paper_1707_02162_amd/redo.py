@@ -17,7 +17,7 @@ import torch
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libredo.so")
 
 PREC_F32, PREC_F32_3M, PREC_BF16X3 = 0, 1, 2
-OP_COMPOSE, OP_CHAIN, OP_GRAPE, OP_EXPM_CHAIN, OP_EXPM_GRAPE, OP_STATE_GRAPE = 0, 1, 2, 3, 4, 5
+OP_COMPOSE, OP_CHAIN, OP_GRAPE, OP_EXPM_CHAIN, OP_EXPM_GRAPE, OP_STATE_GRAPE, OP_KRON_CHAIN = 0, 1, 2, 3, 4, 5, 6
 STATUS = {0: "REDO_OK", 1: "REDO_ERR_ARG", 2: "REDO_ERR_ALLOC", 3: "REDO_ERR_HIP", 4: "REDO_ERR_NOT_HERMITIAN",
           5: "REDO_ERR_NONFINITE", 6: "REDO_ERR_UNSUPPORTED", 7: "REDO_ERR_WORKSPACE", 100: "REDO_WARN_CLAMPED"}
 
@@ -36,6 +36,8 @@ _SIG = {
     "redo_chain_propagator": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _P, _I, _P, _P,
                                    ctypes.c_size_t, _P]),
     "redo_unitary_fidelity": (_I, [_I, _I, _P, _P, _P, _P, _P]),
+    "redo_table_spins": (_I, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "redo_kron_chain": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P, _P, ctypes.c_size_t, _P]),
     "redo_grape_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _I, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "redo_expm_chain": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P, _P, ctypes.c_size_t, _P]),
     "redo_expm_grape_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _I, _P, _P, _P, _P, ctypes.c_size_t, _P]),
@@ -231,6 +233,35 @@ class RedoTable:
                                            reproject_every, _ptr(X0t), _ptr(U), _ptr(Xp), _ptr(cols), _ptr(vals),
                                            w, _ptr(obs), _ptr(ws), ws.numel(), _stream()))
         return U, Xp, obs
+
+    @property
+    def spins(self) -> int:
+        """n when d = 2^n and every generator is a sum of single-spin terms, else 0."""
+        n = ctypes.c_int32(0)
+        _check(lib().redo_table_spins(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def kron_chain(self, u, n_steps=None, quantised: bool = True, X0=None, reproject_every: int = 0,
+                   step_offset: int = 0, observable=None, out: Optional[torch.Tensor] = None):
+        """Structure-aware chain (spin-factorised control blocks; needs self.spins > 0).
+        quantised: REDO codes (True) or the amplitudes as given.  Returns (U_total, obs or None)."""
+        ut = self._u(u)
+        B, N = ut.shape[:2]
+        ns = None if n_steps is None else _dev(n_steps, torch.int32, self.device)
+        X0t = None if X0 is None else _dev(X0, torch.complex64, self.device)
+        U = out if out is not None else torch.empty((B, self.d, self.d), dtype=torch.complex64, device=self.device)
+        cols = vals = obs = None
+        w = 0
+        if observable is not None:
+            cols = _dev(observable[0], torch.int32, self.device)
+            vals = _dev(observable[1], torch.complex64, self.device)
+            w = cols.shape[1]
+            obs = torch.empty((B, N), dtype=torch.float64, device=self.device)
+        ws = self.workspace(OP_KRON_CHAIN, B, N)
+        _check(lib().redo_kron_chain(self._h, 1 if quantised else 0, _ptr(ut), _ptr(ns), B, N, step_offset,
+                                     reproject_every, _ptr(X0t), _ptr(U), _ptr(cols), _ptr(vals), w, _ptr(obs),
+                                     _ptr(ws), ws.numel(), _stream()))
+        return U, obs
 
     def grape(self, u, U_target, n_steps=None, checkpoint_every: int = 0, precision: int = PREC_F32):
         """Returns (fidelity float64 [B], overlap complex128 [B], grad float32 like u)."""
