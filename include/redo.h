@@ -372,13 +372,16 @@ redo_status redo_to_bf16(int64_t n, const float* in, uint16_t* out, void* stream
 
 /*
  * Launch timing (diagnostics, not part of the method).  While enabled, every
- * batched complex-GEMM launch of the large-d path is bracketed by HIP events
- * recorded on the stream it runs on.  redo_profile_read waits for those
- * events and returns the summed duration (ms) and the number of launches
- * since the last reset.  Process-wide; may be called from any thread.
+ * batched complex-GEMM launch of the large-d path (kind 0) and every step
+ * launch of redo_kron_chain (kind 1) is bracketed by HIP events recorded on
+ * the stream it runs on.  redo_profile_read_kind waits for those events and
+ * returns the summed duration (ms) and the number of launches of one kind
+ * since that kind's last reset; redo_profile_read is kind 0.  Process-wide;
+ * may be called from any thread.
  */
 redo_status redo_profile_enable(int32_t enable);
 redo_status redo_profile_read(double* gemm_ms, int64_t* gemm_launches, int32_t reset);
+redo_status redo_profile_read_kind(int32_t kind, double* ms, int64_t* launches, int32_t reset);
 
 const char* redo_status_string(redo_status status);
 const char* redo_last_error(void);

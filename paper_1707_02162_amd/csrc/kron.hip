@@ -14,8 +14,9 @@
 namespace redo {
 namespace {
 
-constexpr int KRON_NT = 256;
-constexpr int KRON_VALS = 32;   // values per thread: 5 bits of the row index per round
+constexpr int KRON_NT = 512;
+constexpr int KRON_VB = 4;                  // row bits held in registers per round
+constexpr int KRON_VALS = 1 << KRON_VB;     // values per thread
 
 // per instance and step: the spins' 2 x 2 factors in FP64 (rounded once to FP32) and
 // the two diagonal row scalings
@@ -115,20 +116,21 @@ __device__ inline long long kron_xcd(long long bid, long long nb) {
     return (nb % 8 == 0) ? (bid % 8) * (nb / 8) + bid / 8 : bid;
 }
 
-// LDS row swizzle: the low 5 row bits XOR the next 5 (a bijection), so that the rows
-// one instruction touches in either round fall into different banks
-__device__ inline int kron_lds(int a, int c, int sw) { return (a ^ ((a >> 5) & 31)) * sw + c; }
+// LDS row swizzle: the low KRON_VB row bits XOR the next KRON_VB (a bijection), so that
+// the rows one instruction touches in any round fall into different banks
+__device__ inline int kron_lds(int a, int c, int sw) { return (a ^ ((a >> KRON_VB) & (KRON_VALS - 1))) * sw + c; }
 
 template <int D>
 struct KronShape {
     static constexpr int n = D == 128 ? 7 : D == 256 ? 8 : D == 512 ? 9 : D == 1024 ? 10 : D == 2048 ? 11 : 12;
     static constexpr int SW = KRON_NT * KRON_VALS / D;   // columns per workgroup (8192 values in LDS)
-    static constexpr int rounds = (n + 4) / 5;
+    static constexpr int rounds = (n + KRON_VB - 1) / KRON_VB;
+    static_assert(rounds >= 2 && rounds <= 3, "two or three register rounds");
 };
 
 // row of register value i and thread part `rest` in a round whose register bits start at lo
 __device__ inline int kron_row(int rest, int i, int lo) {
-    return (rest & ((1 << lo) - 1)) | (i << lo) | ((rest >> lo) << (lo + 5));
+    return (rest & ((1 << lo) - 1)) | (i << lo) | ((rest >> lo) << (lo + KRON_VB));
 }
 
 template <int J>
@@ -149,12 +151,12 @@ __device__ inline void kron_gate_bit(float2 (&v)[KRON_VALS], const float2* gq) {
     }
 }
 
-// register bits of round R start at row bit lo(R); round R applies spins 5 R .. 5 R + 4
+// register bits of round R start at row bit lo(R); round R applies spins VB R .. VB R + VB - 1
 template <int D, int R>
 struct KronRound {
-    static constexpr int n = KronShape<D>::n;
-    static constexpr int lo = 5 * R < n - 5 ? 5 * R : n - 5;
-    static constexpr int q0 = 5 * R, q1 = 5 * R + 5 < n ? 5 * R + 5 : n;
+    static constexpr int n = KronShape<D>::n, VB = KRON_VB;
+    static constexpr int lo = VB * R < n - VB ? VB * R : n - VB;
+    static constexpr int q0 = VB * R, q1 = VB * R + VB < n ? VB * R + VB : n;
 };
 
 template <int D, int R, int Q>
@@ -165,11 +167,11 @@ __device__ inline void kron_round_gate(float2 (&v)[KRON_VALS], const float2* gl)
 
 template <int D, int R>
 __device__ inline void kron_round_gates(float2 (&v)[KRON_VALS], const float2* gl) {
+    static_assert(KRON_VB == 4, "one call per register bit");
     kron_round_gate<D, R, 0>(v, gl);
     kron_round_gate<D, R, 1>(v, gl);
     kron_round_gate<D, R, 2>(v, gl);
     kron_round_gate<D, R, 3>(v, gl);
-    kron_round_gate<D, R, 4>(v, gl);
 }
 
 // hand the strip from the register layout of round R - 1 to that of round R through LDS
@@ -185,12 +187,13 @@ __device__ inline void kron_exchange(float2 (&v)[KRON_VALS], float2* buf, int re
 }
 
 // One step for every instance: workgroup = (instance, strip of SW columns).  Round 0
-// reads the strip from HBM with register bits = row bits 0..4, applies the pre
-// scaling and spins 0..4, and parks the strip in LDS; round r takes row bits
-// lo_r .. lo_r + 4 (lo_r = min(5 r, n - 5)) and applies spins 5 r .. 5 r + 4; the
-// last round applies the post scaling and writes the strip back in place.
+// reads the strip from HBM with register bits = row bits 0..VB-1, applies the pre
+// scaling and spins 0..VB-1, and parks the strip in LDS; round r takes row bits
+// lo_r .. lo_r + VB - 1 (lo_r = min(VB r, n - VB)) and applies spins VB r .. VB r + VB - 1;
+// the last round applies the post scaling and writes the strip back in place.
+// 64 KiB of LDS per workgroup: two workgroups (four waves per SIMD) per CU.
 template <int D>
-__global__ __launch_bounds__(KRON_NT, 2) void kron_step_kernel(float2* X0, float2* X1, const int* loc,
+__global__ __launch_bounds__(KRON_NT, 4) void kron_step_kernel(float2* X0, float2* X1, const int* loc,
                                                                long long xstride, const float2* __restrict__ gates,
                                                                const float2* __restrict__ pre,
                                                                const float2* __restrict__ post, const int* n_steps,
@@ -233,8 +236,12 @@ template <int D>
 hipError_t launch_kron_step(int B, float2* X0, float2* X1, const int* loc, long long xstride, const float2* gates,
                             const float2* pre, const float2* post, const int* n_steps, int step, hipStream_t st) {
     constexpr int NSTRIP = D / KronShape<D>::SW;
+    void* tok = nullptr;
+    const bool prof = profiling_on();
+    if (prof) profile_begin(st, &tok, 1);
     hipLaunchKernelGGL(kron_step_kernel<D>, dim3((unsigned)((long long)B * NSTRIP)), dim3(KRON_NT), 0, st, X0, X1, loc,
                        xstride, gates, pre, post, n_steps, step);
+    if (prof) profile_end(st, tok);
     return hipGetLastError();
 }
 

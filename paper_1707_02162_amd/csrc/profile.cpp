@@ -1,7 +1,8 @@
-// Launch timing of the batched GEMM kernels: when enabled, every product
-// launch is bracketed by HIP events recorded on the launch's own stream, so
-// a benchmark can divide the algorithmic work of a launch by its measured
-// duration.  Diagnostics only: no effect on results.
+// Launch timing of the batched GEMM kernels (kind 0) and of the structure-aware
+// step kernel (kind 1): when enabled, every such launch is bracketed by HIP
+// events recorded on the launch's own stream, so a benchmark can divide the
+// algorithmic work of a launch by its measured duration.  Diagnostics only: no
+// effect on results.
 #include <mutex>
 #include <vector>
 
@@ -12,10 +13,14 @@ namespace {
 struct Prof {
     std::mutex mu;
     bool on = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> open;
+    struct Open {
+        hipEvent_t a, b;
+        int kind;
+    };
+    std::vector<Open> open;
     std::vector<hipEvent_t> pool;
-    double ms = 0.0;
-    long long launches = 0;
+    double ms[PROFILE_KINDS] = {};
+    long long launches[PROFILE_KINDS] = {};
 };
 Prof& prof() {
     static Prof p;
@@ -35,7 +40,7 @@ hipEvent_t take_event(Prof& p) {
 
 bool profiling_on() { return prof().on; }
 
-void profile_begin(hipStream_t st, void** token) {
+void profile_begin(hipStream_t st, void** token, int kind) {
     Prof& p = prof();
     std::lock_guard<std::mutex> g(p.mu);
     hipEvent_t a = take_event(p), b = take_event(p);
@@ -44,7 +49,7 @@ void profile_begin(hipStream_t st, void** token) {
         return;
     }
     (void)hipEventRecord(a, st);
-    p.open.emplace_back(a, b);
+    p.open.push_back({a, b, kind});
     *token = reinterpret_cast<void*>(p.open.size());
 }
 
@@ -53,7 +58,7 @@ void profile_end(hipStream_t st, void* token) {
     Prof& p = prof();
     std::lock_guard<std::mutex> g(p.mu);
     const size_t i = reinterpret_cast<size_t>(token) - 1;
-    if (i < p.open.size()) (void)hipEventRecord(p.open[i].second, st);
+    if (i < p.open.size()) (void)hipEventRecord(p.open[i].b, st);
 }
 
 }  // namespace redo
@@ -67,25 +72,30 @@ redo_status redo_profile_enable(int32_t enable) {
     return REDO_OK;
 }
 
-redo_status redo_profile_read(double* gemm_ms, int64_t* gemm_launches, int32_t reset) {
+redo_status redo_profile_read_kind(int32_t kind, double* ms, int64_t* launches, int32_t reset) {
+    if (kind < 0 || kind >= redo::PROFILE_KINDS) return redo::fail(REDO_ERR_ARG, "unknown launch kind");
     redo::Prof& p = redo::prof();
     std::lock_guard<std::mutex> g(p.mu);
     for (auto& ev : p.open) {
-        if (hipEventSynchronize(ev.second) != hipSuccess) return redo::fail(REDO_ERR_HIP, "event synchronize failed");
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) p.ms += ms;
-        p.launches += 1;
-        p.pool.push_back(ev.first);
-        p.pool.push_back(ev.second);
+        if (hipEventSynchronize(ev.b) != hipSuccess) return redo::fail(REDO_ERR_HIP, "event synchronize failed");
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev.a, ev.b) == hipSuccess) p.ms[ev.kind] += t;
+        p.launches[ev.kind] += 1;
+        p.pool.push_back(ev.a);
+        p.pool.push_back(ev.b);
     }
     p.open.clear();
-    if (gemm_ms) *gemm_ms = p.ms;
-    if (gemm_launches) *gemm_launches = p.launches;
+    if (ms) *ms = p.ms[kind];
+    if (launches) *launches = p.launches[kind];
     if (reset) {
-        p.ms = 0.0;
-        p.launches = 0;
+        p.ms[kind] = 0.0;
+        p.launches[kind] = 0;
     }
     return REDO_OK;
+}
+
+redo_status redo_profile_read(double* gemm_ms, int64_t* gemm_launches, int32_t reset) {
+    return redo_profile_read_kind(0, gemm_ms, gemm_launches, reset);
 }
 
 }  // extern "C"

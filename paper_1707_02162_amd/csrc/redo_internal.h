@@ -226,7 +226,8 @@ hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision,
 
 // launch timing (profile.cpp)
 bool profiling_on();
-void profile_begin(hipStream_t st, void** token);
+constexpr int PROFILE_KINDS = 2;   // 0: batched GEMM, 1: structure-aware step
+void profile_begin(hipStream_t st, void** token, int kind = 0);
 void profile_end(hipStream_t st, void* token);
 
 }  // namespace redo

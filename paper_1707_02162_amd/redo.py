@@ -45,6 +45,7 @@ _SIG = {
     "redo_get_device_status": (_I, [_P, _P, ctypes.POINTER(ctypes.c_int64)]),
     "redo_profile_enable": (_I, [_I]),
     "redo_profile_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _I]),
+    "redo_profile_read_kind": (_I, [_I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _I]),
     "redo_mlp_target_features": (_I, [_I, _I, _P, _P, _P]),
     "redo_mlp_forward": (_I, [_P, _I, _P, _P, _P]),
     "redo_mlp_loss_grad": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P]),
@@ -340,11 +341,12 @@ def profile_enable(on: bool = True) -> None:
     _check(lib().redo_profile_enable(1 if on else 0))
 
 
-def profile_read(reset: bool = True):
-    """(summed GEMM-launch milliseconds, launch count) since the last reset."""
+def profile_read(reset: bool = True, kind: int = 0):
+    """(summed launch milliseconds, launch count) since the last reset, for the
+    batched GEMM (kind 0) or the structure-aware step kernel (kind 1)."""
     ms = ctypes.c_double()
     n = ctypes.c_int64()
-    _check(lib().redo_profile_read(ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
+    _check(lib().redo_profile_read_kind(kind, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
     return ms.value, n.value
 
 
