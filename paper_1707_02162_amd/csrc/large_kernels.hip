@@ -257,17 +257,37 @@ __device__ inline long long xcd_local(long long bid, long long nb) {
     return (nb % 8 == 0) ? (bid % 8) * (nb / 8) + bid / 8 : bid;
 }
 
+// the row list of row a from the packed layout [d][WP] (padded entries: column a,
+// value 0), as WP/4 + WP/2 16-byte loads
 template <int WP>
-__device__ inline void obs_list(const int* __restrict__ cols, const float2* __restrict__ vals, int w, int a,
+__device__ inline void obs_list(const int* __restrict__ cols, const float2* __restrict__ vals, int a,
                                 int (&cc)[WP], float2 (&cv)[WP]) {
+    const int4* c4 = reinterpret_cast<const int4*>(cols + (long long)a * WP);
+    const float4* v4 = reinterpret_cast<const float4*>(vals + (long long)a * WP);
 #pragma unroll
-    for (int t = 0; t < WP; ++t) {
-        const int tt = t < w ? t : w - 1;     // always a valid entry of row a
-        const int c = cols[(long long)a * w + tt];
-        const float2 v = vals[(long long)a * w + tt];
-        cc[t] = t < w ? c : a;
-        cv[t] = t < w ? v : make_float2(0.f, 0.f);
+    for (int q = 0; q < WP / 4; ++q) {
+        const int4 x = c4[q];
+        cc[4 * q] = x.x;
+        cc[4 * q + 1] = x.y;
+        cc[4 * q + 2] = x.z;
+        cc[4 * q + 3] = x.w;
     }
+#pragma unroll
+    for (int q = 0; q < WP / 2; ++q) {
+        const float4 y = v4[q];
+        cv[2 * q] = make_float2(y.x, y.y);
+        cv[2 * q + 1] = make_float2(y.z, y.w);
+    }
+}
+
+// caller's row lists [d][w] -> packed [d][WP]
+__global__ void obs_pack_kernel(int d, int w, int wp, const int* __restrict__ cols, const float2* __restrict__ vals,
+                                int* __restrict__ pc, float2* __restrict__ pv) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= d * wp) return;
+    const int a = e / wp, t = e % wp;
+    pc[e] = t < w ? cols[(long long)a * w + t] : a;
+    pv[e] = t < w ? vals[(long long)a * w + t] : make_float2(0.f, 0.f);
 }
 
 // Pass 1.  SW columns per strip; CPL complex entries per lane, LPR lanes per
@@ -294,8 +314,8 @@ __global__ __launch_bounds__(NT, NT / 128) void observable_mx_kernel(int d, int 
     int a = tid / LPR;
     int cc0[WP], cc1[WP];
     float2 cv0[WP], cv1[WP];
-    obs_list<WP>(cols, vals, w, min(a, d - 1), cc0, cv0);
-    obs_list<WP>(cols, vals, w, min(a + RPP, d - 1), cc1, cv1);
+    obs_list<WP>(cols, vals, min(a, d - 1), cc0, cv0);
+    obs_list<WP>(cols, vals, min(a + RPP, d - 1), cc1, cv1);
     const int n = d * SW;
     if (n % (NT * 16) == 0) {
         for (int base = 0; base < n; base += NT * 16) {
@@ -317,7 +337,7 @@ __global__ __launch_bounds__(NT, NT / 128) void observable_mx_kernel(int d, int 
         int cc2[WP];
         float2 cv2[WP];
         const int a2 = a + 2 * RPP;
-        if (a2 < d) obs_list<WP>(cols, vals, w, a2, cc2, cv2);
+        if (a2 < d) obs_list<WP>(cols, vals, a2, cc2, cv2);
         float2 acc[CPL];
 #pragma unroll
         for (int u = 0; u < CPL; ++u) acc[u] = make_float2(0.f, 0.f);
@@ -374,7 +394,7 @@ __global__ __launch_bounds__(NT, NT / 128) void observable_dot_kernel(int d, int
     float2 cv[WP], mx[R];
     if (active) {
         const int c_ = min(c, d - 1);
-        obs_list<WP>(cols, vals, w, c_, cc, cv);
+        obs_list<WP>(cols, vals, c_, cc, cv);
 #pragma unroll
         for (int r = 0; r < R; ++r) mx[r] = Tb[(long long)r * d + c_];
         // rows rb R .. rb R + R - 1, R 16-byte loads in flight per lane and pass
@@ -398,7 +418,7 @@ __global__ __launch_bounds__(NT, NT / 128) void observable_dot_kernel(int d, int
             int nc[WP];
             float2 nv[WP], nm[R];
             if (cn < d) {
-                obs_list<WP>(cols, vals, w, cn, nc, nv);
+                obs_list<WP>(cols, vals, cn, nc, nv);
 #pragma unroll
                 for (int r = 0; r < R; ++r) nm[r] = Tb[(long long)r * d + cn];
             }
@@ -879,7 +899,10 @@ hipError_t grape_pair_descs(GemmDesc* descs, int N, int B, const float2* U, long
     return hipGetLastError();
 }
 
-size_t observable_partial_doubles(int d, int B) { return (size_t)B * (d / obs_rows(d)); }
+// partial sums of every instance, then the packed row lists ([d][OBS_WMAX] ints and complex)
+size_t observable_partial_doubles(int d, int B) {
+    return (size_t)B * (d / obs_rows(d)) + (size_t)d * OBS_WMAX * 3 / 2 + 2;
+}
 
 template <int SW, int WP, int NT>
 static hipError_t launch_mx(int d, int cnt, int b0, const float2* X0, const float2* X1, const int* loc,
@@ -936,14 +959,21 @@ hipError_t observable(int d, int B, const float2* X0, const float2* X1, const in
                       double* out, long long out_stride, float2* T, int chunk, hipStream_t st) {
     if (w < 1 || w > OBS_WMAX) return hipErrorInvalidValue;
     const int wp = (w + 3) / 4 * 4;
+    // packed lists after the partial sums, 16-byte aligned
+    const size_t np = (size_t)B * (d / obs_rows(d));
+    int* pc = reinterpret_cast<int*>(partial + np + (np & 1));
+    float2* pv = reinterpret_cast<float2*>(pc + (size_t)d * OBS_WMAX);
+    hipLaunchKernelGGL(obs_pack_kernel, dim3((d * wp + 255) / 256), dim3(256), 0, st, d, w, wp, cols, vals, pc, pv);
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
     for (int b0 = 0; b0 < B; b0 += chunk) {
         const int cnt = std::min(chunk, B - b0);
         hipError_t e;
         switch (wp) {
-            case 4: e = obs_chunk<4>(d, cnt, b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T, partial, st); break;
-            case 8: e = obs_chunk<8>(d, cnt, b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T, partial, st); break;
-            case 12: e = obs_chunk<12>(d, cnt, b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T, partial, st); break;
-            default: e = obs_chunk<16>(d, cnt, b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T, partial, st);
+            case 4: e = obs_chunk<4>(d, cnt, b0, X0, X1, loc, xstride, pc, pv, wp, n_steps, step, T, partial, st); break;
+            case 8: e = obs_chunk<8>(d, cnt, b0, X0, X1, loc, xstride, pc, pv, wp, n_steps, step, T, partial, st); break;
+            case 12: e = obs_chunk<12>(d, cnt, b0, X0, X1, loc, xstride, pc, pv, wp, n_steps, step, T, partial, st); break;
+            default: e = obs_chunk<16>(d, cnt, b0, X0, X1, loc, xstride, pc, pv, wp, n_steps, step, T, partial, st);
         }
         if (e != hipSuccess) return e;
     }
