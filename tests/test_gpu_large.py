@@ -415,3 +415,21 @@ def test_strang_signed_grape_d128_vs_oracle():
     g = grad[0].cpu().numpy()
     assert np.linalg.norm(g - gro) <= GRAD_TOL * np.linalg.norm(gro)
 
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_chain_large_batch_tiles_d128_vs_oracle(prec):
+    """Enough instances for the 128 x 64 tiles (4M and 3M) with a ragged length
+    and the observable; sampled instances against the oracle."""
+    B, N = 300, 12
+    lens = np.full(B, N, np.int32)
+    lens[7] = 5
+    p = W.ising_freezing(n=7, B=B, N=N)
+    t = R().RedoTable.from_problem(p)
+    cols, vals = W.observable_ell(p.M)
+    U, _, m = t.chain(torch.tensor(p.u).cuda(), n_steps=torch.tensor(lens), observable=(cols, vals), precision=prec)
+    U, m = U.cpu().numpy(), m.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in (0, 7, B - 1):
+        mo, X = O.magnetisation_series(O.compose_all_redo(p, tab, b, n_steps=int(lens[b])), p.M)
+        assert nfrob(U[b], X) < FROB_TOL
+        assert np.abs(m[b, :lens[b]] - mo).max() < 1e-5
