@@ -208,14 +208,16 @@ def test_ising_d1024_special_cases_full_dimension():
     assert np.abs(m2.cpu().numpy()[0] - want).max() < 1e-4
 
 
-def test_ising_d1024_full_batch_sampled_vs_oracle():
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ising_d1024_full_batch_sampled_vs_oracle(prec):
     """The benchmark's launch shape (4096 realisations x d = 1024, one call
-    per step window) on its first steps; sampled realisations against the oracle."""
+    per step window) on its first steps, four- and three-product GEMMs;
+    sampled realisations against the oracle."""
     n_steps = 3
     p = W.ising_freezing(n=10, B=4096, N=n_steps)
     t = R().RedoTable.from_problem(p)
     cols, vals = W.observable_ell(p.M)
-    U, _, m = t.chain(torch.tensor(p.u).cuda(), observable=(cols, vals))
+    U, _, m = t.chain(torch.tensor(p.u).cuda(), observable=(cols, vals), precision=prec)
     torch.cuda.synchronize()
     tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
     for b in (0, 4095):
