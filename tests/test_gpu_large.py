@@ -418,10 +418,10 @@ def test_strang_signed_grape_d128_vs_oracle():
     assert np.linalg.norm(g - gro) <= GRAD_TOL * np.linalg.norm(gro)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_chain_large_batch_tiles_d128_vs_oracle(prec):
-    """Enough instances for the 128 x 64 tiles (4M and 3M) with a ragged length
-    and the observable; sampled instances against the oracle."""
+    """Enough instances for the 128 x 64 tiles (4M, 3M and split BF16) with a
+    ragged length and the observable; sampled instances against the oracle."""
     B, N = 300, 12
     lens = np.full(B, N, np.int32)
     lens[7] = 5
@@ -433,5 +433,6 @@ def test_chain_large_batch_tiles_d128_vs_oracle(prec):
     tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
     for b in (0, 7, B - 1):
         mo, X = O.magnetisation_series(O.compose_all_redo(p, tab, b, n_steps=int(lens[b])), p.M)
-        assert nfrob(U[b], X) < FROB_TOL
-        assert np.abs(m[b, :lens[b]] - mo).max() < 1e-5
+        tol = BF_TOL if prec == 2 else FROB_TOL
+        assert nfrob(U[b], X) < tol
+        assert np.abs(m[b, :lens[b]] - mo).max() < (BF_TOL if prec == 2 else 1e-5)
