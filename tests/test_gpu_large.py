@@ -117,14 +117,16 @@ def test_chunked_chain_equals_one_call_d128():
     assert torch.equal(U_all, U_b)
 
 
-def test_grape_d128_phased_vs_oracle():
+@pytest.mark.parametrize("prec", [0, 1])
+def test_grape_d128_phased_vs_oracle(prec):
     """Default schedule at d = 128 (every state kept, traces from the sparse
-    pattern of the collective generators); every fifth step has zero
-    amplitude, so the q = 0 (Cartesian) derivative is exercised too."""
+    pattern of the collective generators), four- and three-product GEMMs;
+    every fifth step has zero amplitude, so the q = 0 (Cartesian) derivative
+    is exercised too."""
     p = W.nmr_chain(7, 2, 30, 2e-6, 32, 2, 205)
     p.u[:, ::5] = 0.0
     t = R().RedoTable.from_problem(p)
-    F, ov, grad = t.grape(torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda())
+    F, ov, grad = t.grape(torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda(), precision=prec)
     F, ov, grad = F.cpu().numpy(), ov.cpu().numpy(), grad.cpu().numpy()
     tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
     for b in range(p.B):
