@@ -352,14 +352,6 @@ __global__ void state_final_kernel(int d, int K, int phased, const float2* psif,
     }
 }
 
-__global__ void copy_vectors_kernel(int d, int B, const float2* src, long long ss, float2* dst, long long ds) {
-    const int b = blockIdx.y;
-    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < d; a += gridDim.x * blockDim.x)
-        dst[(long long)b * ds + a] = src[(long long)b * ss + a];
-}
-
-size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
-
 struct StateWS {
     int* codes;
     double* phi;

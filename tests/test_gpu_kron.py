@@ -147,3 +147,43 @@ def test_kron_ising_d1024_full_batch_sampled_vs_oracle():
         mo, X = O.magnetisation_series(O.compose_all_redo(p, tab, b), p.M)
         assert nfrob(U[b].cpu().numpy(), X) < FROB_TOL
         assert np.abs(m[b].cpu().numpy() - mo).max() < OBS_TOL
+
+
+def test_kron_argument_errors_and_unsupported_cases():
+    """Errors are reported on the host, before anything is launched."""
+    redo = R()
+    p = W.ising_freezing(n=7, B=2, N=3)
+    t = redo.RedoTable.from_problem(p)
+    u = torch.tensor(p.u).cuda()
+    U = torch.empty((2, p.d, p.d), dtype=torch.complex64, device="cuda")
+    ws = t.workspace(redo.OP_KRON_CHAIN, 2, 3)
+    lib = redo.lib()
+    P = redo._ptr
+    # quantised must be 0 or 1; B and N at least 1; a workspace that is too small
+    assert lib.redo_kron_chain(t._h, 2, P(u), None, 2, 3, 0, 0, None, P(U), None, None, 0, None, P(ws), ws.numel(),
+                               None) == 1
+    assert lib.redo_kron_chain(t._h, 1, P(u), None, 0, 3, 0, 0, None, P(U), None, None, 0, None, P(ws), ws.numel(),
+                               None) == 1
+    assert lib.redo_kron_chain(t._h, 1, P(u), None, 2, 3, 0, 0, None, P(U), None, None, 0, None, P(ws), 16,
+                               None) == 7
+    # observables with more than 16 entries per row
+    cols = torch.zeros((p.d, 17), dtype=torch.int32, device="cuda")
+    vals = torch.zeros((p.d, 17), dtype=torch.complex64, device="cuda")
+    obs = torch.empty((2, 3), dtype=torch.float64, device="cuda")
+    assert lib.redo_kron_chain(t._h, 1, P(u), None, 2, 3, 0, 0, None, P(U), P(cols), P(vals), 17, P(obs), P(ws),
+                               ws.numel(), None) == 6
+    # d = 64: single-spin structure is recognised, the chain needs d >= 128
+    q = W.ising_freezing(n=6, B=1, N=2)
+    tq = redo.RedoTable.from_problem(q)
+    assert tq.spins == 6
+    with pytest.raises(redo.RedoError, match="d = 128"):
+        tq.kron_chain(torch.tensor(q.u).cuda())
+    # a dense drift is refused
+    r = W.ising_freezing(n=7, B=1, N=2)
+    r.H0 = np.stack([np.diag(r.H0[0]).astype(np.complex128)])
+    r.drift_is_diag = False
+    tr = redo.RedoTable.from_problem(r)
+    assert tr.spins == 7
+    with pytest.raises(redo.RedoError, match="diagonal drift"):
+        tr.kron_chain(torch.tensor(r.u).cuda())
+    torch.cuda.synchronize()
