@@ -367,6 +367,83 @@ __global__ __launch_bounds__(NT, NT / 128) void observable_mx_kernel(int d, int 
     }
 }
 
+// Pass 1 for 8-column strips: LPR lanes per row (1 when the strip has at least NT
+// rows), each lane CPL = 8 / LPR columns, so one load instruction of a wave fetches
+// the lists of 64 / LPR rows.  The strip's 16-byte chunks (two columns) are swizzled
+// by row, chunk c of row a at position c ^ ((a >> 2) & 3), so that the chunks 16
+// lanes of 16 neighbouring rows read fall into distinct banks.
+__device__ inline int mx8_off(int a, int col) { return a * 8 + ((((col >> 1) ^ (a >> 2)) & 3) << 1) + (col & 1); }
+
+template <int WP, int NT, int LPR>
+__global__ __launch_bounds__(NT, NT / 128) void observable_mx8_kernel(int d, int b0, const float2* __restrict__ X0,
+                                                                      const float2* __restrict__ X1, const int* loc,
+                                                                      long long xstride, const int* __restrict__ cols,
+                                                                      const float2* __restrict__ vals,
+                                                                      const int* n_steps, int step, float2* T) {
+    constexpr int SW = 8, CPL = SW / LPR, NCH = CPL / 2, RPP = NT / LPR;
+    extern __shared__ float2 strip[];   // [d][8], 16-byte chunks swizzled (mx8_off)
+    const int nstrip = d / SW;
+    const long long bid = xcd_local(blockIdx.x, gridDim.x);
+    const int i = (int)(bid / nstrip), sidx = (int)(bid % nstrip);
+    const int b = b0 + i;
+    if (n_steps && step >= n_steps[b]) return;      // uniform over the workgroup
+    const float2* Xb = ((loc && loc[b]) ? X1 : X0) + (long long)b * xstride;
+    const int c0 = sidx * SW;
+    const int tid = threadIdx.x;
+    const int n = d * SW;
+    for (int base = 0; base < n; base += NT * 16) {
+        float2 r[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = min(base + u * NT + tid, n - 1);
+            r[u] = Xb[(long long)(e / SW) * d + c0 + e % SW];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = base + u * NT + tid;
+            if (e < n) strip[mx8_off(e / SW, e % SW)] = r[u];
+        }
+    }
+    __syncthreads();
+    const float4* strip4 = reinterpret_cast<const float4*>(strip);
+    const int lr = tid % LPR;
+    int a = tid / LPR;
+    float2* Tb = T + (long long)i * d * d;
+    int cc[WP];
+    float2 cv[WP];
+    obs_list<WP>(cols, vals, min(a, d - 1), cc, cv);
+    for (; a < d; a += RPP) {
+        int nc[WP];
+        float2 nv[WP];
+        const int an = a + RPP;
+        if (an < d) obs_list<WP>(cols, vals, an, nc, nv);
+        float2 acc[CPL];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) acc[u] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int t = 0; t < WP; ++t) {
+#pragma unroll
+            for (int j = 0; j < NCH; ++j) {
+                const int ch = lr * NCH + j;
+                const float4 x = strip4[cc[t] * 4 + ((ch ^ (cc[t] >> 2)) & 3)];
+                cfma(acc[2 * j], cv[t], make_float2(x.x, x.y));
+                cfma(acc[2 * j + 1], cv[t], make_float2(x.z, x.w));
+            }
+        }
+        float2* dst = Tb + (long long)a * d + c0 + lr * CPL;
+#pragma unroll
+        for (int j = 0; j < NCH; ++j)
+            *reinterpret_cast<float4*>(dst + 2 * j) = make_float4(acc[2 * j].x, acc[2 * j].y, acc[2 * j + 1].x, acc[2 * j + 1].y);
+        if (an < d) {
+#pragma unroll
+            for (int t = 0; t < WP; ++t) {
+                cc[t] = nc[t];
+                cv[t] = nv[t];
+            }
+        }
+    }
+}
+
 // Pass 2.  R rows of X per workgroup, held column-major in LDS ([d][R]: the R
 // entries of a column are one contiguous run, read as R/2 16-byte words);
 // each lane takes columns c, c + NT, ...; the R entries of T and the row list
@@ -917,6 +994,19 @@ static hipError_t launch_mx(int d, int cnt, int b0, const float2* X0, const floa
     return hipGetLastError();
 }
 
+template <int WP, int NT, int LPR>
+static hipError_t launch_mx8(int d, int cnt, int b0, const float2* X0, const float2* X1, const int* loc,
+                             long long xstride, const int* cols, const float2* vals, int w, const int* n_steps,
+                             int step, float2* T, hipStream_t st) {
+    const void* k = (const void*)observable_mx8_kernel<WP, NT, LPR>;
+    const size_t lds = sizeof(float2) * (size_t)8 * d;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((observable_mx8_kernel<WP, NT, LPR>), dim3((unsigned)((long long)(d / 8) * cnt)), dim3(NT), lds,
+                       st, d, b0, X0, X1, loc, xstride, cols, vals, n_steps, step, T);
+    return hipGetLastError();
+}
+
 template <int R, int WP, int NT>
 static hipError_t launch_dot(int d, int cnt, int b0, const float2* X0, const float2* X1, const int* loc,
                              long long xstride, const int* cols, const float2* vals, int w, const int* n_steps,
@@ -939,7 +1029,9 @@ static hipError_t obs_chunk(int d, int cnt, int b0, const float2* X0, const floa
 #define MXA d, cnt, b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T, st
 #define DTA d, cnt, b0, X0, X1, loc, xstride, cols, vals, w, n_steps, step, T, partial, st
     switch (SW) {
-        case 8: e = launch_mx<8, WP, 256>(MXA); break;
+        case 8:
+            e = d >= 256 ? launch_mx8<WP, 256, 1>(MXA) : d >= 128 ? launch_mx8<WP, 256, 2>(MXA) : launch_mx8<WP, 256, 4>(MXA);
+            break;
         case 4: e = launch_mx<4, WP, 256>(MXA); break;
         case 2: e = launch_mx<2, WP, 256>(MXA); break;
         default: e = launch_mx<1, WP, 256>(MXA);
