@@ -196,6 +196,66 @@ def bench_grape(args, redo, W, torch):
     return res
 
 
+def bench_next(args, redo, W, torch):
+    """The NEXT rows measured on d = 1024 workloads: the Strang splitting on the
+    headline workload (4096 realisations, observable every step, three-product
+    GEMMs) and state-transfer GRAPE on the GRAPE workload (target: the state the
+    Haar target unitary makes of |0>)."""
+    out = {}
+    B, K, Wm = args.realisations, args.steps, args.warmup
+    p = W.ising_freezing(n=10, B=B, N=Wm + K)
+    p.splitting = "strang"
+    table = redo.RedoTable.from_problem(p)
+    if args.cache:
+        table.cache_levels()
+    u = torch.tensor(p.u, device="cuda")
+    cols, vals = W.observable_ell(p.M)
+    obs = (torch.tensor(cols, device="cuda"), torch.tensor(vals, device="cuda", dtype=torch.complex64))
+    U = torch.empty((B, p.d, p.d), dtype=torch.complex64, device="cuda")
+    def advance(n0, n1):
+        table.chain(u[:, n0:n1].contiguous(), X0=None if n0 == 0 else U, out=U, step_offset=n0,
+                    reproject_every=args.reproject, observable=obs, precision=1)
+
+    for n0 in range(0, Wm, args.chunk):
+        advance(n0, min(Wm, n0 + args.chunk))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n0 in range(Wm, Wm + K, args.chunk):
+        advance(n0, min(Wm + K, n0 + args.chunk))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["strang"] = {"workload": "headline workload with the Strang splitting V(dt/2) C_n V(dt/2)",
+                     "value": B * K / el, "unit": "propagator steps/s", "ms_per_step": 1e3 * el / K}
+    log(f"[bench] Strang headline: {B * K / el:.4g} steps/s")
+    del table, U
+    torch.cuda.empty_cache()
+    q = W.c6_grape_1024(B=1, N=500)
+    table = redo.RedoTable.from_problem(q)
+    if args.cache:
+        table.cache_levels()
+    uq = torch.tensor(q.u, device="cuda")
+    psi0 = np.zeros((1, q.d), np.complex128)
+    psi0[0, 0] = 1.0
+    psif = q.U_target[:, :, 0].copy()
+    table.state_grape(uq, psi0, psif)
+    torch.cuda.synchronize()
+    iters = 20
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        F, _, g = table.state_grape(uq, psi0, psif)
+        uq = torch.clamp(uq + 1e3 * g, -q.u_scale, q.u_scale)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / iters
+    # each step applies its one composed factor (8 d^2 bytes read) to the forward and the backward vector
+    gbs = 2 * q.N * 8 * q.d * q.d / el / 1e9
+    out["state_grape"] = {"workload": "10-qubit NMR chain d=1024, N=500, F_S = |<psi_f|U|0>|^2, gradient + update",
+                          "iters_per_s": 1.0 / el, "ms_per_iter": 1e3 * el,
+                          "factor_read_GBs": gbs, "frac_of_hbm": gbs / PEAK_HBM_GBS}
+    log(f"[bench] state GRAPE d=1024: {1.0 / el:.4g} it/s ({gbs:.0f} GB/s of factor reads)")
+    del table
+    return out
+
+
 def bench_c2(args, redo, W, torch):
     """Secondary comparison at d = 64 (6-qubit chain, 256 replicas x 2000 steps):
     the fused small-d REDO chain against the plain per-step exponential on the
@@ -280,6 +340,7 @@ def main():
     ap.add_argument("--no-4m", action="store_true", help="skip the four-product FP32 line")
     ap.add_argument("--no-expm", action="store_true")
     ap.add_argument("--no-kron", action="store_true", help="skip the structure-aware chain on the headline workload")
+    ap.add_argument("--no-next", action="store_true", help="skip the Strang and state-GRAPE lines")
     ap.add_argument("--expm-steps", type=int, default=4)
     ap.add_argument("--chunk", type=int, default=4, help="time segments advanced per library call")
     ap.add_argument("--calibrate", action="store_true",
@@ -317,6 +378,8 @@ def main():
     gr = None if args.no_grape else bench_grape(args, redo, W, torch)
     torch.cuda.empty_cache()
     c2 = None if args.no_c2 else bench_c2(args, redo, W, torch)
+    torch.cuda.empty_cache()
+    nx = None if (args.no_next or args.no_freezing) else bench_next(args, redo, W, torch)
     torch.cuda.empty_cache()
     sw = None if args.no_sweep else bench_sweep(args)
     torch.cuda.empty_cache()
@@ -386,6 +449,8 @@ def main():
         "grape_speedup_vs_expm": None if (rg is None or eg is None) else rg["iters_per_s"] / eg["iters_per_s"],
         "d64_chain": c2,
         "paper_freezing_sweep_d8": sw,
+        "strang": None if nx is None else nx["strang"],
+        "state_grape": None if nx is None else nx["state_grape"],
         "table_build_s": fr["table_build_s"],
         "level_cache_build_s": fr["cache_build_s"],
         "roofline": {"bound": "mfma", "kernel": "cgemm_kernel<128,64,3M> (batched complex GEMM, FP32, three real products)",

@@ -28,76 +28,92 @@ struct MvDesc {
     int conj_scales;      // 1: conj(pre), conj(post)
 };
 
-constexpr int MV_ROWS = 64;   // output rows per workgroup
+// y = post . op(F) (pre . x) in two kernels: 64 x 64 tiles of op(F) give partial sums
+// over their 64 columns (so even one instance spreads over (d / 64)^2 workgroups, each
+// with 16 independent loads per thread), then one pass sums the column tiles of each
+// row in a fixed order and applies the output scaling
+constexpr int MV_T = 64;
 
-// y = post . op(F) (pre . x) for rows [r0, r0 + 64) of one instance
-__global__ __launch_bounds__(256) void matvec_kernel(int d, const MvDesc* __restrict__ descs, int B) {
-    extern __shared__ float2 xs[];   // pre . x, d entries
-    __shared__ float2 part[4][MV_ROWS];
-    const int b = blockIdx.y;
-    const int r0 = blockIdx.x * MV_ROWS;
+__device__ inline float2 mv_scale(const MvDesc& m, const float2* s, int i) {
+    const float2 p = s[i];
+    return m.conj_scales ? cconj(p) : p;
+}
+
+__global__ __launch_bounds__(256) void matvec_tile_kernel(int d, const MvDesc* __restrict__ descs, int B,
+                                                          float2* __restrict__ part) {
+    const int r0 = blockIdx.x * MV_T, c0 = blockIdx.y * MV_T, b = blockIdx.z;
     const MvDesc m = descs[b];
-    const int tid = threadIdx.x;
-    for (int c = tid; c < d; c += 256) {
-        float2 v = m.x[c];
-        if (m.pre) {
-            const float2 p = m.pre[c];
-            v = cmul(m.conj_scales ? cconj(p) : p, v);
+    if (!m.F) return;   // identity factor: the sum kernel copies
+    __shared__ float2 xs[MV_T];
+    __shared__ float2 red[4][MV_T];
+    const int t = threadIdx.x;
+    if (t < MV_T) {
+        const int c = c0 + t;
+        float2 v = make_float2(0.f, 0.f);
+        if (c < d) {
+            v = m.x[c];
+            if (m.pre) v = cmul(mv_scale(m, m.pre, c), v);
         }
-        xs[c] = v;
+        xs[t] = v;
     }
     __syncthreads();
     float2 acc = make_float2(0.f, 0.f);
-    const int lane = tid & 63, wave = tid >> 6;
-    int r = r0 + lane;
-    if (!m.F) {
-        // identity factor: a scaled copy
-        if (wave == 0 && r < d) {
-            float2 v = xs[r];
-            if (m.post) {
-                const float2 p = m.post[r];
-                v = cmul(m.conj_scales ? cconj(p) : p, v);
-            }
-            m.y[r] = v;
-        }
-        return;
-    }
+    float2* out = part + ((long long)blockIdx.y * B + b) * d;
     if (m.adj) {
-        // y_r = sum_c conj(F[c][r]) x_c: lanes over r (coalesced rows of F), waves split c
-        if (r < d)
-            for (int c = wave; c < d; c += 4) cfma(acc, cconj(m.F[(long long)c * d + r]), xs[c]);
-        part[wave][lane] = acc;
-        __syncthreads();
-        if (wave == 0 && r < d) {
-            float2 v = make_float2(part[0][lane].x + part[1][lane].x + part[2][lane].x + part[3][lane].x,
-                                   part[0][lane].y + part[1][lane].y + part[2][lane].y + part[3][lane].y);
-            if (m.post) {
-                const float2 p = m.post[r];
-                v = cmul(m.conj_scales ? cconj(p) : p, v);
-            }
-            m.y[r] = v;
-        }
-    } else {
-        // y_r = sum_c F[r][c] x_c: a wave per row, lanes over c (coalesced), shuffle reduction
-        for (int rr = wave; rr < MV_ROWS; rr += 4) {
-            const int row = r0 + rr;
-            if (row >= d) break;
-            float2 a = make_float2(0.f, 0.f);
-            for (int c = lane; c < d; c += 64) cfma(a, m.F[(long long)row * d + c], xs[c]);
+        // y_r = sum_c conj(F[c][r]) x_c: lanes over r (each load a row segment of F), waves over 16 c each
+        const int rl = t & 63, wv = t >> 6, r = r0 + rl;
+        if (r < d) {
+            float2 f[16];
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                a.x += __shfl_xor(a.x, o);
-                a.y += __shfl_xor(a.y, o);
+            for (int j = 0; j < 16; ++j) {
+                const int c = c0 + 16 * wv + j;
+                f[j] = c < d ? m.F[(long long)c * d + r] : make_float2(0.f, 0.f);
             }
-            if (lane == 0) {
-                if (m.post) {
-                    const float2 p = m.post[row];
-                    a = cmul(m.conj_scales ? cconj(p) : p, a);
-                }
-                m.y[row] = a;
-            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) cfma(acc, cconj(f[j]), xs[16 * wv + j]);
         }
+        red[wv][rl] = acc;
+        __syncthreads();
+        if (t < MV_T && r0 + t < d)
+            out[r0 + t] = make_float2(red[0][t].x + red[1][t].x + red[2][t].x + red[3][t].x,
+                                      red[0][t].y + red[1][t].y + red[2][t].y + red[3][t].y);
+    } else {
+        // y_r = sum_c F[r][c] x_c: four lanes per row, 16 consecutive columns each, shuffle sum
+        const int rl = t >> 2, cq = t & 3, r = r0 + rl;
+        if (r < d) {
+            float2 f[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int c = c0 + 16 * cq + j;
+                f[j] = c < d ? m.F[(long long)r * d + c] : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) cfma(acc, f[j], xs[16 * cq + j]);
+        }
+        acc.x += __shfl_xor(acc.x, 1);
+        acc.y += __shfl_xor(acc.y, 1);
+        acc.x += __shfl_xor(acc.x, 2);
+        acc.y += __shfl_xor(acc.y, 2);
+        if (cq == 0 && r < d) out[r] = acc;
     }
+}
+
+__global__ void matvec_sum_kernel(int d, const MvDesc* __restrict__ descs, int B, const float2* __restrict__ part,
+                                  int nct) {
+    const int b = blockIdx.y;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= d) return;
+    const MvDesc m = descs[b];
+    float2 v;
+    if (!m.F) {
+        v = m.x[r];
+        if (m.pre) v = cmul(mv_scale(m, m.pre, r), v);
+    } else {
+        v = make_float2(0.f, 0.f);
+        for (int ct = 0; ct < nct; ++ct) v = cadd(v, part[((long long)ct * B + b) * d + r]);
+    }
+    if (m.post) v = cmul(mv_scale(m, m.post, r), v);
+    m.y[r] = v;
 }
 
 struct StatePlan {
@@ -111,26 +127,33 @@ struct StatePlan {
     const int* n_steps;
     long long ent;
     int d, K, P, base, n_drift, phased, dense, strang, cache_levels, all_cached, slots, N, step, backward;
+    int all;                // 1: grid (B, N), every step and both directions in one launch
     double dt;
-    const float2* src;      // input vectors [B], stride vs
-    float2* dst;            // output vectors [B], stride vs
-    long long src_stride, dst_stride;
+    float2* Psi;            // forward vectors [B][N + 1][d]
+    float2* Chi;            // backward vectors [B][N + 1][d]
+    long long vs;           // per-instance stride of Psi and Chi
     float2* tmp0;           // [B][d] ping-pong for the slots in between
     float2* tmp1;
-    float2 *pre, *post, *pstar;   // [B][d]
-    MvDesc* descs;          // [slots][B]
+    float2 *pre, *post, *pstar;   // [B][d] per planned step
+    MvDesc* descs;          // [slots][B] per planned step and direction
     int B;
 };
 
-// per instance: the step's scale vectors and one descriptor per slot.  Forward
+// per instance and step: the step's scale vectors and one descriptor per slot.  Forward
 // (psi <- U psi): pre on slot 0 (with the dense drift as slot 0 and Z^dag after it),
 // post on the last slot.  Backward (chi <- U^dag chi): the slots in reverse order,
-// adjoint factors, conjugated scalings.
+// adjoint factors, conjugated scalings.  With a.all the launch covers every step
+// (blockIdx.y) and writes the descriptors of both directions.
 __global__ void state_plan_kernel(StatePlan a) {
     const int b = blockIdx.x, d = a.d;
-    const bool active = a.n_steps ? a.step < a.n_steps[b] : true;
-    const int* cb = a.codes + ((long long)b * a.N + a.step) * a.K;
-    const double* pb = a.phi ? a.phi + ((long long)b * a.N + a.step) * a.K : nullptr;
+    const int step = a.all ? (int)blockIdx.y : a.step;
+    const long long so = a.all ? (long long)step * a.B * d : 0;
+    float2* pre = a.pre + so;
+    float2* post = a.post + so;
+    float2* pstar = a.pstar + so;
+    const bool active = a.n_steps ? step < a.n_steps[b] : true;
+    const int* cb = a.codes + ((long long)b * a.N + step) * a.K;
+    const double* pb = a.phi ? a.phi + ((long long)b * a.N + step) * a.K : nullptr;
     const int drift = b % a.n_drift;
     for (int r = threadIdx.x; r < d; r += blockDim.x) {
         double th = 0.0;
@@ -138,59 +161,62 @@ __global__ void state_plan_kernel(StatePlan a) {
             for (int k = 0; k < a.K; ++k) th += pb[k] * a.g[(long long)k * d + r];
         const double hd = (!a.dense && a.strang) ? 0.5 * a.dt * a.h[(long long)drift * d + r] : 0.0;
         const double2 po = expmi(th + hd);
-        a.post[(long long)b * d + r] = make_float2((float)po.x, (float)po.y);
-        a.pstar[(long long)b * d + r] = make_float2((float)po.x, (float)-po.y);
+        post[(long long)b * d + r] = make_float2((float)po.x, (float)po.y);
+        pstar[(long long)b * d + r] = make_float2((float)po.x, (float)-po.y);
         if (!a.dense) {
             const double hdt = a.strang ? 0.5 * a.dt : a.dt;
             const double2 pr = expmi(hdt * a.h[(long long)drift * d + r] - th);
-            a.pre[(long long)b * d + r] = make_float2((float)pr.x, (float)pr.y);
+            pre[(long long)b * d + r] = make_float2((float)pr.x, (float)pr.y);
         }
     }
     if (threadIdx.x != 0) return;
     const int S = a.slots;
-    for (int i = 0; i < S; ++i) {
-        // forward slot index of the i-th application
-        const int s = a.backward ? S - 1 - i : i;
-        MvDesc m{};
-        m.x = i == 0 ? a.src + (long long)b * a.src_stride : ((i - 1) % 2 == 0 ? a.tmp0 : a.tmp1) + (long long)b * d;
-        m.y = i == S - 1 ? a.dst + (long long)b * a.dst_stride : (i % 2 == 0 ? a.tmp0 : a.tmp1) + (long long)b * d;
-        if (active) {
-            int fadj = 0;
-            if (a.dense && s == 0) {
-                m.F = a.V + (long long)drift * a.ent;
-            } else {
-                const int slot = s - a.dense;
-                const int k = a.all_cached ? slot : slot / a.P;
-                const int j = a.all_cached ? 0 : slot % a.P;
-                const int q = cb[k];
-                const int aq = q < 0 ? -q : q;
-                fadj = q < 0 ? 1 : 0;
-                if (a.all_cached) {
-                    if (aq != 0) m.F = a.cache + ((long long)k * a.cache_levels + aq) * a.ent;
+    for (int dir = a.all ? 0 : a.backward; dir <= (a.all ? 1 : a.backward); ++dir) {
+        const float2* src = dir ? a.Chi + (long long)(step + 1) * d : a.Psi + (long long)step * d;
+        float2* dst = dir ? a.Chi + (long long)step * d : a.Psi + (long long)(step + 1) * d;
+        MvDesc* out = a.all ? a.descs + (long long)(dir * a.N + step) * S * a.B : a.descs;
+        for (int i = 0; i < S; ++i) {
+            // forward slot index of the i-th application
+            const int s = dir ? S - 1 - i : i;
+            MvDesc m{};
+            m.x = i == 0 ? src + (long long)b * a.vs : ((i - 1) % 2 == 0 ? a.tmp0 : a.tmp1) + (long long)b * d;
+            m.y = i == S - 1 ? dst + (long long)b * a.vs : (i % 2 == 0 ? a.tmp0 : a.tmp1) + (long long)b * d;
+            if (active) {
+                int fadj = 0;
+                if (a.dense && s == 0) {
+                    m.F = a.V + (long long)drift * a.ent;
                 } else {
-                    const int c = digit_of(q, j, a.base);
-                    if (c) m.F = a.T + ((long long)(k * a.P + j) * (a.base - 1) + (c - 1)) * a.ent;
+                    const int slot = s - a.dense;
+                    const int k = a.all_cached ? slot : slot / a.P;
+                    const int j = a.all_cached ? 0 : slot % a.P;
+                    const int q = cb[k];
+                    const int aq = q < 0 ? -q : q;
+                    fadj = q < 0 ? 1 : 0;
+                    if (a.all_cached) {
+                        if (aq != 0) m.F = a.cache + ((long long)k * a.cache_levels + aq) * a.ent;
+                    } else {
+                        const int c = digit_of(q, j, a.base);
+                        if (c) m.F = a.T + ((long long)(k * a.P + j) * (a.base - 1) + (c - 1)) * a.ent;
+                    }
+                }
+                m.adj = dir ? 1 - fadj : fadj;
+                // the scalings of the forward step: pre before slot 0 (diagonal drift), Z^dag after
+                // the dense drift (slot 0), Z (times the second half drift, Strang) after the last slot
+                const float2* fpre = (!a.dense && s == 0) ? pre + (long long)b * d : nullptr;
+                const float2* fpost = nullptr;
+                if (a.dense && s == 0 && a.phased) fpost = pstar + (long long)b * d;
+                if (s == S - 1 && (a.phased || a.strang) && !(a.dense && s == 0)) fpost = post + (long long)b * d;
+                if (!dir) {
+                    m.pre = fpre;
+                    m.post = fpost;
+                } else {
+                    m.pre = fpost;
+                    m.post = fpre;
+                    m.conj_scales = 1;
                 }
             }
-            m.adj = a.backward ? 1 - fadj : fadj;
-            // the scalings of the forward step: pre before slot 0 (diagonal drift), Z^dag after
-            // the dense drift (slot 0), Z (times the second half drift, Strang) after the last slot
-            const float2* fpre = (!a.dense && s == 0) ? a.pre + (long long)b * d : nullptr;
-            const float2* fpost = nullptr;
-            if (a.dense && s == 0 && a.phased) fpost = a.pstar + (long long)b * d;
-            if (s == S - 1 && (a.phased || a.strang) && !(a.dense && s == 0)) {
-                fpost = a.post + (long long)b * d;
-            }
-            if (!a.backward) {
-                m.pre = fpre;
-                m.post = fpost;
-            } else {
-                m.pre = fpost;
-                m.post = fpre;
-                m.conj_scales = 1;
-            }
+            out[(long long)i * a.B + b] = m;
         }
-        a.descs[(long long)i * a.B + b] = m;
     }
 }
 
@@ -357,10 +383,11 @@ struct StateWS {
     double* phi;
     float2 *Psi, *Chi, *tmp0, *tmp1, *pre, *post, *pstar;
     MvDesc* descs;
+    float2* part;           // [d / 64][B][d] column-tile partial sums of one factor application
     double *tr, *d0, *nu;
     double2* ov;
     size_t bytes;
-    StateWS(const redo_table_s* t, int B, int N, int slots, void* base) {
+    StateWS(const redo_table_s* t, int B, int N, int slots, void* base, int plan_steps = 1) {
         const int d = t->desc.d, K = t->desc.K;
         char* p = static_cast<char*>(base);
         size_t used = 0;
@@ -375,10 +402,11 @@ struct StateWS {
         Chi = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * (N + 1) * d));
         tmp0 = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * d));
         tmp1 = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * d));
-        pre = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * d));
-        post = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * d));
-        pstar = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * d));
-        descs = reinterpret_cast<MvDesc*>(take(sizeof(MvDesc) * (size_t)B * slots));
+        pre = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)plan_steps * B * d));
+        post = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)plan_steps * B * d));
+        pstar = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)plan_steps * B * d));
+        descs = reinterpret_cast<MvDesc*>(take(sizeof(MvDesc) * (size_t)(plan_steps > 1 ? 2 : 1) * plan_steps * B * slots));
+        part = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)((d + MV_T - 1) / MV_T) * B * d));
         tr = reinterpret_cast<double*>(take(sizeof(double) * (size_t)B * N * K * 6));
         d0 = reinterpret_cast<double*>(take(sizeof(double) * (size_t)B * K * 2));
         nu = reinterpret_cast<double*>(take(sizeof(double) * (size_t)B));
@@ -395,20 +423,29 @@ int state_slots(const redo_table_s* t) {
     return (t->desc.drift_is_diag ? 0 : 1) + (cached_all(t) ? t->desc.K : t->desc.K * t->desc.digits);
 }
 
+// every step planned in one launch when its scale vectors and descriptors take at most this much
+constexpr size_t STATE_PLAN_ALL_BYTES = size_t(256) << 20;
+
+int state_plan_steps(const redo_table_s* t, int B, int N) {
+    const size_t per_step = (size_t)B * (3 * sizeof(float2) * t->desc.d + 2 * sizeof(MvDesc) * state_slots(t));
+    return (N <= 65535 && per_step * N <= STATE_PLAN_ALL_BYTES) ? N : 1;   // grid.y bounds N
+}
+
 }  // namespace
 
 size_t state_grape_workspace_bytes(const redo_table_s* t, int B, int N) {
-    return StateWS(t, B, N, state_slots(t), nullptr).bytes;
+    return StateWS(t, B, N, state_slots(t), nullptr, state_plan_steps(t, B, N)).bytes;
 }
 
 redo_status state_grape(redo_table_s* t, const float* u, const int* n_steps, int B, int N, const float* psi0,
                         const float* psif, double* fidelity, double* overlap, float* grad, void* workspace,
                         size_t workspace_bytes, hipStream_t st) {
     const int S = state_slots(t);
-    StateWS need(t, B, N, S, nullptr);
+    const int PS = state_plan_steps(t, B, N);
+    StateWS need(t, B, N, S, nullptr, PS);
     if (!workspace || workspace_bytes < need.bytes)
         return fail(REDO_ERR_WORKSPACE, "state GRAPE workspace needs " + std::to_string(need.bytes) + " bytes");
-    StateWS w(t, B, N, S, workspace);
+    StateWS w(t, B, N, S, workspace, PS);
     const int d = t->desc.d, K = t->desc.K;
     const long long vs = (long long)(N + 1) * d;
     REDO_HIP(quantise_all(t, u, B, N, w.codes, w.phi, st));
@@ -447,27 +484,37 @@ redo_status state_grape(redo_table_s* t, const float* u, const int* n_steps, int
     p.pstar = w.pstar;
     p.descs = w.descs;
     p.B = B;
-    p.src_stride = vs;
-    p.dst_stride = vs;
-    const dim3 mv_grid((d + MV_ROWS - 1) / MV_ROWS, B);
-    const size_t mv_lds = sizeof(float2) * (size_t)d;
-    REDO_HIP(hipFuncSetAttribute((const void*)matvec_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mv_lds));
+    p.vs = vs;
+    p.Psi = w.Psi;
+    p.Chi = w.Chi;
+    p.all = PS > 1 ? 1 : 0;
+    const int nct = (d + MV_T - 1) / MV_T;
+    const dim3 mv_grid(nct, nct, B);
+    const dim3 sum_grid((d + 255) / 256, B);
+    if (S == 0) return fail(REDO_ERR_UNSUPPORTED, "no factor slots");
+    if (p.all) {
+        hipLaunchKernelGGL(state_plan_kernel, dim3(B, N), dim3(256), 0, st, p);
+        REDO_HIP(hipGetLastError());
+    }
     auto run_step = [&](int n, int backward) -> hipError_t {
-        p.step = n;
-        p.backward = backward;
-        p.src = backward ? w.Chi + (size_t)(n + 1) * d : w.Psi + (size_t)n * d;
-        p.dst = backward ? w.Chi + (size_t)n * d : w.Psi + (size_t)(n + 1) * d;
-        hipLaunchKernelGGL(state_plan_kernel, dim3(B), dim3(256), 0, st, p);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        const MvDesc* dv = w.descs;
+        if (p.all) {
+            dv = w.descs + (size_t)(backward * N + n) * S * B;
+        } else {
+            p.step = n;
+            p.backward = backward;
+            hipLaunchKernelGGL(state_plan_kernel, dim3(B), dim3(256), 0, st, p);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
         for (int i = 0; i < S; ++i) {
-            hipLaunchKernelGGL(matvec_kernel, mv_grid, dim3(256), mv_lds, st, d, w.descs + (size_t)i * B, B);
-            e = hipGetLastError();
+            hipLaunchKernelGGL(matvec_tile_kernel, mv_grid, dim3(256), 0, st, d, dv + (size_t)i * B, B, w.part);
+            hipLaunchKernelGGL(matvec_sum_kernel, sum_grid, dim3(256), 0, st, d, dv + (size_t)i * B, B, w.part, nct);
+            const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     };
-    if (S == 0) return fail(REDO_ERR_UNSUPPORTED, "no factor slots");
     for (int n = 0; n < N; ++n) REDO_HIP(run_step(n, 0));
     for (int n = N - 1; n >= 0; --n) REDO_HIP(run_step(n, 1));
     hipLaunchKernelGGL(state_final_kernel, dim3(B), dim3(256), 0, st, d, K, t->desc.phased,
