@@ -271,8 +271,11 @@ redo_status redo_grape_fidelity_grad(redo_table table, int32_t precision, const 
  * and the backward scan chi_{n-1} = U_n^dag chi_n, chi_N = psi_f, with the trace
  * identities of redo_grape_fidelity_grad on the rank-one Y_n = psi_n chi_n^dag
  * (no normalisation: g = <psi_f|psi_N>).  Every product is a batched
- * matrix-vector product (FP32, REDO_PREC_F32 only); every state is kept.
- * Same channel conditions as redo_grape_fidelity_grad.
+ * matrix-vector product (FP32, REDO_PREC_F32 only); every state is kept, and
+ * when every step's plan fits (N_max <= 65535) each launch applies one factor
+ * of forward step n and one of backward step N_max - 1 - n together.
+ * Same channel conditions as redo_grape_fidelity_grad.  B <= 32767
+ * (REDO_ERR_UNSUPPORTED beyond).
  *   psi0, psi_f  c64 [B][d] (the caller normalises them)
  *   fidelity double [B];  overlap c128 [B] (g) or NULL;  grad float, same layout as u
  * Workspace: redo_workspace_bytes(table, REDO_OP_STATE_GRAPE, B, N_max).

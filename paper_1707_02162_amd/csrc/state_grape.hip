@@ -28,92 +28,115 @@ struct MvDesc {
     int conj_scales;      // 1: conj(pre), conj(post)
 };
 
-// y = post . op(F) (pre . x) in two kernels: 64 x 64 tiles of op(F) give partial sums
-// over their 64 columns (so even one instance spreads over (d / 64)^2 workgroups, each
-// with 16 independent loads per thread), then one pass sums the column tiles of each
-// row in a fixed order and applies the output scaling
-constexpr int MV_T = 64;
+// y = post . op(F) (pre . x), one workgroup of 16 waves per 16 rows of y reading those
+// rows of op(F) whole (16 d complex entries, 128 KiB at d = 1024) in blocks of 16
+// independent loads per thread, the scaled input in LDS: nothing leaves the workgroup
+// before the result, so one factor application is one launch and the summation order
+// is fixed.  blockIdx.y runs over the instances of up to two independent chains, the
+// forward chain and the backward scan: y < B takes descs0[y], y >= B descs1[y - B].
+constexpr int MV_R = 16;
+constexpr int MV_NT = 1024;
+constexpr int MV_U = 16;    // loads per thread in flight
+
+// the factors come through descriptors, which the compiler cannot place in an address
+// space: mark them global so the loads are global (vector-memory counter only), not flat
+typedef float mv_v2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const mv_v2 mv_gv2;
+
+__device__ inline float2 mv_load(const float2* p, long long i) {
+    const mv_v2 v = ((mv_gv2*)p)[i];
+    return make_float2(v.x, v.y);
+}
 
 __device__ inline float2 mv_scale(const MvDesc& m, const float2* s, int i) {
     const float2 p = s[i];
     return m.conj_scales ? cconj(p) : p;
 }
 
-__global__ __launch_bounds__(256) void matvec_tile_kernel(int d, const MvDesc* __restrict__ descs, int B,
-                                                          float2* __restrict__ part) {
-    const int r0 = blockIdx.x * MV_T, c0 = blockIdx.y * MV_T, b = blockIdx.z;
-    const MvDesc m = descs[b];
-    if (!m.F) return;   // identity factor: the sum kernel copies
-    __shared__ float2 xs[MV_T];
-    __shared__ float2 red[4][MV_T];
-    const int t = threadIdx.x;
-    if (t < MV_T) {
-        const int c = c0 + t;
-        float2 v = make_float2(0.f, 0.f);
-        if (c < d) {
-            v = m.x[c];
-            if (m.pre) v = cmul(mv_scale(m, m.pre, c), v);
-        }
-        xs[t] = v;
-    }
-    __syncthreads();
-    float2 acc = make_float2(0.f, 0.f);
-    float2* out = part + ((long long)blockIdx.y * B + b) * d;
-    if (m.adj) {
-        // y_r = sum_c conj(F[c][r]) x_c: lanes over r (each load a row segment of F), waves over 16 c each
-        const int rl = t & 63, wv = t >> 6, r = r0 + rl;
-        if (r < d) {
-            float2 f[16];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int c = c0 + 16 * wv + j;
-                f[j] = c < d ? m.F[(long long)c * d + r] : make_float2(0.f, 0.f);
-            }
-#pragma unroll
-            for (int j = 0; j < 16; ++j) cfma(acc, cconj(f[j]), xs[16 * wv + j]);
-        }
-        red[wv][rl] = acc;
-        __syncthreads();
-        if (t < MV_T && r0 + t < d)
-            out[r0 + t] = make_float2(red[0][t].x + red[1][t].x + red[2][t].x + red[3][t].x,
-                                      red[0][t].y + red[1][t].y + red[2][t].y + red[3][t].y);
-    } else {
-        // y_r = sum_c F[r][c] x_c: four lanes per row, 16 consecutive columns each, shuffle sum
-        const int rl = t >> 2, cq = t & 3, r = r0 + rl;
-        if (r < d) {
-            float2 f[16];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int c = c0 + 16 * cq + j;
-                f[j] = c < d ? m.F[(long long)r * d + c] : make_float2(0.f, 0.f);
-            }
-#pragma unroll
-            for (int j = 0; j < 16; ++j) cfma(acc, f[j], xs[16 * cq + j]);
-        }
-        acc.x += __shfl_xor(acc.x, 1);
-        acc.y += __shfl_xor(acc.y, 1);
-        acc.x += __shfl_xor(acc.x, 2);
-        acc.y += __shfl_xor(acc.y, 2);
-        if (cq == 0 && r < d) out[r] = acc;
-    }
+__device__ inline float2 mv_input(const MvDesc& m, int c) {
+    const float2 v = m.x[c];
+    return m.pre ? cmul(mv_scale(m, m.pre, c), v) : v;
 }
 
-__global__ void matvec_sum_kernel(int d, const MvDesc* __restrict__ descs, int B, const float2* __restrict__ part,
-                                  int nct) {
-    const int b = blockIdx.y;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= d) return;
-    const MvDesc m = descs[b];
-    float2 v;
-    if (!m.F) {
-        v = m.x[r];
-        if (m.pre) v = cmul(mv_scale(m, m.pre, r), v);
-    } else {
-        v = make_float2(0.f, 0.f);
-        for (int ct = 0; ct < nct; ++ct) v = cadd(v, part[((long long)ct * B + b) * d + r]);
+__global__ __launch_bounds__(MV_NT) void matvec_kernel(int d, const MvDesc* __restrict__ descs0,
+                                                       const MvDesc* __restrict__ descs1, int B) {
+    extern __shared__ float2 xs[];   // [d]: pre . x
+    __shared__ float2 red[MV_NT / 64][MV_R];
+    const int z = blockIdx.y;
+    const MvDesc m = z < B ? descs0[z] : descs1[z - B];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int r0 = blockIdx.x * MV_R;
+    if (!m.F) {   // identity factor: copy with the scalings
+        const int r = r0 + t;
+        if (t < MV_R && r < d) {
+            float2 v = mv_input(m, r);
+            if (m.post) v = cmul(mv_scale(m, m.post, r), v);
+            m.y[r] = v;
+        }
+        return;
     }
-    if (m.post) v = cmul(mv_scale(m, m.post, r), v);
-    m.y[r] = v;
+    for (int c = t; c < d; c += MV_NT) xs[c] = mv_input(m, c);
+    __syncthreads();
+    float2 acc = make_float2(0.f, 0.f);
+    if (m.adj) {
+        // y_r = sum_c conj(F[c][r]) x_c: lanes over 16 rows (one 128-byte segment of row c
+        // of F) and 4 column groups, waves over 16 more; column c = 64 j + group
+        const int rl = lane & 15, cg = (lane >> 4) + 4 * wv, r = r0 + rl;
+        const bool ok = r < d;
+        for (int cb = 0; cb < d; cb += 64 * MV_U) {
+            float2 f[MV_U];
+#pragma unroll
+            for (int j = 0; j < MV_U; ++j) {
+                const int c = cb + cg + 64 * j;
+                f[j] = (ok && c < d) ? mv_load(m.F, (long long)c * d + r) : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int j = 0; j < MV_U; ++j) {
+                const int c = cb + cg + 64 * j;
+                if (c < d) cfma(acc, cconj(f[j]), xs[c]);
+            }
+        }
+        acc.x += __shfl_xor(acc.x, 16);
+        acc.y += __shfl_xor(acc.y, 16);
+        acc.x += __shfl_xor(acc.x, 32);
+        acc.y += __shfl_xor(acc.y, 32);
+        if (lane < MV_R) red[wv][lane] = acc;
+    } else {
+        // y_r = sum_c F[r][c] x_c: wave w takes row r0 + w, lanes over columns c = lane + 64 j
+        // (512 contiguous bytes of the row per load), then a wave sum
+        const int r = r0 + wv;
+        const bool ok = r < d;
+        for (int cb = 0; cb < d; cb += 64 * MV_U) {
+            float2 f[MV_U];
+#pragma unroll
+            for (int j = 0; j < MV_U; ++j) {
+                const int c = cb + lane + 64 * j;
+                f[j] = (ok && c < d) ? mv_load(m.F, (long long)r * d + c) : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int j = 0; j < MV_U; ++j) {
+                const int c = cb + lane + 64 * j;
+                if (c < d) cfma(acc, f[j], xs[c]);
+            }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            acc.x += __shfl_xor(acc.x, o);
+            acc.y += __shfl_xor(acc.y, o);
+        }
+        if (lane == 0) red[0][wv] = acc;
+    }
+    __syncthreads();
+    const int r = r0 + t;
+    if (t < MV_R && r < d) {
+        float2 v = red[0][t];
+        if (m.adj) {
+#pragma unroll
+            for (int w = 1; w < MV_NT / 64; ++w) v = cadd(v, red[w][t]);
+        }
+        if (m.post) v = cmul(mv_scale(m, m.post, r), v);
+        m.y[r] = v;
+    }
 }
 
 struct StatePlan {
@@ -132,7 +155,7 @@ struct StatePlan {
     float2* Psi;            // forward vectors [B][N + 1][d]
     float2* Chi;            // backward vectors [B][N + 1][d]
     long long vs;           // per-instance stride of Psi and Chi
-    float2* tmp0;           // [B][d] ping-pong for the slots in between
+    float2* tmp0;           // [2][B][d] ping-pong for the slots in between, per direction
     float2* tmp1;
     float2 *pre, *post, *pstar;   // [B][d] per planned step
     MvDesc* descs;          // [slots][B] per planned step and direction
@@ -179,8 +202,9 @@ __global__ void state_plan_kernel(StatePlan a) {
             // forward slot index of the i-th application
             const int s = dir ? S - 1 - i : i;
             MvDesc m{};
-            m.x = i == 0 ? src + (long long)b * a.vs : ((i - 1) % 2 == 0 ? a.tmp0 : a.tmp1) + (long long)b * d;
-            m.y = i == S - 1 ? dst + (long long)b * a.vs : (i % 2 == 0 ? a.tmp0 : a.tmp1) + (long long)b * d;
+            const long long tb = (long long)(dir * a.B + b) * d;
+            m.x = i == 0 ? src + (long long)b * a.vs : ((i - 1) % 2 == 0 ? a.tmp0 : a.tmp1) + tb;
+            m.y = i == S - 1 ? dst + (long long)b * a.vs : (i % 2 == 0 ? a.tmp0 : a.tmp1) + tb;
             if (active) {
                 int fadj = 0;
                 if (a.dense && s == 0) {
@@ -383,7 +407,6 @@ struct StateWS {
     double* phi;
     float2 *Psi, *Chi, *tmp0, *tmp1, *pre, *post, *pstar;
     MvDesc* descs;
-    float2* part;           // [d / 64][B][d] column-tile partial sums of one factor application
     double *tr, *d0, *nu;
     double2* ov;
     size_t bytes;
@@ -400,13 +423,12 @@ struct StateWS {
         phi = reinterpret_cast<double*>(take(sizeof(double) * (size_t)B * N * K));
         Psi = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * (N + 1) * d));
         Chi = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * (N + 1) * d));
-        tmp0 = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * d));
-        tmp1 = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * d));
+        tmp0 = reinterpret_cast<float2*>(take(sizeof(float2) * 2 * (size_t)B * d));
+        tmp1 = reinterpret_cast<float2*>(take(sizeof(float2) * 2 * (size_t)B * d));
         pre = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)plan_steps * B * d));
         post = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)plan_steps * B * d));
         pstar = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)plan_steps * B * d));
         descs = reinterpret_cast<MvDesc*>(take(sizeof(MvDesc) * (size_t)(plan_steps > 1 ? 2 : 1) * plan_steps * B * slots));
-        part = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)((d + MV_T - 1) / MV_T) * B * d));
         tr = reinterpret_cast<double*>(take(sizeof(double) * (size_t)B * N * K * 6));
         d0 = reinterpret_cast<double*>(take(sizeof(double) * (size_t)B * K * 2));
         nu = reinterpret_cast<double*>(take(sizeof(double) * (size_t)B));
@@ -440,6 +462,7 @@ size_t state_grape_workspace_bytes(const redo_table_s* t, int B, int N) {
 redo_status state_grape(redo_table_s* t, const float* u, const int* n_steps, int B, int N, const float* psi0,
                         const float* psif, double* fidelity, double* overlap, float* grad, void* workspace,
                         size_t workspace_bytes, hipStream_t st) {
+    if (B > 32767) return fail(REDO_ERR_UNSUPPORTED, "state GRAPE takes at most 32767 instances per call");
     const int S = state_slots(t);
     const int PS = state_plan_steps(t, B, N);
     StateWS need(t, B, N, S, nullptr, PS);
@@ -488,35 +511,36 @@ redo_status state_grape(redo_table_s* t, const float* u, const int* n_steps, int
     p.Psi = w.Psi;
     p.Chi = w.Chi;
     p.all = PS > 1 ? 1 : 0;
-    const int nct = (d + MV_T - 1) / MV_T;
-    const dim3 mv_grid(nct, nct, B);
-    const dim3 sum_grid((d + 255) / 256, B);
+    const int nrt = (d + MV_R - 1) / MV_R;
     if (S == 0) return fail(REDO_ERR_UNSUPPORTED, "no factor slots");
+    const size_t mv_lds = sizeof(float2) * (size_t)d;
+    REDO_HIP(hipFuncSetAttribute((const void*)matvec_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mv_lds));
     if (p.all) {
+        // every step planned at once: step n of the forward chain and step N - 1 - n of the
+        // backward scan (independent chains) share each launch
         hipLaunchKernelGGL(state_plan_kernel, dim3(B, N), dim3(256), 0, st, p);
         REDO_HIP(hipGetLastError());
-    }
-    auto run_step = [&](int n, int backward) -> hipError_t {
-        const MvDesc* dv = w.descs;
-        if (p.all) {
-            dv = w.descs + (size_t)(backward * N + n) * S * B;
-        } else {
+        for (int n = 0; n < N; ++n) {
+            const MvDesc* fw = w.descs + (size_t)n * S * B;
+            const MvDesc* bw = w.descs + (size_t)(N + N - 1 - n) * S * B;
+            for (int i = 0; i < S; ++i)
+                hipLaunchKernelGGL(matvec_kernel, dim3(nrt, 2 * B), dim3(MV_NT), mv_lds, st, d, fw + (size_t)i * B,
+                                   bw + (size_t)i * B, B);
+            REDO_HIP(hipGetLastError());
+        }
+    } else {
+        auto run_step = [&](int n, int backward) -> hipError_t {
             p.step = n;
             p.backward = backward;
             hipLaunchKernelGGL(state_plan_kernel, dim3(B), dim3(256), 0, st, p);
-            const hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-        }
-        for (int i = 0; i < S; ++i) {
-            hipLaunchKernelGGL(matvec_tile_kernel, mv_grid, dim3(256), 0, st, d, dv + (size_t)i * B, B, w.part);
-            hipLaunchKernelGGL(matvec_sum_kernel, sum_grid, dim3(256), 0, st, d, dv + (size_t)i * B, B, w.part, nct);
-            const hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
-    };
-    for (int n = 0; n < N; ++n) REDO_HIP(run_step(n, 0));
-    for (int n = N - 1; n >= 0; --n) REDO_HIP(run_step(n, 1));
+            for (int i = 0; i < S; ++i)
+                hipLaunchKernelGGL(matvec_kernel, dim3(nrt, B), dim3(MV_NT), mv_lds, st, d, w.descs + (size_t)i * B,
+                                   (const MvDesc*)nullptr, B);
+            return hipGetLastError();
+        };
+        for (int n = 0; n < N; ++n) REDO_HIP(run_step(n, 0));
+        for (int n = N - 1; n >= 0; --n) REDO_HIP(run_step(n, 1));
+    }
     hipLaunchKernelGGL(state_final_kernel, dim3(B), dim3(256), 0, st, d, K, t->desc.phased,
                        reinterpret_cast<const float2*>(psif), w.Psi, w.Chi, vs, N, n_steps, t->g64, w.ov, fidelity,
                        w.d0, w.nu);

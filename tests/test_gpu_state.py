@@ -104,3 +104,23 @@ def test_state_fidelity_equals_chain_entry():
     F, ov, _ = t.state_grape(u, np.stack([e[1], e[3]]), np.stack([e[2], e[0]]))
     U = U.cpu().numpy()
     assert abs(ov[0].item() - U[0, 2, 1]) < 1e-6 and abs(ov[1].item() - U[1, 0, 3]) < 1e-6
+
+
+def test_state_grape_per_step_plans_equal_one_plan_d128():
+    """64 instances x 1400 steps at d = 128: the plan of every step (scale vectors and
+    descriptors) exceeds the 256 MiB bound, so each step is planned and applied on its own,
+    one scan after the other.  Instance by instance this equals the call that plans every
+    step at once and runs both scans side by side, bit for bit (same arithmetic, fixed
+    summation order); two instances against the oracle."""
+    from paper_1707_02162_amd import redo as R
+    p = W.nmr_chain(7, 64, 1400, 2e-6, 32, 2, 233)
+    t = R.RedoTable.from_problem(p)
+    assert R.lib().redo_workspace_bytes(t._h, R.OP_STATE_GRAPE, 64, 1400) < 300e6   # per-step plans
+    psi0, psif = _states(128, 64, 6)
+    u = torch.tensor(p.u).cuda()
+    F, ov, grad = t.state_grape(u, psi0, psif)
+    for b in (0, 37):
+        F1, ov1, g1 = t.state_grape(u[b:b + 1].contiguous(), psi0[b:b + 1], psif[b:b + 1])
+        assert torch.equal(F[b:b + 1], F1) and torch.equal(ov[b:b + 1], ov1) and torch.equal(grad[b:b + 1], g1)
+    _check(p.subset([5, 63]), psi0[[5, 63]], psif[[5, 63]], F.cpu().numpy()[[5, 63]], ov.cpu().numpy()[[5, 63]],
+           grad.cpu().numpy()[[5, 63]])
