@@ -676,6 +676,52 @@ __global__ void trace_final_kernel(int ntile, int K, const double* partial, doub
     if (threadIdx.x < 6) out[(long long)b * out_bstride + k * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Contribution of one pattern entry to the traces of channel k: entry (a, j) of S_k
+// (is_diag false, slot e of row a) or the diagonal (is_diag, for D), with
+// y = Y[j][a]: T1 += S^psi_aj y, T2 += S^{pi/2}_aj y (origin), D += g_a y, where
+// S^psi_aj = exp(-i psi (g_a - g_j)) S_aj, times exp(-i dt/2 (h_a - h_j)) with the
+// Strang splitting (hdt != 0).
+struct SptChannel {
+    bool origin;     // phased with q = 0, or Cartesian: also T2
+    double psi;      // phase of the step (0 unless phased and not at the origin)
+};
+
+__device__ inline SptChannel spt_channel(int phased, int cartesian, const int* codes, const double* phi, long long ci) {
+    SptChannel c;
+    const int q = codes[ci];
+    c.origin = phased && (q == 0 || cartesian);
+    c.psi = phased && !c.origin ? phi[ci] : 0.0;
+    return c;
+}
+
+__device__ inline void spt_contrib(double v[6], bool is_diag, int phased, const SptChannel& ch, int d, int k, int a,
+                                   int j, int e, int sw, double yr, double yi, const double2* __restrict__ spv,
+                                   const double* __restrict__ g, const double* __restrict__ h, long long hb,
+                                   double hdt) {
+    if (!is_diag) {
+        double2 sv = spv[((long long)k * d + a) * sw + e];
+        if (hdt != 0.0) sv = zmul(expmi(hdt * (h[hb + a] - h[hb + j])), sv);   // V(dt/2) S V(dt/2)^dag
+        double cr = sv.x, cim = sv.y;
+        if (phased && ch.psi != 0.0) {
+            const double2 p = expmi(ch.psi * (g[(long long)k * d + a] - g[(long long)k * d + j]));
+            cr = p.x * sv.x - p.y * sv.y;
+            cim = p.x * sv.y + p.y * sv.x;
+        }
+        v[0] += cr * yr - cim * yi;
+        v[1] += cr * yi + cim * yr;
+        if (ch.origin) {
+            const double2 p = expmi(1.5707963267948966 * (g[(long long)k * d + a] - g[(long long)k * d + j]));
+            const double r_ = p.x * sv.x - p.y * sv.y, i_ = p.x * sv.y + p.y * sv.x;
+            v[2] += r_ * yr - i_ * yi;
+            v[3] += r_ * yi + i_ * yr;
+        }
+    } else if (phased) {
+        const double ga = g[(long long)k * d + a];
+        v[4] += ga * yr;
+        v[5] += ga * yi;
+    }
+}
+
 // GRAPE traces from stored factors, for generators with a sparse pattern:
 // Y = X_{s+1} L_{s+1} is needed only where S_k^T (and the diagonal) is
 // nonzero, and L = LH^H is stored conjugate-transposed so that both operands
@@ -684,9 +730,16 @@ __global__ void trace_final_kernel(int ntile, int K, const double* partial, doub
 // For every channel k the row's share of T1 = Tr(S^psi Y), T2 = Tr(S^{pi/2} Y)
 // (phased, q = 0 or Cartesian) and D = Tr(G Y) goes to partial[(b N + s)][k][blk][6]
 // (s counted from step0).
+// Workgroups are dealt to the 8 XCDs, each with its own L2, in turn by linear index; the
+// index is remapped so that every row block of one step runs on the same XCD (step = XCD
+// mod 8), whose L2 then serves the rows of X_s that the step's row blocks share, instead
+// of every XCD pulling the whole state.  grid.x = (d / SPT_RPB) * (steps rounded up to a
+// multiple of 8), grid.y = B.
 constexpr int SPT_RPB = 4;
+constexpr int SPT_XCD = 8;
 template <int WP>
-__global__ __launch_bounds__(256) void sparse_trace_kernel(int d, int N, int step0, int K, int phased, int cartesian,
+__global__ __launch_bounds__(256) void sparse_trace_kernel(int d, int N, int step0, int nsl, int K, int phased,
+                                                           int cartesian,
                                                            int sw, const float2* __restrict__ X, long long xsb,
                                                            const float2* __restrict__ LH, long long lsb,
                                                            const int* __restrict__ spc,
@@ -698,8 +751,11 @@ __global__ __launch_bounds__(256) void sparse_trace_kernel(int d, int N, int ste
                                                            int n_drift, double hdt) {
     constexpr int NE = WP + 1;                      // pattern entries + the diagonal
     __shared__ double red[SPT_RPB][NE][6];
-    const int blk = blockIdx.x, sl = blockIdx.y, b = blockIdx.z;
-    const int s = step0 + sl, nblk = gridDim.x, nsl = gridDim.y;
+    const int nblk = d / SPT_RPB;
+    const int xcd = (int)blockIdx.x % SPT_XCD, on_xcd = (int)blockIdx.x / SPT_XCD;
+    const int blk = on_xcd % nblk, sl = (on_xcd / nblk) * SPT_XCD + xcd, b = blockIdx.y;
+    if (sl >= nsl) return;   // padding of the step count to a multiple of 8
+    const int s = step0 + sl;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int a = blk * SPT_RPB + wave;
     const long long mat = (long long)d * d;
@@ -761,39 +817,9 @@ __global__ __launch_bounds__(256) void sparse_trace_kernel(int d, int N, int ste
     const bool mine = active && (lane < sw || lane == WP);
     for (int k = 0; k < K; ++k) {
         double v[6] = {0, 0, 0, 0, 0, 0};
-        if (mine) {
-            const long long ci = ((long long)b * N + s) * K + k;
-            const int q = codes[ci];
-            const bool origin = phased && (q == 0 || cartesian);
-            const double psi = phased && !origin ? phi[ci] : 0.0;
-            if (lane < sw) {
-                double2 sv = spv[((long long)k * d + a) * sw + lane];
-                if (hdt != 0.0) {
-                    // Strang: V(dt/2) S V(dt/2)^dag at entry (a, j)
-                    const long long hb_ = (long long)(b % n_drift) * d;
-                    sv = zmul(expmi(hdt * (h[hb_ + a] - h[hb_ + my_j])), sv);
-                }
-                double cr = sv.x, cim = sv.y;
-                if (phased && psi != 0.0) {
-                    const double2 p = expmi(psi * (g[(long long)k * d + a] - g[(long long)k * d + my_j]));
-                    cr = p.x * sv.x - p.y * sv.y;
-                    cim = p.x * sv.y + p.y * sv.x;
-                }
-                v[0] = cr * my_r - cim * my_i;
-                v[1] = cr * my_i + cim * my_r;
-                if (origin) {
-                    const double2 p =
-                        expmi(1.5707963267948966 * (g[(long long)k * d + a] - g[(long long)k * d + my_j]));
-                    const double r_ = p.x * sv.x - p.y * sv.y, i_ = p.x * sv.y + p.y * sv.x;
-                    v[2] = r_ * my_r - i_ * my_i;
-                    v[3] = r_ * my_i + i_ * my_r;
-                }
-            } else if (phased) {
-                const double ga = g[(long long)k * d + a];
-                v[4] = ga * my_r;
-                v[5] = ga * my_i;
-            }
-        }
+        if (mine)
+            spt_contrib(v, lane == WP, phased, spt_channel(phased, cartesian, codes, phi, ((long long)b * N + s) * K + k),
+                        d, k, a, my_j, lane, sw, my_r, my_i, spv, g, h, (long long)(b % n_drift) * d, hdt);
         if (lane < NE)
 #pragma unroll
             for (int c = 0; c < 6; ++c) red[wave][lane][c] = v[c];
@@ -804,6 +830,145 @@ __global__ __launch_bounds__(256) void sparse_trace_kernel(int d, int N, int ste
                 for (int e = 0; e < NE; ++e) acc += red[w2][e][threadIdx.x];
             partial[((((long long)b * nsl + sl) * K + k) * nblk + blk) * 6 + threadIdx.x] = acc;
         }
+        __syncthreads();
+    }
+}
+
+// The same traces for d <= 1024 in two kernels.  sparse_y_kernel: one workgroup per
+// (instance, step), each thread owning SPS_RPT rows a (a0 and a0 + d / 2); X_s passes
+// through LDS in chunks of SPS_C columns, stored [c][row] so that the lanes of a wave,
+// which read rows of the pattern of consecutive rows, hit consecutive addresses; the
+// thread's rows of LH_(s+1) come straight to its registers, and each thread accumulates
+// its rows' entries Y[j][a] = sum_c X[j][c] conj(LH[a][c]) in FP64 with no partial sums
+// across lanes, then stores them to ybuf[b][s][a][slot].  Every element of X_s and
+// LH_(s+1) is read from memory once.  sparse_ysum_kernel weighs the entries per channel
+// (the FP64 phase factors, which would crowd the accumulators out of registers) and sums
+// the workgroup into tr[b][s][k][6].
+constexpr int SPS_C = 8;
+constexpr int SPS_RPT = 2;
+constexpr int SPS_DMAX = 1024;
+constexpr int SPS_NT = SPS_DMAX / SPS_RPT;
+constexpr int SPS_NE = SPAT_WMAX + 1;   // slots per row in ybuf
+template <int WP>
+__global__ __launch_bounds__(SPS_NT) void sparse_y_kernel(int d, int N, int step0, int steps, int sw,
+                                                          const float2* __restrict__ X, long long xsb,
+                                                          const float2* __restrict__ LH, long long lsb,
+                                                          const int* __restrict__ spc, const int* n_steps,
+                                                          double2* __restrict__ ybuf) {
+    constexpr int NE = WP + 1;                      // pattern slots + the diagonal
+    // [SPS_C][SPS_DMAX]: a fixed row stride, so that each column's offset is an immediate of
+    // the LDS reads (with d as the stride their addresses would have to sit in registers)
+    __shared__ float2 xs[SPS_C * SPS_DMAX];
+    const int sl = blockIdx.x, b = blockIdx.y, s = step0 + sl;
+    const int t = threadIdx.x, nt = d / SPS_RPT;
+    if (!((!n_steps || s < n_steps[b]) && s < N)) return;   // the same for the whole workgroup
+    const long long mat = (long long)d * d;
+    double yr[SPS_RPT][NE], yi[SPS_RPT][NE];
+    int jt[SPS_RPT][NE];
+#pragma unroll
+    for (int r = 0; r < SPS_RPT; ++r) {
+        const int a = t + r * nt;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            yr[r][e] = yi[r][e] = 0.0;
+            // slots past the pattern width (and the diagonal slot WP): row a
+            jt[r][e] = e < sw ? spc[(long long)a * sw + e] : a;
+        }
+    }
+    const float2* Xs = X + (long long)b * xsb + (long long)s * mat;
+    const float2* L0 = LH + (long long)b * lsb + (long long)(s + 1) * mat;
+    for (int c0 = 0; c0 < d; c0 += SPS_C) {
+        __syncthreads();   // the previous chunk is consumed
+        // each thread stages the chunk of its own rows of X_s and keeps that of LH_(s+1): all
+        // loads in flight at once
+        float4 v[SPS_RPT][SPS_C / 2], l[SPS_RPT][SPS_C / 2];
+#pragma unroll
+        for (int r = 0; r < SPS_RPT; ++r)
+#pragma unroll
+            for (int u = 0; u < SPS_C / 2; ++u) {
+                v[r][u] = *reinterpret_cast<const float4*>(Xs + (long long)(t + r * nt) * d + c0 + 2 * u);
+                l[r][u] = *reinterpret_cast<const float4*>(L0 + (long long)(t + r * nt) * d + c0 + 2 * u);
+            }
+#pragma unroll
+        for (int r = 0; r < SPS_RPT; ++r)
+#pragma unroll
+            for (int u = 0; u < SPS_C / 2; ++u) {
+                xs[(2 * u) * SPS_DMAX + t + r * nt] = make_float2(v[r][u].x, v[r][u].y);
+                xs[(2 * u + 1) * SPS_DMAX + t + r * nt] = make_float2(v[r][u].z, v[r][u].w);
+            }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < SPS_C; ++c) {
+#pragma unroll
+            for (int r = 0; r < SPS_RPT; ++r) {
+                const double lr = (c & 1) ? l[r][c / 2].z : l[r][c / 2].x;
+                const double li = (c & 1) ? l[r][c / 2].w : l[r][c / 2].y;
+                // every slot, the padding ones included: no branches in the loop
+#pragma unroll
+                for (int e = 0; e < NE; ++e) {
+                    const float2 x = xs[c * SPS_DMAX + jt[r][e]];
+                    const double xr = x.x, xi = x.y;
+                    // x conj(l) as four FP64 FMAs
+                    yr[r][e] = fma(xr, lr, fma(xi, li, yr[r][e]));
+                    yi[r][e] = fma(xi, lr, fma(-xr, li, yi[r][e]));
+                }
+            }
+            asm volatile("" ::: "memory");   // one column's LDS reads in flight at a time (register pressure)
+        }
+    }
+    double2* yo = ybuf + ((long long)b * steps + sl) * d * SPS_NE;
+#pragma unroll
+    for (int r = 0; r < SPS_RPT; ++r)
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+            if (e < sw || e == WP) yo[(long long)(t + r * nt) * SPS_NE + (e == WP ? SPAT_WMAX : e)] =
+                                       make_double2(yr[r][e], yi[r][e]);
+}
+
+// one workgroup of 256 per (instance, step): weights of the entries in ybuf (slot e < sw
+// of row a: entry (a, spc[a][e]); slot SPAT_WMAX: the diagonal) per channel, summed
+__global__ __launch_bounds__(256) void sparse_ysum_kernel(int d, int N, int step0, int steps, int K, int phased,
+                                                          int cartesian, int sw, const double2* __restrict__ ybuf,
+                                                          const int* __restrict__ spc,
+                                                          const double2* __restrict__ spv,
+                                                          const double* __restrict__ g,
+                                                          const int* __restrict__ codes,
+                                                          const double* __restrict__ phi, const int* n_steps,
+                                                          double* __restrict__ tr, const double* __restrict__ h,
+                                                          int n_drift, double hdt) {
+    __shared__ double red[4][6];
+    const int sl = blockIdx.x, b = blockIdx.y, s = step0 + sl;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    double* out = tr + ((long long)b * N + s) * K * 6;
+    if (!((!n_steps || s < n_steps[b]) && s < N)) {
+        for (int i = t; i < K * 6; i += 256) out[i] = 0.0;
+        return;
+    }
+    const double2* yb = ybuf + ((long long)b * steps + sl) * d * SPS_NE;
+    const long long hb = (long long)(b % n_drift) * d;
+    for (int k = 0; k < K; ++k) {
+        const SptChannel ch = spt_channel(phased, cartesian, codes, phi, ((long long)b * N + s) * K + k);
+        double v[6] = {0, 0, 0, 0, 0, 0};
+        for (int a = t; a < d; a += 256) {
+            for (int e = 0; e < sw; ++e) {
+                const double2 y = yb[(long long)a * SPS_NE + e];
+                spt_contrib(v, false, phased, ch, d, k, a, spc[(long long)a * sw + e], e, sw, y.x, y.y, spv, g, h,
+                            hb, hdt);
+            }
+            if (phased) {
+                const double2 y = yb[(long long)a * SPS_NE + SPAT_WMAX];
+                spt_contrib(v, true, phased, ch, d, k, a, a, 0, sw, y.x, y.y, spv, g, h, hb, hdt);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v[c] += __shfl_xor(v[c], o);
+        if (lane == 0)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) red[wave][c] = v[c];
+        __syncthreads();
+        if (t < 6) out[k * 6 + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
         __syncthreads();
     }
 }
@@ -1105,16 +1270,19 @@ hipError_t d0_traces(int d, int B, int K, int phased, const float2* L, long long
 }
 
 size_t sparse_trace_partial_doubles(int d, int B, int steps, int K) {
-    return (size_t)B * steps * K * (d / SPT_RPB) * 6;
+    const size_t rows = (size_t)B * steps * K * (d / SPT_RPB) * 6;
+    // d <= 1024: the per-step kernels keep every entry of Y at the pattern instead
+    return d <= 1024 ? std::max(rows, (size_t)B * steps * d * (SPAT_WMAX + 1) * 2) : rows;
 }
 
 template <int WP>
-static void launch_spt(dim3 grid, hipStream_t st, int d, int N, int step0, int K, int phased, int cartesian, int sw,
+static void launch_spt(dim3 grid, hipStream_t st, int d, int N, int step0, int nsl, int K, int phased, int cartesian,
+                       int sw,
                        const float2* X, long long xsb, const float2* LH, long long lsb, const int* spc,
                        const double2* spv, const double* g, const int* codes, const double* phi, const int* n_steps,
                        double* partial, const double* h, int n_drift, double hdt) {
-    hipLaunchKernelGGL(sparse_trace_kernel<WP>, grid, dim3(256), 0, st, d, N, step0, K, phased, cartesian, sw, X, xsb,
-                       LH, lsb, spc, spv, g, codes, phi, n_steps, partial, h, n_drift, hdt);
+    hipLaunchKernelGGL(sparse_trace_kernel<WP>, grid, dim3(256), 0, st, d, N, step0, nsl, K, phased, cartesian, sw, X,
+                       xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial, h, n_drift, hdt);
 }
 
 hipError_t sparse_traces(int d, int B, int N, int step0, int steps, int K, int phased, int cartesian, int sw,
@@ -1123,13 +1291,34 @@ hipError_t sparse_traces(int d, int B, int N, int step0, int steps, int K, int p
                          const int* n_steps, double* partial, double* tr, hipStream_t st, const double* h,
                          int n_drift, double hdt) {
     if (sw < 1 || sw > SPAT_WMAX || d % SPT_RPB != 0) return hipErrorInvalidValue;
-    const dim3 grid(d / SPT_RPB, steps, B);
     const int wp = (sw + 3) / 4 * 4;
+    if (d <= SPS_DMAX && d % (64 * SPS_RPT) == 0 && wp <= 12 && B <= 65535) {
+        // partial holds ybuf: [B][steps][d][SPS_NE] complex FP64
+        double2* ybuf = reinterpret_cast<double2*>(partial);
+        const dim3 sgrid(steps, B);
+#define REDO_SPS(W)                                                                                                   \
+    hipLaunchKernelGGL(sparse_y_kernel<W>, sgrid, dim3(d / SPS_RPT), 0, st, d, N, step0, steps, sw, X, xsb, LH, lsb, \
+                       spc, n_steps, ybuf)
+        switch (wp) {   // 16 slots would not fit the registers: the row-block kernel below
+            case 4: REDO_SPS(4); break;
+            case 8: REDO_SPS(8); break;
+            default: REDO_SPS(12);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(sparse_ysum_kernel, sgrid, dim3(256), 0, st, d, N, step0, steps, K, phased, cartesian, sw,
+                           ybuf, spc, spv, g, codes, phi, n_steps, tr, h, n_drift, hdt);
+#undef REDO_SPS
+        return hipGetLastError();
+    }
+    const long long padded = (long long)(d / SPT_RPB) * ((steps + SPT_XCD - 1) / SPT_XCD * SPT_XCD);
+    if (padded > 0x7fffffffLL || B > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)padded, B);
     switch (wp) {
-        case 4: launch_spt<4>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial, h, n_drift, hdt); break;
-        case 8: launch_spt<8>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial, h, n_drift, hdt); break;
-        case 12: launch_spt<12>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial, h, n_drift, hdt); break;
-        default: launch_spt<16>(grid, st, d, N, step0, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial, h, n_drift, hdt);
+        case 4: launch_spt<4>(grid, st, d, N, step0, steps, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial, h, n_drift, hdt); break;
+        case 8: launch_spt<8>(grid, st, d, N, step0, steps, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial, h, n_drift, hdt); break;
+        case 12: launch_spt<12>(grid, st, d, N, step0, steps, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial, h, n_drift, hdt); break;
+        default: launch_spt<16>(grid, st, d, N, step0, steps, K, phased, cartesian, sw, X, xsb, LH, lsb, spc, spv, g, codes, phi, n_steps, partial, h, n_drift, hdt);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

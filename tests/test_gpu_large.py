@@ -136,6 +136,26 @@ def test_grape_d128_phased_vs_oracle(prec):
         assert np.linalg.norm(grad[b] - gro) <= GRAD_TOL * np.linalg.norm(gro)
 
 
+def test_grape_d512_phased_ragged_vs_oracle():
+    """d = 512 (9-spin chain: 9 pattern entries per row and the diagonal, 12 slots of the
+    per-step trace kernel), ragged lengths, every state kept."""
+    p = W.nmr_chain(9, 2, 6, 2e-6, 32, 2, 206)
+    p.n_steps = np.array([6, 4], np.int32)
+    p.u[:, ::3] = 0.0
+    t = R().RedoTable.from_problem(p)
+    F, ov, grad = t.grape(torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda(),
+                          n_steps=torch.tensor(p.n_steps), checkpoint_every=1)
+    F, ov, grad = F.cpu().numpy(), ov.cpu().numpy(), grad.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(p.B):
+        Fo, go, gro = O.fidelity_and_gradient(p, b, model="redo", table=tab)
+        nb = int(p.n_steps[b])
+        assert abs(F[b] - Fo) < FID_TOL
+        assert abs(ov[b] - go) < 1e-5
+        assert np.linalg.norm(grad[b, :nb] - gro) <= GRAD_TOL * np.linalg.norm(gro)
+        assert np.all(grad[b, nb:] == 0)
+
+
 def test_grape_d128_signed_ragged_vs_oracle():
     p = W.ising_freezing(n=7, B=2, N=25)
     p.n_steps = np.array([25, 14], np.int32)
