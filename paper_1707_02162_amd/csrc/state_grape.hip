@@ -36,6 +36,7 @@ struct MvDesc {
 // forward chain and the backward scan: y < B takes descs0[y], y >= B descs1[y - B].
 constexpr int MV_R = 16;
 constexpr int MV_NT = 1024;
+static_assert(MV_NT / 64 == MV_R && 64 % MV_R == 0, "one wave per row, column groups of the adjoint");
 constexpr int MV_U = 16;    // loads per thread in flight
 
 // the factors come through descriptors, which the compiler cannot place in an address
@@ -79,9 +80,9 @@ __global__ __launch_bounds__(MV_NT) void matvec_kernel(int d, const MvDesc* __re
     __syncthreads();
     float2 acc = make_float2(0.f, 0.f);
     if (m.adj) {
-        // y_r = sum_c conj(F[c][r]) x_c: lanes over 16 rows (one 128-byte segment of row c
-        // of F) and 4 column groups, waves over 16 more; column c = 64 j + group
-        const int rl = lane & 15, cg = (lane >> 4) + 4 * wv, r = r0 + rl;
+        // y_r = sum_c conj(F[c][r]) x_c: lanes over the MV_R rows (one segment of row c of F)
+        // and 64 / MV_R column groups, waves over the others (64 in all); column c = 64 j + group
+        const int rl = lane % MV_R, cg = lane / MV_R + (64 / MV_R) * wv, r = r0 + rl;
         const bool ok = r < d;
         for (int cb = 0; cb < d; cb += 64 * MV_U) {
             float2 f[MV_U];
@@ -96,10 +97,11 @@ __global__ __launch_bounds__(MV_NT) void matvec_kernel(int d, const MvDesc* __re
                 if (c < d) cfma(acc, cconj(f[j]), xs[c]);
             }
         }
-        acc.x += __shfl_xor(acc.x, 16);
-        acc.y += __shfl_xor(acc.y, 16);
-        acc.x += __shfl_xor(acc.x, 32);
-        acc.y += __shfl_xor(acc.y, 32);
+#pragma unroll
+        for (int o = MV_R; o < 64; o <<= 1) {
+            acc.x += __shfl_xor(acc.x, o);
+            acc.y += __shfl_xor(acc.y, o);
+        }
         if (lane < MV_R) red[wv][lane] = acc;
     } else {
         // y_r = sum_c F[r][c] x_c: wave w takes row r0 + w, lanes over columns c = lane + 64 j
