@@ -208,6 +208,31 @@ def test_grape_d128_dense_generator_full_storage_vs_oracle():
         assert np.linalg.norm(grad[b] - gro) <= GRAD_TOL * np.linalg.norm(gro)
 
 
+@pytest.mark.parametrize("width", [1, 13])
+def test_grape_d128_pattern_widths_vs_oracle(width):
+    """Generators with 1 entry per row (spin 0 alone: the per-step trace kernel with 4
+    slots) and with 13 (collective X plus nearest-neighbour XX terms: 16 slots, the
+    row-block trace kernel), every state kept."""
+    n, d = 7, 128
+    S = W.collective(n, [0], "x")
+    if width == 13:
+        S = W.collective(n, range(n), "x")
+        for q in range(n - 1):
+            S = S + W.collective(n, [q], "x") @ W.collective(n, [q + 1], "x")
+    assert int((np.abs(S) > 0).sum(1).max()) == width
+    p = generic_problem(d, 2, 10, 216 + width)
+    p.S = S[None]
+    p.U_target = np.stack([W.haar_unitary(d, W.rng(216, 3, b)) for b in range(2)])
+    t = R().RedoTable.from_problem(p)
+    F, ov, grad = t.grape(torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda(), checkpoint_every=1)
+    F, grad = F.cpu().numpy(), grad.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(p.B):
+        Fo, go, gro = O.fidelity_and_gradient(p, b, model="redo", table=tab)
+        assert abs(F[b] - Fo) < FID_TOL
+        assert np.linalg.norm(grad[b] - gro) <= GRAD_TOL * np.linalg.norm(gro)
+
+
 # ---------------------------------------------------------------- full size
 def test_ising_d1024_special_cases_full_dimension():
     """At d = 1024: without coupling the magnetisation stays 1 for any noisy
