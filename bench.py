@@ -95,22 +95,27 @@ def bench_freezing(args, redo, W, torch):
     u = torch.tensor(p.u, device="cuda")
     cols, vals = W.observable_ell(p.M)
     obs = (torch.tensor(cols, device="cuda"), torch.tensor(vals, device="cuda", dtype=torch.complex64))
+    # M = sum_q I_x^(q) is diagonal in the Walsh basis: the states are carried as W = X H / sqrt(d)
+    spec = redo.walsh_spectrum(cols, vals)
+    spec = None if spec is None else torch.tensor(spec, device="cuda")
     U = torch.empty((B, p.d, p.d), dtype=torch.complex64, device="cuda")
     mag = torch.empty((B, N), dtype=torch.float64, device="cuda")
 
-    def run(kind, precision, steps):
+    def run(kind, precision, steps, walsh=True):
+        wf = spec if walsh else None
+
         def advance(n0, n1):
             un = u[:, n0:n1].contiguous()
             X0 = None if n0 == 0 else U
             if kind == "redo":
                 _, _, m = table.chain(un, X0=X0, out=U, step_offset=n0, reproject_every=args.reproject,
-                                      observable=obs, precision=precision)
+                                      observable=obs, precision=precision, walsh=wf)
             elif kind == "kron":
                 _, m = table.kron_chain(un, X0=X0, out=U, step_offset=n0, reproject_every=args.reproject,
-                                        observable=obs)
+                                        observable=obs, walsh=wf)
             else:
                 _, m = table.expm_chain(un, X0=X0, out=U, step_offset=n0, reproject_every=args.reproject,
-                                        observable=obs, precision=precision)
+                                        observable=obs, precision=precision, walsh=wf)
             mag[:, n0:n1] = m
 
         for n0 in range(0, Wm, args.chunk):
@@ -123,6 +128,8 @@ def bench_freezing(args, redo, W, torch):
             n1 = min(Wm + steps, n0 + args.chunk)
             advance(n0, n1)
             log(f"[bench] {kind} p{precision} timed steps {n1 - Wm}/{steps}")
+        if wf is not None:
+            redo.walsh_right(U)   # the final states back in the computational basis
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         gemm_ms, launches = redo.profile_read(reset=True)
@@ -151,11 +158,13 @@ def bench_freezing(args, redo, W, torch):
                     mag_last=m[:, -1].copy())
 
     fp32 = run("redo", 1, K)
+    lists = None if args.no_lists else run("redo", 1, K, walsh=False)
     bf = None if args.no_bf16 else run("redo", 2, K)
     g4 = None if args.no_4m else run("redo", 0, K)
     ex = None if args.no_expm else run("expm", 1, args.expm_steps)
     kr = None if args.no_kron else run("kron", 0, K)
-    out = dict(fp32=fp32, bf16x3=bf, f32_4m=g4, expm=ex, kron=kr, table_build_s=t_table, cache_build_s=t_cache)
+    out = dict(fp32=fp32, lists=lists, bf16x3=bf, f32_4m=g4, expm=ex, kron=kr, table_build_s=t_table,
+               cache_build_s=t_cache)
     del table
     return out, p
 
@@ -211,10 +220,11 @@ def bench_next(args, redo, W, torch):
     u = torch.tensor(p.u, device="cuda")
     cols, vals = W.observable_ell(p.M)
     obs = (torch.tensor(cols, device="cuda"), torch.tensor(vals, device="cuda", dtype=torch.complex64))
+    spec = torch.tensor(redo.walsh_spectrum(cols, vals), device="cuda")
     U = torch.empty((B, p.d, p.d), dtype=torch.complex64, device="cuda")
     def advance(n0, n1):
         table.chain(u[:, n0:n1].contiguous(), X0=None if n0 == 0 else U, out=U, step_offset=n0,
-                    reproject_every=args.reproject, observable=obs, precision=1)
+                    reproject_every=args.reproject, observable=obs, precision=1, walsh=spec)
 
     for n0 in range(0, Wm, args.chunk):
         advance(n0, min(Wm, n0 + args.chunk))
@@ -222,6 +232,7 @@ def bench_next(args, redo, W, torch):
     t0 = time.perf_counter()
     for n0 in range(Wm, Wm + K, args.chunk):
         advance(n0, min(Wm + K, n0 + args.chunk))
+    redo.walsh_right(U)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     out["strang"] = {"workload": "headline workload with the Strang splitting V(dt/2) C_n V(dt/2)",
@@ -340,6 +351,8 @@ def main():
     ap.add_argument("--no-grape", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-4m", action="store_true", help="skip the four-product FP32 line")
+    ap.add_argument("--no-lists", action="store_true",
+                    help="skip the line with the two-pass row-list observable (computational basis)")
     ap.add_argument("--no-expm", action="store_true")
     ap.add_argument("--no-kron", action="store_true", help="skip the structure-aware chain on the headline workload")
     ap.add_argument("--no-next", action="store_true", help="skip the Strang and state-GRAPE lines")
@@ -396,7 +409,7 @@ def main():
                           "grape_expm_iters_per_s": None if eg is None else eg["iters_per_s"],
                           "d64_chain": c2, "paper_freezing_sweep_d8": sw}), flush=True)
         return
-    f32, bf, ex, kr, g4 = fr["fp32"], fr["bf16x3"], fr["expm"], fr["kron"], fr["f32_4m"]
+    f32, bf, ex, kr, g4, ls = fr["fp32"], fr["bf16x3"], fr["expm"], fr["kron"], fr["f32_4m"], fr["lists"]
     out = {
         "metric": "propagator steps/s + GRAPE iters/s at d=1024, REDO vs plain expm, same GPU",
         "value": f32["value"],
@@ -413,13 +426,21 @@ def main():
         "config": {"workload": "noisy-drive freezing, 10-qubit Ising chain, d=1024, 4096 realisations, "
                                "REDO b=100 P=2" + (" with every level composed once (process 3)" if args.cache else "") +
                                ", one step = one time segment for all realisations, "
-                               "magnetisation every step, re-projection every 64 steps",
+                               "magnetisation every step, re-projection every 64 steps; states carried in the "
+                               "right Walsh frame (M diagonal there: one-pass magnetisation), back-transformed "
+                               "once at the end inside the timed region",
                    "realisations": args.realisations, "d": 1024, "base": p.base, "digits": p.digits},
         "expm_baseline": None if ex is None else {
             "value": ex["value"], "unit": "propagator steps/s", "ms_per_step": ex["ms_per_step"],
             "steps": args.expm_steps, "method": "per-step exp(-i dt H_n), scaling-and-squaring Taylor "
-                                                 "(Paterson-Stockmeyer), same batched FP32 MFMA GEMM (three real products)"},
+                                                 "(Paterson-Stockmeyer), same batched FP32 MFMA GEMM (three real products), "
+                                                 "same Walsh-frame magnetisation"},
         "speedup_vs_expm": None if ex is None else f32["value"] / ex["value"],
+        "row_list_observable": None if ls is None else {
+            "value": ls["value"], "unit": "propagator steps/s", "ms_per_step": ls["ms_per_step"],
+            "method": "same chain in the computational basis, magnetisation from the row lists in two passes "
+                      "(T = M X written, then a dot pass)",
+            "max_abs_dm_vs_headline_last_step": float(np.abs(ls["mag_last"] - f32["mag_last"]).max())},
         "bf16x3": None if bf is None else {"value": bf["value"], "unit": "propagator steps/s",
                                           "ms_per_step": bf["ms_per_step"],
                                           "achieved_algorithmic_tflops": bf["achieved"],

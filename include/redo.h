@@ -224,6 +224,65 @@ redo_status redo_kron_chain(redo_table table, int32_t quantised, const float* u,
                             void* stream);
 
 /*
+ * The right Walsh frame.  With H the d x d Sylvester-Hadamard matrix,
+ * H_ij = (-1)^popcount(i & j), and Hn = H / sqrt(d) (orthogonal, Hn Hn = I), an
+ * observable whose entries depend only on i XOR j, M_ij = f(i XOR j) with f real
+ * (a collective transverse magnetisation sum_q I_x^(q), Sec. IV, is one), is
+ * M = Hn diag(D) Hn with D = H f.  A chain state X carried as W = X Hn evolves by
+ * the same left products, W_n = U_n W_{n-1}, the Newton-Schulz step commutes
+ * with the rotation, and the observable of redo_chain_propagator becomes
+ *     Tr(X M X^dag M) = sum_j D_j w_j^dag M w_j   (w_j: column j of W),
+ * one pass over W with no intermediate product M X.
+ *
+ * redo_observable_walsh: host-side analysis of the row lists (host pointers,
+ * layout as obs_cols/obs_vals of redo_chain_propagator, duplicates summed):
+ * REDO_OK and spectrum[d] = D (host, FP64) when M_ij = f(i XOR j) holds for
+ * every entry with f real; REDO_ERR_UNSUPPORTED when it does not;
+ * REDO_ERR_ARG for d not a power of two, NULL pointers or columns out of range.
+ * No GPU work.
+ */
+redo_status redo_observable_walsh(int32_t d, const int32_t* cols, const float* vals, int32_t width,
+                                  double* spectrum);
+
+/*
+ * In place X_b <- X_b Hn for B matrices c64 [d][d] spaced stride complex
+ * entries apart (stride >= d*d) on the device: into the right Walsh frame and,
+ * applied again, back (Hn Hn = I).  d a power of two in 128 .. 4096
+ * (REDO_ERR_ARG otherwise).  FP32, log2(d) butterfly levels per row.
+ */
+redo_status redo_walsh_right(int32_t d, int32_t B, float* X, int64_t stride, void* stream);
+
+/*
+ * redo_chain_propagator, redo_kron_chain and redo_expm_chain (the comparison
+ * point) with the state in the right Walsh frame: W0 (or H/sqrt(d) when NULL, the identity in that frame) and W_total
+ * are W = X Hn (convert with redo_walsh_right), and the observable rows
+ * (device, as obs_cols/obs_vals there) come with spectrum (device, double [d],
+ * from redo_observable_walsh for the same M) for the one-pass evaluation;
+ * obs_out as there.  spectrum may be NULL when obs_out is NULL.  Needs d a
+ * power of two in 128 .. 2048 (REDO_ERR_UNSUPPORTED otherwise); no X_prefix.
+ * Same workspace as the corresponding chain (REDO_OP_CHAIN, REDO_OP_KRON_CHAIN,
+ * REDO_OP_EXPM_CHAIN).
+ */
+redo_status redo_chain_propagator_walsh(redo_table table, int32_t precision, const float* u,
+                                        const int32_t* n_steps, int32_t B, int32_t N_max,
+                                        int32_t step_offset, int32_t reproject_every, const float* W0,
+                                        float* W_total, const int32_t* obs_cols, const float* obs_vals,
+                                        int32_t obs_width, const double* spectrum, double* obs_out,
+                                        void* workspace, size_t workspace_bytes, void* stream);
+redo_status redo_kron_chain_walsh(redo_table table, int32_t quantised, const float* u,
+                                  const int32_t* n_steps, int32_t B, int32_t N_max, int32_t step_offset,
+                                  int32_t reproject_every, const float* W0, float* W_total,
+                                  const int32_t* obs_cols, const float* obs_vals, int32_t obs_width,
+                                  const double* spectrum, double* obs_out, void* workspace,
+                                  size_t workspace_bytes, void* stream);
+redo_status redo_expm_chain_walsh(redo_table table, int32_t precision, const float* u,
+                                  const int32_t* n_steps, int32_t B, int32_t N_max, int32_t step_offset,
+                                  int32_t reproject_every, const float* W0, float* W_total,
+                                  const int32_t* obs_cols, const float* obs_vals, int32_t obs_width,
+                                  const double* spectrum, double* obs_out, void* workspace,
+                                  size_t workspace_bytes, void* stream);
+
+/*
  * Unitary fidelity (Sec. III): g_b = Tr(U_f^dag U) / Tr(U_f^dag U_f),
  * F_b = |g_b|^2, accumulated in FP64.
  *   U_target, U  c64 [B][d][d];  overlap c128 [B] or NULL;  fidelity double [B] or NULL

@@ -683,6 +683,116 @@ redo_status redo_kron_chain(redo_table t, int32_t quantised, const float* u, con
                       obs_vals, obs_width, obs_out, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
 }
 
+redo_status redo_observable_walsh(int32_t d, const int32_t* cols, const float* vals, int32_t width,
+                                  double* spectrum) {
+    g_last_error.clear();
+    if (d < 2 || (d & (d - 1)) != 0) return fail(REDO_ERR_ARG, "d must be a power of two >= 2");
+    if (!cols || !vals || !spectrum || width < 1)
+        return fail(REDO_ERR_ARG, "cols, vals and spectrum must not be NULL, width >= 1");
+    // the nonzeros of each row, duplicates summed, sorted by column
+    struct Entry {
+        int col;
+        double re, im;
+    };
+    auto row_entries = [&](int i, std::vector<Entry>& out) -> bool {
+        out.clear();
+        for (int e = 0; e < width; ++e) {
+            const int c = cols[(size_t)i * width + e];
+            if (c < 0 || c >= d) return false;
+            out.push_back({c, (double)vals[2 * ((size_t)i * width + e)], (double)vals[2 * ((size_t)i * width + e) + 1]});
+        }
+        std::sort(out.begin(), out.end(), [](const Entry& x, const Entry& y) { return x.col < y.col; });
+        std::vector<Entry> m;
+        for (const Entry& x : out) {
+            if (!m.empty() && m.back().col == x.col) {
+                m.back().re += x.re;
+                m.back().im += x.im;
+            } else {
+                m.push_back(x);
+            }
+        }
+        out.clear();
+        for (const Entry& x : m)
+            if (x.re != 0.0 || x.im != 0.0) out.push_back(x);
+        return true;
+    };
+    std::vector<Entry> f0, ri;
+    if (!row_entries(0, f0)) return fail(REDO_ERR_ARG, "a column index is outside 0 .. d-1");
+    for (const Entry& x : f0)
+        if (x.im != 0.0) return fail(REDO_ERR_UNSUPPORTED, "the observable is not a real function of i XOR j");
+    std::vector<double> fv(d, 0.0);
+    for (const Entry& x : f0) fv[x.col] = x.re;
+    for (int i = 1; i < d; ++i) {
+        if (!row_entries(i, ri)) return fail(REDO_ERR_ARG, "a column index is outside 0 .. d-1");
+        if (ri.size() != f0.size())
+            return fail(REDO_ERR_UNSUPPORTED, "the observable is not a real function of i XOR j");
+        for (const Entry& x : ri)
+            if (x.im != 0.0 || x.re != fv[x.col ^ i] || fv[x.col ^ i] == 0.0)
+                return fail(REDO_ERR_UNSUPPORTED, "the observable is not a real function of i XOR j");
+    }
+    // spectrum = H f (Sylvester order), butterflies in FP64
+    for (int h = 1; h < d; h <<= 1)
+        for (int i = 0; i < d; i += 2 * h)
+            for (int j = i; j < i + h; ++j) {
+                const double a = fv[j], b = fv[j + h];
+                fv[j] = a + b;
+                fv[j + h] = a - b;
+            }
+    std::copy(fv.begin(), fv.end(), spectrum);
+    return REDO_OK;
+}
+
+redo_status redo_walsh_right(int32_t d, int32_t B, float* X, int64_t stride, void* stream) {
+    g_last_error.clear();
+    if (d < 128 || d > 4096 || (d & (d - 1)) != 0) return fail(REDO_ERR_ARG, "d must be a power of two in 128 .. 4096");
+    if (B < 1 || !X || stride < (int64_t)d * d) return fail(REDO_ERR_ARG, "B >= 1, X not NULL, stride >= d*d");
+    REDO_HIP(walsh_right(d, B, reinterpret_cast<float2*>(X), (long long)stride, static_cast<hipStream_t>(stream)));
+    return REDO_OK;
+}
+
+redo_status redo_chain_propagator_walsh(redo_table t, int32_t precision, const float* u, const int32_t* n_steps,
+                                        int32_t B, int32_t N_max, int32_t step_offset, int32_t reproject_every,
+                                        const float* W0, float* W_total, const int32_t* obs_cols,
+                                        const float* obs_vals, int32_t obs_width, const double* spectrum,
+                                        double* obs_out, void* workspace, size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    if (B < 1 || N_max < 1) return fail(REDO_ERR_ARG, "B and N_max must be >= 1");
+    if (!u || !W_total) return fail(REDO_ERR_ARG, "u and W_total must not be NULL");
+    if (step_offset < 0 || reproject_every < 0) return fail(REDO_ERR_ARG, "step_offset, reproject_every must be >= 0");
+    if (precision < REDO_PREC_F32 || precision > REDO_PREC_BF16X3) return fail(REDO_ERR_ARG, "unknown precision");
+    if (obs_out && (!obs_cols || !obs_vals || obs_width < 1 || !spectrum))
+        return fail(REDO_ERR_ARG, "obs_out needs obs_cols, obs_vals, obs_width >= 1 and spectrum");
+    if (!walsh_dim(t->desc.d)) return fail(REDO_ERR_UNSUPPORTED, "the Walsh frame needs d = 2^n, 128 .. 2048");
+    if (obs_out && obs_width > 16) return fail(REDO_ERR_UNSUPPORTED, "observables with more than 16 entries per row");
+    return large_chain(t, precision, u, n_steps, B, N_max, step_offset, reproject_every, W0, W_total, obs_cols,
+                       obs_vals, obs_width, obs_out, workspace, workspace_bytes, static_cast<hipStream_t>(stream),
+                       true, spectrum);
+}
+
+redo_status redo_kron_chain_walsh(redo_table t, int32_t quantised, const float* u, const int32_t* n_steps, int32_t B,
+                                  int32_t N_max, int32_t step_offset, int32_t reproject_every, const float* W0,
+                                  float* W_total, const int32_t* obs_cols, const float* obs_vals, int32_t obs_width,
+                                  const double* spectrum, double* obs_out, void* workspace, size_t workspace_bytes,
+                                  void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    if (B < 1 || N_max < 1) return fail(REDO_ERR_ARG, "B and N_max must be >= 1");
+    if (!u || !W_total) return fail(REDO_ERR_ARG, "u and W_total must not be NULL");
+    if (quantised != 0 && quantised != 1) return fail(REDO_ERR_ARG, "quantised must be 0 or 1");
+    if (step_offset < 0 || reproject_every < 0) return fail(REDO_ERR_ARG, "step_offset, reproject_every must be >= 0");
+    if (obs_out && (!obs_cols || !obs_vals || obs_width < 1 || !spectrum))
+        return fail(REDO_ERR_ARG, "obs_out needs obs_cols, obs_vals, obs_width >= 1 and spectrum");
+    if (t->kron_n == 0) return fail(REDO_ERR_UNSUPPORTED, "the generators are not sums of single-spin terms");
+    if (!kron_supported(t))
+        return fail(REDO_ERR_UNSUPPORTED, "the structure-aware chain needs a diagonal drift and d = 128 .. 4096");
+    if (!walsh_dim(t->desc.d)) return fail(REDO_ERR_UNSUPPORTED, "the Walsh frame needs d = 2^n, 128 .. 2048");
+    if (obs_out && obs_width > 16) return fail(REDO_ERR_UNSUPPORTED, "observables with more than 16 entries per row");
+    return kron_chain(t, quantised, u, n_steps, B, N_max, step_offset, reproject_every, W0, W_total, obs_cols,
+                      obs_vals, obs_width, obs_out, workspace, workspace_bytes, static_cast<hipStream_t>(stream),
+                      true, spectrum);
+}
+
 redo_status redo_unitary_fidelity(int32_t d, int32_t B, const float* U_target, const float* U, double* overlap,
                                   double* fidelity, void* stream) {
     g_last_error.clear();
@@ -767,6 +877,25 @@ redo_status redo_expm_chain(redo_table t, int32_t precision, const float* u, con
     if (obs_out && obs_width > 16) return fail(REDO_ERR_UNSUPPORTED, "observables with more than 16 entries per row");
     return expm_chain(t, precision, u, n_steps, B, N_max, step_offset, reproject_every, X0, U_total, obs_cols, obs_vals,
                       obs_width, obs_out, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+redo_status redo_expm_chain_walsh(redo_table t, int32_t precision, const float* u, const int32_t* n_steps, int32_t B,
+                                  int32_t N_max, int32_t step_offset, int32_t reproject_every, const float* W0,
+                                  float* W_total, const int32_t* obs_cols, const float* obs_vals, int32_t obs_width,
+                                  const double* spectrum, double* obs_out, void* workspace, size_t workspace_bytes,
+                                  void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    if (B < 1 || N_max < 1) return fail(REDO_ERR_ARG, "B and N_max must be >= 1");
+    if (!u || !W_total) return fail(REDO_ERR_ARG, "u and W_total must not be NULL");
+    if (step_offset < 0 || reproject_every < 0) return fail(REDO_ERR_ARG, "step_offset, reproject_every must be >= 0");
+    if (precision < REDO_PREC_F32 || precision > REDO_PREC_BF16X3) return fail(REDO_ERR_ARG, "unknown precision");
+    if (obs_out && (!obs_cols || !obs_vals || obs_width < 1 || !spectrum))
+        return fail(REDO_ERR_ARG, "obs_out needs obs_cols, obs_vals, obs_width >= 1 and spectrum");
+    if (!walsh_dim(t->desc.d)) return fail(REDO_ERR_UNSUPPORTED, "the Walsh frame needs d = 2^n, 128 .. 2048");
+    if (obs_out && obs_width > 16) return fail(REDO_ERR_UNSUPPORTED, "observables with more than 16 entries per row");
+    return expm_chain(t, precision, u, n_steps, B, N_max, step_offset, reproject_every, W0, W_total, obs_cols, obs_vals,
+                      obs_width, obs_out, workspace, workspace_bytes, static_cast<hipStream_t>(stream), true, spectrum);
 }
 
 redo_status redo_expm_grape_fidelity_grad(redo_table t, int32_t precision, const float* u, const int32_t* n_steps,

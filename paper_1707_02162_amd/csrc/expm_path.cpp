@@ -191,7 +191,8 @@ redo_status expm_compose_pairs(const redo_table_s* t, int precision, long long I
 
 redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N, int step_offset,
                        int reproject_every, const float* X0, float* U_total, const int* obs_cols, const float* obs_vals,
-                       int obs_width, double* obs_out, void* workspace, size_t workspace_bytes, hipStream_t st) {
+                       int obs_width, double* obs_out, void* workspace, size_t workspace_bytes, hipStream_t st,
+                       bool walsh_frame, const double* walsh) {
     if (precision == REDO_PREC_BF16X3) return fail(REDO_ERR_UNSUPPORTED, "the exponential baseline runs in FP32");
     const size_t need = expm_chain_workspace_bytes(t, B, N);
     if (!workspace || workspace_bytes < need)
@@ -223,7 +224,7 @@ redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int
     const int prec = precision == REDO_PREC_F32_3M ? 1 : 0;
     float2* X[2] = {reinterpret_cast<float2*>(U_total), W1};
     if (!X0)
-        REDO_HIP(fill_identity(d, B, X[0], nn, st));
+        REDO_HIP(walsh_frame ? walsh_fill(d, B, X[0], nn, st) : fill_identity(d, B, X[0], nn, st));
     else if (X0 != U_total)
         REDO_HIP(hipMemcpyAsync(X[0], X0, mat * B, hipMemcpyDeviceToDevice, st));
     REDO_HIP(fill_int(loc, B, 0, st));
@@ -247,8 +248,12 @@ redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int
             }
         }
         if (obs_out)
-            REDO_HIP(observable(d, B, X[0], X[1], loc, nn, obs_cols, reinterpret_cast<const float2*>(obs_vals), obs_width,
-                                n_steps, n, obs_partial, obs_out + n, N, obsT, OBS_CHUNK, st));
+            REDO_HIP(walsh_frame ? observable_walsh(d, B, X[0], X[1], loc, nn, obs_cols,
+                                                    reinterpret_cast<const float2*>(obs_vals), obs_width, walsh,
+                                                    n_steps, n, obs_partial, obs_out + n, N, st)
+                                 : observable(d, B, X[0], X[1], loc, nn, obs_cols,
+                                              reinterpret_cast<const float2*>(obs_vals), obs_width, n_steps, n,
+                                              obs_partial, obs_out + n, N, obsT, OBS_CHUNK, st));
     }
     REDO_HIP(gather_back(d, B, X[0], X[1], nn, loc, st));
     return REDO_OK;

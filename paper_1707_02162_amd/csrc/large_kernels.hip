@@ -4,6 +4,7 @@
 // observable of Sec. IV, and the traces and gradient assembly of the GRAPE
 // adjoint (Sec. III).  All traces accumulate in FP64.
 #include <algorithm>
+#include <cmath>
 
 #include "large_path.h"
 
@@ -243,6 +244,7 @@ __global__ void grape_pair_descs_kernel(GemmDesc* descs, int N, int B, const flo
 // instances) this pair beat a single pass that gathers the rows of M X from
 // L2 instead of writing T (26 vs 16 ms per step of 1024 instances).
 constexpr int OBS_WMAX = 16;
+constexpr int WALSH_DMAX = 2048;   // the strip of 8 columns in LDS: 128 KiB
 inline int pow2_floor(int x) {
     int p = 1;
     while (p * 2 <= x) p *= 2;
@@ -538,6 +540,148 @@ __global__ __launch_bounds__(NT, NT / 128) void observable_dot_kernel(int d, int
         __syncthreads();
     }
     if (tid == 0) partial[(long long)b * nrb + rb] = red[0];
+}
+
+// The right Walsh frame (observables M with M_ij = f(i XOR j)): with H the d x d
+// Sylvester-Hadamard matrix, H_ij = (-1)^popcount(i & j), and Hn = H / sqrt(d) (orthogonal,
+// Hn Hn = I), such an M is Hn D Hn with D = H f real and diagonal.  A state X is carried as
+// W = X Hn: the chain's products act from the left and the Newton-Schulz re-projection
+// commutes with the rotation, so both run on W unchanged, and
+//     Tr(X M X^dag M) = Tr(W D W^dag M) = sum_j D_j w_j^dag M w_j
+// over the columns w_j of W: one pass over W with no intermediate M X.
+
+// W_0 = Hn: the identity in the right Walsh frame
+__global__ void walsh_fill_kernel(long long nn, int d, int B, float2* X, long long stride, float s) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn * B;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long b = e / nn, ij = e % nn;
+        const int i = (int)(ij / d), j = (int)(ij % d);
+        X[b * stride + ij] = make_float2((__popc(i & j) & 1) ? -s : s, 0.f);
+    }
+}
+
+// In place X <- X Hn for a batch of d x d matrices (its own inverse), one wave per row:
+// lane l holds the E = d / 64 consecutive entries l E .. l E + E - 1; the butterflies of
+// the low log2(E) index bits run in registers, those of the six lane bits through xor
+// shuffles.  rows = B d.
+template <int E>
+__global__ __launch_bounds__(256) void walsh_right_kernel(int d, long long rows, float2* X, long long stride,
+                                                          float s) {
+    const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= rows) return;   // a whole wave
+    const int lane = threadIdx.x & 63;
+    const long long b = row / d, i = row % d;
+    float4* p = reinterpret_cast<float4*>(X + b * stride + i * d + (long long)lane * E);
+    float2 v[E];
+#pragma unroll
+    for (int u = 0; u < E / 2; ++u) {
+        const float4 q = p[u];
+        v[2 * u] = make_float2(q.x, q.y);
+        v[2 * u + 1] = make_float2(q.z, q.w);
+    }
+#pragma unroll
+    for (int h = 1; h < E; h <<= 1)
+#pragma unroll
+        for (int k = 0; k < E; ++k)
+            if (!(k & h)) {
+                const float2 a = v[k], c = v[k + h];
+                v[k] = make_float2(a.x + c.x, a.y + c.y);
+                v[k + h] = make_float2(a.x - c.x, a.y - c.y);
+            }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const bool upper = (lane & m) != 0;
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const float ox = __shfl_xor(v[k].x, m), oy = __shfl_xor(v[k].y, m);
+            v[k] = upper ? make_float2(ox - v[k].x, oy - v[k].y) : make_float2(v[k].x + ox, v[k].y + oy);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < E / 2; ++u)
+        p[u] = make_float4(s * v[2 * u].x, s * v[2 * u].y, s * v[2 * u + 1].x, s * v[2 * u + 1].y);
+}
+
+// The observable in the right Walsh frame, one pass: the 8-column strip of W in LDS (as
+// observable_mx8_kernel), each lane forms (M W)_aj for its rows a and columns j from the
+// row lists and adds D_j Re(conj(W_aj) (M W)_aj) (FP32 within a row, FP64 across rows);
+// the workgroup's sum goes to partial[b][strip].
+template <int WP, int NT, int LPR>
+__global__ __launch_bounds__(NT, NT / 128) void observable_walsh_kernel(int d, int b0, const float2* __restrict__ X0,
+                                                                        const float2* __restrict__ X1, const int* loc,
+                                                                        long long xstride,
+                                                                        const int* __restrict__ cols,
+                                                                        const float2* __restrict__ vals,
+                                                                        const double* __restrict__ spec,
+                                                                        const int* n_steps, int step,
+                                                                        double* partial) {
+    constexpr int SW = 8, CPL = SW / LPR, NCH = CPL / 2, RPP = NT / LPR;
+    extern __shared__ float2 strip[];   // [d][8], 16-byte chunks swizzled (mx8_off)
+    __shared__ double red[NT];
+    const int nstrip = d / SW;
+    const long long bid = xcd_local(blockIdx.x, gridDim.x);
+    const int i = (int)(bid / nstrip), sidx = (int)(bid % nstrip);
+    const int b = b0 + i;
+    if (n_steps && step >= n_steps[b]) return;      // uniform over the workgroup
+    const float2* Xb = ((loc && loc[b]) ? X1 : X0) + (long long)b * xstride;
+    const int c0 = sidx * SW;
+    const int tid = threadIdx.x;
+    const int n = d * SW;
+    for (int base = 0; base < n; base += NT * 16) {
+        float2 r[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = min(base + u * NT + tid, n - 1);
+            r[u] = Xb[(long long)(e / SW) * d + c0 + e % SW];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e = base + u * NT + tid;
+            if (e < n) strip[mx8_off(e / SW, e % SW)] = r[u];
+        }
+    }
+    __syncthreads();
+    const float4* strip4 = reinterpret_cast<const float4*>(strip);
+    const int lr = tid % LPR;
+    float dj[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) dj[u] = (float)spec[c0 + lr * CPL + u];
+    double sum = 0.0;
+    for (int a = tid / LPR; a < d; a += RPP) {
+        int cc[WP];
+        float2 cv[WP];
+        obs_list<WP>(cols, vals, a, cc, cv);
+        float2 acc[CPL];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) acc[u] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int t = 0; t < WP; ++t) {
+#pragma unroll
+            for (int j = 0; j < NCH; ++j) {
+                const int ch = lr * NCH + j;
+                const float4 x = strip4[cc[t] * 4 + ((ch ^ (cc[t] >> 2)) & 3)];
+                cfma(acc[2 * j], cv[t], make_float2(x.x, x.y));
+                cfma(acc[2 * j + 1], cv[t], make_float2(x.z, x.w));
+            }
+            asm volatile("" ::: "memory");   // one list entry's gathers at a time (register pressure)
+        }
+        float row = 0.f;
+#pragma unroll
+        for (int j = 0; j < NCH; ++j) {
+            const int ch = lr * NCH + j;
+            const float4 wv = strip4[a * 4 + ((ch ^ (a >> 2)) & 3)];
+            row += dj[2 * j] * (wv.x * acc[2 * j].x + wv.y * acc[2 * j].y) +
+                   dj[2 * j + 1] * (wv.z * acc[2 * j + 1].x + wv.w * acc[2 * j + 1].y);
+        }
+        sum += (double)row;
+    }
+    red[tid] = sum;
+    __syncthreads();
+    for (int st = NT / 2; st > 0; st >>= 1) {
+        if (tid < st) red[tid] += red[tid + st];
+        __syncthreads();
+    }
+    if (tid == 0) partial[(long long)b * nstrip + sidx] = red[0];
 }
 
 __global__ void observable_final_kernel(int nparts, const double* partial, const float2* vals, int nvals,
@@ -1236,6 +1380,77 @@ hipError_t observable(int d, int B, const float2* X0, const float2* X1, const in
     }
     hipLaunchKernelGGL(observable_final_kernel, dim3(B), dim3(256), 0, st, d / obs_rows(d), partial, vals, d * w,
                        n_steps, step, out, out_stride);
+    return hipGetLastError();
+}
+
+bool walsh_dim(int d) { return d >= 128 && d <= WALSH_DMAX && (d & (d - 1)) == 0; }
+
+hipError_t walsh_fill(int d, int B, float2* X, long long stride, hipStream_t st) {
+    const long long nn = (long long)d * d;
+    const long long blocks = std::min<long long>((nn * B + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(walsh_fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st, nn, d, B, X, stride,
+                       (float)(1.0 / std::sqrt((double)d)));
+    return hipGetLastError();
+}
+
+hipError_t walsh_right(int d, int B, float2* X, long long stride, hipStream_t st) {
+    if (d < 128 || d > 4096 || (d & (d - 1)) != 0) return hipErrorInvalidValue;
+    const long long rows = (long long)B * d;
+    const dim3 grid((unsigned)((rows + 3) / 4));
+    const float s = (float)(1.0 / std::sqrt((double)d));
+    switch (d / 64) {
+        case 2: hipLaunchKernelGGL(walsh_right_kernel<2>, grid, dim3(256), 0, st, d, rows, X, stride, s); break;
+        case 4: hipLaunchKernelGGL(walsh_right_kernel<4>, grid, dim3(256), 0, st, d, rows, X, stride, s); break;
+        case 8: hipLaunchKernelGGL(walsh_right_kernel<8>, grid, dim3(256), 0, st, d, rows, X, stride, s); break;
+        case 16: hipLaunchKernelGGL(walsh_right_kernel<16>, grid, dim3(256), 0, st, d, rows, X, stride, s); break;
+        case 32: hipLaunchKernelGGL(walsh_right_kernel<32>, grid, dim3(256), 0, st, d, rows, X, stride, s); break;
+        default: hipLaunchKernelGGL(walsh_right_kernel<64>, grid, dim3(256), 0, st, d, rows, X, stride, s);
+    }
+    return hipGetLastError();
+}
+
+template <int WP, int LPR>
+static hipError_t launch_walsh_obs(int d, int B, const float2* X0, const float2* X1, const int* loc,
+                                   long long xstride, const int* cols, const float2* vals, const double* spec,
+                                   const int* n_steps, int step, double* partial, hipStream_t st) {
+    const void* k = (const void*)observable_walsh_kernel<WP, 256, LPR>;
+    const size_t lds = sizeof(float2) * (size_t)8 * d;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((observable_walsh_kernel<WP, 256, LPR>), dim3((unsigned)((long long)(d / 8) * B)), dim3(256),
+                       lds, st, d, 0, X0, X1, loc, xstride, cols, vals, spec, n_steps, step, partial);
+    return hipGetLastError();
+}
+
+template <int WP>
+static hipError_t walsh_obs(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
+                            const int* cols, const float2* vals, const double* spec, const int* n_steps, int step,
+                            double* partial, hipStream_t st) {
+    return d >= 256 ? launch_walsh_obs<WP, 1>(d, B, X0, X1, loc, xstride, cols, vals, spec, n_steps, step, partial, st)
+                    : launch_walsh_obs<WP, 2>(d, B, X0, X1, loc, xstride, cols, vals, spec, n_steps, step, partial, st);
+}
+
+hipError_t observable_walsh(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
+                            const int* cols, const float2* vals, int w, const double* spec, const int* n_steps,
+                            int step, double* partial, double* out, long long out_stride, hipStream_t st) {
+    if (w < 1 || w > OBS_WMAX || !walsh_dim(d) || (long long)(d / 8) * B > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int wp = (w + 3) / 4 * 4;
+    // packed lists after the partial sums, as observable()
+    const size_t np = (size_t)B * (d / obs_rows(d));
+    int* pc = reinterpret_cast<int*>(partial + np + (np & 1));
+    float2* pv = reinterpret_cast<float2*>(pc + (size_t)d * OBS_WMAX);
+    hipLaunchKernelGGL(obs_pack_kernel, dim3((d * wp + 255) / 256), dim3(256), 0, st, d, w, wp, cols, vals, pc, pv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (wp) {
+        case 4: e = walsh_obs<4>(d, B, X0, X1, loc, xstride, pc, pv, spec, n_steps, step, partial, st); break;
+        case 8: e = walsh_obs<8>(d, B, X0, X1, loc, xstride, pc, pv, spec, n_steps, step, partial, st); break;
+        case 12: e = walsh_obs<12>(d, B, X0, X1, loc, xstride, pc, pv, spec, n_steps, step, partial, st); break;
+        default: e = walsh_obs<16>(d, B, X0, X1, loc, xstride, pc, pv, spec, n_steps, step, partial, st);
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(observable_final_kernel, dim3(B), dim3(256), 0, st, d / 8, partial, vals, d * w, n_steps, step,
+                       out, out_stride);
     return hipGetLastError();
 }
 

@@ -295,7 +295,7 @@ redo_status large_compose(redo_table_s* t, int precision, const float* u, int B,
 redo_status large_chain(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N,
                         int step_offset, int reproject_every, const float* X0, float* U_total, const int* obs_cols,
                         const float* obs_vals, int obs_width, double* obs_out, void* workspace, size_t workspace_bytes,
-                        hipStream_t st) {
+                        hipStream_t st, bool walsh_frame, const double* walsh) {
     redo_status s = check_precision(precision);
     if (s != REDO_OK) return s;
     ChainWS need(t, B, N, nullptr);
@@ -307,7 +307,7 @@ redo_status large_chain(redo_table_s* t, int precision, const float* u, const in
     float2* X[2] = {reinterpret_cast<float2*>(U_total), w.W1};
     REDO_HIP(quantise_all(t, u, B, N, w.codes, w.phi, st));
     if (!X0)
-        REDO_HIP(fill_identity(d, B, X[0], mat, st));
+        REDO_HIP(walsh_frame ? walsh_fill(d, B, X[0], mat, st) : fill_identity(d, B, X[0], mat, st));
     else if (X0 != U_total)
         REDO_HIP(hipMemcpyAsync(X[0], X0, sizeof(float2) * mat * B, hipMemcpyDeviceToDevice, st));
     REDO_HIP(fill_int(w.loc, B, 0, st));
@@ -341,8 +341,12 @@ redo_status large_chain(redo_table_s* t, int precision, const float* u, const in
             }
         }
         if (obs_out)
-            REDO_HIP(observable(d, B, X[0], X[1], w.loc, mat, obs_cols, reinterpret_cast<const float2*>(obs_vals),
-                                obs_width, n_steps, n, w.obs_partial, obs_out + n, N, w.obsT, OBS_CHUNK, st));
+            REDO_HIP(walsh_frame ? observable_walsh(d, B, X[0], X[1], w.loc, mat, obs_cols,
+                                             reinterpret_cast<const float2*>(obs_vals), obs_width, walsh, n_steps,
+                                             n, w.obs_partial, obs_out + n, N, st)
+                           : observable(d, B, X[0], X[1], w.loc, mat, obs_cols,
+                                        reinterpret_cast<const float2*>(obs_vals), obs_width, n_steps, n,
+                                        w.obs_partial, obs_out + n, N, w.obsT, OBS_CHUNK, st));
     }
     REDO_HIP(gather_back(d, B, X[0], X[1], mat, w.loc, st));
     return REDO_OK;

@@ -13,7 +13,7 @@ redo_status large_compose(redo_table_s* t, int precision, const float* u, int B,
 redo_status large_chain(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N_max,
                         int step_offset, int reproject_every, const float* X0, float* U_total, const int* obs_cols,
                         const float* obs_vals, int obs_width, double* obs_out, void* workspace,
-                        size_t workspace_bytes, hipStream_t st);
+                        size_t workspace_bytes, hipStream_t st, bool walsh_frame = false, const double* walsh = nullptr);
 
 // expm = 1: the plain per-step exponential with the first-order GRAPE gradient (the comparison point)
 redo_status large_grape(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N_max,
@@ -28,7 +28,8 @@ redo_status expm_compose_pairs(const redo_table_s* t, int precision, long long I
                                void* ws, hipStream_t st, int* gemms_per_step);
 redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N, int step_offset,
                        int reproject_every, const float* X0, float* U_total, const int* obs_cols, const float* obs_vals,
-                       int obs_width, double* obs_out, void* workspace, size_t workspace_bytes, hipStream_t st);
+                       int obs_width, double* obs_out, void* workspace, size_t workspace_bytes, hipStream_t st,
+                       bool walsh_frame = false, const double* walsh = nullptr);
 
 // ---- kernels of large_kernels.hip
 struct PlanLaunch {
@@ -88,7 +89,10 @@ size_t kron_workspace_bytes(const redo_table_s* t, int B, int N);
 redo_status kron_chain(redo_table_s* t, int quantised, const float* u, const int* n_steps, int B, int N,
                        int step_offset, int reproject_every, const float* X0, float* U_total, const int* obs_cols,
                        const float* obs_vals, int obs_width, double* obs_out, void* workspace, size_t workspace_bytes,
-                       hipStream_t st);
+                       hipStream_t st, bool walsh_frame = false, const double* walsh = nullptr);
+// walsh_frame: the state is carried in the right Walsh frame, W = X H / sqrt(d) (X0 and U_total
+// too; X0 = NULL starts from H / sqrt(d)), and the observable, M = Hn diag(walsh) Hn with walsh
+// its spectrum (device, d doubles), is evaluated there in one pass
 // GRAPE keeps every forward state and backward factor (no recomputation) when
 // that needs at most this much workspace and no checkpoint interval is given
 constexpr size_t GRAPE_FULL_STORAGE_BYTES = size_t(48) << 30;
@@ -106,6 +110,13 @@ int large_grape_checkpoint(const redo_table_s* t, int B, int N, int requested, i
 hipError_t observable(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
                       const int* cols, const float2* vals, int w, const int* n_steps, int step, double* partial,
                       double* out, long long out_stride, float2* T, int chunk, hipStream_t st);
+// the right Walsh frame W = X H / sqrt(d) (observables with M_ij = f(i XOR j))
+bool walsh_dim(int d);   // d = 128 .. 2048, a power of two
+hipError_t walsh_fill(int d, int B, float2* X, long long stride, hipStream_t st);
+hipError_t walsh_right(int d, int B, float2* X, long long stride, hipStream_t st);   // d = 128 .. 4096
+hipError_t observable_walsh(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
+                            const int* cols, const float2* vals, int w, const double* spec, const int* n_steps,
+                            int step, double* partial, double* out, long long out_stride, hipStream_t st);
 hipError_t reproject_descs(GemmDesc* descs, int count, int b0, float2* X0, float2* X1, long long xstride, float2* Z,
                            long long zstride, int* loc, const int* n_steps, int step, int phase, hipStream_t st);
 hipError_t gather_back(int d, int B, float2* X0, const float2* X1, long long xstride, const int* loc, hipStream_t st);

@@ -52,6 +52,14 @@ _SIG = {
     "redo_adam_update": (_I, [ctypes.c_int64, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
     "redo_to_bf16": (_I, [ctypes.c_int64, _P, _P, _P]),
+    "redo_observable_walsh": (_I, [_I, _P, _P, _I, _P]),
+    "redo_walsh_right": (_I, [_I, _I, _P, ctypes.c_int64, _P]),
+    "redo_chain_propagator_walsh": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P, _P, _P,
+                                         ctypes.c_size_t, _P]),
+    "redo_kron_chain_walsh": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P, _P, _P,
+                                   ctypes.c_size_t, _P]),
+    "redo_expm_chain_walsh": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P, _P, _P,
+                                   ctypes.c_size_t, _P]),
     "redo_status_string": (ctypes.c_char_p, [_I]),
     "redo_last_error": (ctypes.c_char_p, []),
 }
@@ -213,8 +221,11 @@ class RedoTable:
         return out
 
     def chain(self, u, n_steps=None, precision: int = PREC_F32, X0=None, reproject_every: int = 0,
-              step_offset: int = 0, prefix: bool = False, observable=None, out: Optional[torch.Tensor] = None):
+              step_offset: int = 0, prefix: bool = False, observable=None, out: Optional[torch.Tensor] = None,
+              walsh=None):
         """Chain of REDO steps.  observable: (cols int32 [d, w], vals complex [d, w]) row lists.
+        walsh: the observable's Walsh spectrum (walsh_spectrum), or True without an observable:
+        the states (X0 and the result) are then W = X H / sqrt(d), the right Walsh frame.
         Returns (U_total, X_prefix or None, obs or None)."""
         ut = self._u(u)
         B, N = ut.shape[:2]
@@ -230,6 +241,14 @@ class RedoTable:
             w = cols.shape[1]
             obs = torch.empty((B, N), dtype=torch.float64, device=self.device)
         ws = self.workspace(OP_CHAIN, B, N)
+        if walsh is not None:
+            if prefix:
+                raise ValueError("prefix states are not provided in the Walsh frame")
+            spec = None if walsh is True else _dev(walsh, torch.float64, self.device)
+            _check(lib().redo_chain_propagator_walsh(self._h, precision, _ptr(ut), _ptr(ns), B, N, step_offset,
+                                                     reproject_every, _ptr(X0t), _ptr(U), _ptr(cols), _ptr(vals), w,
+                                                     _ptr(spec), _ptr(obs), _ptr(ws), ws.numel(), _stream()))
+            return U, None, obs
         _check(lib().redo_chain_propagator(self._h, precision, _ptr(ut), _ptr(ns), B, N, step_offset,
                                            reproject_every, _ptr(X0t), _ptr(U), _ptr(Xp), _ptr(cols), _ptr(vals),
                                            w, _ptr(obs), _ptr(ws), ws.numel(), _stream()))
@@ -243,9 +262,10 @@ class RedoTable:
         return int(n.value)
 
     def kron_chain(self, u, n_steps=None, quantised: bool = True, X0=None, reproject_every: int = 0,
-                   step_offset: int = 0, observable=None, out: Optional[torch.Tensor] = None):
+                   step_offset: int = 0, observable=None, out: Optional[torch.Tensor] = None, walsh=None):
         """Structure-aware chain (spin-factorised control blocks; needs self.spins > 0).
-        quantised: REDO codes (True) or the amplitudes as given.  Returns (U_total, obs or None)."""
+        quantised: REDO codes (True) or the amplitudes as given.  walsh as for chain.
+        Returns (U_total, obs or None)."""
         ut = self._u(u)
         B, N = ut.shape[:2]
         ns = None if n_steps is None else _dev(n_steps, torch.int32, self.device)
@@ -259,6 +279,12 @@ class RedoTable:
             w = cols.shape[1]
             obs = torch.empty((B, N), dtype=torch.float64, device=self.device)
         ws = self.workspace(OP_KRON_CHAIN, B, N)
+        if walsh is not None:
+            spec = None if walsh is True else _dev(walsh, torch.float64, self.device)
+            _check(lib().redo_kron_chain_walsh(self._h, 1 if quantised else 0, _ptr(ut), _ptr(ns), B, N,
+                                               step_offset, reproject_every, _ptr(X0t), _ptr(U), _ptr(cols),
+                                               _ptr(vals), w, _ptr(spec), _ptr(obs), _ptr(ws), ws.numel(), _stream()))
+            return U, obs
         _check(lib().redo_kron_chain(self._h, 1 if quantised else 0, _ptr(ut), _ptr(ns), B, N, step_offset,
                                      reproject_every, _ptr(X0t), _ptr(U), _ptr(cols), _ptr(vals), w, _ptr(obs),
                                      _ptr(ws), ws.numel(), _stream()))
@@ -281,8 +307,9 @@ class RedoTable:
         return F, ov, grad
 
     def expm_chain(self, u, n_steps=None, precision: int = PREC_F32, X0=None, reproject_every: int = 0,
-                   step_offset: int = 0, observable=None, out: Optional[torch.Tensor] = None):
-        """The plain per-step exponential chain (comparison point).  Returns (U_total, obs or None)."""
+                   step_offset: int = 0, observable=None, out: Optional[torch.Tensor] = None, walsh=None):
+        """The plain per-step exponential chain (comparison point); walsh as for chain.
+        Returns (U_total, obs or None)."""
         ut = self._u(u)
         B, N = ut.shape[:2]
         ns = None if n_steps is None else _dev(n_steps, torch.int32, self.device)
@@ -296,6 +323,12 @@ class RedoTable:
             w = cols.shape[1]
             obs = torch.empty((B, N), dtype=torch.float64, device=self.device)
         ws = self.workspace(OP_EXPM_CHAIN, B, N)
+        if walsh is not None:
+            spec = None if walsh is True else _dev(walsh, torch.float64, self.device)
+            _check(lib().redo_expm_chain_walsh(self._h, precision, _ptr(ut), _ptr(ns), B, N, step_offset,
+                                               reproject_every, _ptr(X0t), _ptr(U), _ptr(cols), _ptr(vals), w,
+                                               _ptr(spec), _ptr(obs), _ptr(ws), ws.numel(), _stream()))
+            return U, obs
         _check(lib().redo_expm_chain(self._h, precision, _ptr(ut), _ptr(ns), B, N, step_offset, reproject_every,
                                      _ptr(X0t), _ptr(U), _ptr(cols), _ptr(vals), w, _ptr(obs), _ptr(ws), ws.numel(),
                                      _stream()))
@@ -359,6 +392,32 @@ def unitary_fidelity(U_target: torch.Tensor, U: torch.Tensor):
     F = torch.empty(B, dtype=torch.float64, device=U.device)
     _check(lib().redo_unitary_fidelity(d, B, _ptr(Uf), _ptr(Ut), _ptr(ov), _ptr(F), _stream()))
     return ov, F
+
+
+def walsh_spectrum(cols, vals) -> Optional[np.ndarray]:
+    """Walsh spectrum of an observable given as row lists (host arrays, cols int32 [d, w],
+    vals complex [d, w]): D = H f (float64 [d]) when M_ij = f(i XOR j) with f real, that is
+    M = Hn diag(D) Hn with Hn = H / sqrt(d) the normalised Sylvester-Hadamard matrix; None
+    otherwise.  Host-side analysis in the library, no GPU work."""
+    c = np.ascontiguousarray(np.asarray(cols, dtype=np.int32))
+    v = np.ascontiguousarray(np.asarray(vals, dtype=np.complex64))
+    if c.ndim != 2 or v.shape != c.shape:
+        raise ValueError("cols and vals must both be [d, w]")
+    d, w = c.shape
+    D = np.empty(d, dtype=np.float64)
+    st = lib().redo_observable_walsh(d, c.ctypes.data_as(_P), v.ctypes.data_as(_P), w, D.ctypes.data_as(_P))
+    if st == 6:
+        return None
+    _check(st)
+    return D
+
+
+def walsh_right(X: torch.Tensor) -> torch.Tensor:
+    """In place X <- X Hn for complex64 [B, d, d] on the GPU (its own inverse)."""
+    if X.dtype != torch.complex64 or X.dim() != 3 or X.shape[1] != X.shape[2]:
+        raise ValueError("X must be complex64 [B, d, d]")
+    _check(lib().redo_walsh_right(X.shape[1], X.shape[0], _ptr(X), X.shape[1] * X.shape[2], _stream()))
+    return X
 
 
 class GrapeFidelity(torch.autograd.Function):

@@ -90,3 +90,63 @@ def test_calls_without_table_rejected():
     ms, cnt = ctypes.c_double(-1.0), ctypes.c_int64(-1)
     assert lib.redo_profile_read_kind(1, ctypes.byref(ms), ctypes.byref(cnt), 1) == 0
     assert ms.value == 0.0 and cnt.value == 0
+
+
+def test_walsh_spectrum_collective_x_closed_form():
+    """sum_q I_x^(q) (f = 1/2 at the single-bit offsets): D_k = (n - 2 popcount(k)) / 2."""
+    import numpy as np
+    from paper_1707_02162_amd import redo as R, workloads as W
+    for n in (3, 7, 10):
+        d = 2 ** n
+        D = R.walsh_spectrum(*W.observable_ell(W.collective(n, range(n), "x")))
+        pc = np.array([bin(k).count("1") for k in range(d)])
+        assert np.array_equal(D, 0.5 * (n - 2 * pc))
+
+
+def test_walsh_spectrum_reconstructs_dyadic_observables():
+    """A random real f on a few offsets, M_ij = f(i XOR j) written out, its row lists
+    shuffled and one entry split in two: Hn diag(D) Hn (scipy's Hadamard matrix) is M."""
+    import math
+    import numpy as np
+    from scipy.linalg import hadamard
+    from paper_1707_02162_amd import redo as R
+    rng = np.random.default_rng(41)
+    d = 64
+    f = np.zeros(d)
+    f[rng.choice(d, 6, replace=False)] = rng.normal(size=6)
+    M = np.array([[f[i ^ j] for j in range(d)] for i in range(d)])
+    w = 7
+    cols = np.zeros((d, w), np.int32)
+    vals = np.zeros((d, w), np.complex64)
+    for i in range(d):
+        nz = [j for j in range(d) if M[i, j] != 0]
+        rng.shuffle(nz)
+        cols[i, :len(nz)] = nz
+        vals[i, :len(nz)] = M[i, nz]
+        cols[i, len(nz):] = i          # padding: value 0
+    # one entry as two halves of the same column
+    cols[5, 6] = cols[5, 0]
+    vals[5, 0] = vals[5, 6] = np.float32(M[5, cols[5, 0]]) / 2
+    D = R.walsh_spectrum(cols, vals)
+    Hn = hadamard(d) / math.sqrt(d)
+    assert np.abs(Hn @ np.diag(D) @ Hn - M.astype(np.float32)).max() < 1e-6
+
+
+def test_walsh_spectrum_rejections():
+    """Not a function of i XOR j (collective I_z; one entry missing; a complex f) gives
+    None; bad sizes and column indices are argument errors."""
+    import numpy as np
+    from paper_1707_02162_amd import redo as R, workloads as W
+    n, d = 5, 32
+    assert R.walsh_spectrum(*W.observable_ell(np.diag(W.collective_z_diag(n, range(n))).astype(complex))) is None
+    cols, vals = W.observable_ell(W.collective(n, range(n), "x"))
+    v = np.array(vals).copy()
+    v[3, 0] = 0
+    assert R.walsh_spectrum(cols, v) is None
+    assert R.walsh_spectrum(cols, np.array(vals) * 1j) is None
+    with pytest.raises(R.RedoError, match="power of two"):
+        R.walsh_spectrum(np.zeros((24, 2), np.int32), np.zeros((24, 2), np.complex64))
+    c = np.array(cols).copy()
+    c[2, 1] = d
+    with pytest.raises(R.RedoError, match="outside"):
+        R.walsh_spectrum(c, vals)
