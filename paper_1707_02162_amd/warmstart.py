@@ -1,4 +1,4 @@
-"""Learned warm start for REDO-GRAPE (spec extension; not in the paper).
+"""Learned warm start for REDO-GRAPE (an extension of the method; not in the paper).
 
 A three-layer perceptron (tanh, BF16 weights, FP32 accumulation) maps the
 2 d^2 real entries of a global-phase-free target unitary to the initial
