@@ -169,3 +169,22 @@ def test_walsh_expm_chain_equals_basis_chain_d128():
     Wt, mw = t.expm_chain(u, observable=(cols, vals), reproject_every=8, walsh=D)
     assert nfrob(to_x(Wt), Ub.cpu().numpy().astype(np.complex128)) < FROB_TOL
     assert np.abs(mw.cpu().numpy() - mb.cpu().numpy()).max() < OBS_TOL
+
+
+def test_walsh_chains_d2048_equal_basis_chains():
+    """The largest Walsh-frame size (d = 2048: the 8-column strip is 128 KiB of LDS, eight
+    rows per lane): REDO and structure-aware chains against their computational-basis
+    runs (themselves checked against the oracle at smaller d)."""
+    p = W.ising_freezing(n=11, B=2, N=3)
+    t = R().RedoTable.from_problem(p)
+    cols, vals = W.observable_ell(p.M)
+    D = R().walsh_spectrum(cols, vals)
+    u = torch.tensor(p.u).cuda()
+    Ub, _, mb = t.chain(u, observable=(cols, vals), precision=1)
+    Wt, _, mw = t.chain(u, observable=(cols, vals), precision=1, walsh=D)
+    assert nfrob(to_x(Wt), Ub.cpu().numpy().astype(np.complex128)) < FROB_TOL
+    assert np.abs(mw.cpu().numpy() - mb.cpu().numpy()).max() < OBS_TOL
+    Uk, mk = t.kron_chain(u, observable=(cols, vals))
+    Wk, mkw = t.kron_chain(u, observable=(cols, vals), walsh=D)
+    assert nfrob(to_x(Wk), Uk.cpu().numpy().astype(np.complex128)) < FROB_TOL
+    assert np.abs(mkw.cpu().numpy() - mk.cpu().numpy()).max() < OBS_TOL
