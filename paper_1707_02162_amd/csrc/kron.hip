@@ -232,6 +232,140 @@ __global__ __launch_bounds__(KRON_NT, 4) void kron_step_kernel(float2* X0, float
     }
 }
 
+// kron_step_kernel<1024> followed, in the same workgroup, by the observable in the right
+// Walsh frame on the strip it has just written, while the strip is still in registers: the
+// strip goes to the exchange buffer in the layout of the one-pass observable (16-byte
+// chunks swizzled by row, mx8_off), each pair of lanes forms (M W)_aj for a row and four
+// columns from the packed lists and adds D_j Re(conj(W_aj) (M W)_aj) (FP32 within a row,
+// FP64 across rows); the workgroup's sum goes to partial[b][strip].  The observable's own
+// read of every state disappears.
+template <int WP>
+__global__ __launch_bounds__(KRON_NT, 4) void kron_step_obs_kernel(float2* X0, float2* X1, const int* loc,
+                                                                   long long xstride,
+                                                                   const float2* __restrict__ gates,
+                                                                   const float2* __restrict__ pre,
+                                                                   const float2* __restrict__ post,
+                                                                   const int* n_steps, int step,
+                                                                   const int* __restrict__ cols,
+                                                                   const float2* __restrict__ vals,
+                                                                   const double* __restrict__ spec,
+                                                                   double* __restrict__ partial) {
+    constexpr int D = 1024;
+    using S = KronShape<D>;
+    constexpr int n = S::n, SW = S::SW, NSTRIP = D / SW;
+    static_assert(SW == 8 && S::rounds > 2, "8-column strips, the buffer free after the last exchange");
+    __shared__ float2 buf[KRON_NT * KRON_VALS];
+    __shared__ float2 gl[n * 4];
+    __shared__ double red[KRON_NT / 64];
+    const long long bid = kron_xcd(blockIdx.x, gridDim.x);
+    const int b = (int)(bid / NSTRIP), strip = (int)(bid % NSTRIP);
+    if (n_steps && step >= n_steps[b]) return;   // uniform over the workgroup
+    float2* X = ((loc && loc[b]) ? X1 : X0) + (long long)b * xstride + strip * SW;
+    const int t = threadIdx.x, c = t % SW, rest = t / SW;
+    if (t < n * 4) gl[t] = gates[(long long)b * n * 4 + t];
+    const float2* pb = pre + (long long)b * D;
+    const float2* qb = post + (long long)b * D;
+    float2 v[KRON_VALS];
+#pragma unroll
+    for (int i = 0; i < KRON_VALS; ++i) {
+        const int a = kron_row(rest, i, 0);
+        v[i] = cmul(pb[a], X[(long long)a * D + c]);
+    }
+    __syncthreads();   // gates in LDS
+    kron_round_gates<D, 0>(v, gl);
+    kron_exchange<D, 1>(v, buf, rest, c);
+    kron_round_gates<D, 1>(v, gl);
+    kron_exchange<D, 2>(v, buf, rest, c);
+    kron_round_gates<D, 2>(v, gl);
+    constexpr int flo = KronRound<D, S::rounds - 1>::lo;
+    // the last exchange ended with a barrier after its reads: the buffer is free
+#pragma unroll
+    for (int i = 0; i < KRON_VALS; ++i) {
+        const int a = kron_row(rest, i, flo);
+        const float2 y = cmul(qb[a], v[i]);
+        X[(long long)a * D + c] = y;
+        buf[mx8_off(a, c)] = y;
+    }
+    __syncthreads();
+    asm volatile("" ::: "memory");   // the observable's list loads stay below the step (register pressure)
+    constexpr int LPR = 2, CPL = SW / LPR, NCH = CPL / 2, RPP = KRON_NT / LPR;
+    const float4* strip4 = reinterpret_cast<const float4*>(buf);
+    const int lr = t % LPR;
+    float dj[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) dj[u] = (float)spec[strip * SW + lr * CPL + u];
+    double sum = 0.0;
+    for (int a = t / LPR; a < D; a += RPP) {
+        int cc[WP];
+        float2 cv[WP];
+        obs_list<WP>(cols, vals, a, cc, cv);
+        float2 acc[CPL];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) acc[u] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int e = 0; e < WP; ++e) {
+#pragma unroll
+            for (int j = 0; j < NCH; ++j) {
+                const int ch = lr * NCH + j;
+                const float4 x = strip4[cc[e] * 4 + ((ch ^ (cc[e] >> 2)) & 3)];
+                cfma(acc[2 * j], cv[e], make_float2(x.x, x.y));
+                cfma(acc[2 * j + 1], cv[e], make_float2(x.z, x.w));
+            }
+            asm volatile("" ::: "memory");   // one list entry's gathers at a time (register pressure)
+        }
+        float row = 0.f;
+#pragma unroll
+        for (int j = 0; j < NCH; ++j) {
+            const int ch = lr * NCH + j;
+            const float4 wv = strip4[a * 4 + ((ch ^ (a >> 2)) & 3)];
+            row += dj[2 * j] * (wv.x * acc[2 * j].x + wv.y * acc[2 * j].y) +
+                   dj[2 * j + 1] * (wv.z * acc[2 * j + 1].x + wv.w * acc[2 * j + 1].y);
+        }
+        sum += (double)row;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+    if ((t & 63) == 0) red[t >> 6] = sum;
+    __syncthreads();
+    if (t == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < KRON_NT / 64; ++w) s += red[w];
+        partial[(long long)b * NSTRIP + strip] = s;
+    }
+}
+
+template <int WP>
+hipError_t launch_kron_step_obs(int B, float2* X0, float2* X1, const int* loc, long long xstride, const float2* gates,
+                                const float2* pre, const float2* post, const int* n_steps, int step, const int* pc,
+                                const float2* pv, const double* spec, double* partial, hipStream_t st) {
+    constexpr int NSTRIP = 1024 / KronShape<1024>::SW;
+    void* tok = nullptr;
+    const bool prof = profiling_on();
+    if (prof) profile_begin(st, &tok, 1);
+    hipLaunchKernelGGL(kron_step_obs_kernel<WP>, dim3((unsigned)((long long)B * NSTRIP)), dim3(KRON_NT), 0, st, X0, X1,
+                       loc, xstride, gates, pre, post, n_steps, step, pc, pv, spec, partial);
+    if (prof) profile_end(st, tok);
+    return hipGetLastError();
+}
+
+// the step and the Walsh-frame observable in one launch (d = 1024), then the per-instance sums
+hipError_t kron_step_observable(int B, float2* X0, float2* X1, const int* loc, long long xstride,
+                                const float2* gates, const float2* pre, const float2* post, const int* n_steps,
+                                int step, int w, const int* pc, const float2* pv, const float2* vals,
+                                const double* spec, double* partial, double* out, long long out_stride,
+                                hipStream_t st) {
+    hipError_t e;
+    switch ((w + 3) / 4 * 4) {
+        case 4: e = launch_kron_step_obs<4>(B, X0, X1, loc, xstride, gates, pre, post, n_steps, step, pc, pv, spec, partial, st); break;
+        case 8: e = launch_kron_step_obs<8>(B, X0, X1, loc, xstride, gates, pre, post, n_steps, step, pc, pv, spec, partial, st); break;
+        case 12: e = launch_kron_step_obs<12>(B, X0, X1, loc, xstride, gates, pre, post, n_steps, step, pc, pv, spec, partial, st); break;
+        default: e = launch_kron_step_obs<16>(B, X0, X1, loc, xstride, gates, pre, post, n_steps, step, pc, pv, spec, partial, st);
+    }
+    if (e != hipSuccess) return e;
+    return observable_final(1024 / KronShape<1024>::SW, B, partial, vals, 1024 * w, n_steps, step, out, out_stride, st);
+}
+
 template <int D>
 hipError_t launch_kron_step(int B, float2* X0, float2* X1, const int* loc, long long xstride, const float2* gates,
                             const float2* pre, const float2* post, const int* n_steps, int step, hipStream_t st) {
@@ -338,12 +472,28 @@ redo_status kron_chain(redo_table_s* t, int quantised, const float* u, const int
     } else {
         pa.u = u;
     }
+    // in the Walsh frame at d = 1024 the observable rides on the step kernel (steps without
+    // a re-projection: there it must see the re-projected state)
+    const bool fuse = walsh_frame && obs_out && d == 1024;
+    int* pc = nullptr;
+    float2* pv = nullptr;
+    if (fuse) {
+        REDO_HIP(obs_pack_lists(d, B, obs_width, obs_cols, reinterpret_cast<const float2*>(obs_vals), w.obs_partial, st));
+        obs_packed_lists(d, B, w.obs_partial, &pc, &pv);
+    }
     for (int n = 0; n < N; ++n) {
         pa.step = n;
         hipLaunchKernelGGL(kron_plan_kernel, dim3(B), dim3(256), 0, st, pa);
         REDO_HIP(hipGetLastError());
+        const bool reproj = reproject_every > 0 && ((long long)step_offset + n + 1) % reproject_every == 0;
+        if (fuse && !reproj) {
+            REDO_HIP(kron_step_observable(B, X[0], X[1], w.loc, mat, w.gates, w.pre, w.post, n_steps, n, obs_width, pc,
+                                          pv, reinterpret_cast<const float2*>(obs_vals), walsh, w.obs_partial,
+                                          obs_out + n, N, st));
+            continue;
+        }
         REDO_HIP(kron_step(d, B, X[0], X[1], w.loc, mat, w.gates, w.pre, w.post, n_steps, n, st));
-        if (reproject_every > 0 && ((long long)step_offset + n + 1) % reproject_every == 0) {
+        if (reproj) {
             // X <- X (3I - X^dag X) / 2 = X Z with Z = -X^dag X / 2 + 3/2 I (into the other buffer)
             for (int b0 = 0; b0 < B; b0 += REPROJECT_CHUNK) {
                 const int ch = std::min(REPROJECT_CHUNK, B - b0);

@@ -259,29 +259,6 @@ __device__ inline long long xcd_local(long long bid, long long nb) {
     return (nb % 8 == 0) ? (bid % 8) * (nb / 8) + bid / 8 : bid;
 }
 
-// the row list of row a from the packed layout [d][WP] (padded entries: column a,
-// value 0), as WP/4 + WP/2 16-byte loads
-template <int WP>
-__device__ inline void obs_list(const int* __restrict__ cols, const float2* __restrict__ vals, int a,
-                                int (&cc)[WP], float2 (&cv)[WP]) {
-    const int4* c4 = reinterpret_cast<const int4*>(cols + (long long)a * WP);
-    const float4* v4 = reinterpret_cast<const float4*>(vals + (long long)a * WP);
-#pragma unroll
-    for (int q = 0; q < WP / 4; ++q) {
-        const int4 x = c4[q];
-        cc[4 * q] = x.x;
-        cc[4 * q + 1] = x.y;
-        cc[4 * q + 2] = x.z;
-        cc[4 * q + 3] = x.w;
-    }
-#pragma unroll
-    for (int q = 0; q < WP / 2; ++q) {
-        const float4 y = v4[q];
-        cv[2 * q] = make_float2(y.x, y.y);
-        cv[2 * q + 1] = make_float2(y.z, y.w);
-    }
-}
-
 // caller's row lists [d][w] -> packed [d][WP]
 __global__ void obs_pack_kernel(int d, int w, int wp, const int* __restrict__ cols, const float2* __restrict__ vals,
                                 int* __restrict__ pc, float2* __restrict__ pv) {
@@ -372,10 +349,8 @@ __global__ __launch_bounds__(NT, NT / 128) void observable_mx_kernel(int d, int 
 // Pass 1 for 8-column strips: LPR lanes per row (1 when the strip has at least NT
 // rows), each lane CPL = 8 / LPR columns, so one load instruction of a wave fetches
 // the lists of 64 / LPR rows.  The strip's 16-byte chunks (two columns) are swizzled
-// by row, chunk c of row a at position c ^ ((a >> 2) & 3), so that the chunks 16
-// lanes of 16 neighbouring rows read fall into distinct banks.
-__device__ inline int mx8_off(int a, int col) { return a * 8 + ((((col >> 1) ^ (a >> 2)) & 3) << 1) + (col & 1); }
-
+// by row, chunk c of row a at position c ^ ((a >> 2) & 3) (mx8_off), so that the
+// chunks 16 lanes of 16 neighbouring rows read fall into distinct banks.
 template <int WP, int NT, int LPR>
 __global__ __launch_bounds__(NT, NT / 128) void observable_mx8_kernel(int d, int b0, const float2* __restrict__ X0,
                                                                       const float2* __restrict__ X1, const int* loc,
@@ -1450,6 +1425,29 @@ hipError_t observable_walsh(int d, int B, const float2* X0, const float2* X1, co
     }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(observable_final_kernel, dim3(B), dim3(256), 0, st, d / 8, partial, vals, d * w, n_steps, step,
+                       out, out_stride);
+    return hipGetLastError();
+}
+
+void obs_packed_lists(int d, int B, double* partial, int** pc, float2** pv) {
+    const size_t np = (size_t)B * (d / obs_rows(d));
+    *pc = reinterpret_cast<int*>(partial + np + (np & 1));
+    *pv = reinterpret_cast<float2*>(*pc + (size_t)d * OBS_WMAX);
+}
+
+hipError_t obs_pack_lists(int d, int B, int w, const int* cols, const float2* vals, double* partial, hipStream_t st) {
+    if (w < 1 || w > OBS_WMAX) return hipErrorInvalidValue;
+    const int wp = (w + 3) / 4 * 4;
+    int* pc;
+    float2* pv;
+    obs_packed_lists(d, B, partial, &pc, &pv);
+    hipLaunchKernelGGL(obs_pack_kernel, dim3((d * wp + 255) / 256), dim3(256), 0, st, d, w, wp, cols, vals, pc, pv);
+    return hipGetLastError();
+}
+
+hipError_t observable_final(int nparts, int B, const double* partial, const float2* vals, int nvals,
+                            const int* n_steps, int step, double* out, long long out_stride, hipStream_t st) {
+    hipLaunchKernelGGL(observable_final_kernel, dim3(B), dim3(256), 0, st, nparts, partial, vals, nvals, n_steps, step,
                        out, out_stride);
     return hipGetLastError();
 }

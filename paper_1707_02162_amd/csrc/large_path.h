@@ -110,6 +110,38 @@ int large_grape_checkpoint(const redo_table_s* t, int B, int N, int requested, i
 hipError_t observable(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
                       const int* cols, const float2* vals, int w, const int* n_steps, int step, double* partial,
                       double* out, long long out_stride, float2* T, int chunk, hipStream_t st);
+// observable row lists: the strip layout of the LDS passes and the packed lists
+__device__ inline int mx8_off(int a, int col) { return a * 8 + ((((col >> 1) ^ (a >> 2)) & 3) << 1) + (col & 1); }
+
+// the row list of row a from the packed layout [d][WP] (padded entries: column a,
+// value 0), as WP/4 + WP/2 16-byte loads
+template <int WP>
+__device__ inline void obs_list(const int* __restrict__ cols, const float2* __restrict__ vals, int a,
+                                int (&cc)[WP], float2 (&cv)[WP]) {
+    const int4* c4 = reinterpret_cast<const int4*>(cols + (long long)a * WP);
+    const float4* v4 = reinterpret_cast<const float4*>(vals + (long long)a * WP);
+#pragma unroll
+    for (int q = 0; q < WP / 4; ++q) {
+        const int4 x = c4[q];
+        cc[4 * q] = x.x;
+        cc[4 * q + 1] = x.y;
+        cc[4 * q + 2] = x.z;
+        cc[4 * q + 3] = x.w;
+    }
+#pragma unroll
+    for (int q = 0; q < WP / 2; ++q) {
+        const float4 y = v4[q];
+        cv[2 * q] = make_float2(y.x, y.y);
+        cv[2 * q + 1] = make_float2(y.z, y.w);
+    }
+}
+
+// the packed lists live after the partial sums of observable(); obs_pack_lists fills them
+void obs_packed_lists(int d, int B, double* partial, int** pc, float2** pv);
+hipError_t obs_pack_lists(int d, int B, int w, const int* cols, const float2* vals, double* partial, hipStream_t st);
+hipError_t observable_final(int nparts, int B, const double* partial, const float2* vals, int nvals,
+                            const int* n_steps, int step, double* out, long long out_stride, hipStream_t st);
+
 // the right Walsh frame W = X H / sqrt(d) (observables with M_ij = f(i XOR j))
 bool walsh_dim(int d);   // d = 128 .. 2048, a power of two
 hipError_t walsh_fill(int d, int B, float2* X, long long stride, hipStream_t st);

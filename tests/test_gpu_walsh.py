@@ -188,3 +188,21 @@ def test_walsh_chains_d2048_equal_basis_chains():
     Wk, mkw = t.kron_chain(u, observable=(cols, vals), walsh=D)
     assert nfrob(to_x(Wk), Uk.cpu().numpy().astype(np.complex128)) < FROB_TOL
     assert np.abs(mkw.cpu().numpy() - mk.cpu().numpy()).max() < OBS_TOL
+
+
+def test_walsh_kron_d1024_fused_observable_with_reprojection_and_ragged():
+    """At d = 1024 the structure-aware step carries the Walsh-frame observable in the same
+    launch, except on re-projection steps (separate pass after the re-projection): both
+    kinds of step, ragged lengths, against the computational-basis chain."""
+    p = W.ising_freezing(n=10, B=3, N=9)
+    lens = torch.tensor([9, 5, 8], dtype=torch.int32)
+    t = R().RedoTable.from_problem(p)
+    cols, vals = W.observable_ell(p.M)
+    D = R().walsh_spectrum(cols, vals)
+    u = torch.tensor(p.u).cuda()
+    Uk, mk = t.kron_chain(u, n_steps=lens, observable=(cols, vals), reproject_every=4)
+    Wk, mw = t.kron_chain(u, n_steps=lens, observable=(cols, vals), reproject_every=4, walsh=D)
+    assert nfrob(to_x(Wk), Uk.cpu().numpy().astype(np.complex128)) < FROB_TOL
+    for b in range(3):
+        nb = int(lens[b])
+        assert np.abs(mw[b, :nb].cpu().numpy() - mk[b, :nb].cpu().numpy()).max() < OBS_TOL
