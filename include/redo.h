@@ -421,6 +421,32 @@ redo_status redo_mlp_loss_grad(const redo_mlp* net, int32_t batch, const float* 
                                float* acts, float* scratch, const redo_mlp_grads* grads, double* loss,
                                void* stream);
 
+/*
+ * Batched L-BFGS ascent steps (an optimiser beside plain gradient ascent; for
+ * REDO-GRAPE the objective is F_U and g its gradient).  B instances of P
+ * FP32 parameters each; per instance a history of at most m <= 32 pairs in ring
+ * buffers (device, caller-owned, zero count to start):
+ *   S, Y   float [m][B][P]  s = x_{k+1} - x_k,  y = g_k - g_{k+1}
+ *   rho    double [m][B]    1 / (y . s);  count, head  int32 [B]
+ * redo_lbfgs_direction: dir_b = H_b g_b by the two-loop recursion (initial scale
+ *   s.y / y.y of the newest pair), gd[b] = g_b . dir_b (double); with no pair,
+ *   or when the result is not an ascent direction, dir_b = gamma0 g_b / max|g_b|
+ *   (the largest entry moves by gamma0).  Dot products in FP64.
+ * redo_lbfgs_trial: xt_b = x_b + alpha[b] dir_b (alpha double [B]).
+ * redo_lbfgs_push: for accept[b] != 0 the pair (xn - x, g - gn) enters the
+ *   ring when y.s > 0 (curvature condition); accept[b] == 0 clears instance b's
+ *   history.
+ * Errors: REDO_ERR_ARG (sizes, NULL, m out of range).
+ */
+redo_status redo_lbfgs_direction(int32_t B, int64_t P, int32_t m, const float* g, const float* S,
+                                 const float* Y, const double* rho, const int32_t* count,
+                                 const int32_t* head, double gamma0, float* dir, double* gd, void* stream);
+redo_status redo_lbfgs_trial(int32_t B, int64_t P, const float* x, const float* dir, const double* alpha,
+                             float* xt, void* stream);
+redo_status redo_lbfgs_push(int32_t B, int64_t P, int32_t m, const float* x, const float* xn,
+                            const float* g, const float* gn, const int32_t* accept, float* S, float* Y,
+                            double* rho, int32_t* count, int32_t* head, void* stream);
+
 /* One Adam step on n parameters (bias-corrected with step >= 1): descent when
  * sign = 1, ascent when sign = -1, result clamped to [lo, hi]; when param_bf16
  * is not NULL it receives the updated parameters rounded to BF16.  Also the

@@ -52,6 +52,9 @@ _SIG = {
     "redo_adam_update": (_I, [ctypes.c_int64, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
     "redo_to_bf16": (_I, [ctypes.c_int64, _P, _P, _P]),
+    "redo_lbfgs_direction": (_I, [_I, ctypes.c_int64, _I, _P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P]),
+    "redo_lbfgs_trial": (_I, [_I, ctypes.c_int64, _P, _P, _P, _P, _P]),
+    "redo_lbfgs_push": (_I, [_I, ctypes.c_int64, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "redo_observable_walsh": (_I, [_I, _P, _P, _I, _P]),
     "redo_walsh_right": (_I, [_I, _I, _P, ctypes.c_int64, _P]),
     "redo_chain_propagator_walsh": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P, _P, _P,
