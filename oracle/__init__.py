@@ -9,3 +9,4 @@ the GPU library: the two share no arithmetic, only the seeded inputs of
 Parity status of every function is stated in its module docstring.
 """
 from .redo_oracle import *  # noqa: F401,F403
+from .optim_oracle import bfgs_inverse_matrix, lbfgs_direction  # noqa: F401

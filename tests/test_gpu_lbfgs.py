@@ -1,10 +1,11 @@
-"""The batched L-BFGS kernels through the C ABI against an FP64 numpy two-loop
-recursion written here from the algorithm's definition (the direction H g of the
-limited-memory inverse-curvature estimate), the history rules, and the REDO-GRAPE
-driver's ascent."""
+"""The batched L-BFGS kernels through the C ABI against the FP64 oracle's two-loop
+recursion (the direction H g of the limited-memory inverse-curvature estimate), the
+history rules, and the REDO-GRAPE driver's ascent."""
 import numpy as np
 import pytest
 import torch
+
+import oracle as O
 
 pytestmark = pytest.mark.gpu
 
@@ -12,28 +13,6 @@ pytestmark = pytest.mark.gpu
 def R():
     from paper_1707_02162_amd import redo
     return redo
-
-
-def two_loop(g, pairs, gamma0):
-    """pairs: (s, y) oldest first; FP64."""
-    q = g.astype(np.float64).copy()
-    g0 = gamma0 / np.abs(q).max()
-    al = []
-    for s, y in reversed(pairs):
-        rho = 1.0 / (y @ s)
-        a = rho * (s @ q)
-        q -= a * y
-        al.append((a, rho))
-    al.reverse()
-    if pairs:
-        s, y = pairs[-1]
-        q *= (s @ y) / (y @ y)
-    else:
-        q *= g0
-    for (s, y), (a, rho) in zip(pairs, al):
-        beta = rho * (y @ q)
-        q += s * (a - beta)
-    return q
 
 
 def _state(B, P, m, dev="cuda"):
@@ -84,7 +63,7 @@ def test_lbfgs_direction_and_history_vs_two_loop():
                                          P_(gd), None))
     d = d.cpu().numpy()
     for b in range(B):
-        ref = two_loop(gq[b], hist[b][-m:], 2.5)
+        ref = O.lbfgs_direction(gq[b], hist[b][-m:], 2.5)
         assert np.linalg.norm(d[b] - ref) <= 1e-5 * np.linalg.norm(ref), b
         assert abs(gd[b].item() - float(gq[b].astype(np.float64) @ d[b])) <= 1e-6 * abs(gd[b].item())
     # a rejected step clears the history; a pair without positive curvature is not kept

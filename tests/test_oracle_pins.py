@@ -546,3 +546,29 @@ def test_state_fidelity_is_a_propagator_entry_and_gradient_matches_fd():
         _, _, grad = O.state_fidelity_and_gradient(p, 0, psi0, psif, model=model)
         fd = _fd_state(p, 0, p.u[0].astype(float), psi0, psif, model, 1e-6 * p.u_scale)
         assert np.linalg.norm(grad - fd) <= 1e-7 * np.linalg.norm(fd)
+
+
+def test_lbfgs_oracle_two_loop_equals_explicit_bfgs_inverse():
+    """The oracle's two-loop direction equals the explicit BFGS inverse-update matrix
+    applied to g (a different computation of the same estimate), and the estimate
+    satisfies the secant condition H y = s of its newest pair."""
+    import numpy as np
+    import oracle as O
+    rng = np.random.default_rng(17)
+    n = 40
+    A = rng.normal(size=(n, n))
+    A = A @ A.T / n + 0.3 * np.eye(n)
+    pairs = []
+    for _ in range(6):
+        s = rng.normal(size=n)
+        pairs.append((s, A @ s))
+    g = rng.normal(size=n)
+    s_new, y_new = pairs[-1]
+    gamma = (s_new @ y_new) / (y_new @ y_new)
+    H = O.bfgs_inverse_matrix(pairs, gamma)
+    d = O.lbfgs_direction(g, pairs, 1.0)
+    assert np.abs(d - H @ g).max() <= 1e-10 * np.abs(H @ g).max()
+    assert np.abs(O.lbfgs_direction(y_new, pairs, 1.0) - s_new).max() <= 1e-10 * np.abs(s_new).max()
+    # no history: the gradient scaled to gamma0 in its largest entry
+    d0 = O.lbfgs_direction(g, [], 2.5)
+    assert abs(np.abs(d0).max() - 2.5) < 1e-12 and np.allclose(d0 / g, d0[0] / g[0])
