@@ -87,10 +87,11 @@ __device__ inline void load_stage(const GemmDesc& g, int d, int i0, int j0, int 
     }
 }
 
-// registers -> LDS (k-major tiles As[k][i], Bs[k][j]); conjugation, transposition and the k-scaling here
+// registers -> LDS (k-major tiles As[k][i], Bs[k][j]); conjugation, transposition and the k-scaling
+// here, the stage's KT scaling factors read from LDS (ks)
 template <int BM, int BN>
-__device__ inline void store_stage(const GemmDesc& g, int k0, const float4 (&ra)[GCfg<BM, BN>::AV],
-                                   const float4 (&rb)[GCfg<BM, BN>::BV], float2* As, float2* Bs) {
+__device__ inline void store_stage(const GemmDesc& g, const float4 (&ra)[GCfg<BM, BN>::AV],
+                                   const float4 (&rb)[GCfg<BM, BN>::BV], const float2* ks, float2* As, float2* Bs) {
     using C = GCfg<BM, BN>;
     const int t = threadIdx.x;
 #pragma unroll
@@ -114,7 +115,7 @@ __device__ inline void store_stage(const GemmDesc& g, int k0, const float4 (&ra)
             const int kr = e / (BN / 2), jq = e % (BN / 2);
             float2 a = f2(v.x, v.y), b = f2(v.z, v.w);
             if (g.kscale) {
-                const float2 s = ldg2(g.kscale + k0 + kr);
+                const float2 s = ks[kr];
                 a = cmul(s, a);
                 b = cmul(s, b);
             }
@@ -123,12 +124,28 @@ __device__ inline void store_stage(const GemmDesc& g, int k0, const float4 (&ra)
             const int row = e / (KT / 2), kq = e % (KT / 2);
             float2 a = f2(v.x, -v.y), b = f2(v.z, -v.w);
             if (g.kscale) {
-                a = cmul(ldg2(g.kscale + k0 + 2 * kq), a);
-                b = cmul(ldg2(g.kscale + k0 + 2 * kq + 1), b);
+                a = cmul(ks[2 * kq], a);
+                b = cmul(ks[2 * kq + 1], b);
             }
             Bs[(2 * kq) * C::LDB + row] = a;
             Bs[(2 * kq + 1) * C::LDB + row] = b;
         }
+    }
+}
+
+// The KT k-scaling factors of stage s into LDS (ring slot s % 3) by the first 2 KT lanes, one
+// float each, global -> LDS without registers (a register prefetch would cost the 3M form its
+// third wave per SIMD; loading them in store_stage stalled every stage on a global load).  Lane l
+// writes LDS byte M0 + 4 l.  Issued from asm so that the compiler, which cannot tell the slot from
+// the operand tiles, does not wait for it (and for the tile prefetch) before every LDS read: the
+// caller waits on the vector-memory counter before the barrier that publishes the slot.  Loads the
+// compiler does not know about only make its own vector-memory waits stricter (in-order counter).
+__device__ inline void ks_fetch(const GemmDesc& g, int s, float2 (*Ks)[KT]) {
+    if (g.kscale != nullptr && threadIdx.x < 2 * KT) {
+        const float* src = reinterpret_cast<const float*>(g.kscale + s * KT) + threadIdx.x;
+        const unsigned lds = (unsigned)(size_t)(__attribute__((address_space(3))) float2*)Ks[s % 3];
+        asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dword %1, off" ::"s"(lds), "v"(src)
+                     : "memory", "m0");
     }
 }
 
@@ -169,6 +186,7 @@ __global__ __launch_bounds__(256, 3) void cgemm_kernel(int d, int batch, const G
     using C = GCfg<BM, BN>;
     __shared__ float2 As[2][KT * C::LDA];
     __shared__ float2 Bs[2][KT * C::LDB];
+    __shared__ float2 Ks[3][KT];   // k-scaling of stages kt, kt + 1, kt + 2
     const int tiles_n = d / BN;
     const int ntile = (d / BM) * tiles_n;
     int bid = blockIdx.x;
@@ -184,6 +202,9 @@ __global__ __launch_bounds__(256, 3) void cgemm_kernel(int d, int batch, const G
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wi0 = (wave >> 1) * C::WM, wj0 = (wave & 1) * C::WN;
+    const int nk = d / KT;
+    ks_fetch(g, 0, Ks);
+    if (nk > 1) ks_fetch(g, 1, Ks);
     constexpr int NACC = MODE == 0 ? 2 : 3;
     floatx16 acc[NACC][C::FM][C::FN];
 #pragma unroll
@@ -197,12 +218,15 @@ __global__ __launch_bounds__(256, 3) void cgemm_kernel(int d, int batch, const G
 
     float4 ra[C::AV], rb[C::BV];
     load_stage<BM, BN>(g, d, i0, j0, 0, ra, rb);
-    store_stage<BM, BN>(g, 0, ra, rb, As[0], Bs[0]);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // Ks[0], Ks[1] landed
     __syncthreads();
-    const int nk = d / KT;
+    store_stage<BM, BN>(g, ra, rb, Ks[0], As[0], Bs[0]);
+    __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
         if (kt + 1 < nk) load_stage<BM, BN>(g, d, i0, j0, (kt + 1) * KT, ra, rb);
+        // slot (kt + 2) % 3 was last read by the store of stage kt - 1, before the previous barrier
+        if (kt + 2 < nk) ks_fetch(g, kt + 2, Ks);
         const float2* Ab = As[buf];
         const float2* Bb = Bs[buf];
 #pragma unroll
@@ -253,7 +277,8 @@ __global__ __launch_bounds__(256, 3) void cgemm_kernel(int d, int batch, const G
                                                                               acc[2][ib][jb], 0, 0, 0);
             }
         }
-        if (kt + 1 < nk) store_stage<BM, BN>(g, (kt + 1) * KT, ra, rb, As[buf ^ 1], Bs[buf ^ 1]);
+        if (kt + 1 < nk) store_stage<BM, BN>(g, ra, rb, Ks[(kt + 1) % 3], As[buf ^ 1], Bs[buf ^ 1]);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this stage's ks_fetch landed before the barrier
         __syncthreads();
     }
     // epilogue: element (i, j) of a 32x32 block lives in lane j + 32 * ((i / 4) % 2), register 4 * (i / 8) + i % 4
