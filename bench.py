@@ -39,9 +39,9 @@ PEAK_HBM_GBS = 8000.0
 # is unchanged.
 GEMM_TRAFFIC = {
     "source": "paper_1707_02162_amd/csrc/cgemm.hip",
-    "sha256": "76f18aedac38f61c13588bcd3610cd8c118dfd14c07eb7ba70d8ee87a1c5d558",
-    # FETCH_SIZE 84,066,993 KiB per launch (mean of 3) x 1.99994 (a 1 GiB copy reads as 524,302.5 KiB)
-    "fetch_bytes": 172164452889,
+    "sha256": "2d5ed4d7a760374f68c9d51b8f62a2945ed1403e4f28254e941023b32ece8cf4",
+    # FETCH_SIZE 83,914,834 KiB per launch (mean of 3) x 1.99994 (a 1 GiB copy reads as 524,302.4 KiB)
+    "fetch_bytes": 171852846850,
     # WRITE_SIZE 33,554,432 KiB per launch x 1.0000 (a 1 GiB copy writes 1,048,576 KiB)
     "write_bytes": 34359738368,
 }

@@ -88,9 +88,9 @@ __device__ inline void load_stage(const GemmDesc& g, int d, int i0, int j0, int 
 }
 
 // registers -> LDS (k-major tiles As[k][i], Bs[k][j]); conjugation, transposition and the k-scaling
-// here, the stage's KT scaling factors read from LDS (ks)
-template <int BM, int BN>
-__device__ inline void store_stage(const GemmDesc& g, const float4 (&ra)[GCfg<BM, BN>::AV],
+// here, the stage's KT scaling factors read from LDS (KSL: ks, prefetched) or from global memory
+template <int BM, int BN, bool KSL>
+__device__ inline void store_stage(const GemmDesc& g, int k0, const float4 (&ra)[GCfg<BM, BN>::AV],
                                    const float4 (&rb)[GCfg<BM, BN>::BV], const float2* ks, float2* As, float2* Bs) {
     using C = GCfg<BM, BN>;
     const int t = threadIdx.x;
@@ -115,7 +115,7 @@ __device__ inline void store_stage(const GemmDesc& g, const float4 (&ra)[GCfg<BM
             const int kr = e / (BN / 2), jq = e % (BN / 2);
             float2 a = f2(v.x, v.y), b = f2(v.z, v.w);
             if (g.kscale) {
-                const float2 s = ks[kr];
+                const float2 s = KSL ? ks[kr] : ldg2(g.kscale + k0 + kr);
                 a = cmul(s, a);
                 b = cmul(s, b);
             }
@@ -124,8 +124,8 @@ __device__ inline void store_stage(const GemmDesc& g, const float4 (&ra)[GCfg<BM
             const int row = e / (KT / 2), kq = e % (KT / 2);
             float2 a = f2(v.x, -v.y), b = f2(v.z, -v.w);
             if (g.kscale) {
-                a = cmul(ks[2 * kq], a);
-                b = cmul(ks[2 * kq + 1], b);
+                a = cmul(KSL ? ks[2 * kq] : ldg2(g.kscale + k0 + 2 * kq), a);
+                b = cmul(KSL ? ks[2 * kq + 1] : ldg2(g.kscale + k0 + 2 * kq + 1), b);
             }
             Bs[(2 * kq) * C::LDB + row] = a;
             Bs[(2 * kq + 1) * C::LDB + row] = b;
@@ -144,8 +144,8 @@ __device__ inline void ks_fetch(const GemmDesc& g, int s, float2 (*Ks)[KT]) {
     if (g.kscale != nullptr && threadIdx.x < 2 * KT) {
         const float* src = reinterpret_cast<const float*>(g.kscale + s * KT) + threadIdx.x;
         const unsigned lds = (unsigned)(size_t)(__attribute__((address_space(3))) float2*)Ks[s % 3];
-        asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dword %1, off" ::"s"(lds), "v"(src)
-                     : "memory", "m0");
+        // no memory clobber: the slot is read only after two barriers
+        asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dword %1, off" ::"s"(lds), "v"(src) : "m0");
     }
 }
 
@@ -203,8 +203,13 @@ __global__ __launch_bounds__(256, 3) void cgemm_kernel(int d, int batch, const G
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wi0 = (wave >> 1) * C::WM, wj0 = (wave & 1) * C::WN;
     const int nk = d / KT;
-    ks_fetch(g, 0, Ks);
-    if (nk > 1) ks_fetch(g, 1, Ks);
+    // k-scaling through LDS for the large tile (big batches: 1.1 % faster at d = 1024); the 64 x 64
+    // tile of small batches, latency-bound at two waves per SIMD, was 2 % slower with it
+    constexpr bool KSL = BM == 128;
+    if constexpr (KSL) {
+        ks_fetch(g, 0, Ks);
+        if (nk > 1) ks_fetch(g, 1, Ks);
+    }
     constexpr int NACC = MODE == 0 ? 2 : 3;
     floatx16 acc[NACC][C::FM][C::FN];
 #pragma unroll
@@ -218,15 +223,17 @@ __global__ __launch_bounds__(256, 3) void cgemm_kernel(int d, int batch, const G
 
     float4 ra[C::AV], rb[C::BV];
     load_stage<BM, BN>(g, d, i0, j0, 0, ra, rb);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // Ks[0], Ks[1] landed
-    __syncthreads();
-    store_stage<BM, BN>(g, ra, rb, Ks[0], As[0], Bs[0]);
+    if (KSL && g.kscale != nullptr) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // Ks[0], Ks[1] landed
+        __syncthreads();
+    }
+    store_stage<BM, BN, KSL>(g, 0, ra, rb, Ks[0], As[0], Bs[0]);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
         if (kt + 1 < nk) load_stage<BM, BN>(g, d, i0, j0, (kt + 1) * KT, ra, rb);
         // slot (kt + 2) % 3 was last read by the store of stage kt - 1, before the previous barrier
-        if (kt + 2 < nk) ks_fetch(g, kt + 2, Ks);
+        if (KSL && kt + 2 < nk) ks_fetch(g, kt + 2, Ks);
         const float2* Ab = As[buf];
         const float2* Bb = Bs[buf];
 #pragma unroll
@@ -277,8 +284,8 @@ __global__ __launch_bounds__(256, 3) void cgemm_kernel(int d, int batch, const G
                                                                               acc[2][ib][jb], 0, 0, 0);
             }
         }
-        if (kt + 1 < nk) store_stage<BM, BN>(g, ra, rb, Ks[(kt + 1) % 3], As[buf ^ 1], Bs[buf ^ 1]);
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this stage's ks_fetch landed before the barrier
+        if (kt + 1 < nk) store_stage<BM, BN, KSL>(g, (kt + 1) * KT, ra, rb, Ks[(kt + 1) % 3], As[buf ^ 1], Bs[buf ^ 1]);
+        if (KSL && g.kscale != nullptr) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this stage's ks_fetch landed
         __syncthreads();
     }
     // epilogue: element (i, j) of a 32x32 block lives in lane j + 32 * ((i / 4) % 2), register 4 * (i / 8) + i % 4
