@@ -578,9 +578,11 @@ __global__ __launch_bounds__(256) void walsh_right_kernel(int d, long long rows,
 }
 
 // The observable in the right Walsh frame, one pass: the 8-column strip of W in LDS (as
-// observable_mx8_kernel), each lane forms (M W)_aj for its rows a and columns j from the
-// row lists and adds D_j Re(conj(W_aj) (M W)_aj) (FP32 within a row, FP64 across rows);
-// the workgroup's sum goes to partial[b][strip].
+// observable_mx8_kernel), each lane forms (M W)_aj for its rows a and columns j and adds
+// D_j Re(conj(W_aj) (M W)_aj) (FP32 within a row, FP64 across rows); the workgroup's sum goes
+// to partial[b][strip].  The frame needs M_ac = f(a XOR c), so row a's list is row 0's with
+// every column XORed by a: the masks and values are read once from row 0 (one address for
+// every lane) and its zero entries, the padding among them, are skipped.
 template <int WP, int NT, int LPR>
 __global__ __launch_bounds__(NT, NT / 128) void observable_walsh_kernel(int d, int b0, const float2* __restrict__ X0,
                                                                         const float2* __restrict__ X1, const int* loc,
@@ -621,24 +623,26 @@ __global__ __launch_bounds__(NT, NT / 128) void observable_walsh_kernel(int d, i
     float dj[CPL];
 #pragma unroll
     for (int u = 0; u < CPL; ++u) dj[u] = (float)spec[c0 + lr * CPL + u];
+    int mk[WP];
+    float2 fv[WP];
+    obs_list<WP>(cols, vals, 0, mk, fv);
     double sum = 0.0;
     for (int a = tid / LPR; a < d; a += RPP) {
-        int cc[WP];
-        float2 cv[WP];
-        obs_list<WP>(cols, vals, a, cc, cv);
         float2 acc[CPL];
 #pragma unroll
         for (int u = 0; u < CPL; ++u) acc[u] = make_float2(0.f, 0.f);
 #pragma unroll
         for (int t = 0; t < WP; ++t) {
+            if (fv[t].x == 0.f && fv[t].y == 0.f) continue;   // the same for every lane
+            const int c = a ^ mk[t];
 #pragma unroll
             for (int j = 0; j < NCH; ++j) {
                 const int ch = lr * NCH + j;
-                const float4 x = strip4[cc[t] * 4 + ((ch ^ (cc[t] >> 2)) & 3)];
-                cfma(acc[2 * j], cv[t], make_float2(x.x, x.y));
-                cfma(acc[2 * j + 1], cv[t], make_float2(x.z, x.w));
+                const float4 x = strip4[c * 4 + ((ch ^ (c >> 2)) & 3)];
+                cfma(acc[2 * j], fv[t], make_float2(x.x, x.y));
+                cfma(acc[2 * j + 1], fv[t], make_float2(x.z, x.w));
             }
-            asm volatile("" ::: "memory");   // one list entry's gathers at a time (register pressure)
+            asm volatile("" ::: "memory");   // one mask's gathers at a time (register pressure)
         }
         float row = 0.f;
 #pragma unroll
