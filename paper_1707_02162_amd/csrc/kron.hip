@@ -287,31 +287,35 @@ __global__ __launch_bounds__(KRON_NT, 4) void kron_step_obs_kernel(float2* X0, f
         buf[mx8_off(a, c)] = y;
     }
     __syncthreads();
-    asm volatile("" ::: "memory");   // the observable's list loads stay below the step (register pressure)
+    asm volatile("" ::: "memory");   // the observable's mask loads stay below the step (register pressure)
     constexpr int LPR = 2, CPL = SW / LPR, NCH = CPL / 2, RPP = KRON_NT / LPR;
     const float4* strip4 = reinterpret_cast<const float4*>(buf);
     const int lr = t % LPR;
     float dj[CPL];
 #pragma unroll
     for (int u = 0; u < CPL; ++u) dj[u] = (float)spec[strip * SW + lr * CPL + u];
+    // M_ac = f(a XOR c) (the frame needs it): row a's list is row 0's with every column XORed
+    // by a, so the masks and values are read once (one address for every lane), zeros skipped
+    int mk[WP];
+    float2 fv[WP];
+    obs_list<WP>(cols, vals, 0, mk, fv);
     double sum = 0.0;
     for (int a = t / LPR; a < D; a += RPP) {
-        int cc[WP];
-        float2 cv[WP];
-        obs_list<WP>(cols, vals, a, cc, cv);
         float2 acc[CPL];
 #pragma unroll
         for (int u = 0; u < CPL; ++u) acc[u] = make_float2(0.f, 0.f);
 #pragma unroll
         for (int e = 0; e < WP; ++e) {
+            if (fv[e].x == 0.f && fv[e].y == 0.f) continue;   // the same for every lane
+            const int c = a ^ mk[e];
 #pragma unroll
             for (int j = 0; j < NCH; ++j) {
                 const int ch = lr * NCH + j;
-                const float4 x = strip4[cc[e] * 4 + ((ch ^ (cc[e] >> 2)) & 3)];
-                cfma(acc[2 * j], cv[e], make_float2(x.x, x.y));
-                cfma(acc[2 * j + 1], cv[e], make_float2(x.z, x.w));
+                const float4 x = strip4[c * 4 + ((ch ^ (c >> 2)) & 3)];
+                cfma(acc[2 * j], fv[e], make_float2(x.x, x.y));
+                cfma(acc[2 * j + 1], fv[e], make_float2(x.z, x.w));
             }
-            asm volatile("" ::: "memory");   // one list entry's gathers at a time (register pressure)
+            asm volatile("" ::: "memory");   // one mask's gathers at a time (register pressure)
         }
         float row = 0.f;
 #pragma unroll
