@@ -258,7 +258,11 @@ redo_status redo_walsh_right(int32_t d, int32_t B, float* X, int64_t stride, voi
  * are W = X Hn (convert with redo_walsh_right), and the observable rows
  * (device, as obs_cols/obs_vals there) come with spectrum (device, double [d],
  * from redo_observable_walsh for the same M) for the one-pass evaluation;
- * obs_out as there.  spectrum may be NULL when obs_out is NULL.  Needs d a
+ * obs_out as there.  The lists must describe such an M (redo_observable_walsh
+ * returned REDO_OK for them): the one-pass kernels read only row 0's list and
+ * take row a's entries as column m XOR a with value f(m) for every entry
+ * (m, f(m)) of row 0, so other rows are not checked on the device.
+ * spectrum may be NULL when obs_out is NULL.  Needs d a
  * power of two in 128 .. 2048 (REDO_ERR_UNSUPPORTED otherwise); no X_prefix.
  * Same workspace as the corresponding chain (REDO_OP_CHAIN, REDO_OP_KRON_CHAIN,
  * REDO_OP_EXPM_CHAIN).
