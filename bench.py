@@ -13,7 +13,9 @@ Also reported: GRAPE iterations/s (fidelity + adjoint gradient) of a
 10-qubit NMR chain (d = 1024, N = 500), the plain per-step exponential on the
 same GPU when the library provides it, the roofline fraction of the dominant
 kernel (batched complex GEMM, timed with HIP events on its stream), and the
-FP64 oracle timed on the host cores on a bounded sample.
+FP64 oracle timed on the host cores on a bounded sample: realisation 0 of the
+headline workload over the steps the GPU ran, whose REDO chain and EXACT chain
+(unsplit, unquantised) give the error of every GPU line and REDO's method error.
 """
 from __future__ import annotations
 
@@ -73,12 +75,26 @@ def count_products(codes: np.ndarray, base: int, digits: int) -> int:
     return n
 
 
+def window_warmup(warmup: int, steps: int, reproject: int) -> int:
+    """Smallest warm-up length >= warmup whose timed window of `steps` steps
+    contains a re-projection step (global step count a multiple of `reproject`):
+    with steps >= reproject any window holds one per `reproject` steps; a
+    shorter window then holds one, more often than the run does."""
+    if reproject <= 0:
+        return warmup
+    w = warmup
+    while (w + steps) // reproject == w // reproject:
+        w += 1
+    return w
+
+
 def bench_freezing(args, redo, W, torch):
     """REDO chain (FP32 headline, split BF16) and the plain per-step exponential
     on the same 4096-realisation workload, one table."""
-    B, K, Wm = args.realisations, args.steps, args.warmup
-    N = Wm + max(K, args.expm_steps)
-    log(f"[bench] building the Ising workload: B={B} d=1024 steps={N}")
+    B, K = args.realisations, args.steps
+    Wr = window_warmup(args.warmup, K, args.reproject)
+    N = max(Wr + K, args.warmup + args.expm_steps)
+    log(f"[bench] building the Ising workload: B={B} d=1024 steps={N} (warm-up {Wr}, timed {K})")
     p = W.ising_freezing(n=10, B=B, N=N)
     t0 = time.time()
     table = redo.RedoTable.from_problem(p)
@@ -101,7 +117,7 @@ def bench_freezing(args, redo, W, torch):
     U = torch.empty((B, p.d, p.d), dtype=torch.complex64, device="cuda")
     mag = torch.empty((B, N), dtype=torch.float64, device="cuda")
 
-    def run(kind, precision, steps, walsh=True):
+    def run(kind, precision, steps, warm, walsh=True):
         wf = spec if walsh else None
 
         def advance(n0, n1):
@@ -118,16 +134,16 @@ def bench_freezing(args, redo, W, torch):
                                         observable=obs, precision=precision, walsh=wf)
             mag[:, n0:n1] = m
 
-        for n0 in range(0, Wm, args.chunk):
-            advance(n0, min(Wm, n0 + args.chunk))
+        for n0 in range(0, warm, args.chunk):
+            advance(n0, min(warm, n0 + args.chunk))
         torch.cuda.synchronize()
         redo.profile_enable(True)
         redo.profile_read(reset=True)
         t0 = time.perf_counter()
-        for n0 in range(Wm, Wm + steps, args.chunk):
-            n1 = min(Wm + steps, n0 + args.chunk)
+        for n0 in range(warm, warm + steps, args.chunk):
+            n1 = min(warm + steps, n0 + args.chunk)
             advance(n0, n1)
-            log(f"[bench] {kind} p{precision} timed steps {n1 - Wm}/{steps}")
+            log(f"[bench] {kind} p{precision} timed steps {n1 - warm}/{steps}")
         if wf is not None:
             redo.walsh_right(U)   # the final states back in the computational basis
         torch.cuda.synchronize()
@@ -135,34 +151,35 @@ def bench_freezing(args, redo, W, torch):
         gemm_ms, launches = redo.profile_read(reset=True)
         kron_ms, kron_launches = redo.profile_read(reset=True, kind=1)
         redo.profile_enable(False)
+        m = mag[:, :warm + steps].cpu().numpy()
+        common = dict(value=B * steps / elapsed, ms_per_step=1e3 * elapsed / steps, steps=steps, warmup_run=warm,
+                      reprojections_timed=(warm + steps) // args.reproject - warm // args.reproject
+                      if args.reproject > 0 else 0,
+                      mag_last=m[:, -1].copy(), mag0=m[0].copy(), x0=U[0].cpu().numpy().astype(np.complex128))
         if kind == "kron":
             # one launch per step reads and writes every realisation's state once (algorithmic bytes)
             kbytes = 2.0 * 8 * p.d * p.d * B
-            m = mag[:, :Wm + steps].cpu().numpy()
-            return dict(value=B * steps / elapsed, ms_per_step=1e3 * elapsed / steps,
-                        avg_launch_ms=kron_ms / max(kron_launches, 1), launches=kron_launches,
+            return dict(common, avg_launch_ms=kron_ms / max(kron_launches, 1), launches=kron_launches,
                         bytes_per_launch=kbytes,
-                        achieved_gbs=kbytes / (kron_ms / max(kron_launches, 1) * 1e-3) / 1e9 if kron_launches else None,
-                        mag_last=m[:, -1].copy())
-        codes, _ = table.quantise(u[:, Wm:Wm + steps].contiguous())
+                        achieved_gbs=kbytes / (kron_ms / max(kron_launches, 1) * 1e-3) / 1e9 if kron_launches else None)
+        codes, _ = table.quantise(u[:, warm:warm + steps].contiguous())
         cn = codes.cpu().numpy()
         products = int(np.count_nonzero(cn)) if args.cache else count_products(cn, p.base, p.digits)
+        # every re-projection step adds two products per realisation (X^dag X, then X Z)
+        products += 2 * B * common["reprojections_timed"]
         # the product form's own real flops: 8 d^3 (four real products), 6 d^3 (Gauss, three)
         flops = (6.0 if precision == 1 else 8.0) * p.d ** 3 * products
-        m = mag[:, :Wm + steps].cpu().numpy()
-        return dict(value=B * steps / elapsed, ms_per_step=1e3 * elapsed / steps, gemm_ms=gemm_ms,
-                    gemm_launches=launches, products=products,
+        return dict(common, gemm_ms=gemm_ms, gemm_launches=launches, products=products,
                     achieved=(flops / (gemm_ms * 1e-3) / 1e12) if kind == "redo" else None,
                     step_flops=flops / steps,
-                    flops_per_launch=flops / max(launches, 1), avg_launch_ms=gemm_ms / max(launches, 1),
-                    mag_last=m[:, -1].copy())
+                    flops_per_launch=flops / max(launches, 1), avg_launch_ms=gemm_ms / max(launches, 1))
 
-    fp32 = run("redo", 1, K)
-    lists = None if args.no_lists else run("redo", 1, K, walsh=False)
-    bf = None if args.no_bf16 else run("redo", 2, K)
-    g4 = None if args.no_4m else run("redo", 0, K)
-    ex = None if args.no_expm else run("expm", 1, args.expm_steps)
-    kr = None if args.no_kron else run("kron", 0, K)
+    fp32 = run("redo", 1, K, Wr)
+    lists = None if args.no_lists else run("redo", 1, K, Wr, walsh=False)
+    bf = None if args.no_bf16 else run("redo", 2, K, Wr)
+    g4 = None if args.no_4m else run("redo", 0, K, Wr)
+    ex = None if args.no_expm else run("expm", 1, args.expm_steps, args.warmup)
+    kr = None if args.no_kron else run("kron", 0, K, Wr)
     out = dict(fp32=fp32, lists=lists, bf16x3=bf, f32_4m=g4, expm=ex, kron=kr, table_build_s=t_table,
                cache_build_s=t_cache)
     del table
@@ -177,6 +194,7 @@ def bench_grape(args, redo, W, torch):
     u = torch.tensor(p.u, device="cuda")
     Uf = torch.tensor(p.U_target, device="cuda")
     res = {}
+    first = {}
     for kind in ("redo", "expm"):
         if kind == "expm" and args.no_expm:
             continue
@@ -185,22 +203,32 @@ def bench_grape(args, redo, W, torch):
         fn = lambda uu_, Uf_: fn0(uu_, Uf_, precision=1)
         uu = u.clone()
         # one whole untimed iteration, update included (the first use of each
-        # elementwise kernel loads its code object)
-        _, _, g = fn(uu, Uf)
-        uu = torch.clamp(uu + 1e3 * g, -p.u_scale, p.u_scale)
+        # kernel loads its code object); its F and gradient at the start point
+        # compare the two methods
+        F, _, g = fn(uu, Uf)
+        first[kind] = (float(F.item()), g.double().cpu().numpy())
+        redo.ascent_step(uu, g, 1e3, -p.u_scale, p.u_scale)
         torch.cuda.synchronize()
         uu = u.clone()
         log(f"[bench] {kind} grape warmup done")
         t0 = time.perf_counter()
         for i in range(args.grape_iters):
             F, _, g = fn(uu, Uf)
-            # projected gradient ascent update (the accepted step of an iteration)
-            uu = torch.clamp(uu + 1e3 * g, -p.u_scale, p.u_scale)
+            # projected gradient ascent update (the accepted step of an iteration), in the library
+            redo.ascent_step(uu, g, 1e3, -p.u_scale, p.u_scale)
             torch.cuda.synchronize()
             log(f"[bench] {kind} grape iteration {i + 1}/{args.grape_iters}")
         elapsed = time.perf_counter() - t0
         res[kind] = dict(iters_per_s=args.grape_iters / elapsed, ms_per_iter=1e3 * elapsed / args.grape_iters,
                          fidelity=float(F.item()))
+    if "expm" in first:
+        gr, ge = first["redo"][1], first["expm"][1]
+        res["method"] = {
+            "point": "the workload's start pulse (Haar target, F ~ 1/d^2)",
+            "fidelity_redo": first["redo"][0], "fidelity_expm": first["expm"][0],
+            "grad_rel_l2_redo_vs_expm": float(np.linalg.norm(gr - ge) / np.linalg.norm(ge)),
+            "note": "REDO: quantised split steps, exact straight-through gradient; expm: unquantised unsplit "
+                    "steps, first-order GRAPE gradient"}
     del table
     return res
 
@@ -211,7 +239,8 @@ def bench_next(args, redo, W, torch):
     GEMMs) and state-transfer GRAPE on the GRAPE workload (target: the state the
     Haar target unitary makes of |0>)."""
     out = {}
-    B, K, Wm = args.realisations, args.steps, args.warmup
+    B, K = args.realisations, args.steps
+    Wm = window_warmup(args.warmup, K, args.reproject)
     p = W.ising_freezing(n=10, B=B, N=Wm + K)
     p.splitting = "strang"
     table = redo.RedoTable.from_problem(p)
@@ -250,13 +279,13 @@ def bench_next(args, redo, W, torch):
     psif = q.U_target[:, :, 0].copy()
     # warm-up: one whole iteration, the update included (torch loads its kernels on first use)
     _, _, g = table.state_grape(uq, psi0, psif)
-    uq = torch.clamp(uq + 1e3 * g, -q.u_scale, q.u_scale)
+    redo.ascent_step(uq, g, 1e3, -q.u_scale, q.u_scale)
     torch.cuda.synchronize()
     iters = 20
     t0 = time.perf_counter()
     for _ in range(iters):
         F, _, g = table.state_grape(uq, psi0, psif)
-        uq = torch.clamp(uq + 1e3 * g, -q.u_scale, q.u_scale)
+        redo.ascent_step(uq, g, 1e3, -q.u_scale, q.u_scale)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / iters
     # each step applies its one composed factor (8 d^2 bytes read) to the forward and the backward vector
@@ -317,37 +346,78 @@ def bench_sweep(args):
             "unit": "propagator steps/s", "full_grid_seconds_estimate": 5e9 / (steps / secs)}
 
 
-def cpu_baseline(args, W):
-    """The FP64 oracle on the host: REDO steps of one realisation of the same
-    workload, with the magnetisation at every step."""
-    import oracle as O
-    threads = None
+def blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max(i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas")
+        return max(i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas")
     except Exception:
-        threads = os.cpu_count()
-    n = args.cpu_steps
-    p = W.ising_freezing(n=10, B=1, N=n)
-    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+        return os.cpu_count()
+
+
+def oracle_accuracy(args, W, p, fr):
+    """The FP64 oracle on the host for realisation 0 of the headline workload,
+    over the steps the GPU ran: its REDO chain (Sec. II processes 1-2 with the
+    split step of Sec. III; timed, this is the CPU baseline) and its EXACT chain
+    (Sec. III, Eq. propUn: unsplit, unquantised), and the error of every GPU
+    line against them."""
+    import oracle as O
+    f32 = fr["fp32"]
+    n_r = f32["warmup_run"] + f32["steps"]
+    q = p.subset([0])
+    tab = O.DiscreteTable(q.S, q.dt, q.eps, q.base, q.digits)
     t0 = time.perf_counter()
-    steps = O.compose_all_redo(p, tab, 0)
-    O.magnetisation_series(steps, p.M)
+    m_redo, X_redo = O.magnetisation_series(O.compose_all_redo(q, tab, 0, n_steps=n_r), q.M)
     el = time.perf_counter() - t0
-    return dict(value=n / el, unit="realisation-steps/s", cores=int(threads), kind="oracle",
-                sample=f"1 realisation x {n} steps of the d=1024 Ising workload (REDO products, chain and "
-                       f"magnetisation in FP64 numpy), {el:.1f} s")
+    cpu = dict(value=n_r / el, unit="realisation-steps/s", cores=int(blas_threads()), kind="oracle",
+               sample=f"realisation 0 x {n_r} steps of the d=1024 Ising workload (REDO products, chain and "
+                      f"magnetisation in FP64 numpy), {el:.1f} s")
+    log(f"[bench] oracle REDO chain: {n_r} steps in {el:.1f} s")
+
+    def err(line, m_ref, X_ref):
+        n = len(m_ref)
+        return {"max_abs_dm": float(np.abs(line["mag0"][:n] - m_ref).max()),
+                "nfrob": None if X_ref is None else float(np.linalg.norm(line["x0"] - X_ref) / np.sqrt(p.d))}
+
+    acc = {"realisation": 0, "steps": n_r,
+           "bound_note": "FP32 products at K = 1024: ||dX||_F/sqrt(d) random-walks as ~1.6e-6 sqrt(products); "
+                         "the magnetisation gate is |dm| <= 1e-5"}
+    names = {"fp32": "headline", "lists": "row_list", "bf16x3": "bf16x3", "f32_4m": "f32_4m",
+             "kron": "structure_aware"}
+    for key, name in names.items():
+        if fr.get(key) is not None:
+            acc[name + "_vs_oracle"] = err(fr[key], m_redo, X_redo)
+    if not args.no_exact:
+        H0m = np.diag(q.H0[0]).astype(np.complex128)
+        t0 = time.perf_counter()
+        ex_steps = [O.step_exact(H0m, q.S, None, q.u[0, n].astype(np.float64), q.dt) for n in range(n_r)]
+        m_ex, X_ex = O.magnetisation_series(ex_steps, q.M)
+        el_x = time.perf_counter() - t0
+        log(f"[bench] oracle EXACT chain: {n_r} steps in {el_x:.1f} s")
+        acc["method_error_vs_exact"] = {
+            "steps": n_r,
+            "redo_oracle": {"max_abs_dm": float(np.abs(m_redo - m_ex).max()),
+                            "nfrob": float(np.linalg.norm(X_redo - X_ex) / np.sqrt(p.d))},
+            "headline_gpu": err(f32, m_ex, X_ex),
+            "exact_oracle_seconds": el_x}
+        ex = fr.get("expm")
+        if ex is not None:
+            n_e = ex["warmup_run"] + ex["steps"]
+            X_e = O.chain(ex_steps[:n_e])
+            acc["expm_vs_exact"] = dict(err(ex, m_ex[:n_e], X_e), steps=n_e,
+                                        headline_same_steps_max_abs_dm=float(np.abs(f32["mag0"][:n_e] - m_ex[:n_e]).max()))
+    return cpu, acc
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--realisations", type=int, default=4096)
     ap.add_argument("--reproject", type=int, default=64)
     ap.add_argument("--grape-iters", type=int, default=5)
-    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--no-exact", action="store_true",
+                    help="skip the oracle's EXACT chain (the method-error comparison)")
     ap.add_argument("--no-grape", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-4m", action="store_true", help="skip the four-product FP32 line")
@@ -398,7 +468,7 @@ def main():
     torch.cuda.empty_cache()
     sw = None if args.no_sweep else bench_sweep(args)
     torch.cuda.empty_cache()
-    cpu = None if args.no_cpu else cpu_baseline(args, W)
+    cpu, acc = (None, None) if (args.no_cpu or fr is None) else oracle_accuracy(args, W, p, fr)
     rg = None if gr is None else gr.get("redo")
     eg = None if gr is None else gr.get("expm")
     if fr is None:
@@ -418,6 +488,10 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": f32["ms_per_step"],
+        "timed_window": {"first_step": f32["warmup_run"] + 1, "last_step": f32["warmup_run"] + f32["steps"],
+                         "reprojections": f32["reprojections_timed"],
+                         "note": "untimed warm-up extended from --warmup so that the timed window holds a "
+                                 "re-projection step (one per 64 steps when --steps >= 64, else one in the window)"},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -436,6 +510,10 @@ def main():
                                                  "(Paterson-Stockmeyer), same batched FP32 MFMA GEMM (three real products), "
                                                  "same Walsh-frame magnetisation"},
         "speedup_vs_expm": None if ex is None else f32["value"] / ex["value"],
+        "max_abs_dm_vs_oracle": None if acc is None else acc["headline_vs_oracle"]["max_abs_dm"],
+        "nfrob_vs_oracle": None if acc is None else acc["headline_vs_oracle"]["nfrob"],
+        "method_error_vs_exact": None if acc is None else acc.get("method_error_vs_exact"),
+        "expm_error_vs_exact": None if acc is None else acc.get("expm_vs_exact"),
         "row_list_observable": None if ls is None else {
             "value": ls["value"], "unit": "propagator steps/s", "ms_per_step": ls["ms_per_step"],
             "method": "same chain in the computational basis, magnetisation from the row lists in two passes "
@@ -470,6 +548,7 @@ def main():
                                           **rg},
         "grape_expm_iters_per_s": None if eg is None else eg["iters_per_s"],
         "grape_speedup_vs_expm": None if (rg is None or eg is None) else rg["iters_per_s"] / eg["iters_per_s"],
+        "grape_method_comparison": None if gr is None else gr.get("method"),
         "d64_chain": c2,
         "paper_freezing_sweep_d8": sw,
         "strang": None if nx is None else nx["strang"],
@@ -482,9 +561,13 @@ def main():
                      "traffic": gemm_traffic(args.realisations, args.cache), "traffic_unit": "HBM bytes per launch",
                      "flops_per_launch": f32["flops_per_launch"], "avg_launch_ms": f32["avg_launch_ms"],
                      "launches": f32["gemm_launches"],
-                     "flops_note": "6 d^3 real flops per complex product (the Gauss form's own count); "
-                                   "the four-product form would be 8 d^3"},
+                     "flops_note": "6 d^3 real flops per complex product (the Gauss form's own count; the "
+                                   "four-product form would be 8 d^3), over the step products of the timed "
+                                   "window and the two products per realisation of its re-projection step; "
+                                   "launches = one per step plus two per 256-realisation chunk of a "
+                                   "re-projection"},
         "cpu_baseline": cpu,
+        "accuracy_vs_oracle": acc,
     }
     print(json.dumps(out), flush=True)
 

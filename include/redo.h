@@ -57,7 +57,8 @@ typedef enum {
     REDO_ERR_NONFINITE = 5,      /* a non-finite amplitude was seen on the device */
     REDO_ERR_UNSUPPORTED = 6,    /* valid, but not provided by this build */
     REDO_ERR_WORKSPACE = 7,      /* workspace smaller than redo_workspace_bytes */
-    REDO_WARN_CLAMPED = 100      /* some amplitude exceeded (b^P - 1) eps and was clamped */
+    REDO_WARN_CLAMPED = 100,     /* some amplitude exceeded (b^P - 1) eps and was clamped */
+    REDO_WARN_UNITARITY = 101    /* at a re-projection step a state had ||X^dag X - I||_F / sqrt(d) > 1e-3 */
 } redo_status;
 
 typedef enum {
@@ -334,7 +335,10 @@ redo_status redo_grape_fidelity_grad(redo_table table, int32_t precision, const 
  * and the backward scan chi_{n-1} = U_n^dag chi_n, chi_N = psi_f, with the trace
  * identities of redo_grape_fidelity_grad on the rank-one Y_n = psi_n chi_n^dag
  * (no normalisation: g = <psi_f|psi_N>).  Every product is a batched
- * matrix-vector product (FP32, REDO_PREC_F32 only); every state is kept, and
+ * matrix-vector product of an FP32 factor (REDO_PREC_F32 only) with an FP64
+ * vector, summed in FP64 (psi_n, chi_n and the phase scalings are FP64, so
+ * only the factors' FP32 rounding accumulates); d <= 8192
+ * (REDO_ERR_UNSUPPORTED beyond); every state is kept, and
  * when every step's plan fits (N_max <= 65535) each launch applies one factor
  * of forward step n and one of backward step N_max - 1 - n together.
  * Same channel conditions as redo_grape_fidelity_grad.  B <= 32767
@@ -385,10 +389,23 @@ redo_status redo_expm_grape_fidelity_grad(redo_table table, int32_t precision, c
 /*
  * Waits for `stream`, then reports and clears the conditions latched by the
  * device since the last call: REDO_ERR_NONFINITE if a non-finite amplitude
- * was seen, else REDO_WARN_CLAMPED if any amplitude was clamped, else REDO_OK.
+ * was seen, else REDO_WARN_UNITARITY if the unitarity watchdog fired, else
+ * REDO_WARN_CLAMPED if any amplitude was clamped, else REDO_OK.
  * *n_clamped (host, nullable) receives the number of clamped amplitudes.
+ * The watchdog: at every re-projection step of a chain (reproject_every > 0;
+ * the state is a product of unitary steps, Sec. III Eq. propUn, so FP32
+ * rounding is the only way off the unitary group), the drift
+ * ||X^dag X - I||_F / sqrt(d) of each instance's state is measured in FP64
+ * before the Newton-Schulz step; instances above 1e-3 are counted, and the
+ * largest drift seen is kept (redo_unitarity_report).
  */
 redo_status redo_get_device_status(redo_table table, void* stream, int64_t* n_clamped);
+
+/* The unitarity watchdog as read by the last redo_get_device_status on this
+ * table: the largest drift ||X^dag X - I||_F / sqrt(d) seen at a re-projection
+ * step and the number of (instance, step) pairs above 1e-3 (host outputs,
+ * nullable).  No GPU work. */
+redo_status redo_unitarity_report(redo_table table, double* max_drift, int64_t* count);
 
 /*
  * ---- Learned warm start (not part of the paper's method) ----
@@ -458,6 +475,19 @@ redo_status redo_lbfgs_push(int32_t B, int64_t P, int32_t m, const float* x, con
 redo_status redo_adam_update(int64_t n, float* param, uint16_t* param_bf16, const float* grad, float* m,
                              float* v, float lr, float beta1, float beta2, float eps, int32_t step, float sign,
                              float lo, float hi, void* stream);
+
+/* One projected gradient-ascent step of REDO-GRAPE (the update of Sec. III's
+ * GRAPE loop with the amplitude constraint as a clamp): param <- clamp(param +
+ * alpha grad, lo, hi) elementwise on n floats (device).  REDO_ERR_ARG for n < 1,
+ * NULL pointers or lo > hi. */
+redo_status redo_ascent_step(int64_t n, float* param, const float* grad, float alpha, float lo, float hi,
+                             void* stream);
+
+/* Time average of an observable series (Sec. IV: the order parameter Q is the
+ * mean of the magnetisation response over the time points): out[r] = mean of
+ * in[r][0 .. cols-1], FP64 (device arrays in double [rows][cols], out double
+ * [rows]); the summation order is fixed.  REDO_ERR_ARG for empty sizes or NULL. */
+redo_status redo_time_average(int32_t rows, int32_t cols, const double* in, double* out, void* stream);
 
 /* Round n floats to BF16 (nearest even). */
 redo_status redo_to_bf16(int64_t n, const float* in, uint16_t* out, void* stream);

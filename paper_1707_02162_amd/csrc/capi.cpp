@@ -2,6 +2,7 @@
 // the one-time FP64 table build (Sec. II, process 1), workspace sizing and
 // dispatch to the small-d fused kernels or the large-d MFMA path.
 #include <algorithm>
+#include <cstdio>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -20,6 +21,8 @@ redo_status fail(redo_status st, const std::string& msg) {
     g_last_error = msg;
     return st;
 }
+
+void clear_last_error() { g_last_error.clear(); }
 
 redo_status hip_fail(hipError_t e, const char* what) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
@@ -141,6 +144,7 @@ const char* redo_status_string(redo_status s) {
         case REDO_ERR_UNSUPPORTED: return "unsupported";
         case REDO_ERR_WORKSPACE: return "workspace too small";
         case REDO_WARN_CLAMPED: return "amplitudes clamped";
+        case REDO_WARN_UNITARITY: return "state drifted off unitarity";
         default: return "unknown status";
     }
 }
@@ -923,8 +927,27 @@ redo_status redo_get_device_status(redo_table t, void* stream, int64_t* n_clampe
     REDO_HIP(hipMemcpy(&f, t->flags, sizeof(f), hipMemcpyDeviceToHost));
     REDO_HIP(hipMemset(t->flags, 0, sizeof(DeviceFlags)));
     if (n_clamped) *n_clamped = (int64_t)f.clamped;
+    double drift = 0.0;
+    static_assert(sizeof(drift) == sizeof(f.max_drift), "drift bits");
+    std::memcpy(&drift, &f.max_drift, sizeof(drift));
+    t->drift_max = drift;
+    t->drift_count = (long long)f.unitarity;
     if (f.nonfinite) return fail(REDO_ERR_NONFINITE, "a non-finite amplitude was seen");
+    if (f.unitarity) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "%u re-projection step(s) found ||X^dag X - I||_F / sqrt(d) above %g (largest %.3e)",
+                      f.unitarity, UNITARITY_WARN, drift);
+        return fail(REDO_WARN_UNITARITY, msg);
+    }
     if (f.clamped) return REDO_WARN_CLAMPED;
+    return REDO_OK;
+}
+
+redo_status redo_unitarity_report(redo_table t, double* max_drift, int64_t* count) {
+    g_last_error.clear();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    if (max_drift) *max_drift = t->drift_max;
+    if (count) *count = (int64_t)t->drift_count;
     return REDO_OK;
 }
 

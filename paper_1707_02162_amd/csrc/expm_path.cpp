@@ -243,6 +243,7 @@ redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int
                 const int ch = std::min(256, B - b0);
                 REDO_HIP(reproject_descs(descs, ch, b0, X[0], X[1], nn, Z, nn, loc, n_steps, n, 0, st));
                 REDO_HIP(cgemm_batched(d, ch, descs, prec, st, 1));
+                REDO_HIP(unitarity_check(d, ch, b0, Z, nn, n_steps, n, t->flags, st));
                 REDO_HIP(reproject_descs(descs, ch, b0, X[0], X[1], nn, Z, nn, loc, n_steps, n, 1, st));
                 REDO_HIP(cgemm_batched(d, ch, descs, prec, st, 1));
             }

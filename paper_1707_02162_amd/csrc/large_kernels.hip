@@ -159,6 +159,31 @@ __global__ void reproject_descs_kernel(GemmDesc* descs, int count, int b0, float
     descs[i] = g;
 }
 
+// unitarity watchdog of a re-projection step: Z_b = 3/2 I - X^dag X / 2 holds the Gram
+// matrix, so ||X^dag X - I||_F = 2 ||I - Z_b||_F; one workgroup per active instance, FP64 sum
+__global__ __launch_bounds__(256) void unitarity_check_kernel(int d, const float2* __restrict__ Z, long long zstride,
+                                                              const int* n_steps, int b0, int step, DeviceFlags* flags) {
+    const int i = blockIdx.x;
+    const int b = b0 + i;
+    if (n_steps && step >= n_steps[b]) return;
+    const float2* z = Z + (long long)i * zstride;
+    const long long nn = (long long)d * d;
+    double s = 0.0;
+    for (long long e = threadIdx.x; e < nn; e += 256) {
+        const float2 v = z[e];
+        const double er = (e / d == e % d ? 1.0 : 0.0) - (double)v.x, ei = v.y;
+        s += er * er + ei * ei;
+    }
+    __shared__ double part[256];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) report_drift(flags, 2.0 * sqrt(part[0] / d));
+}
+
 // copies the states that ended in buffer 1 back to buffer 0
 __global__ void gather_back_kernel(long long nn, float2* X0, const float2* X1, long long xstride, const int* loc) {
     const int b = blockIdx.y;
@@ -1233,6 +1258,12 @@ hipError_t reproject_descs(GemmDesc* descs, int count, int b0, float2* X0, float
                            long long zstride, int* loc, const int* n_steps, int step, int phase, hipStream_t st) {
     hipLaunchKernelGGL(reproject_descs_kernel, dim3((count + 63) / 64), dim3(64), 0, st, descs, count, b0, X0, X1,
                        xstride, Z, zstride, loc, n_steps, step, phase);
+    return hipGetLastError();
+}
+
+hipError_t unitarity_check(int d, int count, int b0, const float2* Z, long long zstride, const int* n_steps, int step,
+                           DeviceFlags* flags, hipStream_t st) {
+    hipLaunchKernelGGL(unitarity_check_kernel, dim3(count), dim3(256), 0, st, d, Z, zstride, n_steps, b0, step, flags);
     return hipGetLastError();
 }
 

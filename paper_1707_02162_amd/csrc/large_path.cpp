@@ -336,6 +336,7 @@ redo_status large_chain(redo_table_s* t, int precision, const float* u, const in
                 const int ch = std::min(REPROJECT_CHUNK, B - b0);
                 REDO_HIP(reproject_descs(w.descs, ch, b0, X[0], X[1], mat, w.Z, mat, w.loc, n_steps, n, 0, st));
                 REDO_HIP(cgemm_batched(d, ch, w.descs, prec, st));
+                REDO_HIP(unitarity_check(d, ch, b0, w.Z, mat, n_steps, n, t->flags, st));
                 REDO_HIP(reproject_descs(w.descs, ch, b0, X[0], X[1], mat, w.Z, mat, w.loc, n_steps, n, 1, st));
                 REDO_HIP(cgemm_batched(d, ch, w.descs, prec, st));
             }

@@ -43,8 +43,19 @@ __device__ inline double2 expmi(double x) {
 struct DeviceFlags {
     unsigned long long clamped;
     unsigned int nonfinite;
-    unsigned int pad;
+    unsigned int unitarity;           // re-projection steps whose state drifted off unitarity
+    unsigned long long max_drift;     // bits of the largest ||X^dag X - I||_F / sqrt(d) seen (a non-negative double)
 };
+
+// the unitarity watchdog: a state whose ||X^dag X - I||_F / sqrt(d) exceeds this at a
+// re-projection step is counted (the Newton-Schulz step still runs)
+constexpr double UNITARITY_WARN = 1e-3;
+
+__device__ inline void report_drift(DeviceFlags* f, double drift) {
+    if (!f) return;
+    atomicMax(&f->max_drift, (unsigned long long)__double_as_longlong(drift));
+    if (!(drift <= UNITARITY_WARN)) atomicAdd(&f->unitarity, 1u);   // NaN counts too
+}
 
 // ---------------------------------------------------------------------------
 // Coarse graining (Sec. II, Eq. cgrain): the one place where floating point
@@ -109,6 +120,8 @@ struct redo_table_s {
     std::vector<double> s_norm;  // ||S_k||_1
     redo::DeviceFlags* flags = nullptr;
     size_t bytes = 0;
+    double drift_max = 0.0;       // unitarity watchdog as read by the last redo_get_device_status
+    long long drift_count = 0;
     bool grad_ok = false;   // channels commute with each other, phases with drift
     std::string grad_why;
     // composed level cache (process 3): R(q) for q in [cache_lo, cache_hi]
@@ -132,6 +145,7 @@ namespace redo {
 
 // error reporting (thread-local string)
 redo_status fail(redo_status st, const std::string& msg);
+void clear_last_error();
 redo_status hip_fail(hipError_t e, const char* what);
 
 #define REDO_HIP(call)                                          \

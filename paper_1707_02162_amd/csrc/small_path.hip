@@ -361,10 +361,13 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
     }
 }
 
-// Newton-Schulz polar step x <- x (3I - x^dag x) / 2  (uniform barriers)
+// Newton-Schulz polar step x <- x (3I - x^dag x) / 2  (uniform barriers); the
+// watchdog counts an instance whose ||x^dag x - I||_F / sqrt(D) exceeds UNITARITY_WARN
 template <int D>
-__device__ void reproject(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float2* Fs, bool active, int ti, int tj) {
+__device__ void reproject(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float2* Fs, bool active, int ti, int tj,
+                          double* red, DeviceFlags* flags, bool leader) {
     constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
+    double dev2 = 0.0;
     __syncthreads();
     if (active) store_block<D>(Xs, x, ti, tj);
     __syncthreads();
@@ -390,11 +393,15 @@ __device__ void reproject(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float
         for (int r = 0; r < TB; ++r)
 #pragma unroll
             for (int c = 0; c < TB; ++c) {
+                const double er = (double)z[r][c].x - (ti + NT * r == tj + NT * c ? 1.0 : 0.0), ei = z[r][c].y;
+                dev2 += er * er + ei * ei;
                 z[r][c] = make_float2(-0.5f * z[r][c].x, -0.5f * z[r][c].y);
                 if (ti + NT * r == tj + NT * c) z[r][c].x += 1.5f;
             }
         store_block<D>(Fs, z, ti, tj);
     }
+    dev2 = inst_sum<D>(dev2, red);
+    if (active && leader) report_drift(flags, sqrt(dev2 / D));
     __syncthreads();
     if (active) mul_left<D>(x, Xs, Fs, ti, tj);
 }
@@ -466,7 +473,7 @@ __global__ __launch_bounds__(256) void small_chain_kernel(TView tv, SmallChainAr
         const bool active = valid && n < len;
         step_left<D>(tv, x, Xs, Fs, ub + (long long)n * tv.K * KK, drift, active, lt == 0, lt, ti, tj);
         if (a.reproject_every > 0 && !a.compose && ((a.step_offset + n + 1) % a.reproject_every) == 0)
-            reproject<D>(x, Xs, Fs, active, ti, tj);
+            reproject<D>(x, Xs, Fs, active, ti, tj, red, tv.flags, lt == 0);
         if (a.X_prefix && active) {
             float2* dst = a.X_prefix + ((long long)b * a.N_max + n) * D * D;
 #pragma unroll

@@ -8,7 +8,10 @@
 //     dg/dOmega_kn = -i dt chi_n^dag Z S_k Z^dag psi_n,
 //     dg/dphi_kn   = -i (chi_n^dag G_k psi_n - chi_{n-1}^dag G_k psi_{n-1}),
 // g = <psi_f|psi_N>, dF_S = 2 Re(conj(g) dg).  Every product is a batched
-// matrix-vector product over the instances; traces accumulate in FP64.
+// matrix-vector product over the instances: the factors are the FP32 table
+// entries, the vectors psi_n and chi_n, the phase scalings and the products'
+// sums are FP64, so each factor application adds only the rounding of its
+// stored factor; traces accumulate in FP64.
 #include <algorithm>
 #include <cstring>
 #include <string>
@@ -19,18 +22,19 @@ namespace redo {
 namespace {
 
 struct MvDesc {
-    const float2* F;      // d x d factor, or null (identity)
-    const float2* pre;    // scaling of the input vector, or null
-    const float2* post;   // scaling of the output vector, or null
-    const float2* x;
-    float2* y;
+    const float2* F;      // d x d factor (FP32), or null (identity)
+    const double2* pre;   // scaling of the input vector, or null
+    const double2* post;  // scaling of the output vector, or null
+    const double2* x;
+    double2* y;
     int adj;              // 1: y = post . F^dag (pre . x)
     int conj_scales;      // 1: conj(pre), conj(post)
 };
 
 // y = post . op(F) (pre . x), one workgroup of 16 waves per 16 rows of y reading those
 // rows of op(F) whole (16 d complex entries, 128 KiB at d = 1024) in blocks of 16
-// independent loads per thread, the scaled input in LDS: nothing leaves the workgroup
+// independent loads per thread, the scaled input in LDS (FP64, 16 d bytes), FP64
+// products and sums of the FP32 factor entries: nothing leaves the workgroup
 // before the result, so one factor application is one launch and the summation order
 // is fixed.  blockIdx.y runs over the instances of up to two independent chains, the
 // forward chain and the backward scan: y < B takes descs0[y], y >= B descs1[y - B].
@@ -49,20 +53,30 @@ __device__ inline float2 mv_load(const float2* p, long long i) {
     return make_float2(v.x, v.y);
 }
 
-__device__ inline float2 mv_scale(const MvDesc& m, const float2* s, int i) {
-    const float2 p = s[i];
-    return m.conj_scales ? cconj(p) : p;
+__device__ inline double2 mv_scale(const MvDesc& m, const double2* s, int i) {
+    const double2 p = s[i];
+    return m.conj_scales ? zconj(p) : p;
 }
 
-__device__ inline float2 mv_input(const MvDesc& m, int c) {
-    const float2 v = m.x[c];
-    return m.pre ? cmul(mv_scale(m, m.pre, c), v) : v;
+__device__ inline double2 mv_input(const MvDesc& m, int c) {
+    const double2 v = m.x[c];
+    return m.pre ? zmul(mv_scale(m, m.pre, c), v) : v;
+}
+
+// a += f x and a += conj(f) x in FP64, f an FP32 factor entry
+__device__ inline void zfma_f(double2& a, float2 f, double2 x) {
+    a.x += (double)f.x * x.x - (double)f.y * x.y;
+    a.y += (double)f.x * x.y + (double)f.y * x.x;
+}
+__device__ inline void zfma_fc(double2& a, float2 f, double2 x) {
+    a.x += (double)f.x * x.x + (double)f.y * x.y;
+    a.y += (double)f.x * x.y - (double)f.y * x.x;
 }
 
 __global__ __launch_bounds__(MV_NT) void matvec_kernel(int d, const MvDesc* __restrict__ descs0,
                                                        const MvDesc* __restrict__ descs1, int B) {
-    extern __shared__ float2 xs[];   // [d]: pre . x
-    __shared__ float2 red[MV_NT / 64][MV_R];
+    extern __shared__ double2 xs[];   // [d]: pre . x
+    __shared__ double2 red[MV_NT / 64][MV_R];
     const int z = blockIdx.y;
     const MvDesc m = z < B ? descs0[z] : descs1[z - B];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -70,15 +84,15 @@ __global__ __launch_bounds__(MV_NT) void matvec_kernel(int d, const MvDesc* __re
     if (!m.F) {   // identity factor: copy with the scalings
         const int r = r0 + t;
         if (t < MV_R && r < d) {
-            float2 v = mv_input(m, r);
-            if (m.post) v = cmul(mv_scale(m, m.post, r), v);
+            double2 v = mv_input(m, r);
+            if (m.post) v = zmul(mv_scale(m, m.post, r), v);
             m.y[r] = v;
         }
         return;
     }
     for (int c = t; c < d; c += MV_NT) xs[c] = mv_input(m, c);
     __syncthreads();
-    float2 acc = make_float2(0.f, 0.f);
+    double2 acc = make_double2(0.0, 0.0);
     if (m.adj) {
         // y_r = sum_c conj(F[c][r]) x_c: lanes over the MV_R rows (one segment of row c of F)
         // and 64 / MV_R column groups, waves over the others (64 in all); column c = 64 j + group
@@ -94,7 +108,7 @@ __global__ __launch_bounds__(MV_NT) void matvec_kernel(int d, const MvDesc* __re
 #pragma unroll
             for (int j = 0; j < MV_U; ++j) {
                 const int c = cb + cg + 64 * j;
-                if (c < d) cfma(acc, cconj(f[j]), xs[c]);
+                if (c < d) zfma_fc(acc, f[j], xs[c]);
             }
         }
 #pragma unroll
@@ -118,7 +132,7 @@ __global__ __launch_bounds__(MV_NT) void matvec_kernel(int d, const MvDesc* __re
 #pragma unroll
             for (int j = 0; j < MV_U; ++j) {
                 const int c = cb + lane + 64 * j;
-                if (c < d) cfma(acc, f[j], xs[c]);
+                if (c < d) zfma_f(acc, f[j], xs[c]);
             }
         }
 #pragma unroll
@@ -131,12 +145,12 @@ __global__ __launch_bounds__(MV_NT) void matvec_kernel(int d, const MvDesc* __re
     __syncthreads();
     const int r = r0 + t;
     if (t < MV_R && r < d) {
-        float2 v = red[0][t];
+        double2 v = red[0][t];
         if (m.adj) {
 #pragma unroll
-            for (int w = 1; w < MV_NT / 64; ++w) v = cadd(v, red[w][t]);
+            for (int w = 1; w < MV_NT / 64; ++w) v = make_double2(v.x + red[w][t].x, v.y + red[w][t].y);
         }
-        if (m.post) v = cmul(mv_scale(m, m.post, r), v);
+        if (m.post) v = zmul(mv_scale(m, m.post, r), v);
         m.y[r] = v;
     }
 }
@@ -154,12 +168,12 @@ struct StatePlan {
     int d, K, P, base, n_drift, phased, dense, strang, cache_levels, all_cached, slots, N, step, backward;
     int all;                // 1: grid (B, N), every step and both directions in one launch
     double dt;
-    float2* Psi;            // forward vectors [B][N + 1][d]
-    float2* Chi;            // backward vectors [B][N + 1][d]
+    double2* Psi;           // forward vectors [B][N + 1][d] (FP64)
+    double2* Chi;           // backward vectors [B][N + 1][d] (FP64)
     long long vs;           // per-instance stride of Psi and Chi
-    float2* tmp0;           // [2][B][d] ping-pong for the slots in between, per direction
-    float2* tmp1;
-    float2 *pre, *post, *pstar;   // [B][d] per planned step
+    double2* tmp0;          // [2][B][d] ping-pong for the slots in between, per direction
+    double2* tmp1;
+    double2 *pre, *post, *pstar;  // [B][d] per planned step (FP64 phases)
     MvDesc* descs;          // [slots][B] per planned step and direction
     int B;
 };
@@ -173,9 +187,9 @@ __global__ void state_plan_kernel(StatePlan a) {
     const int b = blockIdx.x, d = a.d;
     const int step = a.all ? (int)blockIdx.y : a.step;
     const long long so = a.all ? (long long)step * a.B * d : 0;
-    float2* pre = a.pre + so;
-    float2* post = a.post + so;
-    float2* pstar = a.pstar + so;
+    double2* pre = a.pre + so;
+    double2* post = a.post + so;
+    double2* pstar = a.pstar + so;
     const bool active = a.n_steps ? step < a.n_steps[b] : true;
     const int* cb = a.codes + ((long long)b * a.N + step) * a.K;
     const double* pb = a.phi ? a.phi + ((long long)b * a.N + step) * a.K : nullptr;
@@ -186,19 +200,18 @@ __global__ void state_plan_kernel(StatePlan a) {
             for (int k = 0; k < a.K; ++k) th += pb[k] * a.g[(long long)k * d + r];
         const double hd = (!a.dense && a.strang) ? 0.5 * a.dt * a.h[(long long)drift * d + r] : 0.0;
         const double2 po = expmi(th + hd);
-        post[(long long)b * d + r] = make_float2((float)po.x, (float)po.y);
-        pstar[(long long)b * d + r] = make_float2((float)po.x, (float)-po.y);
+        post[(long long)b * d + r] = po;
+        pstar[(long long)b * d + r] = zconj(po);
         if (!a.dense) {
             const double hdt = a.strang ? 0.5 * a.dt : a.dt;
-            const double2 pr = expmi(hdt * a.h[(long long)drift * d + r] - th);
-            pre[(long long)b * d + r] = make_float2((float)pr.x, (float)pr.y);
+            pre[(long long)b * d + r] = expmi(hdt * a.h[(long long)drift * d + r] - th);
         }
     }
     if (threadIdx.x != 0) return;
     const int S = a.slots;
     for (int dir = a.all ? 0 : a.backward; dir <= (a.all ? 1 : a.backward); ++dir) {
-        const float2* src = dir ? a.Chi + (long long)(step + 1) * d : a.Psi + (long long)step * d;
-        float2* dst = dir ? a.Chi + (long long)step * d : a.Psi + (long long)(step + 1) * d;
+        const double2* src = dir ? a.Chi + (long long)(step + 1) * d : a.Psi + (long long)step * d;
+        double2* dst = dir ? a.Chi + (long long)step * d : a.Psi + (long long)(step + 1) * d;
         MvDesc* out = a.all ? a.descs + (long long)(dir * a.N + step) * S * a.B : a.descs;
         for (int i = 0; i < S; ++i) {
             // forward slot index of the i-th application
@@ -228,8 +241,8 @@ __global__ void state_plan_kernel(StatePlan a) {
                 m.adj = dir ? 1 - fadj : fadj;
                 // the scalings of the forward step: pre before slot 0 (diagonal drift), Z^dag after
                 // the dense drift (slot 0), Z (times the second half drift, Strang) after the last slot
-                const float2* fpre = (!a.dense && s == 0) ? pre + (long long)b * d : nullptr;
-                const float2* fpost = nullptr;
+                const double2* fpre = (!a.dense && s == 0) ? pre + (long long)b * d : nullptr;
+                const double2* fpost = nullptr;
                 if (a.dense && s == 0 && a.phased) fpost = pstar + (long long)b * d;
                 if (s == S - 1 && (a.phased || a.strang) && !(a.dense && s == 0)) fpost = post + (long long)b * d;
                 if (!dir) {
@@ -250,10 +263,10 @@ __global__ void state_plan_kernel(StatePlan a) {
 //   T1 = chi^dag S^psi psi, T2 = chi^dag S^{pi/2} psi (phased, q = 0), D = chi^dag G psi,
 // with S^psi_aj = exp(-i psi (g_a - g_j)) S_aj (times exp(-i dt/2 (h_a - h_j)), Strang).
 // One workgroup per (instance, step); the column phases ride on psi (rounded to FP32 in
-// LDS), the row phases on chi; sums in FP64.
+// LDS: these traces enter only the gradient), the row phases on chi; sums in FP64.
 __global__ __launch_bounds__(256) void state_trace_kernel(int d, int N, int K, int phased, int strang, double dt,
-                                                          int n_drift, const float2* __restrict__ Psi,
-                                                          const float2* __restrict__ Chi, long long vs,
+                                                          int n_drift, const double2* __restrict__ Psi,
+                                                          const double2* __restrict__ Chi, long long vs,
                                                           const float2* __restrict__ S32, const int* spc,
                                                           const double2* spv, int sw, const double* g,
                                                           const double* h, const int* codes, const double* phi,
@@ -262,8 +275,8 @@ __global__ __launch_bounds__(256) void state_trace_kernel(int d, int N, int K, i
     __shared__ double red[6][256];
     const int s = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
     const bool active = n_steps ? s < n_steps[b] : true;
-    const float2* psi = Psi + (long long)b * vs + (long long)(s + 1) * d;
-    const float2* chi = Chi + (long long)b * vs + (long long)(s + 1) * d;
+    const double2* psi = Psi + (long long)b * vs + (long long)(s + 1) * d;
+    const double2* chi = Chi + (long long)b * vs + (long long)(s + 1) * d;
     const long long hb = (long long)(b % n_drift) * d;
     for (int k = 0; k < K; ++k) {
         const long long ci = ((long long)b * N + s) * K + k;
@@ -275,7 +288,7 @@ __global__ __launch_bounds__(256) void state_trace_kernel(int d, int N, int K, i
         for (int j = tid; j < d; j += 256) {
             const double gj = phased ? g[(long long)k * d + j] : 0.0;
             const double hj = strang ? h[hb + j] : 0.0;
-            const float2 x = psi[j];
+            const double2 x = psi[j];
             const double2 e1 = zconj(expmi(ps * gj + hdt * hj));
             pv[j] = make_float2((float)(e1.x * x.x - e1.y * x.y), (float)(e1.x * x.y + e1.y * x.x));
             if (origin) {
@@ -289,7 +302,7 @@ __global__ __launch_bounds__(256) void state_trace_kernel(int d, int N, int K, i
             for (int a = tid; a < d; a += 256) {
                 const double ga = phased ? g[(long long)k * d + a] : 0.0;
                 const double ha = strang ? h[hb + a] : 0.0;
-                const float2 c = chi[a];
+                const double2 c = chi[a];
                 // row factor conj(chi_a) exp(-i (psi g_a + dt/2 h_a))
                 const double2 ra = zmul(make_double2(c.x, -c.y), expmi(ps * ga + hdt * ha));
                 double s1r = 0, s1i = 0, s2r = 0, s2i = 0;
@@ -328,10 +341,10 @@ __global__ __launch_bounds__(256) void state_trace_kernel(int d, int N, int K, i
                     v[3] += ra2.x * s2i + ra2.y * s2r;
                 }
                 if (phased) {
-                    const float2 x = psi[a];
+                    const double2 x = psi[a];
                     // conj(chi_a) g_a psi_a
-                    v[4] += ga * ((double)c.x * x.x + (double)c.y * x.y);
-                    v[5] += ga * ((double)c.x * x.y - (double)c.y * x.x);
+                    v[4] += ga * (c.x * x.x + c.y * x.y);
+                    v[5] += ga * (c.x * x.y - c.y * x.x);
                 }
             }
 #pragma unroll
@@ -348,15 +361,16 @@ __global__ __launch_bounds__(256) void state_trace_kernel(int d, int N, int K, i
 }
 
 // overlap g = <psi_f|psi_N> (FP64), F_S = |g|^2; D_0 = chi_0^dag G psi_0; nu = 1
-__global__ void state_final_kernel(int d, int K, int phased, const float2* psif, const float2* Psi, const float2* Chi,
-                                   long long vs, int N, const int* n_steps, const double* g, double2* ov,
-                                   double* fidelity, double* d0, double* nu) {
+__global__ void state_final_kernel(int d, int K, int phased, const float2* psif, const double2* Psi,
+                                   const double2* Chi, long long vs, int N, const int* n_steps, const double* g,
+                                   double2* ov, double* fidelity, double* d0, double* nu) {
     const int b = blockIdx.x, tid = threadIdx.x;
     __shared__ double red[2][256];
-    const float2* pn = Psi + (long long)b * vs + (long long)N * d;
+    const double2* pn = Psi + (long long)b * vs + (long long)N * d;
     double gr = 0, gi = 0;
     for (int a = tid; a < d; a += 256) {
-        const float2 f = psif[(long long)b * d + a], x = pn[a];
+        const float2 f = psif[(long long)b * d + a];
+        const double2 x = pn[a];
         gr += (double)f.x * x.x + (double)f.y * x.y;
         gi += (double)f.x * x.y - (double)f.y * x.x;
     }
@@ -375,17 +389,17 @@ __global__ void state_final_kernel(int d, int K, int phased, const float2* psif,
         if (fidelity) fidelity[b] = red[0][0] * red[0][0] + red[1][0] * red[1][0];
         nu[b] = 1.0;
     }
-    const float2* p0 = Psi + (long long)b * vs;
-    const float2* c0 = Chi + (long long)b * vs;
+    const double2* p0 = Psi + (long long)b * vs;
+    const double2* c0 = Chi + (long long)b * vs;
     for (int k = 0; k < K; ++k) {
         __syncthreads();
         double dr = 0, di = 0;
         if (phased)
             for (int a = tid; a < d; a += 256) {
                 const double ga = g[(long long)k * d + a];
-                const float2 c = c0[a], x = p0[a];
-                dr += ga * ((double)c.x * x.x + (double)c.y * x.y);
-                di += ga * ((double)c.x * x.y - (double)c.y * x.x);
+                const double2 c = c0[a], x = p0[a];
+                dr += ga * (c.x * x.x + c.y * x.y);
+                di += ga * (c.x * x.y - c.y * x.x);
             }
         red[0][tid] = dr;
         red[1][tid] = di;
@@ -404,10 +418,19 @@ __global__ void state_final_kernel(int d, int K, int phased, const float2* psif,
     }
 }
 
+// widens the caller's c64 vectors [B][d] into the FP64 chain arrays (instance stride vs)
+__global__ void widen_kernel(int d, const float2* __restrict__ in, double2* __restrict__ out, long long vs) {
+    const int b = blockIdx.y;
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= d) return;
+    const float2 v = in[(long long)b * d + a];
+    out[(long long)b * vs + a] = make_double2(v.x, v.y);
+}
+
 struct StateWS {
     int* codes;
     double* phi;
-    float2 *Psi, *Chi, *tmp0, *tmp1, *pre, *post, *pstar;
+    double2 *Psi, *Chi, *tmp0, *tmp1, *pre, *post, *pstar;
     MvDesc* descs;
     double *tr, *d0, *nu;
     double2* ov;
@@ -423,13 +446,13 @@ struct StateWS {
         };
         codes = reinterpret_cast<int*>(take(sizeof(int) * (size_t)B * N * K));
         phi = reinterpret_cast<double*>(take(sizeof(double) * (size_t)B * N * K));
-        Psi = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * (N + 1) * d));
-        Chi = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)B * (N + 1) * d));
-        tmp0 = reinterpret_cast<float2*>(take(sizeof(float2) * 2 * (size_t)B * d));
-        tmp1 = reinterpret_cast<float2*>(take(sizeof(float2) * 2 * (size_t)B * d));
-        pre = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)plan_steps * B * d));
-        post = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)plan_steps * B * d));
-        pstar = reinterpret_cast<float2*>(take(sizeof(float2) * (size_t)plan_steps * B * d));
+        Psi = reinterpret_cast<double2*>(take(sizeof(double2) * (size_t)B * (N + 1) * d));
+        Chi = reinterpret_cast<double2*>(take(sizeof(double2) * (size_t)B * (N + 1) * d));
+        tmp0 = reinterpret_cast<double2*>(take(sizeof(double2) * 2 * (size_t)B * d));
+        tmp1 = reinterpret_cast<double2*>(take(sizeof(double2) * 2 * (size_t)B * d));
+        pre = reinterpret_cast<double2*>(take(sizeof(double2) * (size_t)plan_steps * B * d));
+        post = reinterpret_cast<double2*>(take(sizeof(double2) * (size_t)plan_steps * B * d));
+        pstar = reinterpret_cast<double2*>(take(sizeof(double2) * (size_t)plan_steps * B * d));
         descs = reinterpret_cast<MvDesc*>(take(sizeof(MvDesc) * (size_t)(plan_steps > 1 ? 2 : 1) * plan_steps * B * slots));
         tr = reinterpret_cast<double*>(take(sizeof(double) * (size_t)B * N * K * 6));
         d0 = reinterpret_cast<double*>(take(sizeof(double) * (size_t)B * K * 2));
@@ -449,9 +472,11 @@ int state_slots(const redo_table_s* t) {
 
 // every step planned in one launch when its scale vectors and descriptors take at most this much
 constexpr size_t STATE_PLAN_ALL_BYTES = size_t(256) << 20;
+// the matrix-vector kernel keeps the FP64 input vector in LDS (16 d bytes)
+constexpr int STATE_MAX_D = 8192;
 
 int state_plan_steps(const redo_table_s* t, int B, int N) {
-    const size_t per_step = (size_t)B * (3 * sizeof(float2) * t->desc.d + 2 * sizeof(MvDesc) * state_slots(t));
+    const size_t per_step = (size_t)B * (3 * sizeof(double2) * t->desc.d + 2 * sizeof(MvDesc) * state_slots(t));
     return (N <= 65535 && per_step * N <= STATE_PLAN_ALL_BYTES) ? N : 1;   // grid.y bounds N
 }
 
@@ -465,6 +490,8 @@ redo_status state_grape(redo_table_s* t, const float* u, const int* n_steps, int
                         const float* psif, double* fidelity, double* overlap, float* grad, void* workspace,
                         size_t workspace_bytes, hipStream_t st) {
     if (B > 32767) return fail(REDO_ERR_UNSUPPORTED, "state GRAPE takes at most 32767 instances per call");
+    if (t->desc.d > STATE_MAX_D)
+        return fail(REDO_ERR_UNSUPPORTED, "state GRAPE keeps its FP64 input vector in LDS: d <= 8192");
     const int S = state_slots(t);
     const int PS = state_plan_steps(t, B, N);
     StateWS need(t, B, N, S, nullptr, PS);
@@ -474,11 +501,12 @@ redo_status state_grape(redo_table_s* t, const float* u, const int* n_steps, int
     const int d = t->desc.d, K = t->desc.K;
     const long long vs = (long long)(N + 1) * d;
     REDO_HIP(quantise_all(t, u, B, N, w.codes, w.phi, st));
-    // psi_0 and chi_N
-    REDO_HIP(hipMemcpy2DAsync(w.Psi, sizeof(float2) * vs, psi0, sizeof(float2) * d, sizeof(float2) * d, B,
-                              hipMemcpyDeviceToDevice, st));
-    REDO_HIP(hipMemcpy2DAsync(w.Chi + (size_t)N * d, sizeof(float2) * vs, psif, sizeof(float2) * d, sizeof(float2) * d,
-                              B, hipMemcpyDeviceToDevice, st));
+    // psi_0 and chi_N, widened to FP64
+    hipLaunchKernelGGL(widen_kernel, dim3((d + 255) / 256, B), dim3(256), 0, st, d,
+                       reinterpret_cast<const float2*>(psi0), w.Psi, vs);
+    hipLaunchKernelGGL(widen_kernel, dim3((d + 255) / 256, B), dim3(256), 0, st, d,
+                       reinterpret_cast<const float2*>(psif), w.Chi + (size_t)N * d, vs);
+    REDO_HIP(hipGetLastError());
     StatePlan p{};
     p.T = t->T32;
     p.V = t->desc.drift_is_diag ? nullptr : t->V32;
@@ -515,7 +543,7 @@ redo_status state_grape(redo_table_s* t, const float* u, const int* n_steps, int
     p.all = PS > 1 ? 1 : 0;
     const int nrt = (d + MV_R - 1) / MV_R;
     if (S == 0) return fail(REDO_ERR_UNSUPPORTED, "no factor slots");
-    const size_t mv_lds = sizeof(float2) * (size_t)d;
+    const size_t mv_lds = sizeof(double2) * (size_t)d;
     REDO_HIP(hipFuncSetAttribute((const void*)matvec_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mv_lds));
     if (p.all) {
         // every step planned at once: step n of the forward chain and step N - 1 - n of the

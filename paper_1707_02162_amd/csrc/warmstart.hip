@@ -122,6 +122,28 @@ __global__ void adam_kernel(long long n, float* p, unsigned short* pb, const flo
     if (pb) pb[e] = to_bf16(x);
 }
 
+// projected gradient ascent: p <- clamp(p + alpha g, lo, hi)
+__global__ void ascent_kernel(long long n, float* p, const float* g, float alpha, float lo, float hi) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    p[e] = fminf(fmaxf(fmaf(alpha, g[e], p[e]), lo), hi);
+}
+
+// out[r] = mean of row r of in[rows][cols], FP64, one workgroup per row (fixed summation order)
+__global__ __launch_bounds__(256) void row_mean_kernel(int cols, const double* in, double* out) {
+    const double* x = in + (long long)blockIdx.x * cols;
+    double s = 0.0;
+    for (int c = threadIdx.x; c < cols; c += 256) s += x[c];
+    __shared__ double part[256];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = part[0] / cols;
+}
+
 __global__ void to_bf16_kernel(long long n, const float* in, unsigned short* out) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < n) out[e] = to_bf16(in[e]);
@@ -250,6 +272,22 @@ redo_status redo_adam_update(int64_t n, float* param, uint16_t* param_bf16, cons
     const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
     hipLaunchKernelGGL(adam_kernel, dim3(nblk(n)), dim3(256), 0, static_cast<hipStream_t>(stream), (long long)n, param,
                        param_bf16, grad, m, v, lr, beta1, beta2, eps, c1, c2, sign, lo, hi);
+    REDO_HIP(hipGetLastError());
+    return REDO_OK;
+}
+
+redo_status redo_ascent_step(int64_t n, float* param, const float* grad, float alpha, float lo, float hi,
+                             void* stream) {
+    if (n < 1 || !param || !grad || !(lo <= hi)) return fail(REDO_ERR_ARG, "bad ascent-step arguments");
+    hipLaunchKernelGGL(ascent_kernel, dim3(nblk(n)), dim3(256), 0, static_cast<hipStream_t>(stream), (long long)n, param,
+                       grad, alpha, lo, hi);
+    REDO_HIP(hipGetLastError());
+    return REDO_OK;
+}
+
+redo_status redo_time_average(int32_t rows, int32_t cols, const double* in, double* out, void* stream) {
+    if (rows < 1 || cols < 1 || !in || !out) return fail(REDO_ERR_ARG, "bad time-average arguments");
+    hipLaunchKernelGGL(row_mean_kernel, dim3(rows), dim3(256), 0, static_cast<hipStream_t>(stream), cols, in, out);
     REDO_HIP(hipGetLastError());
     return REDO_OK;
 }

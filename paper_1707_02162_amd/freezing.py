@@ -58,7 +58,7 @@ def sweep(n_omega: int = 500, n_lambda: int = 1000, N: int = 10000, chunk: int =
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, _, m = table.chain(u, observable=obs, reproject_every=reproject_every)
-        q = m.mean(dim=1)
+        q = R.time_average(m)
         torch.cuda.synchronize()
         gpu_s += time.perf_counter() - t0
         Q[c0:c0 + cnt] = q.cpu().numpy()

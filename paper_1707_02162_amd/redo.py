@@ -19,7 +19,8 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libredo.so
 PREC_F32, PREC_F32_3M, PREC_BF16X3 = 0, 1, 2
 OP_COMPOSE, OP_CHAIN, OP_GRAPE, OP_EXPM_CHAIN, OP_EXPM_GRAPE, OP_STATE_GRAPE, OP_KRON_CHAIN = 0, 1, 2, 3, 4, 5, 6
 STATUS = {0: "REDO_OK", 1: "REDO_ERR_ARG", 2: "REDO_ERR_ALLOC", 3: "REDO_ERR_HIP", 4: "REDO_ERR_NOT_HERMITIAN",
-          5: "REDO_ERR_NONFINITE", 6: "REDO_ERR_UNSUPPORTED", 7: "REDO_ERR_WORKSPACE", 100: "REDO_WARN_CLAMPED"}
+          5: "REDO_ERR_NONFINITE", 6: "REDO_ERR_UNSUPPORTED", 7: "REDO_ERR_WORKSPACE", 100: "REDO_WARN_CLAMPED",
+          101: "REDO_WARN_UNITARITY"}
 
 # name -> (restype, argtypes); mirrors include/redo.h
 _P = ctypes.c_void_p
@@ -43,6 +44,7 @@ _SIG = {
     "redo_expm_grape_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _I, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "redo_grape_state_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "redo_get_device_status": (_I, [_P, _P, ctypes.POINTER(ctypes.c_int64)]),
+    "redo_unitarity_report": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "redo_profile_enable": (_I, [_I]),
     "redo_profile_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _I]),
     "redo_profile_read_kind": (_I, [_I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _I]),
@@ -52,6 +54,8 @@ _SIG = {
     "redo_adam_update": (_I, [ctypes.c_int64, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
     "redo_to_bf16": (_I, [ctypes.c_int64, _P, _P, _P]),
+    "redo_ascent_step": (_I, [ctypes.c_int64, _P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
+    "redo_time_average": (_I, [_I, _I, _P, _P, _P]),
     "redo_lbfgs_direction": (_I, [_I, ctypes.c_int64, _I, _P, _P, _P, _P, _P, _P, ctypes.c_double, _P, _P, _P]),
     "redo_lbfgs_trial": (_I, [_I, ctypes.c_int64, _P, _P, _P, _P, _P]),
     "redo_lbfgs_push": (_I, [_I, ctypes.c_int64, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
@@ -368,9 +372,18 @@ class RedoTable:
         return F, ov, grad
 
     def device_status(self):
+        """(status, clamped amplitudes) latched since the last call; clears them."""
         n = ctypes.c_int64()
         st = lib().redo_get_device_status(self._h, _stream(), ctypes.byref(n))
         return st, n.value
+
+    def unitarity_report(self):
+        """(largest ||X^dag X - I||_F / sqrt(d) at a re-projection step, count above 1e-3)
+        as read by the last device_status call."""
+        x = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().redo_unitarity_report(self._h, ctypes.byref(x), ctypes.byref(n)))
+        return x.value, n.value
 
 
 def profile_enable(on: bool = True) -> None:
@@ -395,6 +408,24 @@ def unitary_fidelity(U_target: torch.Tensor, U: torch.Tensor):
     F = torch.empty(B, dtype=torch.float64, device=U.device)
     _check(lib().redo_unitary_fidelity(d, B, _ptr(Uf), _ptr(Ut), _ptr(ov), _ptr(F), _stream()))
     return ov, F
+
+
+def ascent_step(u: torch.Tensor, grad: torch.Tensor, alpha: float, lo: float, hi: float) -> torch.Tensor:
+    """In place u <- clamp(u + alpha grad, lo, hi) (float32 device tensors of one shape)."""
+    if u.dtype != torch.float32 or grad.dtype != torch.float32 or u.shape != grad.shape:
+        raise ValueError("u and grad must be float32 tensors of one shape")
+    _check(lib().redo_ascent_step(u.numel(), _ptr(u), _ptr(grad), alpha, lo, hi, _stream()))
+    return u
+
+
+def time_average(series: torch.Tensor) -> torch.Tensor:
+    """Row means of a float64 [rows, cols] device tensor (the order parameter of a
+    magnetisation series)."""
+    if series.dtype != torch.float64 or series.dim() != 2:
+        raise ValueError("series must be float64 [rows, cols]")
+    out = torch.empty(series.shape[0], dtype=torch.float64, device=series.device)
+    _check(lib().redo_time_average(series.shape[0], series.shape[1], _ptr(series), _ptr(out), _stream()))
+    return out
 
 
 def walsh_spectrum(cols, vals) -> Optional[np.ndarray]:

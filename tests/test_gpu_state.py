@@ -3,11 +3,10 @@ C ABI against the FP64 oracle: d = 4 phased, d = 8 signed (with the Strang
 splitting and ragged lengths), d = 16 with the level cache, d = 128 with the
 generators' sparse pattern and d = 192 with a dense generator.
 
-Tolerances: gradient relative L2 <= 1e-4 as for the unitary adjoint.  The
-fidelity of one state has no trace to average the FP32 rounding over: each of
-the m = N K P factor applications (each factor rounded once to FP32,
-u = 6e-8) perturbs psi by ~u relative, a random walk to ~u sqrt(m), and
-|dF_S| <= 2 |g| |d psi|; the tests use max(1e-6, 4 u sqrt(m))."""
+Tolerances: |dF_S| <= 1e-6 and gradient relative L2 <= 1e-4 as for the unitary
+adjoint.  The vectors, the phase scalings and the sums of every matrix-vector
+product are FP64, so the FP32 rounding of the stored factors is the only one
+that accumulates along the chain."""
 import math
 
 import numpy as np
@@ -45,9 +44,8 @@ def _check(p, psi0, psif, F, ov, grad):
     for b in range(p.B):
         Fo, go, gro = O.state_fidelity_and_gradient(p, b, psi0[b], psif[b], model="redo", table=tab)
         nb = int(p.lengths()[b])
-        tol = max(FID_TOL, 4 * 6e-8 * math.sqrt(nb * p.K * p.digits))
-        assert abs(F[b] - Fo) < tol, (b, F[b], Fo)
-        assert abs(ov[b] - go) < max(1e-5, tol)
+        assert abs(F[b] - Fo) < FID_TOL, (b, F[b], Fo, abs(F[b] - Fo))
+        assert abs(ov[b] - go) < 1e-5
         assert np.linalg.norm(grad[b, :nb] - gro) <= GRAD_TOL * np.linalg.norm(gro), \
             (b, np.linalg.norm(grad[b, :nb] - gro) / np.linalg.norm(gro))
         assert np.all(grad[b, nb:] == 0)
@@ -115,7 +113,7 @@ def test_state_grape_per_step_plans_equal_one_plan_d128():
     from paper_1707_02162_amd import redo as R
     p = W.nmr_chain(7, 64, 1400, 2e-6, 32, 2, 233)
     t = R.RedoTable.from_problem(p)
-    assert R.lib().redo_workspace_bytes(t._h, R.OP_STATE_GRAPE, 64, 1400) < 300e6   # per-step plans
+    assert R.lib().redo_workspace_bytes(t._h, R.OP_STATE_GRAPE, 64, 1400) < 500e6   # per-step plans
     psi0, psif = _states(128, 64, 6)
     u = torch.tensor(p.u).cuda()
     F, ov, grad = t.state_grape(u, psi0, psif)
