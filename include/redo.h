@@ -408,6 +408,26 @@ redo_status redo_get_device_status(redo_table table, void* stream, int64_t* n_cl
 redo_status redo_unitarity_report(redo_table table, double* max_drift, int64_t* count);
 
 /*
+ * redo_grape_fidelity_grad without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): d <= 64 only (REDO_ERR_UNSUPPORTED otherwise), same
+ * arguments, results and errors as redo_grape_fidelity_grad minus the
+ * workspace.  The fused kernel's scratch (checkpoints, one recomputed segment,
+ * pending traces: redo_grape_workspace_bytes of the same call) comes from a
+ * file-scope device array of redo_grape_noalloc_max_bytes() = 64 MiB, one copy
+ * per GPU held until the process ends; a call that needs more is refused with
+ * REDO_ERR_UNSUPPORTED before anything is launched.  Nothing in the array needs
+ * to start at zero (every entry is written before it is read).  All calls on one
+ * GPU share that array: calls that overlap in time on one GPU (several streams
+ * or threads) race and must be serialised by the caller.
+ */
+size_t redo_grape_noalloc_max_bytes(void);
+redo_status redo_grape_fidelity_grad_noalloc(redo_table table, int32_t precision, const float* u,
+                                             const int32_t* n_steps, int32_t B, int32_t N_max,
+                                             const float* U_target, int32_t checkpoint_every, double* fidelity,
+                                             double* overlap, float* grad, void* stream);
+
+/*
  * ---- Learned warm start (not part of the paper's method) ----
  * A three-layer perceptron maps a target unitary to initial control amplitudes
  * for a REDO-GRAPE run (plain REDO-GRAPE remains the fallback and the judge of

@@ -43,6 +43,8 @@ _SIG = {
     "redo_expm_chain": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P, _P, ctypes.c_size_t, _P]),
     "redo_expm_grape_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _I, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "redo_grape_state_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "redo_grape_noalloc_max_bytes": (ctypes.c_size_t, []),
+    "redo_grape_fidelity_grad_noalloc": (_I, [_P, _I, _P, _P, _I, _I, _P, _I, _P, _P, _P, _P]),
     "redo_get_device_status": (_I, [_P, _P, ctypes.POINTER(ctypes.c_int64)]),
     "redo_unitarity_report": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "redo_profile_enable": (_I, [_I]),
