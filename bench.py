@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_VECTOR_TFLOPS = 78.6   # non-packed FP32 FMA rate: 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz
 
 # HBM bytes per launch of the headline GEMM (three-product FP32 form, 4096
 # products at d = 1024), from two rocprofv3 --pmc runs (FETCH_SIZE, then
@@ -112,26 +113,26 @@ def bench_freezing(args, redo, W, torch):
     cols, vals = W.observable_ell(p.M)
     obs = (torch.tensor(cols, device="cuda"), torch.tensor(vals, device="cuda", dtype=torch.complex64))
     # M = sum_q I_x^(q) is diagonal in the Walsh basis: the states are carried as W = X H / sqrt(d)
-    spec = redo.walsh_spectrum(cols, vals)
-    spec = None if spec is None else torch.tensor(spec, device="cuda")
+    spec = redo.walsh_observable(cols, vals)
     U = torch.empty((B, p.d, p.d), dtype=torch.complex64, device="cuda")
     mag = torch.empty((B, N), dtype=torch.float64, device="cuda")
 
     def run(kind, precision, steps, warm, walsh=True):
         wf = spec if walsh else None
+        ob = None if walsh else obs
 
         def advance(n0, n1):
             un = u[:, n0:n1].contiguous()
             X0 = None if n0 == 0 else U
             if kind == "redo":
                 _, _, m = table.chain(un, X0=X0, out=U, step_offset=n0, reproject_every=args.reproject,
-                                      observable=obs, precision=precision, walsh=wf)
+                                      observable=ob, precision=precision, walsh=wf)
             elif kind == "kron":
                 _, m = table.kron_chain(un, X0=X0, out=U, step_offset=n0, reproject_every=args.reproject,
-                                        observable=obs, walsh=wf)
+                                        observable=ob, walsh=wf)
             else:
                 _, m = table.expm_chain(un, X0=X0, out=U, step_offset=n0, reproject_every=args.reproject,
-                                        observable=obs, precision=precision, walsh=wf)
+                                        observable=ob, precision=precision, walsh=wf)
             mag[:, n0:n1] = m
 
         for n0 in range(0, warm, args.chunk):
@@ -248,12 +249,11 @@ def bench_next(args, redo, W, torch):
         table.cache_levels()
     u = torch.tensor(p.u, device="cuda")
     cols, vals = W.observable_ell(p.M)
-    obs = (torch.tensor(cols, device="cuda"), torch.tensor(vals, device="cuda", dtype=torch.complex64))
-    spec = torch.tensor(redo.walsh_spectrum(cols, vals), device="cuda")
+    spec = redo.walsh_observable(cols, vals)
     U = torch.empty((B, p.d, p.d), dtype=torch.complex64, device="cuda")
     def advance(n0, n1):
         table.chain(u[:, n0:n1].contiguous(), X0=None if n0 == 0 else U, out=U, step_offset=n0,
-                    reproject_every=args.reproject, observable=obs, precision=1, walsh=spec)
+                    reproject_every=args.reproject, precision=1, walsh=spec)
 
     for n0 in range(0, Wm, args.chunk):
         advance(n0, min(Wm, n0 + args.chunk))
@@ -328,6 +328,88 @@ def bench_c2(args, redo, W, torch):
     if "expm" in res:
         out["expm"] = res["expm"]
         out["speedup_vs_expm"] = res["redo"]["value"] / res["expm"]["value"]
+    return out
+
+
+def bench_small(args, redo, W, torch):
+    """The small-d configurations: two spins (d = 4, 65,536 seeded replicas x 200
+    steps, two phased channels, 8-bit levels, every level cached): chain steps/s and
+    GRAPE iterations/s (fidelity + adjoint gradient + update); batched ragged GRAPE of
+    64 five-qubit systems (d = 32, N_b ~ U{500..3000}, five phased channels, each its
+    own drift and target): iterations/s.  Algorithmic work: 8 d^3 real flops per
+    table-factor product (one per non-zero code with every level cached), the
+    VALU-bound kernels' roofline against the non-packed FP32 vector peak."""
+    out = {}
+    p = W.c1_two_spin(B=args.c1_replicas, N=200)
+    table = redo.RedoTable.from_problem(p)
+    table.cache_levels()
+    u = torch.tensor(p.u, device="cuda")
+    Uf = torch.tensor(p.U_target, device="cuda")
+    codes, _ = table.quantise(u)
+    nnz = int(torch.count_nonzero(codes).item())
+    table.chain(u)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        table.chain(u)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    steps = p.B * p.N
+    flops = 8.0 * p.d ** 3 * nnz
+    chain = {"value": steps / el, "unit": "propagator steps/s", "ms_per_call": 1e3 * el,
+             "achieved_tflops": flops / el / 1e12, "peak_tflops": PEAK_FP32_VECTOR_TFLOPS,
+             "frac": flops / el / 1e12 / PEAK_FP32_VECTOR_TFLOPS}
+    F, _, g = table.grape(u, Uf)
+    redo.ascent_step(u, g, 1e3, -p.u_scale, p.u_scale)
+    torch.cuda.synchronize()
+    iters = 5
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        F, _, g = table.grape(u, Uf)
+        redo.ascent_step(u, g, 1e3, -p.u_scale, p.u_scale)
+    torch.cuda.synchronize()
+    elg = (time.perf_counter() - t0) / iters
+    # forward, recomputed segment and backward scan apply every factor once each, plus Y = X L per step
+    gflops = 8.0 * p.d ** 3 * (3 * nnz + steps)
+    out["c1_two_spin"] = {
+        "workload": "2 spins (d=4), 65,536 replicas x 200 steps of 5 us, 2 phased channels, b=16 P=2 "
+                    "(every level cached), Haar targets",
+        "chain": chain,
+        "grape": {"iters_per_s": 1.0 / elg, "ms_per_iter": 1e3 * elg, "replica_steps_per_s": steps / elg,
+                  "achieved_tflops": gflops / elg / 1e12, "frac": gflops / elg / 1e12 / PEAK_FP32_VECTOR_TFLOPS}}
+    log(f"[bench] d=4 chain {steps / el:.3g} steps/s, GRAPE {1.0 / elg:.3g} it/s")
+    del table, u, Uf
+    torch.cuda.empty_cache()
+    q = W.c4_batched_grape(B=64)
+    table = redo.RedoTable.from_problem(q)
+    table.cache_levels()
+    u = torch.tensor(q.u, device="cuda")
+    Uf = torch.tensor(q.U_target, device="cuda")
+    ns = torch.tensor(q.n_steps, device="cuda")
+    codes, _ = table.quantise(u)
+    live = (torch.arange(q.N, device="cuda")[None, :] < ns[:, None]).unsqueeze(-1)
+    nnz = int(torch.count_nonzero(codes * live).item())
+    F, _, g = table.grape(u, Uf, n_steps=ns)
+    redo.ascent_step(u, g, 1e3, -q.u_scale, q.u_scale)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        F, _, g = table.grape(u, Uf, n_steps=ns)
+        redo.ascent_step(u, g, 1e3, -q.u_scale, q.u_scale)
+    torch.cuda.synchronize()
+    elc = (time.perf_counter() - t0) / iters
+    total = int(q.n_steps.sum())
+    cflops = 8.0 * q.d ** 3 * (3 * nnz + total)
+    out["c4_batched_grape"] = {
+        "workload": "64 five-qubit systems (d=32), ragged N_b ~ U{500..3000} (sum %d), 5 phased channels, "
+                    "b=32 P=2 (every level cached), own drift and Haar target each, checkpoints every "
+                    "ceil(sqrt N) steps" % total,
+        "iters_per_s": 1.0 / elc, "ms_per_iter": 1e3 * elc, "system_steps_per_s": total / elc,
+        "achieved_tflops": cflops / elc / 1e12, "frac": cflops / elc / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
+        "note": "one workgroup per system: 64 workgroups on 256 compute units, latency-bound"}
+    log(f"[bench] d=32 batched GRAPE {1.0 / elc:.3g} it/s")
+    del table
     return out
 
 
@@ -436,6 +518,8 @@ def main():
     ap.add_argument("--no-freezing", action="store_true",
                     help="skip the headline workload (profiling runs of the others; prints no headline value)")
     ap.add_argument("--sweep-instances", type=int, default=8000)
+    ap.add_argument("--c1-replicas", type=int, default=65536)
+    ap.add_argument("--no-small", action="store_true", help="skip the d=4 and d=32 lines")
     ap.add_argument("--no-cache", dest="cache", action="store_false",
                     help="apply one product per non-zero digit instead of the composed level of each amplitude")
     args = ap.parse_args()
@@ -468,6 +552,8 @@ def main():
     torch.cuda.empty_cache()
     sw = None if args.no_sweep else bench_sweep(args)
     torch.cuda.empty_cache()
+    sm = None if args.no_small else bench_small(args, redo, W, torch)
+    torch.cuda.empty_cache()
     cpu, acc = (None, None) if (args.no_cpu or fr is None) else oracle_accuracy(args, W, p, fr)
     rg = None if gr is None else gr.get("redo")
     eg = None if gr is None else gr.get("expm")
@@ -477,7 +563,7 @@ def main():
                           "value": None, "note": "headline workload skipped (--no-freezing)",
                           "grape_iters_per_s": None if rg is None else rg["iters_per_s"],
                           "grape_expm_iters_per_s": None if eg is None else eg["iters_per_s"],
-                          "d64_chain": c2, "paper_freezing_sweep_d8": sw}), flush=True)
+                          "d64_chain": c2, "paper_freezing_sweep_d8": sw, "small_d": sm}), flush=True)
         return
     f32, bf, ex, kr, g4, ls = fr["fp32"], fr["bf16x3"], fr["expm"], fr["kron"], fr["f32_4m"], fr["lists"]
     out = {
@@ -551,6 +637,7 @@ def main():
         "grape_method_comparison": None if gr is None else gr.get("method"),
         "d64_chain": c2,
         "paper_freezing_sweep_d8": sw,
+        "small_d": sm,
         "strang": None if nx is None else nx["strang"],
         "state_grape": None if nx is None else nx["state_grape"],
         "table_build_s": fr["table_build_s"],

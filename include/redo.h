@@ -131,6 +131,18 @@ redo_status redo_table_destroy(redo_table table);
  */
 redo_status redo_cache_levels(redo_table table, int32_t q_lo, int32_t q_hi, void* stream);
 
+/*
+ * Check of process 1 in FP64 (not part of the method's hot path): the level
+ * R_k(q) = T_k[0][c_0] T_k[1][c_1] ... of channel k, code q (0 <= q <= b^P - 1),
+ * composed in FP64 on the device by the operations, in the order, that
+ * redo_build_table and redo_cache_levels use before their single rounding to
+ * FP32 (scaling-and-squaring Taylor exponential of each digit's generator
+ * exp(-i b^j eps dt S_k), powers by repeated products, then the product over
+ * the digits).  out: c128 [d][d], device, caller-owned.  Allocates scratch;
+ * synchronises `stream`.  REDO_ERR_ARG for k or q out of range.
+ */
+redo_status redo_level_f64(redo_table table, int32_t k, int32_t q, double* out, void* stream);
+
 /* Host copy of the descriptor and the table's device footprint in bytes. */
 redo_status redo_table_query(redo_table table, redo_table_desc* desc, size_t* device_bytes);
 
@@ -254,38 +266,48 @@ redo_status redo_observable_walsh(int32_t d, const int32_t* cols, const float* v
 redo_status redo_walsh_right(int32_t d, int32_t B, float* X, int64_t stride, void* stream);
 
 /*
+ * An observable of the right Walsh frame bound to its spectrum.  Created from
+ * row lists on the host (layout as obs_cols/obs_vals of redo_chain_propagator,
+ * duplicates summed) by the analysis of redo_observable_walsh: REDO_OK when
+ * M_ij = f(i XOR j) holds for every entry with f real, and then *out owns
+ * device copies of the lists and of the spectrum D = H f; REDO_ERR_UNSUPPORTED
+ * when M is not of that form; REDO_ERR_ARG for bad sizes or pointers;
+ * REDO_ERR_ALLOC / REDO_ERR_HIP.  The handle is the only way an observable
+ * reaches the Walsh-frame chains, so a spectrum always describes its lists.
+ * Synchronous.  redo_walsh_observable_spectrum copies D to the host (double [d]);
+ * redo_walsh_observable_destroy frees the handle (NULL accepted; synchronises
+ * the device).
+ */
+typedef struct redo_walsh_obs_s* redo_walsh_obs;
+redo_status redo_walsh_observable_create(int32_t d, const int32_t* cols, const float* vals, int32_t width,
+                                         redo_walsh_obs* out);
+redo_status redo_walsh_observable_spectrum(redo_walsh_obs obs, double* spectrum);
+redo_status redo_walsh_observable_destroy(redo_walsh_obs obs);
+
+/*
  * redo_chain_propagator, redo_kron_chain and redo_expm_chain (the comparison
- * point) with the state in the right Walsh frame: W0 (or H/sqrt(d) when NULL, the identity in that frame) and W_total
- * are W = X Hn (convert with redo_walsh_right), and the observable rows
- * (device, as obs_cols/obs_vals there) come with spectrum (device, double [d],
- * from redo_observable_walsh for the same M) for the one-pass evaluation;
- * obs_out as there.  The lists must describe such an M (redo_observable_walsh
- * returned REDO_OK for them): the one-pass kernels read only row 0's list and
- * take row a's entries as column m XOR a with value f(m) for every entry
- * (m, f(m)) of row 0, so other rows are not checked on the device.
- * spectrum may be NULL when obs_out is NULL.  Needs d a
- * power of two in 128 .. 2048 (REDO_ERR_UNSUPPORTED otherwise); no X_prefix.
- * Same workspace as the corresponding chain (REDO_OP_CHAIN, REDO_OP_KRON_CHAIN,
- * REDO_OP_EXPM_CHAIN).
+ * point) with the state in the right Walsh frame: W0 (or H/sqrt(d) when NULL,
+ * the identity in that frame) and W_total are W = X Hn (convert with
+ * redo_walsh_right), and the observable comes as a handle from
+ * redo_walsh_observable_create (of the table's dimension, at most 16 entries per
+ * row) for the one-pass evaluation; obs_out as there (obs may be NULL when
+ * obs_out is NULL).  Needs d a power of two in 128 .. 2048
+ * (REDO_ERR_UNSUPPORTED otherwise); no X_prefix.  Same workspace as the
+ * corresponding chain (REDO_OP_CHAIN, REDO_OP_KRON_CHAIN, REDO_OP_EXPM_CHAIN).
  */
 redo_status redo_chain_propagator_walsh(redo_table table, int32_t precision, const float* u,
                                         const int32_t* n_steps, int32_t B, int32_t N_max,
                                         int32_t step_offset, int32_t reproject_every, const float* W0,
-                                        float* W_total, const int32_t* obs_cols, const float* obs_vals,
-                                        int32_t obs_width, const double* spectrum, double* obs_out,
+                                        float* W_total, redo_walsh_obs obs, double* obs_out,
                                         void* workspace, size_t workspace_bytes, void* stream);
 redo_status redo_kron_chain_walsh(redo_table table, int32_t quantised, const float* u,
                                   const int32_t* n_steps, int32_t B, int32_t N_max, int32_t step_offset,
-                                  int32_t reproject_every, const float* W0, float* W_total,
-                                  const int32_t* obs_cols, const float* obs_vals, int32_t obs_width,
-                                  const double* spectrum, double* obs_out, void* workspace,
-                                  size_t workspace_bytes, void* stream);
+                                  int32_t reproject_every, const float* W0, float* W_total, redo_walsh_obs obs,
+                                  double* obs_out, void* workspace, size_t workspace_bytes, void* stream);
 redo_status redo_expm_chain_walsh(redo_table table, int32_t precision, const float* u,
                                   const int32_t* n_steps, int32_t B, int32_t N_max, int32_t step_offset,
-                                  int32_t reproject_every, const float* W0, float* W_total,
-                                  const int32_t* obs_cols, const float* obs_vals, int32_t obs_width,
-                                  const double* spectrum, double* obs_out, void* workspace,
-                                  size_t workspace_bytes, void* stream);
+                                  int32_t reproject_every, const float* W0, float* W_total, redo_walsh_obs obs,
+                                  double* obs_out, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * Unitary fidelity (Sec. III): g_b = Tr(U_f^dag U) / Tr(U_f^dag U_f),

@@ -13,6 +13,15 @@
 #include "large_path.h"
 #include "redo_internal.h"
 
+// an observable M_ij = f(i XOR j) bound to its Walsh spectrum (host analysis, device copies)
+struct redo_walsh_obs_s {
+    int d = 0, w = 0;
+    int* cols = nullptr;          // device [d][w]
+    float2* vals = nullptr;       // device [d][w]
+    double* spec = nullptr;       // device [d]
+    std::vector<double> spectrum; // host copy
+};
+
 namespace redo {
 
 static thread_local std::string g_last_error;
@@ -114,6 +123,16 @@ redo_status check_desc(const redo_table_desc* d) {
     if (d->splitting != 0 && d->splitting != 1) return fail(REDO_ERR_ARG, "splitting must be 0 or 1");
     if (d->splitting == 1 && !d->drift_is_diag)
         return fail(REDO_ERR_UNSUPPORTED, "the Strang splitting is provided for diagonal drifts");
+    return REDO_OK;
+}
+
+// the observable of a Walsh-frame chain: present when obs_out is, of the table's dimension,
+// at most 16 entries per row
+redo_status check_walsh_obs(const redo_table_s* t, const redo_walsh_obs_s* obs, const double* obs_out) {
+    if (!obs_out) return REDO_OK;
+    if (!obs) return fail(REDO_ERR_ARG, "obs_out needs a Walsh observable");
+    if (obs->d != t->desc.d) return fail(REDO_ERR_ARG, "the Walsh observable is of another dimension than the table");
+    if (obs->w > 16) return fail(REDO_ERR_UNSUPPORTED, "observables with more than 16 entries per row");
     return REDO_OK;
 }
 
@@ -551,6 +570,71 @@ redo_status redo_cache_levels(redo_table t, int32_t q_lo, int32_t q_hi, void* st
     return REDO_OK;
 }
 
+redo_status redo_level_f64(redo_table t, int32_t k, int32_t q, double* out, void* stream) {
+    g_last_error.clear();
+    if (!t || !out) return fail(REDO_ERR_ARG, "table and out must not be NULL");
+    if (k < 0 || k >= t->desc.K) return fail(REDO_ERR_ARG, "channel out of range");
+    if (q < 0 || (double)q > t->qmax) return fail(REDO_ERR_ARG, "need 0 <= q <= b^P - 1");
+    const int d = t->desc.d, P = t->desc.digits, b = t->desc.base;
+    const size_t nn = (size_t)d * d;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    double2* R = reinterpret_cast<double2*>(out);
+    DevBuf E, Tc, Tn, Rh, Rn, scratch;
+    REDO_HIP(dev_alloc(E, sizeof(double2) * nn));
+    REDO_HIP(dev_alloc(Tc, sizeof(double2) * nn));
+    REDO_HIP(dev_alloc(Tn, sizeof(double2) * nn));
+    REDO_HIP(dev_alloc(Rh, sizeof(double2) * nn));
+    REDO_HIP(dev_alloc(Rn, sizeof(double2) * nn));
+    REDO_HIP(dev_alloc(scratch, sizeof(double2) * nn));
+    // T[j][c] = E_j^c with E_j from the scaling-and-squaring Taylor exponential and the
+    // powers by repeated products, then R = T[0][c_0] (T[1][c_1] T[2][c_2] ...): the
+    // operations and their order of redo_build_table and redo_cache_levels
+    auto digit_op = [&](int j, int c, double2* dst) -> redo_status {
+        const double theta = std::pow((double)b, j) * t->desc.eps * t->desc.dt;
+        redo_status st = expm_fp64(d, t->S64 + nn * k, theta, t->s_norm[k], E.as<double2>(), scratch.as<double2>(), hs);
+        if (st != REDO_OK) return st;
+        REDO_HIP(hipMemcpyAsync(Tc.p, E.p, sizeof(double2) * nn, hipMemcpyDeviceToDevice, hs));
+        for (int e = 2; e <= c; ++e) {
+            REDO_HIP(zgemm_batched(d, 1, Tc.as<double2>(), 0, E.as<double2>(), 0, Tn.as<double2>(), 0,
+                                   make_double2(1.0, 0.0), 0.0, hs));
+            std::swap(Tc.p, Tn.p);
+        }
+        REDO_HIP(hipMemcpyAsync(dst, Tc.p, sizeof(double2) * nn, hipMemcpyDeviceToDevice, hs));
+        return REDO_OK;
+    };
+    bool have_high = false;
+    long long rest = q / b;
+    for (int j = 1; j < P; ++j) {
+        const int c = (int)(rest % b);
+        rest /= b;
+        if (c == 0) continue;
+        redo_status st = digit_op(j, c, have_high ? Rn.as<double2>() : Rh.as<double2>());
+        if (st != REDO_OK) return st;
+        if (have_high) {
+            REDO_HIP(zgemm_batched(d, 1, Rh.as<double2>(), 0, Rn.as<double2>(), 0, scratch.as<double2>(), 0,
+                                   make_double2(1.0, 0.0), 0.0, hs));
+            REDO_HIP(hipMemcpyAsync(Rh.p, scratch.p, sizeof(double2) * nn, hipMemcpyDeviceToDevice, hs));
+        }
+        have_high = true;
+    }
+    const int c0 = q % b;
+    if (c0 == 0) {
+        if (have_high) {
+            REDO_HIP(hipMemcpyAsync(R, Rh.p, sizeof(double2) * nn, hipMemcpyDeviceToDevice, hs));
+        } else {
+            REDO_HIP(fill_identity_z(d, 1, R, 0, hs));
+        }
+    } else {
+        redo_status st = digit_op(0, c0, have_high ? Rn.as<double2>() : R);
+        if (st != REDO_OK) return st;
+        if (have_high)
+            REDO_HIP(zgemm_batched(d, 1, Rn.as<double2>(), 0, Rh.as<double2>(), 0, R, 0, make_double2(1.0, 0.0), 0.0,
+                                   hs));
+    }
+    REDO_HIP(hipStreamSynchronize(hs));
+    return REDO_OK;
+}
+
 redo_status redo_table_query(redo_table t, redo_table_desc* desc, size_t* bytes) {
     if (!t) return fail(REDO_ERR_ARG, "table is NULL");
     if (desc) *desc = t->desc;
@@ -746,6 +830,50 @@ redo_status redo_observable_walsh(int32_t d, const int32_t* cols, const float* v
     return REDO_OK;
 }
 
+redo_status redo_walsh_observable_create(int32_t d, const int32_t* cols, const float* vals, int32_t width,
+                                         redo_walsh_obs* out) {
+    g_last_error.clear();
+    if (!out) return fail(REDO_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    std::vector<double> spec(d > 0 ? (size_t)d : 1);
+    redo_status st = redo_observable_walsh(d, cols, vals, width, spec.data());
+    if (st != REDO_OK) return st;
+    auto h = std::make_unique<redo_walsh_obs_s>();
+    h->d = d;
+    h->w = width;
+    h->spectrum = spec;
+    const size_t ne = (size_t)d * width;
+    hipError_t e = hipMalloc((void**)&h->cols, sizeof(int) * ne);
+    if (e == hipSuccess) e = hipMalloc((void**)&h->vals, sizeof(float2) * ne);
+    if (e == hipSuccess) e = hipMalloc((void**)&h->spec, sizeof(double) * d);
+    if (e == hipSuccess) e = hipMemcpy(h->cols, cols, sizeof(int) * ne, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->vals, vals, sizeof(float2) * ne, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->spec, spec.data(), sizeof(double) * d, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        redo_walsh_observable_destroy(h.release());
+        return hip_fail(e, "Walsh observable upload");
+    }
+    *out = h.release();
+    return REDO_OK;
+}
+
+redo_status redo_walsh_observable_spectrum(redo_walsh_obs obs, double* spectrum) {
+    g_last_error.clear();
+    if (!obs || !spectrum) return fail(REDO_ERR_ARG, "obs and spectrum must not be NULL");
+    std::copy(obs->spectrum.begin(), obs->spectrum.end(), spectrum);
+    return REDO_OK;
+}
+
+redo_status redo_walsh_observable_destroy(redo_walsh_obs obs) {
+    if (!obs) return REDO_OK;
+    (void)hipDeviceSynchronize();
+    if (obs->cols) (void)hipFree(obs->cols);
+    if (obs->vals) (void)hipFree(obs->vals);
+    if (obs->spec) (void)hipFree(obs->spec);
+    delete obs;
+    return REDO_OK;
+}
+
 redo_status redo_walsh_right(int32_t d, int32_t B, float* X, int64_t stride, void* stream) {
     g_last_error.clear();
     if (d < 128 || d > 4096 || (d & (d - 1)) != 0) return fail(REDO_ERR_ARG, "d must be a power of two in 128 .. 4096");
@@ -756,45 +884,43 @@ redo_status redo_walsh_right(int32_t d, int32_t B, float* X, int64_t stride, voi
 
 redo_status redo_chain_propagator_walsh(redo_table t, int32_t precision, const float* u, const int32_t* n_steps,
                                         int32_t B, int32_t N_max, int32_t step_offset, int32_t reproject_every,
-                                        const float* W0, float* W_total, const int32_t* obs_cols,
-                                        const float* obs_vals, int32_t obs_width, const double* spectrum,
-                                        double* obs_out, void* workspace, size_t workspace_bytes, void* stream) {
+                                        const float* W0, float* W_total, redo_walsh_obs obs, double* obs_out,
+                                        void* workspace, size_t workspace_bytes, void* stream) {
     g_last_error.clear();
     if (!t) return fail(REDO_ERR_ARG, "table is NULL");
     if (B < 1 || N_max < 1) return fail(REDO_ERR_ARG, "B and N_max must be >= 1");
     if (!u || !W_total) return fail(REDO_ERR_ARG, "u and W_total must not be NULL");
     if (step_offset < 0 || reproject_every < 0) return fail(REDO_ERR_ARG, "step_offset, reproject_every must be >= 0");
     if (precision < REDO_PREC_F32 || precision > REDO_PREC_BF16X3) return fail(REDO_ERR_ARG, "unknown precision");
-    if (obs_out && (!obs_cols || !obs_vals || obs_width < 1 || !spectrum))
-        return fail(REDO_ERR_ARG, "obs_out needs obs_cols, obs_vals, obs_width >= 1 and spectrum");
+    redo_status st = check_walsh_obs(t, obs, obs_out);
+    if (st != REDO_OK) return st;
     if (!walsh_dim(t->desc.d)) return fail(REDO_ERR_UNSUPPORTED, "the Walsh frame needs d = 2^n, 128 .. 2048");
-    if (obs_out && obs_width > 16) return fail(REDO_ERR_UNSUPPORTED, "observables with more than 16 entries per row");
-    return large_chain(t, precision, u, n_steps, B, N_max, step_offset, reproject_every, W0, W_total, obs_cols,
-                       obs_vals, obs_width, obs_out, workspace, workspace_bytes, static_cast<hipStream_t>(stream),
-                       true, spectrum);
+    return large_chain(t, precision, u, n_steps, B, N_max, step_offset, reproject_every, W0, W_total,
+                       obs_out ? obs->cols : nullptr, obs_out ? reinterpret_cast<const float*>(obs->vals) : nullptr,
+                       obs_out ? obs->w : 0, obs_out, workspace, workspace_bytes, static_cast<hipStream_t>(stream),
+                       true, obs_out ? obs->spec : nullptr);
 }
 
 redo_status redo_kron_chain_walsh(redo_table t, int32_t quantised, const float* u, const int32_t* n_steps, int32_t B,
                                   int32_t N_max, int32_t step_offset, int32_t reproject_every, const float* W0,
-                                  float* W_total, const int32_t* obs_cols, const float* obs_vals, int32_t obs_width,
-                                  const double* spectrum, double* obs_out, void* workspace, size_t workspace_bytes,
-                                  void* stream) {
+                                  float* W_total, redo_walsh_obs obs, double* obs_out, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
     g_last_error.clear();
     if (!t) return fail(REDO_ERR_ARG, "table is NULL");
     if (B < 1 || N_max < 1) return fail(REDO_ERR_ARG, "B and N_max must be >= 1");
     if (!u || !W_total) return fail(REDO_ERR_ARG, "u and W_total must not be NULL");
     if (quantised != 0 && quantised != 1) return fail(REDO_ERR_ARG, "quantised must be 0 or 1");
     if (step_offset < 0 || reproject_every < 0) return fail(REDO_ERR_ARG, "step_offset, reproject_every must be >= 0");
-    if (obs_out && (!obs_cols || !obs_vals || obs_width < 1 || !spectrum))
-        return fail(REDO_ERR_ARG, "obs_out needs obs_cols, obs_vals, obs_width >= 1 and spectrum");
+    redo_status st = check_walsh_obs(t, obs, obs_out);
+    if (st != REDO_OK) return st;
     if (t->kron_n == 0) return fail(REDO_ERR_UNSUPPORTED, "the generators are not sums of single-spin terms");
     if (!kron_supported(t))
         return fail(REDO_ERR_UNSUPPORTED, "the structure-aware chain needs a diagonal drift and d = 128 .. 4096");
     if (!walsh_dim(t->desc.d)) return fail(REDO_ERR_UNSUPPORTED, "the Walsh frame needs d = 2^n, 128 .. 2048");
-    if (obs_out && obs_width > 16) return fail(REDO_ERR_UNSUPPORTED, "observables with more than 16 entries per row");
-    return kron_chain(t, quantised, u, n_steps, B, N_max, step_offset, reproject_every, W0, W_total, obs_cols,
-                      obs_vals, obs_width, obs_out, workspace, workspace_bytes, static_cast<hipStream_t>(stream),
-                      true, spectrum);
+    return kron_chain(t, quantised, u, n_steps, B, N_max, step_offset, reproject_every, W0, W_total,
+                      obs_out ? obs->cols : nullptr, obs_out ? reinterpret_cast<const float*>(obs->vals) : nullptr,
+                      obs_out ? obs->w : 0, obs_out, workspace, workspace_bytes, static_cast<hipStream_t>(stream), true,
+                      obs_out ? obs->spec : nullptr);
 }
 
 redo_status redo_unitary_fidelity(int32_t d, int32_t B, const float* U_target, const float* U, double* overlap,
@@ -885,21 +1011,21 @@ redo_status redo_expm_chain(redo_table t, int32_t precision, const float* u, con
 
 redo_status redo_expm_chain_walsh(redo_table t, int32_t precision, const float* u, const int32_t* n_steps, int32_t B,
                                   int32_t N_max, int32_t step_offset, int32_t reproject_every, const float* W0,
-                                  float* W_total, const int32_t* obs_cols, const float* obs_vals, int32_t obs_width,
-                                  const double* spectrum, double* obs_out, void* workspace, size_t workspace_bytes,
-                                  void* stream) {
+                                  float* W_total, redo_walsh_obs obs, double* obs_out, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
     g_last_error.clear();
     if (!t) return fail(REDO_ERR_ARG, "table is NULL");
     if (B < 1 || N_max < 1) return fail(REDO_ERR_ARG, "B and N_max must be >= 1");
     if (!u || !W_total) return fail(REDO_ERR_ARG, "u and W_total must not be NULL");
     if (step_offset < 0 || reproject_every < 0) return fail(REDO_ERR_ARG, "step_offset, reproject_every must be >= 0");
     if (precision < REDO_PREC_F32 || precision > REDO_PREC_BF16X3) return fail(REDO_ERR_ARG, "unknown precision");
-    if (obs_out && (!obs_cols || !obs_vals || obs_width < 1 || !spectrum))
-        return fail(REDO_ERR_ARG, "obs_out needs obs_cols, obs_vals, obs_width >= 1 and spectrum");
+    redo_status st = check_walsh_obs(t, obs, obs_out);
+    if (st != REDO_OK) return st;
     if (!walsh_dim(t->desc.d)) return fail(REDO_ERR_UNSUPPORTED, "the Walsh frame needs d = 2^n, 128 .. 2048");
-    if (obs_out && obs_width > 16) return fail(REDO_ERR_UNSUPPORTED, "observables with more than 16 entries per row");
-    return expm_chain(t, precision, u, n_steps, B, N_max, step_offset, reproject_every, W0, W_total, obs_cols, obs_vals,
-                      obs_width, obs_out, workspace, workspace_bytes, static_cast<hipStream_t>(stream), true, spectrum);
+    return expm_chain(t, precision, u, n_steps, B, N_max, step_offset, reproject_every, W0, W_total,
+                      obs_out ? obs->cols : nullptr, obs_out ? reinterpret_cast<const float*>(obs->vals) : nullptr,
+                      obs_out ? obs->w : 0, obs_out, workspace, workspace_bytes, static_cast<hipStream_t>(stream), true,
+                      obs_out ? obs->spec : nullptr);
 }
 
 redo_status redo_expm_grape_fidelity_grad(redo_table t, int32_t precision, const float* u, const int32_t* n_steps,

@@ -30,6 +30,7 @@ _SIG = {
     "redo_table_destroy": (_I, [_P]),
     "redo_table_query": (_I, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
     "redo_cache_levels": (_I, [_P, _I, _I, _P]),
+    "redo_level_f64": (_I, [_P, _I, _I, _P, _P]),
     "redo_workspace_bytes": (ctypes.c_size_t, [_P, _I, _I, _I]),
     "redo_grape_workspace_bytes": (ctypes.c_size_t, [_P, _I, _I, _I]),
     "redo_quantise": (_I, [_P, _P, _I, _I, _P, _P, _P]),
@@ -63,12 +64,12 @@ _SIG = {
     "redo_lbfgs_push": (_I, [_I, ctypes.c_int64, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "redo_observable_walsh": (_I, [_I, _P, _P, _I, _P]),
     "redo_walsh_right": (_I, [_I, _I, _P, ctypes.c_int64, _P]),
-    "redo_chain_propagator_walsh": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P, _P, _P,
-                                         ctypes.c_size_t, _P]),
-    "redo_kron_chain_walsh": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P, _P, _P,
-                                   ctypes.c_size_t, _P]),
-    "redo_expm_chain_walsh": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P, _P, _P,
-                                   ctypes.c_size_t, _P]),
+    "redo_walsh_observable_create": (_I, [_I, _P, _P, _I, ctypes.POINTER(_P)]),
+    "redo_walsh_observable_spectrum": (_I, [_P, _P]),
+    "redo_walsh_observable_destroy": (_I, [_P]),
+    "redo_chain_propagator_walsh": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "redo_kron_chain_walsh": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "redo_expm_chain_walsh": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "redo_status_string": (ctypes.c_char_p, [_I]),
     "redo_last_error": (ctypes.c_char_p, []),
 }
@@ -192,6 +193,13 @@ class RedoTable:
             q_hi = self.base ** self.digits - 1
         _check(lib().redo_cache_levels(self._h, q_lo, q_hi, _stream()))
 
+    def level_f64(self, k: int, q: int) -> torch.Tensor:
+        """R_k(q) composed in FP64 on the device as the table build composes it before
+        rounding (complex128 [d, d]); a check of process 1, not the hot path."""
+        out = torch.empty((self.d, self.d), dtype=torch.complex128, device=self.device)
+        _check(lib().redo_level_f64(self._h, k, q, _ptr(out), _stream()))
+        return out
+
     def clear_cache(self) -> None:
         _check(lib().redo_cache_levels(self._h, 0, -1, _stream()))
 
@@ -233,8 +241,9 @@ class RedoTable:
               step_offset: int = 0, prefix: bool = False, observable=None, out: Optional[torch.Tensor] = None,
               walsh=None):
         """Chain of REDO steps.  observable: (cols int32 [d, w], vals complex [d, w]) row lists.
-        walsh: the observable's Walsh spectrum (walsh_spectrum), or True without an observable:
-        the states (X0 and the result) are then W = X H / sqrt(d), the right Walsh frame.
+        walsh: a WalshObservable (the observable of the call, with its spectrum; `observable`
+        is then not given), or True for the frame without an observable: the states (X0 and
+        the result) are then W = X H / sqrt(d), the right Walsh frame.
         Returns (U_total, X_prefix or None, obs or None)."""
         ut = self._u(u)
         B, N = ut.shape[:2]
@@ -253,15 +262,29 @@ class RedoTable:
         if walsh is not None:
             if prefix:
                 raise ValueError("prefix states are not provided in the Walsh frame")
-            spec = None if walsh is True else _dev(walsh, torch.float64, self.device)
+            h, obs = self._walsh_args(walsh, observable, B, N)
             _check(lib().redo_chain_propagator_walsh(self._h, precision, _ptr(ut), _ptr(ns), B, N, step_offset,
-                                                     reproject_every, _ptr(X0t), _ptr(U), _ptr(cols), _ptr(vals), w,
-                                                     _ptr(spec), _ptr(obs), _ptr(ws), ws.numel(), _stream()))
+                                                     reproject_every, _ptr(X0t), _ptr(U), h, _ptr(obs), _ptr(ws),
+                                                     ws.numel(), _stream()))
             return U, None, obs
         _check(lib().redo_chain_propagator(self._h, precision, _ptr(ut), _ptr(ns), B, N, step_offset,
                                            reproject_every, _ptr(X0t), _ptr(U), _ptr(Xp), _ptr(cols), _ptr(vals),
                                            w, _ptr(obs), _ptr(ws), ws.numel(), _stream()))
         return U, Xp, obs
+
+    def _walsh_args(self, walsh, observable, B, N):
+        """(handle or None, obs_out or None) of a Walsh-frame call."""
+        if walsh is True:
+            if observable is not None:
+                raise ValueError("an observable in the Walsh frame comes as a WalshObservable (walsh=...)")
+            return None, None
+        if not isinstance(walsh, WalshObservable):
+            raise TypeError("walsh must be a WalshObservable or True")
+        if observable is not None:
+            raise ValueError("pass the observable once, as the WalshObservable")
+        if walsh.d != self.d:
+            raise ValueError("the WalshObservable is of another dimension than the table")
+        return walsh._h, torch.empty((B, N), dtype=torch.float64, device=self.device)
 
     @property
     def spins(self) -> int:
@@ -289,10 +312,10 @@ class RedoTable:
             obs = torch.empty((B, N), dtype=torch.float64, device=self.device)
         ws = self.workspace(OP_KRON_CHAIN, B, N)
         if walsh is not None:
-            spec = None if walsh is True else _dev(walsh, torch.float64, self.device)
+            h, obs = self._walsh_args(walsh, observable, B, N)
             _check(lib().redo_kron_chain_walsh(self._h, 1 if quantised else 0, _ptr(ut), _ptr(ns), B, N,
-                                               step_offset, reproject_every, _ptr(X0t), _ptr(U), _ptr(cols),
-                                               _ptr(vals), w, _ptr(spec), _ptr(obs), _ptr(ws), ws.numel(), _stream()))
+                                               step_offset, reproject_every, _ptr(X0t), _ptr(U), h, _ptr(obs),
+                                               _ptr(ws), ws.numel(), _stream()))
             return U, obs
         _check(lib().redo_kron_chain(self._h, 1 if quantised else 0, _ptr(ut), _ptr(ns), B, N, step_offset,
                                      reproject_every, _ptr(X0t), _ptr(U), _ptr(cols), _ptr(vals), w, _ptr(obs),
@@ -333,10 +356,10 @@ class RedoTable:
             obs = torch.empty((B, N), dtype=torch.float64, device=self.device)
         ws = self.workspace(OP_EXPM_CHAIN, B, N)
         if walsh is not None:
-            spec = None if walsh is True else _dev(walsh, torch.float64, self.device)
+            h, obs = self._walsh_args(walsh, observable, B, N)
             _check(lib().redo_expm_chain_walsh(self._h, precision, _ptr(ut), _ptr(ns), B, N, step_offset,
-                                               reproject_every, _ptr(X0t), _ptr(U), _ptr(cols), _ptr(vals), w,
-                                               _ptr(spec), _ptr(obs), _ptr(ws), ws.numel(), _stream()))
+                                               reproject_every, _ptr(X0t), _ptr(U), h, _ptr(obs), _ptr(ws),
+                                               ws.numel(), _stream()))
             return U, obs
         _check(lib().redo_expm_chain(self._h, precision, _ptr(ut), _ptr(ns), B, N, step_offset, reproject_every,
                                      _ptr(X0t), _ptr(U), _ptr(cols), _ptr(vals), w, _ptr(obs), _ptr(ws), ws.numel(),
@@ -446,6 +469,50 @@ def walsh_spectrum(cols, vals) -> Optional[np.ndarray]:
         return None
     _check(st)
     return D
+
+
+class WalshObservable:
+    """An observable M_ij = f(i XOR j) (row lists on the host) bound to its Walsh spectrum
+    D = H f: the library checks the form and keeps device copies of both, so the
+    Walsh-frame chains cannot receive a spectrum of another observable."""
+
+    def __init__(self, cols, vals):
+        c = np.ascontiguousarray(np.asarray(cols, dtype=np.int32))
+        v = np.ascontiguousarray(np.asarray(vals, dtype=np.complex64))
+        if c.ndim != 2 or v.shape != c.shape:
+            raise ValueError("cols and vals must both be [d, w]")
+        self.d, self.w = c.shape
+        h = ctypes.c_void_p()
+        _check(lib().redo_walsh_observable_create(self.d, c.ctypes.data_as(_P), v.ctypes.data_as(_P), self.w,
+                                                  ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def spectrum(self) -> np.ndarray:
+        D = np.empty(self.d, dtype=np.float64)
+        _check(lib().redo_walsh_observable_spectrum(self._h, D.ctypes.data_as(_P)))
+        return D
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().redo_walsh_observable_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def walsh_observable(cols, vals) -> Optional[WalshObservable]:
+    """WalshObservable of the row lists, or None when M is not a real function of i XOR j."""
+    try:
+        return WalshObservable(cols, vals)
+    except RedoError as e:
+        if e.status == 6:
+            return None
+        raise
 
 
 def walsh_right(X: torch.Tensor) -> torch.Tensor:

@@ -150,3 +150,23 @@ def test_walsh_spectrum_rejections():
     c[2, 1] = d
     with pytest.raises(R.RedoError, match="outside"):
         R.walsh_spectrum(c, vals)
+
+
+def test_walsh_observable_refused_before_any_device_work():
+    """A Walsh observable is only created from lists that pass the analysis: the same
+    refusals as the spectrum (None for a non-XOR observable, argument errors for bad
+    sizes or columns), decided on the host before the library touches the device."""
+    import numpy as np
+    from paper_1707_02162_amd import redo as R, workloads as W
+    n, d = 5, 32
+    assert R.walsh_observable(*W.observable_ell(np.diag(W.collective_z_diag(n, range(n))).astype(complex))) is None
+    cols, vals = W.observable_ell(W.collective(n, range(n), "x"))
+    assert R.walsh_observable(cols, np.array(vals) * 1j) is None
+    with pytest.raises(R.RedoError, match="power of two"):
+        R.walsh_observable(np.zeros((24, 2), np.int32), np.zeros((24, 2), np.complex64))
+    c = np.array(cols).copy()
+    c[2, 1] = d
+    with pytest.raises(R.RedoError, match="outside"):
+        R.walsh_observable(c, vals)
+    lib = R.lib()
+    assert lib.redo_walsh_observable_destroy(None) == 0

@@ -71,17 +71,16 @@ def run_headline(p, precision):
     t = redo.RedoTable.from_problem(p)
     t.cache_levels()
     cols, vals = W.observable_ell(p.M)
-    D = redo.walsh_spectrum(cols, vals)
+    D = redo.walsh_observable(cols, vals)
     assert D is not None
     u = torch.tensor(p.u).cuda()
-    obs = (torch.tensor(cols).cuda(), torch.tensor(vals).cuda().to(torch.complex64))
     Wt = torch.empty((p.B, p.d, p.d), dtype=torch.complex64, device="cuda")
     mag = torch.empty((p.B, p.N), dtype=torch.float64, device="cuda")
     snaps = {}
     for n0 in range(0, p.N, CHUNK):
         n1 = min(p.N, n0 + CHUNK)
         _, _, m = t.chain(u[:, n0:n1].contiguous(), X0=None if n0 == 0 else Wt, out=Wt, step_offset=n0,
-                          reproject_every=REPROJECT, observable=obs, precision=precision, walsh=D)
+                          reproject_every=REPROJECT, precision=precision, walsh=D)
         mag[:, n0:n1] = m
         snaps[n1] = torch.stack([Wt[b] for b in SAMPLES])
     st, _ = t.device_status()

@@ -89,8 +89,9 @@ def test_lbfgs_trial_point():
 
 def test_grape_lbfgs_ascends_reachable_targets_d16():
     """Reachable 4-qubit targets (d = 16, two phased channels, b = 32, P = 2) from seeded
-    random pulses: every accepted iterate keeps or raises F, and after 25 iterations
-    L-BFGS is ahead of 25 plain Adam ascent steps on the same starts."""
+    random pulses: an instance's F never falls (a step is taken only when it raises F
+    strictly), and after 25 iterations L-BFGS is ahead of 25 plain Adam ascent steps on
+    the same starts."""
     from paper_1707_02162_amd import lbfgs, warmstart, workloads as W
     redo = R()
     p = W.c5_four_qubit(B=1, N=100)
@@ -99,7 +100,7 @@ def test_grape_lbfgs_ascends_reachable_targets_d16():
     u0 = warmstart.random_starts(p, 902, 8)
     u, F, hist = lbfgs.grape_lbfgs(t, u0, Uf, iters=25)
     H = torch.stack(hist).cpu().numpy()
-    assert np.all(np.diff(H, axis=0) >= -1e-12)
+    assert np.all(np.diff(H, axis=0) >= 0)
     _, Fa, _, _ = warmstart.grape(t, u0, Uf, u_max=float(p.u_scale) * 4, iters=25, lr=1000.0)
     print("L-BFGS mean infidelity", float((1 - F).mean()), "Adam", float((1 - Fa).mean()), "start", float((1 - H[0]).mean()))
     assert float((1 - F).mean()) < float((1 - Fa).mean())

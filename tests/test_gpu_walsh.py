@@ -53,9 +53,9 @@ def test_walsh_chain_ising_d128_vs_oracle():
     p = W.ising_freezing(n=7, B=3, N=70)
     t = R().RedoTable.from_problem(p)
     cols, vals = W.observable_ell(p.M)
-    D = R().walsh_spectrum(cols, vals)
+    D = R().walsh_observable(cols, vals)
     assert D is not None
-    Wt, _, m = t.chain(torch.tensor(p.u).cuda(), observable=(cols, vals), reproject_every=64, walsh=D)
+    Wt, _, m = t.chain(torch.tensor(p.u).cuda(), reproject_every=64, walsh=D)
     U, m = to_x(Wt), m.cpu().numpy()
     tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
     for b in range(p.B):
@@ -74,18 +74,17 @@ def test_walsh_chain_equals_basis_chain_phased_ragged_strang_d256():
     t = R().RedoTable.from_problem(p)
     M = W.collective(8, range(8), "x")
     cols, vals = W.observable_ell(M)
-    D = R().walsh_spectrum(cols, vals)
+    D = R().walsh_observable(cols, vals)
     u = torch.tensor(p.u).cuda()
     ns = torch.tensor(lens)
     Ub, _, mb = t.chain(u, n_steps=ns, observable=(cols, vals), reproject_every=8)
-    Wt, _, mw = t.chain(u, n_steps=ns, observable=(cols, vals), reproject_every=8, walsh=D)
+    Wt, _, mw = t.chain(u, n_steps=ns, reproject_every=8, walsh=D)
     assert nfrob(to_x(Wt), Ub.cpu().numpy().astype(np.complex128)) < FROB_TOL
     for b in range(p.B):
         assert np.abs(mw[b, :lens[b]].cpu().numpy() - mb[b, :lens[b]].cpu().numpy()).max() < OBS_TOL
-    Wa, _, ma = t.chain(u[:, :10].contiguous(), n_steps=ns.clamp(max=10), observable=(cols, vals),
-                        reproject_every=8, walsh=D)
+    Wa, _, ma = t.chain(u[:, :10].contiguous(), n_steps=ns.clamp(max=10), reproject_every=8, walsh=D)
     Wb, _, mb2 = t.chain(u[:, 10:].contiguous(), n_steps=(ns - 10).clamp(min=0), X0=Wa,
-                         observable=(cols, vals), reproject_every=8, step_offset=10, walsh=D)
+                         reproject_every=8, step_offset=10, walsh=D)
     assert torch.equal(Wb, Wt)
     tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
     for b in range(p.B):
@@ -98,9 +97,9 @@ def test_walsh_kron_chain_d256_vs_oracle(quantised):
     p = W.ising_freezing(n=8, B=2, N=20)
     t = R().RedoTable.from_problem(p)
     cols, vals = W.observable_ell(p.M)
-    D = R().walsh_spectrum(cols, vals)
+    D = R().walsh_observable(cols, vals)
     u = torch.tensor(p.u).cuda()
-    Wt, m = t.kron_chain(u, quantised=quantised, observable=(cols, vals), reproject_every=8, walsh=D)
+    Wt, m = t.kron_chain(u, quantised=quantised, reproject_every=8, walsh=D)
     Uk, mk = t.kron_chain(u, quantised=quantised, observable=(cols, vals), reproject_every=8)
     U, m = to_x(Wt), m.cpu().numpy()
     assert nfrob(U, Uk.cpu().numpy().astype(np.complex128)) < FROB_TOL
@@ -120,10 +119,10 @@ def test_walsh_chain_ising_d1024_full_batch_sampled_vs_oracle():
     t = R().RedoTable.from_problem(p)
     t.cache_levels()
     cols, vals = W.observable_ell(p.M)
-    D = R().walsh_spectrum(cols, vals)
+    D = R().walsh_observable(cols, vals)
     u = torch.tensor(p.u).cuda()
-    Wr, _, mr = t.chain(u, observable=(cols, vals), precision=1, walsh=D)
-    Wk, mk = t.kron_chain(u, observable=(cols, vals), walsh=D)
+    Wr, _, mr = t.chain(u, precision=1, walsh=D)
+    Wk, mk = t.kron_chain(u, walsh=D)
     torch.cuda.synchronize()
     tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
     for b in (0, 4095):
@@ -140,14 +139,23 @@ def test_walsh_argument_errors():
     cols, vals = W.observable_ell(p.M)
     u = torch.tensor(p.u).cuda()
     U = torch.empty((2, p.d, p.d), dtype=torch.complex64, device="cuda")
-    c = torch.tensor(cols).cuda()
-    v = torch.tensor(vals).cuda().to(torch.complex64)
     obs = torch.empty((2, 3), dtype=torch.float64, device="cuda")
     ws = t.workspace(redo.OP_CHAIN, 2, 3)
     P = redo._ptr
-    # an observable without its spectrum
-    assert redo.lib().redo_chain_propagator_walsh(t._h, 0, P(u), None, 2, 3, 0, 0, None, P(U), P(c), P(v),
-                                                  c.shape[1], None, P(obs), P(ws), ws.numel(), None) == 1
+    # an observable series without an observable
+    assert redo.lib().redo_chain_propagator_walsh(t._h, 0, P(u), None, 2, 3, 0, 0, None, P(U), None, P(obs),
+                                                  P(ws), ws.numel(), None) == 1
+    # an observable of another dimension
+    q8 = W.ising_freezing(n=8, B=1, N=2)
+    D8 = redo.walsh_observable(*W.observable_ell(q8.M))
+    assert redo.lib().redo_chain_propagator_walsh(t._h, 0, P(u), None, 2, 3, 0, 0, None, P(U), D8._h, P(obs),
+                                                  P(ws), ws.numel(), None) == 1
+    with pytest.raises(ValueError):
+        t.chain(u, walsh=D8)
+    # a list observable beside a Walsh observable
+    D7 = redo.walsh_observable(cols, vals)
+    with pytest.raises(ValueError):
+        t.chain(u, observable=(cols, vals), walsh=D7)
     # d = 64 and d = 4096 tables: outside the Walsh frame's range
     q = W.ising_freezing(n=6, B=1, N=2)
     with pytest.raises(redo.RedoError, match="2048"):
@@ -163,10 +171,10 @@ def test_walsh_expm_chain_equals_basis_chain_d128():
     p = W.ising_freezing(n=7, B=2, N=12)
     t = R().RedoTable.from_problem(p)
     cols, vals = W.observable_ell(p.M)
-    D = R().walsh_spectrum(cols, vals)
+    D = R().walsh_observable(cols, vals)
     u = torch.tensor(p.u).cuda()
     Ub, mb = t.expm_chain(u, observable=(cols, vals), reproject_every=8)
-    Wt, mw = t.expm_chain(u, observable=(cols, vals), reproject_every=8, walsh=D)
+    Wt, mw = t.expm_chain(u, reproject_every=8, walsh=D)
     assert nfrob(to_x(Wt), Ub.cpu().numpy().astype(np.complex128)) < FROB_TOL
     assert np.abs(mw.cpu().numpy() - mb.cpu().numpy()).max() < OBS_TOL
 
@@ -178,14 +186,14 @@ def test_walsh_chains_d2048_equal_basis_chains():
     p = W.ising_freezing(n=11, B=2, N=3)
     t = R().RedoTable.from_problem(p)
     cols, vals = W.observable_ell(p.M)
-    D = R().walsh_spectrum(cols, vals)
+    D = R().walsh_observable(cols, vals)
     u = torch.tensor(p.u).cuda()
     Ub, _, mb = t.chain(u, observable=(cols, vals), precision=1)
-    Wt, _, mw = t.chain(u, observable=(cols, vals), precision=1, walsh=D)
+    Wt, _, mw = t.chain(u, precision=1, walsh=D)
     assert nfrob(to_x(Wt), Ub.cpu().numpy().astype(np.complex128)) < FROB_TOL
     assert np.abs(mw.cpu().numpy() - mb.cpu().numpy()).max() < OBS_TOL
     Uk, mk = t.kron_chain(u, observable=(cols, vals))
-    Wk, mkw = t.kron_chain(u, observable=(cols, vals), walsh=D)
+    Wk, mkw = t.kron_chain(u, walsh=D)
     assert nfrob(to_x(Wk), Uk.cpu().numpy().astype(np.complex128)) < FROB_TOL
     assert np.abs(mkw.cpu().numpy() - mk.cpu().numpy()).max() < OBS_TOL
 
@@ -198,10 +206,10 @@ def test_walsh_kron_d1024_fused_observable_with_reprojection_and_ragged():
     lens = torch.tensor([9, 5, 8], dtype=torch.int32)
     t = R().RedoTable.from_problem(p)
     cols, vals = W.observable_ell(p.M)
-    D = R().walsh_spectrum(cols, vals)
+    D = R().walsh_observable(cols, vals)
     u = torch.tensor(p.u).cuda()
     Uk, mk = t.kron_chain(u, n_steps=lens, observable=(cols, vals), reproject_every=4)
-    Wk, mw = t.kron_chain(u, n_steps=lens, observable=(cols, vals), reproject_every=4, walsh=D)
+    Wk, mw = t.kron_chain(u, n_steps=lens, reproject_every=4, walsh=D)
     assert nfrob(to_x(Wk), Uk.cpu().numpy().astype(np.complex128)) < FROB_TOL
     for b in range(3):
         nb = int(lens[b])
