@@ -70,6 +70,39 @@ struct Cfg {
     static constexpr int IPB = 256 / TPI;      // instances per workgroup
 };
 
+// Barrier among the threads of one instance around its LDS buffers.  At d <= 16
+// an instance's threads are lanes of one wave, whose LDS accesses execute in
+// program order: a compiler fence suffices and the waves of a workgroup run
+// independently.  At d >= 32 an instance spans the workgroup's four waves.
+template <int D>
+__device__ inline void inst_sync() {
+    if constexpr (Cfg<D>::TPI > 64) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// Drift phases exp(-i hdt h_a) of the rows (or columns) idx + NT r the thread owns
+// (hdt = dt, or dt/2 for the Strang halves), FP64 rounded once to FP32: constant
+// along the chain, so computed once per instance.
+template <int D>
+__device__ inline void drift_phases(const TView& tv, int drift, int idx, float2 (&ph)[Cfg<D>::TB]) {
+    constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
+    const double hdt = tv.strang ? 0.5 * tv.dt : tv.dt;
+#pragma unroll
+    for (int r = 0; r < TB; ++r) {
+        if (tv.diag) {
+            const double2 e = expmi(hdt * tv.h[(long long)drift * D + idx + NT * r]);
+            ph[r] = make_float2((float)e.x, (float)e.y);
+        } else {
+            ph[r] = make_float2(1.f, 0.f);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- LDS helpers
 // element (r, c) of the thread's sub-block is (ti + NT r, tj + NT c)
 template <int D>
@@ -182,9 +215,11 @@ __device__ inline void step_phases(const TView& tv, const float* us, bool active
 }
 
 // x <- U_n x with U_n = Z [prod_k R_k] Z^dag V
+// dph: the drift phases of the thread's rows (drift_phases), used when the channels are unphased
 template <int D>
 __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float2* Fs,
-                          const float* us, int drift, bool active, bool report, int lt, int ti, int tj) {
+                          const float* us, int drift, bool active, bool report, int lt, int ti, int tj,
+                          const float2 (&dph)[Cfg<D>::TB]) {
     constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
     const int KK = tv.phased ? 2 : 1;
     double th[TB];
@@ -195,19 +230,22 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
         if (active) {
 #pragma unroll
             for (int r = 0; r < TB; ++r) {
-                const double2 e = expmi(hdt * tv.h[(long long)drift * D + ti + NT * r] - th[r]);
-                const float2 s = make_float2((float)e.x, (float)e.y);
+                float2 s = dph[r];
+                if (tv.phased) {
+                    const double2 e = expmi(hdt * tv.h[(long long)drift * D + ti + NT * r] - th[r]);
+                    s = make_float2((float)e.x, (float)e.y);
+                }
 #pragma unroll
                 for (int c = 0; c < TB; ++c) x[r][c] = cmul(s, x[r][c]);
             }
         }
     } else {
-        __syncthreads();
+        inst_sync<D>();
         if (active) {
             stage<D>(Fs, tv.V + (long long)drift * tv.ent, false, lt);
             store_block<D>(Xs, x, ti, tj);
         }
-        __syncthreads();
+        inst_sync<D>();
         if (active) {
             mul_left<D>(x, Fs, Xs, ti, tj);
             if (tv.phased) {
@@ -246,12 +284,12 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
     const float2* f = entry_of(0, q);
     if (f) fetch_factor<D>(fr, f, lt);
     for (int sl = 0; sl < nslot; ++sl) {
-        __syncthreads();
+        inst_sync<D>();
         if (f) {
             put_factor<D>(Fs, fr, q < 0, lt);
             store_block<D>(Xs, x, ti, tj);
         }
-        __syncthreads();
+        inst_sync<D>();
         const bool mult = f != nullptr;
         if (sl + 1 < nslot) {
             const int sn = sl + 1;
@@ -265,8 +303,11 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
     if (active && (tv.phased || tv.strang)) {
 #pragma unroll
         for (int r = 0; r < TB; ++r) {
-            const double2 e = expmi(th[r] + (tv.strang ? hdt * tv.h[(long long)drift * D + ti + NT * r] : 0.0));
-            const float2 s = make_float2((float)e.x, (float)e.y);
+            float2 s = dph[r];
+            if (tv.phased) {
+                const double2 e = expmi(th[r] + (tv.strang ? hdt * tv.h[(long long)drift * D + ti + NT * r] : 0.0));
+                s = make_float2((float)e.x, (float)e.y);
+            }
 #pragma unroll
             for (int c = 0; c < TB; ++c) x[r][c] = cmul(s, x[r][c]);
         }
@@ -274,9 +315,11 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
 }
 
 // l <- l U_n  (the backward scan), U_n = Z [prod_k R_k] Z^dag V
+// dpc: the drift phases of the thread's columns (drift_phases), used when the channels are unphased
 template <int D>
 __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB], float2* Ls, float2* Fs,
-                           const float* us, int drift, bool active, int lt, int ti, int tj) {
+                           const float* us, int drift, bool active, int lt, int ti, int tj,
+                           const float2 (&dpc)[Cfg<D>::TB]) {
     constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
     const int KK = tv.phased ? 2 : 1;
     // column phases: theta_c for the columns the thread owns
@@ -287,8 +330,11 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
     if (active && (tv.phased || tv.strang)) {
 #pragma unroll
         for (int c = 0; c < TB; ++c) {
-            const double2 e = expmi(thc[c] + (tv.strang ? hdt * tv.h[(long long)drift * D + tj + NT * c] : 0.0));
-            const float2 s = make_float2((float)e.x, (float)e.y);
+            float2 s = dpc[c];
+            if (tv.phased) {
+                const double2 e = expmi(thc[c] + (tv.strang ? hdt * tv.h[(long long)drift * D + tj + NT * c] : 0.0));
+                s = make_float2((float)e.x, (float)e.y);
+            }
 #pragma unroll
             for (int r = 0; r < TB; ++r) l[r][c] = cmul(l[r][c], s);
         }
@@ -315,12 +361,12 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
         const float2* f = entry_of(sl, q);
         if (f) fetch_factor<D>(fr, f, lt);
         for (; sl >= 0; --sl) {
-            __syncthreads();
+            inst_sync<D>();
             if (f) {
                 put_factor<D>(Fs, fr, q < 0, lt);
                 store_block<D>(Ls, l, ti, tj);
             }
-            __syncthreads();
+            inst_sync<D>();
             const bool mult = f != nullptr;
             if (sl > 0) {
                 const int sn = sl - 1;
@@ -335,8 +381,11 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
         if (active) {
 #pragma unroll
             for (int c = 0; c < TB; ++c) {
-                const double2 e = expmi(hdt * tv.h[(long long)drift * D + tj + NT * c] - thc[c]);
-                const float2 s = make_float2((float)e.x, (float)e.y);
+                float2 s = dpc[c];
+                if (tv.phased) {
+                    const double2 e = expmi(hdt * tv.h[(long long)drift * D + tj + NT * c] - thc[c]);
+                    s = make_float2((float)e.x, (float)e.y);
+                }
 #pragma unroll
                 for (int r = 0; r < TB; ++r) l[r][c] = cmul(l[r][c], s);
             }
@@ -351,12 +400,12 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
                 for (int r = 0; r < TB; ++r) l[r][c] = cmul(l[r][c], s);
             }
         }
-        __syncthreads();
+        inst_sync<D>();
         if (active) {
             stage<D>(Fs, tv.V + (long long)drift * tv.ent, false, lt);
             store_block<D>(Ls, l, ti, tj);
         }
-        __syncthreads();
+        inst_sync<D>();
         if (active) mul_left<D>(l, Ls, Fs, ti, tj);
     }
 }
@@ -368,9 +417,9 @@ __device__ void reproject(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float
                           double* red, DeviceFlags* flags, bool leader) {
     constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
     double dev2 = 0.0;
-    __syncthreads();
+    inst_sync<D>();
     if (active) store_block<D>(Xs, x, ti, tj);
-    __syncthreads();
+    inst_sync<D>();
     float2 z[TB][TB];
     if (active) {
         // z = x^dag x on the thread's block
@@ -402,7 +451,7 @@ __device__ void reproject(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float
     }
     dev2 = inst_sum<D>(dev2, red);
     if (active && leader) report_drift(flags, sqrt(dev2 / D));
-    __syncthreads();
+    inst_sync<D>();
     if (active) mul_left<D>(x, Xs, Fs, ti, tj);
 }
 
@@ -469,9 +518,64 @@ __global__ __launch_bounds__(256) void small_chain_kernel(TView tv, SmallChainAr
         }
         obs_norm = inst_sum<D>(s, red);
     }
+    // An observable with M_ac = f(a XOR c) (the collective transverse magnetisation of
+    // Sec. IV is one), checked here on the device: every row's list is row 0's with its
+    // columns XORed by the row index, no duplicate columns, at most XMAX terms.  Then
+    // (X M)_ab = sum_t conj(f_t) X_{a, b^m_t} and (M X)_ab = sum_t f_t X_{a^m_t, b} need
+    // no list: for an instance inside one wave (d <= 16) the partner entries are lane
+    // shuffles (low bits of the mask) and the thread's own other sub-block entry (the
+    // high bit).
+    constexpr int XMAX = 8;
+    int nmask = 0;
+    int mk[XMAX];
+    float2 fv[XMAX];
+    if constexpr (TPI <= 64) {
+        __shared__ int xor_ok;
+        if (a.obs_out) {
+            if (tid == 0) xor_ok = 1;
+            __syncthreads();
+            const int w = a.obs_width;
+            for (int ra = tid; ra < D; ra += 256) {
+                int cnt = 0, cnt0 = 0;
+                bool ok = true;
+                for (int e = 0; e < w; ++e) {
+                    const float2 v0 = ovs[e];
+                    if (v0.x != 0.f || v0.y != 0.f) ++cnt0;
+                    const float2 v = ovs[ra * w + e];
+                    if (v.x == 0.f && v.y == 0.f) continue;
+                    ++cnt;
+                    const int c = ocs[ra * w + e];
+                    bool found = false;
+                    for (int e0 = 0; e0 < w; ++e0) {
+                        const float2 u0 = ovs[e0];
+                        if ((u0.x != 0.f || u0.y != 0.f) && ocs[e0] == (c ^ ra) && u0.x == v.x && u0.y == v.y)
+                            found = true;
+                    }
+                    for (int e2 = 0; e2 < e; ++e2) {
+                        const float2 u2 = ovs[ra * w + e2];
+                        if ((u2.x != 0.f || u2.y != 0.f) && ocs[ra * w + e2] == c) ok = false;   // duplicate
+                    }
+                    ok = ok && found;
+                }
+                if (!ok || cnt != cnt0 || cnt0 > XMAX) atomicAnd(&xor_ok, 0);
+            }
+            __syncthreads();
+            if (xor_ok) {
+                for (int e = 0; e < w; ++e) {
+                    const float2 v = ovs[e];
+                    if (v.x == 0.f && v.y == 0.f) continue;
+                    mk[nmask < XMAX ? nmask : XMAX - 1] = ocs[e];
+                    fv[nmask < XMAX ? nmask : XMAX - 1] = v;
+                    ++nmask;
+                }
+            }
+        }
+    }
+    float2 dph[TB];
+    drift_phases<D>(tv, drift, ti, dph);
     for (int n = 0; n < N; ++n) {
         const bool active = valid && n < len;
-        step_left<D>(tv, x, Xs, Fs, ub + (long long)n * tv.K * KK, drift, active, lt == 0, lt, ti, tj);
+        step_left<D>(tv, x, Xs, Fs, ub + (long long)n * tv.K * KK, drift, active, lt == 0, lt, ti, tj, dph);
         if (a.reproject_every > 0 && !a.compose && ((a.step_offset + n + 1) % a.reproject_every) == 0)
             reproject<D>(x, Xs, Fs, active, ti, tj, red, tv.flags, lt == 0);
         if (a.X_prefix && active) {
@@ -481,11 +585,46 @@ __global__ __launch_bounds__(256) void small_chain_kernel(TView tv, SmallChainAr
 #pragma unroll
                 for (int c = 0; c < TB; ++c) dst[(ti + NT * r) * D + tj + NT * c] = x[r][c];
         }
-        if (a.obs_out) {
+        if (a.obs_out && nmask > 0) {
+            // m_n = sum_ab (X M)_ab conj((M X)_ab) / Tr(M M) with the XOR masks (lane shuffles)
+            float2 xm[TB][TB], mx[TB][TB];
+#pragma unroll
+            for (int r = 0; r < TB; ++r)
+#pragma unroll
+                for (int c = 0; c < TB; ++c) xm[r][c] = mx[r][c] = make_float2(0.f, 0.f);
+            for (int t = 0; t < nmask; ++t) {
+                const int ml = mk[t] % NT, mh = mk[t] / NT;   // mh is 0 or 1 (TB = 2)
+                const float2 f = fv[t];
+#pragma unroll
+                for (int r = 0; r < TB; ++r)
+#pragma unroll
+                    for (int c = 0; c < TB; ++c) {
+                        // X_{a, b^m}: lane tj ^ ml, own column c ^ mh;  X_{a^m, b}: lane ti ^ ml, row r ^ mh
+                        const float2 sc = mh ? x[r][c ^ 1] : x[r][c];
+                        const float2 sr = mh ? x[r ^ 1][c] : x[r][c];
+                        float2 vc = sc, vr = sr;
+                        if (ml) {
+                            vc = make_float2(__shfl_xor(sc.x, ml, 64), __shfl_xor(sc.y, ml, 64));
+                            vr = make_float2(__shfl_xor(sr.x, ml * NT, 64), __shfl_xor(sr.y, ml * NT, 64));
+                        }
+                        cfma(xm[r][c], vc, cconj(f));
+                        cfma(mx[r][c], f, vr);
+                    }
+            }
+            double acc = 0.0;
+            if (active) {
+#pragma unroll
+                for (int r = 0; r < TB; ++r)
+#pragma unroll
+                    for (int c = 0; c < TB; ++c) acc += (double)xm[r][c].x * mx[r][c].x + (double)xm[r][c].y * mx[r][c].y;
+            }
+            acc = inst_sum<D>(acc, red);
+            if (active && lt == 0) a.obs_out[(long long)b * a.N_max + n] = acc / obs_norm;
+        } else if (a.obs_out) {
             // m_n = sum_ab (X M)_ab conj((M X)_ab) / Tr(M M)
-            __syncthreads();
+            inst_sync<D>();
             if (active) store_block<D>(Xs, x, ti, tj);
-            __syncthreads();
+            inst_sync<D>();
             double acc = 0.0;
             if (active) {
 #pragma unroll
@@ -570,10 +709,13 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv, SmallGrapeAr
     for (int r = 0; r < TB; ++r)
 #pragma unroll
         for (int c = 0; c < TB; ++c) x[r][c] = make_float2((ti + NT * r) == (tj + NT * c) ? 1.f : 0.f, 0.f);
+    float2 dph[TB], dpc[TB];
+    drift_phases<D>(tv, drift, ti, dph);
+    drift_phases<D>(tv, drift, tj, dpc);
     for (int n = 0; n < N; ++n) {
         const bool active = valid && n < len;
         if (active && n % C == 0) save_block<D>(x, ck + (long long)(n / C) * D * D, ti, tj);
-        step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, lt == 0, lt, ti, tj);
+        step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, lt == 0, lt, ti, tj, dph);
     }
     // ---- overlap g = Tr(U_f^dag X_N) / Tr(U_f^dag U_f)
     const float2* Uf = a.U_target + (long long)(valid ? b : 0) * D * D;
@@ -643,20 +785,20 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv, SmallGrapeAr
         if (seg_active) load_block<D>(x, ck + (long long)sgi * D * D, ti, tj);
         for (int n = s0; n < s1; ++n) {
             const bool active = valid && n < len;
-            step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, false, lt, ti, tj);
+            step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, false, lt, ti, tj, dph);
             if (active) save_block<D>(x, sg + (long long)(n - s0) * D * D, ti, tj);
         }
         for (int s = s1 - 1; s >= s0; --s) {
             const bool active = valid && s < len;
             // Y_{s+1} = X_{s+1} L_{s+1}
-            __syncthreads();
+            inst_sync<D>();
             if (active) {
                 float2 xs[TB][TB];
                 load_block<D>(xs, sg + (long long)(s - s0) * D * D, ti, tj);
                 store_block<D>(Xs, xs, ti, tj);
                 store_block<D>(Ls, l, ti, tj);
             }
-            __syncthreads();
+            inst_sync<D>();
             float2 y[TB][TB];
             if (active) mul_left<D>(y, Xs, Ls, ti, tj);
             // traces per channel; lane 0 completes the gradient of the pending (later) step
@@ -741,7 +883,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv, SmallGrapeAr
                 pend_step = s;
             }
             // L_s = L_{s+1} U_s
-            step_right<D>(tv, l, Ls, Fs, us, drift, active, lt, ti, tj);
+            step_right<D>(tv, l, Ls, Fs, us, drift, active, lt, ti, tj, dpc);
         }
     }
     // D_0 = Tr(G Y_0), Y_0 = X_0 L_0 = L_0

@@ -423,3 +423,28 @@ def test_strang_grape_small_vs_oracle():
     F, ov, grad = t2.grape(torch.tensor(qs.u).cuda(), torch.tensor(qs.U_target).cuda())
     tab2 = O.DiscreteTable(q.S, q.dt, q.eps, q.base, q.digits)
     _grape_check(qs, tab2, F.cpu().numpy(), ov.cpu().numpy(), grad.cpu().numpy(), range(q.B))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("kind", ["xor", "general"])
+def test_observable_xor_and_general_forms_vs_oracle(n, kind):
+    """The fused chain's observable for M = sum_i I_ix (a function of a XOR c: the d <= 16
+    kernels take the partner entries by lane shuffles from row 0's masks) and for the same
+    M plus 0.3 I_z of spin 0 (not of that form: the list path), against the oracle's
+    magnetisation series, with a re-projection and ragged lengths."""
+    d = 2 ** n
+    B = 5
+    p = W.ising_freezing(n=n, B=B, N=150)
+    lens = np.array([150, 99, 150, 1, 64], np.int32)
+    M = p.M.copy()
+    if kind == "general":
+        M = M + 0.3 * np.diag(W.spin_z_diag(n, 0)).astype(complex)
+    t = table(p)
+    cols, vals = W.observable_ell(M)
+    _, _, m = t.chain(torch.tensor(p.u).cuda(), n_steps=torch.tensor(lens), observable=(cols, vals),
+                      reproject_every=64)
+    m = m.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(B):
+        mo, _ = O.magnetisation_series(O.compose_all_redo(p, tab, b, n_steps=int(lens[b])), M)
+        assert np.abs(m[b, :lens[b]] - mo).max() < 1e-5, (b, np.abs(m[b, :lens[b]] - mo).max())
