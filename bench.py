@@ -130,6 +130,9 @@ def bench_freezing(args, redo, W, torch):
             elif kind == "kron":
                 _, m = table.kron_chain(un, X0=X0, out=U, step_offset=n0, reproject_every=args.reproject,
                                         observable=ob, walsh=wf)
+            elif kind == "expm_split":
+                _, m = table.expm_split_chain(un, X0=X0, out=U, step_offset=n0, reproject_every=args.reproject,
+                                              precision=precision, walsh=wf)
             else:
                 _, m = table.expm_chain(un, X0=X0, out=U, step_offset=n0, reproject_every=args.reproject,
                                         observable=ob, precision=precision, walsh=wf)
@@ -180,8 +183,9 @@ def bench_freezing(args, redo, W, torch):
     bf = None if args.no_bf16 else run("redo", 2, K, Wr)
     g4 = None if args.no_4m else run("redo", 0, K, Wr)
     ex = None if args.no_expm else run("expm", 1, args.expm_steps, args.warmup)
+    exs = None if args.no_expm else run("expm_split", 1, args.expm_steps, args.warmup)
     kr = None if args.no_kron else run("kron", 0, K, Wr)
-    out = dict(fp32=fp32, lists=lists, bf16x3=bf, f32_4m=g4, expm=ex, kron=kr, table_build_s=t_table,
+    out = dict(fp32=fp32, lists=lists, bf16x3=bf, f32_4m=g4, expm=ex, expm_split=exs, kron=kr, table_build_s=t_table,
                cache_build_s=t_cache)
     del table
     return out, p
@@ -448,7 +452,8 @@ def oracle_accuracy(args, W, p, fr):
     q = p.subset([0])
     tab = O.DiscreteTable(q.S, q.dt, q.eps, q.base, q.digits)
     t0 = time.perf_counter()
-    m_redo, X_redo = O.magnetisation_series(O.compose_all_redo(q, tab, 0, n_steps=n_r), q.M)
+    redo_steps = O.compose_all_redo(q, tab, 0, n_steps=n_r)
+    m_redo, X_redo = O.magnetisation_series(redo_steps, q.M)
     el = time.perf_counter() - t0
     cpu = dict(value=n_r / el, unit="realisation-steps/s", cores=int(blas_threads()), kind="oracle",
                sample=f"realisation 0 x {n_r} steps of the d=1024 Ising workload (REDO products, chain and "
@@ -468,6 +473,11 @@ def oracle_accuracy(args, W, p, fr):
     for key, name in names.items():
         if fr.get(key) is not None:
             acc[name + "_vs_oracle"] = err(fr[key], m_redo, X_redo)
+    exs = fr.get("expm_split")
+    if exs is not None:
+        n_s = exs["warmup_run"] + exs["steps"]
+        acc["expm_equal_result_vs_oracle"] = dict(err(exs, m_redo[:n_s], O.chain(redo_steps[:n_s])), steps=n_s)
+    del redo_steps
     if not args.no_exact:
         H0m = np.diag(q.H0[0]).astype(np.complex128)
         t0 = time.perf_counter()
@@ -596,6 +606,15 @@ def main():
                                                  "(Paterson-Stockmeyer), same batched FP32 MFMA GEMM (three real products), "
                                                  "same Walsh-frame magnetisation"},
         "speedup_vs_expm": None if ex is None else f32["value"] / ex["value"],
+        "expm_equal_result": None if fr.get("expm_split") is None else {
+            "value": fr["expm_split"]["value"], "unit": "propagator steps/s",
+            "ms_per_step": fr["expm_split"]["ms_per_step"], "steps": args.expm_steps,
+            "method": "the same split, coarse-grained steps as REDO with each control factor "
+                      "exp(-i dt q eps S) by the same Taylor / Paterson-Stockmeyer evaluation and GEMMs, "
+                      "drift phases in the chain product: equal to REDO's result up to FP32 rounding",
+            "error_vs_redo_oracle": None if acc is None else acc.get("expm_equal_result_vs_oracle")},
+        "speedup_vs_expm_equal_result": None if fr.get("expm_split") is None else
+            f32["value"] / fr["expm_split"]["value"],
         "max_abs_dm_vs_oracle": None if acc is None else acc["headline_vs_oracle"]["max_abs_dm"],
         "nfrob_vs_oracle": None if acc is None else acc["headline_vs_oracle"]["nfrob"],
         "method_error_vs_exact": None if acc is None else acc.get("method_error_vs_exact"),

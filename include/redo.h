@@ -394,6 +394,28 @@ redo_status redo_expm_chain(redo_table table, int32_t precision, const float* u,
                             void* stream);
 
 /*
+ * The equal-result comparison point: the chain of redo_chain_propagator's split
+ * model with each control factor evaluated as an exponential instead of table
+ * products, U_n = exp(-i dt (sign q eps)_n S) V (Sec. III, Eq. propUn split as in
+ * Eq. vnd; the amplitude coarse-grained as in Eq. cgrain, Sec. II), by the
+ * scaling-and-squaring Taylor polynomial of redo_expm_chain on the same GEMMs,
+ * the drift phases V applied inside the chain product.  Its result is that of
+ * the REDO chain up to FP32 rounding (the table product equals the exponential
+ * at the quantised amplitude), so a speed ratio against the REDO chain compares
+ * the two at equal accuracy.  One signed channel, a diagonal drift and the Lie
+ * split (REDO_ERR_UNSUPPORTED otherwise); d a multiple of 64; FP32.
+ *   walsh_frame  0: X0 / U_total in the computational basis, no observable
+ *                   (obs_out must be NULL);
+ *                1: the right Walsh frame as redo_expm_chain_walsh, with obs and
+ *                   obs_out as there
+ * Workspace: redo_workspace_bytes(table, REDO_OP_EXPM_CHAIN, B, N_max).
+ */
+redo_status redo_expm_split_chain(redo_table table, int32_t precision, const float* u, const int32_t* n_steps,
+                                  int32_t B, int32_t N_max, int32_t step_offset, int32_t reproject_every,
+                                  const float* X0, float* U_total, int32_t walsh_frame, redo_walsh_obs obs,
+                                  double* obs_out, void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * GRAPE with the plain per-step exponential (the comparison point): the
  * fidelity of the unquantised chain and the usual first-order gradient
  * dU_n/du ~ -i dt H_k U_n (the GRAPE approximation of Khaneja et al., cited in

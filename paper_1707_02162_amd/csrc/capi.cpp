@@ -1028,6 +1028,29 @@ redo_status redo_expm_chain_walsh(redo_table t, int32_t precision, const float* 
                       obs_out ? obs->spec : nullptr);
 }
 
+redo_status redo_expm_split_chain(redo_table t, int32_t precision, const float* u, const int32_t* n_steps, int32_t B,
+                                  int32_t N_max, int32_t step_offset, int32_t reproject_every, const float* X0,
+                                  float* U_total, int32_t walsh_frame, redo_walsh_obs obs, double* obs_out,
+                                  void* workspace, size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    if (B < 1 || N_max < 1) return fail(REDO_ERR_ARG, "B and N_max must be >= 1");
+    if (!u || !U_total) return fail(REDO_ERR_ARG, "u and U_total must not be NULL");
+    if (step_offset < 0 || reproject_every < 0) return fail(REDO_ERR_ARG, "step_offset, reproject_every must be >= 0");
+    if (precision < REDO_PREC_F32 || precision > REDO_PREC_BF16X3) return fail(REDO_ERR_ARG, "unknown precision");
+    if (walsh_frame != 0 && walsh_frame != 1) return fail(REDO_ERR_ARG, "walsh_frame must be 0 or 1");
+    if (!walsh_frame && obs_out) return fail(REDO_ERR_ARG, "the observable is evaluated in the Walsh frame only");
+    redo_status st = check_walsh_obs(t, obs, obs_out);
+    if (st != REDO_OK) return st;
+    if (t->desc.d % 64 != 0) return fail(REDO_ERR_UNSUPPORTED, "the exponential baseline needs d a multiple of 64");
+    if (walsh_frame && !walsh_dim(t->desc.d))
+        return fail(REDO_ERR_UNSUPPORTED, "the Walsh frame needs d = 2^n, 128 .. 2048");
+    return expm_chain(t, precision, u, n_steps, B, N_max, step_offset, reproject_every, X0, U_total,
+                      obs_out ? obs->cols : nullptr, obs_out ? reinterpret_cast<const float*>(obs->vals) : nullptr,
+                      obs_out ? obs->w : 0, obs_out, workspace, workspace_bytes, static_cast<hipStream_t>(stream),
+                      walsh_frame != 0, obs_out ? obs->spec : nullptr, 1);
+}
+
 redo_status redo_expm_grape_fidelity_grad(redo_table t, int32_t precision, const float* u, const int32_t* n_steps,
                                           int32_t B, int32_t N_max, const float* U_target, int32_t checkpoint_every,
                                           double* fidelity, double* overlap, float* grad, void* workspace,

@@ -30,11 +30,14 @@ __global__ void amp_bound_kernel(long long count, int K, int phased, const float
 
 // A_b = -i scale (H0 + sum_k H_k(u_bk)) for the pairs of a chunk; pair i reads
 // its amplitudes at u + (pair0 + i) * ustride and its drift ((pair0 + i) / drift_div) % n_drift
+// split = 1 (signed channels): A_b = -i scale sum_k (sign q eps)_bk S_k, the control term alone
+// at the coarse-grained amplitude of Eq. cgrain, for the split step exp(A) V
 __global__ __launch_bounds__(256) void build_A_kernel(int d, int K, int phased, int dense, int n_drift, int count,
                                                       long long pair0, int drift_div, const float* __restrict__ u,
                                                       long long ustride, const float2* __restrict__ S,
                                                       const float2* __restrict__ Sy, const double* __restrict__ h,
-                                                      const float2* __restrict__ H, double scale, float2* A) {
+                                                      const float2* __restrict__ H, double scale, float2* A, int split,
+                                                      double eps, double qmax) {
     const long long nn = (long long)d * d;
     const int i = blockIdx.y;
     if (i >= count) return;
@@ -42,17 +45,25 @@ __global__ __launch_bounds__(256) void build_A_kernel(int d, int K, int phased, 
     const int drift = (int)((pair / drift_div) % n_drift);
     const float* up = u + pair * ustride;
     const int kk = phased ? 2 : 1;
+    float uq[16];
+    if (split)
+        for (int k = 0; k < K && k < 16; ++k) {
+            double phi;
+            uq[k] = (float)((double)quantise_one(up + k, 0, eps, qmax, &phi, nullptr) * eps);
+        }
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (long long)gridDim.x * blockDim.x) {
         const int a = (int)(e / d), c = (int)(e % d);
         float2 hv;
-        if (dense) {
+        if (split) {
+            hv = make_float2(0.f, 0.f);
+        } else if (dense) {
             hv = H[(long long)drift * nn + e];
         } else {
             hv = make_float2(a == c ? (float)h[(long long)drift * d + a] : 0.f, 0.f);
         }
         for (int k = 0; k < K; ++k) {
             const float2 sv = S[(long long)k * nn + e];
-            const float ux = up[k * kk];
+            const float ux = split ? uq[k < 16 ? k : 15] : up[k * kk];
             hv.x = fmaf(ux, sv.x, hv.x);
             hv.y = fmaf(ux, sv.y, hv.y);
             if (phased) {
@@ -114,11 +125,11 @@ hipError_t expm_amp_bound(int B, int N, int K, int phased, const float* u, const
 }
 
 hipError_t expm_build_A(const redo_table_s* t, int count, long long pair0, int drift_div, const float* u, long long ustride,
-                        double scale, float2* A, hipStream_t st) {
+                        double scale, float2* A, hipStream_t st, int split) {
     const int d = t->desc.d;
     hipLaunchKernelGGL(build_A_kernel, dim3(grid_x((long long)d * d, count), count), dim3(256), 0, st, d, t->desc.K,
                        t->desc.phased, t->desc.drift_is_diag ? 0 : 1, t->desc.n_drift, count, pair0, drift_div, u,
-                       ustride, t->S32, t->Sy32, t->h64, t->H32, scale, A);
+                       ustride, t->S32, t->Sy32, t->h64, t->H32, scale, A, split, t->desc.eps, t->qmax);
     return hipGetLastError();
 }
 
@@ -141,8 +152,10 @@ hipError_t expm_descs(GemmDesc* descs, int count, const float2* A, long long sA,
 namespace redo {
 namespace {
 // chain descriptors from tracked locations: X[loc^1]_b = U_i X[loc]_b for b = b0 + i, inactive skipped
+// kscale (nullable): diagonal of the right factor, per drift ([n_drift][d]): X' = U diag(v) X
 __global__ void chain_descs_kernel(GemmDesc* descs, int count, int b0, const float2* U, long long sU, float2* X0,
-                                   float2* X1, long long xstride, int* loc, const int* n_steps, int step) {
+                                   float2* X1, long long xstride, int* loc, const int* n_steps, int step,
+                                   const float2* kscale, int d, int n_drift) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const int b = b0 + i;
@@ -155,15 +168,17 @@ __global__ void chain_descs_kernel(GemmDesc* descs, int count, int b0, const flo
     g.A = U + i * sU;
     g.B = X[l] + (long long)b * xstride;
     g.C = X[l ^ 1] + (long long)b * xstride;
+    if (kscale) g.kscale = kscale + (long long)(b % n_drift) * d;
     descs[i] = g;
     if (active) loc[b] = l ^ 1;
 }
 }  // namespace
 
 hipError_t chain_descs(GemmDesc* descs, int count, int b0, const float2* U, long long sU, float2* X0, float2* X1,
-                       long long xstride, int* loc, const int* n_steps, int step, hipStream_t st) {
+                       long long xstride, int* loc, const int* n_steps, int step, hipStream_t st, const float2* kscale,
+                       int d, int n_drift) {
     hipLaunchKernelGGL(chain_descs_kernel, dim3((count + 63) / 64), dim3(64), 0, st, descs, count, b0, U, sU, X0, X1,
-                       xstride, loc, n_steps, step);
+                       xstride, loc, n_steps, step, kscale, d, n_drift);
     return hipGetLastError();
 }
 }  // namespace redo

@@ -17,12 +17,13 @@ namespace redo {
 hipError_t expm_amp_bound(int B, int N, int K, int phased, const float* u, const double* snorm, unsigned long long* out,
                           hipStream_t st);
 hipError_t expm_build_A(const redo_table_s* t, int count, long long pair0, int drift_div, const float* u,
-                        long long ustride, double scale, float2* A, hipStream_t st);
+                        long long ustride, double scale, float2* A, hipStream_t st, int split = 0);
 hipError_t expm_lincomb(int d, int count, int r, const float* c, const float2* pw, float2* out, hipStream_t st);
 hipError_t expm_descs(GemmDesc* descs, int count, const float2* A, long long sA, const float2* B, long long sB, float2* C,
                       long long sC, const float2* add, long long sAdd, hipStream_t st);
 hipError_t chain_descs(GemmDesc* descs, int count, int b0, const float2* U, long long sU, float2* X0, float2* X1,
-                       long long xstride, int* loc, const int* n_steps, int step, hipStream_t st);
+                       long long xstride, int* loc, const int* n_steps, int step, hipStream_t st,
+                       const float2* kscale = nullptr, int d = 0, int n_drift = 1);
 
 namespace {
 
@@ -97,10 +98,10 @@ struct ExpmChunkWS {
 
 // exp(A_i) for `cnt` pairs starting at pair0; result left in w.P (stride d*d)
 redo_status expm_chunk(const redo_table_s* t, const PSPlan& pl, int prec, int cnt, long long pair0, int drift_div,
-                       const float* u, long long ustride, ExpmChunkWS& w, hipStream_t st) {
+                       const float* u, long long ustride, ExpmChunkWS& w, hipStream_t st, int split = 0) {
     const int d = t->desc.d;
     const long long nn = (long long)d * d;
-    REDO_HIP(expm_build_A(t, cnt, pair0, drift_div, u, ustride, t->desc.dt / std::ldexp(1.0, pl.s), w.pw, st));
+    REDO_HIP(expm_build_A(t, cnt, pair0, drift_div, u, ustride, t->desc.dt / std::ldexp(1.0, pl.s), w.pw, st, split));
     for (int j = 2; j <= pl.r; ++j) {
         REDO_HIP(expm_descs(w.descs, cnt, w.pw + (size_t)(j - 2) * cnt * nn, nn, w.pw, nn,
                             w.pw + (size_t)(j - 1) * cnt * nn, nn, nullptr, 0, st));
@@ -136,7 +137,7 @@ redo_status expm_chunk(const redo_table_s* t, const PSPlan& pl, int prec, int cn
 }
 
 redo_status plan_for_call(const redo_table_s* t, int B, int N, const float* u, unsigned long long* dbound, PSPlan* out,
-                          hipStream_t st) {
+                          hipStream_t st, int split = 0) {
     REDO_HIP(hipMemsetAsync(dbound, 0, sizeof(unsigned long long), st));
     REDO_HIP(expm_amp_bound(B, N, t->desc.K, t->desc.phased, u, t->s_norm.data(), dbound, st));
     unsigned long long bits = 0;
@@ -145,7 +146,11 @@ redo_status plan_for_call(const redo_table_s* t, int B, int N, const float* u, u
     double amp;
     std::memcpy(&amp, &bits, sizeof(amp));
     double hmax = 0.0;
-    for (double v : t->h_norm) hmax = std::max(hmax, v);
+    if (!split)
+        for (double v : t->h_norm) hmax = std::max(hmax, v);
+    // split: the coarse-grained amplitude exceeds the given one by at most eps / 2 per channel
+    if (split)
+        for (int k = 0; k < t->desc.K; ++k) amp += 0.5 * t->desc.eps * t->s_norm[k];
     *out = choose_plan(t->desc.dt * (hmax + amp));
     return REDO_OK;
 }
@@ -192,8 +197,11 @@ redo_status expm_compose_pairs(const redo_table_s* t, int precision, long long I
 redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N, int step_offset,
                        int reproject_every, const float* X0, float* U_total, const int* obs_cols, const float* obs_vals,
                        int obs_width, double* obs_out, void* workspace, size_t workspace_bytes, hipStream_t st,
-                       bool walsh_frame, const double* walsh) {
+                       bool walsh_frame, const double* walsh, int split) {
     if (precision == REDO_PREC_BF16X3) return fail(REDO_ERR_UNSUPPORTED, "the exponential baseline runs in FP32");
+    if (split && (t->desc.phased || t->desc.K != 1 || !t->desc.drift_is_diag || t->desc.splitting))
+        return fail(REDO_ERR_UNSUPPORTED,
+                    "the split exponential chain takes one signed channel, a diagonal drift and the Lie split");
     const size_t need = expm_chain_workspace_bytes(t, B, N);
     if (!workspace || workspace_bytes < need)
         return fail(REDO_ERR_WORKSPACE, "exponential chain workspace needs " + std::to_string(need) + " bytes");
@@ -218,7 +226,7 @@ redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int
     off += align_up(8);
     ExpmChunkWS w(d, ps_r_max(d), base + off);
     PSPlan pl;
-    redo_status s = plan_for_call(t, B, N, u, dbound, &pl, st);
+    redo_status s = plan_for_call(t, B, N, u, dbound, &pl, st, split);
     if (s != REDO_OK) return s;
     if (pl.r > ps_r_max(d)) return fail(REDO_ERR_UNSUPPORTED, "exponential norm too large for the baseline plan");
     const int prec = precision == REDO_PREC_F32_3M ? 1 : 0;
@@ -233,9 +241,11 @@ redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int
         for (int b0 = 0; b0 < B; b0 += EXPM_CHUNK) {
             const int cnt = std::min(EXPM_CHUNK, B - b0);
             // entry i is instance b = b0 + i: amplitudes at u + (b N + n) K(2), drift b % n_drift
-            s = expm_chunk(t, pl, prec, cnt, b0, 1, u + (long long)n * ustride_pair, ustride_pair * N, w, st);
+            s = expm_chunk(t, pl, prec, cnt, b0, 1, u + (long long)n * ustride_pair, ustride_pair * N, w, st, split);
             if (s != REDO_OK) return s;
-            REDO_HIP(chain_descs(descs, cnt, b0, w.P, nn, X[0], X[1], nn, loc, n_steps, n, st));
+            // split: X' = exp(A) V X with the drift phases V on the right (diagonal drift)
+            REDO_HIP(chain_descs(descs, cnt, b0, w.P, nn, X[0], X[1], nn, loc, n_steps, n, st,
+                                 split ? t->V32 : nullptr, d, t->desc.n_drift));
             REDO_HIP(cgemm_batched(d, cnt, descs, prec, st, 1));
         }
         if (reproject_every > 0 && ((long long)step_offset + n + 1) % reproject_every == 0) {

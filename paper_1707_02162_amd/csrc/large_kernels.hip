@@ -603,11 +603,14 @@ __global__ __launch_bounds__(256) void walsh_right_kernel(int d, long long rows,
 }
 
 // The observable in the right Walsh frame, one pass: the 8-column strip of W in LDS (as
-// observable_mx8_kernel), each lane forms (M W)_aj for its rows a and columns j and adds
-// D_j Re(conj(W_aj) (M W)_aj) (FP32 within a row, FP64 across rows); the workgroup's sum goes
-// to partial[b][strip].  The frame needs M_ac = f(a XOR c), so row a's list is row 0's with
-// every column XORed by a: the masks and values are read once from row 0 (one address for
-// every lane) and its zero entries, the padding among them, are skipped.
+// observable_mx8_kernel).  The frame needs M_ac = f(a XOR c) with f real, so row a's list is
+// row 0's with every column XORed by a: the masks m and values f(m) are read once from row 0
+// (one address for every lane; zero entries, the padding among them, skipped) and
+//     w_j^dag M w_j = f(0) sum_a |W_aj|^2 + sum_{m != 0} 2 f(m) sum_{a < a^m} Re(conj(W_aj) W_{a^m, j}),
+// each unordered pair once: the rows with a zero at the top bit of m, a = the pair index with
+// that zero inserted.  LPR lanes share a pair (8 / LPR columns each); a lane's column sums
+// stay in FP32 over its pairs and masks, then D_j weights them and the workgroup sum runs in
+// FP64 to partial[b][strip].
 template <int WP, int NT, int LPR>
 __global__ __launch_bounds__(NT, NT / 128) void observable_walsh_kernel(int d, int b0, const float2* __restrict__ X0,
                                                                         const float2* __restrict__ X1, const int* loc,
@@ -651,34 +654,49 @@ __global__ __launch_bounds__(NT, NT / 128) void observable_walsh_kernel(int d, i
     int mk[WP];
     float2 fv[WP];
     obs_list<WP>(cols, vals, 0, mk, fv);
-    double sum = 0.0;
-    for (int a = tid / LPR; a < d; a += RPP) {
-        float2 acc[CPL];
+    // the lane's NCH 16-byte chunks of row a: columns lr * CPL .. lr * CPL + CPL - 1
+    auto chunk = [&](int a, int j) { return strip4[a * 4 + (((lr * NCH + j) ^ (a >> 2)) & 3)]; };
+    float acc[CPL];
 #pragma unroll
-        for (int u = 0; u < CPL; ++u) acc[u] = make_float2(0.f, 0.f);
+    for (int u = 0; u < CPL; ++u) acc[u] = 0.f;
 #pragma unroll
-        for (int t = 0; t < WP; ++t) {
-            if (fv[t].x == 0.f && fv[t].y == 0.f) continue;   // the same for every lane
-            const int c = a ^ mk[t];
+    for (int t = 0; t < WP; ++t) {
+        if (fv[t].x == 0.f && fv[t].y == 0.f) continue;   // the same for every lane
+        const int m = mk[t];
+        float sm[CPL];
 #pragma unroll
-            for (int j = 0; j < NCH; ++j) {
-                const int ch = lr * NCH + j;
-                const float4 x = strip4[c * 4 + ((ch ^ (c >> 2)) & 3)];
-                cfma(acc[2 * j], fv[t], make_float2(x.x, x.y));
-                cfma(acc[2 * j + 1], fv[t], make_float2(x.z, x.w));
+        for (int u = 0; u < CPL; ++u) sm[u] = 0.f;
+        if (m == 0) {
+            for (int a = tid / LPR; a < d; a += RPP) {
+#pragma unroll
+                for (int j = 0; j < NCH; ++j) {
+                    const float4 x = chunk(a, j);
+                    sm[2 * j] = fmaf(x.x, x.x, fmaf(x.y, x.y, sm[2 * j]));
+                    sm[2 * j + 1] = fmaf(x.z, x.z, fmaf(x.w, x.w, sm[2 * j + 1]));
+                }
             }
-            asm volatile("" ::: "memory");   // one mask's gathers at a time (register pressure)
-        }
-        float row = 0.f;
 #pragma unroll
-        for (int j = 0; j < NCH; ++j) {
-            const int ch = lr * NCH + j;
-            const float4 wv = strip4[a * 4 + ((ch ^ (a >> 2)) & 3)];
-            row += dj[2 * j] * (wv.x * acc[2 * j].x + wv.y * acc[2 * j].y) +
-                   dj[2 * j + 1] * (wv.z * acc[2 * j + 1].x + wv.w * acc[2 * j + 1].y);
+            for (int u = 0; u < CPL; ++u) acc[u] = fmaf(fv[t].x, sm[u], acc[u]);
+        } else {
+            const int top = 31 - __clz(m);
+            const int low = (1 << top) - 1;
+            for (int pr = tid / LPR; pr < d / 2; pr += RPP) {
+                const int a = ((pr & ~low) << 1) | (pr & low);
+                const int c = a ^ m;
+#pragma unroll
+                for (int j = 0; j < NCH; ++j) {
+                    const float4 x = chunk(a, j), y = chunk(c, j);
+                    sm[2 * j] = fmaf(x.x, y.x, fmaf(x.y, y.y, sm[2 * j]));
+                    sm[2 * j + 1] = fmaf(x.z, y.z, fmaf(x.w, y.w, sm[2 * j + 1]));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CPL; ++u) acc[u] = fmaf(2.f * fv[t].x, sm[u], acc[u]);
         }
-        sum += (double)row;
     }
+    double sum = 0.0;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) sum += (double)dj[u] * (double)acc[u];
     red[tid] = sum;
     __syncthreads();
     for (int st = NT / 2; st > 0; st >>= 1) {
@@ -1436,8 +1454,10 @@ template <int WP>
 static hipError_t walsh_obs(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
                             const int* cols, const float2* vals, const double* spec, const int* n_steps, int step,
                             double* partial, hipStream_t st) {
-    return d >= 256 ? launch_walsh_obs<WP, 1>(d, B, X0, X1, loc, xstride, cols, vals, spec, n_steps, step, partial, st)
-                    : launch_walsh_obs<WP, 2>(d, B, X0, X1, loc, xstride, cols, vals, spec, n_steps, step, partial, st);
+    // enough lanes per pair that the d / 2 pairs of a mask cover the 256 threads
+    if (d >= 512) return launch_walsh_obs<WP, 1>(d, B, X0, X1, loc, xstride, cols, vals, spec, n_steps, step, partial, st);
+    if (d == 256) return launch_walsh_obs<WP, 2>(d, B, X0, X1, loc, xstride, cols, vals, spec, n_steps, step, partial, st);
+    return launch_walsh_obs<WP, 4>(d, B, X0, X1, loc, xstride, cols, vals, spec, n_steps, step, partial, st);
 }
 
 hipError_t observable_walsh(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,

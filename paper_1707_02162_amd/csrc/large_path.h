@@ -29,7 +29,7 @@ redo_status expm_compose_pairs(const redo_table_s* t, int precision, long long I
 redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int* n_steps, int B, int N, int step_offset,
                        int reproject_every, const float* X0, float* U_total, const int* obs_cols, const float* obs_vals,
                        int obs_width, double* obs_out, void* workspace, size_t workspace_bytes, hipStream_t st,
-                       bool walsh_frame = false, const double* walsh = nullptr);
+                       bool walsh_frame = false, const double* walsh = nullptr, int split = 0);
 
 // ---- kernels of large_kernels.hip
 struct PlanLaunch {

@@ -43,6 +43,7 @@ _SIG = {
     "redo_grape_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _I, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "redo_expm_chain": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _I, _P, _P, ctypes.c_size_t, _P]),
     "redo_expm_grape_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _I, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "redo_expm_split_chain": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _I, _P, _P, _P, ctypes.c_size_t, _P]),
     "redo_grape_state_fidelity_grad": (_I, [_P, _I, _P, _P, _I, _I, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "redo_grape_noalloc_max_bytes": (ctypes.c_size_t, []),
     "redo_grape_fidelity_grad_noalloc": (_I, [_P, _I, _P, _P, _I, _I, _P, _I, _P, _P, _P, _P]),
@@ -364,6 +365,24 @@ class RedoTable:
         _check(lib().redo_expm_chain(self._h, precision, _ptr(ut), _ptr(ns), B, N, step_offset, reproject_every,
                                      _ptr(X0t), _ptr(U), _ptr(cols), _ptr(vals), w, _ptr(obs), _ptr(ws), ws.numel(),
                                      _stream()))
+        return U, obs
+
+    def expm_split_chain(self, u, n_steps=None, precision: int = PREC_F32, X0=None, reproject_every: int = 0,
+                         step_offset: int = 0, out: Optional[torch.Tensor] = None, walsh=None):
+        """The equal-result comparison point: the REDO chain's split model with each control
+        factor an exponential at the coarse-grained amplitude (one signed channel, diagonal
+        drift).  walsh: None (computational basis, no observable), True (the right Walsh
+        frame) or a WalshObservable (the frame and its observable).  Returns (U_total, obs or None)."""
+        ut = self._u(u)
+        B, N = ut.shape[:2]
+        ns = None if n_steps is None else _dev(n_steps, torch.int32, self.device)
+        X0t = None if X0 is None else _dev(X0, torch.complex64, self.device)
+        U = out if out is not None else torch.empty((B, self.d, self.d), dtype=torch.complex64, device=self.device)
+        h, obs = (None, None) if walsh is None else self._walsh_args(walsh, None, B, N)
+        ws = self.workspace(OP_EXPM_CHAIN, B, N)
+        _check(lib().redo_expm_split_chain(self._h, precision, _ptr(ut), _ptr(ns), B, N, step_offset, reproject_every,
+                                           _ptr(X0t), _ptr(U), 0 if walsh is None else 1, h, _ptr(obs), _ptr(ws),
+                                           ws.numel(), _stream()))
         return U, obs
 
     def state_grape(self, u, psi0, psi_f, n_steps=None):
