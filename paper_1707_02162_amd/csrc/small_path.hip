@@ -456,8 +456,14 @@ __device__ void reproject(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float
 }
 
 // ---------------------------------------------------------------- chain kernel
-template <int D>
-__global__ __launch_bounds__(256) void small_chain_kernel(TView tv, SmallChainArgs a, int ninst) {
+// PH: the table's phased flag as a compile-time constant (the signed-channel instance carries
+// no phase arithmetic: no atan2 or sincos per step, far fewer registers).  That instance at
+// d <= 16 fits 128 registers without spills, four waves per SIMD.
+template <int D, int PH>
+__global__ __launch_bounds__(256, (PH == 0 && D <= 16) ? 4 : 1) void small_chain_kernel(TView tv_in, SmallChainArgs a,
+                                                                                        int ninst) {
+    TView tv = tv_in;
+    tv.phased = PH;
     constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT, TPI = Cfg<D>::TPI, IPB = Cfg<D>::IPB;
     extern __shared__ float2 lds[];
     __shared__ double red[4];
@@ -560,12 +566,22 @@ __global__ __launch_bounds__(256) void small_chain_kernel(TView tv, SmallChainAr
                 if (!ok || cnt != cnt0 || cnt0 > XMAX) atomicAnd(&xor_ok, 0);
             }
             __syncthreads();
+#pragma unroll
+            for (int t = 0; t < XMAX; ++t) {
+                mk[t] = 0;
+                fv[t] = make_float2(0.f, 0.f);
+            }
             if (xor_ok) {
                 for (int e = 0; e < w; ++e) {
                     const float2 v = ovs[e];
                     if (v.x == 0.f && v.y == 0.f) continue;
-                    mk[nmask < XMAX ? nmask : XMAX - 1] = ocs[e];
-                    fv[nmask < XMAX ? nmask : XMAX - 1] = v;
+                    // compile-time register indices (a runtime index would put the arrays in scratch)
+#pragma unroll
+                    for (int t = 0; t < XMAX; ++t)
+                        if (t == nmask) {
+                            mk[t] = ocs[e];
+                            fv[t] = v;
+                        }
                     ++nmask;
                 }
             }
@@ -592,7 +608,9 @@ __global__ __launch_bounds__(256) void small_chain_kernel(TView tv, SmallChainAr
             for (int r = 0; r < TB; ++r)
 #pragma unroll
                 for (int c = 0; c < TB; ++c) xm[r][c] = mx[r][c] = make_float2(0.f, 0.f);
-            for (int t = 0; t < nmask; ++t) {
+#pragma unroll
+            for (int t = 0; t < XMAX; ++t) {
+                if (t >= nmask) break;                        // the same for every lane
                 const int ml = mk[t] % NT, mh = mk[t] / NT;   // mh is 0 or 1 (TB = 2)
                 const float2 f = fv[t];
 #pragma unroll
@@ -676,8 +694,10 @@ __device__ inline void save_block(const float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], flo
         for (int c = 0; c < TB; ++c) dst[(ti + NT * r) * D + tj + NT * c] = x[r][c];
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void small_grape_kernel(TView tv, SmallGrapeArgs a) {
+template <int D, int PH>
+__global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrapeArgs a) {
+    TView tv = tv_in;
+    tv.phased = PH;
     constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT, TPI = Cfg<D>::TPI, IPB = Cfg<D>::IPB;
     extern __shared__ float2 lds[];
     __shared__ double red[4];
@@ -913,11 +933,14 @@ hipError_t launch_chain(const TView& tv, const SmallChainArgs& a, int ninst, hip
     constexpr int IPB = Cfg<D>::IPB;
     const size_t lds = (size_t)IPB * 2 * D * D * sizeof(float2) +
                        (a.obs_out ? (size_t)D * a.obs_width * (sizeof(float2) + sizeof(int)) : 0);
-    hipError_t e = hipFuncSetAttribute((const void*)small_chain_kernel<D>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const void* k = tv.phased ? (const void*)small_chain_kernel<D, 1> : (const void*)small_chain_kernel<D, 0>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int grid = (ninst + IPB - 1) / IPB;
-    hipLaunchKernelGGL(small_chain_kernel<D>, dim3(grid), dim3(256), lds, st, tv, a, ninst);
+    if (tv.phased)
+        hipLaunchKernelGGL((small_chain_kernel<D, 1>), dim3(grid), dim3(256), lds, st, tv, a, ninst);
+    else
+        hipLaunchKernelGGL((small_chain_kernel<D, 0>), dim3(grid), dim3(256), lds, st, tv, a, ninst);
     return hipGetLastError();
 }
 
@@ -925,11 +948,14 @@ template <int D>
 hipError_t launch_grape(const TView& tv, const SmallGrapeArgs& a, hipStream_t st) {
     constexpr int IPB = Cfg<D>::IPB;
     const size_t lds = (size_t)IPB * 3 * D * D * sizeof(float2);
-    hipError_t e = hipFuncSetAttribute((const void*)small_grape_kernel<D>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const void* k = tv.phased ? (const void*)small_grape_kernel<D, 1> : (const void*)small_grape_kernel<D, 0>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int grid = (a.B + IPB - 1) / IPB;
-    hipLaunchKernelGGL(small_grape_kernel<D>, dim3(grid), dim3(256), lds, st, tv, a);
+    if (tv.phased)
+        hipLaunchKernelGGL((small_grape_kernel<D, 1>), dim3(grid), dim3(256), lds, st, tv, a);
+    else
+        hipLaunchKernelGGL((small_grape_kernel<D, 0>), dim3(grid), dim3(256), lds, st, tv, a);
     return hipGetLastError();
 }
 
