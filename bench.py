@@ -152,8 +152,9 @@ def bench_freezing(args, redo, W, torch):
             redo.walsh_right(U)   # the final states back in the computational basis
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        gemm_ms, launches = redo.profile_read(reset=True)
+        gemm_ms, launches = redo.profile_read(reset=True)                # step products
         kron_ms, kron_launches = redo.profile_read(reset=True, kind=1)
+        rp_ms, rp_launches = redo.profile_read(reset=True, kind=2)       # re-projection products
         redo.profile_enable(False)
         m = mag[:, :warm + steps].cpu().numpy()
         common = dict(value=B * steps / elapsed, ms_per_step=1e3 * elapsed / steps, steps=steps, warmup_run=warm,
@@ -169,18 +170,36 @@ def bench_freezing(args, redo, W, torch):
         codes, _ = table.quantise(u[:, warm:warm + steps].contiguous())
         cn = codes.cpu().numpy()
         products = int(np.count_nonzero(cn)) if args.cache else count_products(cn, p.base, p.digits)
-        # every re-projection step adds two products per realisation (X^dag X, then X Z)
-        products += 2 * B * common["reprojections_timed"]
         # the product form's own real flops: 8 d^3 (four real products), 6 d^3 (Gauss, three)
-        flops = (6.0 if precision == 1 else 8.0) * p.d ** 3 * products
+        per_product = (6.0 if precision == 1 else 8.0) * p.d ** 3
+        flops = per_product * products
+        # every re-projection step adds two products per realisation (X^dag X, then X Z), timed apart
+        rp_products = 2 * B * common["reprojections_timed"]
+        rp = None
+        if kind == "redo" and rp_launches:
+            rp = dict(launches=rp_launches, avg_launch_ms=rp_ms / rp_launches, products=rp_products,
+                      achieved_tflops=per_product * rp_products / (rp_ms * 1e-3) / 1e12)
         return dict(common, gemm_ms=gemm_ms, gemm_launches=launches, products=products,
                     achieved=(flops / (gemm_ms * 1e-3) / 1e12) if kind == "redo" else None,
-                    step_flops=flops / steps,
+                    step_flops=(flops + per_product * rp_products) / steps, reproject_gemm=rp,
                     flops_per_launch=flops / max(launches, 1), avg_launch_ms=gemm_ms / max(launches, 1))
 
     fp32 = run("redo", 1, K, Wr)
     lists = None if args.no_lists else run("redo", 1, K, Wr, walsh=False)
-    bf = None if args.no_bf16 else run("redo", 2, K, Wr)
+    bf = None
+    if not args.no_bf16:
+        t_split = None
+        if args.cache:
+            # the cached levels as pre-split BF16 panels: only the state is split as it is loaded
+            t0 = time.time()
+            table.cache_split_bf16()
+            torch.cuda.synchronize()
+            t_split = time.time() - t0
+            log(f"[bench] cached levels pre-split to BF16 in {t_split:.2f}s")
+        bf = run("redo", 2, K, Wr)
+        bf["presplit_build_s"] = t_split
+        if args.cache:
+            table.cache_split_bf16(False)
     g4 = None if args.no_4m else run("redo", 0, K, Wr)
     ex = None if args.no_expm else run("expm", 1, args.expm_steps, args.warmup)
     exs = None if args.no_expm else run("expm_split", 1, args.expm_steps, args.warmup)
@@ -527,7 +546,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the d=8 freezing sweep")
     ap.add_argument("--no-freezing", action="store_true",
                     help="skip the headline workload (profiling runs of the others; prints no headline value)")
-    ap.add_argument("--sweep-instances", type=int, default=8000)
+    ap.add_argument("--sweep-instances", type=int, default=16384)
     ap.add_argument("--c1-replicas", type=int, default=65536)
     ap.add_argument("--no-small", action="store_true", help="skip the d=4 and d=32 lines")
     ap.add_argument("--no-cache", dest="cache", action="store_false",
@@ -630,6 +649,9 @@ def main():
                                           "executed_bf16_tflops": 3 * bf["achieved"],
                                           "frac_of_bf16_peak": 3 * bf["achieved"] / 2500.0,
                                           "avg_launch_ms": bf["avg_launch_ms"],
+                                          "reproject_gemm": bf["reproject_gemm"],
+                                          "presplit_levels": bf["presplit_build_s"] is not None,
+                                          "presplit_build_s": bf["presplit_build_s"],
                                           "max_abs_dm_vs_fp32_last_step": float(np.abs(bf["mag_last"] - f32["mag_last"]).max())},
         "f32_4m": None if g4 is None else {
             "value": g4["value"], "unit": "propagator steps/s", "ms_per_step": g4["ms_per_step"],
@@ -668,10 +690,10 @@ def main():
                      "flops_per_launch": f32["flops_per_launch"], "avg_launch_ms": f32["avg_launch_ms"],
                      "launches": f32["gemm_launches"],
                      "flops_note": "6 d^3 real flops per complex product (the Gauss form's own count; the "
-                                   "four-product form would be 8 d^3), over the step products of the timed "
-                                   "window and the two products per realisation of its re-projection step; "
-                                   "launches = one per step plus two per 256-realisation chunk of a "
-                                   "re-projection"},
+                                   "four-product form would be 8 d^3) over the step products of the timed "
+                                   "window, one launch per step (4096 products); the re-projection products "
+                                   "run as a separate instantiation (role 2) and are reported apart",
+                     "reproject_gemm": f32["reproject_gemm"]},
         "cpu_baseline": cpu,
         "accuracy_vs_oracle": acc,
     }

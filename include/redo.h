@@ -125,11 +125,31 @@ redo_status redo_table_destroy(redo_table table);
  * calls apply one product per channel and step for every amplitude whose
  * level is cached, instead of one per non-zero digit (at d <= 64 only when
  * the cache holds every level 0 .. b^P - 1); results then agree with the
- * uncached path to FP32 rounding.  Replaces
- * any earlier cache; q_hi < 0 only frees it.  Synchronises `stream`.  Must not
- * overlap other calls on the same table.  Errors: REDO_ERR_ARG, REDO_ERR_ALLOC.
+ * uncached path to FP32 rounding.  A channel whose generator is real (every
+ * imaginary part zero) has symmetric levels; their FP64 products are made
+ * exactly symmetric, (R + R^T)/2, before the rounding.  Replaces any earlier
+ * cache (and frees its pre-split copy); q_hi < 0 only frees it.  Synchronises
+ * `stream`.  Must not overlap other calls on the same table.  Errors:
+ * REDO_ERR_ARG, REDO_ERR_ALLOC.
  */
 redo_status redo_cache_levels(redo_table table, int32_t q_lo, int32_t q_hi, void* stream);
+
+/*
+ * The cached levels of process 3 (Sec. II) a second time, as the operands of
+ * the split-BF16 products (precision REDO_PREC_BF16X3) read them: every FP32
+ * entry x held as hi = RNE_bf16(x) and lo = RNE_bf16(x - hi) for its real and
+ * imaginary parts, in panels of 16 columns (8 bytes per entry, the size of the
+ * FP32 cache).  Split-BF16 products at d >= 128 then load a cached level
+ * without splitting it; the state is still split as it is loaded.  A negative
+ * level q uses the panel of |q| conjugated, which is R(|q|)^H only when every
+ * channel's generator is real (levels exactly symmetric); otherwise negative
+ * levels keep the in-kernel split.  Results are identical (as values) to those
+ * without the copy.  keep = 1 builds the copy (replacing an earlier one), 0
+ * frees it; it is also freed with the cache.  Synchronises `stream`.  Errors:
+ * REDO_ERR_ARG (no cache), REDO_ERR_UNSUPPORTED (d < 128 or d % 64 != 0),
+ * REDO_ERR_ALLOC, REDO_ERR_HIP.
+ */
+redo_status redo_cache_split_bf16(redo_table table, int32_t keep, void* stream);
 
 /*
  * Check of process 1 in FP64 (not part of the method's hot path): the level
@@ -138,7 +158,8 @@ redo_status redo_cache_levels(redo_table table, int32_t q_lo, int32_t q_hi, void
  * redo_build_table and redo_cache_levels use before their single rounding to
  * FP32 (scaling-and-squaring Taylor exponential of each digit's generator
  * exp(-i b^j eps dt S_k), powers by repeated products, then the product over
- * the digits).  out: c128 [d][d], device, caller-owned.  Allocates scratch;
+ * the digits, made exactly symmetric when S_k is real).  out: c128 [d][d],
+ * device, caller-owned.  Allocates scratch;
  * synchronises `stream`.  REDO_ERR_ARG for k or q out of range.
  */
 redo_status redo_level_f64(redo_table table, int32_t k, int32_t q, double* out, void* stream);
@@ -558,9 +579,10 @@ redo_status redo_to_bf16(int64_t n, const float* in, uint16_t* out, void* stream
 
 /*
  * Launch timing (diagnostics, not part of the method).  While enabled, every
- * batched complex-GEMM launch of the large-d path (kind 0) and every step
- * launch of redo_kron_chain (kind 1) is bracketed by HIP events recorded on
- * the stream it runs on.  redo_profile_read_kind waits for those events and
+ * batched complex-GEMM launch of the large-d path (kind 0: the step products
+ * and those of the comparison point), every step launch of redo_kron_chain
+ * (kind 1) and every GEMM launch of a Newton-Schulz re-projection (kind 2) is
+ * bracketed by HIP events recorded on the stream it runs on.  redo_profile_read_kind waits for those events and
  * returns the summed duration (ms) and the number of launches of one kind
  * since that kind's last reset; redo_profile_read is kind 0.  Process-wide;
  * may be called from any thread.

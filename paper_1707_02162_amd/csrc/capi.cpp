@@ -143,6 +143,16 @@ long long ceil_sqrt(long long n) {
     return std::max(1LL, c);
 }
 
+// the pre-split BF16 copy of the level cache, if any
+redo_status free_cache_bf(redo_table_s* t) {
+    if (!t->cache_bf) return REDO_OK;
+    REDO_HIP(hipFree(t->cache_bf));
+    t->bytes -= sizeof(float2) * (size_t)t->entry_elems * t->desc.K * (size_t)(t->cache_hi - t->cache_lo + 1);
+    t->cache_bf = nullptr;
+    t->cache_bf_conj = false;
+    return REDO_OK;
+}
+
 }  // namespace
 }  // namespace redo
 
@@ -298,6 +308,13 @@ redo_status redo_build_table(const redo_table_desc* desc, const double* H0, cons
     REDO_HIP(alloc((void**)&t->S64, sizeof(double2) * nn * K));
     REDO_HIP(hipMemcpyAsync(t->S64, S, sizeof(double2) * nn * K, hipMemcpyDeviceToDevice, hs));
     t->s_norm = s_norm;
+    t->s_real.assign(K, 1);
+    for (int k = 0; k < K; ++k)
+        for (size_t e = 0; e < nn; ++e)
+            if (hS[2 * (nn * k + e) + 1] != 0.0) {
+                t->s_real[k] = 0;
+                break;
+            }
     REDO_HIP(alloc((void**)&t->flags, sizeof(DeviceFlags)));
     REDO_HIP(hipMemsetAsync(t->flags, 0, sizeof(DeviceFlags), hs));
     if (desc->drift_is_diag) {
@@ -477,11 +494,42 @@ redo_status redo_build_table(const redo_table_desc* desc, const double* H0, cons
 redo_status redo_table_destroy(redo_table t) {
     if (!t) return REDO_OK;
     (void)hipDeviceSynchronize();
-    void* bufs[] = {t->T32, t->h64,   t->V32,   t->g64,       t->S32,      t->S64,      t->Sy32,
-                    t->H32, t->flags, t->cache, t->spat_cols, t->spat_vals, t->kron_s};
+    void* bufs[] = {t->T32,   t->h64,    t->V32,       t->g64,       t->S32,    t->S64,   t->Sy32,
+                    t->H32,   t->flags,  t->cache,     t->cache_bf,  t->spat_cols, t->spat_vals, t->kron_s};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     delete t;
+    return REDO_OK;
+}
+
+redo_status redo_cache_split_bf16(redo_table t, int32_t keep, void* stream) {
+    clear_last_error();
+    if (!t) return fail(REDO_ERR_ARG, "table is NULL");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    REDO_HIP(hipStreamSynchronize(hs));
+    {
+        const redo_status fs = free_cache_bf(t);
+        if (fs != REDO_OK) return fs;
+    }
+    if (!keep) return REDO_OK;
+    if (!t->cache) return fail(REDO_ERR_ARG, "no level cache to split (call redo_cache_levels first)");
+    if (t->desc.d < 128 || t->desc.d % 64 != 0)
+        return fail(REDO_ERR_UNSUPPORTED, "pre-split levels serve the d >= 128 (d % 64 == 0) products only");
+    const long long count = (long long)t->desc.K * (t->cache_hi - t->cache_lo + 1);
+    const size_t bytes = sizeof(float2) * (size_t)t->entry_elems * (size_t)count;
+    void* p = nullptr;
+    REDO_HIP(hipMalloc(&p, bytes));
+    const hipError_t e = split_panels(t->desc.d, count, t->cache, static_cast<uint16_t*>(p), hs);
+    const hipError_t e2 = e == hipSuccess ? hipStreamSynchronize(hs) : e;
+    if (e2 != hipSuccess) {
+        (void)hipFree(p);
+        return hip_fail(e2, "split_panels");
+    }
+    t->cache_bf = static_cast<uint16_t*>(p);
+    bool conj = true;
+    for (int k = 0; k < t->desc.K; ++k) conj = conj && t->s_real[k];
+    t->cache_bf_conj = conj;
+    t->bytes += bytes;
     return REDO_OK;
 }
 
@@ -490,6 +538,10 @@ redo_status redo_cache_levels(redo_table t, int32_t q_lo, int32_t q_hi, void* st
     if (!t) return fail(REDO_ERR_ARG, "table is NULL");
     hipStream_t hs = static_cast<hipStream_t>(stream);
     REDO_HIP(hipStreamSynchronize(hs));
+    {
+        const redo_status fs = free_cache_bf(t);
+        if (fs != REDO_OK) return fs;
+    }
     if (t->cache) {
         REDO_HIP(hipFree(t->cache));
         t->bytes -= sizeof(float2) * (size_t)t->entry_elems * t->desc.K * (size_t)(t->cache_hi - t->cache_lo + 1);
@@ -555,10 +607,13 @@ redo_status redo_cache_levels(redo_table t, int32_t q_lo, int32_t q_hi, void* st
             if (R) {
                 REDO_HIP(zgemm_batched(d, cnt, T + nn * (size_t)c_lo, nn, R, 0, tmp.as<double2>(), nn,
                                        make_double2(1.0, 0.0), 0.0, hs));
-                REDO_HIP(round_table_entries(d, cnt, tmp.as<double2>(), dst, nn, hs));
             } else {
-                REDO_HIP(round_table_entries(d, cnt, T + nn * (size_t)c_lo, dst, nn, hs));
+                REDO_HIP(hipMemcpyAsync(tmp.p, T + nn * (size_t)c_lo, sizeof(double2) * nn * cnt,
+                                        hipMemcpyDeviceToDevice, hs));
             }
+            // a real generator gives symmetric levels: make the FP64 products exactly so
+            if (t->s_real[k]) REDO_HIP(symmetrize_z(d, cnt, tmp.as<double2>(), nn, hs));
+            REDO_HIP(round_table_entries(d, cnt, tmp.as<double2>(), dst, nn, hs));
         }
     }
     REDO_HIP(hipStreamSynchronize(hs));
@@ -631,6 +686,7 @@ redo_status redo_level_f64(redo_table t, int32_t k, int32_t q, double* out, void
             REDO_HIP(zgemm_batched(d, 1, Rn.as<double2>(), 0, Rh.as<double2>(), 0, R, 0, make_double2(1.0, 0.0), 0.0,
                                    hs));
     }
+    if (t->s_real[k]) REDO_HIP(symmetrize_z(d, 1, R, 0, hs));
     REDO_HIP(hipStreamSynchronize(hs));
     return REDO_OK;
 }

@@ -175,9 +175,10 @@ __device__ inline void copy_tile(const GemmDesc& g, int d, int i0, int j0, int B
     }
 }
 
-// MODE 0: 4M, MODE 1: 3M (Gauss).  ROLE only separates the instantiation that
-// the plain-exponential comparison point launches (1) from the method's (0), so
-// that profiles attribute their time apart; the code is the same.
+// MODE 0: 4M, MODE 1: 3M (Gauss).  ROLE only separates the instantiations that
+// the method's step products (0), the plain-exponential comparison point (1) and
+// the Newton-Schulz re-projections (2) launch, so that profiles attribute their
+// time apart; the code is the same.
 template <int BM, int BN, int MODE, int ROLE>
 // at least three waves per SIMD: the 3M form then keeps its 96 accumulators in VGPRs
 // (167 registers, no spills) instead of two waves with AGPRs, 240 -> 218 ms for 4096
@@ -347,7 +348,9 @@ struct BCfg {
     static constexpr int LDK = KT;                      // bf16 per LDS row (32-byte rows, see bf_off)
     static constexpr int AV = BM * KT / 2 / THREADS;
     static constexpr int BV = BN * KT / 2 / THREADS;
-    static constexpr int APLANE = BM * LDK, BPLANE = BN * LDK;
+    // A planes 64 bytes apart beyond their size: the pre-split stores of 16 lanes
+    // (two rows, four planes, two k-halves) then fall into distinct LDS banks
+    static constexpr int APLANE = BM * LDK + 32, BPLANE = BN * LDK;
 };
 
 // LDS offset (bf16 units) of element (row, k) of a plane: 32-byte rows whose two
@@ -356,9 +359,10 @@ struct BCfg {
 __device__ inline int bf_off(int row, int k) { return row * KT + ((((k >> 3) ^ (row >> 3)) & 1) << 3) + (k & 7); }
 
 // plane p of element e: 0 re hi, 1 re lo, 2 im hi, 3 im lo
-template <int BM, int BN>
+template <int BM, int BN, bool KSL>
 __device__ inline void store_stage_bf(const GemmDesc& g, int k0, const float4 (&ra)[GCfg<BM, BN>::AV],
-                                      const float4 (&rb)[GCfg<BM, BN>::BV], unsigned short* As, unsigned short* Bs) {
+                                      const float4 (&rb)[GCfg<BM, BN>::BV], const float2* ks, unsigned short* As,
+                                      unsigned short* Bs) {
     using C = BCfg<BM, BN>;
     const int t = threadIdx.x;
 #pragma unroll
@@ -406,7 +410,7 @@ __device__ inline void store_stage_bf(const GemmDesc& g, int k0, const float4 (&
             const int kr = e / (BN / 2), jq = e % (BN / 2);
             float2 a = f2(v.x, v.y), b = f2(v.z, v.w);
             if (g.kscale) {
-                const float2 sc = ldg2(g.kscale + k0 + kr);
+                const float2 sc = KSL ? ks[kr] : ldg2(g.kscale + k0 + kr);
                 a = cmul(sc, a);
                 b = cmul(sc, b);
             }
@@ -428,8 +432,8 @@ __device__ inline void store_stage_bf(const GemmDesc& g, int k0, const float4 (&
             const int row = e / (KT / 2), kq = e % (KT / 2);
             float2 a = f2(v.x, -v.y), b = f2(v.z, -v.w);
             if (g.kscale) {
-                a = cmul(ldg2(g.kscale + k0 + 2 * kq), a);
-                b = cmul(ldg2(g.kscale + k0 + 2 * kq + 1), b);
+                a = cmul(KSL ? ks[2 * kq] : ldg2(g.kscale + k0 + 2 * kq), a);
+                b = cmul(KSL ? ks[2 * kq + 1] : ldg2(g.kscale + k0 + 2 * kq + 1), b);
             }
             split_bf16(a.x, h[0], l[0]);
             split_bf16(a.y, h[1], l[1]);
@@ -453,16 +457,31 @@ __device__ inline void store_stage_bf(const GemmDesc& g, int k0, const float4 (&
 template <int BM, int BN>
 __device__ constexpr bool bf_fast_tiles() { return BM == 128 && BN == 64; }
 
-template <int BM, int BN>
+// Staging modes of the split-BF16 product, uniform per workgroup: 0 any op(A), op(B)
+// (generic loads and splits); 1 A and B as given (A split as loaded); 2 A from its
+// pre-split panels (no split), B as given.  Modes 1 and 2 need 128 x 64 tiles.
+//
+// Mode 2 reads the 128 x 16 tile of op(A) as the 16 KiB of contiguous panel memory
+// that hold it: lane l of wave w takes 16 bytes at 4096 w + 1024 m + 16 l (m = 0..3),
+// that is row 32 w + 8 m + l / 8, plane (l / 2) % 4, k-half l % 2.
+template <int BM, int BN, int MODE>
 __device__ inline void load_stage_bf(const GemmDesc& g, int d, int i0, int j0, int k0, float4 (&ra)[GCfg<BM, BN>::AV],
                                      float4 (&rb)[GCfg<BM, BN>::BV]) {
-    if constexpr (bf_fast_tiles<BM, BN>()) {
-        if (g.opA == 0 && g.opB == 0) {
+    if constexpr (MODE != 0) {
+        static_assert(bf_fast_tiles<BM, BN>(), "staging modes 1 and 2 need 128 x 64 tiles");
+        {
             const int t = threadIdx.x;
-            const int row = (t & 15) + 16 * (t >> 5), kh = (t >> 4) & 1;
-            const float2* sa = g.A + (long long)(i0 + row) * d + k0 + 8 * kh;
+            if constexpr (MODE == 2) {
+                const float2* sp = reinterpret_cast<const float2*>(g.Abf + ((long long)(k0 / KT) * d + i0) * 64) +
+                                   512 * (t >> 6) + 2 * (t & 63);
 #pragma unroll
-            for (int m = 0; m < 4; ++m) ra[m] = ldg4(sa + 2 * m);
+                for (int m = 0; m < 4; ++m) ra[m] = ldg4(sp + 128 * m);
+            } else {
+                const int row = (t & 15) + 16 * (t >> 5), kh = (t >> 4) & 1;
+                const float2* sa = g.A + (long long)(i0 + row) * d + k0 + 8 * kh;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) ra[m] = ldg4(sa + 2 * m);
+            }
             const int j = (t & 15) + 16 * ((t >> 5) & 3), kg = ((t >> 4) & 1) + 2 * (t >> 7);
             const float2* sb = g.B + (long long)(k0 + 4 * kg) * d + j0 + j;
             const float2 v0 = ldg2(sb), v1 = ldg2(sb + d), v2 = ldg2(sb + 2 * (long long)d),
@@ -477,13 +496,29 @@ __device__ inline void load_stage_bf(const GemmDesc& g, int d, int i0, int j0, i
 
 __device__ inline unsigned pack_bf(unsigned short lo16, unsigned short hi16) { return lo16 | ((unsigned)hi16 << 16); }
 
-template <int BM, int BN>
-__device__ inline void store_stage_bf_fast(const GemmDesc& g, int k0, const float4 (&ra)[GCfg<BM, BN>::AV],
-                                           const float4 (&rb)[GCfg<BM, BN>::BV], unsigned short* As,
-                                           unsigned short* Bs) {
+template <int BM, int BN, int MODE>
+__device__ inline void store_stage_bf_fast(const GemmDesc& g, const float4 (&ra)[GCfg<BM, BN>::AV],
+                                           const float4 (&rb)[GCfg<BM, BN>::BV], const float2* ks,
+                                           unsigned short* As, unsigned short* Bs) {
     using C = BCfg<BM, BN>;
     const int t = threadIdx.x;
-    {
+    if constexpr (MODE == 2) {
+        // A from panels: each 16 bytes are 8 k of one plane of one row, stored as loaded;
+        // conjugation flips the sign bits of the imaginary planes (the split of -x is
+        // minus the split of x)
+        const int lane = t & 63, pl = (lane >> 1) & 3, kh = lane & 1;
+        const unsigned flip = (g.conjA && pl >= 2) ? 0x80008000u : 0u;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int row = 32 * (t >> 6) + 8 * m + (lane >> 3);
+            uint4 v = __builtin_bit_cast(uint4, ra[m]);
+            v.x ^= flip;
+            v.y ^= flip;
+            v.z ^= flip;
+            v.w ^= flip;
+            *reinterpret_cast<uint4*>(As + pl * C::APLANE + bf_off(row, 8 * kh)) = v;
+        }
+    } else {
         // A: 8 complex at k = 8 kh .. 8 kh + 7 of one row -> one uint4 per plane
         const int row = (t & 15) + 16 * (t >> 5), kh = (t >> 4) & 1;
         unsigned w[4][4];   // [plane][k pair]
@@ -503,7 +538,7 @@ __device__ inline void store_stage_bf_fast(const GemmDesc& g, int k0, const floa
         float2 v[4] = {f2(rb[0].x, rb[0].y), f2(rb[0].z, rb[0].w), f2(rb[1].x, rb[1].y), f2(rb[1].z, rb[1].w)};
         if (g.kscale) {
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) v[kk] = cmul(ldg2(g.kscale + k0 + 4 * kg + kk), v[kk]);
+            for (int kk = 0; kk < 4; ++kk) v[kk] = cmul(ks[4 * kg + kk], v[kk]);
         }
         unsigned w[4][2];   // [plane][k pair]
 #pragma unroll
@@ -514,6 +549,33 @@ __device__ inline void store_stage_bf_fast(const GemmDesc& g, int k0, const floa
         const int o = bf_off(j, 4 * kg);
 #pragma unroll
         for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<uint2*>(Bs + pl * C::BPLANE + o) = make_uint2(w[pl][0], w[pl][1]);
+    }
+}
+
+// Pre-split panels (layout in split_panels): one thread per (matrix, 16-column
+// block, row) turns 16 FP32 complex entries into the 128 bytes of four planes,
+// with the rounding of split_bf16
+__global__ __launch_bounds__(256) void split_panels_kernel(int d, long long count, const float2* __restrict__ src,
+                                                           uint16_t* __restrict__ dst) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long per = (long long)d * (d / KT);
+    if (e >= count * per) return;
+    const long long mtx = e / per, r = e % per;
+    const int kb = (int)(r / d), i = (int)(r % d);
+    const float2* s = src + mtx * d * d + (long long)i * d + kb * KT;
+    uint16_t* o = dst + mtx * 4 * d * d + ((long long)kb * d + i) * 64;
+    unsigned w[4][8];   // [plane][k pair]
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const float4 v = ldg4(s + 2 * q);
+        split_bf16x2(v.x, v.z, w[0][q], w[1][q]);
+        split_bf16x2(v.y, v.w, w[2][q], w[3][q]);
+    }
+    uint4* o4 = reinterpret_cast<uint4*>(o);
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+        o4[2 * pl] = make_uint4(w[pl][0], w[pl][1], w[pl][2], w[pl][3]);
+        o4[2 * pl + 1] = make_uint4(w[pl][4], w[pl][5], w[pl][6], w[pl][7]);
     }
 }
 
@@ -528,25 +590,18 @@ __device__ inline bf16x8 neg8(bf16x8 x) {
 
 #define MF16(a, b, c) __builtin_amdgcn_mfma_f32_32x32x16_bf16((a), (b), (c), 0, 0, 0)
 
-template <int BM, int BN>
-// at least three waves per SIMD (a 12-byte spill; 211 -> 192 ms for 4096 products at d = 1024):
-// the splits keep the vector ALU busy, and a third wave hides more of it behind the MFMAs
-__global__ __launch_bounds__(256, 3) void cgemm_bf16x3_kernel(int d, int batch, const GemmDesc* __restrict__ descs) {
+// One 128 x 64 (or 64 x 64) output tile; MODE is the staging mode of load_stage_bf
+template <int BM, int BN, int MODE>
+__device__ __forceinline__ void bf16x3_tile(const GemmDesc& g, int d, int i0, int j0,
+                                            unsigned short (*As)[4 * BCfg<BM, BN>::APLANE],
+                                            unsigned short (*Bs)[4 * BCfg<BM, BN>::BPLANE], float2 (*Ks)[KT]) {
     using C = BCfg<BM, BN>;
-    __shared__ __attribute__((aligned(16))) unsigned short As[2][4 * C::APLANE];
-    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][4 * C::BPLANE];
-    const int tiles_n = d / BN;
-    const int ntile = (d / BM) * tiles_n;
-    int bid = blockIdx.x;
-    const int nb = gridDim.x;
-    if (nb % NXCD == 0) bid = (bid % NXCD) * (nb / NXCD) + bid / NXCD;
-    const int be = bid / ntile, tile = bid % ntile;
-    const GemmDesc g = descs[be];
-    if (!g.active) return;
-    const int i0 = (tile / tiles_n) * BM, j0 = (tile % tiles_n) * BN;
-    if (g.A == nullptr || g.B == nullptr) {
-        copy_tile(g, d, i0, j0, BM, BN);
-        return;
+    const int nk = d / KT;
+    // k-scaling through LDS, prefetched two stages ahead as in cgemm_kernel (128 x 64 tiles)
+    constexpr bool KSL = BM == 128;
+    if constexpr (KSL) {
+        ks_fetch(g, 0, Ks);
+        if (nk > 1) ks_fetch(g, 1, Ks);
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wi0 = (wave >> 1) * C::WM, wj0 = (wave & 1) * C::WN;
@@ -561,19 +616,22 @@ __global__ __launch_bounds__(256, 3) void cgemm_bf16x3_kernel(int d, int batch, 
                 accI[ib][jb][r] = 0.f;
             }
     float4 ra[C::AV], rb[C::BV];
-    bool fast = false;
-    if constexpr (bf_fast_tiles<BM, BN>()) fast = g.opA == 0 && g.opB == 0;   // uniform per workgroup
-    load_stage_bf<BM, BN>(g, d, i0, j0, 0, ra, rb);
-    if (fast)
-        store_stage_bf_fast<BM, BN>(g, 0, ra, rb, As[0], Bs[0]);
+    load_stage_bf<BM, BN, MODE>(g, d, i0, j0, 0, ra, rb);
+    if (KSL && g.kscale != nullptr) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // Ks[0], Ks[1] landed
+        __syncthreads();
+    }
+    if constexpr (MODE != 0)
+        store_stage_bf_fast<BM, BN, MODE>(g, ra, rb, Ks[0], As[0], Bs[0]);
     else
-        store_stage_bf<BM, BN>(g, 0, ra, rb, As[0], Bs[0]);
+        store_stage_bf<BM, BN, KSL>(g, 0, ra, rb, Ks[0], As[0], Bs[0]);
     __syncthreads();
-    const int nk = d / KT;
     const int koff = 8 * (lane >> 5);
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
-        if (kt + 1 < nk) load_stage_bf<BM, BN>(g, d, i0, j0, (kt + 1) * KT, ra, rb);
+        if (kt + 1 < nk) load_stage_bf<BM, BN, MODE>(g, d, i0, j0, (kt + 1) * KT, ra, rb);
+        // slot (kt + 2) % 3 was last read by the store of stage kt - 1, before the previous barrier
+        if (KSL && kt + 2 < nk) ks_fetch(g, kt + 2, Ks);
         bf16x8 a[C::FM][4], b[C::FN][4], na[C::FM][2];
 #pragma unroll
         for (int ib = 0; ib < C::FM; ++ib)
@@ -642,11 +700,12 @@ __global__ __launch_bounds__(256, 3) void cgemm_bf16x3_kernel(int d, int batch, 
 #pragma unroll
             for (int jb = 0; jb < C::FN; ++jb) accI[ib][jb] = MF16(a[ib][3], b[jb][0], accI[ib][jb]);
         if (kt + 1 < nk) {
-            if (fast)
-                store_stage_bf_fast<BM, BN>(g, (kt + 1) * KT, ra, rb, As[buf ^ 1], Bs[buf ^ 1]);
+            if constexpr (MODE != 0)
+                store_stage_bf_fast<BM, BN, MODE>(g, ra, rb, Ks[(kt + 1) % 3], As[buf ^ 1], Bs[buf ^ 1]);
             else
-                store_stage_bf<BM, BN>(g, (kt + 1) * KT, ra, rb, As[buf ^ 1], Bs[buf ^ 1]);
+                store_stage_bf<BM, BN, KSL>(g, (kt + 1) * KT, ra, rb, Ks[(kt + 1) % 3], As[buf ^ 1], Bs[buf ^ 1]);
         }
+        if (KSL && g.kscale != nullptr) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this stage's ks_fetch landed
         __syncthreads();
     }
 #pragma unroll
@@ -667,13 +726,54 @@ __global__ __launch_bounds__(256, 3) void cgemm_bf16x3_kernel(int d, int batch, 
                 stg2(g.C + (long long)i * d + j, v);
             }
 }
+
+template <int BM, int BN, int ROLE>
+// ROLE separates instantiations for profiles only (as in cgemm_kernel); at least three waves per SIMD (a 12-byte spill; 211 -> 192 ms for 4096 products at d = 1024):
+// the splits keep the vector ALU busy, and a third wave hides more of it behind the MFMAs
+__global__ __launch_bounds__(256, 3) void cgemm_bf16x3_kernel(int d, int batch, const GemmDesc* __restrict__ descs) {
+    using C = BCfg<BM, BN>;
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][4 * C::APLANE];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][4 * C::BPLANE];
+    __shared__ float2 Ks[3][KT];   // k-scaling of stages kt, kt + 1, kt + 2
+    const int tiles_n = d / BN;
+    const int ntile = (d / BM) * tiles_n;
+    int bid = blockIdx.x;
+    const int nb = gridDim.x;
+    if (nb % NXCD == 0) bid = (bid % NXCD) * (nb / NXCD) + bid / NXCD;
+    const int be = bid / ntile, tile = bid % ntile;
+    const GemmDesc g = descs[be];
+    if (!g.active) return;
+    const int i0 = (tile / tiles_n) * BM, j0 = (tile % tiles_n) * BN;
+    if (g.A == nullptr || g.B == nullptr) {
+        copy_tile(g, d, i0, j0, BM, BN);
+        return;
+    }
+    // the staging mode is uniform per workgroup: one inlined copy of the tile per mode
+    if constexpr (bf_fast_tiles<BM, BN>()) {
+        if (g.opB == 0 && g.Abf) {
+            bf16x3_tile<BM, BN, 2>(g, d, i0, j0, As, Bs, Ks);
+            return;
+        }
+        if (g.opB == 0 && g.opA == 0) {
+            bf16x3_tile<BM, BN, 1>(g, d, i0, j0, As, Bs, Ks);
+            return;
+        }
+    }
+    bf16x3_tile<BM, BN, 0>(g, d, i0, j0, As, Bs, Ks);
+}
+
 #undef MF16
 
 template <int BM, int BN>
-hipError_t launch_bf(int d, int batch, const GemmDesc* descs, hipStream_t st) {
+hipError_t launch_bf(int d, int batch, const GemmDesc* descs, hipStream_t st, int role) {
     const long long blocks = (long long)(d / BM) * (d / BN) * batch;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((cgemm_bf16x3_kernel<BM, BN>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
+    if (role == GEMM_ROLE_REPROJECT)
+        hipLaunchKernelGGL((cgemm_bf16x3_kernel<BM, BN, 2>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
+    else if (role == GEMM_ROLE_EXPM)
+        hipLaunchKernelGGL((cgemm_bf16x3_kernel<BM, BN, 1>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
+    else
+        hipLaunchKernelGGL((cgemm_bf16x3_kernel<BM, BN, 0>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
     return hipGetLastError();
 }
 
@@ -681,7 +781,9 @@ template <int BM, int BN, int MODE>
 hipError_t launch(int d, int batch, const GemmDesc* descs, hipStream_t st, int role) {
     const long long blocks = (long long)(d / BM) * (d / BN) * batch;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (role)
+    if (role == GEMM_ROLE_REPROJECT)
+        hipLaunchKernelGGL((cgemm_kernel<BM, BN, MODE, 2>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
+    else if (role == GEMM_ROLE_EXPM)
         hipLaunchKernelGGL((cgemm_kernel<BM, BN, MODE, 1>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
     else
         hipLaunchKernelGGL((cgemm_kernel<BM, BN, MODE, 0>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
@@ -690,6 +792,16 @@ hipError_t launch(int d, int batch, const GemmDesc* descs, hipStream_t st, int r
 
 }  // namespace
 
+hipError_t split_panels(int d, long long count, const float2* src, uint16_t* dst, hipStream_t st) {
+    if (d % KT != 0 || count < 0) return hipErrorInvalidValue;
+    const long long threads = count * d * (d / KT);
+    if (threads == 0) return hipSuccess;
+    const long long blocks = (threads + 255) / 256;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(split_panels_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d, count, src, dst);
+    return hipGetLastError();
+}
+
 // precision: 0 = 4M FP32, 1 = 3M FP32, 2 = split BF16 (hi*hi + hi*lo + lo*hi)
 hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision, hipStream_t st, int role) {
     if (d % 64 != 0 || batch < 1) return hipErrorInvalidValue;
@@ -697,11 +809,11 @@ hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision,
     const bool big = d % 128 == 0 && (long long)(d / 128) * (d / 64) * batch >= 512;
     void* tok = nullptr;
     const bool prof = profiling_on();
-    if (prof) profile_begin(st, &tok);
+    if (prof) profile_begin(st, &tok, role == GEMM_ROLE_REPROJECT ? 2 : 0);
     // 128x64 tiles: three workgroups per CU for 4M (64 accumulator registers per lane); 3M (96)
     // is also faster there than on 128x128 tiles (240 vs 280 ms for 4096 products at d = 1024)
     if (precision == 2)
-        e = big ? launch_bf<128, 64>(d, batch, descs, st) : launch_bf<64, 64>(d, batch, descs, st);
+        e = big ? launch_bf<128, 64>(d, batch, descs, st, role) : launch_bf<64, 64>(d, batch, descs, st, role);
     else if (precision == 1)
         e = big ? launch<128, 64, 1>(d, batch, descs, st, role) : launch<64, 64, 1>(d, batch, descs, st, role);
     else

@@ -34,6 +34,8 @@ struct PlanArgs {
     int compose;            // 1: the state starts as the identity (no B operand)
     int slots;              // launched slots: dense + K (all levels cached) or dense + K * P
     int all_cached;
+    const uint16_t* cache_bf;   // pre-split BF16 panels of the cache, or null
+    int bf_conj;            // negative levels may use the conjugated panel of |q|
     int strang;             // U_n = V(dt/2) C_n V(dt/2): half drift in pre, half in post (diagonal drift)
     float2* pre;            // [B][d] scale vectors of this step
     float2* post;
@@ -74,10 +76,12 @@ __global__ __launch_bounds__(256) void plan_step_kernel(PlanArgs a) {
     int loc = a.loc[b];
     // factors of every slot (null = identity)
     const float2* fa[64];
+    const uint16_t* fb[64];   // the factor's pre-split panel, if any
     int fo[64];
     int last = -1, first_table = -1;
     for (int s = 0; s < S; ++s) {
         fa[s] = nullptr;
+        fb[s] = nullptr;
         fo[s] = 0;
         if (!active) continue;
         if (a.dense && s == 0) {
@@ -90,8 +94,11 @@ __global__ __launch_bounds__(256) void plan_step_kernel(PlanArgs a) {
             const int aq = q < 0 ? -q : q;
             fo[s] = q < 0 ? 1 : 0;
             if (a.cache && aq >= a.cache_lo && aq <= a.cache_hi) {
-                if (j == 0 && aq != 0)
-                    fa[s] = a.cache + ((long long)k * a.cache_levels + (aq - a.cache_lo)) * a.ent;
+                if (j == 0 && aq != 0) {
+                    const long long ce = (long long)k * a.cache_levels + (aq - a.cache_lo);
+                    fa[s] = a.cache + ce * a.ent;
+                    if (a.cache_bf && (q > 0 || a.bf_conj)) fb[s] = a.cache_bf + ce * 4 * a.ent;
+                }
             } else {
                 const int c = digit_of(q, j, a.base);
                 if (c) fa[s] = a.T + ((long long)(k * a.P + j) * (a.base - 1) + (c - 1)) * a.ent;
@@ -112,6 +119,8 @@ __global__ __launch_bounds__(256) void plan_step_kernel(PlanArgs a) {
         if (use) {
             g.A = fa[s];
             g.opA = fo[s];
+            g.Abf = fb[s];
+            g.conjA = fo[s];
             g.B = (a.compose && first_op) ? nullptr : a.X[loc] + (long long)b * a.xstride;
             g.C = a.X[loc ^ 1] + (long long)b * a.xstride;
             if (a.dense) {
@@ -1262,6 +1271,8 @@ hipError_t plan_step(const PlanLaunch& p, hipStream_t st) {
     a.compose = p.compose;
     a.slots = p.slots;
     a.all_cached = p.all_cached;
+    a.cache_bf = p.cache_bf;
+    a.bf_conj = p.bf_conj;
     a.pre = p.pre;
     a.post = p.post;
     a.pstar = p.pstar;

@@ -214,6 +214,8 @@ PlanLaunch plan_base(const redo_table_s* t) {
     p.cache_hi = t->cache_hi;
     p.slots = launch_slots(t);
     p.all_cached = all_cached(t) ? 1 : 0;
+    p.cache_bf = t->cache_bf;
+    p.bf_conj = t->cache_bf_conj ? 1 : 0;
     p.strang = t->desc.splitting;
     return p;
 }
@@ -335,10 +337,10 @@ redo_status large_chain(redo_table_s* t, int precision, const float* u, const in
             for (int b0 = 0; b0 < B; b0 += REPROJECT_CHUNK) {
                 const int ch = std::min(REPROJECT_CHUNK, B - b0);
                 REDO_HIP(reproject_descs(w.descs, ch, b0, X[0], X[1], mat, w.Z, mat, w.loc, n_steps, n, 0, st));
-                REDO_HIP(cgemm_batched(d, ch, w.descs, prec, st));
+                REDO_HIP(cgemm_batched(d, ch, w.descs, prec, st, GEMM_ROLE_REPROJECT));
                 REDO_HIP(unitarity_check(d, ch, b0, w.Z, mat, n_steps, n, t->flags, st));
                 REDO_HIP(reproject_descs(w.descs, ch, b0, X[0], X[1], mat, w.Z, mat, w.loc, n_steps, n, 1, st));
-                REDO_HIP(cgemm_batched(d, ch, w.descs, prec, st));
+                REDO_HIP(cgemm_batched(d, ch, w.descs, prec, st, GEMM_ROLE_REPROJECT));
             }
         }
         if (obs_out)

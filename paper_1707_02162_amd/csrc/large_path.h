@@ -50,6 +50,8 @@ struct PlanLaunch {
     long long xstride;
     int* loc;
     int compose, slots, all_cached;
+    const uint16_t* cache_bf;   // pre-split BF16 panels of the cache (split-BF16 products), or null
+    int bf_conj;             // negative levels take the conjugated panel of |q|
     int strang;              // 1: half the drift before the controls, half after
     float2* pre;
     float2* post;

@@ -1,5 +1,5 @@
-// Launch timing of the batched GEMM kernels (kind 0) and of the structure-aware
-// step kernel (kind 1): when enabled, every such launch is bracketed by HIP
+// Launch timing of the batched GEMM kernels (kind 0), of the structure-aware
+// step kernel (kind 1) and of the re-projection GEMMs (kind 2): when enabled, every such launch is bracketed by HIP
 // events recorded on the launch's own stream, so a benchmark can divide the
 // algorithmic work of a launch by its measured duration.  Diagnostics only: no
 // effect on results.

@@ -127,6 +127,12 @@ struct redo_table_s {
     // composed level cache (process 3): R(q) for q in [cache_lo, cache_hi]
     float2* cache = nullptr;
     int cache_lo = 0, cache_hi = -1;
+    // the same levels as pre-split BF16 panels (hi/lo of re and im) for the split-BF16
+    // products, or null; cache_bf_conj: every channel's generator is real, so each cached
+    // level is an exactly symmetric matrix and R(-q) = R(q)^H = conj(R(q))
+    uint16_t* cache_bf = nullptr;
+    bool cache_bf_conj = false;
+    std::vector<char> s_real;   // per channel: the generator has no imaginary part
     // sparsity pattern of the generators (union over channels), when every row has at
     // most SPAT_WMAX nonzeros: column lists [d][spat_w] (padded with the row index) and
     // the FP64 values of every channel at those positions [K][d][spat_w] (0 where absent)
@@ -166,7 +172,13 @@ hipError_t round_table_entries(int n, int batch, const double2* src, float2* dst
                                hipStream_t st);
 hipError_t drift_diag_phases(int d, int n_drift, const double* h, double dt, float2* V, hipStream_t st);
 hipError_t round_z_to_c(long long count, const double2* src, float2* dst, hipStream_t st);
-hipError_t split_bf16(long long count, const float2* src, uint16_t* hi, uint16_t* lo, hipStream_t st);
+// A[b] <- (A[b] + A[b]^T) / 2 in place (n x n c128): the exact symmetry of a level
+// whose generator is real, restored after the FP64 products
+hipError_t symmetrize_z(int n, int batch, double2* A, long long sA, hipStream_t st);
+// pre-split BF16 panels of count d x d FP32 complex matrices (cgemm.hip): entry (i, k) of
+// plane p (0 re hi, 1 re lo, 2 im hi, 3 im lo; hi = RNE(x), lo = RNE(x - hi)) at bf16
+// offset ((k / 16) d + i) 64 + 16 p + k % 16 of its matrix (8 d^2 bytes per matrix)
+hipError_t split_panels(int d, long long count, const float2* src, uint16_t* dst, hipStream_t st);
 
 hipError_t quantise_all(const redo_table_s* t, const float* u, int B, int N, int* codes, double* phi,
                         hipStream_t st);
@@ -230,17 +242,22 @@ struct GemmDesc {
     int active;          // 0: skip this entry entirely
     float beta_identity; // C += beta * I after scaling (Newton-Schulz), usually 0
     float alpha;         // C = alpha * (...)
-    int pad;
+    int conjA;           // with Abf: op(A) = conj(panel matrix), which equals its adjoint (symmetric)
     const float2* addend;  // C += addend (d x d) after alpha, or null
+    const uint16_t* Abf;   // op(A) as pre-split BF16 panels (split_panels layout), or null;
+                           // read by the split-BF16 product in place of A, which stays valid
 };
 static_assert(sizeof(GemmDesc) % 8 == 0, "desc alignment");
 
-// role 1: the plain-exponential comparison point (a separate kernel instantiation for profiles)
+// role: 0 a REDO step product, 1 the plain-exponential comparison point, 2 a Newton-Schulz
+// re-projection product; each role is a separate kernel instantiation (same code), so that
+// profiles attribute time apart, and re-projection launches are timed as profile kind 2
+constexpr int GEMM_ROLE_STEP = 0, GEMM_ROLE_EXPM = 1, GEMM_ROLE_REPROJECT = 2;
 hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision, hipStream_t st, int role = 0);
 
 // launch timing (profile.cpp)
 bool profiling_on();
-constexpr int PROFILE_KINDS = 2;   // 0: batched GEMM, 1: structure-aware step
+constexpr int PROFILE_KINDS = 3;   // 0: batched GEMM, 1: structure-aware step, 2: re-projection GEMM
 void profile_begin(hipStream_t st, void** token, int kind = 0);
 void profile_end(hipStream_t st, void* token);
 

@@ -106,24 +106,18 @@ __global__ void drift_diag_kernel(long long count, const double* __restrict__ h,
     V[e] = make_float2((float)v.x, (float)v.y);
 }
 
-// round-to-nearest-even float -> bf16 bits
-__device__ inline uint16_t bf16_rne(float x) {
-    unsigned u = __float_as_uint(x);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float(((unsigned)h) << 16); }
-
-// hi = RNE(x), lo = RNE(x - hi), per real component
-__global__ void split_bf16_kernel(long long count, const float* __restrict__ src, uint16_t* __restrict__ hi,
-                                  uint16_t* __restrict__ lo) {
+// A <- (A + A^T) / 2: the thread of element (i, j), i < j, writes the same value to both places
+__global__ void symmetrize_kernel(int n, double2* __restrict__ A, long long sA) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= count) return;
-    const float x = src[e];
-    const uint16_t h = bf16_rne(x);
-    hi[e] = h;
-    lo[e] = bf16_rne(x - bf16_to_f(h));
+    const long long nn = (long long)n * n;
+    if (e >= nn) return;
+    const long long i = e / n, j = e % n;
+    if (i >= j) return;
+    double2* a = A + sA * blockIdx.y;
+    const double2 x = a[i * n + j], y = a[j * n + i];
+    const double2 v = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y + y.y));
+    a[i * n + j] = v;
+    a[j * n + i] = v;
 }
 
 inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -162,10 +156,10 @@ hipError_t drift_diag_phases(int d, int n_drift, const double* h, double dt, flo
     return hipGetLastError();
 }
 
-hipError_t split_bf16(long long count, const float2* src, uint16_t* hi, uint16_t* lo, hipStream_t st) {
-    const long long reals = 2 * count;
-    hipLaunchKernelGGL(split_bf16_kernel, dim3(blocks_for(reals, 256)), dim3(256), 0, st, reals,
-                       reinterpret_cast<const float*>(src), hi, lo);
+hipError_t symmetrize_z(int n, int batch, double2* A, long long sA, hipStream_t st) {
+    if (n < 2 || batch < 1) return hipSuccess;
+    if (batch > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(symmetrize_kernel, dim3(blocks_for((long long)n * n, 256), batch), dim3(256), 0, st, n, A, sA);
     return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ _SIG = {
     "redo_table_query": (_I, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
     "redo_cache_levels": (_I, [_P, _I, _I, _P]),
     "redo_level_f64": (_I, [_P, _I, _I, _P, _P]),
+    "redo_cache_split_bf16": (_I, [_P, _I, _P]),
     "redo_workspace_bytes": (ctypes.c_size_t, [_P, _I, _I, _I]),
     "redo_grape_workspace_bytes": (ctypes.c_size_t, [_P, _I, _I, _I]),
     "redo_quantise": (_I, [_P, _P, _I, _I, _P, _P, _P]),
@@ -203,6 +204,12 @@ class RedoTable:
 
     def clear_cache(self) -> None:
         _check(lib().redo_cache_levels(self._h, 0, -1, _stream()))
+
+    def cache_split_bf16(self, keep: bool = True) -> None:
+        """Keep the cached levels a second time as pre-split BF16 panels, which the
+        split-BF16 products (precision=2, d >= 128) then read without splitting;
+        keep=False frees them."""
+        _check(lib().redo_cache_split_bf16(self._h, 1 if keep else 0, _stream()))
 
     @property
     def device_bytes(self) -> int:

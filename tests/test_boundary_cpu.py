@@ -84,8 +84,8 @@ def test_calls_without_table_rejected():
     assert lib.redo_kron_chain(None, 1, d, None, 1, 1, 0, 0, None, d, None, None, 0, None, None, 0, None) == 1
     n = ctypes.c_int32(-1)
     assert lib.redo_table_spins(None, ctypes.byref(n)) == 1 and n.value == -1
-    # launch timing: two kinds; reading with nothing recorded touches no device
-    assert lib.redo_profile_read_kind(2, None, None, 0) == 1
+    # launch timing: three kinds; reading with nothing recorded touches no device
+    assert lib.redo_profile_read_kind(3, None, None, 0) == 1
     assert lib.redo_profile_read_kind(-1, None, None, 0) == 1
     ms, cnt = ctypes.c_double(-1.0), ctypes.c_int64(-1)
     assert lib.redo_profile_read_kind(1, ctypes.byref(ms), ctypes.byref(cnt), 1) == 0
