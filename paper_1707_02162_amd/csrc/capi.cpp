@@ -136,6 +136,20 @@ redo_status check_walsh_obs(const redo_table_s* t, const redo_walsh_obs_s* obs, 
     return REDO_OK;
 }
 
+// Powers of one digit operator, Tj[c] = E^c for c = 2 .. b - 1, from Tj[1] = E: by
+// doubling, E^(h + i) = E^i E^h for h = 1, 2, 4, ... and i = 1 .. min(h, b - 1 - h),
+// one batched product per h (log2(b) sequential launches instead of b - 2, and a
+// product depth of log2(c) for E^c).  Every table build and check uses this order.
+redo_status digit_powers(int d, int b, double2* Tj, hipStream_t hs) {
+    const size_t nn = (size_t)d * d;
+    for (int h = 1; h < b - 1; h *= 2) {
+        const int cnt = std::min(h, b - 1 - h);
+        REDO_HIP(zgemm_batched(d, cnt, Tj + nn, (long long)nn, Tj + nn * h, 0, Tj + nn * (h + 1), (long long)nn,
+                               make_double2(1.0, 0.0), 0.0, hs));
+    }
+    return REDO_OK;
+}
+
 long long ceil_sqrt(long long n) {
     long long c = (long long)std::ceil(std::sqrt((double)n));
     while (c * c < n) ++c;
@@ -414,31 +428,24 @@ redo_status redo_build_table(const redo_table_desc* desc, const double* H0, cons
         }
     }
 
-    // ---- FP64 build: E_kj = exp(-i b^j eps dt S_k), T_kj[c] = E_kj^c
+    // ---- FP64 build: E_kj = exp(-i b^j eps dt S_k), T_kj[c] = E_kj^c (powers by doubling)
     {
-        const int KP = K * P;
-        DevBuf E, Pw, Pn, scratch;
-        REDO_HIP(dev_alloc(E, sizeof(double2) * nn * KP));
-        REDO_HIP(dev_alloc(Pw, sizeof(double2) * nn * KP));
-        REDO_HIP(dev_alloc(Pn, sizeof(double2) * nn * KP));
+        DevBuf E, Tj, scratch;
+        REDO_HIP(dev_alloc(E, sizeof(double2) * nn));
+        REDO_HIP(dev_alloc(Tj, sizeof(double2) * nn * b));
         REDO_HIP(dev_alloc(scratch, sizeof(double2) * nn));
         const double2* Sd = reinterpret_cast<const double2*>(S);
         for (int k = 0; k < K; ++k)
             for (int j = 0; j < P; ++j) {
                 const double theta = std::pow((double)b, j) * desc->eps * desc->dt;
-                st = expm_fp64(d, Sd + nn * k, theta, s_norm[k], E.as<double2>() + nn * (k * P + j),
-                               scratch.as<double2>(), hs);
+                double2* T = Tj.as<double2>();
+                st = expm_fp64(d, Sd + nn * k, theta, s_norm[k], T + nn, scratch.as<double2>(), hs);
                 if (st != REDO_OK) return st;
+                st = digit_powers(d, b, T, hs);
+                if (st != REDO_OK) return st;
+                REDO_HIP(round_table_entries(d, b - 1, T + nn, t->T32 + (long long)nn * (b - 1) * (k * P + j),
+                                             (long long)nn, hs));
             }
-        const long long entry_stride = (long long)nn * (b - 1);  // between (k, j) blocks of T32
-        REDO_HIP(round_table_entries(d, KP, E.as<double2>(), t->T32, entry_stride, hs));
-        REDO_HIP(hipMemcpyAsync(Pw.p, E.p, sizeof(double2) * nn * KP, hipMemcpyDeviceToDevice, hs));
-        for (int c = 2; c <= b - 1; ++c) {
-            REDO_HIP(zgemm_batched(d, KP, Pw.as<double2>(), nn, E.as<double2>(), nn, Pn.as<double2>(), nn,
-                                   make_double2(1.0, 0.0), 0.0, hs));
-            std::swap(Pw.p, Pn.p);
-            REDO_HIP(round_table_entries(d, KP, Pw.as<double2>(), t->T32 + (long long)nn * (c - 1), entry_stride, hs));
-        }
         // drift propagators V = exp(-i dt H0)
         if (desc->drift_is_diag) {
             REDO_HIP(hipMemcpyAsync(t->h64, H0, sizeof(double) * d * R, hipMemcpyDeviceToDevice, hs));
@@ -579,9 +586,8 @@ redo_status redo_cache_levels(redo_table t, int32_t q_lo, int32_t q_hi, void* st
             double2* Tj = T + nn * (size_t)j * b;
             REDO_HIP(fill_identity_z(d, 1, Tj, 0, hs));
             REDO_HIP(hipMemcpyAsync(Tj + nn, E.p, sizeof(double2) * nn, hipMemcpyDeviceToDevice, hs));
-            for (int c = 2; c < b; ++c)
-                REDO_HIP(zgemm_batched(d, 1, Tj + nn * (c - 1), 0, E.as<double2>(), 0, Tj + nn * c, 0,
-                                       make_double2(1.0, 0.0), 0.0, hs));
+            st = digit_powers(d, b, Tj, hs);
+            if (st != REDO_OK) return st;
         }
         // R(q) = T[0][c_0] (T[1][c_1] T[2][c_2] ...), grouped by the high part h = q / b
         for (long long h = q_lo / b; h <= q_hi / b; ++h) {
@@ -634,27 +640,22 @@ redo_status redo_level_f64(redo_table t, int32_t k, int32_t q, double* out, void
     const size_t nn = (size_t)d * d;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     double2* R = reinterpret_cast<double2*>(out);
-    DevBuf E, Tc, Tn, Rh, Rn, scratch;
-    REDO_HIP(dev_alloc(E, sizeof(double2) * nn));
-    REDO_HIP(dev_alloc(Tc, sizeof(double2) * nn));
-    REDO_HIP(dev_alloc(Tn, sizeof(double2) * nn));
+    DevBuf Tb, Rh, Rn, scratch;
+    REDO_HIP(dev_alloc(Tb, sizeof(double2) * nn * b));
     REDO_HIP(dev_alloc(Rh, sizeof(double2) * nn));
     REDO_HIP(dev_alloc(Rn, sizeof(double2) * nn));
     REDO_HIP(dev_alloc(scratch, sizeof(double2) * nn));
     // T[j][c] = E_j^c with E_j from the scaling-and-squaring Taylor exponential and the
-    // powers by repeated products, then R = T[0][c_0] (T[1][c_1] T[2][c_2] ...): the
-    // operations and their order of redo_build_table and redo_cache_levels
+    // powers by doubling, then R = T[0][c_0] (T[1][c_1] T[2][c_2] ...): the operations
+    // and their order of redo_build_table and redo_cache_levels
     auto digit_op = [&](int j, int c, double2* dst) -> redo_status {
         const double theta = std::pow((double)b, j) * t->desc.eps * t->desc.dt;
-        redo_status st = expm_fp64(d, t->S64 + nn * k, theta, t->s_norm[k], E.as<double2>(), scratch.as<double2>(), hs);
+        double2* T = Tb.as<double2>();
+        redo_status st = expm_fp64(d, t->S64 + nn * k, theta, t->s_norm[k], T + nn, scratch.as<double2>(), hs);
         if (st != REDO_OK) return st;
-        REDO_HIP(hipMemcpyAsync(Tc.p, E.p, sizeof(double2) * nn, hipMemcpyDeviceToDevice, hs));
-        for (int e = 2; e <= c; ++e) {
-            REDO_HIP(zgemm_batched(d, 1, Tc.as<double2>(), 0, E.as<double2>(), 0, Tn.as<double2>(), 0,
-                                   make_double2(1.0, 0.0), 0.0, hs));
-            std::swap(Tc.p, Tn.p);
-        }
-        REDO_HIP(hipMemcpyAsync(dst, Tc.p, sizeof(double2) * nn, hipMemcpyDeviceToDevice, hs));
+        st = digit_powers(d, b, T, hs);
+        if (st != REDO_OK) return st;
+        REDO_HIP(hipMemcpyAsync(dst, T + nn * c, sizeof(double2) * nn, hipMemcpyDeviceToDevice, hs));
         return REDO_OK;
     };
     bool have_high = false;

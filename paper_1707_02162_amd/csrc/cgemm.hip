@@ -176,9 +176,10 @@ __device__ inline void copy_tile(const GemmDesc& g, int d, int i0, int j0, int B
 }
 
 // MODE 0: 4M, MODE 1: 3M (Gauss).  ROLE only separates the instantiations that
-// the method's step products (0), the plain-exponential comparison point (1) and
-// the Newton-Schulz re-projections (2) launch, so that profiles attribute their
-// time apart; the code is the same.
+// the method's chain step products (0), the plain-exponential comparison point (1),
+// the Newton-Schulz re-projections (2) and the composition of single step
+// propagators (3) launch, so that profiles attribute their time apart; the code is
+// the same.
 template <int BM, int BN, int MODE, int ROLE>
 // at least three waves per SIMD: the 3M form then keeps its 96 accumulators in VGPRs
 // (167 registers, no spills) instead of two waves with AGPRs, 240 -> 218 ms for 4096
@@ -345,18 +346,25 @@ struct BCfg {
     static constexpr int THREADS = 256;
     static constexpr int WM = BM / 2, WN = BN / 2;
     static constexpr int FM = WM / 32, FN = WN / 32;
-    static constexpr int LDK = KT;                      // bf16 per LDS row (32-byte rows, see bf_off)
     static constexpr int AV = BM * KT / 2 / THREADS;
     static constexpr int BV = BN * KT / 2 / THREADS;
-    // A planes 64 bytes apart beyond their size: the pre-split stores of 16 lanes
-    // (two rows, four planes, two k-halves) then fall into distinct LDS banks
-    static constexpr int APLANE = BM * LDK + 32, BPLANE = BN * LDK;
+    // bf16 per plane: 32-byte rows (KT values); the A planes 32 bytes apart beyond their size
+    static constexpr int APLANE = BM * KT + 16, BPLANE = BN * KT;
+    static constexpr int ASZ = 4 * APLANE, BSZ = 4 * BPLANE;   // bf16 per stage buffer
 };
 
-// LDS offset (bf16 units) of element (row, k) of a plane: 32-byte rows whose two
-// 16-byte halves swap on every other group of 8 rows, so that the 16-byte fragment
-// reads of 32 rows (two halves each) and the staging stores fall into distinct banks
-__device__ inline int bf_off(int row, int k) { return row * KT + ((((k >> 3) ^ (row >> 3)) & 1) << 3) + (k & 7); }
+// LDS offset (bf16 units) of element (row, k) of plane p: planes PLANE apart, 32-byte rows whose
+// two 16-byte halves swap when bit 2 and bit 3 of the row differ.  With the A planes 32 bytes
+// beyond a multiple of 128 bytes apart, every access pattern of the kernel is free of bank
+// conflicts: the 16-byte fragment reads of 16 consecutive rows (64 banks per pass), the
+// 16-byte stores of 8 lanes (one row, four planes, two halves; or 8 rows of one plane) and the
+// 8-byte stores of 16 lanes (8 rows, both quarters of one half) (32 banks per pass on stores).
+// Each pattern was checked with the LDS bank-conflict counter; the swap on bit 3 alone left
+// every store two-way conflicted.
+template <int PLANE>
+__device__ inline int pl_off(int row, int p, int k) {
+    return p * PLANE + row * KT + ((((k >> 3) ^ (row >> 2) ^ (row >> 3)) & 1) << 3) + (k & 7);
+}
 
 // plane p of element e: 0 re hi, 1 re lo, 2 im hi, 3 im lo
 template <int BM, int BN, bool KSL>
@@ -377,11 +385,10 @@ __device__ inline void store_stage_bf(const GemmDesc& g, int k0, const float4 (&
             split_bf16(v.y, h[1], l[1]);
             split_bf16(v.z, h[2], l[2]);
             split_bf16(v.w, h[3], l[3]);
-            const int o = bf_off(row, 2 * kq);
-            *reinterpret_cast<unsigned*>(As + 0 * C::APLANE + o) = h[0] | ((unsigned)h[2] << 16);
-            *reinterpret_cast<unsigned*>(As + 1 * C::APLANE + o) = l[0] | ((unsigned)l[2] << 16);
-            *reinterpret_cast<unsigned*>(As + 2 * C::APLANE + o) = h[1] | ((unsigned)h[3] << 16);
-            *reinterpret_cast<unsigned*>(As + 3 * C::APLANE + o) = l[1] | ((unsigned)l[3] << 16);
+            *reinterpret_cast<unsigned*>(As + pl_off<C::APLANE>(row, 0, 2 * kq)) = h[0] | ((unsigned)h[2] << 16);
+            *reinterpret_cast<unsigned*>(As + pl_off<C::APLANE>(row, 1, 2 * kq)) = l[0] | ((unsigned)l[2] << 16);
+            *reinterpret_cast<unsigned*>(As + pl_off<C::APLANE>(row, 2, 2 * kq)) = h[1] | ((unsigned)h[3] << 16);
+            *reinterpret_cast<unsigned*>(As + pl_off<C::APLANE>(row, 3, 2 * kq)) = l[1] | ((unsigned)l[3] << 16);
         } else {
             // A^H: elements (2iq, kr) and (2iq + 1, kr), conjugated
             const int kr = e / (BM / 2), iq = e % (BM / 2);
@@ -389,15 +396,15 @@ __device__ inline void store_stage_bf(const GemmDesc& g, int k0, const float4 (&
             split_bf16(-v.y, h[1], l[1]);
             split_bf16(v.z, h[2], l[2]);
             split_bf16(-v.w, h[3], l[3]);
-            const int o0 = bf_off(2 * iq, kr), o1 = bf_off(2 * iq + 1, kr);
-            As[0 * C::APLANE + o0] = h[0];
-            As[1 * C::APLANE + o0] = l[0];
-            As[2 * C::APLANE + o0] = h[1];
-            As[3 * C::APLANE + o0] = l[1];
-            As[0 * C::APLANE + o1] = h[2];
-            As[1 * C::APLANE + o1] = l[2];
-            As[2 * C::APLANE + o1] = h[3];
-            As[3 * C::APLANE + o1] = l[3];
+            const int r0 = 2 * iq, r1 = 2 * iq + 1;
+            As[pl_off<C::APLANE>(r0, 0, kr)] = h[0];
+            As[pl_off<C::APLANE>(r0, 1, kr)] = l[0];
+            As[pl_off<C::APLANE>(r0, 2, kr)] = h[1];
+            As[pl_off<C::APLANE>(r0, 3, kr)] = l[1];
+            As[pl_off<C::APLANE>(r1, 0, kr)] = h[2];
+            As[pl_off<C::APLANE>(r1, 1, kr)] = l[2];
+            As[pl_off<C::APLANE>(r1, 2, kr)] = h[3];
+            As[pl_off<C::APLANE>(r1, 3, kr)] = l[3];
         }
     }
 #pragma unroll
@@ -418,15 +425,15 @@ __device__ inline void store_stage_bf(const GemmDesc& g, int k0, const float4 (&
             split_bf16(a.y, h[1], l[1]);
             split_bf16(b.x, h[2], l[2]);
             split_bf16(b.y, h[3], l[3]);
-            const int o0 = bf_off(2 * jq, kr), o1 = bf_off(2 * jq + 1, kr);
-            Bs[0 * C::BPLANE + o0] = h[0];
-            Bs[1 * C::BPLANE + o0] = l[0];
-            Bs[2 * C::BPLANE + o0] = h[1];
-            Bs[3 * C::BPLANE + o0] = l[1];
-            Bs[0 * C::BPLANE + o1] = h[2];
-            Bs[1 * C::BPLANE + o1] = l[2];
-            Bs[2 * C::BPLANE + o1] = h[3];
-            Bs[3 * C::BPLANE + o1] = l[3];
+            const int c0 = 2 * jq, c1 = 2 * jq + 1;
+            Bs[pl_off<C::BPLANE>(c0, 0, kr)] = h[0];
+            Bs[pl_off<C::BPLANE>(c0, 1, kr)] = l[0];
+            Bs[pl_off<C::BPLANE>(c0, 2, kr)] = h[1];
+            Bs[pl_off<C::BPLANE>(c0, 3, kr)] = l[1];
+            Bs[pl_off<C::BPLANE>(c1, 0, kr)] = h[2];
+            Bs[pl_off<C::BPLANE>(c1, 1, kr)] = l[2];
+            Bs[pl_off<C::BPLANE>(c1, 2, kr)] = h[3];
+            Bs[pl_off<C::BPLANE>(c1, 3, kr)] = l[3];
         } else {
             // B^H: elements (k = 2kq, j = row) and (2kq + 1, row), conjugated: pack along k
             const int row = e / (KT / 2), kq = e % (KT / 2);
@@ -439,11 +446,10 @@ __device__ inline void store_stage_bf(const GemmDesc& g, int k0, const float4 (&
             split_bf16(a.y, h[1], l[1]);
             split_bf16(b.x, h[2], l[2]);
             split_bf16(b.y, h[3], l[3]);
-            const int o = bf_off(row, 2 * kq);
-            *reinterpret_cast<unsigned*>(Bs + 0 * C::BPLANE + o) = h[0] | ((unsigned)h[2] << 16);
-            *reinterpret_cast<unsigned*>(Bs + 1 * C::BPLANE + o) = l[0] | ((unsigned)l[2] << 16);
-            *reinterpret_cast<unsigned*>(Bs + 2 * C::BPLANE + o) = h[1] | ((unsigned)h[3] << 16);
-            *reinterpret_cast<unsigned*>(Bs + 3 * C::BPLANE + o) = l[1] | ((unsigned)l[3] << 16);
+            *reinterpret_cast<unsigned*>(Bs + pl_off<C::BPLANE>(row, 0, 2 * kq)) = h[0] | ((unsigned)h[2] << 16);
+            *reinterpret_cast<unsigned*>(Bs + pl_off<C::BPLANE>(row, 1, 2 * kq)) = l[0] | ((unsigned)l[2] << 16);
+            *reinterpret_cast<unsigned*>(Bs + pl_off<C::BPLANE>(row, 2, 2 * kq)) = h[1] | ((unsigned)h[3] << 16);
+            *reinterpret_cast<unsigned*>(Bs + pl_off<C::BPLANE>(row, 3, 2 * kq)) = l[1] | ((unsigned)l[3] << 16);
         }
     }
 }
@@ -451,15 +457,16 @@ __device__ inline void store_stage_bf(const GemmDesc& g, int k0, const float4 (&
 // Split-BF16 staging of op(A) = A and op(B) = B on 128 x 64 tiles: every thread
 // takes a run of consecutive k (8 of one row of A as four 16-byte loads; 4 of one
 // column of B as four 8-byte loads) and writes each bf16 plane as one 16-byte (A)
-// or 8-byte (B) word.  A thread's row (column) is (t & 15) + 16 (t >> 5) and its
-// k-run follows (t >> 4) & 1 (and t >> 7 for B), so the words that 16 (A) or 32 (B)
-// lanes write fall into distinct LDS banks (bf_off).
+// or 8-byte (B) word.  A thread's row is (t & 15) + 16 (t >> 5) with k-half
+// (t >> 4) & 1; its B column is (t >> 1) & 63 with k-quarter (t & 1) + 2 (t >> 7),
+// so that the words of one store pass fall into distinct LDS banks (pl_off).
 template <int BM, int BN>
 __device__ constexpr bool bf_fast_tiles() { return BM == 128 && BN == 64; }
 
 // Staging modes of the split-BF16 product, uniform per workgroup: 0 any op(A), op(B)
 // (generic loads and splits); 1 A and B as given (A split as loaded); 2 A from its
-// pre-split panels (no split), B as given.  Modes 1 and 2 need 128 x 64 tiles.
+// pre-split panels (no split), B as given; 3 as 2 with op(A) the conjugate of the
+// panel matrix.  Modes 1 to 3 need 128 x 64 tiles.
 //
 // Mode 2 reads the 128 x 16 tile of op(A) as the 16 KiB of contiguous panel memory
 // that hold it: lane l of wave w takes 16 bytes at 4096 w + 1024 m + 16 l (m = 0..3),
@@ -471,7 +478,7 @@ __device__ inline void load_stage_bf(const GemmDesc& g, int d, int i0, int j0, i
         static_assert(bf_fast_tiles<BM, BN>(), "staging modes 1 and 2 need 128 x 64 tiles");
         {
             const int t = threadIdx.x;
-            if constexpr (MODE == 2) {
+            if constexpr (MODE >= 2) {
                 const float2* sp = reinterpret_cast<const float2*>(g.Abf + ((long long)(k0 / KT) * d + i0) * 64) +
                                    512 * (t >> 6) + 2 * (t & 63);
 #pragma unroll
@@ -482,7 +489,7 @@ __device__ inline void load_stage_bf(const GemmDesc& g, int d, int i0, int j0, i
 #pragma unroll
                 for (int m = 0; m < 4; ++m) ra[m] = ldg4(sa + 2 * m);
             }
-            const int j = (t & 15) + 16 * ((t >> 5) & 3), kg = ((t >> 4) & 1) + 2 * (t >> 7);
+            const int j = (t >> 1) & 63, kg = (t & 1) + 2 * (t >> 7);
             const float2* sb = g.B + (long long)(k0 + 4 * kg) * d + j0 + j;
             const float2 v0 = ldg2(sb), v1 = ldg2(sb + d), v2 = ldg2(sb + 2 * (long long)d),
                          v3 = ldg2(sb + 3 * (long long)d);
@@ -502,21 +509,14 @@ __device__ inline void store_stage_bf_fast(const GemmDesc& g, const float4 (&ra)
                                            unsigned short* As, unsigned short* Bs) {
     using C = BCfg<BM, BN>;
     const int t = threadIdx.x;
-    if constexpr (MODE == 2) {
-        // A from panels: each 16 bytes are 8 k of one plane of one row, stored as loaded;
-        // conjugation flips the sign bits of the imaginary planes (the split of -x is
-        // minus the split of x)
+    if constexpr (MODE >= 2) {
+        // A from panels: each 16 bytes are 8 k of one plane of one row, stored as loaded
+        // (the conjugation of MODE 3 is taken in the products)
         const int lane = t & 63, pl = (lane >> 1) & 3, kh = lane & 1;
-        const unsigned flip = (g.conjA && pl >= 2) ? 0x80008000u : 0u;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const int row = 32 * (t >> 6) + 8 * m + (lane >> 3);
-            uint4 v = __builtin_bit_cast(uint4, ra[m]);
-            v.x ^= flip;
-            v.y ^= flip;
-            v.z ^= flip;
-            v.w ^= flip;
-            *reinterpret_cast<uint4*>(As + pl * C::APLANE + bf_off(row, 8 * kh)) = v;
+            *reinterpret_cast<uint4*>(As + pl_off<C::APLANE>(row, pl, 8 * kh)) = __builtin_bit_cast(uint4, ra[m]);
         }
     } else {
         // A: 8 complex at k = 8 kh .. 8 kh + 7 of one row -> one uint4 per plane
@@ -527,14 +527,14 @@ __device__ inline void store_stage_bf_fast(const GemmDesc& g, const float4 (&ra)
             split_bf16x2(ra[m].x, ra[m].z, w[0][m], w[1][m]);
             split_bf16x2(ra[m].y, ra[m].w, w[2][m], w[3][m]);
         }
-        const int o = bf_off(row, 8 * kh);
 #pragma unroll
         for (int pl = 0; pl < 4; ++pl)
-            *reinterpret_cast<uint4*>(As + pl * C::APLANE + o) = make_uint4(w[pl][0], w[pl][1], w[pl][2], w[pl][3]);
+            *reinterpret_cast<uint4*>(As + pl_off<C::APLANE>(row, pl, 8 * kh)) = make_uint4(w[pl][0], w[pl][1], w[pl][2], w[pl][3]);
     }
     {
-        // B: 4 complex at k = 4 kg .. 4 kg + 3 of one column -> one uint2 per plane
-        const int j = (t & 15) + 16 * ((t >> 5) & 3), kg = ((t >> 4) & 1) + 2 * (t >> 7);
+        // B: 4 complex at k = 4 kg .. 4 kg + 3 of one column -> one uint2 per plane; the
+        // two quarters of a half-row are neighbouring lanes (16 lanes: 8 columns x 2)
+        const int j = (t >> 1) & 63, kg = (t & 1) + 2 * (t >> 7);
         float2 v[4] = {f2(rb[0].x, rb[0].y), f2(rb[0].z, rb[0].w), f2(rb[1].x, rb[1].y), f2(rb[1].z, rb[1].w)};
         if (g.kscale) {
 #pragma unroll
@@ -546,9 +546,8 @@ __device__ inline void store_stage_bf_fast(const GemmDesc& g, const float4 (&ra)
             split_bf16x2(v[2 * q].x, v[2 * q + 1].x, w[0][q], w[1][q]);
             split_bf16x2(v[2 * q].y, v[2 * q + 1].y, w[2][q], w[3][q]);
         }
-        const int o = bf_off(j, 4 * kg);
 #pragma unroll
-        for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<uint2*>(Bs + pl * C::BPLANE + o) = make_uint2(w[pl][0], w[pl][1]);
+        for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<uint2*>(Bs + pl_off<C::BPLANE>(j, pl, 4 * kg)) = make_uint2(w[pl][0], w[pl][1]);
     }
 }
 
@@ -593,8 +592,8 @@ __device__ inline bf16x8 neg8(bf16x8 x) {
 // One 128 x 64 (or 64 x 64) output tile; MODE is the staging mode of load_stage_bf
 template <int BM, int BN, int MODE>
 __device__ __forceinline__ void bf16x3_tile(const GemmDesc& g, int d, int i0, int j0,
-                                            unsigned short (*As)[4 * BCfg<BM, BN>::APLANE],
-                                            unsigned short (*Bs)[4 * BCfg<BM, BN>::BPLANE], float2 (*Ks)[KT]) {
+                                            unsigned short (*As)[BCfg<BM, BN>::ASZ],
+                                            unsigned short (*Bs)[BCfg<BM, BN>::BSZ], float2 (*Ks)[KT]) {
     using C = BCfg<BM, BN>;
     const int nk = d / KT;
     // k-scaling through LDS, prefetched two stages ahead as in cgemm_kernel (128 x 64 tiles)
@@ -637,18 +636,24 @@ __device__ __forceinline__ void bf16x3_tile(const GemmDesc& g, int d, int i0, in
         for (int ib = 0; ib < C::FM; ++ib)
 #pragma unroll
             for (int pl = 0; pl < 4; ++pl)
-                a[ib][pl] = *reinterpret_cast<const bf16x8*>(As[buf] + pl * C::APLANE +
-                                                             bf_off(wi0 + ib * 32 + (lane & 31), koff));
+                a[ib][pl] = *reinterpret_cast<const bf16x8*>(As[buf] + pl_off<C::APLANE>(wi0 + ib * 32 + (lane & 31), pl, koff));
 #pragma unroll
         for (int jb = 0; jb < C::FN; ++jb)
 #pragma unroll
             for (int pl = 0; pl < 4; ++pl)
-                b[jb][pl] = *reinterpret_cast<const bf16x8*>(Bs[buf] + pl * C::BPLANE +
-                                                             bf_off(wj0 + jb * 32 + (lane & 31), koff));
+                b[jb][pl] = *reinterpret_cast<const bf16x8*>(Bs[buf] + pl_off<C::BPLANE>(wj0 + jb * 32 + (lane & 31), pl, koff));
+        // pi: the imaginary planes that enter Ci, mi: their negatives that enter Cr; MODE 3
+        // takes conj(A) by exchanging the two (Ai -> -Ai), at no cost
+        bf16x8 pi[C::FM][2], mi[C::FM][2];
 #pragma unroll
         for (int ib = 0; ib < C::FM; ++ib) {
             na[ib][0] = neg8(a[ib][2]);
             na[ib][1] = neg8(a[ib][3]);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                pi[ib][h] = MODE == 3 ? na[ib][h] : a[ib][2 + h];
+                mi[ib][h] = MODE == 3 ? a[ib][2 + h] : na[ib][h];
+            }
         }
         // Cr += Ar Br - Ai Bi,  Ci += Ar Bi + Ai Br; each real product hi*hi + hi*lo + lo*hi
 #pragma unroll
@@ -678,27 +683,27 @@ __device__ __forceinline__ void bf16x3_tile(const GemmDesc& g, int d, int i0, in
 #pragma unroll
         for (int ib = 0; ib < C::FM; ++ib)
 #pragma unroll
-            for (int jb = 0; jb < C::FN; ++jb) accR[ib][jb] = MF16(na[ib][0], b[jb][2], accR[ib][jb]);
+            for (int jb = 0; jb < C::FN; ++jb) accR[ib][jb] = MF16(mi[ib][0], b[jb][2], accR[ib][jb]);
 #pragma unroll
         for (int ib = 0; ib < C::FM; ++ib)
 #pragma unroll
-            for (int jb = 0; jb < C::FN; ++jb) accI[ib][jb] = MF16(a[ib][2], b[jb][0], accI[ib][jb]);
+            for (int jb = 0; jb < C::FN; ++jb) accI[ib][jb] = MF16(pi[ib][0], b[jb][0], accI[ib][jb]);
 #pragma unroll
         for (int ib = 0; ib < C::FM; ++ib)
 #pragma unroll
-            for (int jb = 0; jb < C::FN; ++jb) accR[ib][jb] = MF16(na[ib][0], b[jb][3], accR[ib][jb]);
+            for (int jb = 0; jb < C::FN; ++jb) accR[ib][jb] = MF16(mi[ib][0], b[jb][3], accR[ib][jb]);
 #pragma unroll
         for (int ib = 0; ib < C::FM; ++ib)
 #pragma unroll
-            for (int jb = 0; jb < C::FN; ++jb) accI[ib][jb] = MF16(a[ib][2], b[jb][1], accI[ib][jb]);
+            for (int jb = 0; jb < C::FN; ++jb) accI[ib][jb] = MF16(pi[ib][0], b[jb][1], accI[ib][jb]);
 #pragma unroll
         for (int ib = 0; ib < C::FM; ++ib)
 #pragma unroll
-            for (int jb = 0; jb < C::FN; ++jb) accR[ib][jb] = MF16(na[ib][1], b[jb][2], accR[ib][jb]);
+            for (int jb = 0; jb < C::FN; ++jb) accR[ib][jb] = MF16(mi[ib][1], b[jb][2], accR[ib][jb]);
 #pragma unroll
         for (int ib = 0; ib < C::FM; ++ib)
 #pragma unroll
-            for (int jb = 0; jb < C::FN; ++jb) accI[ib][jb] = MF16(a[ib][3], b[jb][0], accI[ib][jb]);
+            for (int jb = 0; jb < C::FN; ++jb) accI[ib][jb] = MF16(pi[ib][1], b[jb][0], accI[ib][jb]);
         if (kt + 1 < nk) {
             if constexpr (MODE != 0)
                 store_stage_bf_fast<BM, BN, MODE>(g, ra, rb, Ks[(kt + 1) % 3], As[buf ^ 1], Bs[buf ^ 1]);
@@ -732,8 +737,8 @@ template <int BM, int BN, int ROLE>
 // the splits keep the vector ALU busy, and a third wave hides more of it behind the MFMAs
 __global__ __launch_bounds__(256, 3) void cgemm_bf16x3_kernel(int d, int batch, const GemmDesc* __restrict__ descs) {
     using C = BCfg<BM, BN>;
-    __shared__ __attribute__((aligned(16))) unsigned short As[2][4 * C::APLANE];
-    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][4 * C::BPLANE];
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][C::ASZ];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][C::BSZ];
     __shared__ float2 Ks[3][KT];   // k-scaling of stages kt, kt + 1, kt + 2
     const int tiles_n = d / BN;
     const int ntile = (d / BM) * tiles_n;
@@ -751,7 +756,10 @@ __global__ __launch_bounds__(256, 3) void cgemm_bf16x3_kernel(int d, int batch, 
     // the staging mode is uniform per workgroup: one inlined copy of the tile per mode
     if constexpr (bf_fast_tiles<BM, BN>()) {
         if (g.opB == 0 && g.Abf) {
-            bf16x3_tile<BM, BN, 2>(g, d, i0, j0, As, Bs, Ks);
+            if (g.conjA)
+                bf16x3_tile<BM, BN, 3>(g, d, i0, j0, As, Bs, Ks);
+            else
+                bf16x3_tile<BM, BN, 2>(g, d, i0, j0, As, Bs, Ks);
             return;
         }
         if (g.opB == 0 && g.opA == 0) {
@@ -770,6 +778,8 @@ hipError_t launch_bf(int d, int batch, const GemmDesc* descs, hipStream_t st, in
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     if (role == GEMM_ROLE_REPROJECT)
         hipLaunchKernelGGL((cgemm_bf16x3_kernel<BM, BN, 2>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
+    else if (role == GEMM_ROLE_COMPOSE)
+        hipLaunchKernelGGL((cgemm_bf16x3_kernel<BM, BN, 3>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
     else if (role == GEMM_ROLE_EXPM)
         hipLaunchKernelGGL((cgemm_bf16x3_kernel<BM, BN, 1>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
     else
@@ -783,6 +793,8 @@ hipError_t launch(int d, int batch, const GemmDesc* descs, hipStream_t st, int r
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     if (role == GEMM_ROLE_REPROJECT)
         hipLaunchKernelGGL((cgemm_kernel<BM, BN, MODE, 2>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
+    else if (role == GEMM_ROLE_COMPOSE)
+        hipLaunchKernelGGL((cgemm_kernel<BM, BN, MODE, 3>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
     else if (role == GEMM_ROLE_EXPM)
         hipLaunchKernelGGL((cgemm_kernel<BM, BN, MODE, 1>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
     else

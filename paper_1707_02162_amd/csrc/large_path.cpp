@@ -246,7 +246,8 @@ redo_status compose_pairs(redo_table_s* t, int precision, long long I, int N, co
         p.B = ch;
         REDO_HIP(fill_int(w.loc, ch, 0, st));
         REDO_HIP(plan_step(p, st));
-        for (int s = 0; s < S; ++s) REDO_HIP(cgemm_batched(t->desc.d, ch, w.descs + (size_t)s * ch, gemm_prec(precision), st));
+        for (int s = 0; s < S; ++s)
+            REDO_HIP(cgemm_batched(t->desc.d, ch, w.descs + (size_t)s * ch, gemm_prec(precision), st, GEMM_ROLE_COMPOSE));
         REDO_HIP(gather_back(t->desc.d, ch, p.X0, w.tmp, mat, w.loc, st));
     }
     return REDO_OK;

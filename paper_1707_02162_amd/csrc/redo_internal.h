@@ -249,10 +249,12 @@ struct GemmDesc {
 };
 static_assert(sizeof(GemmDesc) % 8 == 0, "desc alignment");
 
-// role: 0 a REDO step product, 1 the plain-exponential comparison point, 2 a Newton-Schulz
-// re-projection product; each role is a separate kernel instantiation (same code), so that
-// profiles attribute time apart, and re-projection launches are timed as profile kind 2
-constexpr int GEMM_ROLE_STEP = 0, GEMM_ROLE_EXPM = 1, GEMM_ROLE_REPROJECT = 2;
+// role: 0 a REDO chain step product, 1 the plain-exponential comparison point, 2 a
+// Newton-Schulz re-projection product, 3 the composition of single step propagators
+// (redo_compose_steps, the step factors of GRAPE); each role is a separate kernel
+// instantiation (same code), so that profiles attribute time apart, and re-projection
+// launches are timed as profile kind 2
+constexpr int GEMM_ROLE_STEP = 0, GEMM_ROLE_EXPM = 1, GEMM_ROLE_REPROJECT = 2, GEMM_ROLE_COMPOSE = 3;
 hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision, hipStream_t st, int role = 0);
 
 // launch timing (profile.cpp)

@@ -68,6 +68,11 @@ struct Cfg {
     static constexpr int NT = D / TB;          // threads along a row of sub-blocks
     static constexpr int TPI = NT * NT;        // threads per instance
     static constexpr int IPB = 256 / TPI;      // instances per workgroup
+    // float2 of padding after each instance's LDS buffers: their sizes (2 or 3 d^2 float2) are
+    // multiples of 256 bytes at d = 4, 8, so that without it the lanes of the instances sharing a
+    // wave would meet in the same banks at every access (measured: 70-75 % of the LDS cycles of the
+    // d = 4 kernels were bank conflicts)
+    static constexpr int PAD = 4;
 };
 
 // Barrier among the threads of one instance around its LDS buffers.  At d <= 16
@@ -472,7 +477,7 @@ __global__ __launch_bounds__(256, (PH == 0 && D <= 16) ? 4 : 1) void small_chain
     const int ti = lt / NT, tj = lt % NT;
     const int inst = blockIdx.x * IPB + slot;
     const bool valid = inst < ninst;
-    float2* Xs = lds + (long long)slot * 2 * D * D;
+    float2* Xs = lds + (long long)slot * (2 * D * D + Cfg<D>::PAD);
     float2* Fs = Xs + D * D;
     int b = 0, n0 = 0, len = 0;
     if (valid) {
@@ -508,7 +513,7 @@ __global__ __launch_bounds__(256, (PH == 0 && D <= 16) ? 4 : 1) void small_chain
 
     double obs_norm = 1.0;
     // the observable's row lists, once per workgroup, after the instances' buffers
-    float2* ovs = lds + (long long)IPB * 2 * D * D;
+    float2* ovs = lds + (long long)IPB * (2 * D * D + Cfg<D>::PAD);
     int* ocs = reinterpret_cast<int*>(ovs + (a.obs_out ? D * a.obs_width : 0));
     if (a.obs_out) {
         for (int e = tid; e < D * a.obs_width; e += 256) {
@@ -706,7 +711,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
     const int ti = lt / NT, tj = lt % NT;
     const int b = blockIdx.x * IPB + slot;
     const bool valid = b < a.B;
-    float2* Xs = lds + (long long)slot * 3 * D * D;
+    float2* Xs = lds + (long long)slot * (3 * D * D + Cfg<D>::PAD);
     float2* Fs = Xs + D * D;
     float2* Ls = Fs + D * D;
     const int len = valid ? (a.n_steps ? a.n_steps[b] : a.N_max) : 0;
@@ -931,7 +936,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
 template <int D>
 hipError_t launch_chain(const TView& tv, const SmallChainArgs& a, int ninst, hipStream_t st) {
     constexpr int IPB = Cfg<D>::IPB;
-    const size_t lds = (size_t)IPB * 2 * D * D * sizeof(float2) +
+    const size_t lds = (size_t)IPB * (2 * D * D + Cfg<D>::PAD) * sizeof(float2) +
                        (a.obs_out ? (size_t)D * a.obs_width * (sizeof(float2) + sizeof(int)) : 0);
     const void* k = tv.phased ? (const void*)small_chain_kernel<D, 1> : (const void*)small_chain_kernel<D, 0>;
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -947,7 +952,7 @@ hipError_t launch_chain(const TView& tv, const SmallChainArgs& a, int ninst, hip
 template <int D>
 hipError_t launch_grape(const TView& tv, const SmallGrapeArgs& a, hipStream_t st) {
     constexpr int IPB = Cfg<D>::IPB;
-    const size_t lds = (size_t)IPB * 3 * D * D * sizeof(float2);
+    const size_t lds = (size_t)IPB * (3 * D * D + Cfg<D>::PAD) * sizeof(float2);
     const void* k = tv.phased ? (const void*)small_grape_kernel<D, 1> : (const void*)small_grape_kernel<D, 0>;
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

@@ -8,15 +8,19 @@
 namespace redo {
 namespace {
 
-constexpr int ZT = 64;   // output tile edge
 constexpr int ZK = 16;   // k-slice
 
-// C[b] = alpha * A[b] B[b] + beta * I for n x n row-major c128 matrices.
-// 256 threads, each owns a 4x4 strided sub-block (rows ty + 16 r, cols tx + 16 c).
+// C[b] = alpha * A[b] B[b] + beta * I for n x n row-major c128 matrices, ZT x ZT
+// output tiles (64, or 32 for launches of few tiles).  256 threads, each owns an
+// R x R strided sub-block (rows ty + 16 r, cols tx + 16 c), R = ZT / 16; every
+// element is one FMA chain over k = 0 .. n - 1 in order, whatever the tile edge.
+template <int ZT>
 __global__ __launch_bounds__(256) void zgemm_kernel(int n, const double2* __restrict__ A, long long sA,
                                                      const double2* __restrict__ B, long long sB,
                                                      double2* __restrict__ C, long long sC, double2 alpha,
                                                      double beta) {
+    constexpr int RR = ZT / 16;
+    constexpr int LOADS = ZK * ZT / 256;
     __shared__ double2 As[ZK][ZT + 1];
     __shared__ double2 Bs[ZK][ZT + 1];
     const int bz = blockIdx.z;
@@ -25,14 +29,14 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int n, const double2* __rest
     C += sC * bz;
     const int i0 = blockIdx.y * ZT, j0 = blockIdx.x * ZT;
     const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-    double2 acc[4][4];
+    double2 acc[RR][RR];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < RR; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = make_double2(0.0, 0.0);
+        for (int c = 0; c < RR; ++c) acc[r][c] = make_double2(0.0, 0.0);
     for (int k0 = 0; k0 < n; k0 += ZK) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < LOADS; ++m) {
             const int e = tid + 256 * m;
             const int ai = e / ZK, ak = e % ZK;
             const int gi = i0 + ai, gk = k0 + ak;
@@ -44,15 +48,15 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int n, const double2* __rest
         __syncthreads();
 #pragma unroll 4
         for (int k = 0; k < ZK; ++k) {
-            double2 a[4], b[4];
+            double2 a[RR], b[RR];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = As[k][ty + 16 * r];
+            for (int r = 0; r < RR; ++r) a[r] = As[k][ty + 16 * r];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] = Bs[k][tx + 16 * c];
+            for (int c = 0; c < RR; ++c) b[c] = Bs[k][tx + 16 * c];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < RR; ++r)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
+                for (int c = 0; c < RR; ++c) {
                     acc[r][c].x = fma(a[r].x, b[c].x, acc[r][c].x);
                     acc[r][c].x = fma(-a[r].y, b[c].y, acc[r][c].x);
                     acc[r][c].y = fma(a[r].x, b[c].y, acc[r][c].y);
@@ -62,9 +66,9 @@ __global__ __launch_bounds__(256) void zgemm_kernel(int n, const double2* __rest
         __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < RR; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < RR; ++c) {
             const int i = i0 + ty + 16 * r, j = j0 + tx + 16 * c;
             if (i < n && j < n) {
                 double2 v = zmul(alpha, acc[r][c]);
@@ -126,8 +130,17 @@ inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) /
 
 hipError_t zgemm_batched(int n, int batch, const double2* A, long long sA, const double2* B, long long sB,
                          double2* C, long long sC, double2 alpha, double beta, hipStream_t st) {
-    dim3 grid((n + ZT - 1) / ZT, (n + ZT - 1) / ZT, batch);
-    hipLaunchKernelGGL(zgemm_kernel, grid, dim3(256), 0, st, n, A, sA, B, sB, C, sC, alpha, beta);
+    if (batch < 1) return hipSuccess;
+    if (batch > 65535) return hipErrorInvalidValue;
+    const long long t64 = (long long)((n + 63) / 64) * ((n + 63) / 64) * batch;
+    if (t64 >= 1024 || n <= 32) {
+        dim3 grid((n + 63) / 64, (n + 63) / 64, batch);
+        hipLaunchKernelGGL(zgemm_kernel<64>, grid, dim3(256), 0, st, n, A, sA, B, sB, C, sC, alpha, beta);
+    } else {
+        // few tiles (single products, small batches): 32 x 32 tiles, four times the workgroups
+        dim3 grid((n + 31) / 32, (n + 31) / 32, batch);
+        hipLaunchKernelGGL(zgemm_kernel<32>, grid, dim3(256), 0, st, n, A, sA, B, sB, C, sC, alpha, beta);
+    }
     return hipGetLastError();
 }
 

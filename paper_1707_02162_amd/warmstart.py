@@ -166,24 +166,25 @@ def grape(table: R.RedoTable, u0: torch.Tensor, Uf: torch.Tensor, u_max: float, 
     return torch.where(done, u_best, u), F, reached, hist
 
 
-def reachable_targets(table: R.RedoTable, p: W.Problem, config_id: int, B: int):
-    """Targets reached by smooth seeded pulses (so that a solution exists).
-    Returns (U_f, the pulses that produce them)."""
+def reachable_targets(table: R.RedoTable, p: W.Problem, config_id: int, B: int, amp: float = 1.0):
+    """Targets reached by smooth seeded pulses (so that a solution exists), the
+    pulses scaled by `amp`.  Returns (U_f, the pulses that produce them)."""
     gen = W.nmr_chain(4, B, p.N, p.dt, p.base, p.digits, config_id, species=[[0, 1], [2, 3]],
                       targets=False)
-    ug = torch.tensor(gen.u, device="cuda")
+    ug = torch.tensor(gen.u * np.float32(amp), device="cuda")
     U, _, _ = table.chain(ug)
     return U, ug
 
 
-def random_starts(p: W.Problem, config_id: int, B: int) -> torch.Tensor:
+def random_starts(p: W.Problem, config_id: int, B: int, amp: float = 1.0) -> torch.Tensor:
+    """Seeded smooth pulses from the targets' own distribution (scaled by `amp`)."""
     st = W.nmr_chain(4, B, p.N, p.dt, p.base, p.digits, config_id, species=[[0, 1], [2, 3]], targets=False)
-    return torch.tensor(st.u, device="cuda")
+    return torch.tensor(st.u * np.float32(amp), device="cuda")
 
 
 def experiment(n_train: int, n_test: int, N: int = 500, grape_iters: int = 2000, lr_grape: float = 1000.0,
                epochs: int = 40, batch: int = 256, lr_net: float = 1e-3, width: int = 512, goal: float = 1e-4,
-               labels: str = "source", loss: str = "both", fid_epochs: int = 40, log=print):
+               labels: str = "source", loss: str = "both", fid_epochs: int = 40, amp: float = 1.0, log=print):
     """C5-shaped run: d = 16, two species with collective X/Y, N steps of 2 us.
 
     labels "source": each training target is labelled with the smooth pulse
@@ -197,15 +198,19 @@ def experiment(n_train: int, n_test: int, N: int = 500, grape_iters: int = 2000,
       proposed pulse for its target, its gradient dF/du from the library's
       REDO-GRAPE adjoint back-propagated through the network (any pulse that
       reaches the target is a right answer); "both": least squares, then
-      fid_epochs of the fidelity loss."""
+      fid_epochs of the fidelity loss.
+
+    amp scales every pulse (sources and random starts alike): at small areas the
+    propagator is close to linear in the pulse (first-order Magnus term) and the
+    target -> pulse map becomes learnable."""
     p = W.c5_four_qubit(B=1, N=N)
     table = R.RedoTable.from_problem(p)
     table.cache_levels()
     u_max = float(p.u_scale)
     t0 = time.time()
     # training set: reachable targets and REDO-GRAPE-optimised pulses for them
-    Uf, ug = reachable_targets(table, p, 501, n_train)
-    u0 = ug if labels == "source" else random_starts(p, 502, n_train)
+    Uf, ug = reachable_targets(table, p, 501, n_train, amp)
+    u0 = ug if labels == "source" else random_starts(p, 502, n_train, amp)
     u_opt, F_opt, it_opt, _ = grape(table, u0, Uf, u_max, grape_iters, lr_grape, goal=goal, log=log, tag="dataset")
     keep = (1.0 - F_opt) <= goal
     log(f"[warmstart] dataset: {int(keep.sum())}/{n_train} optimised to {goal:g} in {time.time() - t0:.1f}s")
@@ -246,8 +251,8 @@ def experiment(n_train: int, n_test: int, N: int = 500, grape_iters: int = 2000,
                 log(f"[warmstart] fidelity epoch {ep}: mean infidelity of the proposals {fid_losses[-1]:.4f}")
         log(f"[warmstart] fidelity training: mean infidelity {fid_losses[0]:.4f} -> {fid_losses[-1]:.4f}")
     # held-out targets: network start (with fallback) vs random start
-    Ut, _ = reachable_targets(table, p, 601, n_test)
-    ur = random_starts(p, 602, n_test)
+    Ut, _ = reachable_targets(table, p, 601, n_test, amp)
+    ur = random_starts(p, 602, n_test, amp)
     un = (net.forward(target_features(Ut)) * u_max).reshape(ur.shape).contiguous()
     Fr0, _, _ = table.grape(ur, Ut)
     Fn0, _, _ = table.grape(un, Ut)
@@ -265,7 +270,7 @@ def experiment(n_train: int, n_test: int, N: int = 500, grape_iters: int = 2000,
     conv_fb = its_fb >= 0
     both = conv_r & conv_fb
     res = dict(
-        labels=labels, dataset_grape_iters_median=float(it_opt[keep].double().median()) if keep.any() else None,
+        labels=labels, amp=amp, dataset_grape_iters_median=float(it_opt[keep].double().median()) if keep.any() else None,
         n_train=n_train, n_train_converged=int(keep.sum()), n_test=n_test, N=N, epochs=epochs, goal=goal,
         loss_first=losses[0], loss_last=losses[-1], loss_kind=loss,
         fidelity_loss_first=fid_losses[0] if fid_losses else None,
@@ -299,9 +304,10 @@ def main():
     ap.add_argument("--labels", choices=["source", "grape"], default="source")
     ap.add_argument("--loss", choices=["mse", "fidelity", "both"], default="both")
     ap.add_argument("--fid-epochs", type=int, default=40)
+    ap.add_argument("--amp", type=float, default=1.0, help="scale of every pulse (lower-area regime below 1)")
     a = ap.parse_args()
     res = experiment(a.train, a.test, N=a.N, grape_iters=a.grape_iters, lr_grape=a.lr_grape, epochs=a.epochs,
-                     goal=a.goal, width=a.width, labels=a.labels, loss=a.loss, fid_epochs=a.fid_epochs,
+                     goal=a.goal, width=a.width, labels=a.labels, loss=a.loss, fid_epochs=a.fid_epochs, amp=a.amp,
                      log=lambda s: print(s, file=sys.stderr, flush=True))
     print(json.dumps(res))
 
