@@ -38,26 +38,32 @@ PEAK_FP32_VECTOR_TFLOPS = 78.6   # non-packed FP32 FMA rate: 256 CUs x 4 SIMDs x
 # products at d = 1024), from two rocprofv3 --pmc runs (FETCH_SIZE, then
 # WRITE_SIZE) of this script with --calibrate, each counter scaled by what it
 # reads for the plain 1 GiB device copy of that run.  The figure belongs to
-# the kernel source it was measured on and is reported only while that source
-# is unchanged.
+# the kernel sources it was measured on (the FP32 GEMM and the header it shares
+# with the split-BF16 one; SHA-256 of the two files in this order) and is
+# reported only while they are unchanged.
 GEMM_TRAFFIC = {
-    "source": "paper_1707_02162_amd/csrc/cgemm.hip",
-    "sha256": "2d5ed4d7a760374f68c9d51b8f62a2945ed1403e4f28254e941023b32ece8cf4",
-    # FETCH_SIZE 83,914,834 KiB per launch (mean of 3) x 1.99994 (a 1 GiB copy reads as 524,302.4 KiB)
-    "fetch_bytes": 171852846850,
-    # WRITE_SIZE 33,554,432 KiB per launch x 1.0000 (a 1 GiB copy writes 1,048,576 KiB)
-    "write_bytes": 34359738368,
+    "sources": ["paper_1707_02162_amd/csrc/cgemm.hip", "paper_1707_02162_amd/csrc/cgemm_common.h"],
+    "sha256": None,
+    "fetch_bytes": None,
+    "write_bytes": None,
 }
 
 
-def gemm_traffic(realisations, cache):
+def gemm_sources_sha256():
     import hashlib
+    h = hashlib.sha256()
+    for src in GEMM_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def gemm_traffic(realisations, cache):
     t = GEMM_TRAFFIC
     if t["sha256"] is None or realisations != 4096 or not cache:
         return None
-    with open(os.path.join(ROOT, t["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
-            return None
+    if gemm_sources_sha256() != t["sha256"]:
+        return None
     return t["fetch_bytes"] + t["write_bytes"]
 
 

@@ -256,6 +256,8 @@ static_assert(sizeof(GemmDesc) % 8 == 0, "desc alignment");
 // launches are timed as profile kind 2
 constexpr int GEMM_ROLE_STEP = 0, GEMM_ROLE_EXPM = 1, GEMM_ROLE_REPROJECT = 2, GEMM_ROLE_COMPOSE = 3;
 hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision, hipStream_t st, int role = 0);
+// the split-BF16 launch behind cgemm_batched (cgemm_bf16.hip): 128 x 64 tiles when big, else 64 x 64
+hipError_t cgemm_bf16_launch(int d, int batch, const GemmDesc* descs, hipStream_t st, int role, bool big);
 
 // launch timing (profile.cpp)
 bool profiling_on();
