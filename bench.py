@@ -43,9 +43,11 @@ PEAK_FP32_VECTOR_TFLOPS = 78.6   # non-packed FP32 FMA rate: 256 CUs x 4 SIMDs x
 # reported only while they are unchanged.
 GEMM_TRAFFIC = {
     "sources": ["paper_1707_02162_amd/csrc/cgemm.hip", "paper_1707_02162_amd/csrc/cgemm_common.h"],
-    "sha256": None,
-    "fetch_bytes": None,
-    "write_bytes": None,
+    "sha256": "e3bd8e1b8a9c2a502b91c68f3659f661dc4b78df947bcce7f88b5e3d8bc354ea",
+    # FETCH_SIZE 83,909,772 KiB per launch (mean of 64) x 1.99993 (a 1 GiB copy reads as 524,305 KiB)
+    "fetch_bytes": 171841531597,
+    # WRITE_SIZE 33,554,432 KiB per launch x 1.0000 (a 1 GiB copy writes 1,048,576 KiB)
+    "write_bytes": 34359738368,
 }
 
 
