@@ -502,11 +502,17 @@ def _step_derivatives(model, S, g, amp_n, dt, V, H0m, K, d, Vh=None):
             yield (k, 0), c * dU_dom - (s / om[k]) * dU_dphi
             yield (k, 1), s * dU_dom + (c / om[k]) * dU_dphi
         else:
-            # at the origin the Cartesian derivatives are the generators themselves
+            # at the origin the Cartesian derivatives are the generators themselves: the
+            # block exp(-i dt (u_x S + u_y S^y)) has them as its derivatives whatever the
+            # phase of the zero pair, so the channel's own phase (atan2 gives +-pi for a
+            # negative zero) is left out of the rotation around them
+            phi0 = phi.copy()
+            phi0[k] = 0.0
+            Z0 = phase_diag(phi0, g)
             Sy = y_generator(S[k], g[k])
             P0 = np.eye(d, dtype=np.complex128)
             for kk in range(K):
                 if kk != k:
                     P0 = X[kk] @ P0
             for a, Gen in ((0, S[k]), (1, Sy)):
-                yield (k, a), with_drift(Z @ (-1j * dt * Gen) @ P0 @ Z.conj().T, V, Vh)
+                yield (k, a), with_drift(Z0 @ (-1j * dt * Gen) @ P0 @ Z0.conj().T, V, Vh)

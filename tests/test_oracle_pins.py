@@ -325,6 +325,27 @@ def test_t12_gradient_vs_central_differences_phased(model):
     assert np.linalg.norm(grad - fd) <= 1e-7 * np.linalg.norm(fd)
 
 
+@pytest.mark.parametrize("origin", [(0.0, 0.0), (-0.0, 0.0), (-0.0, -0.0), (0.0, -0.0)])
+def test_t12_gradient_at_the_origin_vs_central_differences(origin):
+    """A phased channel at the origin: the Cartesian derivatives are those of
+    exp(-i dt (u_x S + u_y S^y)), which do not depend on the phase of the zero pair
+    (atan2 gives +-pi for a negative zero): every signed zero gives the central
+    differences taken across the origin."""
+    p = W.c1_two_spin(B=1, N=6)
+    amp0 = p.u[0].astype(float)
+    amp0[2, 0, :] = origin
+    fd = np.zeros(2)
+    h = 1e-6 * p.u_scale
+    for a in range(2):
+        a1 = amp0.copy(); a1[2, 0, a] = h
+        a2 = amp0.copy(); a2[2, 0, a] = -h
+        F1 = O.fidelity_and_gradient(p, 0, model="split", amps=a1)[0]
+        F2 = O.fidelity_and_gradient(p, 0, model="split", amps=a2)[0]
+        fd[a] = (F1 - F2) / (2 * h)
+    _, _, grad = O.fidelity_and_gradient(p, 0, model="split", amps=amp0)
+    assert np.linalg.norm(grad[2, 0] - fd) <= 1e-6 * np.linalg.norm(fd), (grad[2, 0], fd)
+
+
 def test_t12_gradient_vs_central_differences_signed():
     p = W.ising_freezing(n=3, B=1, N=8)
     p.U_target = W.haar_unitary(8, W.rng(3, 2, 0))[None]
