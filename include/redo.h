@@ -247,7 +247,8 @@ redo_status redo_table_spins(redo_table table, int32_t* n_spins);
  *                 cgrain), the same U_n as redo_chain_propagator up to
  *                 rounding; 0: the amplitudes as given (the exact split step)
  * Other arguments, layouts, the observable and the re-projection as
- * redo_chain_propagator (FP32).  Needs d = 128 .. 4096 and a diagonal drift;
+ * redo_chain_propagator (FP32; the re-projection's two dense products per
+ * realisation in the three-product form).  Needs d = 128 .. 4096 and a diagonal drift;
  * REDO_ERR_UNSUPPORTED otherwise.
  * Workspace: redo_workspace_bytes(table, REDO_OP_KRON_CHAIN, B, N_max).
  */

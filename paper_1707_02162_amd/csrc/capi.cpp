@@ -491,6 +491,22 @@ redo_status redo_build_table(const redo_table_desc* desc, const double* H0, cons
             }
         }
         if (desc->phased) REDO_HIP(hipMemcpyAsync(t->g64, g, sizeof(double) * d * K, hipMemcpyDeviceToDevice, hs));
+        // phase generators of spins (every entry a half-integer): the fused small-d kernels then form
+        // exp(i phi g) as a power of exp(i phi / 2), with no transcendental function per step
+        if (desc->phased) {
+            std::vector<signed char> g2((size_t)K * d);
+            bool half = true;
+            for (size_t e = 0; e < g2.size() && half; ++e) {
+                const double v = 2.0 * hg[e];
+                if (!(std::fabs(v) <= 64.0) || v != std::nearbyint(v)) half = false;
+                else g2[e] = (signed char)std::lround(v);
+            }
+            if (half) {
+                REDO_HIP(alloc((void**)&t->g2, g2.size()));
+                REDO_HIP(hipMemcpyAsync(t->g2, g2.data(), g2.size(), hipMemcpyHostToDevice, hs));
+                REDO_HIP(hipStreamSynchronize(hs));
+            }
+        }
         REDO_HIP(hipStreamSynchronize(hs));
     }
     guard.armed = false;
@@ -501,7 +517,7 @@ redo_status redo_build_table(const redo_table_desc* desc, const double* H0, cons
 redo_status redo_table_destroy(redo_table t) {
     if (!t) return REDO_OK;
     (void)hipDeviceSynchronize();
-    void* bufs[] = {t->T32,   t->h64,    t->V32,       t->g64,       t->S32,    t->S64,   t->Sy32,
+    void* bufs[] = {t->T32,   t->h64,    t->V32,       t->g64,       t->g2,     t->S32,    t->S64,   t->Sy32,
                     t->H32,   t->flags,  t->cache,     t->cache_bf,  t->spat_cols, t->spat_vals, t->kron_s};
     for (void* p : bufs)
         if (p) (void)hipFree(p);

@@ -502,10 +502,10 @@ redo_status kron_chain(redo_table_s* t, int quantised, const float* u, const int
             for (int b0 = 0; b0 < B; b0 += REPROJECT_CHUNK) {
                 const int ch = std::min(REPROJECT_CHUNK, B - b0);
                 REDO_HIP(reproject_descs(w.descs, ch, b0, X[0], X[1], mat, w.Z, mat, w.loc, n_steps, n, 0, st));
-                REDO_HIP(cgemm_batched(d, ch, w.descs, 0, st, GEMM_ROLE_REPROJECT));
+                REDO_HIP(cgemm_batched(d, ch, w.descs, 1, st, GEMM_ROLE_REPROJECT));
                 REDO_HIP(unitarity_check(d, ch, b0, w.Z, mat, n_steps, n, t->flags, st));
                 REDO_HIP(reproject_descs(w.descs, ch, b0, X[0], X[1], mat, w.Z, mat, w.loc, n_steps, n, 1, st));
-                REDO_HIP(cgemm_batched(d, ch, w.descs, 0, st, GEMM_ROLE_REPROJECT));
+                REDO_HIP(cgemm_batched(d, ch, w.descs, 1, st, GEMM_ROLE_REPROJECT));
             }
         }
         if (obs_out)

@@ -39,6 +39,35 @@ __device__ inline double2 expmi(double x) {
     return make_double2(c, -s);
 }
 
+// exp(+i phi / 2) for the phase phi = atan2(uy, ux) in (-pi, pi] of a Cartesian
+// control pair (signed zeros as atan2; a non-finite pair has phi = 0, as in
+// quantise_one), from the half-angle formulas on (ux, uy) / |u|: no
+// transcendental function.  The branch keeps both components well conditioned:
+// cos(phi/2) >= 1/sqrt(2) when cos(phi) >= 0, else |sin(phi/2)| >= 1/sqrt(2).
+__device__ inline double2 half_phase(double ux, double uy) {
+    const double om = sqrt(ux * ux + uy * uy);
+    if (!(om <= 1.7976931348623157e308)) return make_double2(1.0, 0.0);
+    if (om == 0.0) return signbit(ux) ? make_double2(0.0, copysign(1.0, uy)) : make_double2(1.0, copysign(0.0, uy));
+    const double c = ux / om, s = uy / om;
+    if (c >= 0.0) {
+        const double ch = sqrt(0.5 * (1.0 + c));
+        return make_double2(ch, s / (2.0 * ch));
+    }
+    const double sh = sqrt(0.5 * (1.0 - c));
+    return make_double2(fabs(s) / (2.0 * sh), copysign(sh, uy));
+}
+
+// z^m for an integer m (conj(z)^|m| for m < 0) by repeated products
+__device__ inline double2 zpow(double2 z, int m) {
+    if (m < 0) {
+        z.y = -z.y;
+        m = -m;
+    }
+    double2 r = make_double2(1.0, 0.0);
+    for (int i = 0; i < m; ++i) r = make_double2(r.x * z.x - r.y * z.y, r.x * z.y + r.y * z.x);
+    return r;
+}
+
 // Device-side latched conditions (one per table).
 struct DeviceFlags {
     unsigned long long clamped;
@@ -70,16 +99,16 @@ __device__ inline int quantise_one(const float* up, int phased, double eps, doub
     if (phased) {
         const double ux = up[0], uy = up[1];
         om = sqrt(ux * ux + uy * uy);
-        *phi = atan2(uy, ux);
+        if (phi) *phi = atan2(uy, ux);
     } else {
         const double x = up[0];
         om = fabs(x);
         neg = x < 0.0;
-        *phi = 0.0;
+        if (phi) *phi = 0.0;
     }
     if (!(om <= 1.7976931348623157e308)) {  // NaN or Inf
         if (flags) atomicOr(&flags->nonfinite, 1u);
-        *phi = 0.0;
+        if (phi) *phi = 0.0;
         return 0;
     }
     double qf = floor(om / eps + 0.5);
@@ -112,6 +141,7 @@ struct redo_table_s {
     double* h64 = nullptr;  // diagonal drifts [n_drift][d] (drift_is_diag)
     float2* V32 = nullptr;  // drift propagators: diag [n_drift][d] or dense [n_drift][d][d]
     double* g64 = nullptr;  // phase generators [K][d] (phased)
+    signed char* g2 = nullptr;  // 2 g64 as integers [K][d] when every entry is a half-integer with |2g| <= 64, else null
     float2* S32 = nullptr;  // generators rounded to FP32, [K][d][d]
     float2* Sy32 = nullptr; // y-partners exp(-i pi/2 G) S exp(i pi/2 G) of phased generators, FP32 [K][d][d]
     float2* H32 = nullptr;  // dense drifts rounded to FP32 [n_drift][d][d] (dense drift only)

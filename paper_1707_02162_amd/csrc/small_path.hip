@@ -23,6 +23,7 @@ struct TView {
     const float2* V;
     const double* h;
     const double* g;
+    const signed char* g2;   // 2 g as integers (every g a half-integer), or null
     const float2* S;
     DeviceFlags* flags;
     long long ent;   // d*d
@@ -42,6 +43,7 @@ TView view_of(const redo_table_s* t) {
     v.V = t->V32;
     v.h = t->h64;
     v.g = t->g64;
+    v.g2 = t->g2;
     v.S = t->S32;
     v.flags = t->flags;
     v.ent = t->entry_elems;
@@ -91,18 +93,21 @@ __device__ inline void inst_sync() {
 }
 
 // Drift phases exp(-i hdt h_a) of the rows (or columns) idx + NT r the thread owns
-// (hdt = dt, or dt/2 for the Strang halves), FP64 rounded once to FP32: constant
-// along the chain, so computed once per instance.
+// (hdt = dt, or dt/2 for the Strang halves), in FP64 (ph64, combined with the phase
+// rotations of phased channels before the single rounding) and rounded once to FP32
+// (ph): constant along the chain, so computed once per instance.
 template <int D>
-__device__ inline void drift_phases(const TView& tv, int drift, int idx, float2 (&ph)[Cfg<D>::TB]) {
+__device__ inline void drift_phases(const TView& tv, int drift, int idx, float2 (&ph)[Cfg<D>::TB],
+                                    double2 (&ph64)[Cfg<D>::TB]) {
     constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
     const double hdt = tv.strang ? 0.5 * tv.dt : tv.dt;
 #pragma unroll
     for (int r = 0; r < TB; ++r) {
         if (tv.diag) {
-            const double2 e = expmi(hdt * tv.h[(long long)drift * D + idx + NT * r]);
-            ph[r] = make_float2((float)e.x, (float)e.y);
+            ph64[r] = expmi(hdt * tv.h[(long long)drift * D + idx + NT * r]);
+            ph[r] = make_float2((float)ph64[r].x, (float)ph64[r].y);
         } else {
+            ph64[r] = make_double2(1.0, 0.0);
             ph[r] = make_float2(1.f, 0.f);
         }
     }
@@ -203,43 +208,57 @@ __device__ inline double inst_sum(double v, double* scratch) {
 }
 
 // ---------------------------------------------------------------- one step
-// phase angle theta_a = sum_k phi_k g_k[a] of every row a the thread owns;
-// also returns the number of channels.  Quantises all channels of the step.
+// Phase rotations exp(+i theta_a), theta_a = sum_k phi_k g_k[a], of the rows (or
+// columns) idx + NT r the thread owns (phased channels, Sec. III: Z = exp(-i theta G),
+// so Z^dag scales index a by exp(+i theta_a)).  Phase generators of spins (every g a
+// half-integer) give exp(i phi_k g) = (exp(i phi_k / 2))^(2g) from the control pair
+// itself, with no transcendental function; others one FP64 sincos of the summed angle.
 template <int D>
-__device__ inline void step_phases(const TView& tv, const float* us, bool active, int ti, double (&th)[Cfg<D>::TB]) {
+__device__ inline void step_rotations(const TView& tv, const float* us, bool active, int idx,
+                                      double2 (&P)[Cfg<D>::TB]) {
     constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
 #pragma unroll
-    for (int r = 0; r < TB; ++r) th[r] = 0.0;
+    for (int r = 0; r < TB; ++r) P[r] = make_double2(1.0, 0.0);
     if (!active || !tv.phased) return;
-    for (int k = 0; k < tv.K; ++k) {
-        double phi;
-        quantise_one(us + 2 * k, 1, tv.eps, tv.qmax, &phi, nullptr);
+    if (tv.g2) {
+        for (int k = 0; k < tv.K; ++k) {
+            const double2 hp = half_phase((double)us[2 * k], (double)us[2 * k + 1]);
 #pragma unroll
-        for (int r = 0; r < TB; ++r) th[r] += phi * tv.g[(long long)k * D + ti + NT * r];
+            for (int r = 0; r < TB; ++r) P[r] = zmul(P[r], zpow(hp, tv.g2[(long long)k * D + idx + NT * r]));
+        }
+    } else {
+        double th[TB];
+#pragma unroll
+        for (int r = 0; r < TB; ++r) th[r] = 0.0;
+        for (int k = 0; k < tv.K; ++k) {
+            double phi;
+            quantise_one(us + 2 * k, 1, tv.eps, tv.qmax, &phi, nullptr);
+#pragma unroll
+            for (int r = 0; r < TB; ++r) th[r] += phi * tv.g[(long long)k * D + idx + NT * r];
+        }
+#pragma unroll
+        for (int r = 0; r < TB; ++r) P[r] = zconj(expmi(th[r]));
     }
 }
+
+__device__ inline float2 to_f2(double2 e) { return make_float2((float)e.x, (float)e.y); }
 
 // x <- U_n x with U_n = Z [prod_k R_k] Z^dag V
 // dph: the drift phases of the thread's rows (drift_phases), used when the channels are unphased
 template <int D>
 __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float2* Fs,
                           const float* us, int drift, bool active, bool report, int lt, int ti, int tj,
-                          const float2 (&dph)[Cfg<D>::TB]) {
-    constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
+                          const float2 (&dph)[Cfg<D>::TB], const double2 (&dph64)[Cfg<D>::TB]) {
+    constexpr int TB = Cfg<D>::TB;
     const int KK = tv.phased ? 2 : 1;
-    double th[TB];
-    step_phases<D>(tv, us, active, ti, th);
+    double2 P[TB];
+    step_rotations<D>(tv, us, active, ti, P);
     // drift (or its first half, Strang), then Z^dag (diagonal scalings of rows)
-    const double hdt = tv.strang ? 0.5 * tv.dt : tv.dt;
     if (tv.diag) {
         if (active) {
 #pragma unroll
             for (int r = 0; r < TB; ++r) {
-                float2 s = dph[r];
-                if (tv.phased) {
-                    const double2 e = expmi(hdt * tv.h[(long long)drift * D + ti + NT * r] - th[r]);
-                    s = make_float2((float)e.x, (float)e.y);
-                }
+                const float2 s = tv.phased ? to_f2(zmul(dph64[r], P[r])) : dph[r];
 #pragma unroll
                 for (int c = 0; c < TB; ++c) x[r][c] = cmul(s, x[r][c]);
             }
@@ -256,8 +275,7 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
             if (tv.phased) {
 #pragma unroll
                 for (int r = 0; r < TB; ++r) {
-                    const double2 e = expmi(-th[r]);
-                    const float2 s = make_float2((float)e.x, (float)e.y);
+                    const float2 s = to_f2(P[r]);
 #pragma unroll
                     for (int c = 0; c < TB; ++c) x[r][c] = cmul(s, x[r][c]);
                 }
@@ -270,8 +288,7 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
     const int PE = tv.cache ? 1 : tv.P;
     const int nslot = tv.K * PE;
     auto slot_code = [&](int sl, bool rep) -> int {
-        double phi;
-        return active ? quantise_one(us + KK * (sl / PE), tv.phased, tv.eps, tv.qmax, &phi,
+        return active ? quantise_one(us + KK * (sl / PE), tv.phased, tv.eps, tv.qmax, nullptr,
                                      rep ? tv.flags : nullptr)
                       : 0;
     };
@@ -309,10 +326,7 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
 #pragma unroll
         for (int r = 0; r < TB; ++r) {
             float2 s = dph[r];
-            if (tv.phased) {
-                const double2 e = expmi(th[r] + (tv.strang ? hdt * tv.h[(long long)drift * D + ti + NT * r] : 0.0));
-                s = make_float2((float)e.x, (float)e.y);
-            }
+            if (tv.phased) s = to_f2(tv.strang ? zmul(zconj(P[r]), dph64[r]) : zconj(P[r]));
 #pragma unroll
             for (int c = 0; c < TB; ++c) x[r][c] = cmul(s, x[r][c]);
         }
@@ -324,22 +338,18 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
 template <int D>
 __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB], float2* Ls, float2* Fs,
                            const float* us, int drift, bool active, int lt, int ti, int tj,
-                           const float2 (&dpc)[Cfg<D>::TB]) {
-    constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
+                           const float2 (&dpc)[Cfg<D>::TB], const double2 (&dpc64)[Cfg<D>::TB]) {
+    constexpr int TB = Cfg<D>::TB;
     const int KK = tv.phased ? 2 : 1;
-    // column phases: theta_c for the columns the thread owns
-    double thc[TB];
-    step_phases<D>(tv, us, active, tj, thc);
-    const double hdt = tv.strang ? 0.5 * tv.dt : tv.dt;
+    // phase rotations exp(i theta_c) of the columns the thread owns
+    double2 Pc[TB];
+    step_rotations<D>(tv, us, active, tj, Pc);
     // columns: the second half of the drift (Strang), then Z
     if (active && (tv.phased || tv.strang)) {
 #pragma unroll
         for (int c = 0; c < TB; ++c) {
             float2 s = dpc[c];
-            if (tv.phased) {
-                const double2 e = expmi(thc[c] + (tv.strang ? hdt * tv.h[(long long)drift * D + tj + NT * c] : 0.0));
-                s = make_float2((float)e.x, (float)e.y);
-            }
+            if (tv.phased) s = to_f2(tv.strang ? zmul(zconj(Pc[c]), dpc64[c]) : zconj(Pc[c]));
 #pragma unroll
             for (int r = 0; r < TB; ++r) l[r][c] = cmul(l[r][c], s);
         }
@@ -349,8 +359,7 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
         const int PE = tv.cache ? 1 : tv.P;
         const int nslot = tv.K * PE;
         auto slot_code = [&](int sl) -> int {
-            double phi;
-            return active ? quantise_one(us + KK * (sl / PE), tv.phased, tv.eps, tv.qmax, &phi, nullptr) : 0;
+            return active ? quantise_one(us + KK * (sl / PE), tv.phased, tv.eps, tv.qmax, nullptr, nullptr) : 0;
         };
         auto entry_of = [&](int sl, int q) -> const float2* {
             if (tv.cache) {
@@ -386,11 +395,7 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
         if (active) {
 #pragma unroll
             for (int c = 0; c < TB; ++c) {
-                float2 s = dpc[c];
-                if (tv.phased) {
-                    const double2 e = expmi(hdt * tv.h[(long long)drift * D + tj + NT * c] - thc[c]);
-                    s = make_float2((float)e.x, (float)e.y);
-                }
+                const float2 s = tv.phased ? to_f2(zmul(dpc64[c], Pc[c])) : dpc[c];
 #pragma unroll
                 for (int r = 0; r < TB; ++r) l[r][c] = cmul(l[r][c], s);
             }
@@ -399,8 +404,7 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
         if (active && tv.phased) {
 #pragma unroll
             for (int c = 0; c < TB; ++c) {
-                const double2 e = expmi(-thc[c]);
-                const float2 s = make_float2((float)e.x, (float)e.y);
+                const float2 s = to_f2(Pc[c]);
 #pragma unroll
                 for (int r = 0; r < TB; ++r) l[r][c] = cmul(l[r][c], s);
             }
@@ -593,10 +597,11 @@ __global__ __launch_bounds__(256, (PH == 0 && D <= 16) ? 4 : 1) void small_chain
         }
     }
     float2 dph[TB];
-    drift_phases<D>(tv, drift, ti, dph);
+    double2 dph64[TB];
+    drift_phases<D>(tv, drift, ti, dph, dph64);
     for (int n = 0; n < N; ++n) {
         const bool active = valid && n < len;
-        step_left<D>(tv, x, Xs, Fs, ub + (long long)n * tv.K * KK, drift, active, lt == 0, lt, ti, tj, dph);
+        step_left<D>(tv, x, Xs, Fs, ub + (long long)n * tv.K * KK, drift, active, lt == 0, lt, ti, tj, dph, dph64);
         if (a.reproject_every > 0 && !a.compose && ((a.step_offset + n + 1) % a.reproject_every) == 0)
             reproject<D>(x, Xs, Fs, active, ti, tj, red, tv.flags, lt == 0);
         if (a.X_prefix && active) {
@@ -735,12 +740,13 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
 #pragma unroll
         for (int c = 0; c < TB; ++c) x[r][c] = make_float2((ti + NT * r) == (tj + NT * c) ? 1.f : 0.f, 0.f);
     float2 dph[TB], dpc[TB];
-    drift_phases<D>(tv, drift, ti, dph);
-    drift_phases<D>(tv, drift, tj, dpc);
+    double2 dph64[TB], dpc64[TB];
+    drift_phases<D>(tv, drift, ti, dph, dph64);
+    drift_phases<D>(tv, drift, tj, dpc, dpc64);
     for (int n = 0; n < N; ++n) {
         const bool active = valid && n < len;
         if (active && n % C == 0) save_block<D>(x, ck + (long long)(n / C) * D * D, ti, tj);
-        step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, lt == 0, lt, ti, tj, dph);
+        step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, lt == 0, lt, ti, tj, dph, dph64);
     }
     // ---- overlap g = Tr(U_f^dag X_N) / Tr(U_f^dag U_f)
     const float2* Uf = a.U_target + (long long)(valid ? b : 0) * D * D;
@@ -784,8 +790,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
     auto finalize = [&](int s, int k, double Dr, double Di) {
         const float* us = ub + (long long)s * ustride;
         const double* pk = pb_ + k * 6;
-        double phi;
-        const int q = quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, &phi, nullptr);
+        const int q = quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, nullptr, nullptr);
         auto im_gc = [&](double zr, double zi) { return gr * zi - gi * zr; };   // Im(conj(g) z)
         if (!tv.phased) {
             gb[(long long)s * ustride + k] = (float)(scale * tv.dt * im_gc(pk[0], pk[1]));
@@ -796,7 +801,9 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
             const double om = (double)q * tv.eps;
             const double dFo = scale * tv.dt * im_gc(pk[0], pk[1]);
             const double dFp = scale * im_gc(pk[4] - Dr, pk[5] - Di);
-            const double cp = cos(phi), sp = sin(phi);
+            // cos and sin of phi = atan2(u_y, u_x): the pair over its modulus (q != 0: finite, nonzero)
+            const double ux = us[2 * k], uy = us[2 * k + 1], mu = sqrt(ux * ux + uy * uy);
+            const double cp = ux / mu, sp = uy / mu;
             gb[(long long)s * ustride + 2 * k] = (float)(cp * dFo - sp * dFp / om);
             gb[(long long)s * ustride + 2 * k + 1] = (float)(sp * dFo + cp * dFp / om);
         }
@@ -810,7 +817,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
         if (seg_active) load_block<D>(x, ck + (long long)sgi * D * D, ti, tj);
         for (int n = s0; n < s1; ++n) {
             const bool active = valid && n < len;
-            step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, false, lt, ti, tj, dph);
+            step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, false, lt, ti, tj, dph, dph64);
             if (active) save_block<D>(x, sg + (long long)(n - s0) * D * D, ti, tj);
         }
         for (int s = s1 - 1; s >= s0; --s) {
@@ -830,9 +837,20 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
             const float* us = ub + (long long)s * ustride;
             for (int k = 0; k < tv.K; ++k) {
                 double phi = 0.0;
-                const int q = active ? quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, &phi, nullptr) : 0;
+                int q = 0;
+                if (active) {
+                    if (tv.g2)
+                        q = quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, nullptr, nullptr);
+                    else
+                        q = quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, &phi, nullptr);
+                }
                 const bool origin = tv.phased && q == 0;
                 const double psi = tv.phased ? (origin ? 0.0 : phi) : 0.0;
+                // half-integer generators: exp(i psi / 2) from the pair, and exp(i pi / 4) at the origin
+                const double2 hp = (tv.g2 && tv.phased && !origin && active)
+                                       ? half_phase((double)us[2 * k], (double)us[2 * k + 1])
+                                       : make_double2(1.0, 0.0);
+                const double2 hq = make_double2(0.70710678118654752, 0.70710678118654752);
                 double tr = 0.0, tim = 0.0, ur = 0.0, ui = 0.0, dr = 0.0, di = 0.0;
                 if (active) {
                     const double* gk = tv.phased ? tv.g + (long long)k * D : nullptr;
@@ -851,13 +869,24 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
                         }
                         qa[t2] = pa[t2];
                         qb[t2] = pb[t2];
-                        if (gk && psi != 0.0) {
-                            pa[t2] = zmul(pa[t2], expmi(psi * gk[tj + NT * t2]));
-                            pb[t2] = zmul(pb[t2], zconj(expmi(psi * gk[ti + NT * t2])));
-                        }
-                        if (origin) {
-                            qa[t2] = zmul(qa[t2], expmi(1.5707963267948966 * gk[tj + NT * t2]));
-                            qb[t2] = zmul(qb[t2], zconj(expmi(1.5707963267948966 * gk[ti + NT * t2])));
+                        if (gk && tv.g2) {
+                            const signed char* g2k = tv.g2 + (long long)k * D;
+                            if (!origin) {
+                                pa[t2] = zmul(pa[t2], zconj(zpow(hp, g2k[tj + NT * t2])));
+                                pb[t2] = zmul(pb[t2], zpow(hp, g2k[ti + NT * t2]));
+                            } else {
+                                qa[t2] = zmul(qa[t2], zconj(zpow(hq, g2k[tj + NT * t2])));
+                                qb[t2] = zmul(qb[t2], zpow(hq, g2k[ti + NT * t2]));
+                            }
+                        } else {
+                            if (gk && psi != 0.0) {
+                                pa[t2] = zmul(pa[t2], expmi(psi * gk[tj + NT * t2]));
+                                pb[t2] = zmul(pb[t2], zconj(expmi(psi * gk[ti + NT * t2])));
+                            }
+                            if (origin) {
+                                qa[t2] = zmul(qa[t2], expmi(1.5707963267948966 * gk[tj + NT * t2]));
+                                qb[t2] = zmul(qb[t2], zconj(expmi(1.5707963267948966 * gk[ti + NT * t2])));
+                            }
                         }
                     }
 #pragma unroll
@@ -908,7 +937,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
                 pend_step = s;
             }
             // L_s = L_{s+1} U_s
-            step_right<D>(tv, l, Ls, Fs, us, drift, active, lt, ti, tj, dpc);
+            step_right<D>(tv, l, Ls, Fs, us, drift, active, lt, ti, tj, dpc, dpc64);
         }
     }
     // D_0 = Tr(G Y_0), Y_0 = X_0 L_0 = L_0

@@ -247,6 +247,44 @@ def test_grape_c1_vs_oracle_gradient():
     _grape_check(p, tab, F.cpu().numpy(), ov.cpu().numpy(), grad.cpu().numpy(), range(p.B))
 
 
+def _edge_phase_problem(B=2, N=24):
+    """C1 with Cartesian pairs at the edges of phi = atan2(u_y, u_x): +-pi from both
+    signed zeros, +-0, +-pi/2, the origin with every sign of zero, a pair just off the
+    negative axis, and a nearly vertical one."""
+    p = W.c1_two_spin(B=B, N=N)
+    a = np.float32(0.5 * p.u_scale)
+    z = np.float32(0.0)
+    edge = [(a, z), (a, -z), (-a, z), (-a, -z), (z, a), (z, -a), (-a, np.float32(1e-30)),
+            (-a, np.float32(-1e-30)), (z, z), (-z, z), (-z, -z), (a, a), (-a, -a), (a * np.float32(1e-7), -a)]
+    u = p.u.copy()
+    for b in range(B):
+        for n in range(len(edge)):
+            for k in range(p.K):
+                u[b, n, k, :] = edge[(n + k + b) % len(edge)]
+    p.u = u
+    return p
+
+
+@pytest.mark.parametrize("cached", [False, True])
+def test_phased_edge_phases_chain_and_grape_vs_oracle(cached):
+    """The phase rotations of phased channels (half-angle formulas and integer powers for
+    spin generators) at the edge cases of atan2, chain and gradient against the oracle."""
+    p = _edge_phase_problem()
+    t = table(p)
+    if cached:
+        t.cache_levels()
+    u = torch.tensor(p.u).cuda()
+    assert torch.signbit(u[0, 3, 0, 1]).item()   # a negative zero reached the device
+    U, _, _ = t.chain(u)
+    U = U.cpu().numpy()
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    for b in range(p.B):
+        X = O.chain(O.compose_all_redo(p, tab, b))
+        assert nfrob(U[b], X) < FROB_TOL, (b, nfrob(U[b], X))
+    F, ov, grad = t.grape(u, torch.tensor(p.U_target).cuda())
+    _grape_check(p, tab, F.cpu().numpy(), ov.cpu().numpy(), grad.cpu().numpy(), range(p.B))
+
+
 def test_grape_signed_channel_vs_oracle_gradient():
     p = W.ising_freezing(n=3, B=2, N=120)
     p.U_target = np.stack([W.haar_unitary(8, W.rng(31, 2, b)) for b in range(2)])
