@@ -207,6 +207,17 @@ __device__ inline double inst_sum(double v, double* scratch) {
     return v;
 }
 
+// the six trace sums over the instance's lanes within each wave (the first half of inst_sum)
+template <int D>
+__device__ inline void wave_sums(double (&v)[6]) {
+    constexpr int TPI = Cfg<D>::TPI;
+    constexpr int W = TPI < 64 ? TPI : 64;
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int j = 0; j < 6; ++j) v[j] += __shfl_xor(v[j], off, 64);
+}
+
 // ---------------------------------------------------------------- one step
 // Phase rotations exp(+i theta_a), theta_a = sum_k phi_k g_k[a], of the rows (or
 // columns) idx + NT r the thread owns (phased channels, Sec. III: Z = exp(-i theta G),
@@ -709,8 +720,10 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
     TView tv = tv_in;
     tv.phased = PH;
     constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT, TPI = Cfg<D>::TPI, IPB = Cfg<D>::IPB;
+    constexpr int NW = TPI > 64 ? TPI / 64 : 1;   // waves per instance
     extern __shared__ float2 lds[];
     __shared__ double red[4];
+    __shared__ double tred[NW > 1 ? KMAX * 6 * NW : 1];   // per-wave partial traces [k][6][wave]
     __shared__ int nblk;
     const int tid = threadIdx.x, slot = tid / TPI, lt = tid % TPI;
     const int ti = lt / NT, tj = lt % NT;
@@ -807,6 +820,15 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
             gb[(long long)s * ustride + 2 * k] = (float)(cp * dFo - sp * dFp / om);
             gb[(long long)s * ustride + 2 * k + 1] = (float)(sp * dFo + cp * dFp / om);
         }
+    };
+
+    // the traces of channel k of the current step: complete the pending (later) step's
+    // gradient with this step's D, then keep them as pending
+    auto commit = [&](int k, const double (&v6)[6]) {
+        if (has_pend) finalize(pend_step, k, v6[4], v6[5]);
+        double* pk = pb_ + k * 6;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) pk[j] = v6[j];
     };
 
     const int nseg = (N + C - 1) / C;
@@ -913,23 +935,34 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
                             }
                         }
                 }
-                tr = inst_sum<D>(tr, red);
-                tim = inst_sum<D>(tim, red);
-                if (tv.phased) {
-                    ur = inst_sum<D>(ur, red);
-                    ui = inst_sum<D>(ui, red);
-                    dr = inst_sum<D>(dr, red);
-                    di = inst_sum<D>(di, red);
+                double v6[6] = {tr, tim, ur, ui, dr, di};
+                const int nv = tv.phased ? 6 : 2;
+                wave_sums<D>(v6);
+                if constexpr (NW > 1) {
+                    // the wave's partial sums wait in LDS for the one barrier after the last channel
+                    if ((lt & 63) == 0)
+                        for (int j = 0; j < nv; ++j) tred[(k * 6 + j) * NW + (lt >> 6)] = v6[j];
+                } else if (active && lt == 0) {
+                    commit(k, v6);
                 }
+            }
+            if constexpr (NW > 1) {
+                // one barrier for every channel's traces (instead of two per trace); thread 0 adds
+                // the waves' partials in wave order.  The next writes to tred follow the barriers
+                // of step_right.
+                __syncthreads();
                 if (active && lt == 0) {
-                    if (has_pend) finalize(pend_step, k, dr, di);
-                    double* pk = pb_ + k * 6;
-                    pk[0] = tr;
-                    pk[1] = tim;
-                    pk[2] = ur;
-                    pk[3] = ui;
-                    pk[4] = dr;
-                    pk[5] = di;
+                    const int nv = tv.phased ? 6 : 2;
+                    for (int k = 0; k < tv.K; ++k) {
+                        double v6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                        for (int j = 0; j < nv; ++j) {
+                            double t = tred[(k * 6 + j) * NW];
+#pragma unroll
+                            for (int w = 1; w < NW; ++w) t += tred[(k * 6 + j) * NW + w];
+                            v6[j] = t;
+                        }
+                        commit(k, v6);
+                    }
                 }
             }
             if (active) {
