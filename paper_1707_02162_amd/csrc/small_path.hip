@@ -75,6 +75,9 @@ struct Cfg {
     // wave would meet in the same banks at every access (measured: 70-75 % of the LDS cycles of the
     // d = 4 kernels were bank conflicts)
     static constexpr int PAD = 4;
+    // instances of at least one wave take each step's codes and control pairs from a per-step
+    // header in LDS (ChanHdr)
+    static constexpr bool HDR = TPI >= 64;
 };
 
 // Barrier among the threads of one instance around its LDS buffers.  At d <= 16
@@ -219,6 +222,39 @@ __device__ inline void wave_sums(double (&v)[6]) {
 }
 
 // ---------------------------------------------------------------- one step
+// The channels of one step, for instances of at least one wave: one thread per channel quantises
+// its control (Sec. II, Eq. cgrain) and, for a phased channel, forms the rotation angle's half-angle
+// phase (or the angle), and every thread of the instance reads them from LDS; without it every
+// thread walks each channel's chain of dependent loads and FP64 arithmetic itself, once per slot.
+struct ChanHdr {
+    int q;          // the code
+    float ux, uy;   // the control as given (uy: phased channels)
+    double2 rot;    // phased: half_phase(ux, uy) with half-integer generators, else (phi, 0)
+};
+
+// thread lt < K writes channel lt's entry; report: this pass reports non-finite and clamped controls
+template <int D>
+__device__ inline void make_header(const TView& tv, const float* us, bool active, bool report, int lt,
+                                   ChanHdr* hd) {
+    if (lt >= tv.K) return;
+    const int KK = tv.phased ? 2 : 1;
+    ChanHdr c;
+    c.ux = active ? us[KK * lt] : 0.f;
+    c.uy = (active && tv.phased) ? us[KK * lt + 1] : 0.f;
+    double phi = 0.0;
+    DeviceFlags* fl = report ? tv.flags : nullptr;
+    c.q = 0;
+    if (active) {
+        // two calls with fixed pointer arguments: a conditional &phi would put phi in scratch memory
+        if (tv.phased && !tv.g2)
+            c.q = quantise_one(us + KK * lt, tv.phased, tv.eps, tv.qmax, &phi, fl);
+        else
+            c.q = quantise_one(us + KK * lt, tv.phased, tv.eps, tv.qmax, nullptr, fl);
+    }
+    c.rot = (active && tv.phased && tv.g2) ? half_phase((double)c.ux, (double)c.uy) : make_double2(phi, 0.0);
+    hd[lt] = c;
+}
+
 // Phase rotations exp(+i theta_a), theta_a = sum_k phi_k g_k[a], of the rows (or
 // columns) idx + NT r the thread owns (phased channels, Sec. III: Z = exp(-i theta G),
 // so Z^dag scales index a by exp(+i theta_a)).  Phase generators of spins (every g a
@@ -252,18 +288,56 @@ __device__ inline void step_rotations(const TView& tv, const float* us, bool act
     }
 }
 
+// step_rotations from the step's header: the same arithmetic in the same order
+template <int D>
+__device__ inline void header_rotations(const TView& tv, const ChanHdr* hd, const signed char* g2l, const double* gl,
+                                        bool active, int idx, double2 (&P)[Cfg<D>::TB]) {
+    constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
+#pragma unroll
+    for (int r = 0; r < TB; ++r) P[r] = make_double2(1.0, 0.0);
+    if (!active || !tv.phased) return;
+    if (tv.g2) {
+        for (int k = 0; k < tv.K; ++k) {
+            const double2 hp = hd[k].rot;
+#pragma unroll
+            for (int r = 0; r < TB; ++r) P[r] = zmul(P[r], zpow(hp, g2l[k * D + idx + NT * r]));
+        }
+    } else {
+        double th[TB];
+#pragma unroll
+        for (int r = 0; r < TB; ++r) th[r] = 0.0;
+        for (int k = 0; k < tv.K; ++k) {
+            const double phi = hd[k].rot.x;
+#pragma unroll
+            for (int r = 0; r < TB; ++r) th[r] += phi * gl[k * D + idx + NT * r];
+        }
+#pragma unroll
+        for (int r = 0; r < TB; ++r) P[r] = zconj(expmi(th[r]));
+    }
+}
+
 __device__ inline float2 to_f2(double2 e) { return make_float2((float)e.x, (float)e.y); }
 
 // x <- U_n x with U_n = Z [prod_k R_k] Z^dag V
 // dph: the drift phases of the thread's rows (drift_phases), used when the channels are unphased
+// report: non-finite and clamped controls are reported (by the header's channel threads with HDR,
+// else by the thread that passes it); hd: the instance's step header (HDR)
 template <int D>
 __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float2* Fs,
                           const float* us, int drift, bool active, bool report, int lt, int ti, int tj,
-                          const float2 (&dph)[Cfg<D>::TB], const double2 (&dph64)[Cfg<D>::TB]) {
+                          const float2 (&dph)[Cfg<D>::TB], const double2 (&dph64)[Cfg<D>::TB], ChanHdr* hd,
+                          const signed char* g2l, const double* gl) {
     constexpr int TB = Cfg<D>::TB;
     const int KK = tv.phased ? 2 : 1;
     double2 P[TB];
-    step_rotations<D>(tv, us, active, ti, P);
+    if constexpr (Cfg<D>::HDR) {
+        // the previous step's header was last read before the barriers of its last slot
+        make_header<D>(tv, us, active, report, lt, hd);
+        inst_sync<D>();
+        header_rotations<D>(tv, hd, g2l, gl, active, ti, P);
+    } else {
+        step_rotations<D>(tv, us, active, ti, P);
+    }
     // drift (or its first half, Strang), then Z^dag (diagonal scalings of rows)
     if (tv.diag) {
         if (active) {
@@ -299,6 +373,7 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
     const int PE = tv.cache ? 1 : tv.P;
     const int nslot = tv.K * PE;
     auto slot_code = [&](int sl, bool rep) -> int {
+        if constexpr (Cfg<D>::HDR) return hd[sl / PE].q;
         return active ? quantise_one(us + KK * (sl / PE), tv.phased, tv.eps, tv.qmax, nullptr,
                                      rep ? tv.flags : nullptr)
                       : 0;
@@ -346,15 +421,20 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
 
 // l <- l U_n  (the backward scan), U_n = Z [prod_k R_k] Z^dag V
 // dpc: the drift phases of the thread's columns (drift_phases), used when the channels are unphased
+// hd: the step's header, published by the caller (HDR)
 template <int D>
 __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB], float2* Ls, float2* Fs,
                            const float* us, int drift, bool active, int lt, int ti, int tj,
-                           const float2 (&dpc)[Cfg<D>::TB], const double2 (&dpc64)[Cfg<D>::TB]) {
+                           const float2 (&dpc)[Cfg<D>::TB], const double2 (&dpc64)[Cfg<D>::TB], const ChanHdr* hd,
+                           const signed char* g2l, const double* gl) {
     constexpr int TB = Cfg<D>::TB;
     const int KK = tv.phased ? 2 : 1;
     // phase rotations exp(i theta_c) of the columns the thread owns
     double2 Pc[TB];
-    step_rotations<D>(tv, us, active, tj, Pc);
+    if constexpr (Cfg<D>::HDR)
+        header_rotations<D>(tv, hd, g2l, gl, active, tj, Pc);
+    else
+        step_rotations<D>(tv, us, active, tj, Pc);
     // columns: the second half of the drift (Strang), then Z
     if (active && (tv.phased || tv.strang)) {
 #pragma unroll
@@ -370,6 +450,7 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
         const int PE = tv.cache ? 1 : tv.P;
         const int nslot = tv.K * PE;
         auto slot_code = [&](int sl) -> int {
+            if constexpr (Cfg<D>::HDR) return hd[sl / PE].q;
             return active ? quantise_one(us + KK * (sl / PE), tv.phased, tv.eps, tv.qmax, nullptr, nullptr) : 0;
         };
         auto entry_of = [&](int sl, int q) -> const float2* {
@@ -475,6 +556,21 @@ __device__ void reproject(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float
     if (active) mul_left<D>(x, Xs, Fs, ti, tj);
 }
 
+// The phase generators' diagonals (g, and 2g as integers) into LDS for the header kernels: every
+// thread reads them at every step (through these arrays, which the compiler then knows to be LDS).
+template <int D>
+__device__ inline void stage_generators(const TView& tv, signed char* g2s, double* gs) {
+    if constexpr (Cfg<D>::HDR) {
+        if (tv.phased) {
+            for (int e = threadIdx.x; e < tv.K * D; e += 256) {
+                gs[e] = tv.g[e];
+                if (tv.g2) g2s[e] = tv.g2[e];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- chain kernel
 // PH: the table's phased flag as a compile-time constant (the signed-channel instance carries
 // no phase arithmetic: no atan2 or sincos per step, far fewer registers).  That instance at
@@ -492,6 +588,12 @@ __global__ __launch_bounds__(256, (PH == 0 && D <= 16) ? 4 : 1) void small_chain
     const int ti = lt / NT, tj = lt % NT;
     const int inst = blockIdx.x * IPB + slot;
     const bool valid = inst < ninst;
+    constexpr bool HDR = Cfg<D>::HDR;
+    __shared__ ChanHdr hdr[HDR ? IPB * KMAX : 1];
+    __shared__ signed char g2s[HDR ? KMAX * D : 1];
+    __shared__ double gs[HDR ? KMAX * D : 1];
+    stage_generators<D>(tv, g2s, gs);
+    ChanHdr* hd = hdr + (HDR ? slot * KMAX : 0);
     float2* Xs = lds + (long long)slot * (2 * D * D + Cfg<D>::PAD);
     float2* Fs = Xs + D * D;
     int b = 0, n0 = 0, len = 0;
@@ -612,7 +714,7 @@ __global__ __launch_bounds__(256, (PH == 0 && D <= 16) ? 4 : 1) void small_chain
     drift_phases<D>(tv, drift, ti, dph, dph64);
     for (int n = 0; n < N; ++n) {
         const bool active = valid && n < len;
-        step_left<D>(tv, x, Xs, Fs, ub + (long long)n * tv.K * KK, drift, active, lt == 0, lt, ti, tj, dph, dph64);
+        step_left<D>(tv, x, Xs, Fs, ub + (long long)n * tv.K * KK, drift, active, HDR || lt == 0, lt, ti, tj, dph, dph64, hd, g2s, gs);
         if (a.reproject_every > 0 && !a.compose && ((a.step_offset + n + 1) % a.reproject_every) == 0)
             reproject<D>(x, Xs, Fs, active, ti, tj, red, tv.flags, lt == 0);
         if (a.X_prefix && active) {
@@ -729,6 +831,14 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
     const int ti = lt / NT, tj = lt % NT;
     const int b = blockIdx.x * IPB + slot;
     const bool valid = b < a.B;
+    constexpr bool HDR = Cfg<D>::HDR;
+    // step headers per instance: [0] the forward and recompute scans, [1 + (s & 1)] backward step s
+    __shared__ ChanHdr hdr[HDR ? IPB * 3 * KMAX : 1];
+    __shared__ signed char g2s[HDR ? KMAX * D : 1];
+    __shared__ double gs[HDR ? KMAX * D : 1];
+    stage_generators<D>(tv, g2s, gs);
+    ChanHdr* hF = hdr + (HDR ? slot * 3 * KMAX : 0);
+    ChanHdr* hB = hF + (HDR ? KMAX : 0);
     float2* Xs = lds + (long long)slot * (3 * D * D + Cfg<D>::PAD);
     float2* Fs = Xs + D * D;
     float2* Ls = Fs + D * D;
@@ -759,7 +869,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
     for (int n = 0; n < N; ++n) {
         const bool active = valid && n < len;
         if (active && n % C == 0) save_block<D>(x, ck + (long long)(n / C) * D * D, ti, tj);
-        step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, lt == 0, lt, ti, tj, dph, dph64);
+        step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, HDR || lt == 0, lt, ti, tj, dph, dph64, hF, g2s, gs);
     }
     // ---- overlap g = Tr(U_f^dag X_N) / Tr(U_f^dag U_f)
     const float2* Uf = a.U_target + (long long)(valid ? b : 0) * D * D;
@@ -803,7 +913,8 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
     auto finalize = [&](int s, int k, double Dr, double Di) {
         const float* us = ub + (long long)s * ustride;
         const double* pk = pb_ + k * 6;
-        const int q = quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, nullptr, nullptr);
+        const ChanHdr* hs = hB + (s & 1) * KMAX;   // step s's header (HDR), intact until step s - 2
+        const int q = HDR ? hs[k].q : quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, nullptr, nullptr);
         auto im_gc = [&](double zr, double zi) { return gr * zi - gi * zr; };   // Im(conj(g) z)
         if (!tv.phased) {
             gb[(long long)s * ustride + k] = (float)(scale * tv.dt * im_gc(pk[0], pk[1]));
@@ -815,7 +926,8 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
             const double dFo = scale * tv.dt * im_gc(pk[0], pk[1]);
             const double dFp = scale * im_gc(pk[4] - Dr, pk[5] - Di);
             // cos and sin of phi = atan2(u_y, u_x): the pair over its modulus (q != 0: finite, nonzero)
-            const double ux = us[2 * k], uy = us[2 * k + 1], mu = sqrt(ux * ux + uy * uy);
+            const double ux = HDR ? hs[k].ux : us[2 * k], uy = HDR ? hs[k].uy : us[2 * k + 1];
+            const double mu = sqrt(ux * ux + uy * uy);
             const double cp = ux / mu, sp = uy / mu;
             gb[(long long)s * ustride + 2 * k] = (float)(cp * dFo - sp * dFp / om);
             gb[(long long)s * ustride + 2 * k + 1] = (float)(sp * dFo + cp * dFp / om);
@@ -839,11 +951,15 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
         if (seg_active) load_block<D>(x, ck + (long long)sgi * D * D, ti, tj);
         for (int n = s0; n < s1; ++n) {
             const bool active = valid && n < len;
-            step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, false, lt, ti, tj, dph, dph64);
+            step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, false, lt, ti, tj, dph, dph64, hF, g2s, gs);
             if (active) save_block<D>(x, sg + (long long)(n - s0) * D * D, ti, tj);
         }
         for (int s = s1 - 1; s >= s0; --s) {
             const bool active = valid && s < len;
+            // step s's header: its buffer last served step s + 2, whose readers are all past the
+            // barriers of step s + 1; the barriers below publish it
+            ChanHdr* hs = hB + (s & 1) * KMAX;
+            if constexpr (HDR) make_header<D>(tv, ub + (long long)s * ustride, active, false, lt, hs);
             // Y_{s+1} = X_{s+1} L_{s+1}
             inst_sync<D>();
             if (active) {
@@ -861,21 +977,25 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
                 double phi = 0.0;
                 int q = 0;
                 if (active) {
-                    if (tv.g2)
+                    if constexpr (HDR) {
+                        q = hs[k].q;
+                        if (!tv.g2) phi = hs[k].rot.x;
+                    } else if (tv.g2) {
                         q = quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, nullptr, nullptr);
-                    else
+                    } else {
                         q = quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, &phi, nullptr);
+                    }
                 }
                 const bool origin = tv.phased && q == 0;
                 const double psi = tv.phased ? (origin ? 0.0 : phi) : 0.0;
                 // half-integer generators: exp(i psi / 2) from the pair, and exp(i pi / 4) at the origin
-                const double2 hp = (tv.g2 && tv.phased && !origin && active)
-                                       ? half_phase((double)us[2 * k], (double)us[2 * k + 1])
-                                       : make_double2(1.0, 0.0);
+                double2 hp = make_double2(1.0, 0.0);
+                if (tv.g2 && tv.phased && !origin && active)
+                    hp = HDR ? hs[k].rot : half_phase((double)us[2 * k], (double)us[2 * k + 1]);
                 const double2 hq = make_double2(0.70710678118654752, 0.70710678118654752);
                 double tr = 0.0, tim = 0.0, ur = 0.0, ui = 0.0, dr = 0.0, di = 0.0;
                 if (active) {
-                    const double* gk = tv.phased ? tv.g + (long long)k * D : nullptr;
+                    const double* gk = tv.phased ? (HDR ? (const double*)gs : tv.g) + (long long)k * D : nullptr;
                     const float2* Sk = tv.S + (long long)k * D * D;
                     // exp(-i psi (g_aa - g_bb)) = pa[c] pb[r] (aa = column index of the block, bb = row);
                     // Strang: the generator seen by the trace is V(dt/2) S V(dt/2)^dag, one more phase
@@ -892,7 +1012,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
                         qa[t2] = pa[t2];
                         qb[t2] = pb[t2];
                         if (gk && tv.g2) {
-                            const signed char* g2k = tv.g2 + (long long)k * D;
+                            const signed char* g2k = (HDR ? (const signed char*)g2s : tv.g2) + (long long)k * D;
                             if (!origin) {
                                 pa[t2] = zmul(pa[t2], zconj(zpow(hp, g2k[tj + NT * t2])));
                                 pb[t2] = zmul(pb[t2], zpow(hp, g2k[ti + NT * t2]));
@@ -970,7 +1090,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
                 pend_step = s;
             }
             // L_s = L_{s+1} U_s
-            step_right<D>(tv, l, Ls, Fs, us, drift, active, lt, ti, tj, dpc, dpc64);
+            step_right<D>(tv, l, Ls, Fs, us, drift, active, lt, ti, tj, dpc, dpc64, hs, g2s, gs);
         }
     }
     // D_0 = Tr(G Y_0), Y_0 = X_0 L_0 = L_0
