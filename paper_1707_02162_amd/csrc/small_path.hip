@@ -78,7 +78,25 @@ struct Cfg {
     // instances of at least one wave take each step's codes and control pairs from a per-step
     // header in LDS (ChanHdr)
     static constexpr bool HDR = TPI >= 64;
+    // the products run on the matrix cores (one output quadrant per wave, the result handed to the
+    // owning threads through one more LDS buffer): chains at d = 32, 64, GRAPE at d = 32 (at d = 64
+    // its accumulators would push the GRAPE kernel's live state out of registers)
+    static constexpr bool MF = D == 32 || D == 64, MFG = D == 32;
+    static constexpr int NBUF_CHAIN = MF ? 3 : 2, NBUF_GRAPE = MFG ? 4 : 3;   // d x d LDS buffers per instance
 };
+
+// LDS word of element (r, c) of an instance's d x d buffer.  d = 32, 64: the column index is XORed
+// with a function of the row, so that the matrix-core operand reads (lanes down a column of the
+// left factor, or along a row of the right one) fall in distinct banks; smaller d: row-major.
+template <int D>
+__device__ inline int lidx(int r, int c) {
+    if constexpr (D == 32)
+        return r * D + (c ^ (((r << 1) ^ ((r & 1) << 4)) & 31));
+    else if constexpr (D == 64)
+        return r * D + (c ^ (r & 31));
+    else
+        return r * D + c;
+}
 
 // Barrier among the threads of one instance around its LDS buffers.  At d <= 16
 // an instance's threads are lanes of one wave, whose LDS accesses execute in
@@ -124,7 +142,7 @@ __device__ inline void store_block(float2* Ms, const float2 (&x)[Cfg<D>::TB][Cfg
 #pragma unroll
     for (int r = 0; r < TB; ++r)
 #pragma unroll
-        for (int c = 0; c < TB; ++c) Ms[(ti + NT * r) * D + tj + NT * c] = x[r][c];
+        for (int c = 0; c < TB; ++c) Ms[lidx<D>(ti + NT * r, tj + NT * c)] = x[r][c];
 }
 
 // Ms <- src (d x d from global), or src^dag when adj
@@ -134,9 +152,9 @@ __device__ inline void stage(float2* Ms, const float2* __restrict__ src, bool ad
     for (int e = lt; e < D * D; e += TPI) {
         const float2 v = src[e];
         if (adj)
-            Ms[(e % D) * D + e / D] = cconj(v);
+            Ms[lidx<D>(e % D, e / D)] = cconj(v);
         else
-            Ms[e] = v;
+            Ms[lidx<D>(e / D, e % D)] = v;
     }
 }
 
@@ -160,29 +178,76 @@ __device__ inline void put_factor(float2* Ms, const FactorRegs<D>& f, bool adj, 
     for (int i = 0; i < NR; ++i) {
         const int e = lt + TPI * i;
         if (adj)
-            Ms[(e % D) * D + e / D] = cconj(f.v[i]);
+            Ms[lidx<D>(e % D, e / D)] = cconj(f.v[i]);
         else
-            Ms[e] = f.v[i];
+            Ms[lidx<D>(e / D, e % D)] = f.v[i];
     }
 }
 
-// x <- Fs * Xs  (rows of the thread's block)
-template <int D>
-__device__ inline void mul_left(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], const float2* Fs, const float2* Xs, int ti,
-                                int tj) {
+// x <- (A B) on the thread's block, A and B d x d in LDS.  Matrix cores (MM; d = 32, 64): wave w forms
+// output quadrant (w / 2, w % 2) with four real products per k-block (v_mfma_f32_16x16x4_f32 at
+// d = 32, v_mfma_f32_32x32x2_f32 at d = 64; FP32 accumulation), writes it to Rs and, after a barrier,
+// every thread reads its own block back; the caller's next barrier precedes the next write of Rs.
+// Vector FMAs on the thread's block otherwise.
+template <int D, bool MM>
+__device__ inline void mul_left(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], const float2* A, const float2* B, float2* Rs,
+                                int ti, int tj) {
     constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
+    if constexpr (MM) {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, qi = w >> 1, qj = w & 1;
+        if constexpr (D == 32) {
+            typedef float fx4 __attribute__((ext_vector_type(4)));
+            const int i = 16 * qi + (lane & 15), j = 16 * qj + (lane & 15), kq = lane >> 4;
+            fx4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k0 = 0; k0 < D; k0 += 4) {
+                const float2 a = A[lidx<D>(i, k0 + kq)], b = B[lidx<D>(k0 + kq, j)];
+                cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cr, 0, 0, 0);
+                ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, ci, 0, 0, 0);
+                cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, cr, 0, 0, 0);
+                ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, ci, 0, 0, 0);
+            }
+            // element (4 (lane / 16) + r, lane % 16) of the quadrant in register r
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Rs[lidx<D>(16 * qi + 4 * kq + r, j)] = make_float2(cr[r], ci[r]);
+        } else {
+            typedef float fx16 __attribute__((ext_vector_type(16)));
+            const int i = 32 * qi + (lane & 31), j = 32 * qj + (lane & 31), kq = lane >> 5;
+            fx16 cr, ci;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) cr[r] = ci[r] = 0.f;
+#pragma unroll 4
+            for (int k0 = 0; k0 < D; k0 += 2) {
+                const float2 a = A[lidx<D>(i, k0 + kq)], b = B[lidx<D>(k0 + kq, j)];
+                cr = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, cr, 0, 0, 0);
+                ci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, ci, 0, 0, 0);
+                cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.y, b.y, cr, 0, 0, 0);
+                ci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, ci, 0, 0, 0);
+            }
+            // element (8 (r / 4) + 4 (lane / 32) + r % 4, lane % 32) of the quadrant in register r
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                Rs[lidx<D>(32 * qi + 8 * (r >> 2) + 4 * kq + (r & 3), j)] = make_float2(cr[r], ci[r]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < TB; ++r)
+#pragma unroll
+            for (int c = 0; c < TB; ++c) x[r][c] = Rs[lidx<D>(ti + NT * r, tj + NT * c)];
+        return;
+    }
     float2 acc[TB][TB];
 #pragma unroll
     for (int r = 0; r < TB; ++r)
 #pragma unroll
         for (int c = 0; c < TB; ++c) acc[r][c] = make_float2(0.f, 0.f);
-#pragma unroll 4
+#pragma unroll 8
     for (int m = 0; m < D; ++m) {
         float2 f[TB], y[TB];
 #pragma unroll
-        for (int r = 0; r < TB; ++r) f[r] = Fs[(ti + NT * r) * D + m];
+        for (int r = 0; r < TB; ++r) f[r] = A[lidx<D>(ti + NT * r, m)];
 #pragma unroll
-        for (int c = 0; c < TB; ++c) y[c] = Xs[m * D + tj + NT * c];
+        for (int c = 0; c < TB; ++c) y[c] = B[lidx<D>(m, tj + NT * c)];
 #pragma unroll
         for (int r = 0; r < TB; ++r)
 #pragma unroll
@@ -321,9 +386,9 @@ __device__ inline float2 to_f2(double2 e) { return make_float2((float)e.x, (floa
 // x <- U_n x with U_n = Z [prod_k R_k] Z^dag V
 // dph: the drift phases of the thread's rows (drift_phases), used when the channels are unphased
 // report: non-finite and clamped controls are reported (by the header's channel threads with HDR,
-// else by the thread that passes it); hd: the instance's step header (HDR)
-template <int D>
-__device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float2* Fs,
+// else by the thread that passes it); hd: the instance's step header (HDR); MM: matrix-core products
+template <int D, bool MM>
+__device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float2* Fs, float2* Rs,
                           const float* us, int drift, bool active, bool report, int lt, int ti, int tj,
                           const float2 (&dph)[Cfg<D>::TB], const double2 (&dph64)[Cfg<D>::TB], ChanHdr* hd,
                           const signed char* g2l, const double* gl) {
@@ -356,7 +421,7 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
         }
         inst_sync<D>();
         if (active) {
-            mul_left<D>(x, Fs, Xs, ti, tj);
+            mul_left<D, MM>(x, Fs, Xs, Rs, ti, tj);
             if (tv.phased) {
 #pragma unroll
                 for (int r = 0; r < TB; ++r) {
@@ -405,7 +470,7 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
             f = entry_of(sn, q);
             if (f) fetch_factor<D>(fr, f, lt);
         }
-        if (mult) mul_left<D>(x, Fs, Xs, ti, tj);
+        if (mult) mul_left<D, MM>(x, Fs, Xs, Rs, ti, tj);
     }
     // Z, then the second half of the drift (Strang)
     if (active && (tv.phased || tv.strang)) {
@@ -421,9 +486,9 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
 
 // l <- l U_n  (the backward scan), U_n = Z [prod_k R_k] Z^dag V
 // dpc: the drift phases of the thread's columns (drift_phases), used when the channels are unphased
-// hd: the step's header, published by the caller (HDR)
-template <int D>
-__device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB], float2* Ls, float2* Fs,
+// hd: the step's header, published by the caller (HDR); MM: matrix-core products
+template <int D, bool MM>
+__device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB], float2* Ls, float2* Fs, float2* Rs,
                            const float* us, int drift, bool active, int lt, int ti, int tj,
                            const float2 (&dpc)[Cfg<D>::TB], const double2 (&dpc64)[Cfg<D>::TB], const ChanHdr* hd,
                            const signed char* g2l, const double* gl) {
@@ -480,7 +545,7 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
                 f = entry_of(sn, q);
                 if (f) fetch_factor<D>(fr, f, lt);
             }
-            if (mult) mul_left<D>(l, Ls, Fs, ti, tj);  // (Ls Fs) restricted to own block
+            if (mult) mul_left<D, MM>(l, Ls, Fs, Rs, ti, tj);  // (Ls Fs) restricted to own block
         }
     }
     if (tv.diag) {
@@ -507,14 +572,14 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
             store_block<D>(Ls, l, ti, tj);
         }
         inst_sync<D>();
-        if (active) mul_left<D>(l, Ls, Fs, ti, tj);
+        if (active) mul_left<D, MM>(l, Ls, Fs, Rs, ti, tj);
     }
 }
 
 // Newton-Schulz polar step x <- x (3I - x^dag x) / 2  (uniform barriers); the
 // watchdog counts an instance whose ||x^dag x - I||_F / sqrt(D) exceeds UNITARITY_WARN
 template <int D>
-__device__ void reproject(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float2* Fs, bool active, int ti, int tj,
+__device__ void reproject(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float2* Fs, float2* Rs, bool active, int ti, int tj,
                           double* red, DeviceFlags* flags, bool leader) {
     constexpr int TB = Cfg<D>::TB, NT = Cfg<D>::NT;
     double dev2 = 0.0;
@@ -531,9 +596,9 @@ __device__ void reproject(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float
         for (int m = 0; m < D; ++m) {
             float2 a[TB], b[TB];
 #pragma unroll
-            for (int r = 0; r < TB; ++r) a[r] = cconj(Xs[m * D + ti + NT * r]);
+            for (int r = 0; r < TB; ++r) a[r] = cconj(Xs[lidx<D>(m, ti + NT * r)]);
 #pragma unroll
-            for (int c = 0; c < TB; ++c) b[c] = Xs[m * D + tj + NT * c];
+            for (int c = 0; c < TB; ++c) b[c] = Xs[lidx<D>(m, tj + NT * c)];
 #pragma unroll
             for (int r = 0; r < TB; ++r)
 #pragma unroll
@@ -553,7 +618,7 @@ __device__ void reproject(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float
     dev2 = inst_sum<D>(dev2, red);
     if (active && leader) report_drift(flags, sqrt(dev2 / D));
     inst_sync<D>();
-    if (active) mul_left<D>(x, Xs, Fs, ti, tj);
+    if (active) mul_left<D, Cfg<D>::MF>(x, Xs, Fs, Rs, ti, tj);
 }
 
 // The phase generators' diagonals (g, and 2g as integers) into LDS for the header kernels: every
@@ -594,8 +659,9 @@ __global__ __launch_bounds__(256, (PH == 0 && D <= 16) ? 4 : 1) void small_chain
     __shared__ double gs[HDR ? KMAX * D : 1];
     stage_generators<D>(tv, g2s, gs);
     ChanHdr* hd = hdr + (HDR ? slot * KMAX : 0);
-    float2* Xs = lds + (long long)slot * (2 * D * D + Cfg<D>::PAD);
+    float2* Xs = lds + (long long)slot * (Cfg<D>::NBUF_CHAIN * D * D + Cfg<D>::PAD);
     float2* Fs = Xs + D * D;
+    float2* Rs = Fs + D * D;   // product results (matrix-core products)
     int b = 0, n0 = 0, len = 0;
     if (valid) {
         if (a.compose) {
@@ -630,7 +696,7 @@ __global__ __launch_bounds__(256, (PH == 0 && D <= 16) ? 4 : 1) void small_chain
 
     double obs_norm = 1.0;
     // the observable's row lists, once per workgroup, after the instances' buffers
-    float2* ovs = lds + (long long)IPB * (2 * D * D + Cfg<D>::PAD);
+    float2* ovs = lds + (long long)IPB * (Cfg<D>::NBUF_CHAIN * D * D + Cfg<D>::PAD);
     int* ocs = reinterpret_cast<int*>(ovs + (a.obs_out ? D * a.obs_width : 0));
     if (a.obs_out) {
         for (int e = tid; e < D * a.obs_width; e += 256) {
@@ -714,9 +780,9 @@ __global__ __launch_bounds__(256, (PH == 0 && D <= 16) ? 4 : 1) void small_chain
     drift_phases<D>(tv, drift, ti, dph, dph64);
     for (int n = 0; n < N; ++n) {
         const bool active = valid && n < len;
-        step_left<D>(tv, x, Xs, Fs, ub + (long long)n * tv.K * KK, drift, active, HDR || lt == 0, lt, ti, tj, dph, dph64, hd, g2s, gs);
+        step_left<D, Cfg<D>::MF>(tv, x, Xs, Fs, Rs, ub + (long long)n * tv.K * KK, drift, active, HDR || lt == 0, lt, ti, tj, dph, dph64, hd, g2s, gs);
         if (a.reproject_every > 0 && !a.compose && ((a.step_offset + n + 1) % a.reproject_every) == 0)
-            reproject<D>(x, Xs, Fs, active, ti, tj, red, tv.flags, lt == 0);
+            reproject<D>(x, Xs, Fs, Rs, active, ti, tj, red, tv.flags, lt == 0);
         if (a.X_prefix && active) {
             float2* dst = a.X_prefix + ((long long)b * a.N_max + n) * D * D;
 #pragma unroll
@@ -776,9 +842,9 @@ __global__ __launch_bounds__(256, (PH == 0 && D <= 16) ? 4 : 1) void small_chain
                         float2 xm = make_float2(0.f, 0.f), mx = make_float2(0.f, 0.f);
                         for (int t = 0; t < a.obs_width; ++t) {
                             const int colb = ocs[cb * a.obs_width + t];
-                            cfma(xm, Xs[ra * D + colb], cconj(ovs[cb * a.obs_width + t]));
+                            cfma(xm, Xs[lidx<D>(ra, colb)], cconj(ovs[cb * a.obs_width + t]));
                             const int cola = ocs[ra * a.obs_width + t];
-                            cfma(mx, ovs[ra * a.obs_width + t], Xs[cola * D + cb]);
+                            cfma(mx, ovs[ra * a.obs_width + t], Xs[lidx<D>(cola, cb)]);
                         }
                         acc += (double)xm.x * mx.x + (double)xm.y * mx.y;
                     }
@@ -839,9 +905,10 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
     stage_generators<D>(tv, g2s, gs);
     ChanHdr* hF = hdr + (HDR ? slot * 3 * KMAX : 0);
     ChanHdr* hB = hF + (HDR ? KMAX : 0);
-    float2* Xs = lds + (long long)slot * (3 * D * D + Cfg<D>::PAD);
+    float2* Xs = lds + (long long)slot * (Cfg<D>::NBUF_GRAPE * D * D + Cfg<D>::PAD);
     float2* Fs = Xs + D * D;
     float2* Ls = Fs + D * D;
+    float2* Rs = Ls + D * D;   // product results (matrix-core products)
     const int len = valid ? (a.n_steps ? a.n_steps[b] : a.N_max) : 0;
     if (tid == 0) nblk = 0;
     __syncthreads();
@@ -869,7 +936,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
     for (int n = 0; n < N; ++n) {
         const bool active = valid && n < len;
         if (active && n % C == 0) save_block<D>(x, ck + (long long)(n / C) * D * D, ti, tj);
-        step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, HDR || lt == 0, lt, ti, tj, dph, dph64, hF, g2s, gs);
+        step_left<D, Cfg<D>::MFG>(tv, x, Xs, Fs, Rs, ub + n * ustride, drift, active, HDR || lt == 0, lt, ti, tj, dph, dph64, hF, g2s, gs);
     }
     // ---- overlap g = Tr(U_f^dag X_N) / Tr(U_f^dag U_f)
     const float2* Uf = a.U_target + (long long)(valid ? b : 0) * D * D;
@@ -951,7 +1018,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
         if (seg_active) load_block<D>(x, ck + (long long)sgi * D * D, ti, tj);
         for (int n = s0; n < s1; ++n) {
             const bool active = valid && n < len;
-            step_left<D>(tv, x, Xs, Fs, ub + n * ustride, drift, active, false, lt, ti, tj, dph, dph64, hF, g2s, gs);
+            step_left<D, Cfg<D>::MFG>(tv, x, Xs, Fs, Rs, ub + n * ustride, drift, active, false, lt, ti, tj, dph, dph64, hF, g2s, gs);
             if (active) save_block<D>(x, sg + (long long)(n - s0) * D * D, ti, tj);
         }
         for (int s = s1 - 1; s >= s0; --s) {
@@ -970,7 +1037,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
             }
             inst_sync<D>();
             float2 y[TB][TB];
-            if (active) mul_left<D>(y, Xs, Ls, ti, tj);
+            if (active) mul_left<D, Cfg<D>::MFG>(y, Xs, Ls, Rs, ti, tj);
             // traces per channel; lane 0 completes the gradient of the pending (later) step
             const float* us = ub + (long long)s * ustride;
             for (int k = 0; k < tv.K; ++k) {
@@ -1090,7 +1157,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
                 pend_step = s;
             }
             // L_s = L_{s+1} U_s
-            step_right<D>(tv, l, Ls, Fs, us, drift, active, lt, ti, tj, dpc, dpc64, hs, g2s, gs);
+            step_right<D, Cfg<D>::MFG>(tv, l, Ls, Fs, Rs, us, drift, active, lt, ti, tj, dpc, dpc64, hs, g2s, gs);
         }
     }
     // D_0 = Tr(G Y_0), Y_0 = X_0 L_0 = L_0
@@ -1118,7 +1185,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
 template <int D>
 hipError_t launch_chain(const TView& tv, const SmallChainArgs& a, int ninst, hipStream_t st) {
     constexpr int IPB = Cfg<D>::IPB;
-    const size_t lds = (size_t)IPB * (2 * D * D + Cfg<D>::PAD) * sizeof(float2) +
+    const size_t lds = (size_t)IPB * (Cfg<D>::NBUF_CHAIN * D * D + Cfg<D>::PAD) * sizeof(float2) +
                        (a.obs_out ? (size_t)D * a.obs_width * (sizeof(float2) + sizeof(int)) : 0);
     const void* k = tv.phased ? (const void*)small_chain_kernel<D, 1> : (const void*)small_chain_kernel<D, 0>;
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1134,7 +1201,7 @@ hipError_t launch_chain(const TView& tv, const SmallChainArgs& a, int ninst, hip
 template <int D>
 hipError_t launch_grape(const TView& tv, const SmallGrapeArgs& a, hipStream_t st) {
     constexpr int IPB = Cfg<D>::IPB;
-    const size_t lds = (size_t)IPB * (3 * D * D + Cfg<D>::PAD) * sizeof(float2);
+    const size_t lds = (size_t)IPB * (Cfg<D>::NBUF_GRAPE * D * D + Cfg<D>::PAD) * sizeof(float2);
     const void* k = tv.phased ? (const void*)small_grape_kernel<D, 1> : (const void*)small_grape_kernel<D, 0>;
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
