@@ -76,7 +76,7 @@ struct Cfg {
     // d = 4 kernels were bank conflicts)
     static constexpr int PAD = 4;
     // instances of at least one wave take each step's codes and control pairs from a per-step
-    // header in LDS (ChanHdr)
+    // header in LDS (ChanHdr); so do phased channels at every d (HD below)
     static constexpr bool HDR = TPI >= 64;
     // the products run on the matrix cores (one output quadrant per wave, the result handed to the
     // owning threads through one more LDS buffer): chains at d = 32, 64, GRAPE at d = 32 (at d = 64
@@ -296,6 +296,7 @@ struct ChanHdr {
     float ux, uy;   // the control as given (uy: phased channels)
     double2 rot;    // phased: half_phase(ux, uy) with half-integer generators, else (phi, 0)
 };
+static_assert(sizeof(ChanHdr) == 32, "four float2 of LDS per channel");
 
 // thread lt < K writes channel lt's entry; report: this pass reports non-finite and clamped controls
 template <int D>
@@ -385,9 +386,9 @@ __device__ inline float2 to_f2(double2 e) { return make_float2((float)e.x, (floa
 
 // x <- U_n x with U_n = Z [prod_k R_k] Z^dag V
 // dph: the drift phases of the thread's rows (drift_phases), used when the channels are unphased
-// report: non-finite and clamped controls are reported (by the header's channel threads with HDR,
-// else by the thread that passes it); hd: the instance's step header (HDR); MM: matrix-core products
-template <int D, bool MM>
+// report: non-finite and clamped controls are reported (by the header's channel threads with HD,
+// else by the thread that passes it); hd: the instance's step header (HD); MM: matrix-core products
+template <int D, bool MM, bool HD>
 __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float2* Fs, float2* Rs,
                           const float* us, int drift, bool active, bool report, int lt, int ti, int tj,
                           const float2 (&dph)[Cfg<D>::TB], const double2 (&dph64)[Cfg<D>::TB], ChanHdr* hd,
@@ -395,7 +396,7 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
     constexpr int TB = Cfg<D>::TB;
     const int KK = tv.phased ? 2 : 1;
     double2 P[TB];
-    if constexpr (Cfg<D>::HDR) {
+    if constexpr (HD) {
         // the previous step's header was last read before the barriers of its last slot
         make_header<D>(tv, us, active, report, lt, hd);
         inst_sync<D>();
@@ -438,7 +439,7 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
     const int PE = tv.cache ? 1 : tv.P;
     const int nslot = tv.K * PE;
     auto slot_code = [&](int sl, bool rep) -> int {
-        if constexpr (Cfg<D>::HDR) return hd[sl / PE].q;
+        if constexpr (HD) return hd[sl / PE].q;
         return active ? quantise_one(us + KK * (sl / PE), tv.phased, tv.eps, tv.qmax, nullptr,
                                      rep ? tv.flags : nullptr)
                       : 0;
@@ -486,8 +487,8 @@ __device__ void step_left(const TView& tv, float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], 
 
 // l <- l U_n  (the backward scan), U_n = Z [prod_k R_k] Z^dag V
 // dpc: the drift phases of the thread's columns (drift_phases), used when the channels are unphased
-// hd: the step's header, published by the caller (HDR); MM: matrix-core products
-template <int D, bool MM>
+// hd: the step's header, published by the caller (HD); MM: matrix-core products
+template <int D, bool MM, bool HD>
 __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB], float2* Ls, float2* Fs, float2* Rs,
                            const float* us, int drift, bool active, int lt, int ti, int tj,
                            const float2 (&dpc)[Cfg<D>::TB], const double2 (&dpc64)[Cfg<D>::TB], const ChanHdr* hd,
@@ -496,7 +497,7 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
     const int KK = tv.phased ? 2 : 1;
     // phase rotations exp(i theta_c) of the columns the thread owns
     double2 Pc[TB];
-    if constexpr (Cfg<D>::HDR)
+    if constexpr (HD)
         header_rotations<D>(tv, hd, g2l, gl, active, tj, Pc);
     else
         step_rotations<D>(tv, us, active, tj, Pc);
@@ -515,7 +516,7 @@ __device__ void step_right(const TView& tv, float2 (&l)[Cfg<D>::TB][Cfg<D>::TB],
         const int PE = tv.cache ? 1 : tv.P;
         const int nslot = tv.K * PE;
         auto slot_code = [&](int sl) -> int {
-            if constexpr (Cfg<D>::HDR) return hd[sl / PE].q;
+            if constexpr (HD) return hd[sl / PE].q;
             return active ? quantise_one(us + KK * (sl / PE), tv.phased, tv.eps, tv.qmax, nullptr, nullptr) : 0;
         };
         auto entry_of = [&](int sl, int q) -> const float2* {
@@ -623,9 +624,9 @@ __device__ void reproject(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float
 
 // The phase generators' diagonals (g, and 2g as integers) into LDS for the header kernels: every
 // thread reads them at every step (through these arrays, which the compiler then knows to be LDS).
-template <int D>
+template <int D, bool HD>
 __device__ inline void stage_generators(const TView& tv, signed char* g2s, double* gs) {
-    if constexpr (Cfg<D>::HDR) {
+    if constexpr (HD) {
         if (tv.phased) {
             for (int e = threadIdx.x; e < tv.K * D; e += 256) {
                 gs[e] = tv.g[e];
@@ -653,12 +654,13 @@ __global__ __launch_bounds__(256, (PH == 0 && D <= 16) ? 4 : 1) void small_chain
     const int ti = lt / NT, tj = lt % NT;
     const int inst = blockIdx.x * IPB + slot;
     const bool valid = inst < ninst;
-    constexpr bool HDR = Cfg<D>::HDR;
-    __shared__ ChanHdr hdr[HDR ? IPB * KMAX : 1];
+    constexpr bool HDR = Cfg<D>::HDR || PH == 1;
     __shared__ signed char g2s[HDR ? KMAX * D : 1];
     __shared__ double gs[HDR ? KMAX * D : 1];
-    stage_generators<D>(tv, g2s, gs);
-    ChanHdr* hd = hdr + (HDR ? slot * KMAX : 0);
+    stage_generators<D, HDR>(tv, g2s, gs);
+    // step headers (K per instance) after the instances' buffers, then the observable's row lists
+    ChanHdr* hdr = reinterpret_cast<ChanHdr*>(lds + (long long)IPB * (Cfg<D>::NBUF_CHAIN * D * D + Cfg<D>::PAD));
+    ChanHdr* hd = hdr + (HDR ? slot * tv.K : 0);
     float2* Xs = lds + (long long)slot * (Cfg<D>::NBUF_CHAIN * D * D + Cfg<D>::PAD);
     float2* Fs = Xs + D * D;
     float2* Rs = Fs + D * D;   // product results (matrix-core products)
@@ -696,7 +698,7 @@ __global__ __launch_bounds__(256, (PH == 0 && D <= 16) ? 4 : 1) void small_chain
 
     double obs_norm = 1.0;
     // the observable's row lists, once per workgroup, after the instances' buffers
-    float2* ovs = lds + (long long)IPB * (Cfg<D>::NBUF_CHAIN * D * D + Cfg<D>::PAD);
+    float2* ovs = reinterpret_cast<float2*>(hdr + (HDR ? IPB * tv.K : 0));
     int* ocs = reinterpret_cast<int*>(ovs + (a.obs_out ? D * a.obs_width : 0));
     if (a.obs_out) {
         for (int e = tid; e < D * a.obs_width; e += 256) {
@@ -780,7 +782,7 @@ __global__ __launch_bounds__(256, (PH == 0 && D <= 16) ? 4 : 1) void small_chain
     drift_phases<D>(tv, drift, ti, dph, dph64);
     for (int n = 0; n < N; ++n) {
         const bool active = valid && n < len;
-        step_left<D, Cfg<D>::MF>(tv, x, Xs, Fs, Rs, ub + (long long)n * tv.K * KK, drift, active, HDR || lt == 0, lt, ti, tj, dph, dph64, hd, g2s, gs);
+        step_left<D, Cfg<D>::MF, HDR>(tv, x, Xs, Fs, Rs, ub + (long long)n * tv.K * KK, drift, active, HDR || lt == 0, lt, ti, tj, dph, dph64, hd, g2s, gs);
         if (a.reproject_every > 0 && !a.compose && ((a.step_offset + n + 1) % a.reproject_every) == 0)
             reproject<D>(x, Xs, Fs, Rs, active, ti, tj, red, tv.flags, lt == 0);
         if (a.X_prefix && active) {
@@ -897,14 +899,15 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
     const int ti = lt / NT, tj = lt % NT;
     const int b = blockIdx.x * IPB + slot;
     const bool valid = b < a.B;
-    constexpr bool HDR = Cfg<D>::HDR;
-    // step headers per instance: [0] the forward and recompute scans, [1 + (s & 1)] backward step s
-    __shared__ ChanHdr hdr[HDR ? IPB * 3 * KMAX : 1];
+    constexpr bool HDR = Cfg<D>::HDR || PH == 1;
     __shared__ signed char g2s[HDR ? KMAX * D : 1];
     __shared__ double gs[HDR ? KMAX * D : 1];
-    stage_generators<D>(tv, g2s, gs);
-    ChanHdr* hF = hdr + (HDR ? slot * 3 * KMAX : 0);
-    ChanHdr* hB = hF + (HDR ? KMAX : 0);
+    stage_generators<D, HDR>(tv, g2s, gs);
+    // step headers per instance, after the instances' buffers: [0] the forward and recompute scans,
+    // [1 + (s & 1)] backward step s, K channels each
+    ChanHdr* hdr = reinterpret_cast<ChanHdr*>(lds + (long long)IPB * (Cfg<D>::NBUF_GRAPE * D * D + Cfg<D>::PAD));
+    ChanHdr* hF = hdr + (HDR ? slot * 3 * tv.K : 0);
+    ChanHdr* hB = hF + (HDR ? tv.K : 0);
     float2* Xs = lds + (long long)slot * (Cfg<D>::NBUF_GRAPE * D * D + Cfg<D>::PAD);
     float2* Fs = Xs + D * D;
     float2* Ls = Fs + D * D;
@@ -936,7 +939,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
     for (int n = 0; n < N; ++n) {
         const bool active = valid && n < len;
         if (active && n % C == 0) save_block<D>(x, ck + (long long)(n / C) * D * D, ti, tj);
-        step_left<D, Cfg<D>::MFG>(tv, x, Xs, Fs, Rs, ub + n * ustride, drift, active, HDR || lt == 0, lt, ti, tj, dph, dph64, hF, g2s, gs);
+        step_left<D, Cfg<D>::MFG, HDR>(tv, x, Xs, Fs, Rs, ub + n * ustride, drift, active, HDR || lt == 0, lt, ti, tj, dph, dph64, hF, g2s, gs);
     }
     // ---- overlap g = Tr(U_f^dag X_N) / Tr(U_f^dag U_f)
     const float2* Uf = a.U_target + (long long)(valid ? b : 0) * D * D;
@@ -980,7 +983,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
     auto finalize = [&](int s, int k, double Dr, double Di) {
         const float* us = ub + (long long)s * ustride;
         const double* pk = pb_ + k * 6;
-        const ChanHdr* hs = hB + (s & 1) * KMAX;   // step s's header (HDR), intact until step s - 2
+        const ChanHdr* hs = hB + (s & 1) * tv.K;   // step s's header (HDR), intact until step s - 2
         const int q = HDR ? hs[k].q : quantise_one(us + KK * k, tv.phased, tv.eps, tv.qmax, nullptr, nullptr);
         auto im_gc = [&](double zr, double zi) { return gr * zi - gi * zr; };   // Im(conj(g) z)
         if (!tv.phased) {
@@ -1018,14 +1021,14 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
         if (seg_active) load_block<D>(x, ck + (long long)sgi * D * D, ti, tj);
         for (int n = s0; n < s1; ++n) {
             const bool active = valid && n < len;
-            step_left<D, Cfg<D>::MFG>(tv, x, Xs, Fs, Rs, ub + n * ustride, drift, active, false, lt, ti, tj, dph, dph64, hF, g2s, gs);
+            step_left<D, Cfg<D>::MFG, HDR>(tv, x, Xs, Fs, Rs, ub + n * ustride, drift, active, false, lt, ti, tj, dph, dph64, hF, g2s, gs);
             if (active) save_block<D>(x, sg + (long long)(n - s0) * D * D, ti, tj);
         }
         for (int s = s1 - 1; s >= s0; --s) {
             const bool active = valid && s < len;
             // step s's header: its buffer last served step s + 2, whose readers are all past the
             // barriers of step s + 1; the barriers below publish it
-            ChanHdr* hs = hB + (s & 1) * KMAX;
+            ChanHdr* hs = hB + (s & 1) * tv.K;
             if constexpr (HDR) make_header<D>(tv, ub + (long long)s * ustride, active, false, lt, hs);
             // Y_{s+1} = X_{s+1} L_{s+1}
             inst_sync<D>();
@@ -1157,7 +1160,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
                 pend_step = s;
             }
             // L_s = L_{s+1} U_s
-            step_right<D, Cfg<D>::MFG>(tv, l, Ls, Fs, Rs, us, drift, active, lt, ti, tj, dpc, dpc64, hs, g2s, gs);
+            step_right<D, Cfg<D>::MFG, HDR>(tv, l, Ls, Fs, Rs, us, drift, active, lt, ti, tj, dpc, dpc64, hs, g2s, gs);
         }
     }
     // D_0 = Tr(G Y_0), Y_0 = X_0 L_0 = L_0
@@ -1185,7 +1188,9 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
 template <int D>
 hipError_t launch_chain(const TView& tv, const SmallChainArgs& a, int ninst, hipStream_t st) {
     constexpr int IPB = Cfg<D>::IPB;
+    const bool hdr = Cfg<D>::HDR || tv.phased;
     const size_t lds = (size_t)IPB * (Cfg<D>::NBUF_CHAIN * D * D + Cfg<D>::PAD) * sizeof(float2) +
+                       (hdr ? (size_t)IPB * tv.K * sizeof(ChanHdr) : 0) +
                        (a.obs_out ? (size_t)D * a.obs_width * (sizeof(float2) + sizeof(int)) : 0);
     const void* k = tv.phased ? (const void*)small_chain_kernel<D, 1> : (const void*)small_chain_kernel<D, 0>;
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1201,7 +1206,9 @@ hipError_t launch_chain(const TView& tv, const SmallChainArgs& a, int ninst, hip
 template <int D>
 hipError_t launch_grape(const TView& tv, const SmallGrapeArgs& a, hipStream_t st) {
     constexpr int IPB = Cfg<D>::IPB;
-    const size_t lds = (size_t)IPB * (Cfg<D>::NBUF_GRAPE * D * D + Cfg<D>::PAD) * sizeof(float2);
+    const bool hdr = Cfg<D>::HDR || tv.phased;
+    const size_t lds = (size_t)IPB * (Cfg<D>::NBUF_GRAPE * D * D + Cfg<D>::PAD) * sizeof(float2) +
+                       (hdr ? (size_t)IPB * 3 * tv.K * sizeof(ChanHdr) : 0);
     const void* k = tv.phased ? (const void*)small_grape_kernel<D, 1> : (const void*)small_grape_kernel<D, 0>;
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
