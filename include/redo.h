@@ -177,6 +177,13 @@ size_t redo_workspace_bytes(redo_table table, int32_t op, int32_t B, int32_t N_m
  * (0 = automatic). */
 size_t redo_grape_workspace_bytes(redo_table table, int32_t B, int32_t N_max, int32_t checkpoint_every);
 
+/* The smallest workspace redo_grape_fidelity_grad accepts for the same call
+ * (Sec. III, GRAPE through REDO): at d <= 64 the checkpoints, one recomputed
+ * segment and the pending traces, without the precomposed step propagators
+ * (each scan step is then built from its factors); at d >= 128 the same as
+ * redo_grape_workspace_bytes.  0 on invalid arguments. */
+size_t redo_grape_workspace_min_bytes(redo_table table, int32_t B, int32_t N_max, int32_t checkpoint_every);
+
 /*
  * Coarse graining alone (Sec. II, Eq. cgrain): for every (b, n, k) with
  * n < N_max, the code q = min(floor(Omega/eps + 1/2), b^P - 1) with
@@ -360,7 +367,16 @@ redo_status redo_unitary_fidelity(int32_t d, int32_t B, const float* U_target, c
  * of X_n and L_n^dag.  With checkpoint_every = C > 1 only every C-th state is
  * kept and each segment is recomputed during the backward scan.  0 selects 1
  * when that workspace is at most 48 GiB (d >= 128), else ceil(sqrt(N_max));
- * at d <= 64 the fused kernel always checkpoints (0: ceil(sqrt(N_max))).
+ * at d <= 64 the fused kernel always checkpoints (0: ceil(sqrt(N_max))).  At
+ * d <= 64, with the workspace that redo_workspace_bytes / redo_grape_workspace_bytes
+ * report, every step's propagator U_n (B N_max d^2 complex entries, when that
+ * is at most 4 GiB and the batch's threads, B (d/2)^2 below d = 64 and 256 B at
+ * d = 64, are at most 65,536: batches too small to fill the GPU) is composed
+ * first, all (instance, step) pairs in parallel, and each scan step is then one
+ * product; a workspace of only the checkpoints,
+ * one segment and the pending traces (the allocation-free entry's scratch) is
+ * also accepted, and each scan step is then built from its factors (the same
+ * result up to FP32 rounding).
  *   U_target  c64 [B][d][d];  fidelity double [B];  overlap c128 [B] or NULL
  *   grad      float, same layout as u (entries of steps >= n_steps[b] are set to 0)
  * Workspace: redo_workspace_bytes(table, REDO_OP_GRAPE, B, N_max).
@@ -479,7 +495,8 @@ redo_status redo_unitarity_report(redo_table table, double* max_drift, int64_t* 
  * that forbid hipMalloc): d <= 64 only (REDO_ERR_UNSUPPORTED otherwise), same
  * arguments, results and errors as redo_grape_fidelity_grad minus the
  * workspace.  The fused kernel's scratch (checkpoints, one recomputed segment,
- * pending traces: redo_grape_workspace_bytes of the same call) comes from a
+ * pending traces; each scan step built from its factors, no precomposed step
+ * propagators) comes from a
  * file-scope device array of redo_grape_noalloc_max_bytes() = 64 MiB, one copy
  * per GPU held until the process ends; a call that needs more is refused with
  * REDO_ERR_UNSUPPORTED before anything is launched.  Nothing in the array needs

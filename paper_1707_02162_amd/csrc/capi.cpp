@@ -726,7 +726,9 @@ size_t redo_workspace_bytes(redo_table t, int32_t op, int32_t B, int32_t N_max) 
         switch (op) {
             case REDO_OP_COMPOSE:
             case REDO_OP_CHAIN: return 0;
-            case REDO_OP_GRAPE: return small_grape_workspace_bytes(d, t->desc.K, B, N_max, ceil_sqrt(N_max));
+            case REDO_OP_GRAPE:
+                return small_grape_workspace_bytes(d, t->desc.K, B, N_max, ceil_sqrt(N_max)) +
+                       small_grape_precomposed_bytes(d, B, N_max);
             default: return 0;
         }
     }
@@ -734,6 +736,16 @@ size_t redo_workspace_bytes(redo_table t, int32_t op, int32_t B, int32_t N_max) 
 }
 
 size_t redo_grape_workspace_bytes(redo_table t, int32_t B, int32_t N_max, int32_t checkpoint_every) {
+    if (!t || B < 1 || N_max < 1 || checkpoint_every < 0) return 0;
+    const int d = t->desc.d;
+    if (small_dim(d)) {
+        const long long C = checkpoint_every > 0 ? checkpoint_every : ceil_sqrt(N_max);
+        return small_grape_workspace_bytes(d, t->desc.K, B, N_max, C) + small_grape_precomposed_bytes(d, B, N_max);
+    }
+    return large_grape_workspace_bytes(t, B, N_max, checkpoint_every);
+}
+
+size_t redo_grape_workspace_min_bytes(redo_table t, int32_t B, int32_t N_max, int32_t checkpoint_every) {
     if (!t || B < 1 || N_max < 1 || checkpoint_every < 0) return 0;
     const int d = t->desc.d;
     if (small_dim(d)) {
@@ -1042,6 +1054,11 @@ redo_status redo_grape_fidelity_grad(redo_table t, int32_t precision, const floa
             const size_t mats = sizeof(float2) * (size_t)t->desc.d * t->desc.d * (size_t)B * (size_t)(nck + C);
             a.pend = reinterpret_cast<double*>(static_cast<char*>(workspace) + ((mats + 255) & ~size_t(255)));
         }
+        // with room for every step's propagator, they are composed first (in parallel over steps) and
+        // each scan step is one product; with the minimum workspace each step is built from its factors
+        const size_t pre = small_grape_precomposed_bytes(t->desc.d, B, N_max);
+        if (pre > 0 && workspace_bytes >= need + pre)
+            a.Up = reinterpret_cast<float2*>(static_cast<char*>(workspace) + ((need + 255) & ~size_t(255)));
         REDO_HIP(small_grape(t, a, hs));
         return REDO_OK;
     }

@@ -243,10 +243,18 @@ struct SmallGrapeArgs {
     float2* seg;             // workspace [B][checkpoint_every][d][d]
     double* pend;            // workspace [B][K][6]: traces of the step whose gradient waits for the next D
     int n_ckpt;
+    float2* Up;              // workspace [B][N_max][d][d]: the step propagators composed beforehand, or null
 };
 hipError_t small_grape(const redo_table_s* t, const SmallGrapeArgs& a, hipStream_t st);
 // workspace of the fused d <= 64 GRAPE kernel (checkpoints, one segment, pending traces)
 size_t small_grape_workspace_bytes(int d, int K, long long B, long long N_max, long long C);
+// the further workspace of the precomposed form (every step's U_n, 256-byte aligned start), 0 when
+// it would exceed SMALL_PRECOMPOSED_MAX, or when the batch's threads exceed
+// SMALL_PRECOMPOSED_MAX_THREADS (one wave per SIMD on 256 CUs); the fused form then builds
+// each step from its factors
+constexpr size_t SMALL_PRECOMPOSED_MAX = size_t(4) << 30;
+constexpr long long SMALL_PRECOMPOSED_MAX_THREADS = 256LL * 4 * 64;
+size_t small_grape_precomposed_bytes(int d, long long B, long long N_max);
 
 // fidelity reduction, FP64
 hipError_t unitary_fidelity(int d, int B, const float2* Uf, const float2* U, double2* overlap,

@@ -669,7 +669,7 @@ __global__ __launch_bounds__(256, (PH == 0 && D <= 16) ? 4 : 1) void small_chain
         if (a.compose) {
             b = inst / a.N_max;
             n0 = inst % a.N_max;
-            len = 1;
+            len = (a.n_steps && n0 >= a.n_steps[b]) ? 0 : 1;   // steps past a ragged length: none
         } else {
             b = inst;
             len = a.n_steps ? a.n_steps[b] : a.N_max;
@@ -865,6 +865,36 @@ __global__ __launch_bounds__(256, (PH == 0 && D <= 16) ? 4 : 1) void small_chain
 }
 
 // ---------------------------------------------------------------- GRAPE kernel
+// With the step propagators composed beforehand (one chain launch in compose mode, every
+// (instance, step) in parallel), a scan step is one product with the stored U_n:
+// x <- U_n x (forward and recompute) or l <- l U_n (backward).
+template <int D, bool MM>
+__device__ inline void pre_left(float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], float2* Xs, float2* Fs, float2* Rs,
+                                const float2* Un, bool active, int lt, int ti, int tj) {
+    FactorRegs<D> fr;
+    if (active) fetch_factor<D>(fr, Un, lt);
+    inst_sync<D>();
+    if (active) {
+        put_factor<D>(Fs, fr, false, lt);
+        store_block<D>(Xs, x, ti, tj);
+    }
+    inst_sync<D>();
+    if (active) mul_left<D, MM>(x, Fs, Xs, Rs, ti, tj);
+}
+template <int D, bool MM>
+__device__ inline void pre_right(float2 (&l)[Cfg<D>::TB][Cfg<D>::TB], float2* Ls, float2* Fs, float2* Rs,
+                                 const float2* Un, bool active, int lt, int ti, int tj) {
+    FactorRegs<D> fr;
+    if (active) fetch_factor<D>(fr, Un, lt);
+    inst_sync<D>();
+    if (active) {
+        put_factor<D>(Fs, fr, false, lt);
+        store_block<D>(Ls, l, ti, tj);
+    }
+    inst_sync<D>();
+    if (active) mul_left<D, MM>(l, Ls, Fs, Rs, ti, tj);
+}
+
 // Per instance: forward chain with checkpoints, overlap g, then for every
 // checkpoint segment from the last: recompute its states, and walk it
 // backwards with L_N = U_f^dag, Y_n = X_n L_n, L_{n-1} = L_n U_n.
@@ -885,7 +915,8 @@ __device__ inline void save_block(const float2 (&x)[Cfg<D>::TB][Cfg<D>::TB], flo
         for (int c = 0; c < TB; ++c) dst[(ti + NT * r) * D + tj + NT * c] = x[r][c];
 }
 
-template <int D, int PH>
+// PRE: the step propagators are in a.Up (pre_left / pre_right), else built from the factors
+template <int D, int PH, bool PRE>
 __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrapeArgs a) {
     TView tv = tv_in;
     tv.phased = PH;
@@ -939,7 +970,10 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
     for (int n = 0; n < N; ++n) {
         const bool active = valid && n < len;
         if (active && n % C == 0) save_block<D>(x, ck + (long long)(n / C) * D * D, ti, tj);
-        step_left<D, Cfg<D>::MFG, HDR>(tv, x, Xs, Fs, Rs, ub + n * ustride, drift, active, HDR || lt == 0, lt, ti, tj, dph, dph64, hF, g2s, gs);
+        if constexpr (PRE)
+            pre_left<D, Cfg<D>::MFG>(x, Xs, Fs, Rs, a.Up + ((long long)b * a.N_max + n) * D * D, active, lt, ti, tj);
+        else
+            step_left<D, Cfg<D>::MFG, HDR>(tv, x, Xs, Fs, Rs, ub + n * ustride, drift, active, HDR || lt == 0, lt, ti, tj, dph, dph64, hF, g2s, gs);
     }
     // ---- overlap g = Tr(U_f^dag X_N) / Tr(U_f^dag U_f)
     const float2* Uf = a.U_target + (long long)(valid ? b : 0) * D * D;
@@ -1021,7 +1055,10 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
         if (seg_active) load_block<D>(x, ck + (long long)sgi * D * D, ti, tj);
         for (int n = s0; n < s1; ++n) {
             const bool active = valid && n < len;
-            step_left<D, Cfg<D>::MFG, HDR>(tv, x, Xs, Fs, Rs, ub + n * ustride, drift, active, false, lt, ti, tj, dph, dph64, hF, g2s, gs);
+            if constexpr (PRE)
+                pre_left<D, Cfg<D>::MFG>(x, Xs, Fs, Rs, a.Up + ((long long)b * a.N_max + n) * D * D, active, lt, ti, tj);
+            else
+                step_left<D, Cfg<D>::MFG, HDR>(tv, x, Xs, Fs, Rs, ub + n * ustride, drift, active, false, lt, ti, tj, dph, dph64, hF, g2s, gs);
             if (active) save_block<D>(x, sg + (long long)(n - s0) * D * D, ti, tj);
         }
         for (int s = s1 - 1; s >= s0; --s) {
@@ -1160,7 +1197,10 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
                 pend_step = s;
             }
             // L_s = L_{s+1} U_s
-            step_right<D, Cfg<D>::MFG, HDR>(tv, l, Ls, Fs, Rs, us, drift, active, lt, ti, tj, dpc, dpc64, hs, g2s, gs);
+            if constexpr (PRE)
+                pre_right<D, Cfg<D>::MFG>(l, Ls, Fs, Rs, a.Up + ((long long)b * a.N_max + s) * D * D, active, lt, ti, tj);
+            else
+                step_right<D, Cfg<D>::MFG, HDR>(tv, l, Ls, Fs, Rs, us, drift, active, lt, ti, tj, dpc, dpc64, hs, g2s, gs);
         }
     }
     // D_0 = Tr(G Y_0), Y_0 = X_0 L_0 = L_0
@@ -1209,14 +1249,35 @@ hipError_t launch_grape(const TView& tv, const SmallGrapeArgs& a, hipStream_t st
     const bool hdr = Cfg<D>::HDR || tv.phased;
     const size_t lds = (size_t)IPB * (Cfg<D>::NBUF_GRAPE * D * D + Cfg<D>::PAD) * sizeof(float2) +
                        (hdr ? (size_t)IPB * 3 * tv.K * sizeof(ChanHdr) : 0);
-    const void* k = tv.phased ? (const void*)small_grape_kernel<D, 1> : (const void*)small_grape_kernel<D, 0>;
+    const bool pre = a.Up != nullptr;
+    if (pre) {
+        // every step's propagator U_n, all (instance, step) pairs in parallel
+        SmallChainArgs c{};
+        c.u = a.u;
+        c.n_steps = a.n_steps;
+        c.B = a.B;
+        c.N_max = a.N_max;
+        c.compose = 1;
+        c.X_out = a.Up;
+        hipError_t e = launch_chain<D>(tv, c, a.B * a.N_max, st);
+        if (e != hipSuccess) return e;
+    }
+    const void* k = tv.phased ? (pre ? (const void*)small_grape_kernel<D, 1, true> : (const void*)small_grape_kernel<D, 1, false>)
+                              : (pre ? (const void*)small_grape_kernel<D, 0, true> : (const void*)small_grape_kernel<D, 0, false>);
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int grid = (a.B + IPB - 1) / IPB;
-    if (tv.phased)
-        hipLaunchKernelGGL((small_grape_kernel<D, 1>), dim3(grid), dim3(256), lds, st, tv, a);
-    else
-        hipLaunchKernelGGL((small_grape_kernel<D, 0>), dim3(grid), dim3(256), lds, st, tv, a);
+    if (tv.phased) {
+        if (pre)
+            hipLaunchKernelGGL((small_grape_kernel<D, 1, true>), dim3(grid), dim3(256), lds, st, tv, a);
+        else
+            hipLaunchKernelGGL((small_grape_kernel<D, 1, false>), dim3(grid), dim3(256), lds, st, tv, a);
+    } else {
+        if (pre)
+            hipLaunchKernelGGL((small_grape_kernel<D, 0, true>), dim3(grid), dim3(256), lds, st, tv, a);
+        else
+            hipLaunchKernelGGL((small_grape_kernel<D, 0, false>), dim3(grid), dim3(256), lds, st, tv, a);
+    }
     return hipGetLastError();
 }
 
@@ -1240,6 +1301,26 @@ size_t small_grape_workspace_bytes(int d, int K, long long B, long long N_max, l
     const long long nck = (N_max + C - 1) / C;
     const size_t mats = sizeof(float2) * (size_t)d * d * (size_t)B * (size_t)(nck + C);
     return ((mats + 255) & ~size_t(255)) + sizeof(double) * (size_t)B * K * 6;
+}
+
+size_t small_grape_precomposed_bytes(int d, long long B, long long N_max) {
+    // only where the fused kernel leaves the chip mostly idle (at most one wave per SIMD across
+    // the instances): there its sequence of dependent per-factor products is the time, and the
+    // composition, parallel over steps, removes it; a batch that fills the chip gains nothing
+    // from the extra pass and the stored propagators' memory traffic
+    int tpi = 0;
+    switch (d) {
+        case 2: tpi = Cfg<2>::TPI; break;
+        case 4: tpi = Cfg<4>::TPI; break;
+        case 8: tpi = Cfg<8>::TPI; break;
+        case 16: tpi = Cfg<16>::TPI; break;
+        case 32: tpi = Cfg<32>::TPI; break;
+        case 64: tpi = Cfg<64>::TPI; break;
+        default: return 0;
+    }
+    if ((double)B * tpi > (double)SMALL_PRECOMPOSED_MAX_THREADS) return 0;
+    const double bytes = (double)sizeof(float2) * d * d * (double)B * (double)N_max;
+    return bytes <= (double)SMALL_PRECOMPOSED_MAX ? 256 + (size_t)bytes : 0;
 }
 
 hipError_t small_grape(const redo_table_s* t, const SmallGrapeArgs& a, hipStream_t st) {

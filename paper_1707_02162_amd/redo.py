@@ -34,6 +34,7 @@ _SIG = {
     "redo_cache_split_bf16": (_I, [_P, _I, _P]),
     "redo_workspace_bytes": (ctypes.c_size_t, [_P, _I, _I, _I]),
     "redo_grape_workspace_bytes": (ctypes.c_size_t, [_P, _I, _I, _I]),
+    "redo_grape_workspace_min_bytes": (ctypes.c_size_t, [_P, _I, _I, _I]),
     "redo_quantise": (_I, [_P, _P, _I, _I, _P, _P, _P]),
     "redo_compose_steps": (_I, [_P, _I, _P, _I, _I, _P, _P, ctypes.c_size_t, _P]),
     "redo_chain_propagator": (_I, [_P, _I, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _P, _I, _P, _P,
@@ -330,8 +331,11 @@ class RedoTable:
                                      _ptr(ws), ws.numel(), _stream()))
         return U, obs
 
-    def grape(self, u, U_target, n_steps=None, checkpoint_every: int = 0, precision: int = PREC_F32):
-        """Returns (fidelity float64 [B], overlap complex128 [B], grad float32 like u)."""
+    def grape(self, u, U_target, n_steps=None, checkpoint_every: int = 0, precision: int = PREC_F32,
+              precompose: bool = True):
+        """Returns (fidelity float64 [B], overlap complex128 [B], grad float32 like u).
+        precompose=False passes the smallest workspace (d <= 64: every scan step built
+        from its factors instead of from the precomposed step propagators)."""
         ut = self._u(u)
         B, N = ut.shape[:2]
         ns = None if n_steps is None else _dev(n_steps, torch.int32, self.device)
@@ -339,7 +343,8 @@ class RedoTable:
         F = torch.empty(B, dtype=torch.float64, device=self.device)
         ov = torch.empty(B, dtype=torch.complex128, device=self.device)
         grad = torch.empty_like(ut)
-        nbytes = lib().redo_grape_workspace_bytes(self._h, B, N, checkpoint_every)
+        size = lib().redo_grape_workspace_bytes if precompose else lib().redo_grape_workspace_min_bytes
+        nbytes = size(self._h, B, N, checkpoint_every)
         ws = torch.empty(max(int(nbytes), 16), dtype=torch.uint8, device=self.device)
         _check(lib().redo_grape_fidelity_grad(self._h, precision, _ptr(ut), _ptr(ns), B, N, _ptr(Uf),
                                               checkpoint_every, _ptr(F), _ptr(ov), _ptr(grad), _ptr(ws),

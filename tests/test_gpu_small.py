@@ -314,14 +314,45 @@ def test_grape_checkpoint_interval_does_not_change_results():
     assert torch.equal(g1, g2) and torch.equal(g1, g3) and torch.equal(F1, F3)
 
 
-def test_grape_fidelity_matches_chain_fidelity():
+@pytest.mark.parametrize("precompose", [False, True])
+def test_grape_fidelity_matches_chain_fidelity(precompose):
+    """Built from its factors, the GRAPE forward scan is the chain's arithmetic: equal
+    fidelity up to FP64 summation order.  With the step propagators composed first the
+    factors are multiplied together before they meet the state (a different FP32
+    rounding order of the same product, Sec. III, Eq. propUn): equal within FID_TOL."""
     p = W.c5_four_qubit(B=4, N=100)
     t = table(p)
     u, Uf = torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda()
-    F, ov, _ = t.grape(u, Uf)
+    F, ov, _ = t.grape(u, Uf, precompose=precompose)
     U, _, _ = t.chain(u)
     ov2, F2 = R().unitary_fidelity(Uf, U)
-    assert torch.allclose(F, F2, atol=1e-12) and torch.allclose(ov, ov2, atol=1e-12)
+    tol = FID_TOL if precompose else 1e-12
+    assert torch.allclose(F, F2, atol=tol) and torch.allclose(ov, ov2, atol=tol)
+
+
+@pytest.mark.parametrize("which", ["c1", "c4", "c2"])
+def test_grape_precomposed_and_factor_forms_agree(which):
+    """The two forms of the fused GRAPE (step propagators composed first, all steps in
+    parallel; or each scan step built from its factors) against each other and the
+    oracle: d = 4 (two phased channels), d = 32 (five, ragged) and d = 64 (one
+    collective channel, checkpoints every 5 steps)."""
+    if which == "c1":
+        p, ck, ns = W.c1_two_spin(B=3, N=120), 0, None
+    elif which == "c4":
+        p, ck = W.c4_batched_grape(B=4, n_min=60, n_max=140), 0
+        ns = torch.tensor(p.n_steps)
+    else:
+        p, ck, ns = W.c2_six_qubit(B=2, N=60), 5, None
+    t = table(p)
+    t.cache_levels()
+    u, Uf = torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda()
+    F1, ov1, g1 = t.grape(u, Uf, n_steps=ns, checkpoint_every=ck, precompose=True)
+    F0, ov0, g0 = t.grape(u, Uf, n_steps=ns, checkpoint_every=ck, precompose=False)
+    assert torch.allclose(F1, F0, atol=FID_TOL) and torch.allclose(ov1, ov0, atol=1e-5)
+    for b in range(p.B):
+        assert torch.linalg.norm(g1[b] - g0[b]) <= GRAD_TOL * torch.linalg.norm(g0[b])
+    tab = O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    _grape_check(p, tab, F1.cpu().numpy(), ov1.cpu().numpy(), g1.cpu().numpy(), range(min(p.B, 2)))
 
 
 def test_autograd_function_backward():

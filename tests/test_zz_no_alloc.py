@@ -1,8 +1,9 @@
 """The allocation-free GRAPE entry point (d <= 64: scratch in a file-scope device
-array) against redo_grape_fidelity_grad with a caller workspace, through the C
-ABI: two calls in a row, the second with a smaller input, bit for bit (same
-kernel, same checkpoint schedule, same summation order); sizes beyond the
-array are refused on the host."""
+array) against redo_grape_fidelity_grad with the smallest caller workspace
+(redo_grape_workspace_min_bytes: each scan step built from its factors, as the
+allocation-free entry does), through the C ABI: two calls in a row, the second
+with a smaller input, bit for bit (same kernel, same checkpoint schedule, same
+summation order); sizes beyond the array are refused on the host."""
 import numpy as np
 import pytest
 import torch
@@ -48,7 +49,7 @@ def test_noalloc_grape_equals_workspace_entry_two_calls():
         print(f"[no-alloc] B={uu.shape[0]} N={uu.shape[1]} checkpoint_every={ck}", flush=True)
         st, F, ov, g = call_noalloc(t, uu, ff, nn, ck)
         assert st == 0, redo.lib().redo_last_error().decode()
-        F0, ov0, g0 = t.grape(uu, ff, n_steps=nn, checkpoint_every=ck)
+        F0, ov0, g0 = t.grape(uu, ff, n_steps=nn, checkpoint_every=ck, precompose=False)
         torch.cuda.synchronize()
         assert torch.equal(F, F0)
         assert torch.equal(ov, ov0)
