@@ -438,7 +438,8 @@ def bench_small(args, redo, W, torch):
                     "ceil(sqrt N) steps" % total,
         "iters_per_s": 1.0 / elc, "ms_per_iter": 1e3 * elc, "system_steps_per_s": total / elc,
         "achieved_tflops": cflops / elc / 1e12, "frac": cflops / elc / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
-        "note": "one workgroup per system: 64 workgroups on 256 compute units, latency-bound"}
+        "note": "step propagators composed first (all system-steps in parallel), then one workgroup per system "
+                "scans them: 64 workgroups on 256 compute units, latency-bound"}
     log(f"[bench] d=32 batched GRAPE {1.0 / elc:.3g} it/s")
     del table
     return out
