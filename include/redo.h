@@ -513,7 +513,7 @@ redo_status redo_grape_fidelity_grad_noalloc(redo_table table, int32_t precision
 /*
  * ---- Learned warm start (not part of the paper's method) ----
  * A three-layer perceptron maps a target unitary to initial control amplitudes
- * for a REDO-GRAPE run (plain REDO-GRAPE remains the fallback and the judge of
+ * for a REDO-GRAPE run (plain REDO-GRAPE remains the fallback and the arbiter of
  * its fidelity):  h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), y = tanh(W3 h2 + b3).
  * Weights and activations enter the products as BF16 (round to nearest even),
  * products accumulate in FP32 on the matrix cores.

@@ -186,11 +186,11 @@ __device__ inline void kron_exchange(float2 (&v)[KRON_VALS], float2* buf, int re
     __syncthreads();
 }
 
-// One step for every instance: workgroup = (instance, strip of SW columns).  Round 0
+// One step for every instance: workgroup = (instance, strip of SW columns).  Pass 0
 // reads the strip from HBM with register bits = row bits 0..VB-1, applies the pre
-// scaling and spins 0..VB-1, and parks the strip in LDS; round r takes row bits
+// scaling and spins 0..VB-1, and parks the strip in LDS; pass r takes row bits
 // lo_r .. lo_r + VB - 1 (lo_r = min(VB r, n - VB)) and applies spins VB r .. VB r + VB - 1;
-// the last round applies the post scaling and writes the strip back in place.
+// the last pass applies the post scaling and writes the strip back in place.
 // 64 KiB of LDS per workgroup: two workgroups (four waves per SIMD) per CU.
 template <int D>
 __global__ __launch_bounds__(KRON_NT, 4) void kron_step_kernel(float2* X0, float2* X1, const int* loc,

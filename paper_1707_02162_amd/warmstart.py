@@ -11,7 +11,7 @@ solutions for the same target, and a least-squares fit averages them into
 nothing useful; `--labels grape` keeps that variant).  Plain REDO-GRAPE stays
 both the fallback (a random start is used whenever it starts better than the
 network's proposal, and after a network start that misses the goal within the
-budget) and the judge: every reported fidelity is the library's REDO
+budget) and the arbiter: every reported fidelity is the library's REDO
 fidelity.
 
 Every arithmetic step runs in libredo.so: the network's forward and backward
