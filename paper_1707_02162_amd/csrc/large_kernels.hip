@@ -630,8 +630,11 @@ __global__ __launch_bounds__(NT, NT / 128) void observable_walsh_kernel(int d, i
                                                                         const int* n_steps, int step,
                                                                         double* partial) {
     constexpr int SW = 8, CPL = SW / LPR, NCH = CPL / 2, RPP = NT / LPR;
-    extern __shared__ float2 strip[];   // [d][8], 16-byte chunks swizzled (mx8_off)
-    __shared__ double red[NT];
+    // LPR = 1: rows of 10 float2 (80 bytes: the 16 rows that one pass of 16-byte reads covers
+    // start 20 banks apart, all distinct, so lanes read the same chunk position of their rows
+    // without conflicts, at fixed offsets); else [d][8] with swizzled 16-byte chunks (mx8_off)
+    constexpr int RS = LPR == 1 ? 10 : 8;
+    extern __shared__ float2 strip[];   // then, LPR > 1, NT doubles for the reduction
     const int nstrip = d / SW;
     const long long bid = xcd_local(blockIdx.x, gridDim.x);
     const int i = (int)(bid / nstrip), sidx = (int)(bid % nstrip);
@@ -651,7 +654,12 @@ __global__ __launch_bounds__(NT, NT / 128) void observable_walsh_kernel(int d, i
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int e = base + u * NT + tid;
-            if (e < n) strip[mx8_off(e / SW, e % SW)] = r[u];
+            if (e < n) {
+                if constexpr (LPR == 1)
+                    strip[(e / SW) * RS + e % SW] = r[u];
+                else
+                    strip[mx8_off(e / SW, e % SW)] = r[u];
+            }
         }
     }
     __syncthreads();
@@ -675,7 +683,38 @@ __global__ __launch_bounds__(NT, NT / 128) void observable_walsh_kernel(int d, i
         float sm[CPL];
 #pragma unroll
         for (int u = 0; u < CPL; ++u) sm[u] = 0.f;
-        if (m == 0) {
+        if constexpr (LPR == 1) {
+            // a lane owns whole rows: chunk j of row a at fixed offset j of its 80-byte row
+            if (m == 0) {
+                for (int a = tid; a < d; a += NT) {
+                    const float4* xa = strip4 + a * (RS / 2);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float4 x = xa[j];
+                        sm[2 * j] = fmaf(x.x, x.x, fmaf(x.y, x.y, sm[2 * j]));
+                        sm[2 * j + 1] = fmaf(x.z, x.z, fmaf(x.w, x.w, sm[2 * j + 1]));
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < CPL; ++u) acc[u] = fmaf(fv[t].x, sm[u], acc[u]);
+            } else {
+                const int top = 31 - __clz(m);
+                const int low = (1 << top) - 1;
+                for (int pr = tid; pr < d / 2; pr += NT) {
+                    const int a = ((pr & ~low) << 1) | (pr & low);
+                    const float4* xa = strip4 + a * (RS / 2);
+                    const float4* yc = strip4 + (a ^ m) * (RS / 2);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float4 x = xa[j], y = yc[j];
+                        sm[2 * j] = fmaf(x.x, y.x, fmaf(x.y, y.y, sm[2 * j]));
+                        sm[2 * j + 1] = fmaf(x.z, y.z, fmaf(x.w, y.w, sm[2 * j + 1]));
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < CPL; ++u) acc[u] = fmaf(2.f * fv[t].x, sm[u], acc[u]);
+            }
+        } else if (m == 0) {
             for (int a = tid / LPR; a < d; a += RPP) {
 #pragma unroll
                 for (int j = 0; j < NCH; ++j) {
@@ -706,6 +745,10 @@ __global__ __launch_bounds__(NT, NT / 128) void observable_walsh_kernel(int d, i
     double sum = 0.0;
 #pragma unroll
     for (int u = 0; u < CPL; ++u) sum += (double)dj[u] * (double)acc[u];
+    // the reduction after the strip (LPR > 1), or in the strip's own memory once every lane is
+    // done with it (LPR = 1: two 80 KiB workgroups per CU leave no room beside it)
+    double* red = reinterpret_cast<double*>(strip + (LPR == 1 ? 0 : RS * d));
+    if constexpr (LPR == 1) __syncthreads();
     red[tid] = sum;
     __syncthreads();
     for (int st = NT / 2; st > 0; st >>= 1) {
@@ -1453,7 +1496,8 @@ static hipError_t launch_walsh_obs(int d, int B, const float2* X0, const float2*
                                    long long xstride, const int* cols, const float2* vals, const double* spec,
                                    const int* n_steps, int step, double* partial, hipStream_t st) {
     const void* k = (const void*)observable_walsh_kernel<WP, 256, LPR>;
-    const size_t lds = sizeof(float2) * (size_t)8 * d;
+    // LPR = 1: 80-byte rows, the reduction in the strip's memory; else 64-byte rows and NT doubles
+    const size_t lds = LPR == 1 ? sizeof(float2) * (size_t)10 * d : sizeof(float2) * (size_t)8 * d + 256 * sizeof(double);
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((observable_walsh_kernel<WP, 256, LPR>), dim3((unsigned)((long long)(d / 8) * B)), dim3(256),
