@@ -217,7 +217,12 @@ redo_status redo_compose_steps(redo_table table, int32_t precision, const float*
  *   X_prefix  c64 [B][N_max][d][d] receives X_1 .. X_N, or NULL (d <= 64 only)
  *   reproject_every  R > 0: after every step whose global index
  *             (step_offset + n) is a multiple of R, replace X by its
- *             Newton-Schulz polar step X (3I - X^dag X) / 2; 0 = never
+ *             Newton-Schulz polar step X (3I - X^dag X) / 2; 0 = never.
+ *             At d >= 128 it is computed as X + X E with
+ *             E = (I - X^dag X) / 2: X^dag X at the call's precision, X E
+ *             as a split-BF16 product (E is of the order of the drift, so
+ *             its relative error of about 2^-16 stays far below the FP32
+ *             rounding of X), X added in FP32
  *   obs_cols, obs_vals, obs_width  an optional Hermitian observable M in
  *             row-list form: int32 [d][w] column indices and c64 [d][w] values
  *             of row a (pad with value 0); NULL/0 for none

@@ -69,11 +69,12 @@ __device__ inline void store_stage(const GemmDesc& g, int k0, const float4 (&ra)
     }
 }
 
-// MODE 0: 4M, MODE 1: 3M (Gauss).  ROLE only separates the instantiations that
-// the method's chain step products (0), the plain-exponential comparison point (1),
-// the Newton-Schulz re-projections (2) and the composition of single step
-// propagators (3) launch, so that profiles attribute their time apart; the code is
-// the same.
+// MODE 0: 4M, MODE 1: 3M (Gauss).  ROLE separates the instantiations that the
+// method's chain step products (0), the plain-exponential comparison point (1), the
+// Newton-Schulz re-projections (2) and the composition of single step propagators (3)
+// launch, so that profiles attribute their time apart; the code is the same.  The Gram
+// role (4, a re-projection's A^H A) runs only the tiles that meet the upper triangle and
+// mirrors them (gram_tile, store_c).
 template <int BM, int BN, int MODE, int ROLE>
 // at least three waves per SIMD: the 3M form then keeps its 96 accumulators in VGPRs
 // (167 registers, no spills) instead of two waves with AGPRs, 240 -> 218 ms for 4096
@@ -83,15 +84,22 @@ __global__ __launch_bounds__(256, 3) void cgemm_kernel(int d, int batch, const G
     __shared__ float2 As[2][KT * C::LDA];
     __shared__ float2 Bs[2][KT * C::LDB];
     __shared__ float2 Ks[3][KT];   // k-scaling of stages kt, kt + 1, kt + 2
+    constexpr bool GRAM = ROLE == GEMM_ROLE_GRAM;
     const int tiles_n = d / BN;
-    const int ntile = (d / BM) * tiles_n;
+    const int ntile = GRAM ? (int)gram_tile_count<BM, BN>(d) : (d / BM) * tiles_n;
     int bid = blockIdx.x;
     const int nb = gridDim.x;
     if (nb % NXCD == 0) bid = (bid % NXCD) * (nb / NXCD) + bid / NXCD;
     const int be = bid / ntile, tile = bid % ntile;
     const GemmDesc g = descs[be];
     if (!g.active) return;
-    const int i0 = (tile / tiles_n) * BM, j0 = (tile % tiles_n) * BN;
+    int i0, j0;
+    if constexpr (GRAM) {
+        gram_tile<BM, BN>(d, tile, i0, j0);
+    } else {
+        i0 = (tile / tiles_n) * BM;
+        j0 = (tile % tiles_n) * BN;
+    }
     if (g.A == nullptr || g.B == nullptr) {
         copy_tile(g, d, i0, j0, BM, BN);
         return;
@@ -206,15 +214,19 @@ __global__ __launch_bounds__(256, 3) void cgemm_kernel(int d, int batch, const G
                 v.y *= g.alpha;
                 if (g.addend) v = cadd(v, ldg2(g.addend + (long long)i * d + j));
                 if (i == j) v.x += g.beta_identity;
-                stg2(g.C + (long long)i * d + j, v);
+                store_c<GRAM>(g, d, i, j, v);
             }
 }
 
 template <int BM, int BN, int MODE>
 hipError_t launch(int d, int batch, const GemmDesc* descs, hipStream_t st, int role) {
-    const long long blocks = (long long)(d / BM) * (d / BN) * batch;
+    const long long tiles = role == GEMM_ROLE_GRAM ? gram_tile_count<BM, BN>(d) : (long long)(d / BM) * (d / BN);
+    const long long blocks = tiles * batch;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (role == GEMM_ROLE_REPROJECT)
+    if (role == GEMM_ROLE_GRAM)
+        hipLaunchKernelGGL((cgemm_kernel<BM, BN, MODE, GEMM_ROLE_GRAM>), dim3((unsigned)blocks), dim3(256), 0, st, d,
+                           batch, descs);
+    else if (role == GEMM_ROLE_REPROJECT)
         hipLaunchKernelGGL((cgemm_kernel<BM, BN, MODE, 2>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
     else if (role == GEMM_ROLE_COMPOSE)
         hipLaunchKernelGGL((cgemm_kernel<BM, BN, MODE, 3>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
@@ -234,7 +246,7 @@ hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision,
     const bool big = d % 128 == 0 && (long long)(d / 128) * (d / 64) * batch >= 512;
     void* tok = nullptr;
     const bool prof = profiling_on();
-    if (prof) profile_begin(st, &tok, role == GEMM_ROLE_REPROJECT ? 2 : 0);
+    if (prof) profile_begin(st, &tok, role == GEMM_ROLE_REPROJECT || role == GEMM_ROLE_GRAM ? 2 : 0);
     // 128x64 tiles: three workgroups per CU for 4M (64 accumulator registers per lane); 3M (96)
     // is also faster there than on 128x128 tiles (240 vs 280 ms for 4096 products at d = 1024)
     if (precision == 2)

@@ -284,8 +284,9 @@ __device__ inline bf16x8 neg8(bf16x8 x) {
 
 #define MF16(a, b, c) __builtin_amdgcn_mfma_f32_32x32x16_bf16((a), (b), (c), 0, 0, 0)
 
-// One 128 x 64 (or 64 x 64) output tile; MODE is the staging mode of load_stage_bf
-template <int BM, int BN, int MODE>
+// One 128 x 64 (or 64 x 64) output tile; MODE is the staging mode of load_stage_bf, GRAM
+// the store of the Gram role (store_c)
+template <int BM, int BN, int MODE, bool GRAM>
 __device__ __forceinline__ void bf16x3_tile(const GemmDesc& g, int d, int i0, int j0,
                                             unsigned short (*As)[BCfg<BM, BN>::ASZ],
                                             unsigned short (*Bs)[BCfg<BM, BN>::BSZ], float2 (*Ks)[KT]) {
@@ -423,27 +424,36 @@ __device__ __forceinline__ void bf16x3_tile(const GemmDesc& g, int d, int i0, in
                 v.y *= g.alpha;
                 if (g.addend) v = cadd(v, ldg2(g.addend + (long long)i * d + j));
                 if (i == j) v.x += g.beta_identity;
-                stg2(g.C + (long long)i * d + j, v);
+                store_c<GRAM>(g, d, i, j, v);
             }
 }
 
 template <int BM, int BN, int ROLE>
-// ROLE separates instantiations for profiles only (as in cgemm_kernel); at least three waves per SIMD (a 12-byte spill; 211 -> 192 ms for 4096 products at d = 1024):
-// the splits keep the vector ALU busy, and a third wave hides more of it behind the MFMAs
+// ROLE separates instantiations for profiles, and the Gram role (4) runs the upper tiles
+// only, as in cgemm_kernel.  At least three waves per SIMD (a 24-byte spill; 211 -> 192 ms
+// for 4096 products at d = 1024): the splits keep the vector ALU busy, and a third wave
+// hides more of it behind the MFMAs
 __global__ __launch_bounds__(256, 3) void cgemm_bf16x3_kernel(int d, int batch, const GemmDesc* __restrict__ descs) {
     using C = BCfg<BM, BN>;
     __shared__ __attribute__((aligned(16))) unsigned short As[2][C::ASZ];
     __shared__ __attribute__((aligned(16))) unsigned short Bs[2][C::BSZ];
     __shared__ float2 Ks[3][KT];   // k-scaling of stages kt, kt + 1, kt + 2
+    constexpr bool GRAM = ROLE == GEMM_ROLE_GRAM;
     const int tiles_n = d / BN;
-    const int ntile = (d / BM) * tiles_n;
+    const int ntile = GRAM ? (int)gram_tile_count<BM, BN>(d) : (d / BM) * tiles_n;
     int bid = blockIdx.x;
     const int nb = gridDim.x;
     if (nb % NXCD == 0) bid = (bid % NXCD) * (nb / NXCD) + bid / NXCD;
     const int be = bid / ntile, tile = bid % ntile;
     const GemmDesc g = descs[be];
     if (!g.active) return;
-    const int i0 = (tile / tiles_n) * BM, j0 = (tile % tiles_n) * BN;
+    int i0, j0;
+    if constexpr (GRAM) {
+        gram_tile<BM, BN>(d, tile, i0, j0);
+    } else {
+        i0 = (tile / tiles_n) * BM;
+        j0 = (tile % tiles_n) * BN;
+    }
     if (g.A == nullptr || g.B == nullptr) {
         copy_tile(g, d, i0, j0, BM, BN);
         return;
@@ -452,26 +462,30 @@ __global__ __launch_bounds__(256, 3) void cgemm_bf16x3_kernel(int d, int batch, 
     if constexpr (bf_fast_tiles<BM, BN>()) {
         if (g.opB == 0 && g.Abf) {
             if (g.conjA)
-                bf16x3_tile<BM, BN, 3>(g, d, i0, j0, As, Bs, Ks);
+                bf16x3_tile<BM, BN, 3, GRAM>(g, d, i0, j0, As, Bs, Ks);
             else
-                bf16x3_tile<BM, BN, 2>(g, d, i0, j0, As, Bs, Ks);
+                bf16x3_tile<BM, BN, 2, GRAM>(g, d, i0, j0, As, Bs, Ks);
             return;
         }
         if (g.opB == 0 && g.opA == 0) {
-            bf16x3_tile<BM, BN, 1>(g, d, i0, j0, As, Bs, Ks);
+            bf16x3_tile<BM, BN, 1, GRAM>(g, d, i0, j0, As, Bs, Ks);
             return;
         }
     }
-    bf16x3_tile<BM, BN, 0>(g, d, i0, j0, As, Bs, Ks);
+    bf16x3_tile<BM, BN, 0, GRAM>(g, d, i0, j0, As, Bs, Ks);
 }
 
 #undef MF16
 
 template <int BM, int BN>
 hipError_t launch_bf(int d, int batch, const GemmDesc* descs, hipStream_t st, int role) {
-    const long long blocks = (long long)(d / BM) * (d / BN) * batch;
+    const long long tiles = role == GEMM_ROLE_GRAM ? gram_tile_count<BM, BN>(d) : (long long)(d / BM) * (d / BN);
+    const long long blocks = tiles * batch;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    if (role == GEMM_ROLE_REPROJECT)
+    if (role == GEMM_ROLE_GRAM)
+        hipLaunchKernelGGL((cgemm_bf16x3_kernel<BM, BN, GEMM_ROLE_GRAM>), dim3((unsigned)blocks), dim3(256), 0, st, d,
+                           batch, descs);
+    else if (role == GEMM_ROLE_REPROJECT)
         hipLaunchKernelGGL((cgemm_bf16x3_kernel<BM, BN, 2>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);
     else if (role == GEMM_ROLE_COMPOSE)
         hipLaunchKernelGGL((cgemm_bf16x3_kernel<BM, BN, 3>), dim3((unsigned)blocks), dim3(256), 0, st, d, batch, descs);

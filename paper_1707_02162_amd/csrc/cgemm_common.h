@@ -92,6 +92,38 @@ __device__ inline void ks_fetch(const GemmDesc& g, int s, float2 (*Ks)[KT]) {
 }
 
 // An entry with an identity operand: this tile of C = alpha rs o op(X) o (ks or cs) + beta I, no products.
+// Gram role: the tiles (ti, tj) that meet the upper triangle j >= i are those with
+// tj >= ti BM / BN; they are numbered row-tile by row-tile
+template <int BM, int BN>
+__host__ __device__ constexpr long long gram_tile_count(int d) {
+    static_assert(BM % BN == 0, "row tiles are whole multiples of column tiles");
+    return (long long)(d / BM) * (d / BN) - (long long)(BM / BN) * (d / BM) * (d / BM - 1) / 2;
+}
+
+template <int BM, int BN>
+__device__ inline void gram_tile(int d, int u, int& i0, int& j0) {
+    constexpr int q = BM / BN;
+    const int cn = d / BN;
+    int ti = 0;
+    while (u >= cn - q * ti) {   // row-tile ti holds cn - q ti tiles (at least q)
+        u -= cn - q * ti;
+        ++ti;
+    }
+    i0 = ti * BM;
+    j0 = (q * ti + u) * BN;
+}
+
+// the store of element (i, j); in the Gram role only j >= i is stored, the strictly upper
+// elements also as their conjugates at (j, i), so each element of C is written once
+template <bool GRAM>
+__device__ inline void store_c(const GemmDesc& g, int d, int i, int j, float2 v) {
+    if constexpr (GRAM) {
+        if (j < i) return;
+        if (j > i) stg2(g.C + (long long)j * d + i, cconj(v));
+    }
+    stg2(g.C + (long long)i * d + j, v);
+}
+
 __device__ inline void copy_tile(const GemmDesc& g, int d, int i0, int j0, int BM, int BN) {
     for (int e = threadIdx.x; e < BM * BN; e += blockDim.x) {
         const int i = i0 + e / BN, j = j0 + e % BN;

@@ -162,9 +162,9 @@ int ps_r_max(int d) { return 5; }
 size_t expm_chain_workspace_bytes(const redo_table_s* t, int B, int N) {
     const int d = t->desc.d;
     const size_t mat = sizeof(float2) * (size_t)d * d;
-    return align_up(mat * B) + align_up(mat * std::min(B, 256)) + align_up(mat * std::min(B, OBS_CHUNK)) +
+    return align_up(mat * B) + align_up(mat * std::min(B, REPROJECT_CHUNK)) + align_up(mat * std::min(B, OBS_CHUNK)) +
            align_up(sizeof(double) * observable_partial_doubles(d, B)) +
-           align_up(sizeof(int) * B) + align_up(sizeof(GemmDesc) * std::max(B, 256)) + align_up(8) +
+           align_up(sizeof(int) * B) + align_up(sizeof(GemmDesc) * std::max(B, REPROJECT_CHUNK)) + align_up(8) +
            ExpmChunkWS::bytes(d, ps_r_max(d));
 }
 
@@ -213,7 +213,7 @@ redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int
     float2* W1 = reinterpret_cast<float2*>(base + off);
     off += align_up(mat * B);
     float2* Z = reinterpret_cast<float2*>(base + off);
-    off += align_up(mat * std::min(B, 256));
+    off += align_up(mat * std::min(B, REPROJECT_CHUNK));
     float2* obsT = reinterpret_cast<float2*>(base + off);
     off += align_up(mat * std::min(B, OBS_CHUNK));
     double* obs_partial = reinterpret_cast<double*>(base + off);
@@ -221,7 +221,7 @@ redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int
     int* loc = reinterpret_cast<int*>(base + off);
     off += align_up(sizeof(int) * B);
     GemmDesc* descs = reinterpret_cast<GemmDesc*>(base + off);
-    off += align_up(sizeof(GemmDesc) * std::max(B, 256));
+    off += align_up(sizeof(GemmDesc) * std::max(B, REPROJECT_CHUNK));
     unsigned long long* dbound = reinterpret_cast<unsigned long long*>(base + off);
     off += align_up(8);
     ExpmChunkWS w(d, ps_r_max(d), base + off);
@@ -248,16 +248,8 @@ redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int
                                  split ? t->V32 : nullptr, d, t->desc.n_drift));
             REDO_HIP(cgemm_batched(d, cnt, descs, prec, st, 1));
         }
-        if (reproject_every > 0 && ((long long)step_offset + n + 1) % reproject_every == 0) {
-            for (int b0 = 0; b0 < B; b0 += 256) {
-                const int ch = std::min(256, B - b0);
-                REDO_HIP(reproject_descs(descs, ch, b0, X[0], X[1], nn, Z, nn, loc, n_steps, n, 0, st));
-                REDO_HIP(cgemm_batched(d, ch, descs, prec, st, 1));
-                REDO_HIP(unitarity_check(d, ch, b0, Z, nn, n_steps, n, t->flags, st));
-                REDO_HIP(reproject_descs(descs, ch, b0, X[0], X[1], nn, Z, nn, loc, n_steps, n, 1, st));
-                REDO_HIP(cgemm_batched(d, ch, descs, prec, st, 1));
-            }
-        }
+        if (reproject_every > 0 && ((long long)step_offset + n + 1) % reproject_every == 0)
+            REDO_HIP(reproject_states(d, B, X[0], X[1], nn, Z, descs, loc, n_steps, n, prec, t->flags, st));
         if (obs_out)
             REDO_HIP(walsh_frame ? observable_walsh(d, B, X[0], X[1], loc, nn, obs_cols,
                                                     reinterpret_cast<const float2*>(obs_vals), obs_width, walsh,

@@ -139,7 +139,8 @@ __global__ __launch_bounds__(256) void plan_step_kernel(PlanArgs a) {
 }
 
 // re-projection descriptors from the tracked locations:
-// phase 0: Z_b = -X^dag X / 2 + 3/2 I;  phase 1: X'_b = X_b Z_b into the other buffer (and flip loc)
+// phase 0: E_b = (I - X^dag X) / 2 (a Gram product);  phase 1: X'_b = X_b + X_b E_b into the
+// other buffer (and flip loc)
 __global__ void reproject_descs_kernel(GemmDesc* descs, int count, int b0, float2* X0, float2* X1, long long xstride,
                                        float2* Z, long long zstride, int* loc, const int* n_steps, int step, int phase) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -157,19 +158,20 @@ __global__ void reproject_descs_kernel(GemmDesc* descs, int count, int b0, float
         g.B = xb;
         g.C = Z + (long long)i * zstride;
         g.alpha = -0.5f;
-        g.beta_identity = 1.5f;
+        g.beta_identity = 0.5f;
     } else {
         g.A = xb;
         g.B = Z + (long long)i * zstride;
         g.C = X[l ^ 1] + (long long)b * xstride;
         g.alpha = 1.f;
+        g.addend = xb;
         if (active) loc[b] = l ^ 1;
     }
     descs[i] = g;
 }
 
-// unitarity watchdog of a re-projection step: Z_b = 3/2 I - X^dag X / 2 holds the Gram
-// matrix, so ||X^dag X - I||_F = 2 ||I - Z_b||_F; one workgroup per active instance, FP64 sum
+// unitarity watchdog of a re-projection step: E_b = (I - X^dag X) / 2 holds the Gram
+// matrix, so ||X^dag X - I||_F = 2 ||E_b||_F; one workgroup per active instance, FP64 sum
 __global__ __launch_bounds__(256) void unitarity_check_kernel(int d, const float2* __restrict__ Z, long long zstride,
                                                               const int* n_steps, int b0, int step, DeviceFlags* flags) {
     const int i = blockIdx.x;
@@ -180,8 +182,7 @@ __global__ __launch_bounds__(256) void unitarity_check_kernel(int d, const float
     double s = 0.0;
     for (long long e = threadIdx.x; e < nn; e += 256) {
         const float2 v = z[e];
-        const double er = (e / d == e % d ? 1.0 : 0.0) - (double)v.x, ei = v.y;
-        s += er * er + ei * ei;
+        s += (double)v.x * v.x + (double)v.y * v.y;
     }
     __shared__ double part[256];
     part[threadIdx.x] = s;
@@ -1337,6 +1338,20 @@ hipError_t unitarity_check(int d, int count, int b0, const float2* Z, long long 
                            DeviceFlags* flags, hipStream_t st) {
     hipLaunchKernelGGL(unitarity_check_kernel, dim3(count), dim3(256), 0, st, d, Z, zstride, n_steps, b0, step, flags);
     return hipGetLastError();
+}
+
+hipError_t reproject_states(int d, int B, float2* X0, float2* X1, long long xstride, float2* E, GemmDesc* descs,
+                            int* loc, const int* n_steps, int step, int precision, DeviceFlags* flags, hipStream_t st) {
+    for (int b0 = 0; b0 < B; b0 += REPROJECT_CHUNK) {
+        const int ch = std::min(REPROJECT_CHUNK, B - b0);
+        hipError_t e = reproject_descs(descs, ch, b0, X0, X1, xstride, E, xstride, loc, n_steps, step, 0, st);
+        if (e == hipSuccess) e = cgemm_batched(d, ch, descs, precision, st, GEMM_ROLE_GRAM);
+        if (e == hipSuccess) e = unitarity_check(d, ch, b0, E, xstride, n_steps, step, flags, st);
+        if (e == hipSuccess) e = reproject_descs(descs, ch, b0, X0, X1, xstride, E, xstride, loc, n_steps, step, 1, st);
+        if (e == hipSuccess) e = cgemm_batched(d, ch, descs, 2, st, GEMM_ROLE_REPROJECT);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t gather_back(int d, int B, float2* X0, const float2* X1, long long xstride, const int* loc, hipStream_t st) {

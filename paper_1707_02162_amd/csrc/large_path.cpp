@@ -333,17 +333,8 @@ redo_status large_chain(redo_table_s* t, int precision, const float* u, const in
         p.B = B;
         REDO_HIP(plan_step(p, st));
         for (int sl = 0; sl < S; ++sl) REDO_HIP(cgemm_batched(d, B, w.descs + (size_t)sl * B, prec, st));
-        if (reproject_every > 0 && ((long long)step_offset + n + 1) % reproject_every == 0) {
-            // X <- X (3I - X^dag X) / 2 = X Z with Z = -X^dag X / 2 + 3/2 I
-            for (int b0 = 0; b0 < B; b0 += REPROJECT_CHUNK) {
-                const int ch = std::min(REPROJECT_CHUNK, B - b0);
-                REDO_HIP(reproject_descs(w.descs, ch, b0, X[0], X[1], mat, w.Z, mat, w.loc, n_steps, n, 0, st));
-                REDO_HIP(cgemm_batched(d, ch, w.descs, prec, st, GEMM_ROLE_REPROJECT));
-                REDO_HIP(unitarity_check(d, ch, b0, w.Z, mat, n_steps, n, t->flags, st));
-                REDO_HIP(reproject_descs(w.descs, ch, b0, X[0], X[1], mat, w.Z, mat, w.loc, n_steps, n, 1, st));
-                REDO_HIP(cgemm_batched(d, ch, w.descs, prec, st, GEMM_ROLE_REPROJECT));
-            }
-        }
+        if (reproject_every > 0 && ((long long)step_offset + n + 1) % reproject_every == 0)
+            REDO_HIP(reproject_states(d, B, X[0], X[1], mat, w.Z, w.descs, w.loc, n_steps, n, prec, t->flags, st));
         if (obs_out)
             REDO_HIP(walsh_frame ? observable_walsh(d, B, X[0], X[1], w.loc, mat, obs_cols,
                                              reinterpret_cast<const float2*>(obs_vals), obs_width, walsh, n_steps,

@@ -151,12 +151,21 @@ hipError_t walsh_right(int d, int B, float2* X, long long stride, hipStream_t st
 hipError_t observable_walsh(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
                             const int* cols, const float2* vals, int w, const double* spec, const int* n_steps,
                             int step, double* partial, double* out, long long out_stride, hipStream_t st);
-// after phase 0 of a re-projection (Z = 3/2 I - X^dag X / 2 for instances b0 .. b0 + count - 1):
+// after phase 0 of a re-projection (Z = E = (I - X^dag X) / 2 for instances b0 .. b0 + count - 1):
 // counts every active instance with ||X^dag X - I||_F / sqrt(d) > UNITARITY_WARN in flags
 hipError_t unitarity_check(int d, int count, int b0, const float2* Z, long long zstride, const int* n_steps, int step,
                            DeviceFlags* flags, hipStream_t st);
 hipError_t reproject_descs(GemmDesc* descs, int count, int b0, float2* X0, float2* X1, long long xstride, float2* Z,
                            long long zstride, int* loc, const int* n_steps, int step, int phase, hipStream_t st);
+// Newton-Schulz re-projection of every active instance at a re-projection step,
+// X <- X (3I - X^dag X) / 2 written as X + X E with E = (I - X^dag X) / 2, REPROJECT_CHUNK
+// instances at a time through the scratch E (xstride apart) and descs (REPROJECT_CHUNK
+// entries): the Gram product X^dag X at the given GEMM precision (Hermitian: the upper tiles
+// only), the unitarity watchdog on E, then X E as a split-BF16 product with X added in FP32
+// into the other buffer (loc flips).  E is of the order of the drift, so the split's relative
+// error of about 2^-16 in X E stays far below the FP32 rounding of X itself.
+hipError_t reproject_states(int d, int B, float2* X0, float2* X1, long long xstride, float2* E, GemmDesc* descs,
+                            int* loc, const int* n_steps, int step, int precision, DeviceFlags* flags, hipStream_t st);
 hipError_t gather_back(int d, int B, float2* X0, const float2* X1, long long xstride, const int* loc, hipStream_t st);
 hipError_t fill_int(int* p, int n, int v, hipStream_t st);
 size_t trace_partial_doubles(int d, int B, int K);

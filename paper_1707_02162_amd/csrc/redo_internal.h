@@ -290,9 +290,13 @@ static_assert(sizeof(GemmDesc) % 8 == 0, "desc alignment");
 // role: 0 a REDO chain step product, 1 the plain-exponential comparison point, 2 a
 // Newton-Schulz re-projection product, 3 the composition of single step propagators
 // (redo_compose_steps, the step factors of GRAPE); each role is a separate kernel
-// instantiation (same code), so that profiles attribute time apart, and re-projection
-// launches are timed as profile kind 2
-constexpr int GEMM_ROLE_STEP = 0, GEMM_ROLE_EXPM = 1, GEMM_ROLE_REPROJECT = 2, GEMM_ROLE_COMPOSE = 3;
+// instantiation (same code), so that profiles attribute time apart.  Role 4 is the Gram
+// product of a re-projection, C = alpha A^H A + beta I with alpha, beta real and no
+// scaling, addend or null operand: C is Hermitian, so only the tiles that meet the upper
+// triangle run and each writes the conjugate of its strictly upper elements below the
+// diagonal.  Re-projection launches (roles 2 and 4) are timed as profile kind 2
+constexpr int GEMM_ROLE_STEP = 0, GEMM_ROLE_EXPM = 1, GEMM_ROLE_REPROJECT = 2, GEMM_ROLE_COMPOSE = 3,
+              GEMM_ROLE_GRAM = 4;
 hipError_t cgemm_batched(int d, int batch, const GemmDesc* descs, int precision, hipStream_t st, int role = 0);
 // the split-BF16 launch behind cgemm_batched (cgemm_bf16.hip): 128 x 64 tiles when big, else 64 x 64
 hipError_t cgemm_bf16_launch(int d, int batch, const GemmDesc* descs, hipStream_t st, int role, bool big);
