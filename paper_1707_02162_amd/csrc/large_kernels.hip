@@ -612,6 +612,20 @@ __global__ __launch_bounds__(256) void walsh_right_kernel(int d, long long rows,
         p[u] = make_float4(s * v[2 * u].x, s * v[2 * u].y, s * v[2 * u + 1].x, s * v[2 * u + 1].y);
 }
 
+// row of element e of an 8-column strip (column e % 8).  With whole-row lanes (LPR = 1) the
+// 80-byte rows of 8 consecutive e go to rows r and r + 4 by turns within each block of 8 rows:
+// an 8-byte store serves 16 lanes per pass over 32 banks, and rows 4 apart start 16 banks
+// apart, so each pass writes 32 distinct banks (neighbouring rows would share 4)
+template <int LPR>
+__device__ inline int strip_row(int e) {
+    if constexpr (LPR == 1) {
+        const int s = (e >> 3) & 7;
+        return ((e >> 6) << 3) | ((s & 1) << 2) | (s >> 1);
+    } else {
+        return e >> 3;
+    }
+}
+
 // The observable in the right Walsh frame, one pass: the 8-column strip of W in LDS (as
 // observable_mx8_kernel).  The frame needs M_ac = f(a XOR c) with f real, so row a's list is
 // row 0's with every column XORed by a: the masks m and values f(m) are read once from row 0
@@ -650,14 +664,14 @@ __global__ __launch_bounds__(NT, NT / 128) void observable_walsh_kernel(int d, i
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int e = min(base + u * NT + tid, n - 1);
-            r[u] = Xb[(long long)(e / SW) * d + c0 + e % SW];
+            r[u] = Xb[(long long)strip_row<LPR>(e) * d + c0 + e % SW];
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int e = base + u * NT + tid;
             if (e < n) {
                 if constexpr (LPR == 1)
-                    strip[(e / SW) * RS + e % SW] = r[u];
+                    strip[strip_row<LPR>(e) * RS + e % SW] = r[u];
                 else
                     strip[mx8_off(e / SW, e % SW)] = r[u];
             }
@@ -701,8 +715,14 @@ __global__ __launch_bounds__(NT, NT / 128) void observable_walsh_kernel(int d, i
             } else {
                 const int top = 31 - __clz(m);
                 const int low = (1 << top) - 1;
+                // a 16-byte read serves 16 lanes per pass over 64 banks, and row a starts at
+                // bank 20 a mod 64, a function of a mod 16: 16 lanes of consecutive pairs take
+                // 16 residues when top >= 4, but only the 8 with bit top clear when top < 4;
+                // lanes 8..15 of each 16 then start from the partner row a ^ m (the pair's
+                // product is symmetric in its rows, so the sums are the same bit for bit)
+                const int flip = (top < 4 && (tid & 8)) ? m : 0;
                 for (int pr = tid; pr < d / 2; pr += NT) {
-                    const int a = ((pr & ~low) << 1) | (pr & low);
+                    const int a = (((pr & ~low) << 1) | (pr & low)) ^ flip;
                     const float4* xa = strip4 + a * (RS / 2);
                     const float4* yc = strip4 + (a ^ m) * (RS / 2);
 #pragma unroll
