@@ -483,3 +483,81 @@ def test_chain_large_batch_tiles_d128_vs_oracle(prec):
         tol = BF_TOL if prec == 2 else FROB_TOL
         assert nfrob(U[b], X) < tol
         assert np.abs(m[b, :lens[b]] - mo).max() < (BF_TOL if prec == 2 else 1e-5)
+
+
+# ---------------------------------------------------------------- Newton-Schulz re-projection
+def _perturbed_unitaries(d, B, delta, seed):
+    """Haar unitaries times (I + delta G), G Hermitian with ||G||_F / sqrt(d) = 1:
+    ||X^dag X - I||_F / sqrt(d) ~ 2 delta."""
+    gen = np.random.default_rng(seed)
+    X = np.empty((B, d, d), np.complex128)
+    for b in range(B):
+        A = gen.normal(size=(d, d)) + 1j * gen.normal(size=(d, d))
+        G = (A + A.conj().T) / 2
+        G *= math.sqrt(d) / np.linalg.norm(G)
+        X[b] = W.haar_unitary(d, gen) @ (np.eye(d) + delta * G)
+    return X
+
+
+def _unitarity(X):
+    d = X.shape[-1]
+    X = np.asarray(X, np.complex128)
+    return float(np.linalg.norm(X.conj().T @ X - np.eye(d)) / math.sqrt(d))
+
+
+# small batches run the Gram product X^dag X on 64 x 64 tiles, B = 64 at d = 256 on 128 x 64
+REPROJ_CASES = [("chain", 7, 3, 0), ("chain", 7, 3, 1), ("chain", 7, 3, 2), ("chain", 8, 64, 0),
+                ("chain", 8, 64, 1), ("chain", 8, 64, 2), ("chain", 10, 2, 1), ("kron", 8, 64, 1),
+                ("expm", 7, 3, 1)]
+
+
+@pytest.mark.parametrize("kind, n, B, prec", REPROJ_CASES)
+def test_reprojection_step_vs_newton_schulz(kind, n, B, prec):
+    """One step from states about 4e-4 off unitarity, re-projected after it, against
+    the Newton-Schulz polar step Y (3I - Y^dag Y) / 2 of Y = U_1 X0 in FP64 (U_1 the
+    oracle's step; the exact exponential for the comparison-point chain).  The step
+    must also take the state back to unitarity (FP32: below 1e-5; split BF16, whose
+    Gram product carries its own ~1e-5 error: below 1e-4)."""
+    p = W.ising_freezing(n=n, B=B, N=1)
+    d = p.d
+    X0 = _perturbed_unitaries(d, B, 2e-4, 700 + n).astype(np.complex64)
+    t = R().RedoTable.from_problem(p)
+    u = torch.tensor(p.u).cuda()
+    X0t = torch.tensor(X0).cuda()
+    if kind == "chain":
+        U, _, _ = t.chain(u, precision=prec, X0=X0t, reproject_every=1)
+    elif kind == "kron":
+        U, _ = t.kron_chain(u, X0=X0t, reproject_every=1)
+    else:
+        U, _ = t.expm_chain(u, precision=prec, X0=X0t, reproject_every=1)
+    U = U.cpu().numpy()
+    tab = None if kind == "expm" else O.DiscreteTable(p.S, p.dt, p.eps, p.base, p.digits)
+    tol, unit_tol = (1e-3, 1e-4) if prec == 2 else (FROB_TOL, 1e-5)
+    for b in sorted({0, B // 2, B - 1}):
+        step = _exact_steps(p, b)[0] if kind == "expm" else O.compose_all_redo(p, tab, b)[0]
+        Y = step @ X0[b].astype(np.complex128)
+        Xe = Y @ (3 * np.eye(d) - Y.conj().T @ Y) / 2
+        assert _unitarity(Y) > 3e-4
+        assert nfrob(U[b], Xe) < tol, (b, nfrob(U[b], Xe))
+        assert _unitarity(U[b]) < unit_tol, (b, _unitarity(U[b]))
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_reprojection_skips_finished_instances(prec):
+    """Ragged lengths: an instance whose chain has ended (length 0 here) is neither
+    stepped nor re-projected, so it keeps its X0 bit for bit; its neighbours in the
+    same Gram and correction launches are re-projected (B = 64 at d = 256: 128 x 64
+    tiles)."""
+    p = W.ising_freezing(n=8, B=64, N=1)
+    X0 = _perturbed_unitaries(p.d, p.B, 2e-4, 731).astype(np.complex64)
+    lens = np.ones(p.B, np.int32)
+    lens[1::3] = 0
+    t = R().RedoTable.from_problem(p)
+    U, _, _ = t.chain(torch.tensor(p.u).cuda(), n_steps=torch.tensor(lens), precision=prec,
+                      X0=torch.tensor(X0).cuda(), reproject_every=1)
+    U = U.cpu().numpy()
+    for b in range(p.B):
+        if lens[b] == 0:
+            assert np.array_equal(U[b], X0[b]), b
+        else:
+            assert _unitarity(U[b]) < (1e-4 if prec == 2 else 1e-5), (b, _unitarity(U[b]))
