@@ -212,7 +212,7 @@ redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int
     size_t off = 0;
     float2* W1 = reinterpret_cast<float2*>(base + off);
     off += align_up(mat * B);
-    float2* Z = reinterpret_cast<float2*>(base + off);
+    float2* E = reinterpret_cast<float2*>(base + off);   // re-projection scratch
     off += align_up(mat * std::min(B, REPROJECT_CHUNK));
     float2* obsT = reinterpret_cast<float2*>(base + off);
     off += align_up(mat * std::min(B, OBS_CHUNK));
@@ -249,7 +249,7 @@ redo_status expm_chain(redo_table_s* t, int precision, const float* u, const int
             REDO_HIP(cgemm_batched(d, cnt, descs, prec, st, 1));
         }
         if (reproject_every > 0 && ((long long)step_offset + n + 1) % reproject_every == 0)
-            REDO_HIP(reproject_states(d, B, X[0], X[1], nn, Z, descs, loc, n_steps, n, prec, t->flags, st));
+            REDO_HIP(reproject_states(d, B, X[0], X[1], nn, E, descs, loc, n_steps, n, prec, t->flags, st));
         if (obs_out)
             REDO_HIP(walsh_frame ? observable_walsh(d, B, X[0], X[1], loc, nn, obs_cols,
                                                     reinterpret_cast<const float2*>(obs_vals), obs_width, walsh,

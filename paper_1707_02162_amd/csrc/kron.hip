@@ -403,7 +403,7 @@ struct KronWS {
     float2* gates;
     float2 *pre, *post;
     GemmDesc* descs;
-    float2* Z;
+    float2* E;   // re-projection scratch: E = (I - X^dag X) / 2 of a chunk
     double* obs_partial;
     int* loc;
     float2* obsT;
@@ -419,7 +419,7 @@ struct KronWS {
         pre = c.take<float2>((size_t)B * d);
         post = c.take<float2>((size_t)B * d);
         descs = c.take<GemmDesc>((size_t)2 * B);
-        Z = c.take<float2>(mat * std::min(B, REPROJECT_CHUNK));
+        E = c.take<float2>(mat * std::min(B, REPROJECT_CHUNK));
         obs_partial = c.take<double>(observable_partial_doubles(d, B));
         loc = c.take<int>(B);
         obsT = c.take<float2>(mat * std::min(B, OBS_CHUNK));
@@ -498,7 +498,7 @@ redo_status kron_chain(redo_table_s* t, int quantised, const float* u, const int
         }
         REDO_HIP(kron_step(d, B, X[0], X[1], w.loc, mat, w.gates, w.pre, w.post, n_steps, n, st));
         if (reproj)   // X <- X (3I - X^dag X) / 2 into the other buffer, Gram product in 3M FP32
-            REDO_HIP(reproject_states(d, B, X[0], X[1], mat, w.Z, w.descs, w.loc, n_steps, n, 1, t->flags, st));
+            REDO_HIP(reproject_states(d, B, X[0], X[1], mat, w.E, w.descs, w.loc, n_steps, n, 1, t->flags, st));
         if (obs_out)
             REDO_HIP(walsh_frame ? observable_walsh(d, B, X[0], X[1], w.loc, mat, obs_cols,
                                              reinterpret_cast<const float2*>(obs_vals), obs_width, walsh, n_steps,

@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void plan_step_kernel(PlanArgs a) {
 // phase 0: E_b = (I - X^dag X) / 2 (a Gram product);  phase 1: X'_b = X_b + X_b E_b into the
 // other buffer (and flip loc)
 __global__ void reproject_descs_kernel(GemmDesc* descs, int count, int b0, float2* X0, float2* X1, long long xstride,
-                                       float2* Z, long long zstride, int* loc, const int* n_steps, int step, int phase) {
+                                       float2* E, long long estride, int* loc, const int* n_steps, int step, int phase) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const int b = b0 + i;
@@ -156,12 +156,12 @@ __global__ void reproject_descs_kernel(GemmDesc* descs, int count, int b0, float
         g.A = xb;
         g.opA = 1;
         g.B = xb;
-        g.C = Z + (long long)i * zstride;
+        g.C = E + (long long)i * estride;
         g.alpha = -0.5f;
         g.beta_identity = 0.5f;
     } else {
         g.A = xb;
-        g.B = Z + (long long)i * zstride;
+        g.B = E + (long long)i * estride;
         g.C = X[l ^ 1] + (long long)b * xstride;
         g.alpha = 1.f;
         g.addend = xb;
@@ -172,16 +172,16 @@ __global__ void reproject_descs_kernel(GemmDesc* descs, int count, int b0, float
 
 // unitarity watchdog of a re-projection step: E_b = (I - X^dag X) / 2 holds the Gram
 // matrix, so ||X^dag X - I||_F = 2 ||E_b||_F; one workgroup per active instance, FP64 sum
-__global__ __launch_bounds__(256) void unitarity_check_kernel(int d, const float2* __restrict__ Z, long long zstride,
+__global__ __launch_bounds__(256) void unitarity_check_kernel(int d, const float2* __restrict__ E, long long estride,
                                                               const int* n_steps, int b0, int step, DeviceFlags* flags) {
     const int i = blockIdx.x;
     const int b = b0 + i;
     if (n_steps && step >= n_steps[b]) return;
-    const float2* z = Z + (long long)i * zstride;
+    const float2* eb = E + (long long)i * estride;
     const long long nn = (long long)d * d;
     double s = 0.0;
     for (long long e = threadIdx.x; e < nn; e += 256) {
-        const float2 v = z[e];
+        const float2 v = eb[e];
         s += (double)v.x * v.x + (double)v.y * v.y;
     }
     __shared__ double part[256];
@@ -1347,16 +1347,16 @@ hipError_t plan_step(const PlanLaunch& p, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t reproject_descs(GemmDesc* descs, int count, int b0, float2* X0, float2* X1, long long xstride, float2* Z,
-                           long long zstride, int* loc, const int* n_steps, int step, int phase, hipStream_t st) {
+hipError_t reproject_descs(GemmDesc* descs, int count, int b0, float2* X0, float2* X1, long long xstride, float2* E,
+                           long long estride, int* loc, const int* n_steps, int step, int phase, hipStream_t st) {
     hipLaunchKernelGGL(reproject_descs_kernel, dim3((count + 63) / 64), dim3(64), 0, st, descs, count, b0, X0, X1,
-                       xstride, Z, zstride, loc, n_steps, step, phase);
+                       xstride, E, estride, loc, n_steps, step, phase);
     return hipGetLastError();
 }
 
-hipError_t unitarity_check(int d, int count, int b0, const float2* Z, long long zstride, const int* n_steps, int step,
+hipError_t unitarity_check(int d, int count, int b0, const float2* E, long long estride, const int* n_steps, int step,
                            DeviceFlags* flags, hipStream_t st) {
-    hipLaunchKernelGGL(unitarity_check_kernel, dim3(count), dim3(256), 0, st, d, Z, zstride, n_steps, b0, step, flags);
+    hipLaunchKernelGGL(unitarity_check_kernel, dim3(count), dim3(256), 0, st, d, E, estride, n_steps, b0, step, flags);
     return hipGetLastError();
 }
 

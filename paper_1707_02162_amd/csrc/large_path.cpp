@@ -36,7 +36,7 @@ struct ChainWS {
     float2* W1;
     float2 *pre, *post, *pstar;
     GemmDesc* descs;
-    float2* Z;
+    float2* E;   // re-projection scratch: E = (I - X^dag X) / 2 of a chunk
     double* obs_partial;
     int* loc;
     float2* obsT;
@@ -52,7 +52,7 @@ struct ChainWS {
         post = c.take<float2>((size_t)B * d);
         pstar = c.take<float2>((size_t)B * d);
         descs = c.take<GemmDesc>((size_t)std::max(slots_of(t), 2) * B);
-        Z = c.take<float2>(mat * std::min(B, REPROJECT_CHUNK));
+        E = c.take<float2>(mat * std::min(B, REPROJECT_CHUNK));
         obs_partial = c.take<double>(observable_partial_doubles(d, B));
         loc = c.take<int>(B);
         obsT = c.take<float2>(mat * std::min(B, OBS_CHUNK));
@@ -334,7 +334,7 @@ redo_status large_chain(redo_table_s* t, int precision, const float* u, const in
         REDO_HIP(plan_step(p, st));
         for (int sl = 0; sl < S; ++sl) REDO_HIP(cgemm_batched(d, B, w.descs + (size_t)sl * B, prec, st));
         if (reproject_every > 0 && ((long long)step_offset + n + 1) % reproject_every == 0)
-            REDO_HIP(reproject_states(d, B, X[0], X[1], mat, w.Z, w.descs, w.loc, n_steps, n, prec, t->flags, st));
+            REDO_HIP(reproject_states(d, B, X[0], X[1], mat, w.E, w.descs, w.loc, n_steps, n, prec, t->flags, st));
         if (obs_out)
             REDO_HIP(walsh_frame ? observable_walsh(d, B, X[0], X[1], w.loc, mat, obs_cols,
                                              reinterpret_cast<const float2*>(obs_vals), obs_width, walsh, n_steps,

@@ -151,12 +151,12 @@ hipError_t walsh_right(int d, int B, float2* X, long long stride, hipStream_t st
 hipError_t observable_walsh(int d, int B, const float2* X0, const float2* X1, const int* loc, long long xstride,
                             const int* cols, const float2* vals, int w, const double* spec, const int* n_steps,
                             int step, double* partial, double* out, long long out_stride, hipStream_t st);
-// after phase 0 of a re-projection (Z = E = (I - X^dag X) / 2 for instances b0 .. b0 + count - 1):
+// after phase 0 of a re-projection (E = (I - X^dag X) / 2 for instances b0 .. b0 + count - 1):
 // counts every active instance with ||X^dag X - I||_F / sqrt(d) > UNITARITY_WARN in flags
-hipError_t unitarity_check(int d, int count, int b0, const float2* Z, long long zstride, const int* n_steps, int step,
+hipError_t unitarity_check(int d, int count, int b0, const float2* E, long long estride, const int* n_steps, int step,
                            DeviceFlags* flags, hipStream_t st);
-hipError_t reproject_descs(GemmDesc* descs, int count, int b0, float2* X0, float2* X1, long long xstride, float2* Z,
-                           long long zstride, int* loc, const int* n_steps, int step, int phase, hipStream_t st);
+hipError_t reproject_descs(GemmDesc* descs, int count, int b0, float2* X0, float2* X1, long long xstride, float2* E,
+                           long long estride, int* loc, const int* n_steps, int step, int phase, hipStream_t st);
 // Newton-Schulz re-projection of every active instance at a re-projection step,
 // X <- X (3I - X^dag X) / 2 written as X + X E with E = (I - X^dag X) / 2, REPROJECT_CHUNK
 // instances at a time through the scratch E (xstride apart) and descs (REPROJECT_CHUNK
