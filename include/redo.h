@@ -371,8 +371,13 @@ redo_status redo_unitary_fidelity(int32_t d, int32_t B, const float* U_target, c
  * row the traces read Y_n only at those entries, as FP64 dot products of rows
  * of X_n and L_n^dag.  With checkpoint_every = C > 1 only every C-th state is
  * kept and each segment is recomputed during the backward scan.  0 selects 1
- * when that workspace is at most 48 GiB (d >= 128), else ceil(sqrt(N_max));
- * at d <= 64 the fused kernel always checkpoints (0: ceil(sqrt(N_max))).  At
+ * when that workspace is at most 48 GiB (d >= 128), else ceil(sqrt(N_max)).
+ * At d <= 64 the fused kernel keeps the forward states of C consecutive steps
+ * (one segment) besides the checkpoints; a C of at least N_max makes that one
+ * segment the whole chain, written by the forward pass, so nothing is
+ * recomputed (the same states, bit for bit), and 0 selects N_max when that
+ * workspace (B N_max d^2 complex entries and the pending traces) is at most
+ * 8 GiB, else ceil(sqrt(N_max)).  At
  * d <= 64, with the workspace that redo_workspace_bytes / redo_grape_workspace_bytes
  * report, every step's propagator U_n (B N_max d^2 complex entries, when that
  * is at most 4 GiB and the batch's threads, B (d/2)^2 below d = 64 and 256 B at

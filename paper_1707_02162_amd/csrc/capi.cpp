@@ -157,6 +157,14 @@ long long ceil_sqrt(long long n) {
     return std::max(1LL, c);
 }
 
+// checkpoint interval of the fused GRAPE (d <= 64): the requested one, else every state kept
+// (one segment) when that workspace fits SMALL_FULL_STORAGE_MAX, else ceil(sqrt(N_max))
+long long small_grape_interval(const redo_table_s* t, long long B, long long N_max, long long requested) {
+    if (requested > 0) return requested;
+    if (small_grape_workspace_bytes(t->desc.d, t->desc.K, B, N_max, N_max) <= SMALL_FULL_STORAGE_MAX) return N_max;
+    return ceil_sqrt(N_max);
+}
+
 // the pre-split BF16 copy of the level cache, if any
 redo_status free_cache_bf(redo_table_s* t) {
     if (!t->cache_bf) return REDO_OK;
@@ -727,7 +735,7 @@ size_t redo_workspace_bytes(redo_table t, int32_t op, int32_t B, int32_t N_max) 
             case REDO_OP_COMPOSE:
             case REDO_OP_CHAIN: return 0;
             case REDO_OP_GRAPE:
-                return small_grape_workspace_bytes(d, t->desc.K, B, N_max, ceil_sqrt(N_max)) +
+                return small_grape_workspace_bytes(d, t->desc.K, B, N_max, small_grape_interval(t, B, N_max, 0)) +
                        small_grape_precomposed_bytes(d, B, N_max);
             default: return 0;
         }
@@ -739,7 +747,7 @@ size_t redo_grape_workspace_bytes(redo_table t, int32_t B, int32_t N_max, int32_
     if (!t || B < 1 || N_max < 1 || checkpoint_every < 0) return 0;
     const int d = t->desc.d;
     if (small_dim(d)) {
-        const long long C = checkpoint_every > 0 ? checkpoint_every : ceil_sqrt(N_max);
+        const long long C = small_grape_interval(t, B, N_max, checkpoint_every);
         return small_grape_workspace_bytes(d, t->desc.K, B, N_max, C) + small_grape_precomposed_bytes(d, B, N_max);
     }
     return large_grape_workspace_bytes(t, B, N_max, checkpoint_every);
@@ -749,7 +757,7 @@ size_t redo_grape_workspace_min_bytes(redo_table t, int32_t B, int32_t N_max, in
     if (!t || B < 1 || N_max < 1 || checkpoint_every < 0) return 0;
     const int d = t->desc.d;
     if (small_dim(d)) {
-        const long long C = checkpoint_every > 0 ? checkpoint_every : ceil_sqrt(N_max);
+        const long long C = small_grape_interval(t, B, N_max, checkpoint_every);
         return small_grape_workspace_bytes(d, t->desc.K, B, N_max, C);
     }
     return large_grape_workspace_bytes(t, B, N_max, checkpoint_every);
@@ -1029,9 +1037,9 @@ redo_status redo_grape_fidelity_grad(redo_table t, int32_t precision, const floa
     if (checkpoint_every < 0) return fail(REDO_ERR_ARG, "checkpoint_every must be >= 0");
     if (precision < REDO_PREC_F32 || precision > REDO_PREC_BF16X3) return fail(REDO_ERR_ARG, "unknown precision");
     if (!t->grad_ok) return fail(REDO_ERR_UNSUPPORTED, "adjoint needs commuting channels: " + t->grad_why);
-    const long long C = checkpoint_every > 0 ? checkpoint_every : ceil_sqrt(N_max);
     hipStream_t hs = static_cast<hipStream_t>(stream);
     if (small_dim(t->desc.d)) {
+        const long long C = small_grape_interval(t, B, N_max, checkpoint_every);
         if (precision != REDO_PREC_F32) return fail(REDO_ERR_UNSUPPORTED, "d <= 64 runs in FP32 only");
         const long long nck = (N_max + C - 1) / C;
         const size_t need = small_grape_workspace_bytes(t->desc.d, t->desc.K, B, N_max, C);

@@ -253,6 +253,10 @@ size_t small_grape_workspace_bytes(int d, int K, long long B, long long N_max, l
 // SMALL_PRECOMPOSED_MAX_THREADS (one wave per SIMD on 256 CUs); the fused form then builds
 // each step from its factors
 constexpr size_t SMALL_PRECOMPOSED_MAX = size_t(4) << 30;
+// the fused GRAPE (d <= 64) keeps every state of the forward pass (one checkpoint segment, no
+// recompute) when the checkpoint interval is left to the library and its workspace stays
+// within this; else it checkpoints every ceil(sqrt(N_max)) steps
+constexpr size_t SMALL_FULL_STORAGE_MAX = size_t(8) << 30;
 constexpr long long SMALL_PRECOMPOSED_MAX_THREADS = 256LL * 4 * 64;
 size_t small_grape_precomposed_bytes(int d, long long B, long long N_max);
 

@@ -950,6 +950,10 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
     __syncthreads();
     const int N = nblk;
     const int C = a.checkpoint_every;
+    // one segment covers the chain: the forward pass keeps every state in the segment buffer
+    // and the backward pass needs no recompute (the same states, bit for bit); uniform per
+    // workgroup, as C and N are
+    const bool whole = C >= N;
     const int drift = valid ? b % tv.n_drift : 0;
     const int KK = tv.phased ? 2 : 1;
     const long long ustride = (long long)tv.K * KK;
@@ -974,6 +978,7 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
             pre_left<D, Cfg<D>::MFG>(x, Xs, Fs, Rs, a.Up + ((long long)b * a.N_max + n) * D * D, active, lt, ti, tj);
         else
             step_left<D, Cfg<D>::MFG, HDR>(tv, x, Xs, Fs, Rs, ub + n * ustride, drift, active, HDR || lt == 0, lt, ti, tj, dph, dph64, hF, g2s, gs);
+        if (whole && active) save_block<D>(x, sg + (long long)n * D * D, ti, tj);
     }
     // ---- overlap g = Tr(U_f^dag X_N) / Tr(U_f^dag U_f)
     const float2* Uf = a.U_target + (long long)(valid ? b : 0) * D * D;
@@ -1050,10 +1055,11 @@ __global__ __launch_bounds__(256) void small_grape_kernel(TView tv_in, SmallGrap
     const int nseg = (N + C - 1) / C;
     for (int sgi = nseg - 1; sgi >= 0; --sgi) {
         const int s0 = sgi * C, s1 = min(N, s0 + C);
-        // recompute X_{s0+1} .. X_{s1} into the segment buffer
-        const bool seg_active = valid && s0 < len;
+        // recompute X_{s0+1} .. X_{s1} into the segment buffer (kept by the forward pass when
+        // one segment covers the chain)
+        const bool seg_active = valid && s0 < len && !whole;
         if (seg_active) load_block<D>(x, ck + (long long)sgi * D * D, ti, tj);
-        for (int n = s0; n < s1; ++n) {
+        for (int n = s0; n < (whole ? s0 : s1); ++n) {
             const bool active = valid && n < len;
             if constexpr (PRE)
                 pre_left<D, Cfg<D>::MFG>(x, Xs, Fs, Rs, a.Up + ((long long)b * a.N_max + n) * D * D, active, lt, ti, tj);

@@ -355,6 +355,31 @@ def test_grape_precomposed_and_factor_forms_agree(which):
     _grape_check(p, tab, F1.cpu().numpy(), ov1.cpu().numpy(), g1.cpu().numpy(), range(min(p.B, 2)))
 
 
+@pytest.mark.parametrize("which", ["c1", "c4"])
+@pytest.mark.parametrize("precompose", [False, True])
+def test_grape_every_state_kept_equals_checkpointed(which, precompose):
+    """With the interval left to the library the fused GRAPE keeps every state of the
+    forward pass (one segment, no recompute); the checkpointed scan recomputes the same
+    states with the same operations, so fidelity, overlap and gradient agree bit for bit
+    (d = 4, two phased channels; d = 32, five, ragged lengths)."""
+    if which == "c1":
+        p, ns = W.c1_two_spin(B=3, N=120), None
+    else:
+        p = W.c4_batched_grape(B=4, n_min=60, n_max=140)
+        ns = torch.tensor(p.n_steps)
+    t = table(p)
+    t.cache_levels()
+    u, Uf = torch.tensor(p.u).cuda(), torch.tensor(p.U_target).cuda()
+    Fa, ova, ga = t.grape(u, Uf, n_steps=ns, precompose=precompose)
+    Fc, ovc, gc = t.grape(u, Uf, n_steps=ns, checkpoint_every=7, precompose=precompose)
+    assert torch.equal(Fa, Fc) and torch.equal(ova, ovc) and torch.equal(ga, gc)
+    # the interval the library takes keeps every state: its workspace holds N_max of them
+    lib = R().lib()
+    full = lib.redo_grape_workspace_min_bytes(t._h, p.B, p.N, 0)
+    ckpt = lib.redo_grape_workspace_min_bytes(t._h, p.B, p.N, 7)
+    assert full > ckpt > 0
+
+
 def test_autograd_function_backward():
     p = W.c1_two_spin(B=2, N=50)
     t = table(p)
