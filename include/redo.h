@@ -181,7 +181,10 @@ size_t redo_grape_workspace_bytes(redo_table table, int32_t B, int32_t N_max, in
  * (Sec. III, GRAPE through REDO): at d <= 64 the checkpoints, one recomputed
  * segment and the pending traces, without the precomposed step propagators
  * (each scan step is then built from its factors); at d >= 128 the same as
- * redo_grape_workspace_bytes.  0 on invalid arguments. */
+ * redo_grape_workspace_bytes.  The interval is part of the call: with 0 it is
+ * the automatic one, at d <= 64 every state kept when that fits 8 GiB, so a
+ * caller short of memory passes an explicit interval (ceil(sqrt(N_max)) gives
+ * the checkpointed scan).  0 on invalid arguments. */
 size_t redo_grape_workspace_min_bytes(redo_table table, int32_t B, int32_t N_max, int32_t checkpoint_every);
 
 /*
